@@ -1,0 +1,158 @@
+"""Pins of the oracle's Vegas: closed-form integrals (statistical), the
+zero-variance invariant on a frozen grid, chi^2 calibration, and the paper's
+interface semantics (nvec, -999 abort, nbatch, mineval/maxeval)."""
+import numpy as np
+import pytest
+from scipy import stats
+
+import oracle as O
+from closed_forms import exact
+import workloads as W
+
+
+@pytest.mark.parametrize("fam", [0, 1, 2, 4])
+def test_closed_forms_within_4_sigma(fam):
+    zs = []
+    for seed in range(1, 21):
+        a, u = W.genz_params(fam, 4, seed)
+        r = O.vegas(O.genz(fam, a, u), 4, nbins=50, nstart=5000, maxeval=5 * 5000, seed=seed)
+        assert r["fail"] == 1 and r["neval"] == 25000
+        z = (r["integral"] - exact(fam, a, u)) / r["error"]
+        zs.append(z)
+        assert abs(z) < 4.5
+    zs = np.array(zs)
+    # the z-scores of an unbiased estimator with a correct error are ~N(0,1)
+    assert abs(zs.mean()) < 1.0 and 0.4 < zs.std() < 1.8
+
+
+def test_corner_peak_d6():
+    a, u = W.genz_params(3, 6, 5)
+    r = O.vegas(O.genz(3, a, u), 6, nstart=20000, maxeval=10 * 20000, seed=3)
+    assert abs(r["integral"] - exact(3, a, u)) < 4.5 * r["error"]
+
+
+def test_fp32_eval_close_to_fp64():
+    a, u = W.genz_params(2, 8, 1)
+    r64 = O.vegas(O.genz(2, a, u), 8, nstart=20000, maxeval=5 * 20000, seed=2)
+    r32 = O.vegas(O.genz(2, a, u, precision=O.FP32_EVAL), 8, nstart=20000,
+                  maxeval=5 * 20000, seed=2, flags=O.FP32_EVAL)
+    assert abs(r32["integral"] / r64["integral"] - 1) < 1e-5
+    assert abs(r32["error"] / r64["error"] - 1) < 1e-3
+
+
+def test_zero_variance_on_frozen_grid():
+    # f = 1, N a power of two and a frozen (uniform) grid: every v is exactly
+    # 1, so S1 = S2 = n, every sigma_t = 0 and the result is exactly 1
+    one = O.python_integrand(lambda x: np.ones(len(x)))
+    for prec in (O.FP64, O.FP32_EVAL):
+        r = O.vegas(one, 3, nbins=128, nstart=4096, maxeval=3 * 4096,
+                    flags=O.FREEZE_GRID | prec, nvec=4096)
+        assert r["integral"] == 1.0 and r["error"] == 0.0
+        assert np.all(r["iter_var"] == 0.0) and np.all(r["iter_I"] == 1.0)
+
+
+def test_chi2_probability_is_calibrated():
+    # with a frozen grid the iterations are independent draws of the same
+    # estimator, so prob = P(chi^2 <= observed) is uniform on [0,1]
+    probs = []
+    for seed in range(40):
+        a, u = W.genz_params(0, 3, seed)
+        r = O.vegas(O.genz(0, a, u), 3, nbins=16, nstart=2000, maxeval=6 * 2000,
+                    seed=seed, flags=O.FREEZE_GRID)
+        assert r["dof"] == 5
+        probs.append(r["prob"])
+    assert stats.kstest(probs, "uniform").pvalue > 1e-3
+
+
+def test_gauss_legendre_d2():
+    # brute force at d = 2 with 64x64 Gauss-Legendre nodes of the same f
+    x, w = np.polynomial.legendre.leggauss(64)
+    x = (x + 1) / 2
+    w = w / 2
+    a, u = W.genz_params(2, 2, 9)
+    X0, X1 = np.meshgrid(x, x, indexing="ij")
+    f = O.genz_eval(2, a, u, np.stack([X0.ravel(), X1.ravel()], 1))
+    I_gl = float((np.outer(w, w).ravel() * f).sum())
+    r = O.vegas(O.genz(2, a, u), 2, nstart=20000, maxeval=8 * 20000, seed=4)
+    assert abs(r["integral"] - I_gl) < 4.5 * r["error"]
+
+
+def test_nvec_does_not_change_results():
+    a, u = W.genz_params(1, 5, 2)
+    base = None
+    for nvec in (1, 7, 1000):
+        r = O.vegas(O.genz(1, a, u), 5, nstart=3000, maxeval=3 * 3000, nvec=nvec)
+        key = (r["integral"], r["error"], r["prob"])
+        base = base or key
+        assert key == base
+
+
+def test_nvec_batches_seen_by_integrand():
+    seen = []
+
+    def f(x):
+        seen.append(len(x))
+        return np.ones(len(x))
+
+    O.vegas(O.python_integrand(f), 2, nstart=2500, maxeval=2500, nvec=1000)
+    assert seen == [1000, 1000, 500]
+
+
+def test_nbatch_does_not_change_results():
+    a, u = W.genz_params(0, 3, 2)
+    r1 = O.vegas(O.genz(0, a, u), 3, nstart=3000, maxeval=6000, nbatch=1)
+    r2 = O.vegas(O.genz(0, a, u), 3, nstart=3000, maxeval=6000, nbatch=10**6)
+    assert r1["integral"] == r2["integral"] and r1["error"] == r2["error"]
+
+
+def test_abort_minus_999():
+    calls = []
+
+    def f(x):
+        calls.append(1)
+        if len(calls) == 3:
+            return -999
+        return np.ones(len(x))
+
+    r = O.vegas(O.python_integrand(f), 2, nstart=5000, maxeval=10**5, nvec=1000)
+    assert r["fail"] == -99 and len(calls) == 3 and r["neval"] == 3000
+
+
+def test_epsrel_stops_and_mineval():
+    a, u = W.genz_params(0, 2, 1)
+    r = O.vegas(O.genz(0, a, u), 2, epsrel=1e-3, nstart=5000, nincrease=1000,
+                maxeval=10**7)
+    assert r["fail"] == 0 and r["error"] <= 1e-3 * abs(r["integral"])
+    # n_t = nstart + t nincrease
+    T = len(r["iter_I"])
+    assert r["neval"] == sum(5000 + 1000 * t for t in range(T))
+    r2 = O.vegas(O.genz(0, a, u), 2, epsrel=1e-3, nstart=5000, nincrease=1000,
+                 maxeval=10**7, mineval=r["neval"] + 1)
+    assert r2["neval"] > r["neval"]
+
+
+def test_maxeval_stops_before_overrun():
+    a, u = W.genz_params(0, 2, 1)
+    r = O.vegas(O.genz(0, a, u), 2, epsrel=0, nstart=1000, maxeval=3500)
+    assert r["fail"] == 1 and r["neval"] == 3000 and len(r["iter_I"]) == 3
+    # a constant on the first (uniform) grid has zero variance, which meets
+    # any tolerance, including epsrel = epsabs = 0, after one iteration
+    one = O.python_integrand(lambda x: np.ones(len(x)))
+    r = O.vegas(one, 2, epsrel=0, nstart=1024, maxeval=4096)
+    assert r["fail"] == 0 and r["neval"] == 1024 and r["error"] == 0.0
+
+
+def test_stream_id_and_seed_change_points():
+    a, u = W.genz_params(0, 3, 1)
+    base = O.vegas(O.genz(0, a, u), 3, nstart=2000, maxeval=2000)
+    assert O.vegas(O.genz(0, a, u), 3, nstart=2000, maxeval=2000, seed=2)["integral"] != base["integral"]
+    assert O.vegas(O.genz(0, a, u), 3, nstart=2000, maxeval=2000, stream_id=1)["integral"] != base["integral"]
+
+
+def test_bad_arguments():
+    one = O.python_integrand(lambda x: np.ones(len(x)))
+    for kw in (dict(nbins=1), dict(nbins=257), dict(nstart=1)):
+        with pytest.raises(ValueError):
+            O.vegas(one, 2, **kw)
+    with pytest.raises(ValueError):
+        O.vegas(one, 17)
