@@ -1,0 +1,278 @@
+/*
+ * ccuba.h -- C ABI of libccuba: the DoSample hot path of Vegas and Cuhre
+ * ("Concurrent Cuba", T. Hahn, MPP-2014-327) on one AMD Instinct MI355X.
+ *
+ * The paper states the problem every call here solves: integrate f over the
+ * unit hypercube [0,1]^ndim to the requested relative or absolute accuracy,
+ * max(epsabs, epsrel |I|), and return the integral, its error estimate and a
+ * chi^2 probability, with neval, fail and nregions as further outputs
+ * (Sect. 3.2.2, the Vegas and Cuhre prototypes).  All sampling goes through
+ * one batched routine, DoSample (Sect. 2.1), which is what runs on the GPU.
+ *
+ * Differences from the paper's prototypes, all forced by the device:
+ *  - the integrand is a device-side Genz family descriptor (ccuba_integrand)
+ *    instead of a host callback, since the GPU cannot call host code per
+ *    point; nvec and userdata therefore disappear;
+ *  - the `spin' argument (Sect. 3.2.3) becomes a context handle with the same
+ *    three cases (see ccuba_ctx);
+ *  - two entry points are added: a batch of independent Vegas integrals in one
+ *    persistent launch, and a submit/poll pair for a serving loop.
+ *
+ * Conventions for every function:
+ *  - return value: CCUBA_OK (0) or a negative CCUBA_E* status; nothing is
+ *    thrown across the ABI; ccuba_strerror() names a status;
+ *  - host arrays belong to the caller and are read during the call only;
+ *    outputs are written before a synchronous call returns;
+ *  - the context owns all device memory it allocates (grids, region heaps,
+ *    partial sums) and frees it in ccuba_shutdown;
+ *  - a context may be used by one host thread at a time (the serving loop's
+ *    own thread is internal and synchronised).
+ */
+#ifndef CCUBA_H
+#define CCUBA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes -------------------------------------------------------- */
+enum {
+  CCUBA_OK = 0,
+  CCUBA_EINVAL = -1,   /* an argument is out of range */
+  CCUBA_EHIP = -2,     /* a HIP runtime call failed */
+  CCUBA_ENOMEM = -3,   /* the request does not fit the context's HBM budget */
+  CCUBA_ENOENT = -4,   /* unknown ticket or configuration key */
+  CCUBA_ESTATE = -5    /* call not allowed in the context's current state */
+};
+
+/* ---- integrands ---------------------------------------------------------- */
+/* Genz test families (Genz 1987) over [0,1]^d:
+ *   GAUSSIAN      exp(-sum a_i^2 (x_i - u_i)^2)
+ *   OSCILLATORY   cos(2 pi u_1 + sum a_i x_i)
+ *   PRODUCT_PEAK  prod 1 / (a_i^-2 + (x_i - u_i)^2)
+ *   CORNER_PEAK   (1 + sum a_i x_i)^-(d+1)
+ *   C0            exp(-sum a_i |x_i - u_i|)                                  */
+enum { CCUBA_GAUSSIAN = 0, CCUBA_OSCILLATORY = 1, CCUBA_PRODUCT_PEAK = 2,
+       CCUBA_CORNER_PEAK = 3, CCUBA_C0 = 4 };
+
+/* a[ndim] and u[ndim] are host arrays, copied during the call. */
+typedef struct {
+  int family;
+  const double *a;
+  const double *u;
+} ccuba_integrand;
+
+/* ---- flags --------------------------------------------------------------- */
+/* bits 0-1: sampling precision.  FP64: points, map, integrand and sums in
+ * FP64.  FP32_EVAL: point map and integrand in FP32, every sum, the grid
+ * refinement and the final combination in FP64.
+ * bit 4: FREEZE_GRID keeps the initial uniform grid (no refinement). */
+enum { CCUBA_FP64 = 0, CCUBA_FP32_EVAL = 1, CCUBA_PRECISION_MASK = 3,
+       CCUBA_FREEZE_GRID = 1 << 4 };
+
+/* ---- context (the `spin' analog, Sect. 3.2.3) -----------------------------
+ * Every integrator takes `ccuba_ctx **ctx':
+ *   ctx == NULL  : a temporary context is created and destroyed in the call
+ *                  (the paper's NULL / -1: workers started and stopped);
+ *   *ctx == NULL : a context is created and returned in *ctx and kept
+ *                  (the paper's zero-initialised spin variable);
+ *   *ctx != NULL : the existing context is reused (a spin from an earlier
+ *                  call or from cubafork).                                   */
+typedef struct ccuba_ctx ccuba_ctx;
+
+/* Create a context on HIP device `device' (negative: CCUBA_DEVICE from the
+ * environment, else 0) that may allocate at most `hbm_budget' bytes of device
+ * memory (0: CCUBA_HBM_BUDGET from the environment, else 90% of the free
+ * memory).  The analog of cubafork (Sect. 3.2.3).  Errors: CCUBA_EINVAL
+ * (ctx NULL or bad device), CCUBA_EHIP. */
+int ccuba_init(ccuba_ctx **ctx, int device, size_t hbm_budget);
+
+/* Stop the serving loop if running, free all device memory and set *ctx to
+ * NULL.  The analog of cubawait (Sect. 3.2.3).  A NULL *ctx is accepted. */
+int ccuba_shutdown(ccuba_ctx **ctx);
+
+/* Override one setting of the context; explicit settings take precedence
+ * over the environment, as cubacores/cubaaccel override CUBACORES and
+ * CUBAACCEL (Sect. 3.2.4).  Keys:
+ *   "block"          DoSample threads per workgroup (64, 128 or 256)
+ *   "blocks_per_cu"  persistent DoSample workgroups per compute unit (1..16)
+ *   "hist64"         FP32 path: 1 = FP64 LDS histogram, 0 = FP32
+ *   "min_tile"       smallest tile of points in a batched launch (>= 64)
+ *   "autotune"       1 = pick the settings above by measurement, cached in the
+ *                    file named by CCUBA_TUNE_CACHE (if set)
+ *   "graph"          1 = replay iterations from a captured hipGraph
+ *   "serve_slots"    maximum requests resident in the serving loop
+ *   "profile"        1 = time every kernel launch with HIP events (see
+ *                    ccuba_stats_get)
+ * Returns CCUBA_ENOENT for an unknown key, CCUBA_EINVAL for a bad value. */
+int ccuba_config(ccuba_ctx *ctx, const char *key, long long value);
+
+/* Vegas (Sect. 3.2.2 prototype; Lepage 1978).  Iteration t samples
+ * n_t = nstart + t*nincrease points from Philox4x32-10 with counter
+ * (i, (t<<8)|b, stream_id, 0) and key (seed mod 2^32, seed div 2^32), maps
+ * them through the adaptive grid of nbins bins per dimension, and refines the
+ * grid after every iteration.  Iterations combine with inverse-variance
+ * weights; prob = P(dof/2, chi2/2) with dof = iterations - 1.  The run stops
+ * when neval >= mineval and error <= max(epsabs, epsrel |integral|)
+ * (fail = 0), or before an iteration that would take neval past maxeval, or
+ * after 4096 iterations (fail = 1).  nbatch only partitions the sampling
+ * internally and has no bearing on the results (Sect. 3.2.7); it must be
+ * >= 1.  Ranges: 1 <= ndim <= 16, ncomp == 1, 2 <= nbins <= 256,
+ * nstart >= 2, nincrease >= 0, every n_t < 2^32.  Outputs have ncomp = 1
+ * entries.  Errors: CCUBA_EINVAL, CCUBA_EHIP, CCUBA_ENOMEM. */
+int ccuba_vegas(ccuba_ctx **ctx, int ndim, int ncomp, const ccuba_integrand *f,
+                double epsrel, double epsabs, int flags, unsigned long long seed,
+                long long mineval, long long maxeval, long long nstart,
+                long long nincrease, long long nbatch, int nbins,
+                unsigned int stream_id, long long *neval, int *fail,
+                double integral[], double error[], double prob[]);
+
+/* Optional trace of a Vegas run (any pointer may be NULL). */
+typedef struct {
+  int max_iter;     /* capacity of iter_I and iter_var */
+  int n_iter;       /* out: iterations done */
+  double *iter_I;   /* out: I_t per iteration */
+  double *iter_var; /* out: sigma_t^2 per iteration */
+  double chi2;      /* out */
+  int dof;          /* out */
+  double *grid;     /* out: final grid, ndim * (nbins + 1) */
+} ccuba_vegas_trace;
+
+/* ccuba_vegas with a trace (trace may be NULL). */
+int ccuba_vegas_ex(ccuba_ctx **ctx, int ndim, int ncomp, const ccuba_integrand *f,
+                   double epsrel, double epsabs, int flags,
+                   unsigned long long seed, long long mineval, long long maxeval,
+                   long long nstart, long long nincrease, long long nbatch,
+                   int nbins, unsigned int stream_id, long long *neval,
+                   int *fail, double integral[], double error[], double prob[],
+                   ccuba_vegas_trace *trace);
+
+/* Cuhre (Sect. 3.2.2 prototype) with the degree-7 Genz-Malik rule and its
+ * embedded degree-5 rule (Genz & Malik 1980), error |I7 - I5|, bisection of
+ * each selected region along its largest fourth difference.  Each step splits
+ * the K = min(max_regions_per_batch/2, regions) regions of largest error
+ * (ties: lower region id) and evaluates the 2K children in one launch, until
+ * neval >= mineval and error <= max(epsabs, epsrel |integral|) (fail = 0), or
+ * until no child fits maxeval any more (fail = 1).  key must be 0 or 7.
+ * prob is 0.  Ranges: 2 <= ndim <= 16, ncomp == 1,
+ * max_regions_per_batch >= 2.  Errors: CCUBA_EINVAL, CCUBA_EHIP,
+ * CCUBA_ENOMEM (region heap beyond the budget). */
+int ccuba_cuhre(ccuba_ctx **ctx, int ndim, int ncomp, const ccuba_integrand *f,
+                double epsrel, double epsabs, int flags, long long mineval,
+                long long maxeval, int key, long long max_regions_per_batch,
+                int *nregions, long long *neval, int *fail, double integral[],
+                double error[], double prob[]);
+
+/* The Cuhre rule alone on a batch of regions (the DoSample of Cuhre).
+ * c[ndim*nreg] and h[ndim*nreg] are host arrays of centres and half-widths,
+ * structure-of-arrays (dimension-major: c[j*nreg + r]).  Outputs per region:
+ * I7, I5, err = |I7 - I5|, split axis.  Any output may be NULL.
+ * Errors: CCUBA_EINVAL, CCUBA_EHIP, CCUBA_ENOMEM. */
+int ccuba_cuhre_rule(ccuba_ctx *ctx, int ndim, const ccuba_integrand *f,
+                     long long nreg, const double *c, const double *h,
+                     double *I7, double *I5, double *err, int *axis);
+
+/* ---- batched Vegas (many independent integrals, one launch per iteration) */
+typedef struct {
+  int method;               /* 0 Vegas, 1 Cuhre (submit only) */
+  int ndim;
+  ccuba_integrand f;
+  double epsrel, epsabs;
+  int flags;
+  unsigned long long seed;
+  unsigned int stream_id;
+  long long mineval, maxeval, nstart, nincrease;
+  int nbins;                /* Vegas bins (0: 128) */
+  long long max_regions_per_batch; /* Cuhre (0: 100000) */
+} ccuba_job;
+
+typedef struct {
+  long long neval;
+  int nregions, fail, status; /* status: CCUBA_OK or the job's error */
+  double integral, error, prob;
+  double t_submit, t_done;    /* seconds on the context's steady clock */
+} ccuba_result;
+
+/* Run njobs independent Vegas integrals together: every iteration of every
+ * job still running is one persistent DoSample launch over a work list of
+ * (integral, point range) tiles, followed by one refine launch; the
+ * iteration pair is replayed from a captured hipGraph.  Each job's result is
+ * the one ccuba_vegas gives for it alone (same points; sums within
+ * rounding).  out[njobs].  Jobs with method != 0 get status CCUBA_EINVAL.
+ * Errors: CCUBA_EINVAL, CCUBA_EHIP, CCUBA_ENOMEM. */
+int ccuba_vegas_batch(ccuba_ctx *ctx, int njobs, const ccuba_job jobs[],
+                      ccuba_result out[]);
+
+/* ---- serving loop -------------------------------------------------------
+ * ccuba_submit queues one Vegas or Cuhre request and returns a ticket; a
+ * background thread of the context admits queued requests while slots and
+ * the HBM budget allow, keeps their grids and region heaps resident, runs the
+ * next Vegas iteration of every resident Vegas request in one batched launch
+ * and the next region batch of every resident Cuhre request in one batched
+ * rule launch per tick, and retires finished requests.  ccuba_poll returns
+ * 0 and fills *out once the ticket is done (the ticket is then forgotten),
+ * 1 while pending, CCUBA_ENOENT for an unknown ticket.  ccuba_drain waits
+ * until every submitted request is done. */
+int ccuba_submit(ccuba_ctx *ctx, const ccuba_job *job, unsigned long long *ticket);
+int ccuba_poll(ccuba_ctx *ctx, unsigned long long ticket, ccuba_result *out);
+int ccuba_drain(ccuba_ctx *ctx);
+
+/* ---- device-buffer entry points (for callers that own memory/streams) ---
+ * One DoSample pass of Vegas iteration `iteration' over n points on the FP64
+ * grid grid_dev[ndim*(nbins+1)] (device memory), on the caller's HIP stream
+ * (NULL: the default stream).  Writes sums_dev[2] = (sum w f, sum (w f)^2)
+ * and hist_dev[ndim*nbins] = per-bin sums of (w f)^2, all FP64 device memory
+ * owned by the caller and never freed here.  Asynchronous on the stream.
+ * Errors: CCUBA_EINVAL, CCUBA_EHIP, CCUBA_ENOMEM. */
+int ccuba_vegas_dosample_raw(ccuba_ctx *ctx, int ndim, int nbins,
+                             const ccuba_integrand *f, int flags,
+                             unsigned long long seed, unsigned int stream_id,
+                             int iteration, long long npts, const double *grid_dev,
+                             double *sums_dev, double *hist_dev, void *hip_stream);
+
+/* The points DoSample draws (steps: Philox words, uniform, grid map, weight)
+ * for points [i0, i0+npts) of iteration `iteration' on the host grid
+ * grid[ndim*(nbins+1)], computed on the device by the same code.  Outputs
+ * (host, any may be NULL): words[npts*4*ceil(ndim/4)], x[npts*ndim], w[npts],
+ * bin[npts*ndim].  Errors: CCUBA_EINVAL, CCUBA_EHIP. */
+int ccuba_vegas_points(ccuba_ctx *ctx, int ndim, int nbins, int flags,
+                       unsigned long long seed, unsigned int stream_id,
+                       int iteration, const double *grid, long long i0,
+                       long long npts, uint32_t *words, double *x, double *w,
+                       int *bin);
+
+/* One Lepage grid refinement on the device: hist[ndim*nbins] accumulated
+ * (w f)^2 per bin, grid_in[ndim*(nbins+1)] -> grid_out (host arrays).
+ * Errors: CCUBA_EINVAL, CCUBA_EHIP. */
+int ccuba_vegas_refine(ccuba_ctx *ctx, int ndim, int nbins, const double *hist,
+                       const double *grid_in, double *grid_out);
+
+/* Kernel timing of the context, measured with HIP events recorded on the
+ * stream each kernel is launched on, around every DoSample and every refine
+ * launch, while the context's "profile" setting is 1 (iterations are then
+ * launched one by one rather than replayed from a graph).  evals counts the
+ * points sampled by the timed DoSample launches. */
+typedef struct {
+  long long dosample_launches;
+  double dosample_ms;      /* summed DoSample kernel time */
+  long long refine_launches;
+  double refine_ms;
+  long long evals;
+  long long rule_launches; /* Cuhre rule kernels */
+  double rule_ms;
+  long long rule_evals;
+} ccuba_stats;
+
+/* Copy the context's counters to *out and reset them when reset != 0. */
+int ccuba_stats_get(ccuba_ctx *ctx, ccuba_stats *out, int reset);
+
+/* Name of a status code. */
+const char *ccuba_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

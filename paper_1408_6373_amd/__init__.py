@@ -1,0 +1,323 @@
+"""Python binding of libccuba (include/ccuba.h): argument marshalling only.
+
+Every step of the integration runs in the HIP library; this module converts
+Python/numpy arguments to the C ABI and back.  It raises at import time if
+``libccuba.so`` has not been built: there is no fallback path.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+try:
+    # PyTorch ships its own HIP runtime under the same soname as the system
+    # one; loading it first makes the process use a single runtime, so that
+    # device pointers and streams from torch are valid in the library.
+    import torch  # noqa: F401
+except ImportError:  # the library itself does not need torch
+    torch = None
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libccuba.so")
+
+OK, EINVAL, EHIP, ENOMEM, ENOENT, ESTATE = 0, -1, -2, -3, -4, -5
+GAUSSIAN, OSCILLATORY, PRODUCT_PEAK, CORNER_PEAK, C0 = range(5)
+FP64, FP32_EVAL, FREEZE_GRID = 0, 1, 1 << 4
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libccuba.so is not built: run `python -c 'import __graft_entry__ as g; "
+                      "g.build()'` (or paper_1408_6373_amd/build.py) first")
+
+_lib = C.CDLL(LIB_PATH)
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int)
+_llp = C.POINTER(C.c_longlong)
+
+
+class Integrand(C.Structure):
+    _fields_ = [("family", C.c_int), ("a", _dp), ("u", _dp)]
+
+
+class VegasTrace(C.Structure):
+    _fields_ = [("max_iter", C.c_int), ("n_iter", C.c_int), ("iter_I", _dp),
+                ("iter_var", _dp), ("chi2", C.c_double), ("dof", C.c_int), ("grid", _dp)]
+
+
+class Job(C.Structure):
+    _fields_ = [("method", C.c_int), ("ndim", C.c_int), ("f", Integrand),
+                ("epsrel", C.c_double), ("epsabs", C.c_double), ("flags", C.c_int),
+                ("seed", C.c_ulonglong), ("stream_id", C.c_uint),
+                ("mineval", C.c_longlong), ("maxeval", C.c_longlong),
+                ("nstart", C.c_longlong), ("nincrease", C.c_longlong),
+                ("nbins", C.c_int), ("max_regions_per_batch", C.c_longlong)]
+
+
+class Result(C.Structure):
+    _fields_ = [("neval", C.c_longlong), ("nregions", C.c_int), ("fail", C.c_int),
+                ("status", C.c_int), ("integral", C.c_double), ("error", C.c_double),
+                ("prob", C.c_double), ("t_submit", C.c_double), ("t_done", C.c_double)]
+
+
+def _sig(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+_CTXP = C.c_void_p
+_sig("ccuba_init", C.c_int, [C.POINTER(_CTXP), C.c_int, C.c_size_t])
+_sig("ccuba_shutdown", C.c_int, [C.POINTER(_CTXP)])
+_sig("ccuba_config", C.c_int, [_CTXP, C.c_char_p, C.c_longlong])
+_sig("ccuba_strerror", C.c_char_p, [C.c_int])
+_VEGAS_ARGS = [C.POINTER(_CTXP), C.c_int, C.c_int, C.POINTER(Integrand), C.c_double,
+               C.c_double, C.c_int, C.c_ulonglong, C.c_longlong, C.c_longlong, C.c_longlong,
+               C.c_longlong, C.c_longlong, C.c_int, C.c_uint, _llp, _ip, _dp, _dp, _dp]
+_sig("ccuba_vegas", C.c_int, _VEGAS_ARGS)
+_sig("ccuba_vegas_ex", C.c_int, _VEGAS_ARGS + [C.POINTER(VegasTrace)])
+_sig("ccuba_vegas_points", C.c_int, [_CTXP, C.c_int, C.c_int, C.c_int, C.c_ulonglong, C.c_uint,
+                                     C.c_int, _dp, C.c_longlong, C.c_longlong,
+                                     C.POINTER(C.c_uint32), _dp, _dp, _ip])
+_sig("ccuba_vegas_refine", C.c_int, [_CTXP, C.c_int, C.c_int, _dp, _dp, _dp])
+_sig("ccuba_vegas_dosample_raw", C.c_int, [_CTXP, C.c_int, C.c_int, C.POINTER(Integrand),
+                                           C.c_int, C.c_ulonglong, C.c_uint, C.c_int,
+                                           C.c_longlong, C.c_void_p, C.c_void_p, C.c_void_p,
+                                           C.c_void_p])
+_sig("ccuba_vegas_batch", C.c_int, [_CTXP, C.c_int, C.POINTER(Job), C.POINTER(Result)])
+if hasattr(_lib, "ccuba_cuhre"):
+    _sig("ccuba_cuhre", C.c_int, [C.POINTER(_CTXP), C.c_int, C.c_int, C.POINTER(Integrand),
+                                  C.c_double, C.c_double, C.c_int, C.c_longlong, C.c_longlong,
+                                  C.c_int, C.c_longlong, _ip, _llp, _ip, _dp, _dp, _dp])
+    _sig("ccuba_cuhre_rule", C.c_int, [_CTXP, C.c_int, C.POINTER(Integrand), C.c_longlong,
+                                       _dp, _dp, _dp, _dp, _dp, _ip])
+if hasattr(_lib, "ccuba_submit"):
+    _sig("ccuba_submit", C.c_int, [_CTXP, C.POINTER(Job), C.POINTER(C.c_ulonglong)])
+    _sig("ccuba_poll", C.c_int, [_CTXP, C.c_ulonglong, C.POINTER(Result)])
+    _sig("ccuba_drain", C.c_int, [_CTXP])
+
+SYMBOLS = ["ccuba_init", "ccuba_shutdown", "ccuba_config", "ccuba_strerror", "ccuba_vegas",
+           "ccuba_vegas_ex", "ccuba_cuhre", "ccuba_cuhre_rule", "ccuba_vegas_batch",
+           "ccuba_submit", "ccuba_poll", "ccuba_drain", "ccuba_vegas_dosample_raw",
+           "ccuba_vegas_points", "ccuba_vegas_refine"]
+
+
+class CcubaError(RuntimeError):
+    def __init__(self, rc, what):
+        super().__init__("%s: %s (%d)" % (what, strerror(rc), rc))
+        self.rc = rc
+
+
+def strerror(rc):
+    return _lib.ccuba_strerror(rc).decode()
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise CcubaError(rc, what)
+    return rc
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a):
+    return a.ctypes.data_as(_dp)
+
+
+class Context:
+    """A library context (the analog of the paper's spinning-cores handle)."""
+
+    def __init__(self, device=-1, hbm_budget=0):
+        self._h = _CTXP()
+        _check(_lib.ccuba_init(C.byref(self._h), device, hbm_budget), "ccuba_init")
+
+    @property
+    def handle(self):
+        return self._h
+
+    def config(self, key, value):
+        _check(_lib.ccuba_config(self._h, key.encode(), int(value)), "ccuba_config(%s)" % key)
+
+    def close(self):
+        if self._h:
+            _lib.ccuba_shutdown(C.byref(self._h))
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _integrand(family, a, u):
+    a = _f64(a)
+    u = _f64(u)
+    return Integrand(int(family), _ptr(a), _ptr(u)), (a, u)
+
+
+def _ctx_arg(ctx):
+    """ctx=None -> NULL (temporary context); Context -> its handle."""
+    if ctx is None:
+        return None
+    return C.byref(ctx.handle)
+
+
+def vegas(family, a, u, *, ctx=None, epsrel=0.0, epsabs=0.0, flags=FP64, seed=1, mineval=0,
+          maxeval=10**5, nstart=10**4, nincrease=0, nbatch=1000, nbins=128, stream_id=0,
+          trace=False, max_iter=4096):
+    """ccuba_vegas(_ex): returns a dict with neval, fail, integral, error, prob
+    (and iter_I, iter_var, chi2, dof, grid when trace=True)."""
+    f, keep = _integrand(family, a, u)
+    ndim = len(keep[0])
+    neval = C.c_longlong()
+    fail = C.c_int()
+    out = np.zeros(3)
+    res = [np.zeros(1) for _ in range(3)]
+    args = [_ctx_arg(ctx), ndim, 1, C.byref(f), epsrel, epsabs, flags, seed, mineval, maxeval,
+            nstart, nincrease, nbatch, nbins, stream_id, C.byref(neval), C.byref(fail),
+            _ptr(res[0]), _ptr(res[1]), _ptr(res[2])]
+    r = dict()
+    if trace:
+        It = np.zeros(max_iter)
+        Vt = np.zeros(max_iter)
+        grid = np.zeros(ndim * (nbins + 1))
+        tr = VegasTrace(max_iter, 0, _ptr(It), _ptr(Vt), 0.0, 0, _ptr(grid))
+        _check(_lib.ccuba_vegas_ex(*args, C.byref(tr)), "ccuba_vegas_ex")
+        n = tr.n_iter
+        r.update(iter_I=It[:n].copy(), iter_var=Vt[:n].copy(), chi2=tr.chi2, dof=tr.dof,
+                 grid=grid.reshape(ndim, nbins + 1))
+    else:
+        _check(_lib.ccuba_vegas(*args), "ccuba_vegas")
+    del out
+    r.update(neval=neval.value, fail=fail.value, integral=float(res[0][0]),
+             error=float(res[1][0]), prob=float(res[2][0]))
+    return r
+
+
+def vegas_points(ctx, ndim, nbins, grid, seed, stream_id, iteration, i0, npts, flags=FP64):
+    grid = _f64(grid).reshape(-1)
+    nblk = (ndim + 3) // 4
+    words = np.zeros((npts, 4 * nblk), dtype=np.uint32)
+    x = np.zeros((npts, ndim))
+    w = np.zeros(npts)
+    k = np.zeros((npts, ndim), dtype=np.int32)
+    _check(_lib.ccuba_vegas_points(ctx.handle, ndim, nbins, flags, seed, stream_id, iteration,
+                                   _ptr(grid), i0, npts,
+                                   words.ctypes.data_as(C.POINTER(C.c_uint32)), _ptr(x),
+                                   _ptr(w), k.ctypes.data_as(_ip)), "ccuba_vegas_points")
+    return dict(words=words, x=x, w=w, bin=k)
+
+
+def vegas_refine(ctx, hist, grid):
+    hist = _f64(hist)
+    grid = _f64(grid)
+    ndim, nbins = hist.shape
+    out = np.zeros_like(grid)
+    _check(_lib.ccuba_vegas_refine(ctx.handle, ndim, nbins, _ptr(hist), _ptr(grid), _ptr(out)),
+           "ccuba_vegas_refine")
+    return out
+
+
+def vegas_dosample_raw(ctx, family, a, u, nbins, iteration, npts, grid_ptr, sums_ptr, hist_ptr,
+                       stream_ptr=None, flags=FP64, seed=1, stream_id=0):
+    """Device-buffer DoSample: pointers are device addresses (e.g. torch
+    tensor .data_ptr()), stream_ptr a HIP stream handle (or None)."""
+    f, keep = _integrand(family, a, u)
+    _check(_lib.ccuba_vegas_dosample_raw(ctx.handle, len(keep[0]), nbins, C.byref(f), flags,
+                                         seed, stream_id, iteration, npts,
+                                         C.c_void_p(grid_ptr), C.c_void_p(sums_ptr),
+                                         C.c_void_p(hist_ptr),
+                                         C.c_void_p(stream_ptr) if stream_ptr else None),
+           "ccuba_vegas_dosample_raw")
+
+
+def make_jobs(specs):
+    """Build a ctypes Job array from dicts (method, ndim, family, a, u, epsrel,
+    epsabs, flags, seed, stream_id, mineval, maxeval, nstart, nincrease,
+    nbins, max_regions_per_batch)."""
+    arr = (Job * len(specs))()
+    keep = []
+    for q, s in enumerate(specs):
+        f, k = _integrand(s["family"], s["a"], s["u"])
+        keep.append(k)
+        arr[q] = Job(int(s.get("method", 0)), len(k[0]), f, float(s.get("epsrel", 0.0)),
+                     float(s.get("epsabs", 0.0)), int(s.get("flags", 0)), int(s.get("seed", 1)),
+                     int(s.get("stream_id", 0)), int(s.get("mineval", 0)),
+                     int(s.get("maxeval", 10**5)), int(s.get("nstart", 10**4)),
+                     int(s.get("nincrease", 0)), int(s.get("nbins", 128)),
+                     int(s.get("max_regions_per_batch", 0)))
+    return arr, keep
+
+
+def _result_dict(r):
+    return dict(neval=r.neval, nregions=r.nregions, fail=r.fail, status=r.status,
+                integral=r.integral, error=r.error, prob=r.prob, t_submit=r.t_submit,
+                t_done=r.t_done)
+
+
+def vegas_batch(ctx, specs):
+    arr, keep = make_jobs(specs)
+    out = (Result * len(specs))()
+    _check(_lib.ccuba_vegas_batch(ctx.handle, len(specs), arr, out), "ccuba_vegas_batch")
+    return [_result_dict(r) for r in out]
+
+
+def cuhre(family, a, u, *, ctx=None, epsrel=1e-3, epsabs=0.0, flags=0, mineval=0,
+          maxeval=10**7, key=7, max_regions_per_batch=10**5):
+    f, keep = _integrand(family, a, u)
+    nreg = C.c_int()
+    neval = C.c_longlong()
+    fail = C.c_int()
+    res = [np.zeros(1) for _ in range(3)]
+    _check(_lib.ccuba_cuhre(_ctx_arg(ctx), len(keep[0]), 1, C.byref(f), epsrel, epsabs, flags,
+                            mineval, maxeval, key, max_regions_per_batch, C.byref(nreg),
+                            C.byref(neval), C.byref(fail), _ptr(res[0]), _ptr(res[1]),
+                            _ptr(res[2])), "ccuba_cuhre")
+    return dict(nregions=nreg.value, neval=neval.value, fail=fail.value,
+                integral=float(res[0][0]), error=float(res[1][0]), prob=float(res[2][0]))
+
+
+def cuhre_rule(ctx, family, a, u, c, h):
+    """Rule on a batch of regions: c, h arrays of shape (nreg, ndim)."""
+    f, keep = _integrand(family, a, u)
+    c = np.atleast_2d(_f64(c))
+    h = np.atleast_2d(_f64(h))
+    nreg, ndim = c.shape
+    cs = np.ascontiguousarray(c.T)
+    hs = np.ascontiguousarray(h.T)
+    I7 = np.zeros(nreg)
+    I5 = np.zeros(nreg)
+    err = np.zeros(nreg)
+    axis = np.zeros(nreg, dtype=np.int32)
+    _check(_lib.ccuba_cuhre_rule(ctx.handle, ndim, C.byref(f), nreg, _ptr(cs), _ptr(hs),
+                                 _ptr(I7), _ptr(I5), _ptr(err), axis.ctypes.data_as(_ip)),
+           "ccuba_cuhre_rule")
+    return dict(I7=I7, I5=I5, err=err, axis=axis)
+
+
+def submit(ctx, spec):
+    arr, keep = make_jobs([spec])
+    t = C.c_ulonglong()
+    _check(_lib.ccuba_submit(ctx.handle, arr, C.byref(t)), "ccuba_submit")
+    return t.value
+
+
+def poll(ctx, ticket):
+    """None while pending, else the result dict."""
+    r = Result()
+    rc = _lib.ccuba_poll(ctx.handle, ticket, C.byref(r))
+    if rc == 1:
+        return None
+    _check(rc, "ccuba_poll")
+    return _result_dict(r)
+
+
+def drain(ctx):
+    _check(_lib.ccuba_drain(ctx.handle), "ccuba_drain")

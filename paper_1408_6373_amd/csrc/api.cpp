@@ -1,0 +1,402 @@
+// api.cpp -- the C ABI of libccuba (declared in include/ccuba.h).
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <memory>
+#include <new>
+
+#include "ccuba.h"
+#include "context.h"
+#include "tune.h"
+#include "vegas_engine.h"
+
+using namespace ccuba;
+
+namespace ccuba {
+
+int dev_alloc(ccuba_ctx *ctx, void **p, size_t bytes) {
+  const size_t before = ctx->used.fetch_add(bytes);
+  if (before + bytes > ctx->budget) {
+    ctx->used.fetch_sub(bytes);
+    return CCUBA_ENOMEM;
+  }
+  if (hipMalloc(p, bytes) != hipSuccess) {
+    ctx->used.fetch_sub(bytes);
+    *p = nullptr;
+    return CCUBA_ENOMEM;
+  }
+  return CCUBA_OK;
+}
+
+void dev_free(ccuba_ctx *ctx, void *p, size_t bytes) {
+  if (!p) return;
+  (void)hipFree(p);
+  ctx->used.fetch_sub(bytes);
+}
+
+}  // namespace ccuba
+
+namespace {
+
+long long env_ll(const char *name, long long dflt) {
+  const char *v = std::getenv(name);
+  if (!v || !*v) return dflt;
+  char *end = nullptr;
+  const long long r = std::strtoll(v, &end, 10);
+  return (end && *end == 0) ? r : dflt;
+}
+
+// The three cases of the paper's `spin' argument (Sect. 3.2.3).
+struct CtxScope {
+  ccuba_ctx *ctx = nullptr;
+  bool temporary = false;
+  int rc = CCUBA_OK;
+  explicit CtxScope(ccuba_ctx **pp) {
+    if (!pp) {
+      rc = ccuba_init(&ctx, -1, 0);
+      temporary = true;
+    } else if (!*pp) {
+      rc = ccuba_init(pp, -1, 0);
+      ctx = *pp;
+    } else {
+      ctx = *pp;
+    }
+  }
+  ~CtxScope() {
+    if (temporary && ctx) ccuba_shutdown(&ctx);
+  }
+};
+
+int fill_spec(VegasSpec &sp, int ndim, int ncomp, const ccuba_integrand *f, double epsrel,
+              double epsabs, int flags, unsigned long long seed, long long mineval,
+              long long maxeval, long long nstart, long long nincrease, long long nbatch,
+              int nbins, unsigned int stream_id) {
+  if (!f || ncomp != 1 || nbatch < 1 || ndim < 1 || ndim > kMaxDim || !f->a || !f->u)
+    return CCUBA_EINVAL;
+  const int prec = flags & CCUBA_PRECISION_MASK;
+  if (prec != CCUBA_FP64 && prec != CCUBA_FP32_EVAL) return CCUBA_EINVAL;
+  sp.ndim = ndim;
+  sp.nbins = nbins;
+  sp.family = f->family;
+  sp.prec = prec == CCUBA_FP64 ? FP64 : FP32;
+  sp.flags = flags & CCUBA_FREEZE_GRID;
+  sp.seed = seed;
+  sp.sid = stream_id;
+  sp.nstart = nstart;
+  sp.nincrease = nincrease;
+  sp.mineval = mineval;
+  sp.maxeval = maxeval;
+  sp.epsrel = epsrel;
+  sp.epsabs = epsabs;
+  for (int j = 0; j < ndim; ++j) {
+    sp.a[j] = f->a[j];
+    sp.u[j] = f->u[j];
+  }
+  return validate_vegas(sp);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *ccuba_strerror(int status) {
+  switch (status) {
+    case CCUBA_OK: return "success";
+    case CCUBA_EINVAL: return "invalid argument";
+    case CCUBA_EHIP: return "HIP runtime error";
+    case CCUBA_ENOMEM: return "device memory budget exceeded";
+    case CCUBA_ENOENT: return "unknown ticket or key";
+    case CCUBA_ESTATE: return "not allowed in the current state";
+  }
+  return "unknown status";
+}
+
+int ccuba_init(ccuba_ctx **ctx, int device, size_t hbm_budget) {
+  if (!ctx) return CCUBA_EINVAL;
+  *ctx = nullptr;
+  if (device < 0) device = (int)env_ll("CCUBA_DEVICE", 0);
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return CCUBA_EHIP;
+  if (device >= ndev) return CCUBA_EINVAL;
+  if (hipSetDevice(device) != hipSuccess) return CCUBA_EHIP;
+  std::unique_ptr<ccuba_ctx> c(new (std::nothrow) ccuba_ctx());
+  if (!c) return CCUBA_ENOMEM;
+  c->device = device;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return CCUBA_EHIP;
+  c->ncu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  if (hbm_budget == 0) hbm_budget = (size_t)env_ll("CCUBA_HBM_BUDGET", 0);
+  if (hbm_budget == 0) {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) return CCUBA_EHIP;
+    hbm_budget = fr / 10 * 9;
+  }
+  c->budget = hbm_budget;
+  if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) return CCUBA_EHIP;
+  if (set_kernel_limits() != hipSuccess) return CCUBA_EHIP;
+  for (int p = 0; p < 2; ++p) {
+    c->tune[p].block = (int)env_ll("CCUBA_BLOCK", 256);
+    c->tune[p].blocks_per_cu = (int)env_ll("CCUBA_BLOCKS_PER_CU", 4);
+    c->tune[p].min_tile = env_ll("CCUBA_MIN_TILE", 16384);
+  }
+  c->tune[FP32].hist64 = (int)env_ll("CCUBA_HIST64", 1);
+  c->use_graph = (int)env_ll("CCUBA_GRAPH", 1);
+  c->autotune = (int)env_ll("CCUBA_AUTOTUNE", 0);
+  c->serve_slots = (int)env_ll("CCUBA_SERVE_SLOTS", 256);
+  for (int p = 0; p < 2; ++p) {
+    const int b = c->tune[p].block;
+    if (b != 64 && b != 128 && b != 256) c->tune[p].block = 256;
+    c->tune[p].blocks_per_cu = std::min(16, std::max(1, c->tune[p].blocks_per_cu));
+  }
+  *ctx = c.release();
+  return CCUBA_OK;
+}
+
+int ccuba_shutdown(ccuba_ctx **ctx) {
+  if (!ctx || !*ctx) return CCUBA_OK;
+  ccuba_ctx *c = *ctx;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+  *ctx = nullptr;
+  return CCUBA_OK;
+}
+
+int ccuba_config(ccuba_ctx *ctx, const char *key, long long value) {
+  if (!ctx || !key) return CCUBA_EINVAL;
+  std::lock_guard<std::mutex> g(ctx->lock);
+  const std::string k(key);
+  if (k == "block") {
+    if (value != 64 && value != 128 && value != 256) return CCUBA_EINVAL;
+    ctx->tune[0].block = ctx->tune[1].block = (int)value;
+  } else if (k == "blocks_per_cu") {
+    if (value < 1 || value > 16) return CCUBA_EINVAL;
+    ctx->tune[0].blocks_per_cu = ctx->tune[1].blocks_per_cu = (int)value;
+  } else if (k == "hist64") {
+    if (value != 0 && value != 1) return CCUBA_EINVAL;
+    ctx->tune[FP32].hist64 = (int)value;
+  } else if (k == "min_tile") {
+    if (value < 64) return CCUBA_EINVAL;
+    ctx->tune[0].min_tile = ctx->tune[1].min_tile = value;
+  } else if (k == "autotune") {
+    ctx->autotune = value != 0;
+  } else if (k == "graph") {
+    ctx->use_graph = value != 0;
+  } else if (k == "profile") {
+    ctx->profile = value != 0;
+  } else if (k == "serve_slots") {
+    if (value < 1 || value > 1 << 20) return CCUBA_EINVAL;
+    ctx->serve_slots = (int)value;
+  } else {
+    return CCUBA_ENOENT;
+  }
+  return CCUBA_OK;
+}
+
+int ccuba_stats_get(ccuba_ctx *ctx, ccuba_stats *out, int reset) {
+  if (!ctx || !out) return CCUBA_EINVAL;
+  std::lock_guard<std::mutex> g(ctx->lock);
+  *out = ctx->stats;
+  if (reset) ctx->stats = ccuba_stats{};
+  return CCUBA_OK;
+}
+
+int ccuba_vegas_ex(ccuba_ctx **ctxp, int ndim, int ncomp, const ccuba_integrand *f,
+                   double epsrel, double epsabs, int flags, unsigned long long seed,
+                   long long mineval, long long maxeval, long long nstart,
+                   long long nincrease, long long nbatch, int nbins, unsigned int stream_id,
+                   long long *neval, int *fail, double integral[], double error[],
+                   double prob[], ccuba_vegas_trace *trace) {
+  if (!neval || !fail || !integral || !error || !prob) return CCUBA_EINVAL;
+  VegasSpec sp;
+  int rc = fill_spec(sp, ndim, ncomp, f, epsrel, epsabs, flags, seed, mineval, maxeval,
+                     nstart, nincrease, nbatch, nbins, stream_id);
+  if (rc) return rc;
+  CtxScope scope(ctxp);
+  if (scope.rc) return scope.rc;
+  ccuba_ctx *ctx = scope.ctx;
+  std::lock_guard<std::mutex> g(ctx->lock);
+  CCUBA_HIP(hipSetDevice(ctx->device));
+  if (ctx->autotune) maybe_autotune(ctx, sp.prec);
+  VegasEngine eng(ctx);
+  if ((rc = eng.setup({sp}, true, ctx->stream))) return rc;
+  if ((rc = eng.run(ctx->stream))) return rc;
+  std::vector<VState> st;
+  if ((rc = eng.read_states(st, ctx->stream))) return rc;
+  *neval = st[0].neval;
+  *fail = st[0].fail;
+  integral[0] = st[0].integral;
+  error[0] = st[0].error;
+  prob[0] = st[0].prob;
+  if (trace) {
+    trace->n_iter = st[0].T;
+    trace->chi2 = st[0].chi2;
+    trace->dof = st[0].dof;
+    const int n = std::min(trace->max_iter, st[0].T);
+    if (n > 0 && (trace->iter_I || trace->iter_var))
+      if ((rc = eng.read_history(0, n, trace->iter_I, trace->iter_var, ctx->stream))) return rc;
+    if (trace->grid)
+      if ((rc = eng.read_grid(0, st[0].T, trace->grid, ctx->stream))) return rc;
+  }
+  return CCUBA_OK;
+}
+
+int ccuba_vegas(ccuba_ctx **ctx, int ndim, int ncomp, const ccuba_integrand *f, double epsrel,
+                double epsabs, int flags, unsigned long long seed, long long mineval,
+                long long maxeval, long long nstart, long long nincrease, long long nbatch,
+                int nbins, unsigned int stream_id, long long *neval, int *fail,
+                double integral[], double error[], double prob[]) {
+  return ccuba_vegas_ex(ctx, ndim, ncomp, f, epsrel, epsabs, flags, seed, mineval, maxeval,
+                        nstart, nincrease, nbatch, nbins, stream_id, neval, fail, integral,
+                        error, prob, nullptr);
+}
+
+int ccuba_vegas_points(ccuba_ctx *ctx, int ndim, int nbins, int flags, unsigned long long seed,
+                       unsigned int stream_id, int iteration, const double *grid, long long i0,
+                       long long npts, uint32_t *words, double *x, double *w, int *bin) {
+  if (!ctx || !grid || ndim < 1 || ndim > kMaxDim || nbins < 2 || nbins > kMaxBins ||
+      npts < 0 || i0 < 0 || i0 + npts > (1ll << 32) || iteration < 0 ||
+      iteration >= (1 << 24))
+    return CCUBA_EINVAL;
+  const int prec = flags & CCUBA_PRECISION_MASK;
+  if (prec != CCUBA_FP64 && prec != CCUBA_FP32_EVAL) return CCUBA_EINVAL;
+  if (npts == 0) return CCUBA_OK;
+  std::lock_guard<std::mutex> g(ctx->lock);
+  CCUBA_HIP(hipSetDevice(ctx->device));
+  const int nblk = (ndim + 3) / 4;
+  const size_t row = (size_t)ndim * (nbins + 1);
+  DevBuf<double> dgrid, dx, dw;
+  DevBuf<uint32_t> dwords;
+  DevBuf<int> dbin;
+  int rc;
+  if ((rc = dgrid.alloc(ctx, row)) || (rc = dx.alloc(ctx, (size_t)npts * ndim)) ||
+      (rc = dw.alloc(ctx, npts)) || (rc = dwords.alloc(ctx, (size_t)npts * 4 * nblk)) ||
+      (rc = dbin.alloc(ctx, (size_t)npts * ndim)))
+    return rc;
+  CCUBA_HIP(hipMemcpyAsync(dgrid.p, grid, row * sizeof(double), hipMemcpyHostToDevice,
+                           ctx->stream));
+  PointsArgs P;
+  P.ndim = ndim;
+  P.nbins = nbins;
+  P.prec = prec == CCUBA_FP64 ? FP64 : FP32;
+  P.iteration = iteration;
+  P.key0 = (uint32_t)(seed & 0xffffffffull);
+  P.key1 = (uint32_t)(seed >> 32);
+  P.sid = stream_id;
+  P.i0 = i0;
+  P.npts = npts;
+  P.grid = dgrid.p;
+  P.words = dwords.p;
+  P.x = dx.p;
+  P.w = dw.p;
+  P.bin = dbin.p;
+  CCUBA_HIP(launch_points(P, ctx->stream));
+  if (words)
+    CCUBA_HIP(hipMemcpyAsync(words, dwords.p, (size_t)npts * 4 * nblk * 4,
+                             hipMemcpyDeviceToHost, ctx->stream));
+  if (x)
+    CCUBA_HIP(hipMemcpyAsync(x, dx.p, (size_t)npts * ndim * 8, hipMemcpyDeviceToHost,
+                             ctx->stream));
+  if (w)
+    CCUBA_HIP(hipMemcpyAsync(w, dw.p, (size_t)npts * 8, hipMemcpyDeviceToHost, ctx->stream));
+  if (bin)
+    CCUBA_HIP(hipMemcpyAsync(bin, dbin.p, (size_t)npts * ndim * 4, hipMemcpyDeviceToHost,
+                             ctx->stream));
+  CCUBA_HIP(hipStreamSynchronize(ctx->stream));
+  return CCUBA_OK;
+}
+
+int ccuba_vegas_refine(ccuba_ctx *ctx, int ndim, int nbins, const double *hist,
+                       const double *grid_in, double *grid_out) {
+  if (!ctx || !hist || !grid_in || !grid_out || ndim < 1 || ndim > kMaxDim || nbins < 2 ||
+      nbins > kMaxBins)
+    return CCUBA_EINVAL;
+  std::lock_guard<std::mutex> g(ctx->lock);
+  CCUBA_HIP(hipSetDevice(ctx->device));
+  VegasSpec sp;
+  sp.ndim = ndim;
+  sp.nbins = nbins;
+  sp.nstart = 2;
+  sp.maxeval = 1ll << 40;
+  VegasEngine eng(ctx);
+  int rc = eng.setup({sp}, true, ctx->stream);
+  if (rc) return rc;
+  return eng.refine_only(hist, grid_in, grid_out, ctx->stream);
+}
+
+int ccuba_vegas_dosample_raw(ccuba_ctx *ctx, int ndim, int nbins, const ccuba_integrand *f,
+                             int flags, unsigned long long seed, unsigned int stream_id,
+                             int iteration, long long npts, const double *grid_dev,
+                             double *sums_dev, double *hist_dev, void *hip_stream) {
+  if (!ctx || !grid_dev || !sums_dev || !hist_dev || iteration < 0 || iteration >= (1 << 24) ||
+      npts < 2)
+    return CCUBA_EINVAL;
+  VegasSpec sp;
+  int rc = fill_spec(sp, ndim, 1, f, 0.0, 0.0, flags & CCUBA_PRECISION_MASK, seed, 0,
+                     1ll << 62, npts, 0, 1, nbins, stream_id);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> g(ctx->lock);
+  CCUBA_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)hip_stream;
+  VegasEngine eng(ctx);
+  if ((rc = eng.setup({sp}, true, s))) return rc;
+  if ((rc = eng.set_iteration(0, iteration, s))) return rc;
+  if ((rc = eng.load_grid(0, iteration & 1, grid_dev, hipMemcpyDeviceToDevice, s))) return rc;
+  if ((rc = eng.dosample_only(s))) return rc;
+  if ((rc = eng.collect(sums_dev, hist_dev, s))) return rc;
+  // the engine's buffers are released on return: finish before that
+  CCUBA_HIP(hipStreamSynchronize(s));
+  return CCUBA_OK;
+}
+
+int ccuba_vegas_batch(ccuba_ctx *ctx, int njobs, const ccuba_job jobs[], ccuba_result out[]) {
+  if (!ctx || njobs < 0 || (njobs > 0 && (!jobs || !out))) return CCUBA_EINVAL;
+  if (njobs == 0) return CCUBA_OK;
+  std::lock_guard<std::mutex> g(ctx->lock);
+  CCUBA_HIP(hipSetDevice(ctx->device));
+  std::vector<VegasSpec> specs;
+  std::vector<int> index(njobs, -1);
+  const double t_submit = ctx->now();
+  for (int q = 0; q < njobs; ++q) {
+    const ccuba_job &jb = jobs[q];
+    out[q] = ccuba_result{};
+    out[q].t_submit = t_submit;
+    VegasSpec sp;
+    int rc = CCUBA_EINVAL;
+    if (jb.method == 0)
+      rc = fill_spec(sp, jb.ndim, 1, &jb.f, jb.epsrel, jb.epsabs, jb.flags, jb.seed,
+                     jb.mineval, jb.maxeval, jb.nstart, jb.nincrease, 1,
+                     jb.nbins > 0 ? jb.nbins : 128, jb.stream_id);
+    out[q].status = rc;
+    if (rc == CCUBA_OK) {
+      index[q] = (int)specs.size();
+      specs.push_back(sp);
+    }
+  }
+  if (specs.empty()) return CCUBA_OK;
+  if (ctx->autotune) {
+    maybe_autotune(ctx, FP32);
+    maybe_autotune(ctx, FP64);
+  }
+  VegasEngine eng(ctx);
+  int rc;
+  if ((rc = eng.setup(specs, specs.size() == 1, ctx->stream))) return rc;
+  if ((rc = eng.run(ctx->stream))) return rc;
+  std::vector<VState> st;
+  if ((rc = eng.read_states(st, ctx->stream))) return rc;
+  const double t_done = ctx->now();
+  for (int q = 0; q < njobs; ++q) {
+    if (index[q] < 0) continue;
+    const VState &s = st[index[q]];
+    out[q].neval = s.neval;
+    out[q].fail = s.fail;
+    out[q].integral = s.integral;
+    out[q].error = s.error;
+    out[q].prob = s.prob;
+    out[q].t_done = t_done;
+  }
+  return CCUBA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,74 @@
+// context.h -- the library context (the analog of the paper's `spin'
+// handle, Sect. 3.2.3) and the device-memory accounting every engine uses.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <chrono>
+#include <memory>
+#include <mutex>
+
+#include "ccuba.h"
+#include "engine.h"
+
+struct ccuba_ctx {
+  int device = 0;
+  int ncu = 256;
+  size_t budget = 0;                // bytes the context may hold on the device
+  std::atomic<size_t> used{0};      // bytes currently held
+  hipStream_t stream = nullptr;     // the context's own stream (default priority)
+  ccuba::VegasTune tune[2];         // per precision: [FP64], [FP32]
+  int use_graph = 1;
+  int autotune = 0;
+  int tuned[2] = {0, 0};
+  int serve_slots = 256;
+  int profile = 0;
+  ccuba_stats stats{};
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+  std::mutex lock;                  // serialises engine use with the server thread
+  double now() const {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+};
+
+namespace ccuba {
+
+// Device allocation charged to a context's budget.  Returns CCUBA_OK,
+// CCUBA_ENOMEM (budget) or CCUBA_EHIP.
+int dev_alloc(ccuba_ctx *ctx, void **p, size_t bytes);
+void dev_free(ccuba_ctx *ctx, void *p, size_t bytes);
+
+// A typed device buffer that returns its bytes to the context on release.
+template <typename T>
+struct DevBuf {
+  ccuba_ctx *ctx = nullptr;
+  T *p = nullptr;
+  size_t n = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  ~DevBuf() { release(); }
+  int alloc(ccuba_ctx *c, size_t count) {
+    release();
+    ctx = c;
+    if (count == 0) count = 1;
+    void *q = nullptr;
+    const int rc = dev_alloc(c, &q, count * sizeof(T));
+    if (rc != 0) return rc;
+    p = (T *)q;
+    n = count;
+    return 0;
+  }
+  void release() {
+    if (p) dev_free(ctx, p, n * sizeof(T));
+    p = nullptr;
+    n = 0;
+  }
+};
+
+}  // namespace ccuba
+
+#define CCUBA_HIP(call)                       \
+  do {                                        \
+    if ((call) != hipSuccess) return CCUBA_EHIP; \
+  } while (0)

@@ -1,0 +1,129 @@
+// tune.cpp -- launch-geometry autotuner of the DoSample kernel.
+//
+// The sweep times one DoSample pass (no refinement) of a fixed synthetic
+// integral -- d = 8, oscillatory, 128 bins, 2^23 points -- for every
+// candidate (block size, persistent blocks per CU, FP32 histogram precision)
+// and keeps the fastest.  Results do not depend on the choice beyond
+// floating-point summation order.  The cache file holds one line per
+// (device name, precision): "name prec block blocks_per_cu hist64".
+#include "tune.h"
+
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+
+#include "vegas_engine.h"
+
+namespace ccuba {
+
+namespace {
+
+std::string device_key(ccuba_ctx *ctx) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, ctx->device) != hipSuccess) return "unknown";
+  std::string s = prop.gcnArchName;
+  s += "_cu" + std::to_string(prop.multiProcessorCount);
+  for (char &c : s)
+    if (c == ' ' || c == ':') c = '_';
+  return s;
+}
+
+bool load_cache(const char *path, const std::string &key, int prec, VegasTune &t) {
+  std::ifstream f(path);
+  std::string line;
+  while (std::getline(f, line)) {
+    std::istringstream is(line);
+    std::string k;
+    int p, b, bpc, h;
+    if (!(is >> k >> p >> b >> bpc >> h)) continue;
+    if (k == key && p == prec) {
+      t.block = b;
+      t.blocks_per_cu = bpc;
+      t.hist64 = h;
+      return true;
+    }
+  }
+  return false;
+}
+
+void store_cache(const char *path, const std::string &key, int prec, const VegasTune &t) {
+  std::ofstream f(path, std::ios::app);
+  f << key << " " << prec << " " << t.block << " " << t.blocks_per_cu << " " << t.hist64 << "\n";
+}
+
+double time_candidate(ccuba_ctx *ctx, int prec, const VegasTune &cand) {
+  const VegasTune saved = ctx->tune[prec];
+  ctx->tune[prec] = cand;
+  VegasSpec sp;
+  sp.ndim = 8;
+  sp.nbins = 128;
+  sp.family = 1;
+  sp.prec = prec;
+  sp.nstart = 1 << 23;
+  sp.maxeval = 1ll << 40;
+  for (int j = 0; j < 8; ++j) {
+    sp.a[j] = 9.0 / 8.0;
+    sp.u[j] = 0.1 * j;
+  }
+  double best = 1e30;
+  {
+    VegasEngine eng(ctx);
+    if (eng.setup({sp}, true, ctx->stream) == 0) {
+      hipEvent_t a, b;
+      if (hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess) {
+        (void)eng.dosample_only(ctx->stream);  // warm-up
+        for (int r = 0; r < 3; ++r) {
+          (void)hipEventRecord(a, ctx->stream);
+          (void)eng.dosample_only(ctx->stream);
+          (void)hipEventRecord(b, ctx->stream);
+          if (hipEventSynchronize(b) != hipSuccess) break;
+          float ms = 0;
+          (void)hipEventElapsedTime(&ms, a, b);
+          if (ms < best) best = ms;
+        }
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+      }
+    }
+  }
+  ctx->tune[prec] = saved;
+  return best;
+}
+
+}  // namespace
+
+void maybe_autotune(ccuba_ctx *ctx, int prec) {
+  if (ctx->tuned[prec]) return;
+  ctx->tuned[prec] = 1;
+  const char *path = std::getenv("CCUBA_TUNE_CACHE");
+  const std::string key = device_key(ctx);
+  VegasTune t = ctx->tune[prec];
+  if (path && *path && load_cache(path, key, prec, t)) {
+    ctx->tune[prec] = t;
+    return;
+  }
+  VegasTune best = ctx->tune[prec];
+  double best_ms = 1e30;
+  const int blocks[] = {128, 256};
+  const int bpcs[] = {2, 4, 8};
+  for (int b : blocks)
+    for (int bpc : bpcs)
+      for (int h = 0; h < (prec == FP32 ? 2 : 1); ++h) {
+        VegasTune c = ctx->tune[prec];
+        c.block = b;
+        c.blocks_per_cu = bpc;
+        c.hist64 = h;
+        const double ms = time_candidate(ctx, prec, c);
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = c;
+        }
+      }
+  ctx->tune[prec] = best;
+  if (path && *path) store_cache(path, key, prec, best);
+}
+
+}  // namespace ccuba

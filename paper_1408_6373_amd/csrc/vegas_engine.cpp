@@ -1,0 +1,430 @@
+// vegas_engine.cpp -- host driver of the batched Vegas DoSample engine.
+#include "vegas_engine.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+namespace ccuba {
+
+namespace {
+
+const double kTwoPi = 6.283185307179586476925286766559;
+const double kLog2e = 1.4426950408889634073599246810019;
+
+long long round_up(long long v, long long m) { return (v + m - 1) / m * m; }
+size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
+
+template <typename T>
+int upload(DevBuf<T> &b, const std::vector<T> &h, hipStream_t s) {
+  if (h.empty()) return 0;
+  CCUBA_HIP(hipMemcpyAsync(b.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  return 0;
+}
+
+}  // namespace
+
+int validate_vegas(const VegasSpec &s) {
+  if (s.ndim < 1 || s.ndim > kMaxDim || s.nbins < 2 || s.nbins > kMaxBins ||
+      s.nstart < 2 || s.nincrease < 0 || s.family < 0 || s.family > 4 ||
+      (s.prec != FP64 && s.prec != FP32) || s.maxeval < 0 || s.nstart >= (1ll << 32) ||
+      !(s.epsrel >= 0) || !(s.epsabs >= 0))
+    return CCUBA_EINVAL;
+  for (int j = 0; j < s.ndim; ++j)
+    if (!std::isfinite(s.a[j]) || !std::isfinite(s.u[j])) return CCUBA_EINVAL;
+  return CCUBA_OK;
+}
+
+void vegas_budget(const VegasSpec &s, int *iters, long long *nmax) {
+  long long used = 0, nm = s.nstart;
+  int t = 0;
+  while (t < kIterCap) {
+    const long long n = s.nstart + (long long)t * s.nincrease;
+    if (n >= (1ll << 32) || used + n > s.maxeval) break;
+    used += n;
+    nm = n;
+    ++t;
+  }
+  *iters = t;
+  *nmax = nm;
+}
+
+void genz_constants(const VegasSpec &s, double p64[2][kParamRow], float p32[2][kParamRow]) {
+  for (int w = 0; w < 2; ++w)
+    for (int j = 0; j < kParamRow; ++j) {
+      p64[w][j] = 0.0;
+      p32[w][j] = 0.0f;
+    }
+  for (int j = 0; j < s.ndim; ++j) {
+    const double a = s.a[j], u = s.u[j];
+    switch (s.family) {
+      case GAUSSIAN:
+        p64[0][j] = a * a;
+        p64[1][j] = u;
+        p32[0][j] = (float)(a * a * kLog2e);
+        p32[1][j] = (float)u;
+        break;
+      case OSCILLATORY:
+        p64[0][j] = a;
+        p32[0][j] = (float)(a / kTwoPi);
+        break;
+      case PRODUCT_PEAK:
+        p64[0][j] = 1.0 / (a * a);
+        p64[1][j] = u;
+        p32[0][j] = (float)(1.0 / (a * a));
+        p32[1][j] = (float)u;
+        break;
+      case CORNER_PEAK:
+        p64[0][j] = a;
+        p32[0][j] = (float)a;
+        break;
+      default:  // C0
+        p64[0][j] = a;
+        p64[1][j] = u;
+        p32[0][j] = (float)(a * kLog2e);
+        p32[1][j] = (float)u;
+        break;
+    }
+  }
+  if (s.family == OSCILLATORY) {
+    p64[1][0] = kTwoPi * s.u[0];
+    p32[1][0] = (float)s.u[0];
+  }
+}
+
+VegasEngine::~VegasEngine() {
+  if (graph_exec_) (void)hipGraphExecDestroy(graph_exec_);
+  if (graph_) (void)hipGraphDestroy(graph_);
+}
+
+int VegasEngine::setup(const std::vector<VegasSpec> &specs, bool single, hipStream_t s) {
+  specs_ = specs;
+  const int n = (int)specs.size();
+  if (n == 0) return CCUBA_EINVAL;
+  for (const auto &sp : specs)
+    if (validate_vegas(sp) != CCUBA_OK) return CCUBA_EINVAL;
+  hist64_ = ctx_->tune[FP32].hist64;
+  for (int p = 0; p < 2; ++p) {
+    block_[p] = ctx_->tune[p].block;
+    has_prec_[p] = 0;
+  }
+  std::vector<int> iters(n);
+  std::vector<long long> nmax(n);
+  long long total[2] = {0, 0};
+  max_iters_ = 0;
+  evals_iter_ = 0;
+  for (int j = 0; j < n; ++j) {
+    vegas_budget(specs[j], &iters[j], &nmax[j]);
+    max_iters_ = std::max(max_iters_, iters[j]);
+    total[specs[j].prec] += nmax[j];
+    has_prec_[specs[j].prec] = 1;
+    if (iters[j] > 0) evals_iter_ += specs[j].nstart;
+  }
+  // tile plan
+  hjobs_.assign(n, VJob{});
+  std::vector<int> tile_job;
+  long long goff = 0, thoff = 0, ghoff = 0, ioff = 0;
+  int tile0 = 0, group0 = 0;
+  size_t grid_bytes[2] = {0, 0}, hist_bytes[2] = {0, 0}, refine_bytes = 0;
+  for (int j = 0; j < n; ++j) {
+    const VegasSpec &sp = specs[j];
+    const int p = sp.prec;
+    const int bs = block_[p];
+    const long long B = (long long)ctx_->ncu * ctx_->tune[p].blocks_per_cu;
+    long long P;
+    if (single) {
+      P = round_up((nmax[j] + B - 1) / B, bs);
+    } else {
+      const long long target = round_up((total[p] + B * 8 - 1) / (B * 8), bs);
+      P = std::max(round_up(ctx_->tune[p].min_tile, bs), target);
+    }
+    P = std::max<long long>(P, bs);
+    const int nt = (int)std::max<long long>(1, (nmax[j] + P - 1) / P);
+    VJob &J = hjobs_[j];
+    J.ndim = sp.ndim;
+    J.nbins = sp.nbins;
+    J.family = sp.family;
+    J.prec = p;
+    J.flags = sp.flags;
+    J.key0 = (uint32_t)(sp.seed & 0xffffffffull);
+    J.key1 = (uint32_t)(sp.seed >> 32);
+    J.sid = sp.sid;
+    J.nstart = sp.nstart;
+    J.nincrease = sp.nincrease;
+    J.mineval = sp.mineval;
+    J.maxeval = sp.maxeval;
+    J.epsrel = sp.epsrel;
+    J.epsabs = sp.epsabs;
+    J.tile0 = tile0;
+    J.ntiles = nt;
+    J.tile_pts = P;
+    J.group0 = group0;
+    J.hist_cap = std::max(1, iters[j]);
+    const long long dN = (long long)sp.ndim * sp.nbins, row = (long long)sp.ndim * (sp.nbins + 1);
+    J.grid_off = goff;
+    J.thist_off = thoff;
+    J.ghist_off = ghoff;
+    J.iter_off = ioff;
+    J.param_off = j;
+    goff += 2 * row;
+    thoff += nt * dN;
+    ghoff += ngroups_of(nt) * dN;
+    ioff += J.hist_cap;
+    for (int q = 0; q < nt; ++q) tile_job.push_back(j);
+    tile0 += nt;
+    group0 += ngroups_of(nt);
+    const size_t tsz = p == FP64 ? 8 : 4, hsz = (p == FP64 || hist64_) ? 8 : 4;
+    grid_bytes[p] = std::max(grid_bytes[p], align16(row * tsz));
+    hist_bytes[p] = std::max(hist_bytes[p], (size_t)dN * hsz);
+    refine_bytes = std::max(refine_bytes, (size_t)(2 * dN * 8));
+  }
+  ntiles_ = tile0;
+  ngroups_ = group0;
+  for (int p = 0; p < 2; ++p) {
+    grid_bytes_[p] = grid_bytes[p];
+    lds_dosample_[p] = grid_bytes[p] + hist_bytes[p];
+    const long long B = (long long)ctx_->ncu * ctx_->tune[p].blocks_per_cu;
+    nblocks_[p] = (int)std::min<long long>(B, ntiles_);
+  }
+  lds_refine_ = refine_bytes;
+
+  int rc;
+  if ((rc = jobs_.alloc(ctx_, n)) || (rc = state_.alloc(ctx_, n)) ||
+      (rc = tile_job_.alloc(ctx_, ntiles_)) || (rc = grids_.alloc(ctx_, goff)) ||
+      (rc = p64_.alloc(ctx_, (size_t)n * 2 * kParamRow)) ||
+      (rc = p32_.alloc(ctx_, (size_t)n * 2 * kParamRow)) ||
+      (rc = tile_sums_.alloc(ctx_, 2 * (size_t)ntiles_)) || (rc = tile_hist_.alloc(ctx_, thoff)) ||
+      (rc = group_sums_.alloc(ctx_, 2 * (size_t)ngroups_)) ||
+      (rc = group_hist_.alloc(ctx_, ghoff)) || (rc = group_cnt_.alloc(ctx_, ngroups_)) ||
+      (rc = iter_I_.alloc(ctx_, ioff)) || (rc = iter_var_.alloc(ctx_, ioff)))
+    return rc;
+
+  std::vector<double> grids(goff), p64((size_t)n * 2 * kParamRow);
+  std::vector<float> p32((size_t)n * 2 * kParamRow);
+  std::vector<VState> st(n);
+  for (int j = 0; j < n; ++j) {
+    const VegasSpec &sp = specs[j];
+    const int N = sp.nbins, row = N + 1;
+    for (int c = 0; c < 2; ++c)
+      for (int d = 0; d < sp.ndim; ++d)
+        for (int k = 0; k <= N; ++k)
+          grids[hjobs_[j].grid_off + (long long)c * sp.ndim * row + (long long)d * row + k] =
+              (double)k / N;
+    double a64[2][kParamRow];
+    float a32[2][kParamRow];
+    genz_constants(sp, a64, a32);
+    std::memcpy(&p64[(size_t)j * 2 * kParamRow], a64, sizeof(a64));
+    std::memcpy(&p32[(size_t)j * 2 * kParamRow], a32, sizeof(a32));
+    st[j] = VState{};
+    if (iters[j] == 0) {
+      st[j].done = 1;
+      st[j].fail = 1;
+    }
+  }
+  if ((rc = upload(jobs_, hjobs_, s)) || (rc = upload(tile_job_, tile_job, s)) ||
+      (rc = upload(grids_, grids, s)) || (rc = upload(p64_, p64, s)) ||
+      (rc = upload(p32_, p32, s)) || (rc = upload(state_, st, s)))
+    return rc;
+  CCUBA_HIP(hipMemsetAsync(group_cnt_.p, 0, ngroups_ * sizeof(unsigned), s));
+
+  args_.jobs = jobs_.p;
+  args_.state = state_.p;
+  args_.tile_job = tile_job_.p;
+  args_.ntiles = ntiles_;
+  args_.hist64 = hist64_;
+  args_.grids = grids_.p;
+  args_.p64 = p64_.p;
+  args_.p32 = p32_.p;
+  args_.tile_sums = tile_sums_.p;
+  args_.tile_hist = tile_hist_.p;
+  args_.group_sums = group_sums_.p;
+  args_.group_hist = group_hist_.p;
+  args_.group_cnt = group_cnt_.p;
+  args_.iter_I = iter_I_.p;
+  args_.iter_var = iter_var_.p;
+  // host copies of the tables must outlive the async uploads
+  CCUBA_HIP(hipStreamSynchronize(s));
+  return CCUBA_OK;
+}
+
+int VegasEngine::dosample_only(hipStream_t s) {
+  for (int p = 0; p < 2; ++p) {
+    if (!has_prec_[p]) continue;
+    VegasArgs A = args_;
+    A.lds_hist_byte_off = (long long)grid_bytes_[p];  // histogram follows the grid copy
+    CCUBA_HIP(launch_dosample(A, p, nblocks_[p], block_[p], lds_dosample_[p], s));
+  }
+  return CCUBA_OK;
+}
+
+int VegasEngine::launch_iteration(hipStream_t s) {
+  if (ctx_->profile && !capturing_) {
+    // time each kernel with events on the stream it runs on
+    hipEvent_t ev[3];
+    for (auto &e : ev) CCUBA_HIP(hipEventCreate(&e));
+    CCUBA_HIP(hipEventRecord(ev[0], s));
+    int rc = dosample_only(s);
+    if (rc) return rc;
+    CCUBA_HIP(hipEventRecord(ev[1], s));
+    CCUBA_HIP(launch_refine(args_, njobs(), lds_refine_, s));
+    CCUBA_HIP(hipEventRecord(ev[2], s));
+    pending_.push_back({ev[0], ev[1], ev[2], iter_launched_++});
+    return CCUBA_OK;
+  }
+  int rc = dosample_only(s);
+  if (rc) return rc;
+  CCUBA_HIP(launch_refine(args_, njobs(), lds_refine_, s));
+  ++iter_launched_;
+  return CCUBA_OK;
+}
+
+int VegasEngine::flush_timing() {
+  for (auto &p : pending_) {
+    float a = 0, b = 0;
+    CCUBA_HIP(hipEventSynchronize(p.e2));
+    CCUBA_HIP(hipEventElapsedTime(&a, p.e0, p.e1));
+    CCUBA_HIP(hipEventElapsedTime(&b, p.e1, p.e2));
+    ctx_->stats.dosample_launches += 1;
+    ctx_->stats.dosample_ms += a;
+    ctx_->stats.refine_launches += 1;
+    ctx_->stats.refine_ms += b;
+    (void)hipEventDestroy(p.e0);
+    (void)hipEventDestroy(p.e1);
+    (void)hipEventDestroy(p.e2);
+  }
+  pending_.clear();
+  return CCUBA_OK;
+}
+
+int VegasEngine::step(hipStream_t s) { return launch_iteration(s); }
+
+int VegasEngine::run(hipStream_t s) {
+  bool fixed = true;
+  for (const auto &sp : specs_)
+    if (sp.epsrel > 0 || sp.epsabs > 0) fixed = false;
+  int remaining = max_iters_;
+  if (remaining == 0) return CCUBA_OK;
+  const bool graph = ctx_->use_graph != 0 && !ctx_->profile;
+  if (graph && !graph_exec_) {
+    CCUBA_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    capturing_ = true;
+    const int rc = launch_iteration(s);
+    capturing_ = false;
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &g);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return CCUBA_EHIP;
+    graph_ = g;
+    CCUBA_HIP(hipGraphInstantiate(&graph_exec_, graph_, nullptr, nullptr, 0));
+  }
+  int chunk = fixed ? remaining : 2;
+  std::vector<VState> st;
+  while (remaining > 0) {
+    const int k = std::min(chunk, remaining);
+    for (int q = 0; q < k; ++q) {
+      if (graph) {
+        CCUBA_HIP(hipGraphLaunch(graph_exec_, s));
+      } else {
+        const int rc = launch_iteration(s);
+        if (rc) return rc;
+      }
+    }
+    remaining -= k;
+    if (remaining > 0) {
+      const int rc = read_states(st, s);
+      if (rc) return rc;
+      bool all = true;
+      for (const auto &x : st) all = all && x.done;
+      if (all) break;
+      chunk = std::min(chunk * 2, 32);
+    }
+  }
+  CCUBA_HIP(hipStreamSynchronize(s));
+  if (ctx_->profile) {
+    // every point a timed DoSample launch sampled is in some job's neval
+    int rc = read_states(st, s);
+    if (rc) return rc;
+    for (const auto &x : st) ctx_->stats.evals += x.neval;
+  }
+  return flush_timing();
+}
+
+int VegasEngine::read_states(std::vector<VState> &out, hipStream_t s) {
+  out.resize(njobs());
+  CCUBA_HIP(hipMemcpyAsync(out.data(), state_.p, njobs() * sizeof(VState),
+                           hipMemcpyDeviceToHost, s));
+  CCUBA_HIP(hipStreamSynchronize(s));
+  return CCUBA_OK;
+}
+
+int VegasEngine::read_history(int job, int n, double *I, double *var, hipStream_t s) {
+  if (job < 0 || job >= njobs()) return CCUBA_EINVAL;
+  n = std::min(n, hjobs_[job].hist_cap);
+  if (n <= 0) return CCUBA_OK;
+  if (I)
+    CCUBA_HIP(hipMemcpyAsync(I, iter_I_.p + hjobs_[job].iter_off, n * sizeof(double),
+                             hipMemcpyDeviceToHost, s));
+  if (var)
+    CCUBA_HIP(hipMemcpyAsync(var, iter_var_.p + hjobs_[job].iter_off, n * sizeof(double),
+                             hipMemcpyDeviceToHost, s));
+  CCUBA_HIP(hipStreamSynchronize(s));
+  return CCUBA_OK;
+}
+
+int VegasEngine::read_grid(int job, int T, double *grid, hipStream_t s) {
+  if (job < 0 || job >= njobs()) return CCUBA_EINVAL;
+  const VJob &J = hjobs_[job];
+  const long long row = (long long)J.ndim * (J.nbins + 1);
+  CCUBA_HIP(hipMemcpyAsync(grid, grids_.p + J.grid_off + (long long)(T & 1) * row,
+                           row * sizeof(double), hipMemcpyDeviceToHost, s));
+  CCUBA_HIP(hipStreamSynchronize(s));
+  return CCUBA_OK;
+}
+
+int VegasEngine::set_iteration(int job, int t, hipStream_t s) {
+  if (job < 0 || job >= njobs()) return CCUBA_EINVAL;
+  VState st{};
+  st.T = t;
+  // the state is a pinned-free host value; copy synchronously to keep it alive
+  CCUBA_HIP(hipMemcpyAsync(state_.p + job, &st, sizeof(VState), hipMemcpyHostToDevice, s));
+  CCUBA_HIP(hipStreamSynchronize(s));
+  return CCUBA_OK;
+}
+
+int VegasEngine::load_grid(int job, int copy, const double *src, hipMemcpyKind kind,
+                           hipStream_t s) {
+  const VJob &J = hjobs_[job];
+  const long long row = (long long)J.ndim * (J.nbins + 1);
+  CCUBA_HIP(hipMemcpyAsync(grids_.p + J.grid_off + (long long)(copy & 1) * row, src,
+                           row * sizeof(double), kind, s));
+  if (kind == hipMemcpyHostToDevice) CCUBA_HIP(hipStreamSynchronize(s));
+  return CCUBA_OK;
+}
+
+int VegasEngine::collect(double *sums_dev, double *hist_dev, hipStream_t s) {
+  CCUBA_HIP(launch_collect(args_, 1, sums_dev, hist_dev, s));
+  return CCUBA_OK;
+}
+
+int VegasEngine::refine_only(const double *hist, const double *grid_in, double *grid_out,
+                             hipStream_t s) {
+  const VJob &J = hjobs_[0];
+  const long long dN = (long long)J.ndim * J.nbins;
+  int rc = load_grid(0, 0, grid_in, hipMemcpyHostToDevice, s);
+  if (rc) return rc;
+  // a synthetic finished iteration with n = 2, S1 = 1, S2 = 2 (I = 1/2,
+  // sigma^2 = 3/4 > 0, so the zero-tolerance job never converges)
+  const double sums[2] = {1.0, 2.0};
+  CCUBA_HIP(hipMemcpyAsync(group_sums_.p, sums, sizeof(sums), hipMemcpyHostToDevice, s));
+  CCUBA_HIP(hipMemcpyAsync(group_hist_.p, hist, dN * sizeof(double), hipMemcpyHostToDevice, s));
+  CCUBA_HIP(hipStreamSynchronize(s));
+  rc = set_iteration(0, 0, s);
+  if (rc) return rc;
+  CCUBA_HIP(launch_refine(args_, 1, lds_refine_, s));
+  return read_grid(0, 1, grid_out, s);
+}
+
+}  // namespace ccuba

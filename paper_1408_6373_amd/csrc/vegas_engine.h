@@ -1,0 +1,98 @@
+// vegas_engine.h -- host driver of the batched Vegas DoSample engine.
+//
+// One engine holds any number of independent Vegas integrals resident on the
+// device (grids, parameters, partial sums, iteration history, state) and
+// advances all of them one iteration per launch pair (DoSample + refine).
+// A single integral is an engine with one job.
+#pragma once
+#include <vector>
+
+#include "context.h"
+#include "vegas.h"
+
+namespace ccuba {
+
+constexpr int kIterCap = 4096;  // iterations kept per integral
+
+// Host description of one Vegas integral.
+struct VegasSpec {
+  int ndim = 1, nbins = 128, family = 0, prec = FP64, flags = 0;
+  unsigned long long seed = 0;
+  uint32_t sid = 0;
+  long long nstart = 1000, nincrease = 0, mineval = 0, maxeval = 0;
+  double epsrel = 0, epsabs = 0;
+  double a[kMaxDim] = {0}, u[kMaxDim] = {0};
+};
+
+// Validate a spec; CCUBA_OK or CCUBA_EINVAL.
+int validate_vegas(const VegasSpec &s);
+// Iterations the budget allows and the largest n_t among them.
+void vegas_budget(const VegasSpec &s, int *iters, long long *nmax);
+// The per-dimension constants of the device Genz code (see genz.h).
+void genz_constants(const VegasSpec &s, double p64[2][kParamRow], float p32[2][kParamRow]);
+
+class VegasEngine {
+ public:
+  explicit VegasEngine(ccuba_ctx *ctx) : ctx_(ctx) {}
+  // Allocate and upload; `single' plans tiles for one large integral.
+  int setup(const std::vector<VegasSpec> &specs, bool single, hipStream_t s);
+  // One iteration of every unfinished job (async on s).
+  int step(hipStream_t s);
+  // Iterate until every job is done; replays a captured graph if enabled.
+  int run(hipStream_t s);
+  int read_states(std::vector<VState> &out, hipStream_t s);
+  int read_history(int job, int n, double *I, double *var, hipStream_t s);
+  int read_grid(int job, int T, double *grid, hipStream_t s);
+  // Raw pieces: set iteration index of job 0, run DoSample only, and sum the
+  // group partials into caller buffers.
+  int set_iteration(int job, int t, hipStream_t s);
+  int load_grid(int job, int copy, const double *src, hipMemcpyKind kind, hipStream_t s);
+  int dosample_only(hipStream_t s);
+  int collect(double *sums_dev, double *hist_dev, hipStream_t s);
+  // One refinement of job 0 from a given histogram and grid.
+  int refine_only(const double *hist, const double *grid_in, double *grid_out, hipStream_t s);
+
+  int njobs() const { return (int)specs_.size(); }
+  int max_iters() const { return max_iters_; }
+  long long evals_per_iteration() const { return evals_iter_; }
+  const std::vector<VegasSpec> &specs() const { return specs_; }
+  // launch geometry actually used
+  int grid_blocks(int prec) const { return nblocks_[prec]; }
+  int block() const { return block_[1]; }
+
+ private:
+  int launch_iteration(hipStream_t s);
+  int flush_timing();
+  struct Timed {
+    hipEvent_t e0, e1, e2;
+    int iter;
+  };
+  std::vector<Timed> pending_;
+  bool capturing_ = false;
+  int iter_launched_ = 0;
+  ccuba_ctx *ctx_;
+  std::vector<VegasSpec> specs_;
+  std::vector<VJob> hjobs_;
+  DevBuf<VJob> jobs_;
+  DevBuf<VState> state_;
+  DevBuf<int> tile_job_;
+  DevBuf<double> grids_, p64_, tile_sums_, tile_hist_, group_sums_, group_hist_, iter_I_,
+      iter_var_;
+  DevBuf<float> p32_;
+  DevBuf<unsigned> group_cnt_;
+  VegasArgs args_{};
+  int ntiles_ = 0, ngroups_ = 0;
+  int has_prec_[2] = {0, 0};
+  int nblocks_[2] = {0, 0}, block_[2] = {256, 256};
+  size_t lds_dosample_[2] = {0, 0}, grid_bytes_[2] = {0, 0}, lds_refine_ = 0;
+  int hist64_ = 0;
+  int max_iters_ = 0;
+  long long evals_iter_ = 0;
+  hipGraphExec_t graph_exec_ = nullptr;
+  hipGraph_t graph_ = nullptr;
+
+ public:
+  ~VegasEngine();
+};
+
+}  // namespace ccuba
