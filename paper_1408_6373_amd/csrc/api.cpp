@@ -8,6 +8,7 @@
 
 #include "ccuba.h"
 #include "context.h"
+#include "cuhre_engine.h"
 #include "tune.h"
 #include "vegas_engine.h"
 
@@ -348,6 +349,68 @@ int ccuba_vegas_dosample_raw(ccuba_ctx *ctx, int ndim, int nbins, const ccuba_in
   // the engine's buffers are released on return: finish before that
   CCUBA_HIP(hipStreamSynchronize(s));
   return CCUBA_OK;
+}
+
+int ccuba_cuhre(ccuba_ctx **ctxp, int ndim, int ncomp, const ccuba_integrand *f, double epsrel,
+                double epsabs, int flags, long long mineval, long long maxeval, int key,
+                long long max_regions_per_batch, int *nregions, long long *neval, int *fail,
+                double integral[], double error[], double prob[]) {
+  if (!f || !f->a || !f->u || ncomp != 1 || (key != 0 && key != 7) || !nregions || !neval ||
+      !fail || !integral || !error || !prob || ndim < 2 || ndim > kMaxDim ||
+      (flags & CCUBA_PRECISION_MASK) != CCUBA_FP64)
+    return CCUBA_EINVAL;
+  CuhreSpec sp;
+  sp.ndim = ndim;
+  sp.family = f->family;
+  for (int j = 0; j < ndim; ++j) {
+    sp.a[j] = f->a[j];
+    sp.u[j] = f->u[j];
+  }
+  sp.epsrel = epsrel;
+  sp.epsabs = epsabs;
+  sp.mineval = mineval;
+  sp.maxeval = maxeval;
+  sp.batch = max_regions_per_batch;
+  if (validate_cuhre(sp)) return CCUBA_EINVAL;
+  CtxScope scope(ctxp);
+  if (scope.rc) return scope.rc;
+  ccuba_ctx *ctx = scope.ctx;
+  std::lock_guard<std::mutex> g(ctx->lock);
+  CCUBA_HIP(hipSetDevice(ctx->device));
+  CuhreRun run(ctx);
+  int rc;
+  if ((rc = run.start(sp, ctx->stream)) || (rc = run.run(ctx->stream))) return rc;
+  *nregions = (int)std::min<long long>(run.nregions(), 0x7fffffff);
+  *neval = run.neval();
+  *fail = run.fail();
+  integral[0] = run.integral();
+  error[0] = run.error();
+  prob[0] = 0.0;
+  return CCUBA_OK;
+}
+
+int ccuba_cuhre_rule(ccuba_ctx *ctx, int ndim, const ccuba_integrand *f, long long nreg,
+                     const double *c, const double *h, double *I7, double *I5, double *err,
+                     int *axis) {
+  if (!ctx || !f || !f->a || !f->u || ndim < 2 || ndim > kMaxDim || nreg < 0 || !c || !h)
+    return CCUBA_EINVAL;
+  if (nreg == 0) return CCUBA_OK;
+  CuhreSpec sp;
+  sp.ndim = ndim;
+  sp.family = f->family;
+  for (int j = 0; j < ndim; ++j) {
+    sp.a[j] = f->a[j];
+    sp.u[j] = f->u[j];
+  }
+  sp.maxeval = (nreg + 2) * gm_npoints(ndim) * 2;
+  sp.batch = 2;
+  if (validate_cuhre(sp)) return CCUBA_EINVAL;
+  std::lock_guard<std::mutex> g(ctx->lock);
+  CCUBA_HIP(hipSetDevice(ctx->device));
+  CuhreRun run(ctx);
+  int rc = run.start(sp, ctx->stream);
+  if (rc) return rc;
+  return run.rule_only(nreg, c, h, I7, I5, err, axis, ctx->stream);
 }
 
 int ccuba_vegas_batch(ccuba_ctx *ctx, int njobs, const ccuba_job jobs[], ccuba_result out[]) {

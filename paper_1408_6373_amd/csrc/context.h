@@ -7,6 +7,7 @@
 #include <chrono>
 #include <memory>
 #include <mutex>
+#include <utility>
 
 #include "ccuba.h"
 #include "engine.h"
@@ -63,6 +64,11 @@ struct DevBuf {
     if (p) dev_free(ctx, p, n * sizeof(T));
     p = nullptr;
     n = 0;
+  }
+  void swap(DevBuf &o) {
+    std::swap(ctx, o.ctx);
+    std::swap(p, o.p);
+    std::swap(n, o.n);
   }
 };
 

@@ -1,0 +1,371 @@
+// cuhre_engine.cpp -- host driver of Cuhre (globally adaptive subdivision in
+// batches; see cuhre.hip for the kernels).
+//
+// Readings where the paper is silent (it only fixes the interface, Sect.
+// 3.2.2): error |I7 - I5|; each step splits the K = min(B/2, #regions)
+// regions of largest error (ties: lower id), K shrinking so that neval never
+// passes maxeval; the run ends when neval >= mineval and the summed error is
+// within max(epsabs, epsrel |I|) (fail 0) or when no child fits maxeval
+// (fail 1); the root is region 0 and the j-th selected parent in id order
+// gets children next+2j (lower half) and next+2j+1; prob = 0.
+#include "cuhre_engine.h"
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "genz.h"
+#include "vegas_engine.h"
+
+namespace ccuba {
+
+long long gm_npoints(int d) { return (1ll << d) + 2ll * d * d + 2ll * d + 1; }
+
+int validate_cuhre(const CuhreSpec &s) {
+  if (s.ndim < 2 || s.ndim > kMaxDim || s.family < 0 || s.family > 4 || s.batch < 2 ||
+      s.maxeval < 0 || !(s.epsrel >= 0) || !(s.epsabs >= 0))
+    return CCUBA_EINVAL;
+  for (int j = 0; j < s.ndim; ++j)
+    if (!std::isfinite(s.a[j]) || !std::isfinite(s.u[j])) return CCUBA_EINVAL;
+  return CCUBA_OK;
+}
+
+const GMTables &gm_tables() {
+  static GMTables T = [] {
+    GMTables t{};
+    for (int d = 0; d <= 16; ++d) {
+      const double p2 = std::ldexp(1.0, d), dd = d;
+      double *w7 = t.w7 + 5 * d, *w5 = t.w5 + 5 * d;
+      w7[0] = p2 * (12824.0 - 9120.0 * dd + 400.0 * dd * dd) / 19683.0;
+      w7[1] = p2 * 980.0 / 6561.0;
+      w7[2] = p2 * (1820.0 - 400.0 * dd) / 19683.0;
+      w7[3] = p2 * 200.0 / 19683.0;
+      w7[4] = 6859.0 / 19683.0;
+      w5[0] = p2 * (729.0 - 950.0 * dd + 50.0 * dd * dd) / 729.0;
+      w5[1] = p2 * 245.0 / 486.0;
+      w5[2] = p2 * (265.0 - 100.0 * dd) / 1458.0;
+      w5[3] = p2 * 25.0 / 729.0;
+      w5[4] = 0.0;
+    }
+    t.l2 = std::sqrt(9.0 / 70.0);
+    t.l3 = std::sqrt(9.0 / 10.0);
+    t.l4 = std::sqrt(9.0 / 10.0);
+    t.l5 = std::sqrt(9.0 / 19.0);
+    return t;
+  }();
+  return T;
+}
+
+size_t CuhreRun::bytes() const {
+  const int d = spec_.ndim;
+  return (size_t)cap_ * 2 * (2 * d * 8 + 3 * 8 + 4 + 8) + (size_t)cap_ * 4;
+}
+
+int CuhreRun::alloc_store(CRegions &R, DevBuf<double> &cb, DevBuf<double> &hb,
+                          DevBuf<double> &vals, DevBuf<int> &ax, DevBuf<long long> &ids,
+                          long long cap) {
+  const int d = spec_.ndim;
+  int rc;
+  if ((rc = cb.alloc(ctx_, (size_t)d * cap)) || (rc = hb.alloc(ctx_, (size_t)d * cap)) ||
+      (rc = vals.alloc(ctx_, (size_t)3 * cap)) || (rc = ax.alloc(ctx_, cap)) ||
+      (rc = ids.alloc(ctx_, cap)))
+    return rc;
+  R.c = cb.p;
+  R.h = hb.p;
+  R.I7 = vals.p;
+  R.I5 = vals.p + cap;
+  R.err = vals.p + 2 * cap;
+  R.axis = ax.p;
+  R.id = ids.p;
+  R.cap = cap;
+  return CCUBA_OK;
+}
+
+// Grow both stores to hold `need' regions, keeping the leaves in store cur_.
+int CuhreRun::ensure(long long need, hipStream_t s) {
+  if (need <= cap_) return CCUBA_OK;
+  long long cap = std::max<long long>(cap_ * 2, need);
+  const long long limit = spec_.maxeval / np_ + 2;  // no run can hold more regions
+  cap = std::max(need, std::min(cap, limit));
+  const int d = spec_.ndim;
+  // new store for the leaves, copy, then a fresh second store
+  CRegions R{};
+  DevBuf<double> cb, hb, vals;
+  DevBuf<int> ax;
+  DevBuf<long long> ids;
+  int rc = alloc_store(R, cb, hb, vals, ax, ids, cap);
+  if (rc) return rc;
+  const CRegions &O = R_[cur_];
+  if (n_ > 0) {
+    for (int j = 0; j < d; ++j) {
+      CCUBA_HIP(hipMemcpyAsync(R.c + j * cap, O.c + j * O.cap, n_ * 8, hipMemcpyDeviceToDevice, s));
+      CCUBA_HIP(hipMemcpyAsync(R.h + j * cap, O.h + j * O.cap, n_ * 8, hipMemcpyDeviceToDevice, s));
+    }
+    CCUBA_HIP(hipMemcpyAsync(R.I7, O.I7, n_ * 8, hipMemcpyDeviceToDevice, s));
+    CCUBA_HIP(hipMemcpyAsync(R.I5, O.I5, n_ * 8, hipMemcpyDeviceToDevice, s));
+    CCUBA_HIP(hipMemcpyAsync(R.err, O.err, n_ * 8, hipMemcpyDeviceToDevice, s));
+    CCUBA_HIP(hipMemcpyAsync(R.axis, O.axis, n_ * 4, hipMemcpyDeviceToDevice, s));
+    CCUBA_HIP(hipMemcpyAsync(R.id, O.id, n_ * 8, hipMemcpyDeviceToDevice, s));
+  }
+  CCUBA_HIP(hipStreamSynchronize(s));
+  // release the old stores before taking the second new one
+  for (int q = 0; q < 2; ++q) {
+    c_[q].release();
+    h_[q].release();
+    vals_[q].release();
+    axis_[q].release();
+    id_[q].release();
+  }
+  c_[0].swap(cb);
+  h_[0].swap(hb);
+  vals_[0].swap(vals);
+  axis_[0].swap(ax);
+  id_[0].swap(ids);
+  R_[0] = R;
+  cur_ = 0;
+  if ((rc = alloc_store(R_[1], c_[1], h_[1], vals_[1], axis_[1], id_[1], cap))) return rc;
+  const long long nb = scratch_blocks(cap);
+  if ((rc = flag_.alloc(ctx_, cap)) || (rc = bsum_.alloc(ctx_, nb)) ||
+      (rc = tot_.alloc(ctx_, 2 * nb)))
+    return rc;
+  cap_ = cap;
+  S_.flag = flag_.p;
+  S_.bsum = bsum_.p;
+  S_.tot = tot_.p;
+  S_.nbmax = nb;
+  return CCUBA_OK;
+}
+
+int CuhreRun::start(const CuhreSpec &spec, hipStream_t s) {
+  if (validate_cuhre(spec)) return CCUBA_EINVAL;
+  spec_ = spec;
+  const int d = spec.ndim;
+  np_ = gm_npoints(d);
+  n_ = 0;
+  next_id_ = 1;
+  neval_ = 0;
+  batches_ = 0;
+  done_ = false;
+  fail_ = 1;
+  cap_ = 0;
+  int rc;
+  if ((rc = prefix_.alloc(ctx_, 2)) || (rc = krem_.alloc(ctx_, 2)) ||
+      (rc = hist_.alloc(ctx_, 256)) || (rc = out_.alloc(ctx_, 2)) ||
+      (rc = params_.alloc(ctx_, 2 * kParamRow)) || (rc = w7_.alloc(ctx_, 17 * 5)) ||
+      (rc = w5_.alloc(ctx_, 17 * 5)) || (rc = seg_.alloc(ctx_, 1)) ||
+      (rc = seg_end_.alloc(ctx_, 1)))
+    return rc;
+  S_.prefix = prefix_.p;
+  S_.krem = krem_.p;
+  S_.hist = hist_.p;
+  const long long first_cap = std::max<long long>(
+      16, std::min<long long>(std::min<long long>(spec.batch + 1, 1 << 20), spec.maxeval / np_ + 2));
+  // initial stores
+  if ((rc = alloc_store(R_[0], c_[0], h_[0], vals_[0], axis_[0], id_[0], first_cap)) ||
+      (rc = alloc_store(R_[1], c_[1], h_[1], vals_[1], axis_[1], id_[1], first_cap)))
+    return rc;
+  cap_ = first_cap;
+  const long long nb = scratch_blocks(cap_);
+  if ((rc = flag_.alloc(ctx_, cap_)) || (rc = bsum_.alloc(ctx_, nb)) ||
+      (rc = tot_.alloc(ctx_, 2 * nb)))
+    return rc;
+  S_.flag = flag_.p;
+  S_.bsum = bsum_.p;
+  S_.tot = tot_.p;
+  S_.nbmax = nb;
+  cur_ = 0;
+  // constants
+  VegasSpec vs;
+  vs.ndim = d;
+  vs.family = spec.family;
+  for (int j = 0; j < d; ++j) {
+    vs.a[j] = spec.a[j];
+    vs.u[j] = spec.u[j];
+  }
+  double p64[2][kParamRow];
+  float p32[2][kParamRow];
+  genz_constants(vs, p64, p32);
+  const GMTables &T = gm_tables();
+  CCUBA_HIP(hipMemcpyAsync(params_.p, p64, sizeof(p64), hipMemcpyHostToDevice, s));
+  CCUBA_HIP(hipMemcpyAsync(w7_.p, T.w7, sizeof(T.w7), hipMemcpyHostToDevice, s));
+  CCUBA_HIP(hipMemcpyAsync(w5_.p, T.w5, sizeof(T.w5), hipMemcpyHostToDevice, s));
+  // root region [0,1]^d: centre 1/2, half-width 1/2, id 0
+  std::vector<double> half(d, 0.5);
+  for (int j = 0; j < d; ++j) {
+    CCUBA_HIP(hipMemcpyAsync(R_[0].c + j * cap_, &half[j], 8, hipMemcpyHostToDevice, s));
+    CCUBA_HIP(hipMemcpyAsync(R_[0].h + j * cap_, &half[j], 8, hipMemcpyHostToDevice, s));
+  }
+  const long long zero = 0;
+  CCUBA_HIP(hipMemcpyAsync(R_[0].id, &zero, 8, hipMemcpyHostToDevice, s));
+  CCUBA_HIP(hipStreamSynchronize(s));  // host sources are stack values
+  CSeg seg{};
+  seg.ndim = d;
+  seg.family = spec.family;
+  seg.par = params_.p;
+  seg.first = 0;
+  seg.count = 1;
+  seg.regs = R_[0];
+  n_ = 1;
+  neval_ = np_;
+  return launch_rule_alone(seg, s);
+}
+
+int CuhreRun::launch_rule_alone(const CSeg &seg, hipStream_t s) {
+  return launch_rule_segments(ctx_, &seg, 1, seg_, seg_end_, w7_.p, w5_.p, s);
+}
+
+int launch_rule_segments(ccuba_ctx *ctx, const CSeg *segs, int nseg, DevBuf<CSeg> &dsegs,
+                         DevBuf<long long> &dends, const double *w7_dev, const double *w5_dev,
+                         hipStream_t s) {
+  if (nseg <= 0) return CCUBA_OK;
+  int rc;
+  if ((int)dsegs.n < nseg && (rc = dsegs.alloc(ctx, nseg))) return rc;
+  if ((int)dends.n < nseg && (rc = dends.alloc(ctx, nseg))) return rc;
+  std::vector<long long> ends(nseg);
+  long long tot = 0;
+  for (int q = 0; q < nseg; ++q) {
+    tot += segs[q].count;
+    ends[q] = tot;
+  }
+  CCUBA_HIP(hipMemcpyAsync(dsegs.p, segs, nseg * sizeof(CSeg), hipMemcpyHostToDevice, s));
+  CCUBA_HIP(hipMemcpyAsync(dends.p, ends.data(), nseg * sizeof(long long), hipMemcpyHostToDevice,
+                           s));
+  const GMTables &T = gm_tables();
+  RuleArgs A;
+  A.segs = dsegs.p;
+  A.nseg = nseg;
+  A.seg_end = dends.p;
+  A.total = tot;
+  A.w7 = w7_dev;
+  A.w5 = w5_dev;
+  A.l2 = T.l2;
+  A.l3 = T.l3;
+  A.l4 = T.l4;
+  A.l5 = T.l5;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (ctx->profile) {
+    CCUBA_HIP(hipEventCreate(&e0));
+    CCUBA_HIP(hipEventCreate(&e1));
+    CCUBA_HIP(hipEventRecord(e0, s));
+  }
+  CCUBA_HIP(launch_rule(A, s));
+  if (ctx->profile) {
+    CCUBA_HIP(hipEventRecord(e1, s));
+    CCUBA_HIP(hipEventSynchronize(e1));
+    float ms = 0;
+    CCUBA_HIP(hipEventElapsedTime(&ms, e0, e1));
+    ctx->stats.rule_launches += 1;
+    ctx->stats.rule_ms += ms;
+    long long ev = 0;
+    for (int q = 0; q < nseg; ++q) ev += segs[q].count * gm_npoints(segs[q].ndim);
+    ctx->stats.rule_evals += ev;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  }
+  // the host arrays must stay alive until the copies ran
+  CCUBA_HIP(hipStreamSynchronize(s));
+  return CCUBA_OK;
+}
+
+int CuhreRun::launch_totals(hipStream_t s) {
+  CCUBA_HIP(ccuba::launch_totals(R_[cur_], n_, S_, out_.p, s));
+  return CCUBA_OK;
+}
+
+int CuhreRun::read_totals(hipStream_t s) {
+  double t[2];
+  CCUBA_HIP(hipMemcpyAsync(t, out_.p, sizeof(t), hipMemcpyDeviceToHost, s));
+  CCUBA_HIP(hipStreamSynchronize(s));
+  I_ = t[0];
+  E_ = t[1];
+  return CCUBA_OK;
+}
+
+int CuhreRun::plan_and_split(hipStream_t s) {
+  pendK_ = 0;
+  if (done_) return 0;
+  if (neval_ >= spec_.mineval && E_ <= std::max(spec_.epsabs, spec_.epsrel * std::fabs(I_))) {
+    done_ = true;
+    fail_ = 0;
+    return 0;
+  }
+  long long K = std::min(spec_.batch / 2, n_);
+  const long long budget = spec_.maxeval > neval_ ? (spec_.maxeval - neval_) / (2 * np_) : 0;
+  K = std::min(K, budget);
+  if (K <= 0) {
+    done_ = true;
+    fail_ = 1;
+    return 0;
+  }
+  int rc = ensure(n_ + K, s);
+  if (rc) return rc < 0 ? rc : CCUBA_EHIP;
+  const bool all = K == n_;
+  if (!all) CCUBA_HIP(launch_select(R_[cur_], n_, K, S_, s));
+  CCUBA_HIP(launch_split(R_[cur_], R_[1 - cur_], spec_.ndim, n_, K, next_id_, all, S_, s));
+  cur_ = 1 - cur_;
+  pendK_ = K;
+  return 1;
+}
+
+CSeg CuhreRun::pending_segment() const {
+  CSeg seg{};
+  seg.ndim = spec_.ndim;
+  seg.family = spec_.family;
+  seg.par = params_.p;
+  seg.first = n_ - pendK_;
+  seg.count = 2 * pendK_;
+  seg.regs = R_[cur_];
+  return seg;
+}
+
+void CuhreRun::commit_pending() {
+  n_ += pendK_;
+  next_id_ += 2 * pendK_;
+  neval_ += 2 * pendK_ * np_;
+  ++batches_;
+  pendK_ = 0;
+}
+
+int CuhreRun::run(hipStream_t s) {
+  for (;;) {
+    int rc = launch_totals(s);
+    if (rc) return rc;
+    if ((rc = read_totals(s))) return rc;
+    rc = plan_and_split(s);
+    if (rc < 0) return rc;
+    if (rc == 0) break;
+    if ((rc = launch_rule_alone(pending_segment(), s))) return rc;
+    commit_pending();
+  }
+  return CCUBA_OK;
+}
+
+int CuhreRun::rule_only(long long nreg, const double *c, const double *h, double *I7, double *I5,
+                        double *err, int *axis, hipStream_t s) {
+  const int d = spec_.ndim;
+  int rc = ensure(nreg, s);
+  if (rc) return rc;
+  const CRegions &R = R_[cur_];
+  for (int j = 0; j < d; ++j) {
+    CCUBA_HIP(hipMemcpyAsync(R.c + j * R.cap, c + (size_t)j * nreg, nreg * 8,
+                             hipMemcpyHostToDevice, s));
+    CCUBA_HIP(hipMemcpyAsync(R.h + j * R.cap, h + (size_t)j * nreg, nreg * 8,
+                             hipMemcpyHostToDevice, s));
+  }
+  CSeg seg{};
+  seg.ndim = d;
+  seg.family = spec_.family;
+  seg.par = params_.p;
+  seg.first = 0;
+  seg.count = nreg;
+  seg.regs = R;
+  if ((rc = launch_rule_alone(seg, s))) return rc;
+  if (I7) CCUBA_HIP(hipMemcpyAsync(I7, R.I7, nreg * 8, hipMemcpyDeviceToHost, s));
+  if (I5) CCUBA_HIP(hipMemcpyAsync(I5, R.I5, nreg * 8, hipMemcpyDeviceToHost, s));
+  if (err) CCUBA_HIP(hipMemcpyAsync(err, R.err, nreg * 8, hipMemcpyDeviceToHost, s));
+  if (axis) CCUBA_HIP(hipMemcpyAsync(axis, R.axis, nreg * 4, hipMemcpyDeviceToHost, s));
+  CCUBA_HIP(hipStreamSynchronize(s));
+  return CCUBA_OK;
+}
+
+}  // namespace ccuba

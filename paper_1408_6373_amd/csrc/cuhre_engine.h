@@ -1,0 +1,90 @@
+// cuhre_engine.h -- host driver of Cuhre: one integral's resident region heap
+// advanced one batch step at a time.
+#pragma once
+#include "context.h"
+#include "cuhre.h"
+
+namespace ccuba {
+
+struct CuhreSpec {
+  int ndim = 2, family = 0;
+  double a[kMaxDim] = {0}, u[kMaxDim] = {0};
+  double epsrel = 1e-3, epsabs = 0;
+  long long mineval = 0, maxeval = 0, batch = 100000;
+};
+
+int validate_cuhre(const CuhreSpec &s);
+long long gm_npoints(int ndim);
+
+// Rule weights (w7, w5: [17][5]) and generators, from Genz & Malik (1980).
+struct GMTables {
+  double w7[17 * 5], w5[17 * 5];
+  double l2, l3, l4, l5;
+};
+const GMTables &gm_tables();
+
+class CuhreRun {
+ public:
+  explicit CuhreRun(ccuba_ctx *ctx) : ctx_(ctx) {}
+  // Allocate, evaluate the root region (asynchronous).
+  int start(const CuhreSpec &spec, hipStream_t s);
+  // Totals of the current leaves into the device result (asynchronous).
+  int launch_totals(hipStream_t s);
+  // After the totals are read: decide, and if work remains select + split.
+  // Returns 1 if a rule launch over new children is pending, 0 if finished.
+  int plan_and_split(hipStream_t s);
+  // The segment of children awaiting the rule (valid after plan_and_split
+  // returned 1); the caller launches the rule, possibly with other segments.
+  CSeg pending_segment() const;
+  void commit_pending();
+  // Copy the device totals to host (synchronous on s).
+  int read_totals(hipStream_t s);
+  // Run to completion alone.
+  int run(hipStream_t s);
+  int rule_only(long long nreg, const double *c, const double *h, double *I7, double *I5,
+                double *err, int *axis, hipStream_t s);
+
+  bool done() const { return done_; }
+  int fail() const { return fail_; }
+  long long neval() const { return neval_; }
+  long long nregions() const { return n_; }
+  double integral() const { return I_; }
+  double error() const { return E_; }
+  int batches() const { return batches_; }
+  const CuhreSpec &spec() const { return spec_; }
+  size_t bytes() const;
+  int launch_rule_alone(const CSeg &seg, hipStream_t s);
+  const double *params_dev() const { return params_.p; }
+
+ private:
+  int ensure(long long need, hipStream_t s);
+  int alloc_store(CRegions &R, DevBuf<double> &cb, DevBuf<double> &hb, DevBuf<double> &vals,
+                  DevBuf<int> &ax, DevBuf<long long> &ids, long long cap);
+  ccuba_ctx *ctx_;
+  CuhreSpec spec_;
+  long long np_ = 0, n_ = 0, next_id_ = 1, neval_ = 0, cap_ = 0, pendK_ = 0;
+  int fail_ = 1, batches_ = 0;
+  bool done_ = false;
+  double I_ = 0, E_ = 0;
+  int cur_ = 0;  // which store holds the leaves
+  CRegions R_[2]{};
+  DevBuf<double> c_[2], h_[2], vals_[2];
+  DevBuf<int> axis_[2];
+  DevBuf<long long> id_[2];
+  DevBuf<unsigned long long> prefix_;
+  DevBuf<long long> krem_, bsum_;
+  DevBuf<unsigned> hist_;
+  DevBuf<int> flag_;
+  DevBuf<double> tot_, out_, params_, w7_, w5_;
+  DevBuf<CSeg> seg_;
+  DevBuf<long long> seg_end_;
+  CScratch S_{};
+};
+
+// Launch the rule over segments of several integrals in one kernel.  segs
+// and ends are host arrays copied to the device buffers given.
+int launch_rule_segments(ccuba_ctx *ctx, const CSeg *segs, int nseg, DevBuf<CSeg> &dsegs,
+                         DevBuf<long long> &dends, const double *w7_dev, const double *w5_dev,
+                         hipStream_t s);
+
+}  // namespace ccuba
