@@ -9,6 +9,7 @@
 #include "ccuba.h"
 #include "context.h"
 #include "cuhre_engine.h"
+#include "serve.h"
 #include "tune.h"
 #include "vegas_engine.h"
 
@@ -158,6 +159,8 @@ int ccuba_shutdown(ccuba_ctx **ctx) {
   if (!ctx || !*ctx) return CCUBA_OK;
   ccuba_ctx *c = *ctx;
   (void)hipSetDevice(c->device);
+  delete c->server;  // stops the serving thread and frees its requests
+  c->server = nullptr;
   if (c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
   *ctx = nullptr;
@@ -460,6 +463,28 @@ int ccuba_vegas_batch(ccuba_ctx *ctx, int njobs, const ccuba_job jobs[], ccuba_r
     out[q].t_done = t_done;
   }
   return CCUBA_OK;
+}
+
+int ccuba_submit(ccuba_ctx *ctx, const ccuba_job *job, unsigned long long *ticket) {
+  if (!ctx || !job || !ticket) return CCUBA_EINVAL;
+  {
+    std::lock_guard<std::mutex> g(ctx->lock);
+    if (!ctx->server) ctx->server = new (std::nothrow) Server(ctx);
+    if (!ctx->server) return CCUBA_ENOMEM;
+  }
+  return ctx->server->submit(*job, ticket);
+}
+
+int ccuba_poll(ccuba_ctx *ctx, unsigned long long ticket, ccuba_result *out) {
+  if (!ctx || !out) return CCUBA_EINVAL;
+  if (!ctx->server) return CCUBA_ENOENT;
+  return ctx->server->poll(ticket, out);
+}
+
+int ccuba_drain(ccuba_ctx *ctx) {
+  if (!ctx) return CCUBA_EINVAL;
+  if (!ctx->server) return CCUBA_OK;
+  return ctx->server->drain();
 }
 
 }  // extern "C"

@@ -12,6 +12,10 @@
 #include "ccuba.h"
 #include "engine.h"
 
+namespace ccuba {
+class Server;
+}
+
 struct ccuba_ctx {
   int device = 0;
   int ncu = 256;
@@ -27,6 +31,7 @@ struct ccuba_ctx {
   ccuba_stats stats{};
   std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
   std::mutex lock;                  // serialises engine use with the server thread
+  ccuba::Server *server = nullptr;  // the serving loop, started by the first submit
   double now() const {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }

@@ -15,23 +15,31 @@ constexpr int kParamRow = kMaxDim;
 enum Precision { FP64 = 0, FP32 = 1 };
 enum Family { GAUSSIAN = 0, OSCILLATORY = 1, PRODUCT_PEAK = 2, CORNER_PEAK = 3, C0 = 4 };
 
-// One Vegas integral, device resident.  Offsets index the engine's pools.
+struct VState;
+
+// One Vegas integral, device resident: its settings and the device buffers it
+// owns (or that an engine carved out of its pools for it).
 struct VJob {
   int ndim, nbins, family, prec;
   int flags;
   uint32_t key0, key1, sid;
   long long nstart, nincrease, mineval, maxeval;
   double epsrel, epsabs;
-  int tile0, ntiles;      // tiles [tile0, tile0 + ntiles) of the tile list
+  int tile0, ntiles;      // tiles [tile0, tile0 + ntiles) of the launch's tile list
   long long tile_pts;     // points per tile
-  int group0;             // first reduction group
   int hist_cap;           // capacity of the per-iteration history
-  long long grid_off;     // doubles: ndim * (nbins + 1)
-  long long thist_off;    // doubles: ntiles * ndim * nbins
-  long long ghist_off;    // doubles: ngroups * ndim * nbins
-  long long iter_off;     // doubles: hist_cap
-  int param_off;          // job index into the parameter pools
   int pad;
+  VState *state;
+  double *grid;           // two copies of ndim * (nbins + 1), by iteration parity
+  double *tsums;          // [ntiles][2]
+  double *thist;          // [ntiles][ndim * nbins]
+  double *gsums;          // [ngroups][2]
+  double *ghist;          // [ngroups][ndim * nbins]
+  unsigned *gcnt;         // [ngroups], zero between launches
+  double *iter_I;         // [hist_cap]
+  double *iter_var;       // [hist_cap]
+  const double *p64;      // [2][kParamRow]
+  const float *p32;       // [2][kParamRow]
 };
 
 // Per-integral iteration state, written by the refine kernel.

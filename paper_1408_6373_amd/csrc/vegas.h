@@ -4,25 +4,14 @@
 
 namespace ccuba {
 
-// Everything a DoSample / refine launch touches; all pointers are device
-// memory owned by a VegasEngine.
+// Everything a DoSample / refine launch touches: the job table (device
+// memory) and the launch's tile list.
 struct VegasArgs {
   const VJob *jobs;
-  VState *state;
   const int *tile_job;  // job of each tile
   int ntiles;
   int hist64;           // FP32 path: FP64 LDS histogram
   long long lds_hist_byte_off;
-  double *grids;        // two copies per job (ping-pong by iteration parity)
-  const double *p64;    // [job][2][kParamRow]
-  const float *p32;     // [job][2][kParamRow]
-  double *tile_sums;    // [tile][2]
-  double *tile_hist;    // per job: [ntiles][d*N]
-  double *group_sums;   // [group][2]
-  double *group_hist;   // per job: [ngroups][d*N]
-  unsigned *group_cnt;  // [group], zero between launches
-  double *iter_I;       // per job: [hist_cap]
-  double *iter_var;
 };
 
 struct PointsArgs {

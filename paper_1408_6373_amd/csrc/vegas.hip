@@ -64,14 +64,14 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 template <typename T>
-__device__ __forceinline__ const T *param_ptr(const VegasArgs &A, int job, int which);
+__device__ __forceinline__ const T *param_ptr(const VJob &J, int which);
 template <>
-__device__ __forceinline__ const double *param_ptr<double>(const VegasArgs &A, int job, int which) {
-  return A.p64 + ((long long)job * 2 + which) * kParamRow;
+__device__ __forceinline__ const double *param_ptr<double>(const VJob &J, int which) {
+  return J.p64 + which * kParamRow;
 }
 template <>
-__device__ __forceinline__ const float *param_ptr<float>(const VegasArgs &A, int job, int which) {
-  return A.p32 + ((long long)job * 2 + which) * kParamRow;
+__device__ __forceinline__ const float *param_ptr<float>(const VJob &J, int which) {
+  return J.p32 + which * kParamRow;
 }
 
 // Sample the points [i0, i0 + cnt) of one tile; lane sums go to S1, S2.
@@ -160,7 +160,7 @@ __global__ void __launch_bounds__(256) vegas_dosample_kernel(VegasArgs A) {
     const int jb = A.tile_job[tt];
     const VJob J = A.jobs[jb];
     if (J.prec != myprec) continue;
-    const VState st = A.state[jb];
+    const VState st = *J.state;
     if (st.done) continue;
     const int d = J.ndim, N = J.nbins, dN = d * N, row = N + 1;
     const int lt = tt - J.tile0;
@@ -170,13 +170,13 @@ __global__ void __launch_bounds__(256) vegas_dosample_kernel(VegasArgs A) {
     c = c < 0 ? 0 : (c > J.tile_pts ? J.tile_pts : c);
     const int cnt = (int)c;
 
-    const double *E = A.grids + J.grid_off + (long long)(st.T & 1) * d * row;
+    const double *E = J.grid + (long long)(st.T & 1) * d * row;
     for (int e = tid; e < d * row; e += bs) sE[e] = (T)E[e];
     for (int e = tid; e < dN; e += bs) sH[e] = (HT)0;
     __syncthreads();
 
-    const T *p0 = param_ptr<T>(A, J.param_off, 0);
-    const T *p1 = param_ptr<T>(A, J.param_off, 1);
+    const T *p0 = param_ptr<T>(J, 0);
+    const T *p1 = param_ptr<T>(J, 1);
     double S1 = 0.0, S2 = 0.0;
     switch (J.family) {
       case GAUSSIAN: sample_tile_nb<T, HT, GAUSSIAN>(J, st.T, i0, cnt, sE, sH, p0, p1, S1, S2); break;
@@ -198,10 +198,10 @@ __global__ void __launch_bounds__(256) vegas_dosample_kernel(VegasArgs A) {
         a += red[0][q];
         b += red[1][q];
       }
-      A.tile_sums[2 * tt] = a;
-      A.tile_sums[2 * tt + 1] = b;
+      J.tsums[2 * lt] = a;
+      J.tsums[2 * lt + 1] = b;
     }
-    double *th = A.tile_hist + J.thist_off + (long long)lt * dN;
+    double *th = J.thist + (long long)lt * dN;
     for (int e = tid; e < dN; e += bs) th[e] = (double)sH[e];
 
     // fold the 32-tile group once its last tile is written
@@ -210,25 +210,25 @@ __global__ void __launch_bounds__(256) vegas_dosample_kernel(VegasArgs A) {
     __threadfence();
     __syncthreads();
     if (tid == 0) {
-      const unsigned old = atomicAdd(&A.group_cnt[J.group0 + g], 1u);
+      const unsigned old = atomicAdd(&J.gcnt[g], 1u);
       s_last = (old == (unsigned)(gsize - 1));
     }
     __syncthreads();
     if (s_last) {
       __threadfence();
       if (tid == 0) {
-        atomicExch(&A.group_cnt[J.group0 + g], 0u);
+        atomicExch(&J.gcnt[g], 0u);
         double a = 0.0, b = 0.0;
         for (int q = 0; q < gsize; ++q) {
-          const long long ti = J.tile0 + gfirst + q;
-          a += __hip_atomic_load(&A.tile_sums[2 * ti], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          b += __hip_atomic_load(&A.tile_sums[2 * ti + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          const long long ti = gfirst + q;
+          a += __hip_atomic_load(&J.tsums[2 * ti], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          b += __hip_atomic_load(&J.tsums[2 * ti + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        A.group_sums[2 * (J.group0 + g)] = a;
-        A.group_sums[2 * (J.group0 + g) + 1] = b;
+        J.gsums[2 * g] = a;
+        J.gsums[2 * g + 1] = b;
       }
-      const double *src = A.tile_hist + J.thist_off + (long long)gfirst * dN;
-      double *dst = A.group_hist + J.ghist_off + (long long)g * dN;
+      const double *src = J.thist + (long long)gfirst * dN;
+      double *dst = J.ghist + (long long)g * dN;
       for (int e = tid; e < dN; e += bs) {
         double s = 0.0;
         for (int q = 0; q < gsize; ++q)
@@ -284,7 +284,7 @@ __global__ void __launch_bounds__(256) vegas_refine_kernel(VegasArgs A) {
   __shared__ int s_has[kMaxDim];
   const int jb = blockIdx.x, tid = threadIdx.x, bs = blockDim.x;
   const VJob J = A.jobs[jb];
-  VState st = A.state[jb];
+  VState st = *J.state;
   if (st.done) return;
   const int d = J.ndim, N = J.nbins, dN = d * N, row = N + 1;
   const int t = st.T;
@@ -294,14 +294,14 @@ __global__ void __launch_bounds__(256) vegas_refine_kernel(VegasArgs A) {
     const long long n = J.nstart + (long long)t * J.nincrease;
     double S1 = 0.0, S2 = 0.0;
     for (int g = 0; g < ng; ++g) {
-      S1 += A.group_sums[2 * (J.group0 + g)];
-      S2 += A.group_sums[2 * (J.group0 + g) + 1];
+      S1 += J.gsums[2 * g];
+      S2 += J.gsums[2 * g + 1];
     }
     const double I = S1 / (double)n;
     double var = S2 / (double)n - I * I;
     if (var < 0.0) var = 0.0;
     var /= (double)(n - 1);
-    double *hI = A.iter_I + J.iter_off, *hV = A.iter_var + J.iter_off;
+    double *hI = J.iter_I, *hV = J.iter_var;
     hI[t] = I;
     hV[t] = var;
     const int T = t + 1;
@@ -347,14 +347,14 @@ __global__ void __launch_bounds__(256) vegas_refine_kernel(VegasArgs A) {
       st.done = 1;
       st.fail = 1;
     }
-    A.state[jb] = st;
+    *J.state = st;
     s_refine = conv ? 0 : ((J.flags & FLAG_FREEZE_GRID) ? 2 : 1);
   }
   __syncthreads();
   const int mode = s_refine;
   if (mode == 0) return;
-  const double *Eold = A.grids + J.grid_off + (long long)(t & 1) * d * row;
-  double *Enew = A.grids + J.grid_off + (long long)((t + 1) & 1) * d * row;
+  const double *Eold = J.grid + (long long)(t & 1) * d * row;
+  double *Enew = J.grid + (long long)((t + 1) & 1) * d * row;
   if (mode == 2) {
     for (int e = tid; e < d * row; e += bs) Enew[e] = Eold[e];
     return;
@@ -363,7 +363,7 @@ __global__ void __launch_bounds__(256) vegas_refine_kernel(VegasArgs A) {
   double *D = rsm + dN;   // smoothed histogram, later m
   for (int e = tid; e < dN; e += bs) {
     double s = 0.0;
-    for (int g = 0; g < ng; ++g) s += A.group_hist[J.ghist_off + (long long)g * dN + e];
+    for (int g = 0; g < ng; ++g) s += J.ghist[(long long)g * dN + e];
     H[e] = s;
   }
   __syncthreads();
@@ -447,15 +447,15 @@ __global__ void __launch_bounds__(256) vegas_collect_kernel(VegasArgs A, double 
   if (tid == 0) {
     double a = 0.0, b = 0.0;
     for (int g = 0; g < ng; ++g) {
-      a += A.group_sums[2 * (J.group0 + g)];
-      b += A.group_sums[2 * (J.group0 + g) + 1];
+      a += J.gsums[2 * g];
+      b += J.gsums[2 * g + 1];
     }
     sums[2 * jb] = a;
     sums[2 * jb + 1] = b;
   }
   for (int e = tid; e < dN; e += blockDim.x) {
     double s = 0.0;
-    for (int g = 0; g < ng; ++g) s += A.group_hist[J.ghist_off + (long long)g * dN + e];
+    for (int g = 0; g < ng; ++g) s += J.ghist[(long long)g * dN + e];
     hist[e] = s;
   }
 }

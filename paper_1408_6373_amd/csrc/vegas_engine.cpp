@@ -122,6 +122,11 @@ int VegasEngine::setup(const std::vector<VegasSpec> &specs, bool single, hipStre
   }
   // tile plan
   hjobs_.assign(n, VJob{});
+  struct Offsets {
+    long long grid, thist, ghist, iter;
+    int tile0, group0;
+  };
+  std::vector<Offsets> off(n);
   std::vector<int> tile_job;
   long long goff = 0, thoff = 0, ghoff = 0, ioff = 0;
   int tile0 = 0, group0 = 0;
@@ -158,14 +163,9 @@ int VegasEngine::setup(const std::vector<VegasSpec> &specs, bool single, hipStre
     J.tile0 = tile0;
     J.ntiles = nt;
     J.tile_pts = P;
-    J.group0 = group0;
     J.hist_cap = std::max(1, iters[j]);
     const long long dN = (long long)sp.ndim * sp.nbins, row = (long long)sp.ndim * (sp.nbins + 1);
-    J.grid_off = goff;
-    J.thist_off = thoff;
-    J.ghist_off = ghoff;
-    J.iter_off = ioff;
-    J.param_off = j;
+    off[j] = Offsets{goff, thoff, ghoff, ioff, tile0, group0};
     goff += 2 * row;
     thoff += nt * dN;
     ghoff += ngroups_of(nt) * dN;
@@ -199,6 +199,20 @@ int VegasEngine::setup(const std::vector<VegasSpec> &specs, bool single, hipStre
       (rc = iter_I_.alloc(ctx_, ioff)) || (rc = iter_var_.alloc(ctx_, ioff)))
     return rc;
 
+  for (int j = 0; j < n; ++j) {
+    VJob &J = hjobs_[j];
+    J.state = state_.p + j;
+    J.grid = grids_.p + off[j].grid;
+    J.tsums = tile_sums_.p + 2ll * off[j].tile0;
+    J.thist = tile_hist_.p + off[j].thist;
+    J.gsums = group_sums_.p + 2ll * off[j].group0;
+    J.ghist = group_hist_.p + off[j].ghist;
+    J.gcnt = group_cnt_.p + off[j].group0;
+    J.iter_I = iter_I_.p + off[j].iter;
+    J.iter_var = iter_var_.p + off[j].iter;
+    J.p64 = p64_.p + (size_t)j * 2 * kParamRow;
+    J.p32 = p32_.p + (size_t)j * 2 * kParamRow;
+  }
   std::vector<double> grids(goff), p64((size_t)n * 2 * kParamRow);
   std::vector<float> p32((size_t)n * 2 * kParamRow);
   std::vector<VState> st(n);
@@ -208,7 +222,7 @@ int VegasEngine::setup(const std::vector<VegasSpec> &specs, bool single, hipStre
     for (int c = 0; c < 2; ++c)
       for (int d = 0; d < sp.ndim; ++d)
         for (int k = 0; k <= N; ++k)
-          grids[hjobs_[j].grid_off + (long long)c * sp.ndim * row + (long long)d * row + k] =
+          grids[off[j].grid + (long long)c * sp.ndim * row + (long long)d * row + k] =
               (double)k / N;
     double a64[2][kParamRow];
     float a32[2][kParamRow];
@@ -228,20 +242,9 @@ int VegasEngine::setup(const std::vector<VegasSpec> &specs, bool single, hipStre
   CCUBA_HIP(hipMemsetAsync(group_cnt_.p, 0, ngroups_ * sizeof(unsigned), s));
 
   args_.jobs = jobs_.p;
-  args_.state = state_.p;
   args_.tile_job = tile_job_.p;
   args_.ntiles = ntiles_;
   args_.hist64 = hist64_;
-  args_.grids = grids_.p;
-  args_.p64 = p64_.p;
-  args_.p32 = p32_.p;
-  args_.tile_sums = tile_sums_.p;
-  args_.tile_hist = tile_hist_.p;
-  args_.group_sums = group_sums_.p;
-  args_.group_hist = group_hist_.p;
-  args_.group_cnt = group_cnt_.p;
-  args_.iter_I = iter_I_.p;
-  args_.iter_var = iter_var_.p;
   // host copies of the tables must outlive the async uploads
   CCUBA_HIP(hipStreamSynchronize(s));
   return CCUBA_OK;
@@ -365,10 +368,10 @@ int VegasEngine::read_history(int job, int n, double *I, double *var, hipStream_
   n = std::min(n, hjobs_[job].hist_cap);
   if (n <= 0) return CCUBA_OK;
   if (I)
-    CCUBA_HIP(hipMemcpyAsync(I, iter_I_.p + hjobs_[job].iter_off, n * sizeof(double),
+    CCUBA_HIP(hipMemcpyAsync(I, hjobs_[job].iter_I, n * sizeof(double),
                              hipMemcpyDeviceToHost, s));
   if (var)
-    CCUBA_HIP(hipMemcpyAsync(var, iter_var_.p + hjobs_[job].iter_off, n * sizeof(double),
+    CCUBA_HIP(hipMemcpyAsync(var, hjobs_[job].iter_var, n * sizeof(double),
                              hipMemcpyDeviceToHost, s));
   CCUBA_HIP(hipStreamSynchronize(s));
   return CCUBA_OK;
@@ -378,7 +381,7 @@ int VegasEngine::read_grid(int job, int T, double *grid, hipStream_t s) {
   if (job < 0 || job >= njobs()) return CCUBA_EINVAL;
   const VJob &J = hjobs_[job];
   const long long row = (long long)J.ndim * (J.nbins + 1);
-  CCUBA_HIP(hipMemcpyAsync(grid, grids_.p + J.grid_off + (long long)(T & 1) * row,
+  CCUBA_HIP(hipMemcpyAsync(grid, J.grid + (long long)(T & 1) * row,
                            row * sizeof(double), hipMemcpyDeviceToHost, s));
   CCUBA_HIP(hipStreamSynchronize(s));
   return CCUBA_OK;
@@ -398,7 +401,7 @@ int VegasEngine::load_grid(int job, int copy, const double *src, hipMemcpyKind k
                            hipStream_t s) {
   const VJob &J = hjobs_[job];
   const long long row = (long long)J.ndim * (J.nbins + 1);
-  CCUBA_HIP(hipMemcpyAsync(grids_.p + J.grid_off + (long long)(copy & 1) * row, src,
+  CCUBA_HIP(hipMemcpyAsync(J.grid + (long long)(copy & 1) * row, src,
                            row * sizeof(double), kind, s));
   if (kind == hipMemcpyHostToDevice) CCUBA_HIP(hipStreamSynchronize(s));
   return CCUBA_OK;
@@ -418,8 +421,8 @@ int VegasEngine::refine_only(const double *hist, const double *grid_in, double *
   // a synthetic finished iteration with n = 2, S1 = 1, S2 = 2 (I = 1/2,
   // sigma^2 = 3/4 > 0, so the zero-tolerance job never converges)
   const double sums[2] = {1.0, 2.0};
-  CCUBA_HIP(hipMemcpyAsync(group_sums_.p, sums, sizeof(sums), hipMemcpyHostToDevice, s));
-  CCUBA_HIP(hipMemcpyAsync(group_hist_.p, hist, dN * sizeof(double), hipMemcpyHostToDevice, s));
+  CCUBA_HIP(hipMemcpyAsync(J.gsums, sums, sizeof(sums), hipMemcpyHostToDevice, s));
+  CCUBA_HIP(hipMemcpyAsync(J.ghist, hist, dN * sizeof(double), hipMemcpyHostToDevice, s));
   CCUBA_HIP(hipStreamSynchronize(s));
   rc = set_iteration(0, 0, s);
   if (rc) return rc;

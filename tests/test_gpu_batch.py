@@ -1,0 +1,112 @@
+"""GPU checks of the batched Vegas launch: every integral of a batch gets the
+result it gets alone (same points; only the order of FP64 sums may differ),
+and sampled integrals of the full 4096-job workload match the CPU oracle."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cc():
+    import paper_1408_6373_amd as cc
+    return cc
+
+
+@pytest.fixture(scope="module")
+def ctx(cc):
+    c = cc.Context()
+    yield c
+    c.close()
+
+
+def _rel(a, b):
+    return abs(a - b) / max(abs(b), 1e-300)
+
+
+def _specs(n, seed, iters=4, nmax=6e4, prec_mix=True, eps=False):
+    jobs = W.batch_jobs(n, seed=seed, nmin=2e3, nmax=nmax)
+    specs = []
+    for q, j in enumerate(jobs):
+        s = dict(method=0, ndim=j["ndim"], family=j["family"], a=j["a"], u=j["u"],
+                 seed=j["seed"], stream_id=j["stream_id"], nstart=j["nstart"],
+                 maxeval=iters * j["nstart"], nbins=128,
+                 flags=(q % 2) if prec_mix else 1)
+        if eps:
+            s.update(epsrel=10 ** (-2 - q % 3), nincrease=j["nstart"] // 2,
+                     maxeval=40 * j["nstart"])
+        specs.append(s)
+    return specs
+
+
+def _alone(cc, ctx, s):
+    return cc.vegas(s["family"], s["a"], s["u"], ctx=ctx, flags=s["flags"], seed=s["seed"],
+                    stream_id=s["stream_id"], nstart=s["nstart"], maxeval=s["maxeval"],
+                    nbins=s["nbins"], epsrel=s.get("epsrel", 0.0),
+                    nincrease=s.get("nincrease", 0))
+
+
+def test_batch_equals_alone(cc, ctx):
+    specs = _specs(48, 5)
+    res = cc.vegas_batch(ctx, specs)
+    for s, r in zip(specs, res):
+        a = _alone(cc, ctx, s)
+        assert r["status"] == 0 and r["neval"] == a["neval"] and r["fail"] == a["fail"]
+        assert _rel(r["integral"], a["integral"]) < 1e-12
+        assert _rel(r["error"], a["error"]) < 1e-11
+
+
+def test_batch_with_convergence_drops_jobs(cc, ctx):
+    specs = _specs(24, 9, eps=True)
+    res = cc.vegas_batch(ctx, specs)
+    conv = 0
+    for s, r in zip(specs, res):
+        a = _alone(cc, ctx, s)
+        assert r["neval"] == a["neval"] and r["fail"] == a["fail"]
+        assert _rel(r["integral"], a["integral"]) < 1e-12
+        conv += r["fail"] == 0
+    assert conv > 0
+
+
+def test_batch_matches_oracle(cc, ctx):
+    specs = _specs(12, 13, iters=3)
+    res = cc.vegas_batch(ctx, specs)
+    for s, r in zip(specs, res):
+        o = O.vegas(O.genz(s["family"], s["a"], s["u"], precision=s["flags"]), s["ndim"],
+                    flags=s["flags"], seed=s["seed"], stream_id=s["stream_id"],
+                    nstart=s["nstart"], maxeval=s["maxeval"], nbins=128)
+        tol = 1e-12 if s["flags"] == 0 else 1e-6
+        assert _rel(r["integral"], o["integral"]) < tol
+        assert _rel(r["error"], o["error"]) < (1e-11 if s["flags"] == 0 else 1e-5)
+
+
+def test_invalid_job_gets_its_own_status(cc, ctx):
+    specs = _specs(4, 3)
+    specs[1] = dict(specs[1], nbins=1)
+    specs[2] = dict(specs[2], method=1)
+    res = cc.vegas_batch(ctx, specs)
+    assert res[1]["status"] == cc.EINVAL and res[2]["status"] == cc.EINVAL
+    assert res[0]["status"] == 0 and res[3]["status"] == 0
+
+
+def test_full_4096_job_workload_sampled(cc, ctx):
+    # 4096 integrals, d in 2..12, n log-uniform in [1e4, 1e6], 10 iterations,
+    # FP32 evaluation: sampled integrals against the oracle's FP32 emulation
+    jobs = W.batch_jobs(4096, seed=1000)
+    specs = [dict(method=0, ndim=j["ndim"], family=j["family"], a=j["a"], u=j["u"],
+                  seed=j["seed"], stream_id=j["stream_id"], nstart=j["nstart"],
+                  maxeval=10 * j["nstart"], nbins=128, flags=1) for j in jobs]
+    res = cc.vegas_batch(ctx, specs)
+    assert all(r["status"] == 0 and r["neval"] == 10 * s["nstart"] for s, r in zip(specs, res))
+    rng = np.random.default_rng(0)
+    for q in rng.choice(4096, 6, replace=False):
+        s, r = specs[q], res[q]
+        if s["nstart"] > 3e5:
+            continue
+        o = O.vegas(O.genz(s["family"], s["a"], s["u"], precision=1), s["ndim"], flags=1,
+                    seed=s["seed"], stream_id=s["stream_id"], nstart=s["nstart"],
+                    maxeval=s["maxeval"], nbins=128)
+        assert _rel(r["integral"], o["integral"]) < 1e-6
