@@ -1,20 +1,30 @@
 #!/usr/bin/env python3
 """Benchmark of the DoSample hot path on one MI355X.
 
-Workload (the metric's configuration): Vegas in d = 8 with 128 bins per
-dimension, 20 iterations of 10^7 points each, on the Genz oscillatory and
-product-peak integrands (parameters: a_i = 9 r_i / sum r, r, u ~ U(0,1),
-seed 1).  One step = both integrals run to completion, 4 x 10^8 integrand
-evaluations, with FP32 evaluation and FP64 accumulation.  The same step in
-all-FP64 is timed beside it.  Inputs are synthetic and resident on the device
-(the points are generated on the device from Philox counters).
+Headline workload (the metric's configuration): Vegas in d = 8 with 128 bins
+per dimension, 20 iterations of 10^7 points each, on the Genz oscillatory
+and product-peak integrands (a_i = 9 r_i / sum r, r, u ~ U(0,1), seed 1).
+One step = both integrals run to completion (4 x 10^8 integrand evaluations)
+with FP32 evaluation and FP64 accumulation; the same step in all-FP64 is
+timed beside it.  Inputs are synthetic; the points are generated on the
+device from Philox counters, so nothing but the 2 x 8 Genz constants
+crosses PCIe.
 
-Prints one JSON line: value = integrand evaluations per second of the whole
-job (FP32-evaluate path), plus the FP64 figure, a roofline object for the
-DoSample kernel (event-timed inside the library on the stream it runs on) and
-the CPU oracle timed on a bounded sample of the same workload.
+The JSON line also carries:
+  roofline      the DoSample kernel's VALU issue rate (HIP events recorded by
+                the library around each launch, on the stream it runs on)
+                against the FP32 VALU issue peak;
+  batch         4096 independent Vegas integrals (d 2..12, 10^4..10^6
+                points, 10 iterations, FP32) in one persistent launch per
+                iteration;
+  cuhre         corner peak, d = 6, batches of 10^5 regions to epsrel 1e-6;
+  serving       Poisson arrivals of Vegas (70%) and Cuhre (30%) requests,
+                d 2..16, epsrel log-uniform in [1e-5, 1e-3], at 0.7 of the
+                measured saturation rate: p50/p99 latency and evals/s;
+  cpu_baseline  the CPU oracle on a bounded sample of the headline workload.
 """
 import argparse
+import ctypes as C
 import json
 import os
 import sys
@@ -25,11 +35,25 @@ sys.path.insert(0, ROOT)
 
 D, NBINS, NPTS, ITERS = 8, 128, 10**7, 20
 FAMILIES = (1, 2)  # oscillatory, product peak
-PEAK_VALU_SLOTS = 256 * 4 * 16 * 2.4e9  # VALU lane-op issue slots per second
-# VALU issue slots per point of the FP32-evaluate DoSample loop at d = 8 (from
-# the instruction mix of this build: 247 full-rate VALU instructions and 33
-# 64-bit integer multiplies at a quarter of the issue rate)
-SLOTS_PER_POINT = {1: 247 + 4 * 33, 2: 254 + 4 * 33}
+FAMILY_KEYS = {1: "oscillatory", 2: "product_peak"}
+# VALU issue peak: 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz = 78.6 T lane-ops/s
+# (the published 157.3 TFLOP/s FP32 vector rate at 2 flops per FMA)
+PEAK_VALU = 256 * 4 * 32 * 2.4e9
+
+
+class Stats(C.Structure):
+    _fields_ = [("dosample_launches", C.c_longlong), ("dosample_ms", C.c_double),
+                ("refine_launches", C.c_longlong), ("refine_ms", C.c_double),
+                ("evals", C.c_longlong), ("rule_launches", C.c_longlong),
+                ("rule_ms", C.c_double), ("rule_evals", C.c_longlong)]
+
+
+def _stats(cc, ctx, reset=True):
+    fn = cc._lib.ccuba_stats_get
+    fn.argtypes = [C.c_void_p, C.POINTER(Stats), C.c_int]
+    st = Stats()
+    fn(ctx.handle, C.byref(st), 1 if reset else 0)
+    return st
 
 
 def _step(cc, ctx, params, prec):
@@ -57,31 +81,144 @@ def _timed(cc, ctx, params, prec, steps, warmup):
     return ev, time.perf_counter() - t0
 
 
-def _kernel_rate(cc, ctx, params, prec):
-    """Event-timed DoSample launches of one profiled step."""
-    import ctypes as C
-
-    class Stats(C.Structure):
-        _fields_ = [("dosample_launches", C.c_longlong), ("dosample_ms", C.c_double),
-                    ("refine_launches", C.c_longlong), ("refine_ms", C.c_double),
-                    ("evals", C.c_longlong), ("rule_launches", C.c_longlong),
-                    ("rule_ms", C.c_double), ("rule_evals", C.c_longlong)]
-
-    fn = cc._lib.ccuba_stats_get
-    fn.argtypes = [C.c_void_p, C.POINTER(Stats), C.c_int]
-    st = Stats()
-    fn(ctx.handle, C.byref(st), 1)
+def _roofline(cc, ctx, params):
+    """Event-timed DoSample launches of one profiled FP32 step."""
+    from paper_1408_6373_amd import isa_slots
+    table = isa_slots.load() or {}
+    _stats(cc, ctx)
     ctx.config("profile", 1)
-    per_fam = {}
+    ms = evals = launches = 0
+    slots = 0.0
+    refine_ms = 0.0
+    key = "f32h64_ilp2_nb2"  # the defaults: FP64 LDS histogram, 2 points/lane
     for fam in FAMILIES:
         a, u = params[fam]
-        cc.vegas(fam, a, u, ctx=ctx, flags=prec, nbins=NBINS, nstart=NPTS,
+        cc.vegas(fam, a, u, ctx=ctx, flags=cc.FP32_EVAL, nbins=NBINS, nstart=NPTS,
                  maxeval=ITERS * NPTS, seed=1)
-        fn(ctx.handle, C.byref(st), 1)
-        per_fam[fam] = dict(launches=st.dosample_launches, ms=st.dosample_ms, evals=st.evals,
-                            refine_ms=st.refine_ms)
+        st = _stats(cc, ctx)
+        ms += st.dosample_ms
+        evals += st.evals
+        launches += st.dosample_launches
+        refine_ms += st.refine_ms
+        per = table.get(key, {}).get(FAMILY_KEYS[fam])
+        slots = None if (per is None or slots is None) else slots + per * st.evals
     ctx.config("profile", 0)
-    return per_fam
+    out = {"bound": "alu", "kernel": "vegas_dosample_kernel<float,double,2,2> + fold",
+           "unit": "T VALU-slots/s", "peak": PEAK_VALU / 1e12,
+           "avg_launch_ms": ms / max(launches, 1), "launches": launches,
+           "kernel_evals_per_s": evals / (ms * 1e-3),
+           "refine_ms_per_launch": refine_ms / max(launches, 1),
+           "slots_per_point": None if slots is None else slots / evals,
+           "traffic": _traffic()}
+    if slots is not None:
+        out["achieved"] = slots / (ms * 1e-3) / 1e12
+        out["frac"] = out["achieved"] / out["peak"]
+    else:
+        out["achieved"] = out["frac"] = None
+    return out
+
+
+def _traffic():
+    """HBM bytes per DoSample launch from the committed PMC summary, if it was
+    taken on the current kernel source."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "vegas_dosample_d8_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = open(os.path.join(ROOT, "paper_1408_6373_amd", "csrc", "vegas.hip"), "rb").read()
+    if rec.get("kernel_source_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def _batch_leg(cc, ctx):
+    import workloads as W
+    jobs = W.batch_jobs(4096, seed=1000)
+    specs = [dict(method=0, ndim=j["ndim"], family=j["family"], a=j["a"], u=j["u"],
+                  seed=j["seed"], stream_id=j["stream_id"], nstart=j["nstart"],
+                  maxeval=10 * j["nstart"], nbins=128, flags=cc.FP32_EVAL) for j in jobs]
+    cc.vegas_batch(ctx, specs[:64])  # warm-up
+    t0 = time.perf_counter()
+    res = cc.vegas_batch(ctx, specs)
+    dt = time.perf_counter() - t0
+    ev = sum(r["neval"] for r in res)
+    return {"workload": "4096 Vegas integrals, d 2..12, 1e4..1e6 points x 10 iterations, FP32",
+            "value": ev / dt, "unit": "evals/s", "seconds": dt, "evals": ev,
+            "failed": sum(r["status"] != 0 for r in res)}
+
+
+def _cuhre_leg(cc, ctx):
+    import workloads as W
+    a, u = W.genz_params(W.CORNER_PEAK, 6, 1)
+    cc.cuhre(W.CORNER_PEAK, a, u, ctx=ctx, epsrel=1e-3, max_regions_per_batch=10**5)
+    _stats(cc, ctx)
+    ctx.config("profile", 1)
+    t0 = time.perf_counter()
+    r = cc.cuhre(W.CORNER_PEAK, a, u, ctx=ctx, epsrel=1e-6, maxeval=10**10,
+                 max_regions_per_batch=10**5)
+    dt = time.perf_counter() - t0
+    st = _stats(cc, ctx)
+    ctx.config("profile", 0)
+    return {"workload": "Cuhre corner peak d=6, batches of 1e5 regions, epsrel 1e-6, FP64",
+            "value": r["neval"] / dt, "unit": "evals/s", "seconds": dt, "neval": r["neval"],
+            "nregions": r["nregions"], "fail": r["fail"],
+            "rule_kernel_evals_per_s": st.rule_evals / max(st.rule_ms * 1e-3, 1e-12),
+            "rule_launches": st.rule_launches}
+
+
+def _serving_specs(cc, reqs):
+    specs = []
+    for r in reqs:
+        if r["method"] == 0:
+            specs.append(dict(method=0, ndim=r["ndim"], family=r["family"], a=r["a"], u=r["u"],
+                              seed=r["seed"], stream_id=r["stream_id"], epsrel=r["epsrel"],
+                              nstart=200000, nincrease=100000, maxeval=10**8, nbins=128,
+                              flags=cc.FP32_EVAL))
+        else:
+            specs.append(dict(method=1, ndim=r["ndim"], family=r["family"], a=r["a"], u=r["u"],
+                              epsrel=r["epsrel"], maxeval=10**8, max_regions_per_batch=10**5,
+                              flags=0))
+    return specs
+
+
+def _serving_leg(cc, n):
+    import numpy as np
+    import workloads as W
+    # saturation throughput: every request queued at once
+    ctx = cc.Context(device=0)
+    specs = _serving_specs(cc, W.serving_requests(n, rate=1.0, seed=7))
+    t0 = time.perf_counter()
+    tickets = [cc.submit(ctx, s) for s in specs]
+    cc.drain(ctx)
+    t_sat = time.perf_counter() - t0
+    for t in tickets:
+        cc.poll(ctx, t)
+    ctx.close()
+    rate = 0.7 * n / t_sat
+    # timed: Poisson arrivals at 0.7 of saturation
+    reqs = W.serving_requests(n, rate=rate, seed=7)
+    specs = _serving_specs(cc, reqs)
+    ctx = cc.Context(device=0)
+    start = time.perf_counter()
+    tickets = []
+    for r, s in zip(reqs, specs):
+        delay = start + r["arrival"] - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        tickets.append(cc.submit(ctx, s))
+    cc.drain(ctx)
+    res = [cc.poll(ctx, t) for t in tickets]
+    ctx.close()
+    lat = np.array([r["t_done"] - r["t_submit"] for r in res]) * 1e3
+    ev = sum(r["neval"] for r in res)
+    span = max(r["t_done"] for r in res) - min(r["t_submit"] for r in res)
+    return {"workload": "Poisson arrivals, 70%% Vegas (FP32) / 30%% Cuhre (FP64), d 2..16, "
+                        "epsrel logU[1e-5,1e-3], maxeval 1e8, %d requests" % n,
+            "rate_per_s": rate, "saturation_per_s": n / t_sat,
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "evals_per_s": ev / span, "failed_status": sum(r["status"] != 0 for r in res),
+            "not_converged": sum(r["fail"] != 0 for r in res)}
 
 
 def _cpu_baseline(params, iters_sample=4):
@@ -102,10 +239,12 @@ def _cpu_baseline(params, iters_sample=4):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip batch/cuhre/serving legs")
+    ap.add_argument("--serving-requests", type=int, default=300)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (--gpus 1); no multi-GPU path exists",
@@ -137,25 +276,17 @@ def main():
         out["fp64"] = {"value": ev64 / t64, "unit": "evals/s",
                        "ms_per_step": 1e3 * t64 / args.steps,
                        "fp32_speedup": value / (ev64 / t64)}
-
-    k = _kernel_rate(cc, ctx, params, cc.FP32_EVAL)
-    ms = sum(v["ms"] for v in k.values())
-    launches = sum(v["launches"] for v in k.values())
-    evals = sum(v["evals"] for v in k.values())
-    slots = sum(SLOTS_PER_POINT[f] * k[f]["evals"] for f in FAMILIES)
-    avg_ms = ms / max(launches, 1)
-    achieved = slots / (ms * 1e-3) / 1e12
-    peak = PEAK_VALU_SLOTS / 1e12
-    out["roofline"] = {
-        "bound": "alu", "kernel": "vegas_dosample_kernel<float,float>",
-        "achieved": achieved, "peak": peak, "unit": "T VALU-slots/s", "frac": achieved / peak,
-        "traffic": None, "avg_launch_ms": avg_ms, "launches": launches,
-        "kernel_evals_per_s": evals / (ms * 1e-3),
-        "refine_ms_per_launch": sum(v["refine_ms"] for v in k.values()) / max(launches, 1),
-    }
+    out["roofline"] = _roofline(cc, ctx, params)
+    if not args.no_extra:
+        out["batch"] = _batch_leg(cc, ctx)
+        out["cuhre"] = _cuhre_leg(cc, ctx)
+    ctx.close()
+    if not args.no_extra:
+        out["serving"] = _serving_leg(cc, args.serving_requests)
+        out["p50_ms"] = out["serving"]["p50_ms"]
+        out["p99_ms"] = out["serving"]["p99_ms"]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = _cpu_baseline(params)
-    ctx.close()
     print(json.dumps(out))
 
 

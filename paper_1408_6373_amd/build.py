@@ -56,6 +56,16 @@ def build(verbose=False, jobs=8):
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout + r.stderr)
     os.replace(tmp, LIB)
+    # VALU issue slots per point of each DoSample instance (roofline input)
+    try:
+        import importlib.util
+        spec = importlib.util.spec_from_file_location("_ccuba_isa_slots",
+                                                      os.path.join(HERE, "isa_slots.py"))
+        mod = importlib.util.module_from_spec(spec)
+        spec.loader.exec_module(mod)
+        mod.write(HIPCC, FLAGS)
+    except Exception as e:  # the library itself is built; only the table is missing
+        print("warning: kernel slot table not written: %s" % e, file=sys.stderr)
     return LIB
 
 

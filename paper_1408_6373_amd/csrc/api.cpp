@@ -141,6 +141,8 @@ int ccuba_init(ccuba_ctx **ctx, int device, size_t hbm_budget) {
     c->tune[p].block = (int)env_ll("CCUBA_BLOCK", 256);
     c->tune[p].blocks_per_cu = (int)env_ll("CCUBA_BLOCKS_PER_CU", 4);
     c->tune[p].min_tile = env_ll("CCUBA_MIN_TILE", 16384);
+    // measured best on gfx950: two points per lane for FP32, one for FP64
+    c->tune[p].ilp = (int)env_ll("CCUBA_ILP", p == FP32 ? 2 : 1) == 2 ? 2 : 1;
   }
   c->tune[FP32].hist64 = (int)env_ll("CCUBA_HIST64", 1);
   c->use_graph = (int)env_ll("CCUBA_GRAPH", 1);
@@ -180,6 +182,9 @@ int ccuba_config(ccuba_ctx *ctx, const char *key, long long value) {
   } else if (k == "hist64") {
     if (value != 0 && value != 1) return CCUBA_EINVAL;
     ctx->tune[FP32].hist64 = (int)value;
+  } else if (k == "ilp") {
+    if (value != 1 && value != 2) return CCUBA_EINVAL;
+    ctx->tune[0].ilp = ctx->tune[1].ilp = (int)value;
   } else if (k == "min_tile") {
     if (value < 64) return CCUBA_EINVAL;
     ctx->tune[0].min_tile = ctx->tune[1].min_tile = value;

@@ -9,7 +9,7 @@ namespace ccuba {
 
 constexpr int kMaxDim = 16;
 constexpr int kMaxBins = 256;  // bin indices are packed 4 per 32-bit word
-constexpr int kGroupTiles = 32;  // tiles folded by one "last block" reduction
+constexpr int kGroupTiles = 32;  // tiles folded by one wavefront of the fold kernel
 constexpr int kParamRow = kMaxDim;
 
 enum Precision { FP64 = 0, FP32 = 1 };
@@ -35,7 +35,7 @@ struct VJob {
   double *thist;          // [ntiles][ndim * nbins]
   double *gsums;          // [ngroups][2]
   double *ghist;          // [ngroups][ndim * nbins]
-  unsigned *gcnt;         // [ngroups], zero between launches
+  double *hsum;           // [2 + ndim * nbins]: S1, S2 and the folded histogram
   double *iter_I;         // [hist_cap]
   double *iter_var;       // [hist_cap]
   const double *p64;      // [2][kParamRow]
@@ -50,6 +50,11 @@ struct VState {
   int fail;   // 0 converged, 1 maxeval reached
   int dof;
   double integral, error, prob, chi2;
+  // running sums of the combination over iterations t < T, in order
+  double sum_w, sum_wI;  // sum 1/sigma_t^2, sum I_t/sigma_t^2
+  double sum_zI;         // sum of I_t over iterations with sigma_t = 0
+  int nzero;             // number of such iterations
+  int pad;
 };
 
 __host__ __device__ inline int ngroups_of(int ntiles) { return (ntiles + kGroupTiles - 1) / kGroupTiles; }
@@ -62,6 +67,7 @@ struct VegasTune {
   int block = 256;        // threads per block
   int blocks_per_cu = 4;  // persistent blocks per compute unit
   int hist64 = 1;         // FP32 path: 1 = FP64 LDS histogram, 0 = FP32
+  int ilp = 1;            // points per lane per trip (1 or 2)
   int tiles_per_job = 0;  // 0 = automatic (one tile per persistent block)
   long long min_tile = 4096;
 };

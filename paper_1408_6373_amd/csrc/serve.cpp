@@ -19,9 +19,8 @@ struct Server::Req {
   VegasSpec vs;
   VJob hj{};
   bool vdone = false;
-  DevBuf<double> grid, tsums, thist, gsums, ghist, iters, p64;
+  DevBuf<double> grid, tsums, thist, gsums, ghist, hsum, iters, p64;
   DevBuf<float> p32;
-  DevBuf<unsigned> gcnt;
   // Cuhre
   std::unique_ptr<CuhreRun> cuhre;
   bool cpending = false;
@@ -117,10 +116,10 @@ void Server::release(Req &r) {
   r.thist.release();
   r.gsums.release();
   r.ghist.release();
+  r.hsum.release();
   r.iters.release();
   r.p64.release();
   r.p32.release();
-  r.gcnt.release();
   r.cuhre.reset();
   if (r.slot >= 0) free_slots_.push_back(r.slot);
   r.slot = -1;
@@ -187,9 +186,9 @@ int Server::activate(Req &r) {
   int rc;
   if ((rc = r.grid.alloc(ctx_, 2 * row)) || (rc = r.tsums.alloc(ctx_, 2 * nt)) ||
       (rc = r.thist.alloc(ctx_, nt * dN)) || (rc = r.gsums.alloc(ctx_, 2 * ng)) ||
-      (rc = r.ghist.alloc(ctx_, ng * dN)) || (rc = r.iters.alloc(ctx_, 2 * (size_t)cap)) ||
-      (rc = r.p64.alloc(ctx_, 2 * kParamRow)) || (rc = r.p32.alloc(ctx_, 2 * kParamRow)) ||
-      (rc = r.gcnt.alloc(ctx_, ng)))
+      (rc = r.ghist.alloc(ctx_, ng * dN)) || (rc = r.hsum.alloc(ctx_, 2 + dN)) ||
+      (rc = r.iters.alloc(ctx_, 2 * (size_t)cap)) ||
+      (rc = r.p64.alloc(ctx_, 2 * kParamRow)) || (rc = r.p32.alloc(ctx_, 2 * kParamRow)))
     return rc;
   if (free_slots_.empty()) return CCUBA_ENOMEM;
   r.slot = free_slots_.back();
@@ -219,7 +218,7 @@ int Server::activate(Req &r) {
   J.thist = r.thist.p;
   J.gsums = r.gsums.p;
   J.ghist = r.ghist.p;
-  J.gcnt = r.gcnt.p;
+  J.hsum = r.hsum.p;
   J.iter_I = r.iters.p;
   J.iter_var = r.iters.p + cap;
   J.p64 = r.p64.p;
@@ -242,7 +241,6 @@ int Server::activate(Req &r) {
   CCUBA_HIP(hipMemcpyAsync(r.p64.p, a64, sizeof(a64), hipMemcpyHostToDevice, s));
   CCUBA_HIP(hipMemcpyAsync(r.p32.p, a32, sizeof(a32), hipMemcpyHostToDevice, s));
   CCUBA_HIP(hipMemcpyAsync(J.state, &st, sizeof(st), hipMemcpyHostToDevice, s));
-  CCUBA_HIP(hipMemsetAsync(r.gcnt.p, 0, ng * sizeof(unsigned), s));
   CCUBA_HIP(hipStreamSynchronize(s));  // host staging buffers die here
   return CCUBA_OK;
 }
@@ -307,44 +305,37 @@ int Server::tick() {
       stepping.push_back(r.get());
     }
   }
-  // Vegas: one DoSample per precision over every running request, one refine
+  // Vegas: one DoSample per (precision, dimension class) over every running
+  // request, one refine over all of them
   std::vector<VJob> table;
+  std::vector<long long> ends;  // host tables live until the tick's sync
   std::vector<int> tiles;
-  int has[2] = {0, 0};
-  size_t gridb[2] = {0, 0}, histb[2] = {0, 0}, refb = 0;
-  const int hist64 = ctx_->tune[FP32].hist64;
-  for (auto &r : active_) {
-    if (r->job.method != 0 || r->vdone) continue;
-    VJob J = r->hj;
-    J.tile0 = (int)tiles.size();
-    for (int q = 0; q < J.ntiles; ++q) tiles.push_back((int)table.size());
-    table.push_back(J);
-    has[J.prec] = 1;
-    const size_t row = (size_t)J.ndim * (J.nbins + 1), dN = (size_t)J.ndim * J.nbins;
-    const size_t tsz = J.prec == FP64 ? 8 : 4, hsz = (J.prec == FP64 || hist64) ? 8 : 4;
-    gridb[J.prec] = std::max(gridb[J.prec], (row * tsz + 15) & ~(size_t)15);
-    histb[J.prec] = std::max(histb[J.prec], dN * hsz);
-    refb = std::max(refb, 2 * dN * 8);
-  }
+  std::vector<TileGroup> groups;
+  for (auto &r : active_)
+    if (r->job.method == 0 && !r->vdone) table.push_back(r->hj);
   if (!table.empty()) {
-    if (jobs_.n < table.size() && (rc = jobs_.alloc(ctx_, table.size()))) return rc;
+    size_t refb = 0;
+    plan_tile_groups(table, tiles, groups, ctx_->tune[FP32].hist64, &refb);
+    if (jobs_.n < table.size() && (rc = jobs_.alloc(ctx_, table.size() * 2))) return rc;
     if (tiles_.n < tiles.size() && (rc = tiles_.alloc(ctx_, tiles.size() * 2))) return rc;
     CCUBA_HIP(hipMemcpyAsync(jobs_.p, table.data(), table.size() * sizeof(VJob),
                              hipMemcpyHostToDevice, s));
     CCUBA_HIP(hipMemcpyAsync(tiles_.p, tiles.data(), tiles.size() * sizeof(int),
                              hipMemcpyHostToDevice, s));
+    // the host tables above must outlive the copies: the tick syncs before
+    // they go out of scope
     VegasArgs A{};
     A.jobs = jobs_.p;
     A.tile_job = tiles_.p;
-    A.ntiles = (int)tiles.size();
-    A.hist64 = hist64;
-    for (int p = 0; p < 2; ++p) {
-      if (!has[p]) continue;
-      A.lds_hist_byte_off = (long long)gridb[p];
-      const long long B = (long long)ctx_->ncu * ctx_->tune[p].blocks_per_cu;
-      const int nb = (int)std::min<long long>(B, (long long)tiles.size());
-      CCUBA_HIP(launch_dosample(A, p, nb, ctx_->tune[p].block, gridb[p] + histb[p], s));
-    }
+    A.hist64 = ctx_->tune[FP32].hist64;
+    if ((rc = launch_tile_groups(ctx_, A, groups, s))) return rc;
+    long long ftot = 0, ftot2 = 0;
+    fold_tasks(table, ends, &ftot, &ftot2);
+    if (fold_end_.n < ends.size() && (rc = fold_end_.alloc(ctx_, ends.size() * 2))) return rc;
+    CCUBA_HIP(hipMemcpyAsync(fold_end_.p, ends.data(), ends.size() * sizeof(long long),
+                             hipMemcpyHostToDevice, s));
+    FoldArgs F{jobs_.p, fold_end_.p, (int)table.size(), ftot, fold_end_.p + table.size(), ftot2};
+    CCUBA_HIP(launch_fold(F, s));
     CCUBA_HIP(launch_refine(A, (int)table.size(), refb, s));
   }
   // Cuhre: one rule launch over the children of every stepping request

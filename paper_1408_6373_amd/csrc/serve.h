@@ -65,6 +65,7 @@ class Server {
   std::vector<int> free_slots_;
   DevBuf<VJob> jobs_;
   DevBuf<int> tiles_;
+  DevBuf<long long> fold_end_;
   DevBuf<CSeg> segs_;
   DevBuf<long long> seg_end_;
   DevBuf<double> w7_, w5_;

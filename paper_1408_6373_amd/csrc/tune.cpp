@@ -2,10 +2,11 @@
 //
 // The sweep times one DoSample pass (no refinement) of a fixed synthetic
 // integral -- d = 8, oscillatory, 128 bins, 2^23 points -- for every
-// candidate (block size, persistent blocks per CU, FP32 histogram precision)
+// candidate (block size, persistent blocks per CU, points per lane per trip,
+// FP32 histogram precision)
 // and keeps the fastest.  Results do not depend on the choice beyond
 // floating-point summation order.  The cache file holds one line per
-// (device name, precision): "name prec block blocks_per_cu hist64".
+// (device name, precision): "name prec block blocks_per_cu hist64 ilp".
 #include "tune.h"
 
 #include <cstdio>
@@ -37,12 +38,13 @@ bool load_cache(const char *path, const std::string &key, int prec, VegasTune &t
   while (std::getline(f, line)) {
     std::istringstream is(line);
     std::string k;
-    int p, b, bpc, h;
-    if (!(is >> k >> p >> b >> bpc >> h)) continue;
+    int p, b, bpc, h, ilp;
+    if (!(is >> k >> p >> b >> bpc >> h >> ilp)) continue;
     if (k == key && p == prec) {
       t.block = b;
       t.blocks_per_cu = bpc;
       t.hist64 = h;
+      t.ilp = ilp;
       return true;
     }
   }
@@ -51,7 +53,8 @@ bool load_cache(const char *path, const std::string &key, int prec, VegasTune &t
 
 void store_cache(const char *path, const std::string &key, int prec, const VegasTune &t) {
   std::ofstream f(path, std::ios::app);
-  f << key << " " << prec << " " << t.block << " " << t.blocks_per_cu << " " << t.hist64 << "\n";
+  f << key << " " << prec << " " << t.block << " " << t.blocks_per_cu << " " << t.hist64 << " "
+    << t.ilp << "\n";
 }
 
 double time_candidate(ccuba_ctx *ctx, int prec, const VegasTune &cand) {
@@ -108,14 +111,16 @@ void maybe_autotune(ccuba_ctx *ctx, int prec) {
   VegasTune best = ctx->tune[prec];
   double best_ms = 1e30;
   const int blocks[] = {128, 256};
-  const int bpcs[] = {2, 4, 8};
+  const int bpcs[] = {2, 3, 4, 5, 6, 8};
   for (int b : blocks)
     for (int bpc : bpcs)
+      for (int ilp = 1; ilp <= 2; ++ilp)
       for (int h = 0; h < (prec == FP32 ? 2 : 1); ++h) {
         VegasTune c = ctx->tune[prec];
         c.block = b;
-        c.blocks_per_cu = bpc;
-        c.hist64 = h;
+        c.blocks_per_cu = b == 128 ? 2 * bpc : bpc;
+        c.ilp = ilp;
+        c.hist64 = prec == FP32 ? h : 1;
         const double ms = time_candidate(ctx, prec, c);
         if (ms < best_ms) {
           best_ms = ms;

@@ -9,9 +9,22 @@ namespace ccuba {
 struct VegasArgs {
   const VJob *jobs;
   const int *tile_job;  // job of each tile
-  int ntiles;
+  int tile_first;       // the launch's slice of the tile list
+  int tile_count;
   int hist64;           // FP32 path: FP64 LDS histogram
+  int ilp;              // points per lane per trip (1 or 2)
   long long lds_hist_byte_off;
+};
+
+// The fold launch: task_end[j] = inclusive prefix over jobs of
+// ngroups(ntiles_j) * ceil(ndim_j * nbins_j / 64) wavefront tasks.
+struct FoldArgs {
+  const VJob *jobs;
+  const long long *task_end;   // level 1 tasks
+  int njobs;
+  long long total;
+  const long long *task_end2;  // level 2: ceil(ndim * nbins / 64) per job
+  long long total2;
 };
 
 struct PointsArgs {
@@ -25,8 +38,11 @@ struct PointsArgs {
   int *bin;            // npts * ndim
 };
 
-hipError_t launch_dosample(const VegasArgs &A, int prec, int grid, int block, size_t lds,
-                           hipStream_t s);
+// Launch the DoSample instance of precision `prec' and `nb' Philox blocks
+// per point over the slice of the tile list in A.
+hipError_t launch_dosample(const VegasArgs &A, int prec, int nb, int grid, int block,
+                           size_t lds, hipStream_t s);
+hipError_t launch_fold(const FoldArgs &F, hipStream_t s);
 hipError_t launch_refine(const VegasArgs &A, int njobs, size_t lds, hipStream_t s);
 hipError_t launch_collect(const VegasArgs &A, int njobs, double *sums, double *hist,
                           hipStream_t s);

@@ -24,6 +24,8 @@
 #include "philox.h"
 #include "vegas.h"
 
+#include <vector>
+
 namespace ccuba {
 
 // ---------------------------------------------------------------------------
@@ -77,7 +79,10 @@ __device__ __forceinline__ const float *param_ptr<float>(const VJob &J, int whic
 // Sample the points [i0, i0 + cnt) of one tile; lane sums go to S1, S2.
 // NB = ceil(d/4) Philox blocks per point is a template argument so that the
 // per-dimension loop is fully unrolled with only the last block guarded.
-template <typename T, typename HT, int FAM, int NB>
+// Each lane carries ILP independent points per trip (q, q + blockDim, ...),
+// so that several Philox chains are in flight; a point past the tile end is
+// computed (its LDS reads stay in range) but contributes nothing.
+template <typename T, typename HT, int FAM, int NB, int ILP>
 __device__ __forceinline__ void sample_tile(const VJob &J, int t, long long i0, int cnt,
                                             const T *__restrict__ sE, HT *sH,
                                             const T *__restrict__ p0,
@@ -94,72 +99,73 @@ __device__ __forceinline__ void sample_tile(const VJob &J, int t, long long i0, 
     pp1[j] = p1[j];
   }
   const T phase0 = p1[0];
-  for (int q = threadIdx.x; q < cnt; q += blockDim.x) {
-    const uint32_t i = (uint32_t)(i0 + q);
-    T w = (T)1;
-    T acc = Genz<T, FAM>::init(phase0);
-    uint32_t kp[NB];
+  const int bs = blockDim.x;
+  for (int q0 = threadIdx.x; q0 < cnt; q0 += ILP * bs) {
+    T v[ILP];
+    uint32_t kp[ILP][NB];
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      kp[b] = 0;
-      const U4 r = philox4x32_10(U4{i, c1 | (uint32_t)b, sid, 0u}, k0, k1);
-      const uint32_t rr[4] = {r.x, r.y, r.z, r.w};
+    for (int e = 0; e < ILP; ++e) {
+      const uint32_t i = (uint32_t)(i0 + q0 + e * bs);
+      T w = (T)1;
+      T acc = Genz<T, FAM>::init(phase0);
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const int j = 4 * b + c;
-        if (b < NB - 1 || j < d) {
-          T x, jac;
-          int k;
-          map_coord(rr[c], N, Nt, sE + j * row, x, jac, k);
-          w = w * jac;
-          acc = Genz<T, FAM>::step(acc, x, pp0[j], pp1[j]);
-          kp[b] |= (uint32_t)k << (8 * c);
+      for (int b = 0; b < NB; ++b) {
+        kp[e][b] = 0;
+        const U4 r = philox4x32_10(U4{i, c1 | (uint32_t)b, sid, 0u}, k0, k1);
+        const uint32_t rr[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int j = 4 * b + c;
+          if (b < NB - 1 || j < d) {
+            T x, jac;
+            int k;
+            map_coord(rr[c], N, Nt, sE + j * row, x, jac, k);
+            w = w * jac;
+            acc = Genz<T, FAM>::step(acc, x, pp0[j], pp1[j]);
+            kp[e][b] |= (uint32_t)k << (8 * c);
+          }
+        }
+      }
+      v[e] = w * Genz<T, FAM>::finish(acc, d);
+    }
+#pragma unroll
+    for (int e = 0; e < ILP; ++e) {
+      if (e > 0 && q0 + e * bs >= cnt) break;
+      const double vd = (double)v[e];
+      S1 += vd;
+      S2 = fma(vd, vd, S2);
+      const HT v2 = (HT)(v[e] * v[e]);
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int j = 4 * b + c;
+          if (b < NB - 1 || j < d)
+            unsafeAtomicAdd(&sH[j * N + ((kp[e][b] >> (8 * c)) & 255u)], v2);
         }
       }
     }
-    const T f = Genz<T, FAM>::finish(acc, d);
-    const T v = w * f;
-    const double vd = (double)v;
-    S1 += vd;
-    S2 = fma(vd, vd, S2);
-    const HT v2 = (HT)(v * v);
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const int j = 4 * b + c;
-        if (b < NB - 1 || j < d) unsafeAtomicAdd(&sH[j * N + ((kp[b] >> (8 * c)) & 255u)], v2);
-      }
-    }
   }
 }
 
-template <typename T, typename HT, int FAM>
-__device__ __forceinline__ void sample_tile_nb(const VJob &J, int t, long long i0, int cnt,
-                                               const T *sE, HT *sH, const T *p0, const T *p1,
-                                               double &S1, double &S2) {
-  switch ((J.ndim + 3) >> 2) {
-    case 1: sample_tile<T, HT, FAM, 1>(J, t, i0, cnt, sE, sH, p0, p1, S1, S2); break;
-    case 2: sample_tile<T, HT, FAM, 2>(J, t, i0, cnt, sE, sH, p0, p1, S1, S2); break;
-    case 3: sample_tile<T, HT, FAM, 3>(J, t, i0, cnt, sE, sH, p0, p1, S1, S2); break;
-    default: sample_tile<T, HT, FAM, 4>(J, t, i0, cnt, sE, sH, p0, p1, S1, S2); break;
-  }
-}
-
-template <typename T, typename HT>
+// One kernel per (precision, histogram type, ILP, NB): every instance only
+// holds the registers its own dimension class needs.  A launch walks the
+// slice [tile_first, tile_first + tile_count) of the tile list, which holds
+// the tiles of the jobs of that class.
+template <typename T, typename HT, int ILP, int NB>
 __global__ void __launch_bounds__(256) vegas_dosample_kernel(VegasArgs A) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red[2][4];
-  __shared__ int s_last;
   T *sE = (T *)smem;
   HT *sH = (HT *)(smem + A.lds_hist_byte_off);
   const int tid = threadIdx.x, bs = blockDim.x, lane = tid & 63, wid = tid >> 6;
   const int myprec = sizeof(T) == 8 ? FP64 : FP32;
 
-  for (int tt = blockIdx.x; tt < A.ntiles; tt += gridDim.x) {
+  const int tend = A.tile_first + A.tile_count;
+  for (int tt = A.tile_first + blockIdx.x; tt < tend; tt += gridDim.x) {
     const int jb = A.tile_job[tt];
     const VJob J = A.jobs[jb];
-    if (J.prec != myprec) continue;
+    if (J.prec != myprec || ((J.ndim + 3) >> 2) != NB) continue;
     const VState st = *J.state;
     if (st.done) continue;
     const int d = J.ndim, N = J.nbins, dN = d * N, row = N + 1;
@@ -179,11 +185,11 @@ __global__ void __launch_bounds__(256) vegas_dosample_kernel(VegasArgs A) {
     const T *p1 = param_ptr<T>(J, 1);
     double S1 = 0.0, S2 = 0.0;
     switch (J.family) {
-      case GAUSSIAN: sample_tile_nb<T, HT, GAUSSIAN>(J, st.T, i0, cnt, sE, sH, p0, p1, S1, S2); break;
-      case OSCILLATORY: sample_tile_nb<T, HT, OSCILLATORY>(J, st.T, i0, cnt, sE, sH, p0, p1, S1, S2); break;
-      case PRODUCT_PEAK: sample_tile_nb<T, HT, PRODUCT_PEAK>(J, st.T, i0, cnt, sE, sH, p0, p1, S1, S2); break;
-      case CORNER_PEAK: sample_tile_nb<T, HT, CORNER_PEAK>(J, st.T, i0, cnt, sE, sH, p0, p1, S1, S2); break;
-      default: sample_tile_nb<T, HT, C0>(J, st.T, i0, cnt, sE, sH, p0, p1, S1, S2); break;
+      case GAUSSIAN: sample_tile<T, HT, GAUSSIAN, NB, ILP>(J, st.T, i0, cnt, sE, sH, p0, p1, S1, S2); break;
+      case OSCILLATORY: sample_tile<T, HT, OSCILLATORY, NB, ILP>(J, st.T, i0, cnt, sE, sH, p0, p1, S1, S2); break;
+      case PRODUCT_PEAK: sample_tile<T, HT, PRODUCT_PEAK, NB, ILP>(J, st.T, i0, cnt, sE, sH, p0, p1, S1, S2); break;
+      case CORNER_PEAK: sample_tile<T, HT, CORNER_PEAK, NB, ILP>(J, st.T, i0, cnt, sE, sH, p0, p1, S1, S2); break;
+      default: sample_tile<T, HT, C0, NB, ILP>(J, st.T, i0, cnt, sE, sH, p0, p1, S1, S2); break;
     }
     S1 = wave_sum(S1);
     S2 = wave_sum(S2);
@@ -204,39 +210,6 @@ __global__ void __launch_bounds__(256) vegas_dosample_kernel(VegasArgs A) {
     double *th = J.thist + (long long)lt * dN;
     for (int e = tid; e < dN; e += bs) th[e] = (double)sH[e];
 
-    // fold the 32-tile group once its last tile is written
-    const int g = lt / kGroupTiles, gfirst = g * kGroupTiles;
-    const int gsize = min(kGroupTiles, J.ntiles - gfirst);
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) {
-      const unsigned old = atomicAdd(&J.gcnt[g], 1u);
-      s_last = (old == (unsigned)(gsize - 1));
-    }
-    __syncthreads();
-    if (s_last) {
-      __threadfence();
-      if (tid == 0) {
-        atomicExch(&J.gcnt[g], 0u);
-        double a = 0.0, b = 0.0;
-        for (int q = 0; q < gsize; ++q) {
-          const long long ti = gfirst + q;
-          a += __hip_atomic_load(&J.tsums[2 * ti], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          b += __hip_atomic_load(&J.tsums[2 * ti + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        J.gsums[2 * g] = a;
-        J.gsums[2 * g + 1] = b;
-      }
-      const double *src = J.thist + (long long)gfirst * dN;
-      double *dst = J.ghist + (long long)g * dN;
-      for (int e = tid; e < dN; e += bs) {
-        double s = 0.0;
-        for (int q = 0; q < gsize; ++q)
-          s += __hip_atomic_load(&src[(long long)q * dN + e], __ATOMIC_RELAXED,
-                                 __HIP_MEMORY_SCOPE_AGENT);
-        dst[e] = s;
-      }
-    }
     __syncthreads();
   }
 }
@@ -276,27 +249,114 @@ __device__ double gamma_p(double a, double x) {
   return 1.0 - lead * h;
 }
 
-// One workgroup per integral: finish the iteration, combine, decide, refine.
-__global__ void __launch_bounds__(256) vegas_refine_kernel(VegasArgs A) {
+// Fold the per-tile partials of every running integral: one wavefront per
+// (integral, group of kGroupTiles tiles, 64-bin chunk) sums the group's tile
+// rows in tile order; the chunk-0 wave of a group also folds the tile sums.
+__global__ void __launch_bounds__(256) vegas_fold_kernel(FoldArgs F) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const long long g = (long long)blockIdx.x * 4 + w;
+  if (g >= F.total) return;  // whole waves only; no block barrier here
+  int lo = 0, hi = F.njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (F.task_end[mid] > g)
+      hi = mid;
+    else
+      lo = mid + 1;
+  }
+  const VJob &J = F.jobs[lo];
+  if (J.state->done) return;
+  const long long local = g - (lo > 0 ? F.task_end[lo - 1] : 0);
+  const int dN = J.ndim * J.nbins, nch = (dN + 63) >> 6;
+  const int grp = (int)(local / nch), ch = (int)(local - (long long)grp * nch);
+  const int t0 = grp * kGroupTiles, t1 = min(t0 + kGroupTiles, J.ntiles);
+  const int bin = ch * 64 + lane;
+  if (bin < dN) {
+    const double *src = J.thist + (long long)t0 * dN + bin;
+    double s = 0.0;
+#pragma unroll 8
+    for (int t = t0; t < t1; ++t, src += dN) s += *src;
+    J.ghist[(long long)grp * dN + bin] = s;
+  }
+  if (ch == 0 && lane < 2) {
+    double s = 0.0;
+    for (int t = t0; t < t1; ++t) s += J.tsums[2 * t + lane];
+    J.gsums[2 * grp + lane] = s;
+  }
+}
+
+// Second fold level: one wavefront per (integral, 64-bin chunk) sums the
+// group rows in group order into hsum = (S1, S2, H[d*N]).
+__global__ void __launch_bounds__(256) vegas_fold2_kernel(FoldArgs F) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const long long g = (long long)blockIdx.x * 4 + w;
+  if (g >= F.total2) return;
+  int lo = 0, hi = F.njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (F.task_end2[mid] > g)
+      hi = mid;
+    else
+      lo = mid + 1;
+  }
+  const VJob &J = F.jobs[lo];
+  if (J.state->done) return;
+  const int ch = (int)(g - (lo > 0 ? F.task_end2[lo - 1] : 0));
+  const int dN = J.ndim * J.nbins, ng = ngroups_of(J.ntiles);
+  const int bin = ch * 64 + lane;
+  if (bin < dN) {
+    const double *src = J.ghist + bin;
+    double s = 0.0;
+#pragma unroll 8
+    for (int q = 0; q < ng; ++q, src += dN) s += *src;
+    J.hsum[2 + bin] = s;
+  }
+  if (ch == 0 && lane < 2) {
+    double s = 0.0;
+    for (int q = 0; q < ng; ++q) s += J.gsums[2 * q + lane];
+    J.hsum[lane] = s;
+  }
+}
+
+__device__ __forceinline__ double wave_scan_incl(double v, int lane) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const double t = __shfl_up(v, o, 64);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One workgroup per integral: finish the iteration (a7).  Thread 0 forms the
+// iteration's estimate and variance, the inverse-variance combination and
+// the convergence decision; chi^2 and its probability are formed only once
+// the integral is done (no intermediate value is ever observed).  Then, if
+// the grid is to be refined, each wavefront takes whole dimensions: the
+// histogram row is smoothed, damped and prefix-summed with wave-wide scans
+// (lanes own contiguous runs of bins), and every new edge is placed by a
+// binary search of the prefix sums.
+__global__ void __launch_bounds__(1024) vegas_refine_kernel(VegasArgs A) {
   extern __shared__ __align__(16) double rsm[];
-  __shared__ int s_refine;
-  __shared__ double s_share[kMaxDim], s_dsum[kMaxDim];
-  __shared__ int s_has[kMaxDim];
+  __shared__ int s_mode;
   const int jb = blockIdx.x, tid = threadIdx.x, bs = blockDim.x;
+  const int lane = tid & 63, wv = tid >> 6, nwv = bs >> 6;
   const VJob J = A.jobs[jb];
   VState st = *J.state;
   if (st.done) return;
   const int d = J.ndim, N = J.nbins, dN = d * N, row = N + 1;
   const int t = st.T;
-  const int ng = ngroups_of(J.ntiles);
-
+  double *H = rsm;       // histogram, later prefix sums of m
+  double *D = rsm + dN;  // smoothed histogram, later m
+  for (int e = tid; e < dN; e += bs) H[e] = J.hsum[2 + e];
   if (tid == 0) {
     const long long n = J.nstart + (long long)t * J.nincrease;
-    double S1 = 0.0, S2 = 0.0;
-    for (int g = 0; g < ng; ++g) {
-      S1 += J.gsums[2 * g];
-      S2 += J.gsums[2 * g + 1];
-    }
+    const double S1 = J.hsum[0], S2 = J.hsum[1];
     const double I = S1 / (double)n;
     double var = S2 / (double)n - I * I;
     if (var < 0.0) var = 0.0;
@@ -307,35 +367,23 @@ __global__ void __launch_bounds__(256) vegas_refine_kernel(VegasArgs A) {
     const int T = t + 1;
     st.T = T;
     st.neval += n;
-    // inverse-variance combination over all iterations
-    int nz = 0;
-    double zs = 0.0;
-    for (int q = 0; q < T; ++q)
-      if (hV[q] == 0.0) {
-        ++nz;
-        zs += hI[q];
-      }
+    // inverse-variance combination over all iterations (running sums, added
+    // in iteration order)
+    if (var == 0.0) {
+      st.nzero += 1;
+      st.sum_zI += I;
+    } else {
+      st.sum_w += 1.0 / var;
+      st.sum_wI += I / var;
+    }
+    const int nz = st.nzero;
     st.dof = T - 1;
     if (nz > 0) {
-      st.integral = zs / nz;
+      st.integral = st.sum_zI / nz;
       st.error = 0.0;
-      st.chi2 = 0.0;
-      st.prob = 0.0;
     } else {
-      double ws = 0.0, wis = 0.0;
-      for (int q = 0; q < T; ++q) {
-        ws += 1.0 / hV[q];
-        wis += hI[q] / hV[q];
-      }
-      st.integral = wis / ws;
-      st.error = sqrt(1.0 / ws);
-      double chi2 = 0.0;
-      for (int q = 0; q < T; ++q) {
-        const double dl = hI[q] - st.integral;
-        chi2 += dl * dl / hV[q];
-      }
-      st.chi2 = chi2;
-      st.prob = st.dof > 0 ? gamma_p(0.5 * st.dof, 0.5 * chi2) : 0.0;
+      st.integral = st.sum_wI / st.sum_w;
+      st.error = sqrt(1.0 / st.sum_w);
     }
     const double tol = fmax(J.epsabs, J.epsrel * fabs(st.integral));
     const bool conv = st.neval >= J.mineval && st.error <= tol;
@@ -347,11 +395,22 @@ __global__ void __launch_bounds__(256) vegas_refine_kernel(VegasArgs A) {
       st.done = 1;
       st.fail = 1;
     }
+    st.chi2 = 0.0;
+    st.prob = 0.0;
+    if (st.done && nz == 0) {
+      double chi2 = 0.0;
+      for (int q = 0; q < T; ++q) {
+        const double dl = hI[q] - st.integral;
+        chi2 += dl * dl / hV[q];
+      }
+      st.chi2 = chi2;
+      st.prob = st.dof > 0 ? gamma_p(0.5 * st.dof, 0.5 * chi2) : 0.0;
+    }
     *J.state = st;
-    s_refine = conv ? 0 : ((J.flags & FLAG_FREEZE_GRID) ? 2 : 1);
+    s_mode = conv ? 0 : ((J.flags & FLAG_FREEZE_GRID) ? 2 : 1);
   }
   __syncthreads();
-  const int mode = s_refine;
+  const int mode = s_mode;
   if (mode == 0) return;
   const double *Eold = J.grid + (long long)(t & 1) * d * row;
   double *Enew = J.grid + (long long)((t + 1) & 1) * d * row;
@@ -359,105 +418,85 @@ __global__ void __launch_bounds__(256) vegas_refine_kernel(VegasArgs A) {
     for (int e = tid; e < d * row; e += bs) Enew[e] = Eold[e];
     return;
   }
-  double *H = rsm;        // histogram, later prefix sums of m
-  double *D = rsm + dN;   // smoothed histogram, later m
-  for (int e = tid; e < dN; e += bs) {
-    double s = 0.0;
-    for (int g = 0; g < ng; ++g) s += J.ghist[(long long)g * dN + e];
-    H[e] = s;
-  }
-  __syncthreads();
-  // 3-point smoothing
-  for (int e = tid; e < dN; e += bs) {
-    const int j = e / N, k = e - j * N;
-    const double *h = H + j * N;
-    double v;
-    if (k == 0)
-      v = (h[0] + h[1]) / 2.0;
-    else if (k == N - 1)
-      v = (h[N - 2] + h[N - 1]) / 2.0;
-    else
-      v = (h[k - 1] + h[k] + h[k + 1]) / 3.0;
-    D[e] = v;
-  }
-  __syncthreads();
-  if (tid < d) {
-    double hs = 0.0, ds = 0.0;
-    for (int k = 0; k < N; ++k) hs += H[tid * N + k];
-    for (int k = 0; k < N; ++k) ds += D[tid * N + k];
-    s_has[tid] = hs > 0.0;
-    s_dsum[tid] = ds;
-  }
-  __syncthreads();
-  // damping m_k = ((r-1)/ln r)^1.5, r = normalised smoothed histogram
-  for (int e = tid; e < dN; e += bs) {
-    const int j = e / N;
-    if (!s_has[j]) continue;
-    const double r = D[e] / s_dsum[j];
-    double m;
-    if (r == 0.0)
-      m = 0.0;
-    else if (r == 1.0)
-      m = 1.0;
-    else
-      m = pow((r - 1.0) / log(r), 1.5);
-    D[e] = m;
-  }
-  __syncthreads();
-  if (tid < d && s_has[tid]) {
-    double acc = 0.0;
-    for (int k = 0; k < N; ++k) {
-      acc += D[tid * N + k];
-      H[tid * N + k] = acc;
-    }
-    s_share[tid] = acc / N;
-  }
-  __syncthreads();
-  // new edge i of dimension j: smallest old bin k with C_k >= i * share
-  for (int e = tid; e < d * row; e += bs) {
-    const int j = e / row, i = e - j * row;
+  const int per = (N + 63) >> 6;  // contiguous bins per lane
+  for (int j = wv; j < d; j += nwv) {
+    double *h = H + j * N, *dd = D + j * N;
     const double *Eo = Eold + j * row;
-    if (!s_has[j] || i == 0 || i == N) {
-      Enew[e] = s_has[j] ? (i == 0 ? 0.0 : 1.0) : Eo[i];
+    double *En = Enew + j * row;
+    const int k0 = lane * per, k1 = min(k0 + per, N);
+    // smoothing and the two row sums
+    double hs = 0.0, ds = 0.0;
+    for (int k = k0; k < k1; ++k) {
+      double v;
+      if (k == 0)
+        v = (h[0] + h[1]) / 2.0;
+      else if (k == N - 1)
+        v = (h[N - 2] + h[N - 1]) / 2.0;
+      else
+        v = (h[k - 1] + h[k] + h[k + 1]) / 3.0;
+      hs += h[k];
+      ds += v;
+      dd[k] = v;
+    }
+    hs = wave_sum(hs);
+    ds = wave_sum(ds);
+    if (!(hs > 0.0)) {
+      for (int i = lane; i <= N; i += 64) En[i] = Eo[i];
       continue;
     }
-    const double *C = H + j * N;
-    const double target = i * s_share[j];
-    int lo = 0, hi = N - 1;  // C[hi] >= target or hi == N-1
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (C[mid] < target)
-        lo = mid + 1;
+    // damping, then prefix sums of m into h (the histogram is no longer needed)
+    wave_sync_lds();
+    double run = 0.0;
+    for (int k = k0; k < k1; ++k) {
+      const double r = dd[k] / ds;
+      double m;
+      if (r == 0.0)
+        m = 0.0;
+      else if (r == 1.0)
+        m = 1.0;
       else
-        hi = mid;
+        m = pow((r - 1.0) / log(r), 1.5);
+      dd[k] = m;
+      run += m;
     }
-    const int k = lo;
-    const double before = k > 0 ? C[k - 1] : 0.0;
-    Enew[e] = Eo[k] + (target - before) / D[j * N + k] * (Eo[k + 1] - Eo[k]);
+    const double incl = wave_scan_incl(run, lane);
+    double acc = incl - run;
+    for (int k = k0; k < k1; ++k) {
+      acc += dd[k];
+      h[k] = acc;
+    }
+    wave_sync_lds();
+    const double share = h[N - 1] / N;
+    // new edge i: smallest old bin k with C_k >= i * share
+    for (int i = lane; i <= N; i += 64) {
+      if (i == 0 || i == N) {
+        En[i] = i == 0 ? 0.0 : 1.0;
+        continue;
+      }
+      const double target = i * share;
+      int lo = 0, hi = N - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (h[mid] < target)
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+      const double before = lo > 0 ? h[lo - 1] : 0.0;
+      En[i] = Eo[lo] + (target - before) / dd[lo] * (Eo[lo + 1] - Eo[lo]);
+    }
   }
 }
 
-// Copy out the group partials of every job as its iteration total: sums[2]
-// and hist[d*N] (fixed order); used by the raw DoSample entry point.
+// Copy out every job's folded iteration totals: sums[2] and hist[d*N]; used by
+// the raw DoSample entry point.
 __global__ void __launch_bounds__(256) vegas_collect_kernel(VegasArgs A, double *sums,
                                                             double *hist) {
   const int jb = blockIdx.x, tid = threadIdx.x;
   const VJob J = A.jobs[jb];
-  const int dN = J.ndim * J.nbins, ng = ngroups_of(J.ntiles);
-  if (tid == 0) {
-    double a = 0.0, b = 0.0;
-    for (int g = 0; g < ng; ++g) {
-      a += J.gsums[2 * g];
-      b += J.gsums[2 * g + 1];
-    }
-    sums[2 * jb] = a;
-    sums[2 * jb + 1] = b;
-  }
-  for (int e = tid; e < dN; e += blockDim.x) {
-    double s = 0.0;
-    for (int g = 0; g < ng; ++g) s += J.ghist[(long long)g * dN + e];
-    hist[e] = s;
-  }
+  const int dN = J.ndim * J.nbins;
+  if (tid < 2) sums[2 * jb + tid] = J.hsum[tid];
+  for (int e = tid; e < dN; e += blockDim.x) hist[e] = J.hsum[2 + e];
 }
 
 // Debug/parity kernel: the points of one iteration (a1-a3), with the grid
@@ -496,22 +535,53 @@ __global__ void __launch_bounds__(256) vegas_points_kernel(PointsArgs P) {
 // ---------------------------------------------------------------------------
 // launchers
 
-hipError_t launch_dosample(const VegasArgs &A, int prec, int grid, int block, size_t lds,
-                           hipStream_t s) {
+template <int ILP, int NB>
+static void launch_dosample_nb(const VegasArgs &A, int prec, int grid, int block, size_t lds,
+                               hipStream_t s) {
   if (prec == FP64) {
-    hipLaunchKernelGGL((vegas_dosample_kernel<double, double>), dim3(grid), dim3(block), lds, s,
-                       A);
+    hipLaunchKernelGGL((vegas_dosample_kernel<double, double, ILP, NB>), dim3(grid), dim3(block),
+                       lds, s, A);
   } else if (A.hist64) {
-    hipLaunchKernelGGL((vegas_dosample_kernel<float, double>), dim3(grid), dim3(block), lds, s,
-                       A);
+    hipLaunchKernelGGL((vegas_dosample_kernel<float, double, ILP, NB>), dim3(grid), dim3(block),
+                       lds, s, A);
   } else {
-    hipLaunchKernelGGL((vegas_dosample_kernel<float, float>), dim3(grid), dim3(block), lds, s, A);
+    hipLaunchKernelGGL((vegas_dosample_kernel<float, float, ILP, NB>), dim3(grid), dim3(block),
+                       lds, s, A);
   }
+}
+
+template <int ILP>
+static void launch_dosample_ilp(const VegasArgs &A, int prec, int nb, int grid, int block,
+                                size_t lds, hipStream_t s) {
+  switch (nb) {
+    case 1: launch_dosample_nb<ILP, 1>(A, prec, grid, block, lds, s); break;
+    case 2: launch_dosample_nb<ILP, 2>(A, prec, grid, block, lds, s); break;
+    case 3: launch_dosample_nb<ILP, 3>(A, prec, grid, block, lds, s); break;
+    default: launch_dosample_nb<ILP, 4>(A, prec, grid, block, lds, s); break;
+  }
+}
+
+hipError_t launch_dosample(const VegasArgs &A, int prec, int nb, int grid, int block,
+                           size_t lds, hipStream_t s) {
+  if (A.tile_count <= 0 || grid <= 0) return hipSuccess;
+  if (A.ilp == 2)
+    launch_dosample_ilp<2>(A, prec, nb, grid, block, lds, s);
+  else
+    launch_dosample_ilp<1>(A, prec, nb, grid, block, lds, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_fold(const FoldArgs &F, hipStream_t s) {
+  if (F.total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(vegas_fold_kernel, dim3((unsigned)((F.total + 3) / 4)), dim3(256), 0, s, F);
+  hipLaunchKernelGGL(vegas_fold2_kernel, dim3((unsigned)((F.total2 + 3) / 4)), dim3(256), 0, s,
+                     F);
   return hipGetLastError();
 }
 
 hipError_t launch_refine(const VegasArgs &A, int njobs, size_t lds, hipStream_t s) {
-  hipLaunchKernelGGL(vegas_refine_kernel, dim3(njobs), dim3(256), lds, s, A);
+  // one wavefront per dimension (up to 16)
+  hipLaunchKernelGGL(vegas_refine_kernel, dim3(njobs), dim3(1024), lds, s, A);
   return hipGetLastError();
 }
 
@@ -540,10 +610,14 @@ hipError_t set_kernel_limits() {
   // a runtime that refuses keeps its default limit and such launches report
   // an error instead of running
   const int big = 160 * 1024;
-  const void *fns[] = {(const void *)vegas_dosample_kernel<double, double>,
-                       (const void *)vegas_dosample_kernel<float, double>,
-                       (const void *)vegas_dosample_kernel<float, float>,
-                       (const void *)vegas_refine_kernel};
+  std::vector<const void *> fns = {
+      (const void *)vegas_dosample_kernel<double, double, 1, 4>,
+      (const void *)vegas_dosample_kernel<float, double, 1, 4>,
+      (const void *)vegas_dosample_kernel<float, float, 1, 4>,
+      (const void *)vegas_dosample_kernel<double, double, 2, 4>,
+      (const void *)vegas_dosample_kernel<float, double, 2, 4>,
+      (const void *)vegas_dosample_kernel<float, float, 2, 4>,
+      (const void *)vegas_refine_kernel};
   for (const void *f : fns)
     if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, big) != hipSuccess)
       (void)hipGetLastError();

@@ -92,6 +92,63 @@ void genz_constants(const VegasSpec &s, double p64[2][kParamRow], float p32[2][k
   }
 }
 
+void plan_tile_groups(std::vector<VJob> &jobs, std::vector<int> &tiles,
+                      std::vector<TileGroup> &groups, int hist64, size_t *refine_lds) {
+  tiles.clear();
+  groups.clear();
+  size_t ref = 0;
+  for (int p = 0; p < 2; ++p)
+    for (int nb = 1; nb <= 4; ++nb) {
+      TileGroup g{p, nb, (int)tiles.size(), 0, 0, 0};
+      size_t hb = 0;
+      for (int j = 0; j < (int)jobs.size(); ++j) {
+        VJob &J = jobs[j];
+        if (J.prec != p || ((J.ndim + 3) >> 2) != nb) continue;
+        J.tile0 = (int)tiles.size();
+        for (int q = 0; q < J.ntiles; ++q) tiles.push_back(j);
+        const size_t row = (size_t)J.ndim * (J.nbins + 1), dN = (size_t)J.ndim * J.nbins;
+        const size_t tsz = p == FP64 ? 8 : 4, hsz = (p == FP64 || hist64) ? 8 : 4;
+        g.grid_bytes = std::max(g.grid_bytes, align16(row * tsz));
+        hb = std::max(hb, dN * hsz);
+        ref = std::max(ref, 2 * dN * 8);
+      }
+      g.count = (int)tiles.size() - g.first;
+      g.lds = g.grid_bytes + hb;
+      if (g.count > 0) groups.push_back(g);
+    }
+  *refine_lds = ref;
+}
+
+int launch_tile_groups(ccuba_ctx *ctx, VegasArgs A, const std::vector<TileGroup> &groups,
+                       hipStream_t s) {
+  for (const TileGroup &g : groups) {
+    A.tile_first = g.first;
+    A.tile_count = g.count;
+    A.ilp = ctx->tune[g.prec].ilp;
+    A.lds_hist_byte_off = (long long)g.grid_bytes;
+    const long long B = (long long)ctx->ncu * ctx->tune[g.prec].blocks_per_cu;
+    const int grid = (int)std::min<long long>(B, g.count);
+    CCUBA_HIP(launch_dosample(A, g.prec, g.nb, grid, ctx->tune[g.prec].block, g.lds, s));
+  }
+  return CCUBA_OK;
+}
+
+void fold_tasks(const std::vector<VJob> &jobs, std::vector<long long> &ends, long long *total,
+                long long *total2) {
+  const size_t n = jobs.size();
+  ends.resize(2 * n);
+  long long t1 = 0, t2 = 0;
+  for (size_t j = 0; j < n; ++j) {
+    const long long dN = (long long)jobs[j].ndim * jobs[j].nbins, nch = (dN + 63) / 64;
+    t1 += (long long)ngroups_of(jobs[j].ntiles) * nch;
+    t2 += nch;
+    ends[j] = t1;
+    ends[n + j] = t2;
+  }
+  *total = t1;
+  *total2 = t2;
+}
+
 VegasEngine::~VegasEngine() {
   if (graph_exec_) (void)hipGraphExecDestroy(graph_exec_);
   if (graph_) (void)hipGraphDestroy(graph_);
@@ -125,10 +182,11 @@ int VegasEngine::setup(const std::vector<VegasSpec> &specs, bool single, hipStre
   struct Offsets {
     long long grid, thist, ghist, iter;
     int tile0, group0;
+    long long hsum;
   };
   std::vector<Offsets> off(n);
   std::vector<int> tile_job;
-  long long goff = 0, thoff = 0, ghoff = 0, ioff = 0;
+  long long goff = 0, thoff = 0, ghoff = 0, ioff = 0, hsoff = 0;
   int tile0 = 0, group0 = 0;
   size_t grid_bytes[2] = {0, 0}, hist_bytes[2] = {0, 0}, refine_bytes = 0;
   for (int j = 0; j < n; ++j) {
@@ -165,12 +223,12 @@ int VegasEngine::setup(const std::vector<VegasSpec> &specs, bool single, hipStre
     J.tile_pts = P;
     J.hist_cap = std::max(1, iters[j]);
     const long long dN = (long long)sp.ndim * sp.nbins, row = (long long)sp.ndim * (sp.nbins + 1);
-    off[j] = Offsets{goff, thoff, ghoff, ioff, tile0, group0};
+    off[j] = Offsets{goff, thoff, ghoff, ioff, tile0, group0, hsoff};
+    hsoff += 2 + dN;
     goff += 2 * row;
     thoff += nt * dN;
     ghoff += ngroups_of(nt) * dN;
     ioff += J.hist_cap;
-    for (int q = 0; q < nt; ++q) tile_job.push_back(j);
     tile0 += nt;
     group0 += ngroups_of(nt);
     const size_t tsz = p == FP64 ? 8 : 4, hsz = (p == FP64 || hist64_) ? 8 : 4;
@@ -180,13 +238,14 @@ int VegasEngine::setup(const std::vector<VegasSpec> &specs, bool single, hipStre
   }
   ntiles_ = tile0;
   ngroups_ = group0;
+  plan_tile_groups(hjobs_, tile_job, tgroups_, hist64_, &lds_refine_);
   for (int p = 0; p < 2; ++p) {
-    grid_bytes_[p] = grid_bytes[p];
-    lds_dosample_[p] = grid_bytes[p] + hist_bytes[p];
     const long long B = (long long)ctx_->ncu * ctx_->tune[p].blocks_per_cu;
     nblocks_[p] = (int)std::min<long long>(B, ntiles_);
   }
-  lds_refine_ = refine_bytes;
+  (void)grid_bytes;
+  (void)hist_bytes;
+  (void)refine_bytes;
 
   int rc;
   if ((rc = jobs_.alloc(ctx_, n)) || (rc = state_.alloc(ctx_, n)) ||
@@ -195,7 +254,8 @@ int VegasEngine::setup(const std::vector<VegasSpec> &specs, bool single, hipStre
       (rc = p32_.alloc(ctx_, (size_t)n * 2 * kParamRow)) ||
       (rc = tile_sums_.alloc(ctx_, 2 * (size_t)ntiles_)) || (rc = tile_hist_.alloc(ctx_, thoff)) ||
       (rc = group_sums_.alloc(ctx_, 2 * (size_t)ngroups_)) ||
-      (rc = group_hist_.alloc(ctx_, ghoff)) || (rc = group_cnt_.alloc(ctx_, ngroups_)) ||
+      (rc = group_hist_.alloc(ctx_, ghoff)) || (rc = fold_end_.alloc(ctx_, 2 * n)) ||
+      (rc = hsum_.alloc(ctx_, hsoff)) ||
       (rc = iter_I_.alloc(ctx_, ioff)) || (rc = iter_var_.alloc(ctx_, ioff)))
     return rc;
 
@@ -207,7 +267,7 @@ int VegasEngine::setup(const std::vector<VegasSpec> &specs, bool single, hipStre
     J.thist = tile_hist_.p + off[j].thist;
     J.gsums = group_sums_.p + 2ll * off[j].group0;
     J.ghist = group_hist_.p + off[j].ghist;
-    J.gcnt = group_cnt_.p + off[j].group0;
+    J.hsum = hsum_.p + off[j].hsum;
     J.iter_I = iter_I_.p + off[j].iter;
     J.iter_var = iter_var_.p + off[j].iter;
     J.p64 = p64_.p + (size_t)j * 2 * kParamRow;
@@ -239,11 +299,14 @@ int VegasEngine::setup(const std::vector<VegasSpec> &specs, bool single, hipStre
       (rc = upload(grids_, grids, s)) || (rc = upload(p64_, p64, s)) ||
       (rc = upload(p32_, p32, s)) || (rc = upload(state_, st, s)))
     return rc;
-  CCUBA_HIP(hipMemsetAsync(group_cnt_.p, 0, ngroups_ * sizeof(unsigned), s));
+  std::vector<long long> ends;
+  fold_tasks(hjobs_, ends, &fold_total_, &fold_total2_);
+  if ((rc = upload(fold_end_, ends, s))) return rc;
 
   args_.jobs = jobs_.p;
   args_.tile_job = tile_job_.p;
-  args_.ntiles = ntiles_;
+  args_.tile_first = 0;
+  args_.tile_count = ntiles_;
   args_.hist64 = hist64_;
   // host copies of the tables must outlive the async uploads
   CCUBA_HIP(hipStreamSynchronize(s));
@@ -251,12 +314,10 @@ int VegasEngine::setup(const std::vector<VegasSpec> &specs, bool single, hipStre
 }
 
 int VegasEngine::dosample_only(hipStream_t s) {
-  for (int p = 0; p < 2; ++p) {
-    if (!has_prec_[p]) continue;
-    VegasArgs A = args_;
-    A.lds_hist_byte_off = (long long)grid_bytes_[p];  // histogram follows the grid copy
-    CCUBA_HIP(launch_dosample(A, p, nblocks_[p], block_[p], lds_dosample_[p], s));
-  }
+  const int rc = launch_tile_groups(ctx_, args_, tgroups_, s);
+  if (rc) return rc;
+  FoldArgs F{jobs_.p, fold_end_.p, njobs(), fold_total_, fold_end_.p + njobs(), fold_total2_};
+  CCUBA_HIP(launch_fold(F, s));
   return CCUBA_OK;
 }
 
@@ -421,8 +482,8 @@ int VegasEngine::refine_only(const double *hist, const double *grid_in, double *
   // a synthetic finished iteration with n = 2, S1 = 1, S2 = 2 (I = 1/2,
   // sigma^2 = 3/4 > 0, so the zero-tolerance job never converges)
   const double sums[2] = {1.0, 2.0};
-  CCUBA_HIP(hipMemcpyAsync(J.gsums, sums, sizeof(sums), hipMemcpyHostToDevice, s));
-  CCUBA_HIP(hipMemcpyAsync(J.ghist, hist, dN * sizeof(double), hipMemcpyHostToDevice, s));
+  CCUBA_HIP(hipMemcpyAsync(J.hsum, sums, sizeof(sums), hipMemcpyHostToDevice, s));
+  CCUBA_HIP(hipMemcpyAsync(J.hsum + 2, hist, dN * sizeof(double), hipMemcpyHostToDevice, s));
   CCUBA_HIP(hipStreamSynchronize(s));
   rc = set_iteration(0, 0, s);
   if (rc) return rc;

@@ -31,6 +31,25 @@ void vegas_budget(const VegasSpec &s, int *iters, long long *nmax);
 // The per-dimension constants of the device Genz code (see genz.h).
 void genz_constants(const VegasSpec &s, double p64[2][kParamRow], float p32[2][kParamRow]);
 
+// A slice of a launch's tile list holding the tiles of every job of one
+// (precision, Philox blocks per point) class, with the LDS it needs.
+struct TileGroup {
+  int prec, nb, first, count;
+  size_t grid_bytes, lds;
+};
+
+// Order the tiles of `jobs' by class, set each job's tile0 to the position of
+// its first tile, and describe the classes.  Also returns the refine LDS.
+void plan_tile_groups(std::vector<VJob> &jobs, std::vector<int> &tiles,
+                      std::vector<TileGroup> &groups, int hist64, size_t *refine_lds);
+// One DoSample launch per class.
+int launch_tile_groups(ccuba_ctx *ctx, VegasArgs A, const std::vector<TileGroup> &groups,
+                       hipStream_t s);
+// Inclusive prefixes over jobs of their fold tasks, both levels (see
+// FoldArgs); ends holds level 1 then level 2 (2 * njobs entries).
+void fold_tasks(const std::vector<VJob> &jobs, std::vector<long long> &ends, long long *total,
+                long long *total2);
+
 class VegasEngine {
  public:
   explicit VegasEngine(ccuba_ctx *ctx) : ctx_(ctx) {}
@@ -79,9 +98,12 @@ class VegasEngine {
   DevBuf<double> grids_, p64_, tile_sums_, tile_hist_, group_sums_, group_hist_, iter_I_,
       iter_var_;
   DevBuf<float> p32_;
-  DevBuf<unsigned> group_cnt_;
+  DevBuf<long long> fold_end_;
+  DevBuf<double> hsum_;
+  long long fold_total_ = 0, fold_total2_ = 0;
   VegasArgs args_{};
   int ntiles_ = 0, ngroups_ = 0;
+  std::vector<TileGroup> tgroups_;
   int has_prec_[2] = {0, 0};
   int nblocks_[2] = {0, 0}, block_[2] = {256, 256};
   size_t lds_dosample_[2] = {0, 0}, grid_bytes_[2] = {0, 0}, lds_refine_ = 0;
