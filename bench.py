@@ -245,6 +245,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip batch/cuhre/serving legs")
     ap.add_argument("--serving-requests", type=int, default=300)
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="for PMC runs: one 1 GiB device copy (calibration), then one FP32 "
+                         "integral of the headline workload; prints a JSON line")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (--gpus 1); no multi-GPU path exists",
@@ -257,6 +260,18 @@ def main():
 
     torch.cuda.set_device(0)
     params = {fam: W.genz_params(fam, D, 1) for fam in FAMILIES}
+    if args.traffic_probe:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        ctx = cc.Context(device=0)
+        a, u = params[1]
+        r = cc.vegas(1, a, u, ctx=ctx, flags=cc.FP32_EVAL, nbins=NBINS, nstart=NPTS,
+                     maxeval=ITERS * NPTS, seed=1)
+        ctx.close()
+        print(json.dumps({"traffic_probe": True, "copy_bytes": 1 << 30, "neval": r["neval"]}))
+        return
     ctx = cc.Context(device=0)
 
     ev32, t32 = _timed(cc, ctx, params, cc.FP32_EVAL, args.steps, args.warmup)
