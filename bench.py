@@ -45,7 +45,8 @@ class Stats(C.Structure):
     _fields_ = [("dosample_launches", C.c_longlong), ("dosample_ms", C.c_double),
                 ("refine_launches", C.c_longlong), ("refine_ms", C.c_double),
                 ("evals", C.c_longlong), ("rule_launches", C.c_longlong),
-                ("rule_ms", C.c_double), ("rule_evals", C.c_longlong)]
+                ("rule_ms", C.c_double), ("rule_evals", C.c_longlong),
+                ("fold_ms", C.c_double)]
 
 
 def _stats(cc, ctx, reset=True):
@@ -82,32 +83,45 @@ def _timed(cc, ctx, params, prec, steps, warmup):
 
 
 def _roofline(cc, ctx, params):
-    """Event-timed DoSample launches of one profiled FP32 step."""
+    """Event-timed DoSample sampling launches of one profiled FP32 step.
+
+    The library records HIP events on its own stream around the sampling
+    kernel, the fold of its partial sums and the refine kernel of every
+    iteration; the sampling kernel is the dominant one and the roofline is
+    its VALU issue rate: ISA-counted slots per point x points per launch /
+    average launch duration."""
     from paper_1408_6373_amd import isa_slots
     table = isa_slots.load() or {}
     _stats(cc, ctx)
     ctx.config("profile", 1)
-    ms = evals = launches = 0
+    ms = fold_ms = refine_ms = 0.0
+    evals = launches = 0
     slots = 0.0
-    refine_ms = 0.0
-    key = "f32h64_ilp2_nb2"  # the defaults: FP64 LDS histogram, 2 points/lane
+    # the defaults at d = 8, 128 bins: FP64 LDS histogram, 2 points per lane
+    # per trip, 2 Philox blocks per point, power-of-two bin count
+    key = "f32h64_ilp2_nb2_pow2"
     for fam in FAMILIES:
         a, u = params[fam]
         cc.vegas(fam, a, u, ctx=ctx, flags=cc.FP32_EVAL, nbins=NBINS, nstart=NPTS,
                  maxeval=ITERS * NPTS, seed=1)
         st = _stats(cc, ctx)
         ms += st.dosample_ms
+        fold_ms += st.fold_ms
         evals += st.evals
         launches += st.dosample_launches
         refine_ms += st.refine_ms
         per = table.get(key, {}).get(FAMILY_KEYS[fam])
         slots = None if (per is None or slots is None) else slots + per * st.evals
     ctx.config("profile", 0)
-    out = {"bound": "alu", "kernel": "vegas_dosample_kernel<float,double,2,2> + fold",
+    n = max(launches, 1)
+    out = {"bound": "alu", "kernel": "vegas_dosample_kernel<float,double,2,2,true>",
            "unit": "T VALU-slots/s", "peak": PEAK_VALU / 1e12,
-           "avg_launch_ms": ms / max(launches, 1), "launches": launches,
+           "avg_launch_ms": ms / n, "launches": launches,
+           "points_per_launch": evals / n,
            "kernel_evals_per_s": evals / (ms * 1e-3),
-           "refine_ms_per_launch": refine_ms / max(launches, 1),
+           "fold_ms_per_launch": fold_ms / n,
+           "refine_ms_per_launch": refine_ms / n,
+           "sample_fold_refine_evals_per_s": evals / ((ms + fold_ms + refine_ms) * 1e-3),
            "slots_per_point": None if slots is None else slots / evals,
            "traffic": _traffic()}
     if slots is not None:
@@ -130,6 +144,68 @@ def _traffic():
     if rec.get("kernel_source_sha256") != hashlib.sha256(src).hexdigest():
         return None
     return rec.get("bytes_per_launch")
+
+
+def _read_pmc(path):
+    """{kernel name: [counter value per dispatch]} from a rocprofv3 counter CSV."""
+    import csv
+    out = {}
+    with open(path, newline="") as f:
+        for row in csv.DictReader(f):
+            out.setdefault(row["Kernel_Name"], []).append(float(row["Counter_Value"]))
+    return out
+
+
+def summarize_pmc(fetch_csv, write_csv, out_path, commands):
+    """Write the HBM-traffic summary of the DoSample kernels of a
+    --traffic-probe run: FETCH_SIZE and WRITE_SIZE (KiB per dispatch, summed
+    over the XCDs by rocprofv3), each scaled by what the same counter reads
+    for the probe's 1 GiB device-to-device copy."""
+    import hashlib
+    fetch, write = _read_pmc(fetch_csv), _read_pmc(write_csv)
+    copy = "__amd_rocclr_copyBuffer"
+    cf, cw = max(fetch.get(copy, [0])), max(write.get(copy, [0]))
+    if cf <= 0 or cw <= 0:
+        raise SystemExit("no 1 GiB copy dispatch in the counter files")
+    gib = float(1 << 30)
+    fs, ws = gib / (cf * 1024), gib / (cw * 1024)
+    rec = {"what": "HBM bytes per dispatch of the FP32 DoSample kernels (Vegas d=8 "
+                   "oscillatory, 128 bins, 1e7 points per iteration, 20 iterations) from "
+                   "rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by the same counters on a "
+                   "1 GiB device-to-device copy",
+           "commands": commands,
+           "copy_calibration": {"bytes": 1 << 30, "fetch_kib": cf, "write_kib": cw,
+                                "fetch_scale": fs, "write_scale": ws}}
+    for name, key in (("vegas_dosample_kernel", "dosample"), ("vegas_fold_kernel", "fold"),
+                      ("vegas_fold2_kernel", "fold2")):
+        fk = [v for k, vs in fetch.items() if name + "<" in k or name + "(" in k for v in vs]
+        wk = [v for k, vs in write.items() if name + "<" in k or name + "(" in k for v in vs]
+        if not fk or not wk:
+            continue
+        f_avg, w_avg = sum(fk) / len(fk), sum(wk) / len(wk)
+        rec[key] = {"dispatches": len(fk), "fetch_kib": f_avg, "write_kib": w_avg,
+                    "bytes": 1024 * (f_avg * fs + w_avg * ws)}
+    src = open(os.path.join(ROOT, "paper_1408_6373_amd", "csrc", "vegas.hip"), "rb").read()
+    rec["kernel_source_sha256"] = hashlib.sha256(src).hexdigest()
+    rec["bytes_per_launch"] = rec["dosample"]["bytes"]
+    with open(out_path, "w") as f:
+        json.dump(rec, f, indent=1)
+    return rec
+
+
+def summarize_stats(stats_csv, out_path, command, note):
+    """Write a short text table from a rocprofv3 --stats kernel_stats.csv."""
+    import csv
+    rows = list(csv.DictReader(open(stats_csv, newline="")))
+    with open(out_path, "w") as f:
+        f.write("rocprofv3 kernel statistics (MI355X, gfx950)\n")
+        f.write("command: %s\n%s\n\n" % (command, note))
+        f.write("%-72s %7s %11s %11s %7s\n" % ("kernel", "calls", "avg_us", "total_ms", "pct"))
+        for r in rows:
+            name = r["Name"].replace("ccuba::", "")
+            f.write("%-72s %7d %11.1f %11.2f %7.2f\n" % (
+                name[:72], int(r["Calls"]), float(r["AverageNs"]) / 1e3,
+                float(r["TotalDurationNs"]) / 1e6, float(r["Percentage"])))
 
 
 def _batch_leg(cc, ctx):
@@ -248,7 +324,20 @@ def main():
     ap.add_argument("--traffic-probe", action="store_true",
                     help="for PMC runs: one 1 GiB device copy (calibration), then one FP32 "
                          "integral of the headline workload; prints a JSON line")
+    ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT"),
+                    help="write the traffic summary of two --traffic-probe counter runs")
+    ap.add_argument("--stats-summary", nargs=2, metavar=("STATS_CSV", "OUT"),
+                    help="write a text table of a rocprofv3 kernel_stats.csv")
+    ap.add_argument("--command", default="", help="command recorded in a summary")
+    ap.add_argument("--note", default="", help="note recorded in a stats summary")
     args = ap.parse_args()
+    if args.pmc_summary:
+        cmds = [c for c in args.command.split(";;") if c]
+        print(json.dumps(summarize_pmc(*args.pmc_summary[:2], args.pmc_summary[2], cmds)))
+        return
+    if args.stats_summary:
+        summarize_stats(args.stats_summary[0], args.stats_summary[1], args.command, args.note)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (--gpus 1); no multi-GPU path exists",
               file=sys.stderr)

@@ -253,19 +253,21 @@ int ccuba_vegas_refine(ccuba_ctx *ctx, int ndim, int nbins, const double *hist,
                        const double *grid_in, double *grid_out);
 
 /* Kernel timing of the context, measured with HIP events recorded on the
- * stream each kernel is launched on, around every DoSample and every refine
- * launch, while the context's "profile" setting is 1 (iterations are then
- * launched one by one rather than replayed from a graph).  evals counts the
- * points sampled by the timed DoSample launches. */
+ * stream each kernel is launched on, around the sampling kernels, the fold of
+ * their partial sums and the refine launch of every Vegas iteration, and
+ * around every Cuhre rule launch, while the context's "profile" setting is 1
+ * (iterations are then launched one by one rather than replayed from a
+ * graph).  evals counts the points sampled by the timed sampling launches. */
 typedef struct {
-  long long dosample_launches;
-  double dosample_ms;      /* summed DoSample kernel time */
+  long long dosample_launches; /* sampling kernel launches (one per tile class) */
+  double dosample_ms;      /* summed sampling kernel time */
   long long refine_launches;
   double refine_ms;
   long long evals;
   long long rule_launches; /* Cuhre rule kernels */
   double rule_ms;
   long long rule_evals;
+  double fold_ms;          /* summed time of the partial-sum folds */
 } ccuba_stats;
 
 /* Copy the context's counters to *out and reset them when reset != 0. */

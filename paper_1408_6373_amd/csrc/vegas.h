@@ -38,9 +38,9 @@ struct PointsArgs {
   int *bin;            // npts * ndim
 };
 
-// Launch the DoSample instance of precision `prec' and `nb' Philox blocks
-// per point over the slice of the tile list in A.
-hipError_t launch_dosample(const VegasArgs &A, int prec, int nb, int grid, int block,
+// Launch the DoSample instance of precision `prec', `nb' Philox blocks per
+// point and power-of-two bin count or not over the slice of the tile list in A.
+hipError_t launch_dosample(const VegasArgs &A, int prec, int nb, bool pow2, int grid, int block,
                            size_t lds, hipStream_t s);
 hipError_t launch_fold(const FoldArgs &F, hipStream_t s);
 hipError_t launch_refine(const VegasArgs &A, int njobs, size_t lds, hipStream_t s);

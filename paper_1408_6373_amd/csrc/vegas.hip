@@ -76,73 +76,148 @@ __device__ __forceinline__ const float *param_ptr<float>(const VJob &J, int whic
   return J.p32 + which * kParamRow;
 }
 
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return fma(a, b, c); }
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return fmaf(a, b, c); }
+
+// Bin and fractional position of one coordinate (a2 + the first half of
+// a3).  For N = 2^L the bin is the top L bits of the word and the fraction
+// the bits below them, which is exactly what the floating-point formula
+// z = y N, k = floor(z), z - k gives (every step there is exact), so both
+// forms yield identical values.
+__device__ __forceinline__ void bin_frac_pow2(uint32_t r, int L, double &frac, int &k) {
+  k = (int)(r >> (32 - L));
+  const uint32_t m = (r << L) | (1u << (L - 1));  // (r N mod 2^32) + N/2
+  frac = (double)m * 0x1p-32;
+}
+__device__ __forceinline__ void bin_frac_pow2(uint32_t r, int L, float &frac, int &k) {
+  k = (int)(r >> (32 - L));
+  const uint32_t m = (((r >> 9) << L) & 0x7FFFFFu) | (1u << (L - 1));
+  frac = (float)m * 0x1p-23f;
+}
+__device__ __forceinline__ void bin_frac_any(uint32_t r, int N, double Nd, double &frac, int &k) {
+  const double y = (double)r * 0x1p-32 + 0x1p-33;
+  const double z = y * Nd;
+  int kk = (int)z;
+  kk = kk > N - 1 ? N - 1 : kk;
+  frac = z - (double)kk;
+  k = kk;
+}
+__device__ __forceinline__ void bin_frac_any(uint32_t r, int N, float Nf, float &frac, int &k) {
+  const float y = (float)(r >> 9) * 0x1p-23f + 0x1p-24f;
+  const float z = y * Nf;
+  int kk = (int)z;
+  kk = kk > N - 1 ? N - 1 : kk;
+  frac = z - (float)kk;
+  k = kk;
+}
+
 // Sample the points [i0, i0 + cnt) of one tile; lane sums go to S1, S2.
 // NB = ceil(d/4) Philox blocks per point is a template argument so that the
 // per-dimension loop is fully unrolled with only the last block guarded.
 // Each lane carries ILP independent points per trip (q, q + blockDim, ...),
 // so that several Philox chains are in flight; a point past the tile end is
-// computed (its LDS reads stay in range) but contributes nothing.
-template <typename T, typename HT, int FAM, int NB, int ILP>
+// computed (its LDS reads stay in range) but contributes nothing.  All lanes
+// run the same number of trips (a build in which lanes left the loop on
+// different trips, holding deferred updates, produced wrong histograms in
+// partially filled tiles).  The
+// histogram updates of a trip are issued in the next trip, after its grid
+// reads, so that those reads never wait behind the atomics in the LDS queue.
+template <typename T, typename HT, int FAM, int NB, int ILP, bool POW2>
 __device__ __forceinline__ void sample_tile(const VJob &J, int t, long long i0, int cnt,
                                             const T *__restrict__ sE, HT *sH,
                                             const T *__restrict__ p0,
                                             const T *__restrict__ p1, double &S1,
                                             double &S2) {
+  constexpr int ND = 4 * NB;
   const int d = J.ndim, N = J.nbins, row = N + 1;
   const T Nt = (T)N;
+  const int L = POW2 ? 31 - __clz(N) : 0;
   const uint32_t c1 = (uint32_t)t << 8;
   const uint32_t sid = J.sid, k0 = J.key0, k1 = J.key1;
-  T pp0[4 * NB], pp1[4 * NB];
+  T pp0[ND], pp1[ND];
 #pragma unroll
-  for (int j = 0; j < 4 * NB; ++j) {  // parameter rows are zero-padded to 16
+  for (int j = 0; j < ND; ++j) {  // parameter rows are zero-padded to 16
     pp0[j] = p0[j];
     pp1[j] = p1[j];
   }
   const T phase0 = p1[0];
   const int bs = blockDim.x;
-  for (int q0 = threadIdx.x; q0 < cnt; q0 += ILP * bs) {
-    T v[ILP];
-    uint32_t kp[ILP][NB];
+  int pidx[ILP][ND];  // pending histogram slots of the previous trip
+  HT pv[ILP];         // and their value (v^2), 0 for no update
+  bool pending = false;
+  // every lane runs the same number of trips; points past the tile end are
+  // predicated off, so no lane leaves the loop while it holds pending updates
+  const int trips = (cnt + ILP * bs - 1) / (ILP * bs);
+  for (int tr = 0; tr < trips; ++tr) {
+    const int q0 = tr * ILP * bs + (int)threadIdx.x;
+    T fr[ILP][ND], lo[ILP][ND], hi[ILP][ND];
+    int idx[ILP][ND];
+    // words, bins and the grid edges they select
 #pragma unroll
     for (int e = 0; e < ILP; ++e) {
       const uint32_t i = (uint32_t)(i0 + q0 + e * bs);
-      T w = (T)1;
-      T acc = Genz<T, FAM>::init(phase0);
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
-        kp[e][b] = 0;
         const U4 r = philox4x32_10(U4{i, c1 | (uint32_t)b, sid, 0u}, k0, k1);
         const uint32_t rr[4] = {r.x, r.y, r.z, r.w};
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
           const int j = 4 * b + c;
           if (b < NB - 1 || j < d) {
-            T x, jac;
             int k;
-            map_coord(rr[c], N, Nt, sE + j * row, x, jac, k);
-            w = w * jac;
-            acc = Genz<T, FAM>::step(acc, x, pp0[j], pp1[j]);
-            kp[e][b] |= (uint32_t)k << (8 * c);
+            if (POW2)
+              bin_frac_pow2(rr[c], L, fr[e][j], k);
+            else
+              bin_frac_any(rr[c], N, Nt, fr[e][j], k);
+            idx[e][j] = j * N + k;
+            lo[e][j] = sE[j * row + k];
+            hi[e][j] = sE[j * row + k + 1];
           }
         }
       }
-      v[e] = w * Genz<T, FAM>::finish(acc, d);
     }
+    // the previous trip's histogram updates
+    if (pending) {
+#pragma unroll
+      for (int e = 0; e < ILP; ++e) {
+        if (pv[e] != (HT)0) {
+#pragma unroll
+          for (int j = 0; j < ND; ++j)
+            if (j < 4 * (NB - 1) || j < d) unsafeAtomicAdd(&sH[pidx[e][j]], pv[e]);
+        }
+      }
+    }
+    // weights, integrand, sums
 #pragma unroll
     for (int e = 0; e < ILP; ++e) {
-      if (e > 0 && q0 + e * bs >= cnt) break;
-      const double vd = (double)v[e];
+      T w = (T)1;
+      T acc = Genz<T, FAM>::init(phase0);
+#pragma unroll
+      for (int j = 0; j < ND; ++j) {
+        if (j < 4 * (NB - 1) || j < d) {
+          const T width = hi[e][j] - lo[e][j];
+          const T x = fma_t(fr[e][j], width, lo[e][j]);
+          w = w * (Nt * width);
+          acc = Genz<T, FAM>::step(acc, x, pp0[j], pp1[j]);
+          pidx[e][j] = idx[e][j];
+        }
+      }
+      const T v = w * Genz<T, FAM>::finish(acc, d);
+      const bool valid = q0 + e * bs < cnt;  // also false for q0 >= cnt
+      const double vd = valid ? (double)v : 0.0;
       S1 += vd;
       S2 = fma(vd, vd, S2);
-      const HT v2 = (HT)(v[e] * v[e]);
+      pv[e] = valid ? (HT)(v * v) : (HT)0;
+    }
+    pending = true;
+  }
+  if (pending) {
 #pragma unroll
-      for (int b = 0; b < NB; ++b) {
+    for (int e = 0; e < ILP; ++e) {
+      if (pv[e] != (HT)0) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const int j = 4 * b + c;
-          if (b < NB - 1 || j < d)
-            unsafeAtomicAdd(&sH[j * N + ((kp[e][b] >> (8 * c)) & 255u)], v2);
-        }
+        for (int j = 0; j < ND; ++j)
+          if (j < 4 * (NB - 1) || j < d) unsafeAtomicAdd(&sH[pidx[e][j]], pv[e]);
       }
     }
   }
@@ -152,7 +227,7 @@ __device__ __forceinline__ void sample_tile(const VJob &J, int t, long long i0, 
 // holds the registers its own dimension class needs.  A launch walks the
 // slice [tile_first, tile_first + tile_count) of the tile list, which holds
 // the tiles of the jobs of that class.
-template <typename T, typename HT, int ILP, int NB>
+template <typename T, typename HT, int ILP, int NB, bool POW2>
 __global__ void __launch_bounds__(256) vegas_dosample_kernel(VegasArgs A) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red[2][4];
@@ -165,7 +240,8 @@ __global__ void __launch_bounds__(256) vegas_dosample_kernel(VegasArgs A) {
   for (int tt = A.tile_first + blockIdx.x; tt < tend; tt += gridDim.x) {
     const int jb = A.tile_job[tt];
     const VJob J = A.jobs[jb];
-    if (J.prec != myprec || ((J.ndim + 3) >> 2) != NB) continue;
+    if (J.prec != myprec || ((J.ndim + 3) >> 2) != NB || ((J.nbins & (J.nbins - 1)) == 0) != POW2)
+      continue;
     const VState st = *J.state;
     if (st.done) continue;
     const int d = J.ndim, N = J.nbins, dN = d * N, row = N + 1;
@@ -185,11 +261,11 @@ __global__ void __launch_bounds__(256) vegas_dosample_kernel(VegasArgs A) {
     const T *p1 = param_ptr<T>(J, 1);
     double S1 = 0.0, S2 = 0.0;
     switch (J.family) {
-      case GAUSSIAN: sample_tile<T, HT, GAUSSIAN, NB, ILP>(J, st.T, i0, cnt, sE, sH, p0, p1, S1, S2); break;
-      case OSCILLATORY: sample_tile<T, HT, OSCILLATORY, NB, ILP>(J, st.T, i0, cnt, sE, sH, p0, p1, S1, S2); break;
-      case PRODUCT_PEAK: sample_tile<T, HT, PRODUCT_PEAK, NB, ILP>(J, st.T, i0, cnt, sE, sH, p0, p1, S1, S2); break;
-      case CORNER_PEAK: sample_tile<T, HT, CORNER_PEAK, NB, ILP>(J, st.T, i0, cnt, sE, sH, p0, p1, S1, S2); break;
-      default: sample_tile<T, HT, C0, NB, ILP>(J, st.T, i0, cnt, sE, sH, p0, p1, S1, S2); break;
+      case GAUSSIAN: sample_tile<T, HT, GAUSSIAN, NB, ILP, POW2>(J, st.T, i0, cnt, sE, sH, p0, p1, S1, S2); break;
+      case OSCILLATORY: sample_tile<T, HT, OSCILLATORY, NB, ILP, POW2>(J, st.T, i0, cnt, sE, sH, p0, p1, S1, S2); break;
+      case PRODUCT_PEAK: sample_tile<T, HT, PRODUCT_PEAK, NB, ILP, POW2>(J, st.T, i0, cnt, sE, sH, p0, p1, S1, S2); break;
+      case CORNER_PEAK: sample_tile<T, HT, CORNER_PEAK, NB, ILP, POW2>(J, st.T, i0, cnt, sE, sH, p0, p1, S1, S2); break;
+      default: sample_tile<T, HT, C0, NB, ILP, POW2>(J, st.T, i0, cnt, sE, sH, p0, p1, S1, S2); break;
     }
     S1 = wave_sum(S1);
     S2 = wave_sum(S2);
@@ -535,39 +611,46 @@ __global__ void __launch_bounds__(256) vegas_points_kernel(PointsArgs P) {
 // ---------------------------------------------------------------------------
 // launchers
 
-template <int ILP, int NB>
+template <int ILP, int NB, bool POW2>
 static void launch_dosample_nb(const VegasArgs &A, int prec, int grid, int block, size_t lds,
                                hipStream_t s) {
   if (prec == FP64) {
-    hipLaunchKernelGGL((vegas_dosample_kernel<double, double, ILP, NB>), dim3(grid), dim3(block),
-                       lds, s, A);
+    hipLaunchKernelGGL((vegas_dosample_kernel<double, double, ILP, NB, POW2>), dim3(grid),
+                       dim3(block), lds, s, A);
   } else if (A.hist64) {
-    hipLaunchKernelGGL((vegas_dosample_kernel<float, double, ILP, NB>), dim3(grid), dim3(block),
-                       lds, s, A);
+    hipLaunchKernelGGL((vegas_dosample_kernel<float, double, ILP, NB, POW2>), dim3(grid),
+                       dim3(block), lds, s, A);
   } else {
-    hipLaunchKernelGGL((vegas_dosample_kernel<float, float, ILP, NB>), dim3(grid), dim3(block),
-                       lds, s, A);
+    hipLaunchKernelGGL((vegas_dosample_kernel<float, float, ILP, NB, POW2>), dim3(grid),
+                       dim3(block), lds, s, A);
   }
 }
 
-template <int ILP>
+template <int ILP, bool POW2>
 static void launch_dosample_ilp(const VegasArgs &A, int prec, int nb, int grid, int block,
                                 size_t lds, hipStream_t s) {
   switch (nb) {
-    case 1: launch_dosample_nb<ILP, 1>(A, prec, grid, block, lds, s); break;
-    case 2: launch_dosample_nb<ILP, 2>(A, prec, grid, block, lds, s); break;
-    case 3: launch_dosample_nb<ILP, 3>(A, prec, grid, block, lds, s); break;
-    default: launch_dosample_nb<ILP, 4>(A, prec, grid, block, lds, s); break;
+    case 1: launch_dosample_nb<ILP, 1, POW2>(A, prec, grid, block, lds, s); break;
+    case 2: launch_dosample_nb<ILP, 2, POW2>(A, prec, grid, block, lds, s); break;
+    case 3: launch_dosample_nb<ILP, 3, POW2>(A, prec, grid, block, lds, s); break;
+    default: launch_dosample_nb<ILP, 4, POW2>(A, prec, grid, block, lds, s); break;
   }
 }
 
-hipError_t launch_dosample(const VegasArgs &A, int prec, int nb, int grid, int block,
+hipError_t launch_dosample(const VegasArgs &A, int prec, int nb, bool pow2, int grid, int block,
                            size_t lds, hipStream_t s) {
   if (A.tile_count <= 0 || grid <= 0) return hipSuccess;
-  if (A.ilp == 2)
-    launch_dosample_ilp<2>(A, prec, nb, grid, block, lds, s);
-  else
-    launch_dosample_ilp<1>(A, prec, nb, grid, block, lds, s);
+  if (A.ilp == 2) {
+    if (pow2)
+      launch_dosample_ilp<2, true>(A, prec, nb, grid, block, lds, s);
+    else
+      launch_dosample_ilp<2, false>(A, prec, nb, grid, block, lds, s);
+  } else {
+    if (pow2)
+      launch_dosample_ilp<1, true>(A, prec, nb, grid, block, lds, s);
+    else
+      launch_dosample_ilp<1, false>(A, prec, nb, grid, block, lds, s);
+  }
   return hipGetLastError();
 }
 
@@ -611,12 +694,18 @@ hipError_t set_kernel_limits() {
   // an error instead of running
   const int big = 160 * 1024;
   std::vector<const void *> fns = {
-      (const void *)vegas_dosample_kernel<double, double, 1, 4>,
-      (const void *)vegas_dosample_kernel<float, double, 1, 4>,
-      (const void *)vegas_dosample_kernel<float, float, 1, 4>,
-      (const void *)vegas_dosample_kernel<double, double, 2, 4>,
-      (const void *)vegas_dosample_kernel<float, double, 2, 4>,
-      (const void *)vegas_dosample_kernel<float, float, 2, 4>,
+      (const void *)vegas_dosample_kernel<double, double, 1, 4, true>,
+      (const void *)vegas_dosample_kernel<float, double, 1, 4, true>,
+      (const void *)vegas_dosample_kernel<float, float, 1, 4, true>,
+      (const void *)vegas_dosample_kernel<double, double, 2, 4, true>,
+      (const void *)vegas_dosample_kernel<float, double, 2, 4, true>,
+      (const void *)vegas_dosample_kernel<float, float, 2, 4, true>,
+      (const void *)vegas_dosample_kernel<double, double, 1, 4, false>,
+      (const void *)vegas_dosample_kernel<float, double, 1, 4, false>,
+      (const void *)vegas_dosample_kernel<float, float, 1, 4, false>,
+      (const void *)vegas_dosample_kernel<double, double, 2, 4, false>,
+      (const void *)vegas_dosample_kernel<float, double, 2, 4, false>,
+      (const void *)vegas_dosample_kernel<float, float, 2, 4, false>,
       (const void *)vegas_refine_kernel};
   for (const void *f : fns)
     if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, big) != hipSuccess)

@@ -98,12 +98,14 @@ void plan_tile_groups(std::vector<VJob> &jobs, std::vector<int> &tiles,
   groups.clear();
   size_t ref = 0;
   for (int p = 0; p < 2; ++p)
-    for (int nb = 1; nb <= 4; ++nb) {
-      TileGroup g{p, nb, (int)tiles.size(), 0, 0, 0};
+    for (int nb = 1; nb <= 4; ++nb)
+      for (int pw = 0; pw < 2; ++pw) {
+      TileGroup g{p, nb, pw, (int)tiles.size(), 0, 0, 0};
       size_t hb = 0;
       for (int j = 0; j < (int)jobs.size(); ++j) {
         VJob &J = jobs[j];
-        if (J.prec != p || ((J.ndim + 3) >> 2) != nb) continue;
+        const int jp = (J.nbins & (J.nbins - 1)) == 0;
+        if (J.prec != p || ((J.ndim + 3) >> 2) != nb || jp != pw) continue;
         J.tile0 = (int)tiles.size();
         for (int q = 0; q < J.ntiles; ++q) tiles.push_back(j);
         const size_t row = (size_t)J.ndim * (J.nbins + 1), dN = (size_t)J.ndim * J.nbins;
@@ -128,7 +130,8 @@ int launch_tile_groups(ccuba_ctx *ctx, VegasArgs A, const std::vector<TileGroup>
     A.lds_hist_byte_off = (long long)g.grid_bytes;
     const long long B = (long long)ctx->ncu * ctx->tune[g.prec].blocks_per_cu;
     const int grid = (int)std::min<long long>(B, g.count);
-    CCUBA_HIP(launch_dosample(A, g.prec, g.nb, grid, ctx->tune[g.prec].block, g.lds, s));
+    CCUBA_HIP(launch_dosample(A, g.prec, g.nb, g.pow2 != 0, grid, ctx->tune[g.prec].block,
+                              g.lds, s));
   }
   return CCUBA_OK;
 }
@@ -313,9 +316,10 @@ int VegasEngine::setup(const std::vector<VegasSpec> &specs, bool single, hipStre
   return CCUBA_OK;
 }
 
-int VegasEngine::dosample_only(hipStream_t s) {
+int VegasEngine::dosample_only(hipStream_t s, hipEvent_t between) {
   const int rc = launch_tile_groups(ctx_, args_, tgroups_, s);
   if (rc) return rc;
+  if (between) CCUBA_HIP(hipEventRecord(between, s));
   FoldArgs F{jobs_.p, fold_end_.p, njobs(), fold_total_, fold_end_.p + njobs(), fold_total2_};
   CCUBA_HIP(launch_fold(F, s));
   return CCUBA_OK;
@@ -323,16 +327,17 @@ int VegasEngine::dosample_only(hipStream_t s) {
 
 int VegasEngine::launch_iteration(hipStream_t s) {
   if (ctx_->profile && !capturing_) {
-    // time each kernel with events on the stream it runs on
-    hipEvent_t ev[3];
+    // time the sampling kernels, the fold and the refine with events on the
+    // stream they run on
+    hipEvent_t ev[4];
     for (auto &e : ev) CCUBA_HIP(hipEventCreate(&e));
     CCUBA_HIP(hipEventRecord(ev[0], s));
-    int rc = dosample_only(s);
+    int rc = dosample_only(s, ev[1]);
     if (rc) return rc;
-    CCUBA_HIP(hipEventRecord(ev[1], s));
-    CCUBA_HIP(launch_refine(args_, njobs(), lds_refine_, s));
     CCUBA_HIP(hipEventRecord(ev[2], s));
-    pending_.push_back({ev[0], ev[1], ev[2], iter_launched_++});
+    CCUBA_HIP(launch_refine(args_, njobs(), lds_refine_, s));
+    CCUBA_HIP(hipEventRecord(ev[3], s));
+    pending_.push_back({ev[0], ev[1], ev[2], ev[3], iter_launched_++});
     return CCUBA_OK;
   }
   int rc = dosample_only(s);
@@ -344,17 +349,20 @@ int VegasEngine::launch_iteration(hipStream_t s) {
 
 int VegasEngine::flush_timing() {
   for (auto &p : pending_) {
-    float a = 0, b = 0;
-    CCUBA_HIP(hipEventSynchronize(p.e2));
+    float a = 0, b = 0, c = 0;
+    CCUBA_HIP(hipEventSynchronize(p.e3));
     CCUBA_HIP(hipEventElapsedTime(&a, p.e0, p.e1));
     CCUBA_HIP(hipEventElapsedTime(&b, p.e1, p.e2));
-    ctx_->stats.dosample_launches += 1;
+    CCUBA_HIP(hipEventElapsedTime(&c, p.e2, p.e3));
+    ctx_->stats.dosample_launches += (long long)tgroups_.size();
     ctx_->stats.dosample_ms += a;
+    ctx_->stats.fold_ms += b;
     ctx_->stats.refine_launches += 1;
-    ctx_->stats.refine_ms += b;
+    ctx_->stats.refine_ms += c;
     (void)hipEventDestroy(p.e0);
     (void)hipEventDestroy(p.e1);
     (void)hipEventDestroy(p.e2);
+    (void)hipEventDestroy(p.e3);
   }
   pending_.clear();
   return CCUBA_OK;

@@ -34,7 +34,7 @@ void genz_constants(const VegasSpec &s, double p64[2][kParamRow], float p32[2][k
 // A slice of a launch's tile list holding the tiles of every job of one
 // (precision, Philox blocks per point) class, with the LDS it needs.
 struct TileGroup {
-  int prec, nb, first, count;
+  int prec, nb, pow2, first, count;
   size_t grid_bytes, lds;
 };
 
@@ -66,7 +66,9 @@ class VegasEngine {
   // group partials into caller buffers.
   int set_iteration(int job, int t, hipStream_t s);
   int load_grid(int job, int copy, const double *src, hipMemcpyKind kind, hipStream_t s);
-  int dosample_only(hipStream_t s);
+  // the sampling kernels, then the fold; records `between` (if given) after
+  // the sampling kernels
+  int dosample_only(hipStream_t s, hipEvent_t between = nullptr);
   int collect(double *sums_dev, double *hist_dev, hipStream_t s);
   // One refinement of job 0 from a given histogram and grid.
   int refine_only(const double *hist, const double *grid_in, double *grid_out, hipStream_t s);
@@ -83,7 +85,7 @@ class VegasEngine {
   int launch_iteration(hipStream_t s);
   int flush_timing();
   struct Timed {
-    hipEvent_t e0, e1, e2;
+    hipEvent_t e0, e1, e2, e3;
     int iter;
   };
   std::vector<Timed> pending_;

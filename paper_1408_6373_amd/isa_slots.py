@@ -68,10 +68,10 @@ def count(asm_text):
     """{kernel instance: {family: slots per point}} from gfx950 assembly."""
     res = {}
     for kern in re.findall(r"^(_ZN5ccuba21vegas_dosample_kernelI\w+):", asm_text, re.M):
-        m = re.search(r"kernelI(\w)(\w)Li(\d)ELi(\d)E", kern)
+        m = re.search(r"kernelI(\w)(\w)Li(\d)ELi(\d)ELb(\d)E", kern)
         if not m:
             continue
-        T, H, ilp, nb = m.groups()
+        T, H, ilp, nb, pow2 = m.groups()
         start = asm_text.index(kern + ":")
         body = asm_text[start:asm_text.index(".Lfunc_end", start)].splitlines()
         labels = {}
@@ -97,8 +97,8 @@ def count(asm_text):
             fam = _family(ops, nested)
             slots = sum(_weight(o) for o in v) / int(ilp)
             fam_slots.setdefault(fam, []).append(slots)
-        key = "%s%s_ilp%s_nb%s" % ({"f": "f32", "d": "f64"}[T], {"f": "h32", "d": "h64"}[H],
-                                   ilp, nb)
+        key = "%s%s_ilp%s_nb%s%s" % ({"f": "f32", "d": "f64"}[T], {"f": "h32", "d": "h64"}[H],
+                                     ilp, nb, "_pow2" if pow2 == "1" else "")
         res[key] = {f: max(v) for f, v in fam_slots.items()}
     return res
 

@@ -135,6 +135,26 @@ def test_ragged_and_degenerate_sizes(cc, ctx):
     assert g["fail"] == 1 and g["neval"] == 0 and g["integral"] == 0.0
 
 
+@pytest.mark.parametrize("d,N,prec", [(1, 2, 0), (1, 2, 1), (16, 256, 0), (16, 256, 1),
+                                      (12, 100, 1), (9, 37, 0)])
+def test_extreme_dims_and_bins(cc, ctx, d, N, prec):
+    # smallest and largest dimension and bin count, odd bin counts (the
+    # general map rather than the power-of-two one), and three Philox blocks
+    a, u = W.genz_params(2, d, 5)
+    n = 30011
+    g = cc.vegas(2, a, u, ctx=ctx, flags=prec, nbins=N, nstart=n, maxeval=4 * n, seed=9,
+                 trace=True)
+    o = O.vegas(O.genz(2, a, u, precision=prec), d, flags=prec, nbins=N, nstart=n,
+                maxeval=4 * n, seed=9)
+    if prec == 0:
+        _assert_vegas_close(g, o, 1e-12, 1e-11)
+        assert np.max(np.abs(g["grid"] - o["grid"])) < 1e-12
+    else:
+        assert g["neval"] == o["neval"]
+        assert _rel(g["integral"], o["integral"]) < 1e-6
+        assert _rel(g["error"], o["error"]) < 1e-5
+
+
 def test_zero_variance_frozen_grid(cc, ctx):
     # a = 0 makes the Gaussian the constant 1; on the frozen uniform grid with
     # N = 128 every weight is exactly 1, so sigma_t = 0 and the result is 1
