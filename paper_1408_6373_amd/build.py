@@ -40,11 +40,29 @@ def _compile(src):
     return obj, msgs
 
 
+def _slot_table():
+    """VALU issue slots per point of each DoSample instance (roofline input)."""
+    try:
+        import importlib.util
+        spec = importlib.util.spec_from_file_location("_ccuba_isa_slots",
+                                                      os.path.join(HERE, "isa_slots.py"))
+        mod = importlib.util.module_from_spec(spec)
+        spec.loader.exec_module(mod)
+        mod.write(HIPCC, FLAGS)
+        return None
+    except Exception as e:  # the library itself is built; only the table is missing
+        return "warning: kernel slot table not written: %s" % e
+
+
 def build(verbose=False, jobs=8):
     os.makedirs(BUILD, exist_ok=True)
-    srcs = sources()
-    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        results = list(ex.map(_compile, srcs))
+    # the DoSample instances take longest: start them first
+    srcs = sorted(sources(), key=lambda f: (not os.path.basename(f).startswith("vegas_sample_"), f))
+    with cf.ThreadPoolExecutor(max_workers=1) as side:
+        table = side.submit(_slot_table)  # its own assembly builds, alongside
+        with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+            results = list(ex.map(_compile, srcs))
+        warn = table.result()
     if verbose:
         for (obj, msgs) in results:
             if msgs.strip():
@@ -56,16 +74,8 @@ def build(verbose=False, jobs=8):
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout + r.stderr)
     os.replace(tmp, LIB)
-    # VALU issue slots per point of each DoSample instance (roofline input)
-    try:
-        import importlib.util
-        spec = importlib.util.spec_from_file_location("_ccuba_isa_slots",
-                                                      os.path.join(HERE, "isa_slots.py"))
-        mod = importlib.util.module_from_spec(spec)
-        spec.loader.exec_module(mod)
-        mod.write(HIPCC, FLAGS)
-    except Exception as e:  # the library itself is built; only the table is missing
-        print("warning: kernel slot table not written: %s" % e, file=sys.stderr)
+    if warn:
+        print(warn, file=sys.stderr)
     return LIB
 
 

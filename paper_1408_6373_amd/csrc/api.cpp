@@ -70,6 +70,15 @@ struct CtxScope {
   }
 };
 
+void drop_engine_cache(ccuba_ctx *ctx) {
+  delete ctx->vcache;
+  ctx->vcache = nullptr;
+}
+
+// run a set-up single-integral engine to the end and read its results
+int vegas_finish(ccuba_ctx *ctx, VegasEngine &eng, long long *neval, int *fail,
+                 double integral[], double error[], double prob[], ccuba_vegas_trace *trace);
+
 int fill_spec(VegasSpec &sp, int ndim, int ncomp, const ccuba_integrand *f, double epsrel,
               double epsabs, int flags, unsigned long long seed, long long mineval,
               long long maxeval, long long nstart, long long nincrease, long long nbatch,
@@ -163,6 +172,7 @@ int ccuba_shutdown(ccuba_ctx **ctx) {
   (void)hipSetDevice(c->device);
   delete c->server;  // stops the serving thread and frees its requests
   c->server = nullptr;
+  drop_engine_cache(c);
   if (c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
   *ctx = nullptr;
@@ -192,6 +202,9 @@ int ccuba_config(ccuba_ctx *ctx, const char *key, long long value) {
     ctx->autotune = value != 0;
   } else if (k == "graph") {
     ctx->use_graph = value != 0;
+  } else if (k == "engine_cache") {
+    ctx->engine_cache = value != 0;
+    if (!ctx->engine_cache) drop_engine_cache(ctx);
   } else if (k == "profile") {
     ctx->profile = value != 0;
   } else if (k == "serve_slots") {
@@ -228,8 +241,40 @@ int ccuba_vegas_ex(ccuba_ctx **ctxp, int ndim, int ncomp, const ccuba_integrand 
   std::lock_guard<std::mutex> g(ctx->lock);
   CCUBA_HIP(hipSetDevice(ctx->device));
   if (ctx->autotune) maybe_autotune(ctx, sp.prec);
-  VegasEngine eng(ctx);
-  if ((rc = eng.setup({sp}, true, ctx->stream))) return rc;
+  // the context's cached engine (its buffers and graphs serve the next call
+  // of the same shape), or a fresh one when caching is off
+  std::unique_ptr<VegasEngine> own;
+  VegasEngine *ep;
+  if (ctx->engine_cache) {
+    if (!ctx->vcache) ctx->vcache = new VegasEngine(ctx);
+    ep = ctx->vcache;
+  } else {
+    own.reset(new VegasEngine(ctx));
+    ep = own.get();
+  }
+  VegasEngine &eng = *ep;
+  rc = eng.setup({sp}, true, ctx->stream);
+  if (rc == CCUBA_ENOMEM && ctx->vcache) {
+    // the cached buffers may be what exceeds the budget: start afresh
+    drop_engine_cache(ctx);
+    own.reset(new VegasEngine(ctx));
+    rc = own->setup({sp}, true, ctx->stream);
+    if (rc) return rc;
+    return vegas_finish(ctx, *own, neval, fail, integral, error, prob, trace);
+  }
+  if (rc) {
+    drop_engine_cache(ctx);
+    return rc;
+  }
+  rc = vegas_finish(ctx, eng, neval, fail, integral, error, prob, trace);
+  if (rc) drop_engine_cache(ctx);
+  return rc;
+}
+
+namespace {
+int vegas_finish(ccuba_ctx *ctx, VegasEngine &eng, long long *neval, int *fail,
+                 double integral[], double error[], double prob[], ccuba_vegas_trace *trace) {
+  int rc;
   if ((rc = eng.run(ctx->stream))) return rc;
   std::vector<VState> st;
   if ((rc = eng.read_states(st, ctx->stream))) return rc;
@@ -250,6 +295,7 @@ int ccuba_vegas_ex(ccuba_ctx **ctxp, int ndim, int ncomp, const ccuba_integrand 
   }
   return CCUBA_OK;
 }
+}  // namespace
 
 int ccuba_vegas(ccuba_ctx **ctx, int ndim, int ncomp, const ccuba_integrand *f, double epsrel,
                 double epsabs, int flags, unsigned long long seed, long long mineval,
@@ -352,7 +398,7 @@ int ccuba_vegas_dosample_raw(ccuba_ctx *ctx, int ndim, int nbins, const ccuba_in
   if ((rc = eng.setup({sp}, true, s))) return rc;
   if ((rc = eng.set_iteration(0, iteration, s))) return rc;
   if ((rc = eng.load_grid(0, iteration & 1, grid_dev, hipMemcpyDeviceToDevice, s))) return rc;
-  if ((rc = eng.dosample_only(s))) return rc;
+  if ((rc = eng.dosample_only(s, true))) return rc;
   if ((rc = eng.collect(sums_dev, hist_dev, s))) return rc;
   // the engine's buffers are released on return: finish before that
   CCUBA_HIP(hipStreamSynchronize(s));

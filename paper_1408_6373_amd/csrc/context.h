@@ -14,6 +14,7 @@
 
 namespace ccuba {
 class Server;
+class VegasEngine;
 }
 
 struct ccuba_ctx {
@@ -32,6 +33,10 @@ struct ccuba_ctx {
   std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
   std::mutex lock;                  // serialises engine use with the server thread
   ccuba::Server *server = nullptr;  // the serving loop, started by the first submit
+  // the engine of the last single-integral Vegas call, kept (with its device
+  // buffers and captured graphs) for the next call of the same shape
+  ccuba::VegasEngine *vcache = nullptr;
+  int engine_cache = 1;
   double now() const {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
@@ -64,6 +69,11 @@ struct DevBuf {
     p = (T *)q;
     n = count;
     return 0;
+  }
+  // keep the current buffer if it is this context's and large enough
+  int reserve(ccuba_ctx *c, size_t count) {
+    if (p && ctx == c && n >= (count ? count : 1)) return 0;
+    return alloc(c, count);
   }
   void release() {
     if (p) dev_free(ctx, p, n * sizeof(T));

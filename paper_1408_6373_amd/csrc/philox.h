@@ -26,7 +26,11 @@ __device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
     // full 64-bit products: one v_mad_u64_u32 each instead of mul_lo + mul_hi
     const uint64_t p0 = (uint64_t)M0 * (uint64_t)c.x;
     const uint64_t p1 = (uint64_t)M1 * (uint64_t)c.z;
-    c = U4{(uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k1,
+    // three-way xors as one gfx950 three-input bit operation (truth table
+    // 0x96 = a ^ b ^ c) instead of two v_xor_b32
+    c = U4{(uint32_t)__builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c.y, k0, 0x96),
+           (uint32_t)p1,
+           (uint32_t)__builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c.w, k1, 0x96),
            (uint32_t)p0};
     k0 += W0;
     k1 += W1;

@@ -335,7 +335,7 @@ int Server::tick() {
     CCUBA_HIP(hipMemcpyAsync(fold_end_.p, ends.data(), ends.size() * sizeof(long long),
                              hipMemcpyHostToDevice, s));
     FoldArgs F{jobs_.p, fold_end_.p, (int)table.size(), ftot, fold_end_.p + table.size(), ftot2};
-    CCUBA_HIP(launch_fold(F, s));
+    CCUBA_HIP(launch_fold(F, false, s));
     CCUBA_HIP(launch_refine(A, (int)table.size(), refb, s));
   }
   // Cuhre: one rule launch over the children of every stepping request

@@ -1,5 +1,7 @@
 // vegas.h -- kernel arguments and launchers of the Vegas DoSample engine.
 #pragma once
+#include <vector>
+
 #include "engine.h"
 
 namespace ccuba {
@@ -39,10 +41,24 @@ struct PointsArgs {
 };
 
 // Launch the DoSample instance of precision `prec', `nb' Philox blocks per
-// point and power-of-two bin count or not over the slice of the tile list in A.
-hipError_t launch_dosample(const VegasArgs &A, int prec, int nb, bool pow2, int grid, int block,
-                           size_t lds, hipStream_t s);
-hipError_t launch_fold(const FoldArgs &F, hipStream_t s);
+// point, power-of-two bin count or not and d = 4 nb or not over the slice of
+// the tile list in A.
+hipError_t launch_dosample(const VegasArgs &A, int prec, int nb, bool pow2, bool full,
+                           int grid, int block, size_t lds, hipStream_t s);
+// the same per (precision, histogram type), one translation unit each
+hipError_t launch_dosample_f64(const VegasArgs &A, int nb, bool pow2, bool full, int grid,
+                               int block, size_t lds, hipStream_t s);
+hipError_t launch_dosample_f32h64(const VegasArgs &A, int nb, bool pow2, bool full, int grid,
+                                  int block, size_t lds, hipStream_t s);
+hipError_t launch_dosample_f32h32(const VegasArgs &A, int nb, bool pow2, bool full, int grid,
+                                  int block, size_t lds, hipStream_t s);
+// every DoSample instance of a translation unit (for launch attributes)
+void dosample_fns_f64(std::vector<const void *> &fns);
+void dosample_fns_f32h64(std::vector<const void *> &fns);
+void dosample_fns_f32h32(std::vector<const void *> &fns);
+// First fold level (tile rows -> group rows); with level2 also the second
+// (group rows -> hsum), which only the raw DoSample entry point needs.
+hipError_t launch_fold(const FoldArgs &F, bool level2, hipStream_t s);
 hipError_t launch_refine(const VegasArgs &A, int njobs, size_t lds, hipStream_t s);
 hipError_t launch_collect(const VegasArgs &A, int njobs, double *sums, double *hist,
                           hipStream_t s);

@@ -7,15 +7,15 @@
 //   a1 words   W_b = philox(ctr = (i, (t<<8)|b, sid, 0), key = seed)
 //   a2 uniform FP64 y = r 2^-32 + 2^-33 | FP32 y = (r>>9) 2^-23 + 2^-24
 //   a3 map     z = y N, k = min(floor z, N-1), x = E[k] + (z-k)(E[k+1]-E[k]),
-//              w *= N (E[k+1]-E[k])     (grid staged in LDS per tile)
+//              w *= N (E[k+1]-E[k])     (grid cells staged in LDS per tile)
 //   a4 f       Genz family, accumulated one dimension at a time
 //   a5 sums    v = w f: S1 += v, S2 += v^2 in FP64 per lane, wave shuffles,
 //              then a fixed-order block sum -> one FP64 partial per tile
-//   a6 hist    H_j[k_j] += v^2 with LDS atomics, flushed per tile as FP64
-// Tiles are folded 32 at a time by the last block to finish (fixed tile
-// order, so the fold is deterministic), and the refine kernel (one
-// workgroup per integral) finishes the sums in fixed order and does a7:
-// iteration statistics, the inverse-variance combination with chi^2 and its
+//   a6 hist    H_j[k_j] += v^2 with LDS atomics, written per tile as FP64
+// A fold kernel sums the tile rows 32 at a time in tile order and a second
+// one sums those group rows in group order (so the sums are deterministic);
+// the refine kernel (one workgroup per integral) then does a7: iteration
+// statistics, the inverse-variance combination with chi^2 and its
 // probability, the convergence test and Lepage's grid refinement, all in FP64.
 // Iteration t and its point count are read from device state, so a captured
 // iteration replays unchanged.
@@ -23,272 +23,11 @@
 #include "genz.h"
 #include "philox.h"
 #include "vegas.h"
+#include "vegas_sample.h"
 
 #include <vector>
 
 namespace ccuba {
-
-// ---------------------------------------------------------------------------
-// a2 + a3: one coordinate
-
-__device__ __forceinline__ void map_coord(uint32_t r, int N, double Nd, const double *E,
-                                          double &x, double &jac, int &k) {
-  const double y = (double)r * 0x1p-32 + 0x1p-33;
-  const double z = y * Nd;
-  int kk = (int)z;
-  kk = kk > N - 1 ? N - 1 : kk;
-  const double frac = z - (double)kk;
-  const double lo = E[kk];
-  const double width = E[kk + 1] - lo;
-  x = fma(frac, width, lo);
-  jac = Nd * width;
-  k = kk;
-}
-
-__device__ __forceinline__ void map_coord(uint32_t r, int N, float Nf, const float *E,
-                                          float &x, float &jac, int &k) {
-  const float y = (float)(r >> 9) * 0x1p-23f + 0x1p-24f;
-  const float z = y * Nf;
-  int kk = (int)z;
-  kk = kk > N - 1 ? N - 1 : kk;
-  const float frac = z - (float)kk;
-  const float lo = E[kk];
-  const float width = E[kk + 1] - lo;
-  x = fmaf(frac, width, lo);
-  jac = Nf * width;
-  k = kk;
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-template <typename T>
-__device__ __forceinline__ const T *param_ptr(const VJob &J, int which);
-template <>
-__device__ __forceinline__ const double *param_ptr<double>(const VJob &J, int which) {
-  return J.p64 + which * kParamRow;
-}
-template <>
-__device__ __forceinline__ const float *param_ptr<float>(const VJob &J, int which) {
-  return J.p32 + which * kParamRow;
-}
-
-__device__ __forceinline__ double fma_t(double a, double b, double c) { return fma(a, b, c); }
-__device__ __forceinline__ float fma_t(float a, float b, float c) { return fmaf(a, b, c); }
-
-// Bin and fractional position of one coordinate (a2 + the first half of
-// a3).  For N = 2^L the bin is the top L bits of the word and the fraction
-// the bits below them, which is exactly what the floating-point formula
-// z = y N, k = floor(z), z - k gives (every step there is exact), so both
-// forms yield identical values.
-__device__ __forceinline__ void bin_frac_pow2(uint32_t r, int L, double &frac, int &k) {
-  k = (int)(r >> (32 - L));
-  const uint32_t m = (r << L) | (1u << (L - 1));  // (r N mod 2^32) + N/2
-  frac = (double)m * 0x1p-32;
-}
-__device__ __forceinline__ void bin_frac_pow2(uint32_t r, int L, float &frac, int &k) {
-  k = (int)(r >> (32 - L));
-  const uint32_t m = (((r >> 9) << L) & 0x7FFFFFu) | (1u << (L - 1));
-  frac = (float)m * 0x1p-23f;
-}
-__device__ __forceinline__ void bin_frac_any(uint32_t r, int N, double Nd, double &frac, int &k) {
-  const double y = (double)r * 0x1p-32 + 0x1p-33;
-  const double z = y * Nd;
-  int kk = (int)z;
-  kk = kk > N - 1 ? N - 1 : kk;
-  frac = z - (double)kk;
-  k = kk;
-}
-__device__ __forceinline__ void bin_frac_any(uint32_t r, int N, float Nf, float &frac, int &k) {
-  const float y = (float)(r >> 9) * 0x1p-23f + 0x1p-24f;
-  const float z = y * Nf;
-  int kk = (int)z;
-  kk = kk > N - 1 ? N - 1 : kk;
-  frac = z - (float)kk;
-  k = kk;
-}
-
-// Sample the points [i0, i0 + cnt) of one tile; lane sums go to S1, S2.
-// NB = ceil(d/4) Philox blocks per point is a template argument so that the
-// per-dimension loop is fully unrolled with only the last block guarded.
-// Each lane carries ILP independent points per trip (q, q + blockDim, ...),
-// so that several Philox chains are in flight; a point past the tile end is
-// computed (its LDS reads stay in range) but contributes nothing.  All lanes
-// run the same number of trips (a build in which lanes left the loop on
-// different trips, holding deferred updates, produced wrong histograms in
-// partially filled tiles).  The
-// histogram updates of a trip are issued in the next trip, after its grid
-// reads, so that those reads never wait behind the atomics in the LDS queue.
-template <typename T, typename HT, int FAM, int NB, int ILP, bool POW2>
-__device__ __forceinline__ void sample_tile(const VJob &J, int t, long long i0, int cnt,
-                                            const T *__restrict__ sE, HT *sH,
-                                            const T *__restrict__ p0,
-                                            const T *__restrict__ p1, double &S1,
-                                            double &S2) {
-  constexpr int ND = 4 * NB;
-  const int d = J.ndim, N = J.nbins, row = N + 1;
-  const T Nt = (T)N;
-  const int L = POW2 ? 31 - __clz(N) : 0;
-  const uint32_t c1 = (uint32_t)t << 8;
-  const uint32_t sid = J.sid, k0 = J.key0, k1 = J.key1;
-  T pp0[ND], pp1[ND];
-#pragma unroll
-  for (int j = 0; j < ND; ++j) {  // parameter rows are zero-padded to 16
-    pp0[j] = p0[j];
-    pp1[j] = p1[j];
-  }
-  const T phase0 = p1[0];
-  const int bs = blockDim.x;
-  int pidx[ILP][ND];  // pending histogram slots of the previous trip
-  HT pv[ILP];         // and their value (v^2), 0 for no update
-  bool pending = false;
-  // every lane runs the same number of trips; points past the tile end are
-  // predicated off, so no lane leaves the loop while it holds pending updates
-  const int trips = (cnt + ILP * bs - 1) / (ILP * bs);
-  for (int tr = 0; tr < trips; ++tr) {
-    const int q0 = tr * ILP * bs + (int)threadIdx.x;
-    T fr[ILP][ND], lo[ILP][ND], hi[ILP][ND];
-    int idx[ILP][ND];
-    // words, bins and the grid edges they select
-#pragma unroll
-    for (int e = 0; e < ILP; ++e) {
-      const uint32_t i = (uint32_t)(i0 + q0 + e * bs);
-#pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        const U4 r = philox4x32_10(U4{i, c1 | (uint32_t)b, sid, 0u}, k0, k1);
-        const uint32_t rr[4] = {r.x, r.y, r.z, r.w};
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const int j = 4 * b + c;
-          if (b < NB - 1 || j < d) {
-            int k;
-            if (POW2)
-              bin_frac_pow2(rr[c], L, fr[e][j], k);
-            else
-              bin_frac_any(rr[c], N, Nt, fr[e][j], k);
-            idx[e][j] = j * N + k;
-            lo[e][j] = sE[j * row + k];
-            hi[e][j] = sE[j * row + k + 1];
-          }
-        }
-      }
-    }
-    // the previous trip's histogram updates
-    if (pending) {
-#pragma unroll
-      for (int e = 0; e < ILP; ++e) {
-        if (pv[e] != (HT)0) {
-#pragma unroll
-          for (int j = 0; j < ND; ++j)
-            if (j < 4 * (NB - 1) || j < d) unsafeAtomicAdd(&sH[pidx[e][j]], pv[e]);
-        }
-      }
-    }
-    // weights, integrand, sums
-#pragma unroll
-    for (int e = 0; e < ILP; ++e) {
-      T w = (T)1;
-      T acc = Genz<T, FAM>::init(phase0);
-#pragma unroll
-      for (int j = 0; j < ND; ++j) {
-        if (j < 4 * (NB - 1) || j < d) {
-          const T width = hi[e][j] - lo[e][j];
-          const T x = fma_t(fr[e][j], width, lo[e][j]);
-          w = w * (Nt * width);
-          acc = Genz<T, FAM>::step(acc, x, pp0[j], pp1[j]);
-          pidx[e][j] = idx[e][j];
-        }
-      }
-      const T v = w * Genz<T, FAM>::finish(acc, d);
-      const bool valid = q0 + e * bs < cnt;  // also false for q0 >= cnt
-      const double vd = valid ? (double)v : 0.0;
-      S1 += vd;
-      S2 = fma(vd, vd, S2);
-      pv[e] = valid ? (HT)(v * v) : (HT)0;
-    }
-    pending = true;
-  }
-  if (pending) {
-#pragma unroll
-    for (int e = 0; e < ILP; ++e) {
-      if (pv[e] != (HT)0) {
-#pragma unroll
-        for (int j = 0; j < ND; ++j)
-          if (j < 4 * (NB - 1) || j < d) unsafeAtomicAdd(&sH[pidx[e][j]], pv[e]);
-      }
-    }
-  }
-}
-
-// One kernel per (precision, histogram type, ILP, NB): every instance only
-// holds the registers its own dimension class needs.  A launch walks the
-// slice [tile_first, tile_first + tile_count) of the tile list, which holds
-// the tiles of the jobs of that class.
-template <typename T, typename HT, int ILP, int NB, bool POW2>
-__global__ void __launch_bounds__(256) vegas_dosample_kernel(VegasArgs A) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ double red[2][4];
-  T *sE = (T *)smem;
-  HT *sH = (HT *)(smem + A.lds_hist_byte_off);
-  const int tid = threadIdx.x, bs = blockDim.x, lane = tid & 63, wid = tid >> 6;
-  const int myprec = sizeof(T) == 8 ? FP64 : FP32;
-
-  const int tend = A.tile_first + A.tile_count;
-  for (int tt = A.tile_first + blockIdx.x; tt < tend; tt += gridDim.x) {
-    const int jb = A.tile_job[tt];
-    const VJob J = A.jobs[jb];
-    if (J.prec != myprec || ((J.ndim + 3) >> 2) != NB || ((J.nbins & (J.nbins - 1)) == 0) != POW2)
-      continue;
-    const VState st = *J.state;
-    if (st.done) continue;
-    const int d = J.ndim, N = J.nbins, dN = d * N, row = N + 1;
-    const int lt = tt - J.tile0;
-    const long long n_t = J.nstart + (long long)st.T * J.nincrease;
-    const long long i0 = (long long)lt * J.tile_pts;
-    long long c = n_t - i0;
-    c = c < 0 ? 0 : (c > J.tile_pts ? J.tile_pts : c);
-    const int cnt = (int)c;
-
-    const double *E = J.grid + (long long)(st.T & 1) * d * row;
-    for (int e = tid; e < d * row; e += bs) sE[e] = (T)E[e];
-    for (int e = tid; e < dN; e += bs) sH[e] = (HT)0;
-    __syncthreads();
-
-    const T *p0 = param_ptr<T>(J, 0);
-    const T *p1 = param_ptr<T>(J, 1);
-    double S1 = 0.0, S2 = 0.0;
-    switch (J.family) {
-      case GAUSSIAN: sample_tile<T, HT, GAUSSIAN, NB, ILP, POW2>(J, st.T, i0, cnt, sE, sH, p0, p1, S1, S2); break;
-      case OSCILLATORY: sample_tile<T, HT, OSCILLATORY, NB, ILP, POW2>(J, st.T, i0, cnt, sE, sH, p0, p1, S1, S2); break;
-      case PRODUCT_PEAK: sample_tile<T, HT, PRODUCT_PEAK, NB, ILP, POW2>(J, st.T, i0, cnt, sE, sH, p0, p1, S1, S2); break;
-      case CORNER_PEAK: sample_tile<T, HT, CORNER_PEAK, NB, ILP, POW2>(J, st.T, i0, cnt, sE, sH, p0, p1, S1, S2); break;
-      default: sample_tile<T, HT, C0, NB, ILP, POW2>(J, st.T, i0, cnt, sE, sH, p0, p1, S1, S2); break;
-    }
-    S1 = wave_sum(S1);
-    S2 = wave_sum(S2);
-    if (lane == 0) {
-      red[0][wid] = S1;
-      red[1][wid] = S2;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      double a = 0.0, b = 0.0;
-      for (int q = 0; q < (bs >> 6); ++q) {
-        a += red[0][q];
-        b += red[1][q];
-      }
-      J.tsums[2 * lt] = a;
-      J.tsums[2 * lt + 1] = b;
-    }
-    double *th = J.thist + (long long)lt * dN;
-    for (int e = tid; e < dN; e += bs) th[e] = (double)sH[e];
-
-    __syncthreads();
-  }
-}
 
 // ---------------------------------------------------------------------------
 // a7: lower regularized incomplete gamma P(a, x) for the chi^2 probability,
@@ -348,10 +87,17 @@ __global__ void __launch_bounds__(256) vegas_fold_kernel(FoldArgs F) {
   const int t0 = grp * kGroupTiles, t1 = min(t0 + kGroupTiles, J.ntiles);
   const int bin = ch * 64 + lane;
   if (bin < dN) {
+    // all of the group's rows are loaded before the in-order sum, so that
+    // the loads are in flight together
     const double *src = J.thist + (long long)t0 * dN + bin;
+    const int nt = t1 - t0;
+    double v[kGroupTiles];
+#pragma unroll
+    for (int q = 0; q < kGroupTiles; ++q) v[q] = q < nt ? src[(long long)q * dN] : 0.0;
     double s = 0.0;
-#pragma unroll 8
-    for (int t = t0; t < t1; ++t, src += dN) s += *src;
+#pragma unroll
+    for (int q = 0; q < kGroupTiles; ++q)
+      if (q < nt) s += v[q];
     J.ghist[(long long)grp * dN + bin] = s;
   }
   if (ch == 0 && lane < 2) {
@@ -361,8 +107,10 @@ __global__ void __launch_bounds__(256) vegas_fold_kernel(FoldArgs F) {
   }
 }
 
-// Second fold level: one wavefront per (integral, 64-bin chunk) sums the
-// group rows in group order into hsum = (S1, S2, H[d*N]).
+// Second fold level, for callers that want the iteration totals themselves
+// (the refine kernel does this level on its own): one wavefront per
+// (integral, 64-bin chunk) sums the group rows in group order into
+// hsum = (S1, S2, H[d*N]).
 __global__ void __launch_bounds__(256) vegas_fold2_kernel(FoldArgs F) {
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const long long g = (long long)blockIdx.x * 4 + w;
@@ -429,10 +177,40 @@ __global__ void __launch_bounds__(1024) vegas_refine_kernel(VegasArgs A) {
   const int t = st.T;
   double *H = rsm;       // histogram, later prefix sums of m
   double *D = rsm + dN;  // smoothed histogram, later m
-  for (int e = tid; e < dN; e += bs) H[e] = J.hsum[2 + e];
+  __shared__ double s_sums[2];
+  // the last fold level: the group rows in group order (the order of the
+  // separate second-level fold, so both give the same sums)
+  const int ng = ngroups_of(J.ntiles);
+  constexpr int kBatch = 16;  // loads in flight per thread before the adds
+  for (int e = tid; e < dN; e += bs) {
+    const double *src = J.ghist + e;
+    double h = 0.0;
+    for (int q0 = 0; q0 < ng; q0 += kBatch) {
+      double v[kBatch];
+#pragma unroll
+      for (int q = 0; q < kBatch; ++q) v[q] = q0 + q < ng ? src[(long long)(q0 + q) * dN] : 0.0;
+#pragma unroll
+      for (int q = 0; q < kBatch; ++q)
+        if (q0 + q < ng) h += v[q];
+    }
+    H[e] = h;
+  }
+  if (tid < 2) {
+    double h = 0.0;
+    for (int q0 = 0; q0 < ng; q0 += kBatch) {
+      double v[kBatch];
+#pragma unroll
+      for (int q = 0; q < kBatch; ++q) v[q] = q0 + q < ng ? J.gsums[2 * (q0 + q) + tid] : 0.0;
+#pragma unroll
+      for (int q = 0; q < kBatch; ++q)
+        if (q0 + q < ng) h += v[q];
+    }
+    s_sums[tid] = h;
+  }
+  __syncthreads();
   if (tid == 0) {
     const long long n = J.nstart + (long long)t * J.nincrease;
-    const double S1 = J.hsum[0], S2 = J.hsum[1];
+    const double S1 = s_sums[0], S2 = s_sums[1];
     const double I = S1 / (double)n;
     double var = S2 / (double)n - I * I;
     if (var < 0.0) var = 0.0;
@@ -575,19 +353,25 @@ __global__ void __launch_bounds__(256) vegas_collect_kernel(VegasArgs A, double 
   for (int e = tid; e < dN; e += blockDim.x) hist[e] = J.hsum[2 + e];
 }
 
-// Debug/parity kernel: the points of one iteration (a1-a3), with the grid
-// staged in LDS in the working precision exactly as DoSample stages it.
+// Parity kernel: the points of one iteration (a1-a3), computed with the
+// staging and the per-coordinate arithmetic of the DoSample kernel.
 template <typename T>
 __global__ void __launch_bounds__(256) vegas_points_kernel(PointsArgs P) {
   extern __shared__ __align__(16) unsigned char psm[];
-  T *sE = (T *)psm;
-  const int d = P.ndim, N = P.nbins, row = N + 1, nblk = (d + 3) >> 2;
-  for (int e = threadIdx.x; e < d * row; e += blockDim.x) sE[e] = (T)P.grid[e];
+  Cell<T> *sC = (Cell<T> *)psm;
+  const int d = P.ndim, N = P.nbins, nblk = (d + 3) >> 2;
+  const bool pow2 = (N & (N - 1)) == 0;
+  if (pow2)
+    stage_cells<T, true>(P.grid, d, N, sC);
+  else
+    stage_cells<T, false>(P.grid, d, N, sC);
   __syncthreads();
   const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= P.npts) return;
   const uint32_t i = (uint32_t)(P.i0 + p);
   const T Nt = (T)N;
+  const int L = 31 - __clz(N);
+  const T scale = pow2_scale<T>(L);
   T w = (T)1;
   for (int b = 0; b < nblk; ++b) {
     const U4 r = philox4x32_10(U4{i, ((uint32_t)P.iteration << 8) | (uint32_t)b, P.sid, 0u},
@@ -597,10 +381,15 @@ __global__ void __launch_bounds__(256) vegas_points_kernel(PointsArgs P) {
       P.words[(p * nblk + b) * 4 + c] = rr[c];
       const int j = 4 * b + c;
       if (j >= d) continue;
-      T x, jac;
+      T fr;
       int k;
-      map_coord(rr[c], N, Nt, sE + j * row, x, jac, k);
-      w = w * jac;
+      if (pow2)
+        bin_frac_pow2(rr[c], L, scale, fr, k);
+      else
+        bin_frac_any(rr[c], N, Nt, fr, k);
+      const Cell<T> cell = sC[j * N + k];
+      const T x = fma_t(fr, cell.span, cell.lo);
+      w = pow2 ? w * cell.span : w * (Nt * cell.span);
       P.x[p * d + j] = (double)x;
       P.bin[p * d + j] = k;
     }
@@ -611,54 +400,20 @@ __global__ void __launch_bounds__(256) vegas_points_kernel(PointsArgs P) {
 // ---------------------------------------------------------------------------
 // launchers
 
-template <int ILP, int NB, bool POW2>
-static void launch_dosample_nb(const VegasArgs &A, int prec, int grid, int block, size_t lds,
-                               hipStream_t s) {
-  if (prec == FP64) {
-    hipLaunchKernelGGL((vegas_dosample_kernel<double, double, ILP, NB, POW2>), dim3(grid),
-                       dim3(block), lds, s, A);
-  } else if (A.hist64) {
-    hipLaunchKernelGGL((vegas_dosample_kernel<float, double, ILP, NB, POW2>), dim3(grid),
-                       dim3(block), lds, s, A);
-  } else {
-    hipLaunchKernelGGL((vegas_dosample_kernel<float, float, ILP, NB, POW2>), dim3(grid),
-                       dim3(block), lds, s, A);
-  }
-}
-
-template <int ILP, bool POW2>
-static void launch_dosample_ilp(const VegasArgs &A, int prec, int nb, int grid, int block,
-                                size_t lds, hipStream_t s) {
-  switch (nb) {
-    case 1: launch_dosample_nb<ILP, 1, POW2>(A, prec, grid, block, lds, s); break;
-    case 2: launch_dosample_nb<ILP, 2, POW2>(A, prec, grid, block, lds, s); break;
-    case 3: launch_dosample_nb<ILP, 3, POW2>(A, prec, grid, block, lds, s); break;
-    default: launch_dosample_nb<ILP, 4, POW2>(A, prec, grid, block, lds, s); break;
-  }
-}
-
-hipError_t launch_dosample(const VegasArgs &A, int prec, int nb, bool pow2, int grid, int block,
-                           size_t lds, hipStream_t s) {
+hipError_t launch_dosample(const VegasArgs &A, int prec, int nb, bool pow2, bool full,
+                           int grid, int block, size_t lds, hipStream_t s) {
   if (A.tile_count <= 0 || grid <= 0) return hipSuccess;
-  if (A.ilp == 2) {
-    if (pow2)
-      launch_dosample_ilp<2, true>(A, prec, nb, grid, block, lds, s);
-    else
-      launch_dosample_ilp<2, false>(A, prec, nb, grid, block, lds, s);
-  } else {
-    if (pow2)
-      launch_dosample_ilp<1, true>(A, prec, nb, grid, block, lds, s);
-    else
-      launch_dosample_ilp<1, false>(A, prec, nb, grid, block, lds, s);
-  }
-  return hipGetLastError();
+  if (prec == FP64) return launch_dosample_f64(A, nb, pow2, full, grid, block, lds, s);
+  if (A.hist64) return launch_dosample_f32h64(A, nb, pow2, full, grid, block, lds, s);
+  return launch_dosample_f32h32(A, nb, pow2, full, grid, block, lds, s);
 }
 
-hipError_t launch_fold(const FoldArgs &F, hipStream_t s) {
+hipError_t launch_fold(const FoldArgs &F, bool level2, hipStream_t s) {
   if (F.total <= 0) return hipSuccess;
   hipLaunchKernelGGL(vegas_fold_kernel, dim3((unsigned)((F.total + 3) / 4)), dim3(256), 0, s, F);
-  hipLaunchKernelGGL(vegas_fold2_kernel, dim3((unsigned)((F.total2 + 3) / 4)), dim3(256), 0, s,
-                     F);
+  if (level2)
+    hipLaunchKernelGGL(vegas_fold2_kernel, dim3((unsigned)((F.total2 + 3) / 4)), dim3(256), 0,
+                       s, F);
   return hipGetLastError();
 }
 
@@ -678,35 +433,27 @@ hipError_t launch_points(const PointsArgs &P, hipStream_t s) {
   const int block = 256;
   const long long grid = (P.npts + block - 1) / block;
   if (grid == 0) return hipSuccess;
-  const size_t row = (size_t)P.ndim * (P.nbins + 1);
+  const size_t cells = (size_t)P.ndim * P.nbins;
   if (P.prec == FP64)
     hipLaunchKernelGGL(vegas_points_kernel<double>, dim3((unsigned)grid), dim3(block),
-                       row * sizeof(double), s, P);
+                       cells * sizeof(Cell<double>), s, P);
   else
     hipLaunchKernelGGL(vegas_points_kernel<float>, dim3((unsigned)grid), dim3(block),
-                       row * sizeof(float), s, P);
+                       cells * sizeof(Cell<float>), s, P);
   return hipGetLastError();
 }
 
 hipError_t set_kernel_limits() {
-  // allow the large-grid cases (d = 16, 256 bins: ~65 KB) the LDS gfx950 has;
-  // a runtime that refuses keeps its default limit and such launches report
-  // an error instead of running
+  // allow the large-grid cases (d = 16, 256 bins: up to 96 KB of cells and
+  // histogram) the LDS gfx950 has; a runtime that refuses keeps its default
+  // limit and such launches report an error instead of running
   const int big = 160 * 1024;
-  std::vector<const void *> fns = {
-      (const void *)vegas_dosample_kernel<double, double, 1, 4, true>,
-      (const void *)vegas_dosample_kernel<float, double, 1, 4, true>,
-      (const void *)vegas_dosample_kernel<float, float, 1, 4, true>,
-      (const void *)vegas_dosample_kernel<double, double, 2, 4, true>,
-      (const void *)vegas_dosample_kernel<float, double, 2, 4, true>,
-      (const void *)vegas_dosample_kernel<float, float, 2, 4, true>,
-      (const void *)vegas_dosample_kernel<double, double, 1, 4, false>,
-      (const void *)vegas_dosample_kernel<float, double, 1, 4, false>,
-      (const void *)vegas_dosample_kernel<float, float, 1, 4, false>,
-      (const void *)vegas_dosample_kernel<double, double, 2, 4, false>,
-      (const void *)vegas_dosample_kernel<float, double, 2, 4, false>,
-      (const void *)vegas_dosample_kernel<float, float, 2, 4, false>,
-      (const void *)vegas_refine_kernel};
+  std::vector<const void *> fns = {(const void *)vegas_refine_kernel,
+                                   (const void *)vegas_points_kernel<double>,
+                                   (const void *)vegas_points_kernel<float>};
+  dosample_fns_f64(fns);
+  dosample_fns_f32h64(fns);
+  dosample_fns_f32h32(fns);
   for (const void *f : fns)
     if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, big) != hipSuccess)
       (void)hipGetLastError();

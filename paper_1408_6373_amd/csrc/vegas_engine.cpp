@@ -97,27 +97,28 @@ void plan_tile_groups(std::vector<VJob> &jobs, std::vector<int> &tiles,
   tiles.clear();
   groups.clear();
   size_t ref = 0;
-  for (int p = 0; p < 2; ++p)
-    for (int nb = 1; nb <= 4; ++nb)
-      for (int pw = 0; pw < 2; ++pw) {
-      TileGroup g{p, nb, pw, (int)tiles.size(), 0, 0, 0};
-      size_t hb = 0;
-      for (int j = 0; j < (int)jobs.size(); ++j) {
-        VJob &J = jobs[j];
-        const int jp = (J.nbins & (J.nbins - 1)) == 0;
-        if (J.prec != p || ((J.ndim + 3) >> 2) != nb || jp != pw) continue;
-        J.tile0 = (int)tiles.size();
-        for (int q = 0; q < J.ntiles; ++q) tiles.push_back(j);
-        const size_t row = (size_t)J.ndim * (J.nbins + 1), dN = (size_t)J.ndim * J.nbins;
-        const size_t tsz = p == FP64 ? 8 : 4, hsz = (p == FP64 || hist64) ? 8 : 4;
-        g.grid_bytes = std::max(g.grid_bytes, align16(row * tsz));
-        hb = std::max(hb, dN * hsz);
-        ref = std::max(ref, 2 * dN * 8);
-      }
-      g.count = (int)tiles.size() - g.first;
-      g.lds = g.grid_bytes + hb;
-      if (g.count > 0) groups.push_back(g);
+  // one class per (precision, Philox blocks, power-of-two bins, d = 4 nb)
+  for (int cls = 0; cls < 32; ++cls) {
+    const int p = cls >> 4, nb = ((cls >> 2) & 3) + 1, pw = (cls >> 1) & 1, full = cls & 1;
+    TileGroup g{p, nb, pw, full, (int)tiles.size(), 0, 0, 0};
+    size_t hb = 0;
+    for (int j = 0; j < (int)jobs.size(); ++j) {
+      VJob &J = jobs[j];
+      const int jp = (J.nbins & (J.nbins - 1)) == 0, jf = J.ndim == 4 * nb;
+      if (J.prec != p || ((J.ndim + 3) >> 2) != nb || jp != pw || jf != full) continue;
+      J.tile0 = (int)tiles.size();
+      for (int q = 0; q < J.ntiles; ++q) tiles.push_back(j);
+      const size_t dN = (size_t)J.ndim * J.nbins;
+      // LDS: one (lower edge, span) cell per bin, then the histogram
+      const size_t csz = p == FP64 ? 16 : 8, hsz = (p == FP64 || hist64) ? 8 : 4;
+      g.grid_bytes = std::max(g.grid_bytes, align16(dN * csz));
+      hb = std::max(hb, dN * hsz);
+      ref = std::max(ref, 2 * dN * 8);
     }
+    g.count = (int)tiles.size() - g.first;
+    g.lds = g.grid_bytes + hb;
+    if (g.count > 0) groups.push_back(g);
+  }
   *refine_lds = ref;
 }
 
@@ -130,8 +131,8 @@ int launch_tile_groups(ccuba_ctx *ctx, VegasArgs A, const std::vector<TileGroup>
     A.lds_hist_byte_off = (long long)g.grid_bytes;
     const long long B = (long long)ctx->ncu * ctx->tune[g.prec].blocks_per_cu;
     const int grid = (int)std::min<long long>(B, g.count);
-    CCUBA_HIP(launch_dosample(A, g.prec, g.nb, g.pow2 != 0, grid, ctx->tune[g.prec].block,
-                              g.lds, s));
+    CCUBA_HIP(launch_dosample(A, g.prec, g.nb, g.pow2 != 0, g.full != 0, grid,
+                              ctx->tune[g.prec].block, g.lds, s));
   }
   return CCUBA_OK;
 }
@@ -153,8 +154,7 @@ void fold_tasks(const std::vector<VJob> &jobs, std::vector<long long> &ends, lon
 }
 
 VegasEngine::~VegasEngine() {
-  if (graph_exec_) (void)hipGraphExecDestroy(graph_exec_);
-  if (graph_) (void)hipGraphDestroy(graph_);
+  for (auto &g : graphs_) (void)hipGraphExecDestroy(g.exec);
 }
 
 int VegasEngine::setup(const std::vector<VegasSpec> &specs, bool single, hipStream_t s) {
@@ -191,7 +191,6 @@ int VegasEngine::setup(const std::vector<VegasSpec> &specs, bool single, hipStre
   std::vector<int> tile_job;
   long long goff = 0, thoff = 0, ghoff = 0, ioff = 0, hsoff = 0;
   int tile0 = 0, group0 = 0;
-  size_t grid_bytes[2] = {0, 0}, hist_bytes[2] = {0, 0}, refine_bytes = 0;
   for (int j = 0; j < n; ++j) {
     const VegasSpec &sp = specs[j];
     const int p = sp.prec;
@@ -234,10 +233,6 @@ int VegasEngine::setup(const std::vector<VegasSpec> &specs, bool single, hipStre
     ioff += J.hist_cap;
     tile0 += nt;
     group0 += ngroups_of(nt);
-    const size_t tsz = p == FP64 ? 8 : 4, hsz = (p == FP64 || hist64_) ? 8 : 4;
-    grid_bytes[p] = std::max(grid_bytes[p], align16(row * tsz));
-    hist_bytes[p] = std::max(hist_bytes[p], (size_t)dN * hsz);
-    refine_bytes = std::max(refine_bytes, (size_t)(2 * dN * 8));
   }
   ntiles_ = tile0;
   ngroups_ = group0;
@@ -246,20 +241,20 @@ int VegasEngine::setup(const std::vector<VegasSpec> &specs, bool single, hipStre
     const long long B = (long long)ctx_->ncu * ctx_->tune[p].blocks_per_cu;
     nblocks_[p] = (int)std::min<long long>(B, ntiles_);
   }
-  (void)grid_bytes;
-  (void)hist_bytes;
-  (void)refine_bytes;
 
+  // buffers of an earlier setup are kept when large enough (an engine that
+  // is set up again for the same shape keeps its device addresses)
   int rc;
-  if ((rc = jobs_.alloc(ctx_, n)) || (rc = state_.alloc(ctx_, n)) ||
-      (rc = tile_job_.alloc(ctx_, ntiles_)) || (rc = grids_.alloc(ctx_, goff)) ||
-      (rc = p64_.alloc(ctx_, (size_t)n * 2 * kParamRow)) ||
-      (rc = p32_.alloc(ctx_, (size_t)n * 2 * kParamRow)) ||
-      (rc = tile_sums_.alloc(ctx_, 2 * (size_t)ntiles_)) || (rc = tile_hist_.alloc(ctx_, thoff)) ||
-      (rc = group_sums_.alloc(ctx_, 2 * (size_t)ngroups_)) ||
-      (rc = group_hist_.alloc(ctx_, ghoff)) || (rc = fold_end_.alloc(ctx_, 2 * n)) ||
-      (rc = hsum_.alloc(ctx_, hsoff)) ||
-      (rc = iter_I_.alloc(ctx_, ioff)) || (rc = iter_var_.alloc(ctx_, ioff)))
+  if ((rc = jobs_.reserve(ctx_, n)) || (rc = state_.reserve(ctx_, n)) ||
+      (rc = tile_job_.reserve(ctx_, ntiles_)) || (rc = grids_.reserve(ctx_, goff)) ||
+      (rc = p64_.reserve(ctx_, (size_t)n * 2 * kParamRow)) ||
+      (rc = p32_.reserve(ctx_, (size_t)n * 2 * kParamRow)) ||
+      (rc = tile_sums_.reserve(ctx_, 2 * (size_t)ntiles_)) ||
+      (rc = tile_hist_.reserve(ctx_, thoff)) ||
+      (rc = group_sums_.reserve(ctx_, 2 * (size_t)ngroups_)) ||
+      (rc = group_hist_.reserve(ctx_, ghoff)) || (rc = fold_end_.reserve(ctx_, 2 * n)) ||
+      (rc = hsum_.reserve(ctx_, hsoff)) ||
+      (rc = iter_I_.reserve(ctx_, ioff)) || (rc = iter_var_.reserve(ctx_, ioff)))
     return rc;
 
   for (int j = 0; j < n; ++j) {
@@ -311,17 +306,37 @@ int VegasEngine::setup(const std::vector<VegasSpec> &specs, bool single, hipStre
   args_.tile_first = 0;
   args_.tile_count = ntiles_;
   args_.hist64 = hist64_;
+  pending_.clear();
+  iter_launched_ = 0;
+  // captured graphs stay valid only while every kernel argument they hold
+  // is unchanged
+  std::vector<long long> sig = {(long long)(intptr_t)jobs_.p, (long long)(intptr_t)state_.p,
+                                (long long)(intptr_t)tile_job_.p,
+                                (long long)(intptr_t)fold_end_.p, fold_total_, fold_total2_,
+                                n, ntiles_, (long long)lds_refine_, hist64_};
+  for (int p = 0; p < 2; ++p) {
+    const VegasTune &t = ctx_->tune[p];
+    sig.insert(sig.end(), {t.block, t.blocks_per_cu, t.ilp, t.hist64, ctx_->ncu});
+  }
+  for (const TileGroup &g : tgroups_)
+    sig.insert(sig.end(), {g.prec, g.nb, g.pow2, g.full, g.first, g.count,
+                           (long long)g.grid_bytes, (long long)g.lds});
+  if (sig != graph_sig_) {
+    for (auto &g : graphs_) (void)hipGraphExecDestroy(g.exec);
+    graphs_.clear();
+    graph_sig_ = sig;
+  }
   // host copies of the tables must outlive the async uploads
   CCUBA_HIP(hipStreamSynchronize(s));
   return CCUBA_OK;
 }
 
-int VegasEngine::dosample_only(hipStream_t s, hipEvent_t between) {
+int VegasEngine::dosample_only(hipStream_t s, bool level2, hipEvent_t between) {
   const int rc = launch_tile_groups(ctx_, args_, tgroups_, s);
   if (rc) return rc;
   if (between) CCUBA_HIP(hipEventRecord(between, s));
   FoldArgs F{jobs_.p, fold_end_.p, njobs(), fold_total_, fold_end_.p + njobs(), fold_total2_};
-  CCUBA_HIP(launch_fold(F, s));
+  CCUBA_HIP(launch_fold(F, level2, s));
   return CCUBA_OK;
 }
 
@@ -332,7 +347,7 @@ int VegasEngine::launch_iteration(hipStream_t s) {
     hipEvent_t ev[4];
     for (auto &e : ev) CCUBA_HIP(hipEventCreate(&e));
     CCUBA_HIP(hipEventRecord(ev[0], s));
-    int rc = dosample_only(s, ev[1]);
+    int rc = dosample_only(s, false, ev[1]);
     if (rc) return rc;
     CCUBA_HIP(hipEventRecord(ev[2], s));
     CCUBA_HIP(launch_refine(args_, njobs(), lds_refine_, s));
@@ -370,48 +385,65 @@ int VegasEngine::flush_timing() {
 
 int VegasEngine::step(hipStream_t s) { return launch_iteration(s); }
 
+int VegasEngine::graph_for(int k, hipStream_t s, hipGraphExec_t *out) {
+  for (const auto &g : graphs_)
+    if (g.k == k) {
+      *out = g.exec;
+      return CCUBA_OK;
+    }
+  CCUBA_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  capturing_ = true;
+  int rc = CCUBA_OK;
+  for (int q = 0; q < k && rc == CCUBA_OK; ++q) rc = launch_iteration(s);
+  capturing_ = false;
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(s, &g);
+  if (rc == CCUBA_OK && e != hipSuccess) rc = CCUBA_EHIP;
+  hipGraphExec_t exec = nullptr;
+  if (rc == CCUBA_OK && hipGraphInstantiate(&exec, g, nullptr, nullptr, 0) != hipSuccess)
+    rc = CCUBA_EHIP;
+  if (g) (void)hipGraphDestroy(g);
+  if (rc) return rc;
+  graphs_.push_back({k, exec});
+  *out = exec;
+  return CCUBA_OK;
+}
+
 int VegasEngine::run(hipStream_t s) {
   bool fixed = true;
   for (const auto &sp : specs_)
     if (sp.epsrel > 0 || sp.epsabs > 0) fixed = false;
   int remaining = max_iters_;
   if (remaining == 0) return CCUBA_OK;
+  // Iterations are launched in chunks between host checks of the states:
+  // all of them at once when no job can stop early, else 2, 4, 8, ... (a
+  // finished job's state makes the remaining launches of its chunk skip it).
+  // With graphs on, a chunk of k iterations is one graph of 3k kernels, so
+  // that consecutive iterations are not separated by graph launches.
   const bool graph = ctx_->use_graph != 0 && !ctx_->profile;
-  if (graph && !graph_exec_) {
-    CCUBA_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    capturing_ = true;
-    const int rc = launch_iteration(s);
-    capturing_ = false;
-    hipGraph_t g = nullptr;
-    const hipError_t e = hipStreamEndCapture(s, &g);
-    if (rc) {
-      if (g) (void)hipGraphDestroy(g);
-      return rc;
-    }
-    if (e != hipSuccess) return CCUBA_EHIP;
-    graph_ = g;
-    CCUBA_HIP(hipGraphInstantiate(&graph_exec_, graph_, nullptr, nullptr, 0));
-  }
-  int chunk = fixed ? remaining : 2;
+  int chunk = fixed ? std::min(remaining, kMaxGraphIters) : 2;
   std::vector<VState> st;
   while (remaining > 0) {
     const int k = std::min(chunk, remaining);
-    for (int q = 0; q < k; ++q) {
-      if (graph) {
-        CCUBA_HIP(hipGraphLaunch(graph_exec_, s));
-      } else {
+    if (graph) {
+      hipGraphExec_t exec = nullptr;
+      const int rc = graph_for(k, s, &exec);
+      if (rc) return rc;
+      CCUBA_HIP(hipGraphLaunch(exec, s));
+    } else {
+      for (int q = 0; q < k; ++q) {
         const int rc = launch_iteration(s);
         if (rc) return rc;
       }
     }
     remaining -= k;
-    if (remaining > 0) {
+    if (remaining > 0 && !fixed) {
       const int rc = read_states(st, s);
       if (rc) return rc;
       bool all = true;
       for (const auto &x : st) all = all && x.done;
       if (all) break;
-      chunk = std::min(chunk * 2, 32);
+      chunk = std::min(chunk * 2, kMaxGraphIters);
     }
   }
   CCUBA_HIP(hipStreamSynchronize(s));
@@ -489,9 +521,13 @@ int VegasEngine::refine_only(const double *hist, const double *grid_in, double *
   if (rc) return rc;
   // a synthetic finished iteration with n = 2, S1 = 1, S2 = 2 (I = 1/2,
   // sigma^2 = 3/4 > 0, so the zero-tolerance job never converges)
+  // (the refine kernel reads the group rows: row 0 holds it all)
   const double sums[2] = {1.0, 2.0};
-  CCUBA_HIP(hipMemcpyAsync(J.hsum, sums, sizeof(sums), hipMemcpyHostToDevice, s));
-  CCUBA_HIP(hipMemcpyAsync(J.hsum + 2, hist, dN * sizeof(double), hipMemcpyHostToDevice, s));
+  const long long ng = ngroups_of(J.ntiles);
+  CCUBA_HIP(hipMemsetAsync(J.gsums, 0, 2 * ng * sizeof(double), s));
+  CCUBA_HIP(hipMemsetAsync(J.ghist, 0, ng * dN * sizeof(double), s));
+  CCUBA_HIP(hipMemcpyAsync(J.gsums, sums, sizeof(sums), hipMemcpyHostToDevice, s));
+  CCUBA_HIP(hipMemcpyAsync(J.ghist, hist, dN * sizeof(double), hipMemcpyHostToDevice, s));
   CCUBA_HIP(hipStreamSynchronize(s));
   rc = set_iteration(0, 0, s);
   if (rc) return rc;

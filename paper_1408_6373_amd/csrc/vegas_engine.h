@@ -34,7 +34,7 @@ void genz_constants(const VegasSpec &s, double p64[2][kParamRow], float p32[2][k
 // A slice of a launch's tile list holding the tiles of every job of one
 // (precision, Philox blocks per point) class, with the LDS it needs.
 struct TileGroup {
-  int prec, nb, pow2, first, count;
+  int prec, nb, pow2, full, first, count;
   size_t grid_bytes, lds;
 };
 
@@ -66,9 +66,9 @@ class VegasEngine {
   // group partials into caller buffers.
   int set_iteration(int job, int t, hipStream_t s);
   int load_grid(int job, int copy, const double *src, hipMemcpyKind kind, hipStream_t s);
-  // the sampling kernels, then the fold; records `between` (if given) after
-  // the sampling kernels
-  int dosample_only(hipStream_t s, hipEvent_t between = nullptr);
+  // the sampling kernels, then the fold (with level2 both levels, into
+  // hsum); records `between` (if given) after the sampling kernels
+  int dosample_only(hipStream_t s, bool level2 = false, hipEvent_t between = nullptr);
   int collect(double *sums_dev, double *hist_dev, hipStream_t s);
   // One refinement of job 0 from a given histogram and grid.
   int refine_only(const double *hist, const double *grid_in, double *grid_out, hipStream_t s);
@@ -108,12 +108,19 @@ class VegasEngine {
   std::vector<TileGroup> tgroups_;
   int has_prec_[2] = {0, 0};
   int nblocks_[2] = {0, 0}, block_[2] = {256, 256};
-  size_t lds_dosample_[2] = {0, 0}, grid_bytes_[2] = {0, 0}, lds_refine_ = 0;
+  size_t lds_refine_ = 0;
   int hist64_ = 0;
   int max_iters_ = 0;
   long long evals_iter_ = 0;
-  hipGraphExec_t graph_exec_ = nullptr;
-  hipGraph_t graph_ = nullptr;
+  // instantiated graphs of k consecutive iterations
+  struct ChunkGraph {
+    int k;
+    hipGraphExec_t exec;
+  };
+  std::vector<ChunkGraph> graphs_;
+  std::vector<long long> graph_sig_;  // the launch arguments the graphs hold
+  static constexpr int kMaxGraphIters = 32;
+  int graph_for(int k, hipStream_t s, hipGraphExec_t *out);
 
  public:
   ~VegasEngine();

@@ -1,0 +1,370 @@
+// vegas_sample.h -- the Vegas DoSample kernel (a1-a6) and the
+// per-coordinate helpers it shares with the points kernel.
+//
+// The kernel template is instantiated per precision and histogram type in
+// its own translation unit (vegas_sample_*.hip), so that the instances build
+// in parallel; vegas.hip dispatches to them.
+#pragma once
+#include <vector>
+
+#include "engine.h"
+#include "genz.h"
+#include "philox.h"
+#include "vegas.h"
+
+namespace ccuba {
+
+// ---------------------------------------------------------------------------
+// a3: the grid as staged in LDS.  Cell k of dimension j sits at [j * N + k]
+// and holds its lower edge and its span in the working precision: the width
+// E[k+1] - E[k] for a general N, and N times the width when N = 2^L.  Both
+// are formed once per tile from the two converted edges, exactly as they
+// would be formed per point (scaling by 2^L is exact), so staging changes no
+// value.  One LDS read per coordinate fetches both.
+
+template <typename T>
+struct alignas(2 * sizeof(T)) Cell {
+  T lo, span;
+};
+
+template <typename T, bool POW2>
+__device__ __forceinline__ void stage_cells(const double *__restrict__ E, int d, int N,
+                                            Cell<T> *sC) {
+  const int row = N + 1, dN = d * N;
+  const T Nt = (T)N;
+  for (int e = threadIdx.x; e < dN; e += blockDim.x) {
+    const int j = e / N, k = e - j * N;
+    const T lo = (T)E[j * row + k];
+    const T hi = (T)E[j * row + k + 1];
+    sC[e] = Cell<T>{lo, POW2 ? Nt * (hi - lo) : hi - lo};
+  }
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ const T *param_ptr(const VJob &J, int which);
+template <>
+__device__ __forceinline__ const double *param_ptr<double>(const VJob &J, int which) {
+  return J.p64 + which * kParamRow;
+}
+template <>
+__device__ __forceinline__ const float *param_ptr<float>(const VJob &J, int which) {
+  return J.p32 + which * kParamRow;
+}
+
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return fma(a, b, c); }
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return fmaf(a, b, c); }
+
+// Bin and fractional position of one coordinate (a2 + the first half of
+// a3).  General N: z = y N, k = min(floor z, N - 1), frac = z - k, then
+// x = fma(frac, width, lo) and w *= N width.
+// N = 2^L: the bin is the top L bits of the word and the fraction the bits
+// below them, which is exactly what the floating-point formula gives (every
+// step there is exact).  These helpers return fs = frac / N (exact), so that
+// with the staged span s = N width, x = fma(fs, s, lo) has the same exact
+// product fs s = frac width and rounds to the same x, and w *= s is the same
+// product as before: one multiply fewer per coordinate.
+__device__ __forceinline__ void bin_frac_pow2(uint32_t r, int L, double scale, double &fs,
+                                              int &k) {
+  k = (int)(r >> (32 - L));
+  const uint32_t m = (r << L) | (1u << (L - 1));  // (r N mod 2^32) + N/2
+  fs = (double)m * scale;                         // scale = 2^(-32-L)
+}
+__device__ __forceinline__ void bin_frac_pow2(uint32_t r, int L, float scale, float &fs,
+                                              int &k) {
+  k = (int)(r >> (32 - L));
+  // the 23 - L bits of r >> 9 below the bin index, then the half-step bit
+  // 2^(L-1), as the mantissa M of a float with exponent -L: that float is
+  // 2^-L (1 + M 2^-23), and removing 2^-L (= scale) leaves M 2^(-23-L)
+  // = frac / N exactly.  (x & mask) | c is one three-input bit operation
+  // (truth table 0xEA).
+  static_assert(kMaxBins <= 512, "the shift below needs L <= 9");
+  const uint32_t mask = 0x7FFFFFu & ~((1u << L) - 1u);
+  const uint32_t c = ((uint32_t)(127 - L) << 23) | (1u << (L - 1));
+  const uint32_t bits = (uint32_t)__builtin_amdgcn_bitop3_b32(r >> (9 - L), mask, c, 0xEA);
+  fs = __uint_as_float(bits) - scale;
+}
+__device__ __forceinline__ void bin_frac_any(uint32_t r, int N, double Nd, double &frac, int &k) {
+  const double y = (double)r * 0x1p-32 + 0x1p-33;
+  const double z = y * Nd;
+  int kk = (int)z;
+  kk = kk > N - 1 ? N - 1 : kk;
+  frac = z - (double)kk;
+  k = kk;
+}
+__device__ __forceinline__ void bin_frac_any(uint32_t r, int N, float Nf, float &frac, int &k) {
+  const float y = (float)(r >> 9) * 0x1p-23f + 0x1p-24f;
+  const float z = y * Nf;
+  int kk = (int)z;
+  kk = kk > N - 1 ? N - 1 : kk;
+  frac = z - (float)kk;
+  k = kk;
+}
+
+// 2^-L (FP32) or 2^(-32-L) (FP64): the scale of the power-of-two fraction.
+template <typename T>
+__device__ __forceinline__ T pow2_scale(int L);
+template <>
+__device__ __forceinline__ float pow2_scale<float>(int L) {
+  return __uint_as_float((uint32_t)(127 - L) << 23);
+}
+template <>
+__device__ __forceinline__ double pow2_scale<double>(int L) {
+  return __longlong_as_double((long long)(1023 - 32 - L) << 52);
+}
+
+// Sample the points [i0, i0 + cnt) of one tile; lane sums go to S1, S2.
+// NB = ceil(d/4) Philox blocks per point is a template argument so that the
+// per-dimension loop is fully unrolled with only the last block guarded, and
+// FULL (d = 4 NB) drops that guard too.
+// Each lane carries ILP independent points per trip (q, q + blockDim, ...),
+// so that several Philox chains are in flight; a point past the tile end is
+// computed (its LDS reads stay in range) but contributes nothing.  All lanes
+// run the same number of trips (a build in which lanes left the loop on
+// different trips, holding deferred updates, produced wrong histograms in
+// partially filled tiles).  The
+// histogram updates of a trip are issued in the next trip, after its grid
+// reads, so that those reads never wait behind the atomics in the LDS queue.
+template <typename T, typename HT, int FAM, int NB, int ILP, bool POW2, bool FULL>
+__device__ __forceinline__ void sample_tile(const VJob &J, int t, long long i0, int cnt,
+                                            const Cell<T> *__restrict__ sC, HT *sH,
+                                            const T *__restrict__ p0,
+                                            const T *__restrict__ p1, double &S1,
+                                            double &S2) {
+  constexpr int ND = 4 * NB;
+  const int d = J.ndim, N = J.nbins;
+  const T Nt = (T)N;
+  const int L = POW2 ? 31 - __clz(N) : 0;
+  const T scale = pow2_scale<T>(L);
+  const uint32_t c1 = (uint32_t)t << 8;
+  const uint32_t sid = J.sid, k0 = J.key0, k1 = J.key1;
+  T pp0[ND], pp1[ND];
+#pragma unroll
+  for (int j = 0; j < ND; ++j) {  // parameter rows are zero-padded to 16
+    pp0[j] = p0[j];
+    pp1[j] = p1[j];
+  }
+  const T phase0 = p1[0];
+  const int bs = blockDim.x;
+  int pidx[ILP][ND];  // pending histogram slots of the previous trip
+  HT pv[ILP];         // and their value (v^2), 0 for no update
+  bool pending = false;
+  // an assembly comment naming the family, so that the per-point loop that
+  // follows can be found in the assembly listing (it emits no instruction)
+  asm volatile("; ccuba sample_tile family %0" ::"n"(FAM));
+  // every lane runs the same number of trips; points past the tile end are
+  // predicated off, so no lane leaves the loop while it holds pending updates
+  const int trips = (cnt + ILP * bs - 1) / (ILP * bs);
+  for (int tr = 0; tr < trips; ++tr) {
+    const int q0 = tr * ILP * bs + (int)threadIdx.x;
+    T fr[ILP][ND], lo[ILP][ND], sp[ILP][ND];
+    int idx[ILP][ND];
+    // words, bins and the grid edges they select
+#pragma unroll
+    for (int e = 0; e < ILP; ++e) {
+      const uint32_t i = (uint32_t)(i0 + q0 + e * bs);
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const U4 r = philox4x32_10(U4{i, c1 | (uint32_t)b, sid, 0u}, k0, k1);
+        const uint32_t rr[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int j = 4 * b + c;
+          if (FULL || b < NB - 1 || j < d) {
+            int k;
+            if (POW2)
+              bin_frac_pow2(rr[c], L, scale, fr[e][j], k);
+            else
+              bin_frac_any(rr[c], N, Nt, fr[e][j], k);
+            idx[e][j] = j * N + k;
+            const Cell<T> cell = sC[j * N + k];
+            lo[e][j] = cell.lo;
+            sp[e][j] = cell.span;
+          }
+        }
+      }
+    }
+    // the previous trip's histogram updates
+    if (pending) {
+#pragma unroll
+      for (int e = 0; e < ILP; ++e) {
+        if (pv[e] != (HT)0) {
+#pragma unroll
+          for (int j = 0; j < ND; ++j)
+            if (FULL || j < 4 * (NB - 1) || j < d) unsafeAtomicAdd(&sH[pidx[e][j]], pv[e]);
+        }
+      }
+    }
+    // weights, integrand, sums
+#pragma unroll
+    for (int e = 0; e < ILP; ++e) {
+      T w = (T)1;
+      T acc = Genz<T, FAM>::init(phase0);
+#pragma unroll
+      for (int j = 0; j < ND; ++j) {
+        if (FULL || j < 4 * (NB - 1) || j < d) {
+          const T x = fma_t(fr[e][j], sp[e][j], lo[e][j]);
+          w = POW2 ? w * sp[e][j] : w * (Nt * sp[e][j]);
+          acc = Genz<T, FAM>::step(acc, x, pp0[j], pp1[j]);
+          pidx[e][j] = idx[e][j];
+        }
+      }
+      const T v = w * Genz<T, FAM>::finish(acc, d);
+      const bool valid = q0 + e * bs < cnt;  // also false for q0 >= cnt
+      const double vd = valid ? (double)v : 0.0;
+      S1 += vd;
+      S2 = fma(vd, vd, S2);
+      pv[e] = valid ? (HT)(v * v) : (HT)0;
+    }
+    pending = true;
+  }
+  if (pending) {
+#pragma unroll
+    for (int e = 0; e < ILP; ++e) {
+      if (pv[e] != (HT)0) {
+#pragma unroll
+        for (int j = 0; j < ND; ++j)
+          if (FULL || j < 4 * (NB - 1) || j < d) unsafeAtomicAdd(&sH[pidx[e][j]], pv[e]);
+      }
+    }
+  }
+}
+
+// One kernel per (precision, histogram type, ILP, NB, power-of-two bins,
+// d = 4 NB): every instance only holds the registers and the tests its own
+// class needs.  A launch walks the slice [tile_first, tile_first +
+// tile_count) of the tile list, which holds the tiles of the jobs of that
+// class.
+template <typename T, typename HT, int ILP, int NB, bool POW2, bool FULL>
+__global__ void __launch_bounds__(256) vegas_dosample_kernel(VegasArgs A) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double red[2][4];
+  Cell<T> *sC = (Cell<T> *)smem;
+  HT *sH = (HT *)(smem + A.lds_hist_byte_off);
+  const int tid = threadIdx.x, bs = blockDim.x, lane = tid & 63, wid = tid >> 6;
+  const int myprec = sizeof(T) == 8 ? FP64 : FP32;
+
+  const int tend = A.tile_first + A.tile_count;
+  for (int tt = A.tile_first + blockIdx.x; tt < tend; tt += gridDim.x) {
+    const int jb = A.tile_job[tt];
+    const VJob J = A.jobs[jb];
+    if (J.prec != myprec || ((J.ndim + 3) >> 2) != NB ||
+        ((J.nbins & (J.nbins - 1)) == 0) != POW2 || (J.ndim == 4 * NB) != FULL)
+      continue;
+    const VState st = *J.state;
+    if (st.done) continue;
+    const int d = J.ndim, N = J.nbins, dN = d * N, row = N + 1;
+    const int lt = tt - J.tile0;
+    const long long n_t = J.nstart + (long long)st.T * J.nincrease;
+    const long long i0 = (long long)lt * J.tile_pts;
+    long long c = n_t - i0;
+    c = c < 0 ? 0 : (c > J.tile_pts ? J.tile_pts : c);
+    const int cnt = (int)c;
+
+    stage_cells<T, POW2>(J.grid + (long long)(st.T & 1) * d * row, d, N, sC);
+    for (int e = tid; e < dN; e += bs) sH[e] = (HT)0;
+    __syncthreads();
+
+    const T *p0 = param_ptr<T>(J, 0);
+    const T *p1 = param_ptr<T>(J, 1);
+    double S1 = 0.0, S2 = 0.0;
+    switch (J.family) {
+      case GAUSSIAN: sample_tile<T, HT, GAUSSIAN, NB, ILP, POW2, FULL>(J, st.T, i0, cnt, sC, sH, p0, p1, S1, S2); break;
+      case OSCILLATORY: sample_tile<T, HT, OSCILLATORY, NB, ILP, POW2, FULL>(J, st.T, i0, cnt, sC, sH, p0, p1, S1, S2); break;
+      case PRODUCT_PEAK: sample_tile<T, HT, PRODUCT_PEAK, NB, ILP, POW2, FULL>(J, st.T, i0, cnt, sC, sH, p0, p1, S1, S2); break;
+      case CORNER_PEAK: sample_tile<T, HT, CORNER_PEAK, NB, ILP, POW2, FULL>(J, st.T, i0, cnt, sC, sH, p0, p1, S1, S2); break;
+      default: sample_tile<T, HT, C0, NB, ILP, POW2, FULL>(J, st.T, i0, cnt, sC, sH, p0, p1, S1, S2); break;
+    }
+    S1 = wave_sum(S1);
+    S2 = wave_sum(S2);
+    if (lane == 0) {
+      red[0][wid] = S1;
+      red[1][wid] = S2;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double a = 0.0, b = 0.0;
+      for (int q = 0; q < (bs >> 6); ++q) {
+        a += red[0][q];
+        b += red[1][q];
+      }
+      J.tsums[2 * lt] = a;
+      J.tsums[2 * lt + 1] = b;
+    }
+    double *th = J.thist + (long long)lt * dN;
+    for (int e = tid; e < dN; e += bs) th[e] = (double)sH[e];
+
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers of the instances of one (precision, histogram type)
+
+template <typename T, typename HT, int ILP, int NB>
+static void launch_dosample_cls(const VegasArgs &A, bool pow2, bool full, int grid, int block,
+                                size_t lds, hipStream_t s) {
+  if (pow2) {
+    if (full)
+      hipLaunchKernelGGL((vegas_dosample_kernel<T, HT, ILP, NB, true, true>), dim3(grid),
+                         dim3(block), lds, s, A);
+    else
+      hipLaunchKernelGGL((vegas_dosample_kernel<T, HT, ILP, NB, true, false>), dim3(grid),
+                         dim3(block), lds, s, A);
+  } else {
+    if (full)
+      hipLaunchKernelGGL((vegas_dosample_kernel<T, HT, ILP, NB, false, true>), dim3(grid),
+                         dim3(block), lds, s, A);
+    else
+      hipLaunchKernelGGL((vegas_dosample_kernel<T, HT, ILP, NB, false, false>), dim3(grid),
+                         dim3(block), lds, s, A);
+  }
+}
+
+template <typename T, typename HT, int ILP>
+static void launch_dosample_ilp(const VegasArgs &A, int nb, bool pow2, bool full, int grid,
+                                int block, size_t lds, hipStream_t s) {
+  switch (nb) {
+    case 1: launch_dosample_cls<T, HT, ILP, 1>(A, pow2, full, grid, block, lds, s); break;
+    case 2: launch_dosample_cls<T, HT, ILP, 2>(A, pow2, full, grid, block, lds, s); break;
+    case 3: launch_dosample_cls<T, HT, ILP, 3>(A, pow2, full, grid, block, lds, s); break;
+    default: launch_dosample_cls<T, HT, ILP, 4>(A, pow2, full, grid, block, lds, s); break;
+  }
+}
+
+template <typename T, typename HT>
+static hipError_t launch_dosample_t(const VegasArgs &A, int nb, bool pow2, bool full, int grid,
+                                    int block, size_t lds, hipStream_t s) {
+  if (A.ilp == 2)
+    launch_dosample_ilp<T, HT, 2>(A, nb, pow2, full, grid, block, lds, s);
+  else
+    launch_dosample_ilp<T, HT, 1>(A, nb, pow2, full, grid, block, lds, s);
+  return hipGetLastError();
+}
+
+template <typename T, typename HT, int ILP, int NB>
+static void dosample_fns_cls(std::vector<const void *> &fns) {
+  fns.push_back((const void *)vegas_dosample_kernel<T, HT, ILP, NB, true, true>);
+  fns.push_back((const void *)vegas_dosample_kernel<T, HT, ILP, NB, true, false>);
+  fns.push_back((const void *)vegas_dosample_kernel<T, HT, ILP, NB, false, true>);
+  fns.push_back((const void *)vegas_dosample_kernel<T, HT, ILP, NB, false, false>);
+}
+
+template <typename T, typename HT>
+static void dosample_fns_t(std::vector<const void *> &fns) {
+  dosample_fns_cls<T, HT, 1, 1>(fns);
+  dosample_fns_cls<T, HT, 1, 2>(fns);
+  dosample_fns_cls<T, HT, 1, 3>(fns);
+  dosample_fns_cls<T, HT, 1, 4>(fns);
+  dosample_fns_cls<T, HT, 2, 1>(fns);
+  dosample_fns_cls<T, HT, 2, 2>(fns);
+  dosample_fns_cls<T, HT, 2, 3>(fns);
+  dosample_fns_cls<T, HT, 2, 4>(fns);
+}
+
+}  // namespace ccuba

@@ -3,9 +3,10 @@ gfx950 assembly of this build.
 
 The roofline of the Vegas DoSample kernel is the VALU issue rate: every
 point is produced in registers, so HBM traffic is negligible and there is
-no matrix contraction.  This script compiles ``csrc/vegas.hip`` to gfx950
-assembly with the library's flags, finds the per-point loop of each kernel
-instance and family, and weighs its VALU instructions by their issue cost
+no matrix contraction.  This script compiles the DoSample translation
+units (``csrc/vegas_sample_*.hip``) to gfx950 assembly with the library's
+flags, finds the per-point loop of each kernel instance and family, and
+weighs its VALU instructions by their issue cost
 relative to a full-rate FP32 operation (78.6 T lane-ops/s on MI355X = the
 published 157.3 TFLOP/s FP32 vector peak / 2 flops per FMA):
 
@@ -52,54 +53,50 @@ def _ops(lines):
     return out
 
 
-def _family(ops, nested):
-    has_exp = any(o.startswith("v_exp_") for o in ops)
-    has_div = any(o.startswith("v_div_scale") for o in ops)
-    if has_div:
-        return "corner_peak" if nested else "product_peak"
-    if has_exp:
-        # C0 takes |x - u| (one v_and per dimension on the sign bit)
-        n_and = sum(o.startswith("v_and_b32") for o in ops)
-        return "c0" if n_and >= 4 else "gaussian"
-    return "oscillatory"
-
-
 def count(asm_text):
-    """{kernel instance: {family: slots per point}} from gfx950 assembly."""
+    """{kernel instance: {family: slots per point}} from gfx950 assembly.
+
+    Each family's per-point loop follows an assembly comment that the kernel
+    source places just before it ("ccuba sample_tile family F"); the loop is
+    the largest backward-branch region between that comment and the next
+    one that holds no comment itself."""
     res = {}
     for kern in re.findall(r"^(_ZN5ccuba21vegas_dosample_kernelI\w+):", asm_text, re.M):
-        m = re.search(r"kernelI(\w)(\w)Li(\d)ELi(\d)ELb(\d)E", kern)
+        m = re.search(r"kernelI(\w)(\w)Li(\d)ELi(\d)ELb(\d)ELb(\d)E", kern)
         if not m:
             continue
-        T, H, ilp, nb, pow2 = m.groups()
+        T, H, ilp, nb, pow2, full = m.groups()
         start = asm_text.index(kern + ":")
         body = asm_text[start:asm_text.index(".Lfunc_end", start)].splitlines()
-        labels = {}
+        labels, marks = {}, []
         for i, l in enumerate(body):
             mm = re.match(r"^(\.LBB\w+):", l)
             if mm:
                 labels[mm.group(1)] = i
+            mm = re.search(r"ccuba sample_tile family (\d+)", l)
+            if mm:
+                marks.append((i, int(mm.group(1))))
         loops = []
         for i, l in enumerate(body):
             mm = re.match(r"\s+s_cbranch_\w+\s+(\.LBB\w+)", l)
             if mm and mm.group(1) in labels and labels[mm.group(1)] < i:
                 loops.append((labels[mm.group(1)], i))
         fam_slots = {}
-        for a, b in loops:
-            ops = _ops(body[a:b + 1])
-            v = [o for o in ops if o.startswith("v_")]
-            if len(v) < 80:
-                continue
-            # skip loops that contain another sampled loop (the outer tile loop)
-            if sum(o.startswith("v_mad_u64_u32") for o in v) > 20 * int(nb) * int(ilp) + 8:
-                continue
-            nested = any(a < a2 and b2 < b for a2, b2 in loops)
-            fam = _family(ops, nested)
-            slots = sum(_weight(o) for o in v) / int(ilp)
-            fam_slots.setdefault(fam, []).append(slots)
-        key = "%s%s_ilp%s_nb%s%s" % ({"f": "f32", "d": "f64"}[T], {"f": "h32", "d": "h64"}[H],
-                                     ilp, nb, "_pow2" if pow2 == "1" else "")
-        res[key] = {f: max(v) for f, v in fam_slots.items()}
+        for q, (mline, fam) in enumerate(marks):
+            nxt = marks[q + 1][0] if q + 1 < len(marks) else len(body)
+            best = None
+            for a, b in loops:
+                if not (mline < a < nxt) or any(a <= ml <= b for ml, _ in marks):
+                    continue
+                v = [o for o in _ops(body[a:b + 1]) if o.startswith("v_")]
+                if best is None or len(v) > len(best):
+                    best = v
+            if best:
+                fam_slots[FAMILIES[fam]] = sum(_weight(o) for o in best) / int(ilp)
+        key = "%s%s_ilp%s_nb%s%s%s" % ({"f": "f32", "d": "f64"}[T], {"f": "h32", "d": "h64"}[H],
+                                       ilp, nb, "_pow2" if pow2 == "1" else "",
+                                       "_full" if full == "1" else "")
+        res[key] = fam_slots
     return res
 
 
@@ -112,15 +109,21 @@ def _build_module():
 
 
 def compile_asm(hipcc=None, flags=None):
+    """gfx950 assembly of every DoSample translation unit, concatenated."""
+    import concurrent.futures as cf
     if hipcc is None or flags is None:
         B = _build_module()
         hipcc, flags = B.HIPCC, B.FLAGS
-    src = os.path.join(HERE, "csrc", "vegas.hip")
+    srcs = sorted(os.path.join(HERE, "csrc", f) for f in os.listdir(os.path.join(HERE, "csrc"))
+                  if f.startswith("vegas_sample_") and f.endswith(".hip"))
     with tempfile.TemporaryDirectory() as td:
-        out = os.path.join(td, "vegas.s")
-        cmd = [hipcc, "-x", "hip"] + flags + ["--cuda-device-only", "-S", "-o", out, src]
-        subprocess.run(cmd, check=True, capture_output=True)
-        return open(out).read()
+        def one(src):
+            out = os.path.join(td, os.path.basename(src) + ".s")
+            cmd = [hipcc, "-x", "hip"] + flags + ["--cuda-device-only", "-S", "-o", out, src]
+            subprocess.run(cmd, check=True, capture_output=True)
+            return open(out).read()
+        with cf.ThreadPoolExecutor(max_workers=len(srcs)) as ex:
+            return "\n".join(ex.map(one, srcs))
 
 
 def write(hipcc=None, flags=None):
