@@ -148,7 +148,7 @@ int ccuba_init(ccuba_ctx **ctx, int device, size_t hbm_budget) {
   if (set_kernel_limits() != hipSuccess) return CCUBA_EHIP;
   for (int p = 0; p < 2; ++p) {
     c->tune[p].block = (int)env_ll("CCUBA_BLOCK", 256);
-    c->tune[p].blocks_per_cu = (int)env_ll("CCUBA_BLOCKS_PER_CU", 4);
+    c->tune[p].blocks_per_cu = (int)env_ll("CCUBA_BLOCKS_PER_CU", 3);
     c->tune[p].min_tile = env_ll("CCUBA_MIN_TILE", 16384);
     // measured best on gfx950: two points per lane for FP32, one for FP64
     c->tune[p].ilp = (int)env_ll("CCUBA_ILP", p == FP32 ? 2 : 1) == 2 ? 2 : 1;

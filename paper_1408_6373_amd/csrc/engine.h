@@ -65,7 +65,7 @@ enum { FLAG_FREEZE_GRID = 1 << 4 };
 // Launch geometry of the DoSample kernel.
 struct VegasTune {
   int block = 256;        // threads per block
-  int blocks_per_cu = 4;  // persistent blocks per compute unit
+  int blocks_per_cu = 3;  // persistent blocks per compute unit
   int hist64 = 1;         // FP32 path: 1 = FP64 LDS histogram, 0 = FP32
   int ilp = 1;            // points per lane per trip (1 or 2)
   int tiles_per_job = 0;  // 0 = automatic (one tile per persistent block)

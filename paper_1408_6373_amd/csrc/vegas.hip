@@ -181,7 +181,7 @@ __global__ void __launch_bounds__(1024) vegas_refine_kernel(VegasArgs A) {
   // the last fold level: the group rows in group order (the order of the
   // separate second-level fold, so both give the same sums)
   const int ng = ngroups_of(J.ntiles);
-  constexpr int kBatch = 16;  // loads in flight per thread before the adds
+  constexpr int kBatch = 32;  // loads in flight per thread before the adds
   for (int e = tid; e < dN; e += bs) {
     const double *src = J.ghist + e;
     double h = 0.0;
@@ -308,8 +308,10 @@ __global__ void __launch_bounds__(1024) vegas_refine_kernel(VegasArgs A) {
         m = 0.0;
       else if (r == 1.0)
         m = 1.0;
-      else
-        m = pow((r - 1.0) / log(r), 1.5);
+      else {
+        const double q = (r - 1.0) / log(r);
+        m = q * sqrt(q);  // q^1.5
+      }
       dd[k] = m;
       run += m;
     }
