@@ -132,16 +132,27 @@ def _roofline(cc, ctx, params):
     return out
 
 
+# the sources the DoSample kernel is compiled from
+KERNEL_SOURCES = ("vegas_sample.h", "vegas_sample_f32h64.hip", "philox.h", "genz.h",
+                  "engine.h", "vegas.h")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_1408_6373_amd", "csrc", name), "rb").read())
+    return h.hexdigest()
+
+
 def _traffic():
     """HBM bytes per DoSample launch from the committed PMC summary, if it was
     taken on the current kernel source."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", "vegas_dosample_d8_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    src = open(os.path.join(ROOT, "paper_1408_6373_amd", "csrc", "vegas.hip"), "rb").read()
-    if rec.get("kernel_source_sha256") != hashlib.sha256(src).hexdigest():
+    if rec.get("kernel_source_sha256") != kernel_source_hash():
         return None
     return rec.get("bytes_per_launch")
 
@@ -161,7 +172,6 @@ def summarize_pmc(fetch_csv, write_csv, out_path, commands):
     --traffic-probe run: FETCH_SIZE and WRITE_SIZE (KiB per dispatch, summed
     over the XCDs by rocprofv3), each scaled by what the same counter reads
     for the probe's 1 GiB device-to-device copy."""
-    import hashlib
     fetch, write = _read_pmc(fetch_csv), _read_pmc(write_csv)
     copy = "__amd_rocclr_copyBuffer"
     cf, cw = max(fetch.get(copy, [0])), max(write.get(copy, [0]))
@@ -185,8 +195,8 @@ def summarize_pmc(fetch_csv, write_csv, out_path, commands):
         f_avg, w_avg = sum(fk) / len(fk), sum(wk) / len(wk)
         rec[key] = {"dispatches": len(fk), "fetch_kib": f_avg, "write_kib": w_avg,
                     "bytes": 1024 * (f_avg * fs + w_avg * ws)}
-    src = open(os.path.join(ROOT, "paper_1408_6373_amd", "csrc", "vegas.hip"), "rb").read()
-    rec["kernel_source_sha256"] = hashlib.sha256(src).hexdigest()
+    rec["kernel_sources"] = list(KERNEL_SOURCES)
+    rec["kernel_source_sha256"] = kernel_source_hash()
     rec["bytes_per_launch"] = rec["dosample"]["bytes"]
     with open(out_path, "w") as f:
         json.dump(rec, f, indent=1)
