@@ -97,9 +97,10 @@ def _roofline(cc, ctx, params):
     ms = fold_ms = refine_ms = 0.0
     evals = launches = 0
     slots = 0.0
-    # the defaults at d = 8, 128 bins: FP64 LDS histogram, 2 points per lane
-    # per trip, 2 Philox blocks per point, power-of-two bin count, d = 4 x blocks
-    key = "f32h64_ilp2_nb2_pow2_full"
+    # the defaults at d = 8, 128 bins: fixed-point LDS histogram, 2 points per
+    # lane per trip, 2 Philox blocks per point, power-of-two bin count,
+    # d = 4 x blocks
+    key = "f32hfx_ilp2_nb2_pow2_full"
     for fam in FAMILIES:
         a, u = params[fam]
         cc.vegas(fam, a, u, ctx=ctx, flags=cc.FP32_EVAL, nbins=NBINS, nstart=NPTS,
@@ -114,7 +115,7 @@ def _roofline(cc, ctx, params):
         slots = None if (per is None or slots is None) else slots + per * st.evals
     ctx.config("profile", 0)
     n = max(launches, 1)
-    out = {"bound": "alu", "kernel": "vegas_dosample_kernel<float,double,2,2,true,true>",
+    out = {"bound": "alu", "kernel": "vegas_dosample_kernel<float,unsigned long long,2,2,true,true>",
            "unit": "T VALU-slots/s", "peak": PEAK_VALU / 1e12,
            "avg_launch_ms": ms / n, "launches": launches,
            "points_per_launch": evals / n,
@@ -133,7 +134,7 @@ def _roofline(cc, ctx, params):
 
 
 # the sources the DoSample kernel is compiled from
-KERNEL_SOURCES = ("vegas_sample.h", "vegas_sample_f32h64.hip", "philox.h", "genz.h",
+KERNEL_SOURCES = ("vegas_sample.h", "vegas_sample_f32hfx.hip", "philox.h", "genz.h",
                   "engine.h", "vegas.h")
 
 

@@ -99,7 +99,9 @@ int ccuba_shutdown(ccuba_ctx **ctx);
  * CUBAACCEL (Sect. 3.2.4).  Keys:
  *   "block"          DoSample threads per workgroup (64, 128 or 256)
  *   "blocks_per_cu"  persistent DoSample workgroups per compute unit (1..16)
- *   "hist64"         FP32 path: 1 = FP64 LDS histogram (default), 0 = FP32
+ *   "hist64"         FP32 path: 1 = FP64 LDS histogram, 0 = 64-bit fixed point
+ *                    for every v^2 it holds exactly, FP64 for the rest
+ *                    (default; same results up to summation order)
  *   "ilp"            points each lane carries per loop trip, 1 or 2 (default
  *                    2 for FP32, 1 for FP64; the key sets both)
  *   "min_tile"       smallest tile of points in a batched launch (>= 64)

@@ -153,7 +153,7 @@ int ccuba_init(ccuba_ctx **ctx, int device, size_t hbm_budget) {
     // measured best on gfx950: two points per lane for FP32, one for FP64
     c->tune[p].ilp = (int)env_ll("CCUBA_ILP", p == FP32 ? 2 : 1) == 2 ? 2 : 1;
   }
-  c->tune[FP32].hist64 = (int)env_ll("CCUBA_HIST64", 1);
+  c->tune[FP32].hist64 = (int)env_ll("CCUBA_HIST64", 0);
   c->use_graph = (int)env_ll("CCUBA_GRAPH", 1);
   c->autotune = (int)env_ll("CCUBA_AUTOTUNE", 0);
   c->serve_slots = (int)env_ll("CCUBA_SERVE_SLOTS", 256);

@@ -55,6 +55,11 @@ struct VState {
   double sum_zI;         // sum of I_t over iterations with sigma_t = 0
   int nzero;             // number of such iterations
   int pad;
+  // cap on v^2 for the next iteration's fixed-point histogram (FP32
+  // evaluation): 1024 times the mean v^2 of the last iteration, 0 before the
+  // first
+  float hcap;
+  int pad2;
 };
 
 __host__ __device__ inline int ngroups_of(int ntiles) { return (ntiles + kGroupTiles - 1) / kGroupTiles; }
@@ -66,7 +71,7 @@ enum { FLAG_FREEZE_GRID = 1 << 4 };
 struct VegasTune {
   int block = 256;        // threads per block
   int blocks_per_cu = 3;  // persistent blocks per compute unit
-  int hist64 = 1;         // FP32 path: 1 = FP64 LDS histogram, 0 = FP32
+  int hist64 = 0;         // FP32 path: 1 = FP64 LDS histogram, 0 = 64-bit fixed point
   int ilp = 1;            // points per lane per trip (1 or 2)
   int tiles_per_job = 0;  // 0 = automatic (one tile per persistent block)
   long long min_tile = 4096;

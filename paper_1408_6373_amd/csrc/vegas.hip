@@ -260,6 +260,7 @@ __global__ void __launch_bounds__(1024) vegas_refine_kernel(VegasArgs A) {
       st.chi2 = chi2;
       st.prob = st.dof > 0 ? gamma_p(0.5 * st.dof, 0.5 * chi2) : 0.0;
     }
+    st.hcap = (float)(1024.0 * (S2 / (double)n));
     *J.state = st;
     s_mode = conv ? 0 : ((J.flags & FLAG_FREEZE_GRID) ? 2 : 1);
   }
@@ -407,7 +408,7 @@ hipError_t launch_dosample(const VegasArgs &A, int prec, int nb, bool pow2, bool
   if (A.tile_count <= 0 || grid <= 0) return hipSuccess;
   if (prec == FP64) return launch_dosample_f64(A, nb, pow2, full, grid, block, lds, s);
   if (A.hist64) return launch_dosample_f32h64(A, nb, pow2, full, grid, block, lds, s);
-  return launch_dosample_f32h32(A, nb, pow2, full, grid, block, lds, s);
+  return launch_dosample_f32hfx(A, nb, pow2, full, grid, block, lds, s);
 }
 
 hipError_t launch_fold(const FoldArgs &F, bool level2, hipStream_t s) {
@@ -455,7 +456,7 @@ hipError_t set_kernel_limits() {
                                    (const void *)vegas_points_kernel<float>};
   dosample_fns_f64(fns);
   dosample_fns_f32h64(fns);
-  dosample_fns_f32h32(fns);
+  dosample_fns_f32hfx(fns);
   for (const void *f : fns)
     if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, big) != hipSuccess)
       (void)hipGetLastError();

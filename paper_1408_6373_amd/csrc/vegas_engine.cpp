@@ -110,7 +110,9 @@ void plan_tile_groups(std::vector<VJob> &jobs, std::vector<int> &tiles,
       for (int q = 0; q < J.ntiles; ++q) tiles.push_back(j);
       const size_t dN = (size_t)J.ndim * J.nbins;
       // LDS: one (lower edge, span) cell per bin, then the histogram
-      const size_t csz = p == FP64 ? 16 : 8, hsz = (p == FP64 || hist64) ? 8 : 4;
+      // (the fixed-point histogram has an FP64 one beside it for the values
+      // above its cap)
+      const size_t csz = p == FP64 ? 16 : 8, hsz = (p == FP32 && !hist64) ? 16 : 8;
       g.grid_bytes = std::max(g.grid_bytes, align16(dN * csz));
       hb = std::max(hb, dN * hsz);
       ref = std::max(ref, 2 * dN * 8);

@@ -5,6 +5,7 @@
 // its own translation unit (vegas_sample_*.hip), so that the instances build
 // in parallel; vegas.hip dispatches to them.
 #pragma once
+#include <type_traits>
 #include <vector>
 
 #include "engine.h"
@@ -118,24 +119,53 @@ __device__ __forceinline__ double pow2_scale<double>(int L) {
   return __longlong_as_double((long long)(1023 - 32 - L) << 52);
 }
 
+// ---------------------------------------------------------------------------
+// a6 with FP32 evaluation: the histogram in 64-bit fixed point, exactly.
+//
+// LDS integer adds are several times cheaper than FP64 adds on gfx950 (and
+// FP32 LDS atomics far slower still).  With FP32 evaluation every v^2 has a
+// 24-bit mantissa, so a v^2 that is a whole multiple of a unit 2^(E-62) goes
+// into an unsigned 64-bit sum without any rounding; 2^E bounds the tile's
+// total of every bin, so the sums cannot overflow, and integer sums do not
+// depend on the order of the adds.  Every other v^2 -- too small to be a
+// whole multiple of the unit, above the cap, or not finite -- goes to a
+// second, FP64 histogram, as on the FP64 path.  The two are added when the
+// tile is written, so the tile's histogram is the FP64 one up to rounding
+// order: the split changes speed, not results.
+//
+// The bound is 2^E >= 4 cnt c for the tile's cnt points and a cap c on the
+// v^2 that may enter the fixed-point sums.  In an integral's first
+// iteration c is a true bound from the staged grid and the integrand's
+// maximum: w <= prod_j max_k (N width_jk), and f <= 1 for every family except
+// the product peak, where f <= 1 / prod_j a_j^-2 (the FP32 products are
+// formed in the order the point's own products are, so rounding keeps them
+// bounds).  Once the grid adapts that bound grows far beyond the values that
+// occur (it takes every dimension's widest bin), so later iterations take
+// c = 1024 times the mean v^2 of the previous one (at most 1 in 1024 of the
+// v^2 exceed that).
+
+template <typename HT>
+struct FixedHist : std::false_type {};
+template <>
+struct FixedHist<unsigned long long> : std::true_type {};
+
 // Sample the points [i0, i0 + cnt) of one tile; lane sums go to S1, S2.
 // NB = ceil(d/4) Philox blocks per point is a template argument so that the
 // per-dimension loop is fully unrolled with only the last block guarded, and
 // FULL (d = 4 NB) drops that guard too.
 // Each lane carries ILP independent points per trip (q, q + blockDim, ...),
 // so that several Philox chains are in flight; a point past the tile end is
-// computed (its LDS reads stay in range) but contributes nothing.  All lanes
-// run the same number of trips (a build in which lanes left the loop on
-// different trips, holding deferred updates, produced wrong histograms in
-// partially filled tiles).  The
-// histogram updates of a trip are issued in the next trip, after its grid
-// reads, so that those reads never wait behind the atomics in the LDS queue.
+// computed (its LDS reads stay in range) but contributes nothing.  A trip's
+// histogram updates are issued at its end, so that the LDS works through
+// them while the next trip's Philox rounds run; the next trip's wait for its
+// grid reads then finds them done.  (Updates deferred to after the next
+// trip's grid reads made every such wait also wait for the updates.)
 template <typename T, typename HT, int FAM, int NB, int ILP, bool POW2, bool FULL>
 __device__ __forceinline__ void sample_tile(const VJob &J, int t, long long i0, int cnt,
                                             const Cell<T> *__restrict__ sC, HT *sH,
                                             const T *__restrict__ p0,
-                                            const T *__restrict__ p1, double &S1,
-                                            double &S2) {
+                                            const T *__restrict__ p1, int E, float cap,
+                                            double *sHx, double &S1, double &S2) {
   constexpr int ND = 4 * NB;
   const int d = J.ndim, N = J.nbins;
   const T Nt = (T)N;
@@ -151,20 +181,13 @@ __device__ __forceinline__ void sample_tile(const VJob &J, int t, long long i0, 
   }
   const T phase0 = p1[0];
   const int bs = blockDim.x;
-  int pidx[ILP][ND];  // pending histogram slots of the previous trip
-  HT pv[ILP];         // and their value (v^2), 0 for no update
-  bool pending = false;
   // an assembly comment naming the family, so that the per-point loop that
   // follows can be found in the assembly listing (it emits no instruction)
   asm volatile("; ccuba sample_tile family %0" ::"n"(FAM));
-  // every lane runs the same number of trips; points past the tile end are
-  // predicated off, so no lane leaves the loop while it holds pending updates
-  const int trips = (cnt + ILP * bs - 1) / (ILP * bs);
-  for (int tr = 0; tr < trips; ++tr) {
-    const int q0 = tr * ILP * bs + (int)threadIdx.x;
+  for (int q0 = threadIdx.x; q0 < cnt; q0 += ILP * bs) {
     T fr[ILP][ND], lo[ILP][ND], sp[ILP][ND];
     int idx[ILP][ND];
-    // words, bins and the grid edges they select
+    // words, bins and the grid cells they select
 #pragma unroll
     for (int e = 0; e < ILP; ++e) {
       const uint32_t i = (uint32_t)(i0 + q0 + e * bs);
@@ -189,18 +212,7 @@ __device__ __forceinline__ void sample_tile(const VJob &J, int t, long long i0, 
         }
       }
     }
-    // the previous trip's histogram updates
-    if (pending) {
-#pragma unroll
-      for (int e = 0; e < ILP; ++e) {
-        if (pv[e] != (HT)0) {
-#pragma unroll
-          for (int j = 0; j < ND; ++j)
-            if (FULL || j < 4 * (NB - 1) || j < d) unsafeAtomicAdd(&sH[pidx[e][j]], pv[e]);
-        }
-      }
-    }
-    // weights, integrand, sums
+    // weights, integrand, sums, histogram updates
 #pragma unroll
     for (int e = 0; e < ILP; ++e) {
       T w = (T)1;
@@ -211,25 +223,34 @@ __device__ __forceinline__ void sample_tile(const VJob &J, int t, long long i0, 
           const T x = fma_t(fr[e][j], sp[e][j], lo[e][j]);
           w = POW2 ? w * sp[e][j] : w * (Nt * sp[e][j]);
           acc = Genz<T, FAM>::step(acc, x, pp0[j], pp1[j]);
-          pidx[e][j] = idx[e][j];
         }
       }
       const T v = w * Genz<T, FAM>::finish(acc, d);
-      const bool valid = q0 + e * bs < cnt;  // also false for q0 >= cnt
-      const double vd = valid ? (double)v : 0.0;
-      S1 += vd;
-      S2 = fma(vd, vd, S2);
-      pv[e] = valid ? (HT)(v * v) : (HT)0;
-    }
-    pending = true;
-  }
-  if (pending) {
+      if (q0 + e * bs < cnt) {
+        S1 += (double)v;
+        S2 = fma((double)v, (double)v, S2);
+        if constexpr (FixedHist<HT>::value) {
+          const float v2f = (float)(v * v);
+          const uint32_t b = __float_as_uint(v2f);
+          const int sh = (int)(b >> 23) - (88 + E);  // v2 = m 2^sh units
+          if (v2f <= cap && sh >= 0) {
+            const unsigned long long v2 = (unsigned long long)((b & 0x7FFFFFu) | 0x800000u)
+                                          << sh;
 #pragma unroll
-    for (int e = 0; e < ILP; ++e) {
-      if (pv[e] != (HT)0) {
+            for (int j = 0; j < ND; ++j)
+              if (FULL || j < 4 * (NB - 1) || j < d) atomicAdd(&sH[idx[e][j]], v2);
+          } else {  // not a whole multiple of the unit, above the cap, or not finite
+            const double v2 = (double)v2f;
 #pragma unroll
-        for (int j = 0; j < ND; ++j)
-          if (FULL || j < 4 * (NB - 1) || j < d) unsafeAtomicAdd(&sH[pidx[e][j]], pv[e]);
+            for (int j = 0; j < ND; ++j)
+              if (FULL || j < 4 * (NB - 1) || j < d) unsafeAtomicAdd(&sHx[idx[e][j]], v2);
+          }
+        } else {
+          const HT v2 = (HT)(v * v);
+#pragma unroll
+          for (int j = 0; j < ND; ++j)
+            if (FULL || j < 4 * (NB - 1) || j < d) unsafeAtomicAdd(&sH[idx[e][j]], v2);
+        }
       }
     }
   }
@@ -244,6 +265,7 @@ template <typename T, typename HT, int ILP, int NB, bool POW2, bool FULL>
 __global__ void __launch_bounds__(256) vegas_dosample_kernel(VegasArgs A) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red[2][4];
+  __shared__ uint32_t smax[kMaxDim + 2];  // fixed-point histogram: per-dimension maxima, E, cap
   Cell<T> *sC = (Cell<T> *)smem;
   HT *sH = (HT *)(smem + A.lds_hist_byte_off);
   const int tid = threadIdx.x, bs = blockDim.x, lane = tid & 63, wid = tid >> 6;
@@ -268,17 +290,61 @@ __global__ void __launch_bounds__(256) vegas_dosample_kernel(VegasArgs A) {
 
     stage_cells<T, POW2>(J.grid + (long long)(st.T & 1) * d * row, d, N, sC);
     for (int e = tid; e < dN; e += bs) sH[e] = (HT)0;
+    double *sHx = (double *)(sH + dN);  // fixed point: the FP64 histogram above the cap
+    if constexpr (FixedHist<HT>::value) {
+      for (int e = tid; e < dN; e += bs) sHx[e] = 0.0;
+      if (tid <= kMaxDim) smax[tid] = 0u;
+    }
     __syncthreads();
 
     const T *p0 = param_ptr<T>(J, 0);
     const T *p1 = param_ptr<T>(J, 1);
+    int E = 0;
+    float cap = 0.0f;
+    if constexpr (FixedHist<HT>::value) {
+      const float prev = st.hcap;
+      if (!(prev > 0.0f)) {
+        // first iteration: per dimension the largest weight factor
+        // (positive floats order as their bit patterns)
+        const T Nt = (T)N;
+        for (int e = tid; e < dN; e += bs) {
+          const T f = POW2 ? sC[e].span : Nt * sC[e].span;
+          atomicMax(&smax[e / N], __float_as_uint((float)f));
+        }
+        __syncthreads();
+      }
+      if (tid == 0) {
+        float cv;
+        if (prev > 0.0f) {
+          cv = prev;
+        } else {
+          float w = 1.0f, q = 1.0f;
+          for (int j = 0; j < d; ++j) w = w * __uint_as_float(smax[j]);
+          if (J.family == PRODUCT_PEAK) {
+            for (int j = 0; j < d; ++j) q = q * (float)p0[j];
+            q = 1.0f / q;
+          }
+          const float v = w * q;
+          cv = v * v;
+        }
+        // 2^E >= 4 cnt c bounds the fixed-point total of every bin
+        const double B = 4.0 * (double)cv * (double)(cnt > 0 ? cnt : 1);
+        int ex = 0;
+        (void)frexp(B, &ex);
+        smax[kMaxDim] = (uint32_t)ex;
+        smax[kMaxDim + 1] = __float_as_uint(cv);
+      }
+      __syncthreads();
+      E = (int)smax[kMaxDim];
+      cap = __uint_as_float(smax[kMaxDim + 1]);
+    }
     double S1 = 0.0, S2 = 0.0;
     switch (J.family) {
-      case GAUSSIAN: sample_tile<T, HT, GAUSSIAN, NB, ILP, POW2, FULL>(J, st.T, i0, cnt, sC, sH, p0, p1, S1, S2); break;
-      case OSCILLATORY: sample_tile<T, HT, OSCILLATORY, NB, ILP, POW2, FULL>(J, st.T, i0, cnt, sC, sH, p0, p1, S1, S2); break;
-      case PRODUCT_PEAK: sample_tile<T, HT, PRODUCT_PEAK, NB, ILP, POW2, FULL>(J, st.T, i0, cnt, sC, sH, p0, p1, S1, S2); break;
-      case CORNER_PEAK: sample_tile<T, HT, CORNER_PEAK, NB, ILP, POW2, FULL>(J, st.T, i0, cnt, sC, sH, p0, p1, S1, S2); break;
-      default: sample_tile<T, HT, C0, NB, ILP, POW2, FULL>(J, st.T, i0, cnt, sC, sH, p0, p1, S1, S2); break;
+      case GAUSSIAN: sample_tile<T, HT, GAUSSIAN, NB, ILP, POW2, FULL>(J, st.T, i0, cnt, sC, sH, p0, p1, E, cap, sHx, S1, S2); break;
+      case OSCILLATORY: sample_tile<T, HT, OSCILLATORY, NB, ILP, POW2, FULL>(J, st.T, i0, cnt, sC, sH, p0, p1, E, cap, sHx, S1, S2); break;
+      case PRODUCT_PEAK: sample_tile<T, HT, PRODUCT_PEAK, NB, ILP, POW2, FULL>(J, st.T, i0, cnt, sC, sH, p0, p1, E, cap, sHx, S1, S2); break;
+      case CORNER_PEAK: sample_tile<T, HT, CORNER_PEAK, NB, ILP, POW2, FULL>(J, st.T, i0, cnt, sC, sH, p0, p1, E, cap, sHx, S1, S2); break;
+      default: sample_tile<T, HT, C0, NB, ILP, POW2, FULL>(J, st.T, i0, cnt, sC, sH, p0, p1, E, cap, sHx, S1, S2); break;
     }
     S1 = wave_sum(S1);
     S2 = wave_sum(S2);
@@ -297,7 +363,11 @@ __global__ void __launch_bounds__(256) vegas_dosample_kernel(VegasArgs A) {
       J.tsums[2 * lt + 1] = b;
     }
     double *th = J.thist + (long long)lt * dN;
-    for (int e = tid; e < dN; e += bs) th[e] = (double)sH[e];
+    if constexpr (FixedHist<HT>::value) {
+      for (int e = tid; e < dN; e += bs) th[e] = ldexp((double)sH[e], E - 62) + sHx[e];
+    } else {
+      for (int e = tid; e < dN; e += bs) th[e] = (double)sH[e];
+    }
 
     __syncthreads();
   }

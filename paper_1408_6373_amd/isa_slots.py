@@ -53,13 +53,30 @@ def _ops(lines):
     return out
 
 
+def _drop_fallback(lines):
+    """The fixed-point histogram kernels send the rare v^2 that cannot be
+    summed exactly in fixed point to an FP64 histogram; drop the basic blocks
+    of that path (those holding its FP64 LDS adds), which a point takes only
+    in that case, so that the count is the path every other point takes."""
+    blocks, cur = [], []
+    for l in lines:
+        if re.match(r"^(\.LBB\w+:|; %bb\.)", l) and cur:
+            blocks.append(cur)
+            cur = []
+        cur.append(l)
+    if cur:
+        blocks.append(cur)
+    return [l for blk in blocks if not any("ds_add_f64" in x for x in blk) for l in blk]
+
+
 def count(asm_text):
     """{kernel instance: {family: slots per point}} from gfx950 assembly.
 
     Each family's per-point loop follows an assembly comment that the kernel
     source places just before it ("ccuba sample_tile family F"); the loop is
     the largest backward-branch region between that comment and the next
-    one that holds no comment itself."""
+    one that holds no comment itself (a backward branch, conditional or not,
+    closes a loop region)."""
     res = {}
     for kern in re.findall(r"^(_ZN5ccuba21vegas_dosample_kernelI\w+):", asm_text, re.M):
         m = re.search(r"kernelI(\w)(\w)Li(\d)ELi(\d)ELb(\d)ELb(\d)E", kern)
@@ -78,7 +95,7 @@ def count(asm_text):
                 marks.append((i, int(mm.group(1))))
         loops = []
         for i, l in enumerate(body):
-            mm = re.match(r"\s+s_cbranch_\w+\s+(\.LBB\w+)", l)
+            mm = re.match(r"\s+s_(?:cbranch_\w+|branch)\s+(\.LBB\w+)", l)
             if mm and mm.group(1) in labels and labels[mm.group(1)] < i:
                 loops.append((labels[mm.group(1)], i))
         fam_slots = {}
@@ -88,12 +105,15 @@ def count(asm_text):
             for a, b in loops:
                 if not (mline < a < nxt) or any(a <= ml <= b for ml, _ in marks):
                     continue
-                v = [o for o in _ops(body[a:b + 1]) if o.startswith("v_")]
+                lines = body[a:b + 1]
+                if H == "y":
+                    lines = _drop_fallback(lines)
+                v = [o for o in _ops(lines) if o.startswith("v_")]
                 if best is None or len(v) > len(best):
                     best = v
             if best:
                 fam_slots[FAMILIES[fam]] = sum(_weight(o) for o in best) / int(ilp)
-        key = "%s%s_ilp%s_nb%s%s%s" % ({"f": "f32", "d": "f64"}[T], {"f": "h32", "d": "h64"}[H],
+        key = "%s%s_ilp%s_nb%s%s%s" % ({"f": "f32", "d": "f64"}[T], {"y": "hfx", "d": "h64"}[H],
                                        ilp, nb, "_pow2" if pow2 == "1" else "",
                                        "_full" if full == "1" else "")
         res[key] = fam_slots

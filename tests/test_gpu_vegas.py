@@ -107,12 +107,18 @@ def test_families_fp64(cc, ctx, fam, d):
     _assert_vegas_close(g, o, 1e-12)
 
 
+@pytest.mark.parametrize("hist64", [0, 1])
 @pytest.mark.parametrize("fam", range(5))
-def test_families_fp32_eval(cc, ctx, fam):
+def test_families_fp32_eval(cc, fam, hist64):
+    # both FP32-path histograms: 64-bit fixed point (with FP64 for the rest)
+    # and FP64
     d = 5
     a, u = W.genz_params(fam, d, 4)
-    g = cc.vegas(fam, a, u, ctx=ctx, flags=cc.FP32_EVAL, nbins=128, nstart=30000,
+    c = cc.Context()
+    c.config("hist64", hist64)
+    g = cc.vegas(fam, a, u, ctx=c, flags=cc.FP32_EVAL, nbins=128, nstart=30000,
                  maxeval=6 * 30000, seed=3, trace=True)
+    c.close()
     o32 = O.vegas(O.genz(fam, a, u, precision=O.FP32_EVAL), d, flags=O.FP32_EVAL, nbins=128,
                   nstart=30000, maxeval=6 * 30000, seed=3)
     o64 = O.vegas(O.genz(fam, a, u), d, nbins=128, nstart=30000, maxeval=6 * 30000, seed=3)
@@ -153,6 +159,26 @@ def test_extreme_dims_and_bins(cc, ctx, d, N, prec):
         assert g["neval"] == o["neval"]
         assert _rel(g["integral"], o["integral"]) < 1e-6
         assert _rel(g["error"], o["error"]) < 1e-5
+
+
+@pytest.mark.parametrize("fam,d,N", [(0, 5, 128), (2, 8, 128), (1, 12, 50), (4, 3, 256)])
+def test_fixed_point_histogram_equals_fp64_histogram(cc, fam, d, N):
+    # The fixed-point histogram sums exactly what it holds and sends every
+    # other v^2 to an FP64 histogram, so the two FP32-path histograms differ
+    # by summation order only: the runs agree to FP64 rounding.
+    a, u = W.genz_params(fam, d, 6)
+    out = []
+    for h in (1, 0):
+        c = cc.Context()
+        c.config("hist64", h)
+        out.append(cc.vegas(fam, a, u, ctx=c, flags=cc.FP32_EVAL, nbins=N, nstart=50021,
+                            maxeval=8 * 50021, seed=5, trace=True))
+        c.close()
+    r64, rfx = out
+    assert rfx["neval"] == r64["neval"]
+    assert _rel(rfx["integral"], r64["integral"]) < 1e-12
+    assert _rel(rfx["error"], r64["error"]) < 1e-11
+    assert np.max(np.abs(rfx["grid"] - r64["grid"])) < 1e-12
 
 
 def test_zero_variance_frozen_grid(cc, ctx):
