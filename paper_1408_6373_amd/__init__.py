@@ -238,22 +238,66 @@ def vegas_dosample_raw(ctx, family, a, u, nbins, iteration, npts, grid_ptr, sums
            "ccuba_vegas_dosample_raw")
 
 
+def _struct_dtype(st):
+    """numpy dtype with the layout of a ctypes structure (pointers as uint64)."""
+    names, formats, offsets = [], [], []
+    for name, typ in st._fields_:
+        if isinstance(typ, type) and issubclass(typ, C.Structure):
+            fmt = _struct_dtype(typ)
+        elif hasattr(typ, "contents"):
+            fmt = np.uint64
+        else:
+            fmt = np.dtype(typ)
+        names.append(name)
+        formats.append(fmt)
+        offsets.append(getattr(st, name).offset)
+    return np.dtype(dict(names=names, formats=formats, offsets=offsets,
+                         itemsize=C.sizeof(st)))
+
+
+_JOB_DTYPE = _struct_dtype(Job)
+
+
 def make_jobs(specs):
     """Build a ctypes Job array from dicts (method, ndim, family, a, u, epsrel,
     epsabs, flags, seed, stream_id, mineval, maxeval, nstart, nincrease,
-    nbins, max_regions_per_batch)."""
-    arr = (Job * len(specs))()
-    keep = []
+    nbins, max_regions_per_batch).  Returns (array, keep): keep holds the
+    parameter arrays the jobs point into and must outlive the call."""
+    n = len(specs)
+    dmax = max((len(s["a"]) for s in specs), default=1)
+    A = np.zeros((max(n, 1), dmax))
+    U = np.zeros((max(n, 1), dmax))
+    nd = np.zeros(n, dtype=np.int32)
     for q, s in enumerate(specs):
-        f, k = _integrand(s["family"], s["a"], s["u"])
-        keep.append(k)
-        arr[q] = Job(int(s.get("method", 0)), len(k[0]), f, float(s.get("epsrel", 0.0)),
-                     float(s.get("epsabs", 0.0)), int(s.get("flags", 0)), int(s.get("seed", 1)),
-                     int(s.get("stream_id", 0)), int(s.get("mineval", 0)),
-                     int(s.get("maxeval", 10**5)), int(s.get("nstart", 10**4)),
-                     int(s.get("nincrease", 0)), int(s.get("nbins", 128)),
-                     int(s.get("max_regions_per_batch", 0)))
-    return arr, keep
+        a, u = _f64(s["a"]), _f64(s["u"])
+        if len(u) != len(a):
+            raise ValueError("a and u differ in length")
+        nd[q] = len(a)
+        A[q, :len(a)] = a
+        U[q, :len(u)] = u
+    rec = np.zeros(n, dtype=_JOB_DTYPE)
+
+    def col(key, dflt, typ=int):
+        return np.fromiter((typ(s.get(key, dflt)) for s in specs), dtype=np.float64 if typ is float
+                           else np.int64, count=n)
+    rec["method"] = col("method", 0)
+    rec["ndim"] = nd
+    rec["f"]["family"] = np.fromiter((int(s["family"]) for s in specs), dtype=np.int64, count=n)
+    rec["f"]["a"] = A.ctypes.data + np.arange(n, dtype=np.uint64) * (8 * dmax)
+    rec["f"]["u"] = U.ctypes.data + np.arange(n, dtype=np.uint64) * (8 * dmax)
+    rec["epsrel"] = col("epsrel", 0.0, float)
+    rec["epsabs"] = col("epsabs", 0.0, float)
+    rec["flags"] = col("flags", 0)
+    rec["seed"] = np.fromiter((int(s.get("seed", 1)) for s in specs), dtype=np.uint64, count=n)
+    rec["stream_id"] = col("stream_id", 0)
+    rec["mineval"] = col("mineval", 0)
+    rec["maxeval"] = col("maxeval", 10**5)
+    rec["nstart"] = col("nstart", 10**4)
+    rec["nincrease"] = col("nincrease", 0)
+    rec["nbins"] = col("nbins", 128)
+    rec["max_regions_per_batch"] = col("max_regions_per_batch", 0)
+    arr = (Job * n).from_buffer(rec)
+    return arr, (A, U, rec)
 
 
 def _result_dict(r):
@@ -263,9 +307,11 @@ def _result_dict(r):
 
 
 def vegas_batch(ctx, specs):
-    arr, keep = make_jobs(specs)
-    out = (Result * len(specs))()
-    _check(_lib.ccuba_vegas_batch(ctx.handle, len(specs), arr, out), "ccuba_vegas_batch")
+    """Many independent Vegas integrals in one engine.  specs: a list of job
+    dicts (see make_jobs), or the (array, keep) pair make_jobs returns."""
+    arr, keep = specs if isinstance(specs, tuple) else make_jobs(specs)
+    out = (Result * len(arr))()
+    _check(_lib.ccuba_vegas_batch(ctx.handle, len(arr), arr, out), "ccuba_vegas_batch")
     return [_result_dict(r) for r in out]
 
 

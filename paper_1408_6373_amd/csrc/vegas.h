@@ -60,6 +60,8 @@ void dosample_fns_f32hfx(std::vector<const void *> &fns);
 // (group rows -> hsum), which only the raw DoSample entry point needs.
 hipError_t launch_fold(const FoldArgs &F, bool level2, hipStream_t s);
 hipError_t launch_refine(const VegasArgs &A, int njobs, size_t lds, hipStream_t s);
+// Uniform starting grids (both copies) of jobs[0, njobs) (device table).
+hipError_t launch_init_grids(const VJob *jobs, int njobs, hipStream_t s);
 hipError_t launch_collect(const VegasArgs &A, int njobs, double *sums, double *hist,
                           hipStream_t s);
 hipError_t launch_points(const PointsArgs &P, hipStream_t s);

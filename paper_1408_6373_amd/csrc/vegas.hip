@@ -345,6 +345,14 @@ __global__ void __launch_bounds__(1024) vegas_refine_kernel(VegasArgs A) {
   }
 }
 
+// Uniform starting grids, E_j[k] = k/N in both copies, one workgroup per job
+// (the same division the host would do, so the grids are the same).
+__global__ void __launch_bounds__(256) vegas_init_grids_kernel(const VJob *jobs) {
+  const VJob &J = jobs[blockIdx.x];
+  const int N = J.nbins, row = N + 1, tot = 2 * J.ndim * row;
+  for (int e = threadIdx.x; e < tot; e += blockDim.x) J.grid[e] = (double)(e % row) / N;
+}
+
 // Copy out every job's folded iteration totals: sums[2] and hist[d*N]; used by
 // the raw DoSample entry point.
 __global__ void __launch_bounds__(256) vegas_collect_kernel(VegasArgs A, double *sums,
@@ -423,6 +431,12 @@ hipError_t launch_fold(const FoldArgs &F, bool level2, hipStream_t s) {
 hipError_t launch_refine(const VegasArgs &A, int njobs, size_t lds, hipStream_t s) {
   // one wavefront per dimension (up to 16)
   hipLaunchKernelGGL(vegas_refine_kernel, dim3(njobs), dim3(1024), lds, s, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_grids(const VJob *jobs, int njobs, hipStream_t s) {
+  if (njobs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(vegas_init_grids_kernel, dim3(njobs), dim3(256), 0, s, jobs);
   return hipGetLastError();
 }
 

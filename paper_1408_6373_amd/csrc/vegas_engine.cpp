@@ -273,17 +273,11 @@ int VegasEngine::setup(const std::vector<VegasSpec> &specs, bool single, hipStre
     J.p64 = p64_.p + (size_t)j * 2 * kParamRow;
     J.p32 = p32_.p + (size_t)j * 2 * kParamRow;
   }
-  std::vector<double> grids(goff), p64((size_t)n * 2 * kParamRow);
+  std::vector<double> p64((size_t)n * 2 * kParamRow);
   std::vector<float> p32((size_t)n * 2 * kParamRow);
   std::vector<VState> st(n);
   for (int j = 0; j < n; ++j) {
     const VegasSpec &sp = specs[j];
-    const int N = sp.nbins, row = N + 1;
-    for (int c = 0; c < 2; ++c)
-      for (int d = 0; d < sp.ndim; ++d)
-        for (int k = 0; k <= N; ++k)
-          grids[off[j].grid + (long long)c * sp.ndim * row + (long long)d * row + k] =
-              (double)k / N;
     double a64[2][kParamRow];
     float a32[2][kParamRow];
     genz_constants(sp, a64, a32);
@@ -296,9 +290,10 @@ int VegasEngine::setup(const std::vector<VegasSpec> &specs, bool single, hipStre
     }
   }
   if ((rc = upload(jobs_, hjobs_, s)) || (rc = upload(tile_job_, tile_job, s)) ||
-      (rc = upload(grids_, grids, s)) || (rc = upload(p64_, p64, s)) ||
-      (rc = upload(p32_, p32, s)) || (rc = upload(state_, st, s)))
+      (rc = upload(p64_, p64, s)) || (rc = upload(p32_, p32, s)) ||
+      (rc = upload(state_, st, s)))
     return rc;
+  CCUBA_HIP(launch_init_grids(jobs_.p, n, s));
   std::vector<long long> ends;
   fold_tasks(hjobs_, ends, &fold_total_, &fold_total2_);
   if ((rc = upload(fold_end_, ends, s))) return rc;
