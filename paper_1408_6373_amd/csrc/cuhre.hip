@@ -302,22 +302,43 @@ __global__ void __launch_bounds__(256) sel_hist_kernel(const double *err, long l
   if (lh[threadIdx.x]) atomicAdd(&hist[threadIdx.x], lh[threadIdx.x]);
 }
 
-__global__ void sel_pick_kernel(unsigned long long *prefix, long long *krem, unsigned *hist,
-                                int shift) {
-  if (threadIdx.x == 0) {
-    long long need = krem[0];
-    int dg = 255;
-    for (; dg > 0; --dg) {
-      const long long c = hist[dg];
-      if (c >= need) break;
-      need -= c;
-    }
-    krem[0] = need;
-    prefix[0] |= (unsigned long long)dg << shift;
-    prefix[1] |= 255ull << shift;
+// One workgroup of 256 threads: the digit of the K-th largest key among the
+// keys with the current prefix, from the pass's histogram.  Thread t holds
+// digit 255 - t; an inclusive scan over threads gives, for each digit, the
+// count of keys at or above it.  The digit is the top one where that count
+// reaches the remaining need, or 0 if none does; the need left within it is
+// the need less the keys above it.
+__global__ void __launch_bounds__(256) sel_pick_kernel(unsigned long long *prefix,
+                                                       long long *krem, unsigned *hist,
+                                                       int shift) {
+  __shared__ long long wsum[4];
+  __shared__ int s_dg;
+  __shared__ long long s_need;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int dg = 255 - t;
+  const long long need = krem[0];
+  const long long c = hist[dg];
+  hist[dg] = 0u;  // ready for the next pass
+  long long incl = c;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const long long v = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += v;
+  }
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  for (int q = 0; q < w; ++q) incl += wsum[q];
+  const long long excl = incl - c;  // keys above this digit
+  if (excl < need && (incl >= need || dg == 0)) {  // exactly one thread
+    s_dg = dg;
+    s_need = need - excl;
   }
   __syncthreads();
-  for (int q = threadIdx.x; q < 256; q += blockDim.x) hist[q] = 0u;
+  if (t == 0) {
+    krem[0] = s_need;
+    prefix[0] |= (unsigned long long)s_dg << shift;
+    prefix[1] |= 255ull << shift;
+  }
 }
 
 // flag[i] = key > threshold, or key == threshold and among the first krem

@@ -84,7 +84,7 @@ int CuhreRun::alloc_store(CRegions &R, DevBuf<double> &cb, DevBuf<double> &hb,
 // Grow both stores to hold `need' regions, keeping the leaves in store cur_.
 int CuhreRun::ensure(long long need, hipStream_t s) {
   if (need <= cap_) return CCUBA_OK;
-  long long cap = std::max<long long>(cap_ * 2, need);
+  long long cap = std::max<long long>(cap_ * 4, need);
   const long long limit = spec_.maxeval / np_ + 2;  // no run can hold more regions
   cap = std::max(need, std::min(cap, limit));
   const int d = spec_.ndim;
@@ -158,8 +158,11 @@ int CuhreRun::start(const CuhreSpec &spec, hipStream_t s) {
   S_.prefix = prefix_.p;
   S_.krem = krem_.p;
   S_.hist = hist_.p;
+  // room for the first few batches, so that the store rarely grows (growing
+  // means new allocations and a copy)
   const long long first_cap = std::max<long long>(
-      16, std::min<long long>(std::min<long long>(spec.batch + 1, 1 << 20), spec.maxeval / np_ + 2));
+      16, std::min<long long>(std::min<long long>(4 * spec.batch + 1, 1 << 22),
+                              spec.maxeval / np_ + 2));
   // initial stores
   if ((rc = alloc_store(R_[0], c_[0], h_[0], vals_[0], axis_[0], id_[0], first_cap)) ||
       (rc = alloc_store(R_[1], c_[1], h_[1], vals_[1], axis_[1], id_[1], first_cap)))
