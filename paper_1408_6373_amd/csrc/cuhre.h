@@ -23,10 +23,11 @@ struct CSeg {
 };
 
 struct RuleArgs {
-  const CSeg *segs;
+  const CSeg *segs;          // device table (nseg > 1)
   int nseg;
   const long long *seg_end;  // inclusive prefix sums of the segment counts
   long long total;
+  CSeg one;                  // the segment itself when nseg == 1 (no table)
   const double *w7, *w5;     // [ndim][5] rule weights (rows 0..16)
   double l2, l3, l4, l5;
 };

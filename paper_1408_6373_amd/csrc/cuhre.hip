@@ -27,6 +27,8 @@ namespace ccuba {
 
 namespace {
 
+constexpr int kLaneRuleMaxDim = 8;          // lane-per-region rule up to this d
+constexpr long long kLaneRuleMinRegions = 16384;  // and from this many regions on
 constexpr int kScanItems = 4;
 constexpr int kScanBlock = 256;
 constexpr int kScanTile = kScanItems * kScanBlock;  // elements per scan block
@@ -175,7 +177,123 @@ __device__ void rule_region(const RuleArgs &A, const CSeg &S, long long r, int w
   }
 }
 
+// One lane per region, for a single integral of dimension D <= 8: every lane
+// takes the rule points in the same order, so the point's class and axes are
+// the same across the wavefront (decoded once, in scalar registers) and only
+// the region's centre and widths differ.  The point values are the same
+// arithmetic as rule_point_f; the class sums are taken in point order.
+template <int FAM, int D>
+__device__ __forceinline__ double lane_point(const double (&c)[D], const double (&h)[D],
+                                             const double *p0, const double *p1,
+                                             double phase0, int i, bool ni, int jj, bool nj,
+                                             double lam) {
+  double acc = Genz<double, FAM>::init(phase0);
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    double x = c[j];
+    if (j == i || j == jj) {
+      const double t = lam * h[j];
+      const bool neg = j == i ? ni : nj;
+      x = neg ? x - t : x + t;
+    }
+    acc = Genz<double, FAM>::step(acc, x, p0[j], p1[j]);
+  }
+  return Genz<double, FAM>::finish(acc, D);
+}
+
+template <int FAM, int D>
+__device__ void rule_region_lane(const RuleArgs &A, const CSeg &S, long long r) {
+  const long long cap = S.regs.cap;
+  double c[D], h[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    c[j] = S.regs.c[j * cap + r];
+    h[j] = S.regs.h[j * cap + r];
+  }
+  const double *p0 = S.par;
+  const double *p1 = S.par + kParamRow;
+  const double phase0 = p1[0];
+  double Sk[5];
+  // class 0: the centre
+  const double f0 = lane_point<FAM, D>(c, h, p0, p1, phase0, -1, false, -1, false, 0.0);
+  Sk[0] = f0;
+  // classes 1 and 2: +-lambda on one axis; the fourth differences
+  double s1 = 0.0, s2 = 0.0, Dmax = -1.0;
+  int best = 0;
+  double a2[D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    const double fp = lane_point<FAM, D>(c, h, p0, p1, phase0, i, false, -1, false, A.l2);
+    const double fm = lane_point<FAM, D>(c, h, p0, p1, phase0, i, true, -1, false, A.l2);
+    s1 += fp;
+    s1 += fm;
+    a2[i] = fp + fm - 2.0 * f0;
+  }
+  const double ratio = (A.l2 * A.l2) / (A.l3 * A.l3);
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    const double fp = lane_point<FAM, D>(c, h, p0, p1, phase0, i, false, -1, false, A.l3);
+    const double fm = lane_point<FAM, D>(c, h, p0, p1, phase0, i, true, -1, false, A.l3);
+    s2 += fp;
+    s2 += fm;
+    const double a3 = fp + fm - 2.0 * f0;
+    const double Dj = fabs(a2[i] - ratio * a3);
+    if (Dj > Dmax) {  // strictly greater: the lowest axis wins ties
+      Dmax = Dj;
+      best = i;
+    }
+  }
+  Sk[1] = s1;
+  Sk[2] = s2;
+  // class 3: +-lambda4 on two axes i < jj
+  double s3 = 0.0;
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int jj = i + 1; jj < D; ++jj)
+#pragma unroll
+      for (int sg = 0; sg < 4; ++sg)
+        s3 += lane_point<FAM, D>(c, h, p0, p1, phase0, i, sg & 1, jj, (sg >> 1) & 1, A.l4);
+  Sk[3] = s3;
+  // class 4: every corner at +-lambda5
+  double s4 = 0.0;
+  for (unsigned sg = 0; sg < (1u << D); ++sg) {
+    double acc = Genz<double, FAM>::init(phase0);
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      const double t = A.l5 * h[j];
+      const double x = ((sg >> j) & 1u) ? c[j] - t : c[j] + t;
+      acc = Genz<double, FAM>::step(acc, x, p0[j], p1[j]);
+    }
+    s4 += Genz<double, FAM>::finish(acc, D);
+  }
+  Sk[4] = s4;
+  double vol = 1.0;
+#pragma unroll
+  for (int j = 0; j < D; ++j) vol *= h[j];
+  const double *w7 = A.w7 + D * 5, *w5 = A.w5 + D * 5;
+  double r7 = 0.0, r5 = 0.0;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    r7 += w7[k] * Sk[k];
+    r5 += w5[k] * Sk[k];
+  }
+  const double I7 = vol * r7, I5 = vol * r5;
+  S.regs.I7[r] = I7;
+  S.regs.I5[r] = I5;
+  S.regs.err[r] = fabs(I7 - I5);
+  S.regs.axis[r] = best;
+}
+
 }  // namespace
+
+// One integral (A.one), dimension D: one lane per region.
+template <int FAM, int D>
+__global__ void __launch_bounds__(256) gm_rule_lane_kernel(RuleArgs A) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= A.total) return;
+  rule_region_lane<FAM, D>(A, A.one, A.one.first + g);
+}
 
 __global__ void __launch_bounds__(256) gm_rule_kernel(RuleArgs A) {
   __shared__ double sc[4][kMaxDim], sh[4][kMaxDim];
@@ -183,16 +301,22 @@ __global__ void __launch_bounds__(256) gm_rule_kernel(RuleArgs A) {
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const long long g = (long long)blockIdx.x * 4 + w;
   if (g >= A.total) return;  // only whole waves leave; no block barrier below
-  int lo = 0, hi = A.nseg - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (A.seg_end[mid] > g)
-      hi = mid;
-    else
-      lo = mid + 1;
+  CSeg S;
+  long long before = 0;
+  if (A.nseg == 1) {
+    S = A.one;
+  } else {
+    int lo = 0, hi = A.nseg - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (A.seg_end[mid] > g)
+        hi = mid;
+      else
+        lo = mid + 1;
+    }
+    S = A.segs[lo];
+    before = lo > 0 ? A.seg_end[lo - 1] : 0;
   }
-  const CSeg S = A.segs[lo];
-  const long long before = lo > 0 ? A.seg_end[lo - 1] : 0;
   const long long r = S.first + (g - before);
   switch (S.family) {
     case GAUSSIAN: rule_region<GAUSSIAN>(A, S, r, w, lane, sc, sh, sf); break;
@@ -491,8 +615,35 @@ __global__ void __launch_bounds__(kScanBlock) totals_final_kernel(const double *
 
 long long scratch_blocks(long long n) { return (n + kScanTile - 1) / kScanTile; }
 
+template <int FAM>
+static void launch_rule_lane_d(const RuleArgs &A, unsigned grid, hipStream_t s) {
+  switch (A.one.ndim) {
+    case 2: hipLaunchKernelGGL((gm_rule_lane_kernel<FAM, 2>), dim3(grid), dim3(256), 0, s, A); break;
+    case 3: hipLaunchKernelGGL((gm_rule_lane_kernel<FAM, 3>), dim3(grid), dim3(256), 0, s, A); break;
+    case 4: hipLaunchKernelGGL((gm_rule_lane_kernel<FAM, 4>), dim3(grid), dim3(256), 0, s, A); break;
+    case 5: hipLaunchKernelGGL((gm_rule_lane_kernel<FAM, 5>), dim3(grid), dim3(256), 0, s, A); break;
+    case 6: hipLaunchKernelGGL((gm_rule_lane_kernel<FAM, 6>), dim3(grid), dim3(256), 0, s, A); break;
+    case 7: hipLaunchKernelGGL((gm_rule_lane_kernel<FAM, 7>), dim3(grid), dim3(256), 0, s, A); break;
+    default: hipLaunchKernelGGL((gm_rule_lane_kernel<FAM, 8>), dim3(grid), dim3(256), 0, s, A); break;
+  }
+}
+
 hipError_t launch_rule(const RuleArgs &A, hipStream_t s) {
   if (A.total <= 0) return hipSuccess;
+  // A lane per region needs enough regions to fill the device; below that,
+  // and above 8 dimensions (the registers a lane holds grow with d, and the
+  // 2^d corners with it), a wavefront per region.
+  if (A.nseg == 1 && A.one.ndim <= kLaneRuleMaxDim && A.total >= kLaneRuleMinRegions) {
+    const unsigned grid = (unsigned)((A.total + 255) / 256);
+    switch (A.one.family) {
+      case GAUSSIAN: launch_rule_lane_d<GAUSSIAN>(A, grid, s); break;
+      case OSCILLATORY: launch_rule_lane_d<OSCILLATORY>(A, grid, s); break;
+      case PRODUCT_PEAK: launch_rule_lane_d<PRODUCT_PEAK>(A, grid, s); break;
+      case CORNER_PEAK: launch_rule_lane_d<CORNER_PEAK>(A, grid, s); break;
+      default: launch_rule_lane_d<C0>(A, grid, s); break;
+    }
+    return hipGetLastError();
+  }
   const long long grid = (A.total + 3) / 4;
   hipLaunchKernelGGL(gm_rule_kernel, dim3((unsigned)grid), dim3(256), 0, s, A);
   return hipGetLastError();

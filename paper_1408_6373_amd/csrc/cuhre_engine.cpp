@@ -222,23 +222,27 @@ int launch_rule_segments(ccuba_ctx *ctx, const CSeg *segs, int nseg, DevBuf<CSeg
                          hipStream_t s) {
   if (nseg <= 0) return CCUBA_OK;
   int rc;
-  if ((int)dsegs.n < nseg && (rc = dsegs.alloc(ctx, nseg))) return rc;
-  if ((int)dends.n < nseg && (rc = dends.alloc(ctx, nseg))) return rc;
   std::vector<long long> ends(nseg);
   long long tot = 0;
   for (int q = 0; q < nseg; ++q) {
     tot += segs[q].count;
     ends[q] = tot;
   }
-  CCUBA_HIP(hipMemcpyAsync(dsegs.p, segs, nseg * sizeof(CSeg), hipMemcpyHostToDevice, s));
-  CCUBA_HIP(hipMemcpyAsync(dends.p, ends.data(), nseg * sizeof(long long), hipMemcpyHostToDevice,
-                           s));
   const GMTables &T = gm_tables();
-  RuleArgs A;
-  A.segs = dsegs.p;
+  RuleArgs A{};
   A.nseg = nseg;
-  A.seg_end = dends.p;
   A.total = tot;
+  if (nseg == 1) {
+    A.one = segs[0];  // by value: nothing to upload, nothing to wait for
+  } else {
+    if ((int)dsegs.n < nseg && (rc = dsegs.alloc(ctx, nseg))) return rc;
+    if ((int)dends.n < nseg && (rc = dends.alloc(ctx, nseg))) return rc;
+    CCUBA_HIP(hipMemcpyAsync(dsegs.p, segs, nseg * sizeof(CSeg), hipMemcpyHostToDevice, s));
+    CCUBA_HIP(hipMemcpyAsync(dends.p, ends.data(), nseg * sizeof(long long),
+                             hipMemcpyHostToDevice, s));
+    A.segs = dsegs.p;
+    A.seg_end = dends.p;
+  }
   A.w7 = w7_dev;
   A.w5 = w5_dev;
   A.l2 = T.l2;
@@ -265,8 +269,9 @@ int launch_rule_segments(ccuba_ctx *ctx, const CSeg *segs, int nseg, DevBuf<CSeg
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
   }
-  // the host arrays must stay alive until the copies ran
-  CCUBA_HIP(hipStreamSynchronize(s));
+  // the host arrays of a multi-segment launch must stay alive until the
+  // copies ran
+  if (nseg > 1) CCUBA_HIP(hipStreamSynchronize(s));
   return CCUBA_OK;
 }
 

@@ -57,6 +57,28 @@ def test_rule_matches_oracle(cc, ctx, fam, d):
             assert g["axis"][r] == o["axis"]
 
 
+@pytest.mark.parametrize("fam,d", [(f, d) for d in (2, 5, 8) for f in range(5)] +
+                         [(3, 3), (1, 4), (3, 6), (2, 7)])
+def test_rule_lane_per_region_matches_oracle(cc, ctx, fam, d):
+    # from 16384 regions on and up to d = 8 the rule runs one lane per region;
+    # sampled regions against the oracle, to the same bars
+    rng = np.random.default_rng(1000 + 10 * d + fam)
+    a, u = W.genz_params(fam, d, 4)
+    n = 16384 + 123
+    c, h = _regions(rng, d, n)
+    g = cc.cuhre_rule(ctx, fam, a, u, c, h)
+    ig = O.genz(fam, a, u)
+    for r in list(range(0, n, 997)) + [n - 1]:
+        o = O.gm_rule(ig, c[r], h[r])
+        vol = np.prod(h[r]) * 2.0**d
+        assert abs(g["I7"][r] - o["I7"]) <= 1e-12 * abs(o["I7"]) + 1e-15 * vol * 20
+        assert abs(g["I5"][r] - o["I5"]) <= 1e-12 * abs(o["I5"]) + 1e-15 * vol * 60
+        assert abs(g["err"][r] - o["err"]) <= 1e-11 * o["err"] + 1e-13 * abs(o["I7"]) + 1e-15 * vol * 60
+        D = np.sort(o["dfour"])[::-1]
+        if D[0] - D[1] > 1e-9 * D[0]:
+            assert g["axis"][r] == o["axis"]
+
+
 def test_rule_d16(cc, ctx):
     rng = np.random.default_rng(16)
     a, u = W.genz_params(0, 16, 1)
