@@ -239,13 +239,15 @@ def _batch_leg(cc, ctx):
 def _cuhre_leg(cc, ctx):
     import workloads as W
     a, u = W.genz_params(W.CORNER_PEAK, 6, 1)
-    cc.cuhre(W.CORNER_PEAK, a, u, ctx=ctx, epsrel=1e-3, max_regions_per_batch=10**5)
+    kw = dict(epsrel=1e-6, maxeval=10**10, max_regions_per_batch=10**5)
+    cc.cuhre(W.CORNER_PEAK, a, u, ctx=ctx, **kw)  # warm-up
+    t0 = time.perf_counter()
+    r = cc.cuhre(W.CORNER_PEAK, a, u, ctx=ctx, **kw)
+    dt = time.perf_counter() - t0
+    # the rule kernel alone, event-timed in a separate profiled run
     _stats(cc, ctx)
     ctx.config("profile", 1)
-    t0 = time.perf_counter()
-    r = cc.cuhre(W.CORNER_PEAK, a, u, ctx=ctx, epsrel=1e-6, maxeval=10**10,
-                 max_regions_per_batch=10**5)
-    dt = time.perf_counter() - t0
+    cc.cuhre(W.CORNER_PEAK, a, u, ctx=ctx, **kw)
     st = _stats(cc, ctx)
     ctx.config("profile", 0)
     return {"workload": "Cuhre corner peak d=6, batches of 1e5 regions, epsrel 1e-6, FP64",
