@@ -78,7 +78,7 @@ __device__ __forceinline__ double rule_point_f(int d, const double *c, const dou
 template <int FAM>
 __device__ void rule_region(const RuleArgs &A, const CSeg &S, long long r, int w, int lane,
                             double (*sc)[kMaxDim], double (*sh)[kMaxDim],
-                            double (*sf)[4 * kMaxDim + 1]) {
+                            double (*sf)[4 * kMaxDim + 1], double (*sx)[2 * kMaxDim]) {
   const int d = S.ndim;
   const long long cap = S.regs.cap;
   if (lane < d) {
@@ -94,9 +94,9 @@ __device__ void rule_region(const RuleArgs &A, const CSeg &S, long long r, int w
   const double phase0 = p1[0];
   const long long n2 = 2ll * d, n4 = 2ll * d * (d - 1);
   const long long b2 = 1, b3 = 1 + n2, b4 = 1 + 2 * n2, b5 = 1 + 2 * n2 + n4;
-  const long long np = b5 + (1ll << d);
   double Sk[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  for (long long p = lane; p < np; p += 64) {
+  // classes 0-3 (a few hundred points at most)
+  for (long long p = lane; p < b5; p += 64) {
     int cls, i = 0, jj = 0;
     unsigned sgn = 0;
     double lam = 0.0;
@@ -135,6 +135,25 @@ __device__ void rule_region(const RuleArgs &A, const CSeg &S, long long r, int w
     if (cls == 0) sf[w][4 * kMaxDim] = f;
     if (cls == 1) sf[w][(int)(p - b2)] = f;                 // [2i + sign]
     if (cls == 2) sf[w][2 * kMaxDim + (int)(p - b3)] = f;   // [2d.. + 2i + sign]
+  }
+  // class 4, the 2^d corners (all of the work at large d): both coordinates
+  // of every axis, c - l5 h and c + l5 h, are formed once per region (the
+  // values rule_point_f forms per point), so a corner is d selects and the
+  // integrand's own steps
+  if (lane < d) {
+    const double t = A.l5 * h[lane];
+    sx[w][2 * lane] = c[lane] + t;
+    sx[w][2 * lane + 1] = c[lane] - t;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const unsigned ncorner = 1u << d;
+  for (unsigned sg = lane; sg < ncorner; sg += 64) {
+    double acc = Genz<double, FAM>::init(phase0);
+    for (int j = 0; j < d; ++j)
+      acc = Genz<double, FAM>::step(acc, sx[w][2 * j + ((sg >> j) & 1u)], p0[j], p1[j]);
+    Sk[4] += Genz<double, FAM>::finish(acc, d);
   }
 #pragma unroll
   for (int k = 0; k < 5; ++k) Sk[k] = wsum(Sk[k]);
@@ -298,6 +317,7 @@ __global__ void __launch_bounds__(256) gm_rule_lane_kernel(RuleArgs A) {
 __global__ void __launch_bounds__(256) gm_rule_kernel(RuleArgs A) {
   __shared__ double sc[4][kMaxDim], sh[4][kMaxDim];
   __shared__ double sf[4][4 * kMaxDim + 1];
+  __shared__ double sx[4][2 * kMaxDim];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const long long g = (long long)blockIdx.x * 4 + w;
   if (g >= A.total) return;  // only whole waves leave; no block barrier below
@@ -319,11 +339,11 @@ __global__ void __launch_bounds__(256) gm_rule_kernel(RuleArgs A) {
   }
   const long long r = S.first + (g - before);
   switch (S.family) {
-    case GAUSSIAN: rule_region<GAUSSIAN>(A, S, r, w, lane, sc, sh, sf); break;
-    case OSCILLATORY: rule_region<OSCILLATORY>(A, S, r, w, lane, sc, sh, sf); break;
-    case PRODUCT_PEAK: rule_region<PRODUCT_PEAK>(A, S, r, w, lane, sc, sh, sf); break;
-    case CORNER_PEAK: rule_region<CORNER_PEAK>(A, S, r, w, lane, sc, sh, sf); break;
-    default: rule_region<C0>(A, S, r, w, lane, sc, sh, sf); break;
+    case GAUSSIAN: rule_region<GAUSSIAN>(A, S, r, w, lane, sc, sh, sf, sx); break;
+    case OSCILLATORY: rule_region<OSCILLATORY>(A, S, r, w, lane, sc, sh, sf, sx); break;
+    case PRODUCT_PEAK: rule_region<PRODUCT_PEAK>(A, S, r, w, lane, sc, sh, sf, sx); break;
+    case CORNER_PEAK: rule_region<CORNER_PEAK>(A, S, r, w, lane, sc, sh, sf, sx); break;
+    default: rule_region<C0>(A, S, r, w, lane, sc, sh, sf, sx); break;
   }
 }
 
