@@ -17,24 +17,67 @@ using namespace ccuba;
 
 namespace ccuba {
 
+namespace {
+
+// Size classes: 256 B, then four steps per power of two (at most 25% unused).
+size_t size_class(size_t bytes) {
+  if (bytes <= 256) return 256;
+  size_t p = 256;
+  while (p * 2 < bytes) p *= 2;  // p < bytes <= 2p
+  const size_t q = p / 4;
+  return (bytes + q - 1) / q * q;
+}
+
+}  // namespace
+
 int dev_alloc(ccuba_ctx *ctx, void **p, size_t bytes) {
-  const size_t before = ctx->used.fetch_add(bytes);
-  if (before + bytes > ctx->budget) {
-    ctx->used.fetch_sub(bytes);
-    return CCUBA_ENOMEM;
+  const size_t cls = size_class(bytes);
+  {
+    std::lock_guard<std::mutex> g(ctx->pool_lock);
+    auto it = ctx->pool.find(cls);
+    if (it != ctx->pool.end()) {
+      if (ctx->used.load() + cls > ctx->budget) return CCUBA_ENOMEM;
+      *p = it->second;
+      ctx->pool.erase(it);
+      ctx->pooled -= cls;
+      ctx->used.fetch_add(cls);
+      return CCUBA_OK;
+    }
+    if (ctx->used.load() + cls > ctx->budget) return CCUBA_ENOMEM;
+    // pooled blocks count against the budget too: give them back first
+    if (ctx->used.load() + ctx->pooled + cls > ctx->budget) {
+      for (auto &kv : ctx->pool) (void)hipFree(kv.second);
+      ctx->pool.clear();
+      ctx->pooled = 0;
+    }
+    ctx->used.fetch_add(cls);
   }
-  if (hipMalloc(p, bytes) != hipSuccess) {
-    ctx->used.fetch_sub(bytes);
-    *p = nullptr;
-    return CCUBA_ENOMEM;
+  if (hipMalloc(p, cls) != hipSuccess) {
+    // a full device: release the pool and try once more
+    pool_release(ctx);
+    if (hipMalloc(p, cls) != hipSuccess) {
+      ctx->used.fetch_sub(cls);
+      *p = nullptr;
+      return CCUBA_ENOMEM;
+    }
   }
   return CCUBA_OK;
 }
 
 void dev_free(ccuba_ctx *ctx, void *p, size_t bytes) {
   if (!p) return;
-  (void)hipFree(p);
-  ctx->used.fetch_sub(bytes);
+  const size_t cls = size_class(bytes);
+  std::lock_guard<std::mutex> g(ctx->pool_lock);
+  ctx->pool.emplace(cls, p);
+  ctx->pooled += cls;
+  ctx->used.fetch_sub(cls);
+}
+
+void pool_release(ccuba_ctx *ctx) {
+  std::lock_guard<std::mutex> g(ctx->pool_lock);
+  for (auto &kv : ctx->pool) (void)hipFree(kv.second);
+  ctx->pool.clear();
+  ctx->pooled = 0;
 }
 
 }  // namespace ccuba
@@ -173,6 +216,7 @@ int ccuba_shutdown(ccuba_ctx **ctx) {
   delete c->server;  // stops the serving thread and frees its requests
   c->server = nullptr;
   drop_engine_cache(c);
+  pool_release(c);
   if (c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
   *ctx = nullptr;

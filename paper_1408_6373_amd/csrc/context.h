@@ -5,6 +5,7 @@
 
 #include <atomic>
 #include <chrono>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <utility>
@@ -37,6 +38,10 @@ struct ccuba_ctx {
   // buffers and captured graphs) for the next call of the same shape
   ccuba::VegasEngine *vcache = nullptr;
   int engine_cache = 1;
+  // freed device blocks kept for reuse, by size class (see dev_alloc)
+  std::mutex pool_lock;
+  std::multimap<size_t, void *> pool;
+  size_t pooled = 0;  // bytes held in the pool (not in `used')
   double now() const {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
@@ -45,9 +50,13 @@ struct ccuba_ctx {
 namespace ccuba {
 
 // Device allocation charged to a context's budget.  Returns CCUBA_OK,
-// CCUBA_ENOMEM (budget) or CCUBA_EHIP.
+// CCUBA_ENOMEM (budget) or CCUBA_EHIP.  Blocks come from and return to a
+// per-context pool of size classes, so that repeated calls and the serving
+// loop do not pay for hipMalloc/hipFree.
 int dev_alloc(ccuba_ctx *ctx, void **p, size_t bytes);
 void dev_free(ccuba_ctx *ctx, void *p, size_t bytes);
+// Return every pooled block to the device.
+void pool_release(ccuba_ctx *ctx);
 
 // A typed device buffer that returns its bytes to the context on release.
 template <typename T>

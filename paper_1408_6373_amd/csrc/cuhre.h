@@ -44,6 +44,8 @@ struct CScratch {
 };
 
 hipError_t launch_rule(const RuleArgs &A, hipStream_t s);
+// The root region of [0,1]^d (centre 1/2, half-width 1/2, id 0) at position 0.
+hipError_t launch_root(const CRegions &R, int ndim, hipStream_t s);
 // Top-K selection of n regions by (err desc, position asc): flag[i] = 1 for
 // the K chosen.  Positions are in ascending id order.
 hipError_t launch_select(const CRegions &R, long long n, long long K, const CScratch &S,

@@ -306,6 +306,15 @@ __device__ void rule_region_lane(const RuleArgs &A, const CSeg &S, long long r) 
 
 }  // namespace
 
+__global__ void cuhre_root_kernel(CRegions R, int d) {
+  const int j = threadIdx.x;
+  if (j < d) {
+    R.c[j * R.cap] = 0.5;
+    R.h[j * R.cap] = 0.5;
+  }
+  if (j == 0) R.id[0] = 0;
+}
+
 // One integral (A.one), dimension D: one lane per region.
 template <int FAM, int D>
 __global__ void __launch_bounds__(256) gm_rule_lane_kernel(RuleArgs A) {
@@ -646,6 +655,11 @@ static void launch_rule_lane_d(const RuleArgs &A, unsigned grid, hipStream_t s) 
     case 7: hipLaunchKernelGGL((gm_rule_lane_kernel<FAM, 7>), dim3(grid), dim3(256), 0, s, A); break;
     default: hipLaunchKernelGGL((gm_rule_lane_kernel<FAM, 8>), dim3(grid), dim3(256), 0, s, A); break;
   }
+}
+
+hipError_t launch_root(const CRegions &R, int ndim, hipStream_t s) {
+  hipLaunchKernelGGL(cuhre_root_kernel, dim3(1), dim3(64), 0, s, R, ndim);
+  return hipGetLastError();
 }
 
 hipError_t launch_rule(const RuleArgs &A, hipStream_t s) {

@@ -163,11 +163,19 @@ int CuhreRun::start(const CuhreSpec &spec, hipStream_t s) {
   const long long first_cap = std::max<long long>(
       16, std::min<long long>(std::min<long long>(4 * spec.batch + 1, 1 << 22),
                               spec.maxeval / np_ + 2));
-  // initial stores
-  if ((rc = alloc_store(R_[0], c_[0], h_[0], vals_[0], axis_[0], id_[0], first_cap)) ||
-      (rc = alloc_store(R_[1], c_[1], h_[1], vals_[1], axis_[1], id_[1], first_cap)))
-    return rc;
-  cap_ = first_cap;
+  // initial stores (room for one batch only if a tight budget refuses more)
+  long long cap0 = first_cap;
+  for (;;) {
+    rc = alloc_store(R_[0], c_[0], h_[0], vals_[0], axis_[0], id_[0], cap0);
+    if (!rc) rc = alloc_store(R_[1], c_[1], h_[1], vals_[1], axis_[1], id_[1], cap0);
+    if (rc != CCUBA_ENOMEM) break;
+    const long long small = std::max<long long>(
+        16, std::min<long long>(spec.batch + 1, spec.maxeval / np_ + 2));
+    if (cap0 <= small) break;
+    cap0 = small;
+  }
+  if (rc) return rc;
+  cap_ = cap0;
   const long long nb = scratch_blocks(cap_);
   if ((rc = flag_.alloc(ctx_, cap_)) || (rc = bsum_.alloc(ctx_, nb)) ||
       (rc = tot_.alloc(ctx_, 2 * nb)))
@@ -185,22 +193,15 @@ int CuhreRun::start(const CuhreSpec &spec, hipStream_t s) {
     vs.a[j] = spec.a[j];
     vs.u[j] = spec.u[j];
   }
-  double p64[2][kParamRow];
   float p32[2][kParamRow];
-  genz_constants(vs, p64, p32);
+  genz_constants(vs, hp64_, p32);
   const GMTables &T = gm_tables();
-  CCUBA_HIP(hipMemcpyAsync(params_.p, p64, sizeof(p64), hipMemcpyHostToDevice, s));
+  // (host sources: members and static tables, alive while the copies run)
+  CCUBA_HIP(hipMemcpyAsync(params_.p, hp64_, sizeof(hp64_), hipMemcpyHostToDevice, s));
   CCUBA_HIP(hipMemcpyAsync(w7_.p, T.w7, sizeof(T.w7), hipMemcpyHostToDevice, s));
   CCUBA_HIP(hipMemcpyAsync(w5_.p, T.w5, sizeof(T.w5), hipMemcpyHostToDevice, s));
   // root region [0,1]^d: centre 1/2, half-width 1/2, id 0
-  std::vector<double> half(d, 0.5);
-  for (int j = 0; j < d; ++j) {
-    CCUBA_HIP(hipMemcpyAsync(R_[0].c + j * cap_, &half[j], 8, hipMemcpyHostToDevice, s));
-    CCUBA_HIP(hipMemcpyAsync(R_[0].h + j * cap_, &half[j], 8, hipMemcpyHostToDevice, s));
-  }
-  const long long zero = 0;
-  CCUBA_HIP(hipMemcpyAsync(R_[0].id, &zero, 8, hipMemcpyHostToDevice, s));
-  CCUBA_HIP(hipStreamSynchronize(s));  // host sources are stack values
+  CCUBA_HIP(launch_root(R_[0], d, s));
   CSeg seg{};
   seg.ndim = d;
   seg.family = spec.family;
@@ -276,11 +277,16 @@ int launch_rule_segments(ccuba_ctx *ctx, const CSeg *segs, int nseg, DevBuf<CSeg
 }
 
 int CuhreRun::launch_totals(hipStream_t s) {
-  CCUBA_HIP(ccuba::launch_totals(R_[cur_], n_, S_, out_.p, s));
+  CCUBA_HIP(ccuba::launch_totals(R_[cur_], n_, S_, mapped_dev_ ? mapped_dev_ : out_.p, s));
   return CCUBA_OK;
 }
 
 int CuhreRun::read_totals(hipStream_t s) {
+  if (mapped_host_) {  // the caller has synchronised s
+    I_ = mapped_host_[0];
+    E_ = mapped_host_[1];
+    return CCUBA_OK;
+  }
   double t[2];
   CCUBA_HIP(hipMemcpyAsync(t, out_.p, sizeof(t), hipMemcpyDeviceToHost, s));
   CCUBA_HIP(hipStreamSynchronize(s));

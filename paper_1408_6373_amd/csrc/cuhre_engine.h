@@ -39,6 +39,13 @@ class CuhreRun {
   void commit_pending();
   // Copy the device totals to host (synchronous on s).
   int read_totals(hipStream_t s);
+  // Write the totals to pinned host memory (host and device addresses of 2
+  // doubles) instead; read_totals then reads them there and the caller must
+  // have synchronised the stream since launch_totals.
+  void set_mapped_totals(double *host, double *dev) {
+    mapped_host_ = host;
+    mapped_dev_ = dev;
+  }
   // Run to completion alone.
   int run(hipStream_t s);
   int rule_only(long long nreg, const double *c, const double *h, double *I7, double *I5,
@@ -79,6 +86,8 @@ class CuhreRun {
   DevBuf<CSeg> seg_;
   DevBuf<long long> seg_end_;
   CScratch S_{};
+  double hp64_[2][kParamRow];  // host source of the parameter upload
+  double *mapped_host_ = nullptr, *mapped_dev_ = nullptr;
 };
 
 // Launch the rule over segments of several integrals in one kernel.  segs

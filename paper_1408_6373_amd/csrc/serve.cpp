@@ -21,6 +21,11 @@ struct Server::Req {
   bool vdone = false;
   DevBuf<double> grid, tsums, thist, gsums, ghist, hsum, iters, p64;
   DevBuf<float> p32;
+  // host sources of the activation's uploads, alive while the copies are in
+  // flight (the request outlives them)
+  double a64[2][kParamRow];
+  float a32[2][kParamRow];
+  VState st0{};
   // Cuhre
   std::unique_ptr<CuhreRun> cuhre;
   bool cpending = false;
@@ -36,8 +41,10 @@ Server::~Server() {
   cv_.notify_all();
   if (th_.joinable()) th_.join();
   std::lock_guard<std::mutex> g(ctx_->lock);
+  (void)hipStreamSynchronize(ctx_->stream);
   for (auto &r : active_) release(*r);
   active_.clear();
+  if (tot_host_) (void)hipHostFree(tot_host_);
 }
 
 int Server::submit(const ccuba_job &job, unsigned long long *ticket) {
@@ -143,7 +150,11 @@ int Server::activate(Req &r) {
     sp.batch = jb.max_regions_per_batch > 0 ? jb.max_regions_per_batch : 100000;
     if (validate_cuhre(sp) || (jb.flags & CCUBA_PRECISION_MASK) != CCUBA_FP64)
       return CCUBA_EINVAL;
+    if (free_slots_.empty()) return CCUBA_ENOMEM;
+    r.slot = free_slots_.back();
+    free_slots_.pop_back();
     r.cuhre = std::make_unique<CuhreRun>(ctx_);
+    r.cuhre->set_mapped_totals(tot_host_ + 2 * r.slot, tot_dev_ + 2 * r.slot);
     int rc = r.cuhre->start(sp, s);
     if (rc) {
       r.cuhre.reset();
@@ -223,25 +234,18 @@ int Server::activate(Req &r) {
   J.iter_var = r.iters.p + cap;
   J.p64 = r.p64.p;
   J.p32 = r.p32.p;
-  std::vector<double> g(2 * row);
-  for (int c = 0; c < 2; ++c)
-    for (int d = 0; d < sp.ndim; ++d)
-      for (int k = 0; k <= sp.nbins; ++k)
-        g[(size_t)c * row + (size_t)d * (sp.nbins + 1) + k] = (double)k / sp.nbins;
-  double a64[2][kParamRow];
-  float a32[2][kParamRow];
-  genz_constants(sp, a64, a32);
-  VState st{};
+  genz_constants(sp, r.a64, r.a32);
+  r.st0 = VState{};
   if (iters == 0) {
-    st.done = 1;
-    st.fail = 1;
+    r.st0.done = 1;
+    r.st0.fail = 1;
   }
   r.vdone = iters == 0;
-  CCUBA_HIP(hipMemcpyAsync(J.grid, g.data(), g.size() * 8, hipMemcpyHostToDevice, s));
-  CCUBA_HIP(hipMemcpyAsync(r.p64.p, a64, sizeof(a64), hipMemcpyHostToDevice, s));
-  CCUBA_HIP(hipMemcpyAsync(r.p32.p, a32, sizeof(a32), hipMemcpyHostToDevice, s));
-  CCUBA_HIP(hipMemcpyAsync(J.state, &st, sizeof(st), hipMemcpyHostToDevice, s));
-  CCUBA_HIP(hipStreamSynchronize(s));  // host staging buffers die here
+  (void)row;
+  CCUBA_HIP(launch_init_grid(J.grid, sp.ndim, sp.nbins, s));
+  CCUBA_HIP(hipMemcpyAsync(r.p64.p, r.a64, sizeof(r.a64), hipMemcpyHostToDevice, s));
+  CCUBA_HIP(hipMemcpyAsync(r.p32.p, r.a32, sizeof(r.a32), hipMemcpyHostToDevice, s));
+  CCUBA_HIP(hipMemcpyAsync(J.state, &r.st0, sizeof(r.st0), hipMemcpyHostToDevice, s));
   return CCUBA_OK;
 }
 
@@ -280,6 +284,8 @@ int Server::tick() {
         (rc = w7_.alloc(ctx_, 17 * 5)) || (rc = w5_.alloc(ctx_, 17 * 5)))
       return rc;
     for (int q = slots - 1; q >= 0; --q) free_slots_.push_back(q);
+    CCUBA_HIP(hipHostMalloc((void **)&tot_host_, 2 * sizeof(double) * slots, 0));
+    CCUBA_HIP(hipHostGetDevicePointer((void **)&tot_dev_, tot_host_, 0));
     const GMTables &T = gm_tables();
     CCUBA_HIP(hipMemcpy(w7_.p, T.w7, sizeof(T.w7), hipMemcpyHostToDevice));
     CCUBA_HIP(hipMemcpy(w5_.p, T.w5, sizeof(T.w5), hipMemcpyHostToDevice));
@@ -287,7 +293,11 @@ int Server::tick() {
   }
   {
     std::unique_lock<std::mutex> q(qmu_);
+    const size_t before = active_.size();
     admit_locked(q);
+    // newly admitted requests' uploads and first launches (a Cuhre root's
+    // totals among them) complete before this tick reads them
+    if (active_.size() != before) CCUBA_HIP(hipStreamSynchronize(s));
   }
   if (active_.empty()) return CCUBA_OK;
   ++ticks_;

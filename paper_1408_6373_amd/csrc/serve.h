@@ -69,6 +69,8 @@ class Server {
   DevBuf<CSeg> segs_;
   DevBuf<long long> seg_end_;
   DevBuf<double> w7_, w5_;
+  // per slot, the Cuhre totals in pinned host memory the device writes to
+  double *tot_host_ = nullptr, *tot_dev_ = nullptr;
   bool tables_ready_ = false;
 };
 

@@ -62,6 +62,8 @@ hipError_t launch_fold(const FoldArgs &F, bool level2, hipStream_t s);
 hipError_t launch_refine(const VegasArgs &A, int njobs, size_t lds, hipStream_t s);
 // Uniform starting grids (both copies) of jobs[0, njobs) (device table).
 hipError_t launch_init_grids(const VJob *jobs, int njobs, hipStream_t s);
+// The same for one grid of ndim rows of nbins + 1 edges (both copies).
+hipError_t launch_init_grid(double *grid, int ndim, int nbins, hipStream_t s);
 hipError_t launch_collect(const VegasArgs &A, int njobs, double *sums, double *hist,
                           hipStream_t s);
 hipError_t launch_points(const PointsArgs &P, hipStream_t s);

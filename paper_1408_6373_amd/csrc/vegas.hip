@@ -353,6 +353,11 @@ __global__ void __launch_bounds__(256) vegas_init_grids_kernel(const VJob *jobs)
   for (int e = threadIdx.x; e < tot; e += blockDim.x) J.grid[e] = (double)(e % row) / N;
 }
 
+__global__ void __launch_bounds__(256) vegas_init_grid_kernel(double *grid, int d, int N) {
+  const int row = N + 1, tot = 2 * d * row;
+  for (int e = threadIdx.x; e < tot; e += blockDim.x) grid[e] = (double)(e % row) / N;
+}
+
 // Copy out every job's folded iteration totals: sums[2] and hist[d*N]; used by
 // the raw DoSample entry point.
 __global__ void __launch_bounds__(256) vegas_collect_kernel(VegasArgs A, double *sums,
@@ -437,6 +442,11 @@ hipError_t launch_refine(const VegasArgs &A, int njobs, size_t lds, hipStream_t 
 hipError_t launch_init_grids(const VJob *jobs, int njobs, hipStream_t s) {
   if (njobs <= 0) return hipSuccess;
   hipLaunchKernelGGL(vegas_init_grids_kernel, dim3(njobs), dim3(256), 0, s, jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_grid(double *grid, int ndim, int nbins, hipStream_t s) {
+  hipLaunchKernelGGL(vegas_init_grid_kernel, dim3(1), dim3(256), 0, s, grid, ndim, nbins);
   return hipGetLastError();
 }
 
