@@ -89,6 +89,11 @@ int CuhreRun::ensure(long long need, hipStream_t s) {
   cap = std::max(need, std::min(cap, limit));
   const int d = spec_.ndim;
   // new store for the leaves, copy, then a fresh second store
+  // a tight budget: grow only as needed (two new stores must fit beside
+  // what the context holds now; the bytes per region with size-class slack)
+  const double per = ((2.0 * d + 3.0) * 8.0 + 12.0) * 1.25;
+  if ((double)ctx_->used.load() + 2.0 * per * (double)cap + 65536.0 > (double)ctx_->budget)
+    cap = need;
   CRegions R{};
   DevBuf<double> cb, hb, vals;
   DevBuf<int> ax;
