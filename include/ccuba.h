@@ -105,14 +105,25 @@ int ccuba_shutdown(ccuba_ctx **ctx);
  *   "ilp"            points each lane carries per loop trip, 1 or 2 (default
  *                    2 for FP32, 1 for FP64; the key sets both)
  *   "min_tile"       smallest tile of points in a batched launch (>= 64)
- *   "autotune"       1 = pick the settings above by measurement, cached in the
- *                    file named by CCUBA_TUNE_CACHE (if set)
+ *   "autotune"       1 = pick the settings above by measurement: a single
+ *                    integral times a fixed synthetic integral (cached in the
+ *                    file named by CCUBA_TUNE_CACHE, if set); a batch times
+ *                    DoSample passes over its own jobs, once per context and
+ *                    precision
  *   "graph"          1 = replay iterations from a captured hipGraph
+ *   "engine_cache"   1 = keep the engine of the last single-integral Vegas call
+ *                    (its buffers and graphs) for the next call of its shape
  *   "serve_slots"    maximum requests resident in the serving loop
  *   "profile"        1 = time every kernel launch with HIP events (see
  *                    ccuba_stats_get)
  * Returns CCUBA_ENOENT for an unknown key, CCUBA_EINVAL for a bad value. */
 int ccuba_config(ccuba_ctx *ctx, const char *key, long long value);
+
+/* Read one setting into *value: the keys of ccuba_config; the DoSample
+ * launch settings ("block", "blocks_per_cu", "hist64", "ilp", "min_tile") are
+ * those of `precision' (CCUBA_FP64 or CCUBA_FP32_EVAL), e.g. after an
+ * autotuned batch.  Returns CCUBA_ENOENT for an unknown key. */
+int ccuba_config_get(ccuba_ctx *ctx, const char *key, int precision, long long *value);
 
 /* Vegas (Sect. 3.2.2 prototype; Lepage 1978).  Iteration t samples
  * n_t = nstart + t*nincrease points from Philox4x32-10 with counter

@@ -69,6 +69,7 @@ _CTXP = C.c_void_p
 _sig("ccuba_init", C.c_int, [C.POINTER(_CTXP), C.c_int, C.c_size_t])
 _sig("ccuba_shutdown", C.c_int, [C.POINTER(_CTXP)])
 _sig("ccuba_config", C.c_int, [_CTXP, C.c_char_p, C.c_longlong])
+_sig("ccuba_config_get", C.c_int, [_CTXP, C.c_char_p, C.c_int, C.POINTER(C.c_longlong)])
 _sig("ccuba_strerror", C.c_char_p, [C.c_int])
 _VEGAS_ARGS = [C.POINTER(_CTXP), C.c_int, C.c_int, C.POINTER(Integrand), C.c_double,
                C.c_double, C.c_int, C.c_ulonglong, C.c_longlong, C.c_longlong, C.c_longlong,
@@ -95,7 +96,8 @@ if hasattr(_lib, "ccuba_submit"):
     _sig("ccuba_poll", C.c_int, [_CTXP, C.c_ulonglong, C.POINTER(Result)])
     _sig("ccuba_drain", C.c_int, [_CTXP])
 
-SYMBOLS = ["ccuba_init", "ccuba_shutdown", "ccuba_config", "ccuba_strerror", "ccuba_vegas",
+SYMBOLS = ["ccuba_init", "ccuba_shutdown", "ccuba_config", "ccuba_config_get",
+           "ccuba_strerror", "ccuba_vegas",
            "ccuba_vegas_ex", "ccuba_cuhre", "ccuba_cuhre_rule", "ccuba_vegas_batch",
            "ccuba_submit", "ccuba_poll", "ccuba_drain", "ccuba_vegas_dosample_raw",
            "ccuba_vegas_points", "ccuba_vegas_refine"]
@@ -138,6 +140,12 @@ class Context:
 
     def config(self, key, value):
         _check(_lib.ccuba_config(self._h, key.encode(), int(value)), "ccuba_config(%s)" % key)
+
+    def config_get(self, key, precision=FP32_EVAL):
+        v = C.c_longlong()
+        _check(_lib.ccuba_config_get(self._h, key.encode(), int(precision), C.byref(v)),
+               "ccuba_config_get(%s)" % key)
+        return v.value
 
     def close(self):
         if self._h:

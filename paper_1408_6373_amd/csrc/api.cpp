@@ -223,6 +223,37 @@ int ccuba_shutdown(ccuba_ctx **ctx) {
   return CCUBA_OK;
 }
 
+int ccuba_config_get(ccuba_ctx *ctx, const char *key, int precision, long long *value) {
+  if (!ctx || !key || !value || (precision != CCUBA_FP64 && precision != CCUBA_FP32_EVAL))
+    return CCUBA_EINVAL;
+  std::lock_guard<std::mutex> g(ctx->lock);
+  const VegasTune &t = ctx->tune[precision == CCUBA_FP64 ? FP64 : FP32];
+  const std::string k(key);
+  if (k == "block")
+    *value = t.block;
+  else if (k == "blocks_per_cu")
+    *value = t.blocks_per_cu;
+  else if (k == "hist64")
+    *value = t.hist64;
+  else if (k == "ilp")
+    *value = t.ilp;
+  else if (k == "min_tile")
+    *value = t.min_tile;
+  else if (k == "autotune")
+    *value = ctx->autotune;
+  else if (k == "graph")
+    *value = ctx->use_graph;
+  else if (k == "profile")
+    *value = ctx->profile;
+  else if (k == "serve_slots")
+    *value = ctx->serve_slots;
+  else if (k == "engine_cache")
+    *value = ctx->engine_cache;
+  else
+    return CCUBA_ENOENT;
+  return CCUBA_OK;
+}
+
 int ccuba_config(ccuba_ctx *ctx, const char *key, long long value) {
   if (!ctx || !key) return CCUBA_EINVAL;
   std::lock_guard<std::mutex> g(ctx->lock);
@@ -536,10 +567,7 @@ int ccuba_vegas_batch(ccuba_ctx *ctx, int njobs, const ccuba_job jobs[], ccuba_r
     }
   }
   if (specs.empty()) return CCUBA_OK;
-  if (ctx->autotune) {
-    maybe_autotune(ctx, FP32);
-    maybe_autotune(ctx, FP64);
-  }
+  if (ctx->autotune) autotune_batch(ctx, specs);
   VegasEngine eng(ctx);
   int rc;
   if ((rc = eng.setup(specs, specs.size() == 1, ctx->stream))) return rc;

@@ -28,6 +28,7 @@ struct ccuba_ctx {
   int use_graph = 1;
   int autotune = 0;
   int tuned[2] = {0, 0};
+  int tuned_batch[2] = {0, 0};
   int serve_slots = 256;
   int profile = 0;
   ccuba_stats stats{};

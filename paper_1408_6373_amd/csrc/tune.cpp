@@ -131,4 +131,66 @@ void maybe_autotune(ccuba_ctx *ctx, int prec) {
   if (path && *path) store_cache(path, key, prec, best);
 }
 
+namespace {
+
+double time_batch(ccuba_ctx *ctx, const std::vector<VegasSpec> &specs) {
+  double best = 1e30;
+  VegasEngine eng(ctx);
+  if (eng.setup(specs, false, ctx->stream) != 0) return best;
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess) return best;
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return best;
+  }
+  (void)eng.dosample_only(ctx->stream);  // warm-up
+  for (int r = 0; r < 2; ++r) {
+    (void)hipEventRecord(a, ctx->stream);
+    (void)eng.dosample_only(ctx->stream);
+    (void)hipEventRecord(b, ctx->stream);
+    if (hipEventSynchronize(b) != hipSuccess) break;
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, a, b);
+    if (ms < best) best = ms;
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return best;
+}
+
+}  // namespace
+
+void autotune_batch(ccuba_ctx *ctx, const std::vector<VegasSpec> &specs) {
+  for (int prec = 0; prec < 2; ++prec) {
+    if (ctx->tuned_batch[prec]) continue;
+    std::vector<VegasSpec> mine;
+    for (const auto &sp : specs)
+      if (sp.prec == prec) mine.push_back(sp);
+    if (mine.empty()) continue;
+    ctx->tuned_batch[prec] = 1;
+    const VegasTune saved = ctx->tune[prec];
+    VegasTune best = saved;
+    double best_ms = 1e30;
+    const int bpcs[] = {2, 3, 4, 6};
+    const long long tiles[] = {4096, 16384, 65536};
+    for (int bpc : bpcs)
+      for (int ilp = 1; ilp <= 2; ++ilp)
+        for (long long mt : tiles)
+          for (int h = 0; h < (prec == FP32 ? 2 : 1); ++h) {
+            VegasTune c = saved;
+            c.blocks_per_cu = bpc;
+            c.ilp = ilp;
+            c.min_tile = mt;
+            if (prec == FP32) c.hist64 = h;
+            ctx->tune[prec] = c;
+            const double ms = time_batch(ctx, mine);
+            if (ms < best_ms) {
+              best_ms = ms;
+              best = c;
+            }
+          }
+    ctx->tune[prec] = best;
+  }
+}
+
 }  // namespace ccuba

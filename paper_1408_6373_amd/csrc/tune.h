@@ -1,5 +1,7 @@
 // tune.h -- launch-geometry autotuner of the DoSample kernel.
 #pragma once
+#include <vector>
+
 #include "context.h"
 
 namespace ccuba {
@@ -8,5 +10,12 @@ namespace ccuba {
 // for precision `prec' by timing DoSample on a fixed synthetic integral, once
 // per context; the choice is cached in the file named by CCUBA_TUNE_CACHE.
 void maybe_autotune(ccuba_ctx *ctx, int prec);
+
+// The same for a batch, timed on the batch itself: one DoSample pass over
+// the jobs of each precision for every candidate (persistent blocks per CU,
+// points per lane per trip, smallest tile, FP32 histogram type), once per
+// context and precision.
+struct VegasSpec;
+void autotune_batch(ccuba_ctx *ctx, const std::vector<VegasSpec> &specs);
 
 }  // namespace ccuba

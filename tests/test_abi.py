@@ -32,6 +32,11 @@ def test_every_declared_symbol_is_exported(cc):
     assert set(cc.SYMBOLS) <= set(names)
 
 
+def test_config_get_rejects_bad_arguments_on_the_host(cc):
+    v = C.c_longlong()
+    assert cc._lib.ccuba_config_get(None, b"ilp", 1, C.byref(v)) == cc.EINVAL
+
+
 def test_strerror_names_codes(cc):
     for rc in (0, -1, -2, -3, -4, -5):
         assert cc.strerror(rc) not in ("", "unknown status")

@@ -110,3 +110,28 @@ def test_full_4096_job_workload_sampled(cc, ctx):
                     seed=s["seed"], stream_id=s["stream_id"], nstart=s["nstart"],
                     maxeval=s["maxeval"], nbins=128)
         assert _rel(r["integral"], o["integral"]) < 1e-6
+
+
+def test_autotuned_batch_equals_default(cc):
+    # the tuner only changes launch settings: results agree to summation order
+    jobs = W.batch_jobs(96, seed=77)
+    specs = [dict(method=0, ndim=j["ndim"], family=j["family"], a=j["a"], u=j["u"],
+                  seed=j["seed"], stream_id=j["stream_id"], nstart=j["nstart"],
+                  maxeval=4 * j["nstart"], nbins=128, flags=cc.FP32_EVAL if q % 2 else 0)
+             for q, j in enumerate(jobs)]
+    c0 = cc.Context()
+    base = cc.vegas_batch(c0, specs)
+    c0.close()
+    c1 = cc.Context()
+    c1.config("autotune", 1)
+    tuned = cc.vegas_batch(c1, specs)
+    for prec in (cc.FP64, cc.FP32_EVAL):
+        assert c1.config_get("blocks_per_cu", prec) in (2, 3, 4, 6)
+        assert c1.config_get("ilp", prec) in (1, 2)
+        assert c1.config_get("min_tile", prec) in (4096, 16384, 65536)
+    c1.close()
+    for r, b in zip(tuned, base):
+        assert r["status"] == 0 and r["neval"] == b["neval"]
+        assert _rel(r["integral"], b["integral"]) < 1e-12
+        assert _rel(r["error"], b["error"]) < 1e-11
+
