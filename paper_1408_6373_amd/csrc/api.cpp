@@ -366,7 +366,7 @@ int vegas_finish(ccuba_ctx *ctx, VegasEngine &eng, long long *neval, int *fail,
     if (n > 0 && (trace->iter_I || trace->iter_var))
       if ((rc = eng.read_history(0, n, trace->iter_I, trace->iter_var, ctx->stream))) return rc;
     if (trace->grid)
-      if ((rc = eng.read_grid(0, st[0].T, trace->grid, ctx->stream))) return rc;
+      if ((rc = eng.read_grid(0, trace->grid, ctx->stream))) return rc;
   }
   return CCUBA_OK;
 }
@@ -472,7 +472,7 @@ int ccuba_vegas_dosample_raw(ccuba_ctx *ctx, int ndim, int nbins, const ccuba_in
   VegasEngine eng(ctx);
   if ((rc = eng.setup({sp}, true, s))) return rc;
   if ((rc = eng.set_iteration(0, iteration, s))) return rc;
-  if ((rc = eng.load_grid(0, iteration & 1, grid_dev, hipMemcpyDeviceToDevice, s))) return rc;
+  if ((rc = eng.load_grid(0, grid_dev, hipMemcpyDeviceToDevice, s))) return rc;
   if ((rc = eng.dosample_only(s, true))) return rc;
   if ((rc = eng.collect(sums_dev, hist_dev, s))) return rc;
   // the engine's buffers are released on return: finish before that

@@ -30,7 +30,7 @@ struct VJob {
   int hist_cap;           // capacity of the per-iteration history
   int pad;
   VState *state;
-  double *grid;           // two copies of ndim * (nbins + 1), by iteration parity
+  double *grid;           // ndim * (nbins + 1) edges, refined in place
   double *tsums;          // [ntiles][2]
   double *thist;          // [ntiles][ndim * nbins]
   double *gsums;          // [ngroups][2]

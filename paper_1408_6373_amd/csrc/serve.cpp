@@ -195,7 +195,7 @@ int Server::activate(Req &r) {
   const long long dN = (long long)sp.ndim * sp.nbins, row = (long long)sp.ndim * (sp.nbins + 1);
   const int cap = std::max(1, iters);
   int rc;
-  if ((rc = r.grid.alloc(ctx_, 2 * row)) || (rc = r.tsums.alloc(ctx_, 2 * nt)) ||
+  if ((rc = r.grid.alloc(ctx_, row)) || (rc = r.tsums.alloc(ctx_, 2 * nt)) ||
       (rc = r.thist.alloc(ctx_, nt * dN)) || (rc = r.gsums.alloc(ctx_, 2 * ng)) ||
       (rc = r.ghist.alloc(ctx_, ng * dN)) || (rc = r.hsum.alloc(ctx_, 2 + dN)) ||
       (rc = r.iters.alloc(ctx_, 2 * (size_t)cap)) ||
@@ -338,6 +338,7 @@ int Server::tick() {
     A.jobs = jobs_.p;
     A.tile_job = tiles_.p;
     A.hist64 = ctx_->tune[FP32].hist64;
+    A.njobs = (int)table.size();
     if ((rc = launch_tile_groups(ctx_, A, groups, s))) return rc;
     long long ftot = 0, ftot2 = 0;
     fold_tasks(table, ends, &ftot, &ftot2);

@@ -16,6 +16,8 @@ struct VegasArgs {
   int hist64;           // FP32 path: FP64 LDS histogram (else 64-bit fixed point)
   int ilp;              // points per lane per trip (1 or 2)
   long long lds_hist_byte_off;
+  int njobs;  // jobs in the table (1: every tile is job 0's)
+  int pad;
 };
 
 // The fold launch: task_end[j] = inclusive prefix over jobs of
@@ -60,9 +62,9 @@ void dosample_fns_f32hfx(std::vector<const void *> &fns);
 // (group rows -> hsum), which only the raw DoSample entry point needs.
 hipError_t launch_fold(const FoldArgs &F, bool level2, hipStream_t s);
 hipError_t launch_refine(const VegasArgs &A, int njobs, size_t lds, hipStream_t s);
-// Uniform starting grids (both copies) of jobs[0, njobs) (device table).
+// Uniform starting grids of jobs[0, njobs) (device table).
 hipError_t launch_init_grids(const VJob *jobs, int njobs, hipStream_t s);
-// The same for one grid of ndim rows of nbins + 1 edges (both copies).
+// The same for one grid of ndim rows of nbins + 1 edges.
 hipError_t launch_init_grid(double *grid, int ndim, int nbins, hipStream_t s);
 hipError_t launch_collect(const VegasArgs &A, int njobs, double *sums, double *hist,
                           hipStream_t s);

@@ -64,11 +64,17 @@ __device__ double gamma_p(double a, double x) {
   return 1.0 - lead * h;
 }
 
+static_assert(kGroupTiles % 32 == 0, "a group's tile sums fill whole wavefronts");
+constexpr int kFoldBatch = kGroupTiles < 64 ? kGroupTiles : 64;  // rows in flight per lane
+constexpr int kTsPer = 2 * kGroupTiles / 64;  // a group's tile sums per lane
+
 // Fold the per-tile partials of every running integral: one wavefront per
 // (integral, group of kGroupTiles tiles, 64-bin chunk) sums the group's tile
 // rows in tile order; the chunk-0 wave of a group also folds the tile sums.
 __global__ void __launch_bounds__(256) vegas_fold_kernel(FoldArgs F) {
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // the task index is the same for the whole wavefront: saying so makes the
+  // job lookups scalar loads, issued together
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const long long g = (long long)blockIdx.x * 4 + w;
   if (g >= F.total) return;  // whole waves only; no block barrier here
   int lo = 0, hi = F.njobs - 1;
@@ -79,31 +85,57 @@ __global__ void __launch_bounds__(256) vegas_fold_kernel(FoldArgs F) {
     else
       lo = mid + 1;
   }
-  const VJob &J = F.jobs[lo];
-  if (J.state->done) return;
-  const long long local = g - (lo > 0 ? F.task_end[lo - 1] : 0);
-  const int dN = J.ndim * J.nbins, nch = (dN + 63) >> 6;
-  const int grp = (int)(local / nch), ch = (int)(local - (long long)grp * nch);
-  const int t0 = grp * kGroupTiles, t1 = min(t0 + kGroupTiles, J.ntiles);
+  const long long base = lo > 0 ? F.task_end[lo - 1] : 0;
+  const uint32_t jw = load_words<kJobWords>(F.jobs + lo, lane);
+  const int dN = JOB_FIELD(jw, ndim) * JOB_FIELD(jw, nbins), nch = (dN + 63) >> 6;
+  const int local = (int)(g - base);  // a job has fewer than 2^31 tasks
+  const int grp = local / nch, ch = local - grp * nch;
+  const int t0 = grp * kGroupTiles, nt = min(t0 + kGroupTiles, JOB_FIELD(jw, ntiles)) - t0;
   const int bin = ch * 64 + lane;
-  if (bin < dN) {
-    // all of the group's rows are loaded before the in-order sum, so that
-    // the loads are in flight together
-    const double *src = J.thist + (long long)t0 * dN + bin;
-    const int nt = t1 - t0;
-    double v[kGroupTiles];
+  // Every load of the wave's first batch -- the done flag, the group's tile
+  // rows and, in chunk 0, the group's tile sums (kTsPer values per lane) --
+  // is issued before any of them is used, so that together they are one
+  // round trip to memory.  (The rows are allocated whether or not the
+  // integral is done.)
+  const int done = *gload(&JOB_FIELD(jw, state)->done);
+  const gbl<double> *src = gload(JOB_FIELD(jw, thist)) + (long long)t0 * dN + (bin < dN ? bin : 0);
+  const gbl<double> *tsp = gload(JOB_FIELD(jw, tsums)) + 2ll * t0;
+  double ts[kTsPer];
 #pragma unroll
-    for (int q = 0; q < kGroupTiles; ++q) v[q] = q < nt ? src[(long long)q * dN] : 0.0;
-    double s = 0.0;
+  for (int k = 0; k < kTsPer; ++k)
+    ts[k] = (ch == 0 && 64 * k + lane < 2 * nt) ? tsp[64 * k + lane] : 0.0;
+  double s = 0.0;
+  for (int q0 = 0; q0 < nt; q0 += kFoldBatch) {
+    double v[kFoldBatch];
 #pragma unroll
-    for (int q = 0; q < kGroupTiles; ++q)
-      if (q < nt) s += v[q];
-    J.ghist[(long long)grp * dN + bin] = s;
+    for (int q = 0; q < kFoldBatch; ++q)
+      v[q] = (bin < dN && q0 + q < nt) ? src[(long long)(q0 + q) * dN] : 0.0;
+    // keeps the compiler from folding each add into its load's branch, which
+    // would wait for every load before issuing the next
+    asm volatile("" ::: "memory");
+    if (done) return;
+    // tile order; the first row starts the sum (a group has at least one
+    // tile; starting from 0.0 would put the first add, and a wait, inside
+    // the loads)
+    if (q0 == 0) s = v[0];
+#pragma unroll
+    for (int q = 0; q < kFoldBatch; ++q)
+      if ((q0 > 0 || q > 0) && q0 + q < nt) s += v[q];
   }
-  if (ch == 0 && lane < 2) {
-    double s = 0.0;
-    for (int t = t0; t < t1; ++t) s += J.tsums[2 * t + lane];
-    J.gsums[2 * grp + lane] = s;
+  if (bin < dN) gstore(JOB_FIELD(jw, ghist))[(long long)grp * dN + bin] = s;
+  if (ch == 0) {  // the tile sums in tile order, read across the lanes
+    double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < kTsPer; ++k)
+      for (int q = 32 * k; q < min(nt, 32 * k + 32); ++q) {
+        s1 += lane_value(ts[k], 2 * q - 64 * k);
+        s2 += lane_value(ts[k], 2 * q + 1 - 64 * k);
+      }
+    if (lane == 0) {
+      gbl<double> *gs = gstore(JOB_FIELD(jw, gsums));
+      gs[2 * grp] = s1;
+      gs[2 * grp + 1] = s2;
+    }
   }
 }
 
@@ -165,57 +197,105 @@ __device__ __forceinline__ void wave_sync_lds() {
 // histogram row is smoothed, damped and prefix-summed with wave-wide scans
 // (lanes own contiguous runs of bins), and every new edge is placed by a
 // binary search of the prefix sums.
-__global__ void __launch_bounds__(1024) vegas_refine_kernel(VegasArgs A) {
+constexpr int kRefineThreads = 1024;  // the refine kernel's block (launch_refine)
+
+__global__ void __launch_bounds__(kRefineThreads) vegas_refine_kernel(VegasArgs A) {
   extern __shared__ __align__(16) double rsm[];
   __shared__ int s_mode;
-  const int jb = blockIdx.x, tid = threadIdx.x, bs = blockDim.x;
-  const int lane = tid & 63, wv = tid >> 6, nwv = bs >> 6;
-  const VJob J = A.jobs[jb];
-  VState st = *J.state;
-  if (st.done) return;
-  const int d = J.ndim, N = J.nbins, dN = d * N, row = N + 1;
-  const int t = st.T;
-  double *H = rsm;       // histogram, later prefix sums of m
-  double *D = rsm + dN;  // smoothed histogram, later m
   __shared__ double s_sums[2];
+  __shared__ __align__(16) uint32_t s_stw[kStateWords];  // the state, word by word
+  // (a constant block size: reading blockDim would be one more wait)
+  constexpr int bs = kRefineThreads, nwv = kRefineThreads / 64;
+  const int jb = blockIdx.x, tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  // Every wavefront holds the job descriptor, one word per lane.
+  const uint32_t jw = load_words<kJobWords>(A.jobs + jb, lane);
+  const int d = JOB_FIELD(jw, ndim), N = JOB_FIELD(jw, nbins);
+  const int dN = d * N, row = N + 1, drow = d * row;
+  const int ng = ngroups_of(JOB_FIELD(jw, ntiles));
+  double *grid = JOB_FIELD(jw, grid);
+  const double *gsums = JOB_FIELD(jw, gsums);
+  double *H = rsm;           // histogram, later prefix sums of m
+  double *D = rsm + dN;      // smoothed histogram, later m
+  double *G = rsm + 2 * dN;  // the current grid
+  // One round trip to memory for all of: the state (a word per lane of the
+  // first wavefront), the first 32 groups' sums (a value per lane), the
+  // grid and the group rows.  (The grid is staged in LDS before any of it is
+  // rewritten: the new edges replace the old ones in place.)
+  const uint32_t stw = wv == 0 ? load_words<kStateWords>(JOB_FIELD(jw, state), lane) : 0u;
+  const double gsv = (tid < 2 * min(ng, 32)) ? gload(gsums)[tid] : 0.0;
+  constexpr int kGridPer = (kMaxDim * (kMaxBins + 1) + kRefineThreads - 1) / kRefineThreads;
+  double g0[kGridPer];
+#pragma unroll
+  for (int q = 0; q < kGridPer; ++q) {
+    const int e = tid + q * bs;
+    g0[q] = e < drow ? gload(grid)[e] : 0.0;
+  }
   // the last fold level: the group rows in group order (the order of the
   // separate second-level fold, so both give the same sums)
-  const int ng = ngroups_of(J.ntiles);
   constexpr int kBatch = 32;  // loads in flight per thread before the adds
+  const gbl<double> *ghist = gload(JOB_FIELD(jw, ghist));
   for (int e = tid; e < dN; e += bs) {
-    const double *src = J.ghist + e;
+    const gbl<double> *src = ghist + e;
     double h = 0.0;
     for (int q0 = 0; q0 < ng; q0 += kBatch) {
       double v[kBatch];
 #pragma unroll
       for (int q = 0; q < kBatch; ++q) v[q] = q0 + q < ng ? src[(long long)(q0 + q) * dN] : 0.0;
+      asm volatile("" ::: "memory");  // every load of the batch before the adds
+      // (the first group row starts the sum: there is at least one group)
+      if (q0 == 0) h = v[0];
 #pragma unroll
       for (int q = 0; q < kBatch; ++q)
-        if (q0 + q < ng) h += v[q];
+        if ((q0 > 0 || q > 0) && q0 + q < ng) h += v[q];
     }
     H[e] = h;
   }
-  if (tid < 2) {
-    double h = 0.0;
-    for (int q0 = 0; q0 < ng; q0 += kBatch) {
+  if (wv == 0) {
+    if (lane < kStateWords) s_stw[lane] = stw;
+    // the group sums in group order: the first 32 read across the lanes
+    double h1 = 0.0, h2 = 0.0;
+    for (int q = 0; q < min(ng, 32); ++q) {
+      h1 += lane_value(gsv, 2 * q);
+      h2 += lane_value(gsv, 2 * q + 1);
+    }
+    for (int q0 = 32; q0 < ng; q0 += kBatch) {
       double v[kBatch];
 #pragma unroll
-      for (int q = 0; q < kBatch; ++q) v[q] = q0 + q < ng ? J.gsums[2 * (q0 + q) + tid] : 0.0;
+      for (int q = 0; q < kBatch; ++q)
+        v[q] = (lane < 2 && q0 + q < ng) ? gload(gsums)[2 * (q0 + q) + lane] : 0.0;
 #pragma unroll
       for (int q = 0; q < kBatch; ++q)
-        if (q0 + q < ng) h += v[q];
+        if (q0 + q < ng) {
+          h1 += lane_value(v[q], 0);
+          h2 += lane_value(v[q], 1);
+        }
     }
-    s_sums[tid] = h;
+    if (lane == 0) {
+      s_sums[0] = h1;
+      s_sums[1] = h2;
+    }
   }
   __syncthreads();
+  // (state words read as written, uint32_t; the whole state by memcpy below)
+  if (s_stw[offsetof(VState, done) / 4] != 0u) return;  // the same for the whole block
+  const int t = (int)s_stw[offsetof(VState, T) / 4];
+#pragma unroll
+  for (int q = 0; q < kGridPer; ++q) {
+    const int e = tid + q * bs;
+    if (e < drow) G[e] = g0[q];
+  }
   if (tid == 0) {
-    const long long n = J.nstart + (long long)t * J.nincrease;
+    VState st;
+    __builtin_memcpy(&st, s_stw, sizeof(VState));
+    const long long nstart = JOB_FIELD(jw, nstart), ninc = JOB_FIELD(jw, nincrease);
+    const long long n = nstart + (long long)t * ninc;
     const double S1 = s_sums[0], S2 = s_sums[1];
     const double I = S1 / (double)n;
     double var = S2 / (double)n - I * I;
     if (var < 0.0) var = 0.0;
     var /= (double)(n - 1);
-    double *hI = J.iter_I, *hV = J.iter_var;
+    double *hI = JOB_FIELD(jw, iter_I), *hV = JOB_FIELD(jw, iter_var);
     hI[t] = I;
     hV[t] = var;
     const int T = t + 1;
@@ -239,13 +319,14 @@ __global__ void __launch_bounds__(1024) vegas_refine_kernel(VegasArgs A) {
       st.integral = st.sum_wI / st.sum_w;
       st.error = sqrt(1.0 / st.sum_w);
     }
-    const double tol = fmax(J.epsabs, J.epsrel * fabs(st.integral));
-    const bool conv = st.neval >= J.mineval && st.error <= tol;
-    const long long nnext = J.nstart + (long long)T * J.nincrease;
+    const double tol = fmax(JOB_FIELD(jw, epsabs), JOB_FIELD(jw, epsrel) * fabs(st.integral));
+    const bool conv = st.neval >= JOB_FIELD(jw, mineval) && st.error <= tol;
+    const long long nnext = nstart + (long long)T * ninc;
     if (conv) {
       st.done = 1;
       st.fail = 0;
-    } else if (st.neval + nnext > J.maxeval || T >= J.hist_cap || nnext >= (1ll << 32)) {
+    } else if (st.neval + nnext > JOB_FIELD(jw, maxeval) || T >= JOB_FIELD(jw, hist_cap) ||
+               nnext >= (1ll << 32)) {
       st.done = 1;
       st.fail = 1;
     }
@@ -261,22 +342,21 @@ __global__ void __launch_bounds__(1024) vegas_refine_kernel(VegasArgs A) {
       st.prob = st.dof > 0 ? gamma_p(0.5 * st.dof, 0.5 * chi2) : 0.0;
     }
     st.hcap = (float)(1024.0 * (S2 / (double)n));
-    *J.state = st;
-    s_mode = conv ? 0 : ((J.flags & FLAG_FREEZE_GRID) ? 2 : 1);
+    *JOB_FIELD(jw, state) = st;
+    s_mode = conv ? 0 : ((JOB_FIELD(jw, flags) & FLAG_FREEZE_GRID) ? 2 : 1);
   }
   __syncthreads();
   const int mode = s_mode;
   if (mode == 0) return;
-  const double *Eold = J.grid + (long long)(t & 1) * d * row;
-  double *Enew = J.grid + (long long)((t + 1) & 1) * d * row;
+  double *Enew = grid;  // in place: every old edge is read from G
   if (mode == 2) {
-    for (int e = tid; e < d * row; e += bs) Enew[e] = Eold[e];
+    for (int e = tid; e < drow; e += bs) Enew[e] = G[e];
     return;
   }
   const int per = (N + 63) >> 6;  // contiguous bins per lane
   for (int j = wv; j < d; j += nwv) {
     double *h = H + j * N, *dd = D + j * N;
-    const double *Eo = Eold + j * row;
+    const double *Eo = G + j * row;
     double *En = Enew + j * row;
     const int k0 = lane * per, k1 = min(k0 + per, N);
     // smoothing and the two row sums
@@ -345,16 +425,16 @@ __global__ void __launch_bounds__(1024) vegas_refine_kernel(VegasArgs A) {
   }
 }
 
-// Uniform starting grids, E_j[k] = k/N in both copies, one workgroup per job
-// (the same division the host would do, so the grids are the same).
+// Uniform starting grids, E_j[k] = k/N, one workgroup per job (the same
+// division the host would do, so the grids are the same).
 __global__ void __launch_bounds__(256) vegas_init_grids_kernel(const VJob *jobs) {
   const VJob &J = jobs[blockIdx.x];
-  const int N = J.nbins, row = N + 1, tot = 2 * J.ndim * row;
+  const int N = J.nbins, row = N + 1, tot = J.ndim * row;
   for (int e = threadIdx.x; e < tot; e += blockDim.x) J.grid[e] = (double)(e % row) / N;
 }
 
 __global__ void __launch_bounds__(256) vegas_init_grid_kernel(double *grid, int d, int N) {
-  const int row = N + 1, tot = 2 * d * row;
+  const int row = N + 1, tot = d * row;
   for (int e = threadIdx.x; e < tot; e += blockDim.x) grid[e] = (double)(e % row) / N;
 }
 
@@ -435,7 +515,7 @@ hipError_t launch_fold(const FoldArgs &F, bool level2, hipStream_t s) {
 
 hipError_t launch_refine(const VegasArgs &A, int njobs, size_t lds, hipStream_t s) {
   // one wavefront per dimension (up to 16)
-  hipLaunchKernelGGL(vegas_refine_kernel, dim3(njobs), dim3(1024), lds, s, A);
+  hipLaunchKernelGGL(vegas_refine_kernel, dim3(njobs), dim3(kRefineThreads), lds, s, A);
   return hipGetLastError();
 }
 

@@ -115,7 +115,8 @@ void plan_tile_groups(std::vector<VJob> &jobs, std::vector<int> &tiles,
       const size_t csz = p == FP64 ? 16 : 8, hsz = (p == FP32 && !hist64) ? 16 : 8;
       g.grid_bytes = std::max(g.grid_bytes, align16(dN * csz));
       hb = std::max(hb, dN * hsz);
-      ref = std::max(ref, 2 * dN * 8);
+      // refine: histogram, smoothed histogram and the current grid
+      ref = std::max(ref, (2 * dN + (size_t)J.ndim * (J.nbins + 1)) * 8);
     }
     g.count = (int)tiles.size() - g.first;
     g.lds = g.grid_bytes + hb;
@@ -229,7 +230,7 @@ int VegasEngine::setup(const std::vector<VegasSpec> &specs, bool single, hipStre
     const long long dN = (long long)sp.ndim * sp.nbins, row = (long long)sp.ndim * (sp.nbins + 1);
     off[j] = Offsets{goff, thoff, ghoff, ioff, tile0, group0, hsoff};
     hsoff += 2 + dN;
-    goff += 2 * row;
+    goff += row;
     thoff += nt * dN;
     ghoff += ngroups_of(nt) * dN;
     ioff += J.hist_cap;
@@ -303,6 +304,7 @@ int VegasEngine::setup(const std::vector<VegasSpec> &specs, bool single, hipStre
   args_.tile_first = 0;
   args_.tile_count = ntiles_;
   args_.hist64 = hist64_;
+  args_.njobs = n;
   pending_.clear();
   iter_launched_ = 0;
   // captured graphs stay valid only while every kernel argument they hold
@@ -475,12 +477,11 @@ int VegasEngine::read_history(int job, int n, double *I, double *var, hipStream_
   return CCUBA_OK;
 }
 
-int VegasEngine::read_grid(int job, int T, double *grid, hipStream_t s) {
+int VegasEngine::read_grid(int job, double *grid, hipStream_t s) {
   if (job < 0 || job >= njobs()) return CCUBA_EINVAL;
   const VJob &J = hjobs_[job];
   const long long row = (long long)J.ndim * (J.nbins + 1);
-  CCUBA_HIP(hipMemcpyAsync(grid, J.grid + (long long)(T & 1) * row,
-                           row * sizeof(double), hipMemcpyDeviceToHost, s));
+  CCUBA_HIP(hipMemcpyAsync(grid, J.grid, row * sizeof(double), hipMemcpyDeviceToHost, s));
   CCUBA_HIP(hipStreamSynchronize(s));
   return CCUBA_OK;
 }
@@ -495,12 +496,10 @@ int VegasEngine::set_iteration(int job, int t, hipStream_t s) {
   return CCUBA_OK;
 }
 
-int VegasEngine::load_grid(int job, int copy, const double *src, hipMemcpyKind kind,
-                           hipStream_t s) {
+int VegasEngine::load_grid(int job, const double *src, hipMemcpyKind kind, hipStream_t s) {
   const VJob &J = hjobs_[job];
   const long long row = (long long)J.ndim * (J.nbins + 1);
-  CCUBA_HIP(hipMemcpyAsync(J.grid + (long long)(copy & 1) * row, src,
-                           row * sizeof(double), kind, s));
+  CCUBA_HIP(hipMemcpyAsync(J.grid, src, row * sizeof(double), kind, s));
   if (kind == hipMemcpyHostToDevice) CCUBA_HIP(hipStreamSynchronize(s));
   return CCUBA_OK;
 }
@@ -514,7 +513,7 @@ int VegasEngine::refine_only(const double *hist, const double *grid_in, double *
                              hipStream_t s) {
   const VJob &J = hjobs_[0];
   const long long dN = (long long)J.ndim * J.nbins;
-  int rc = load_grid(0, 0, grid_in, hipMemcpyHostToDevice, s);
+  int rc = load_grid(0, grid_in, hipMemcpyHostToDevice, s);
   if (rc) return rc;
   // a synthetic finished iteration with n = 2, S1 = 1, S2 = 2 (I = 1/2,
   // sigma^2 = 3/4 > 0, so the zero-tolerance job never converges)
@@ -529,7 +528,7 @@ int VegasEngine::refine_only(const double *hist, const double *grid_in, double *
   rc = set_iteration(0, 0, s);
   if (rc) return rc;
   CCUBA_HIP(launch_refine(args_, 1, lds_refine_, s));
-  return read_grid(0, 1, grid_out, s);
+  return read_grid(0, grid_out, s);
 }
 
 }  // namespace ccuba

@@ -61,11 +61,11 @@ class VegasEngine {
   int run(hipStream_t s);
   int read_states(std::vector<VState> &out, hipStream_t s);
   int read_history(int job, int n, double *I, double *var, hipStream_t s);
-  int read_grid(int job, int T, double *grid, hipStream_t s);
+  int read_grid(int job, double *grid, hipStream_t s);
   // Raw pieces: set iteration index of job 0, run DoSample only, and sum the
   // group partials into caller buffers.
   int set_iteration(int job, int t, hipStream_t s);
-  int load_grid(int job, int copy, const double *src, hipMemcpyKind kind, hipStream_t s);
+  int load_grid(int job, const double *src, hipMemcpyKind kind, hipStream_t s);
   // the sampling kernels, then the fold (with level2 both levels, into
   // hsum); records `between` (if given) after the sampling kernels
   int dosample_only(hipStream_t s, bool level2 = false, hipEvent_t between = nullptr);

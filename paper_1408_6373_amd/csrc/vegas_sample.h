@@ -5,6 +5,7 @@
 // its own translation unit (vegas_sample_*.hip), so that the instances build
 // in parallel; vegas.hip dispatches to them.
 #pragma once
+#include <cstddef>
 #include <type_traits>
 #include <vector>
 
@@ -16,6 +17,77 @@
 namespace ccuba {
 
 // ---------------------------------------------------------------------------
+// Descriptors read as one word per lane: a single vector load brings a whole
+// VJob (or VState) into the wavefront, where field-by-field scalar loads are
+// issued as each field is first needed and can each cost a round trip to
+// memory.  Lanes past the descriptor's last word read nothing.
+constexpr int kJobWords = (int)(sizeof(VJob) / 4);
+constexpr int kStateWords = (int)(sizeof(VState) / 4);
+static_assert(sizeof(VJob) % 8 == 0 && kJobWords <= 64, "a VJob fits one wavefront");
+static_assert(sizeof(VState) % 8 == 0 && kStateWords <= 64, "a VState fits one wavefront");
+
+template <int NW>
+__device__ __forceinline__ uint32_t load_words(const void *p, int lane) {
+  return lane < NW ? ((const __attribute__((address_space(1))) uint32_t *)p)[lane] : 0u;
+}
+
+// The field at byte offset OFF of the descriptor whose words the wavefront
+// holds (a wave-uniform value).
+template <typename F, int OFF>
+__device__ __forceinline__ F word_field(uint32_t w) {
+  static_assert(OFF % 4 == 0 && (sizeof(F) == 4 || sizeof(F) == 8), "word-aligned field");
+  if constexpr (sizeof(F) == 4) {
+    const uint32_t v = (uint32_t)__builtin_amdgcn_readlane((int)w, OFF / 4);
+    F r;
+    __builtin_memcpy(&r, &v, 4);
+    return r;
+  } else {
+    const unsigned long long v =
+        (unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)w, OFF / 4) |
+        ((unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)w, OFF / 4 + 1) << 32);
+    F r;
+    __builtin_memcpy(&r, &v, 8);
+    return r;
+  }
+}
+#define JOB_FIELD(w, f) (word_field<decltype(VJob::f), (int)offsetof(VJob, f)>(w))
+
+// The whole descriptor from the words the wavefront holds (the reads of
+// fields the caller never uses are dropped).
+template <typename S>
+__device__ __forceinline__ S from_words(uint32_t w) {
+  constexpr int n = (int)(sizeof(S) / 4);
+  uint32_t words[n];
+#pragma unroll
+  for (int i = 0; i < n; ++i) words[i] = (uint32_t)__builtin_amdgcn_readlane((int)w, i);
+  S r;
+  __builtin_memcpy(&r, words, sizeof(S));
+  return r;
+}
+
+// A device pointer taken from a descriptor word is a generic pointer, and
+// loads through it are flat loads, which also count against the scalar
+// memory counter: a wait for any scalar load then waits for them too.
+// Loads through the global-address-space view are global loads.
+template <typename T>
+using gbl = __attribute__((address_space(1))) T;
+template <typename T>
+__device__ __forceinline__ const gbl<T> *gload(const T *p) {
+  return (const gbl<T> *)p;
+}
+template <typename T>
+__device__ __forceinline__ gbl<T> *gstore(T *p) {
+  return (gbl<T> *)p;
+}
+
+// The value lane l of the wavefront holds (l wave-uniform).
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // a3: the grid as staged in LDS.  Cell k of dimension j sits at [j * N + k]
 // and holds its lower edge and its span in the working precision: the width
 // E[k+1] - E[k] for a general N, and N times the width when N = 2^L.  Both
@@ -28,17 +100,37 @@ struct alignas(2 * sizeof(T)) Cell {
   T lo, span;
 };
 
+// Each thread loads the edges of kStageCells cells before it stores any, so
+// that the whole grid of a typical integral (up to kStageCells * blockDim
+// cells) arrives in one round trip to memory.  Indices past the end are
+// clamped to the last cell: their loads stay in range and nothing is stored.
+constexpr int kStageCells = 4;
+
 template <typename T, bool POW2>
 __device__ __forceinline__ void stage_cells(const double *__restrict__ E, int d, int N,
                                             Cell<T> *sC) {
-  const int row = N + 1, dN = d * N;
+  const int row = N + 1, dN = d * N, bs = blockDim.x;
   const T Nt = (T)N;
-  for (int e = threadIdx.x; e < dN; e += blockDim.x) {
-    const int j = e / N, k = e - j * N;
-    const T lo = (T)E[j * row + k];
-    const T hi = (T)E[j * row + k + 1];
-    sC[e] = Cell<T>{lo, POW2 ? Nt * (hi - lo) : hi - lo};
-  }
+  const gbl<double> *Eg = gload(E);
+  auto batch = [&](int e0) {
+    double lo[kStageCells], hi[kStageCells];
+#pragma unroll
+    for (int b = 0; b < kStageCells; ++b) {
+      const int e = min(e0 + b * bs, dN - 1), j = e / N, k = e - j * N;
+      lo[b] = Eg[j * row + k];
+      hi[b] = Eg[j * row + k + 1];
+    }
+#pragma unroll
+    for (int b = 0; b < kStageCells; ++b) {
+      const int e = e0 + b * bs;
+      const T l = (T)lo[b], h = (T)hi[b];
+      if (e < dN) sC[e] = Cell<T>{l, POW2 ? Nt * (h - l) : h - l};
+    }
+  };
+  // the first batch outside the loop: a loop head would wait for every load
+  // in flight (the caller's too) before reusing the batch's registers
+  batch(threadIdx.x);
+  for (int e0 = threadIdx.x + kStageCells * bs; e0 < dN; e0 += kStageCells * bs) batch(e0);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -46,6 +138,7 @@ __device__ __forceinline__ double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
+
 
 template <typename T>
 __device__ __forceinline__ const T *param_ptr(const VJob &J, int which);
@@ -163,8 +256,8 @@ struct FixedHist<unsigned long long> : std::true_type {};
 template <typename T, typename HT, int FAM, int NB, int ILP, bool POW2, bool FULL>
 __device__ __forceinline__ void sample_tile(const VJob &J, int t, long long i0, int cnt,
                                             const Cell<T> *__restrict__ sC, HT *sH,
-                                            const T *__restrict__ p0,
-                                            const T *__restrict__ p1, int E, float cap,
+                                            const T (&pp0)[4 * NB], const T (&pp1)[4 * NB],
+                                            int E, float cap,
                                             double *sHx, double &S1, double &S2) {
   constexpr int ND = 4 * NB;
   const int d = J.ndim, N = J.nbins;
@@ -173,13 +266,7 @@ __device__ __forceinline__ void sample_tile(const VJob &J, int t, long long i0, 
   const T scale = pow2_scale<T>(L);
   const uint32_t c1 = (uint32_t)t << 8;
   const uint32_t sid = J.sid, k0 = J.key0, k1 = J.key1;
-  T pp0[ND], pp1[ND];
-#pragma unroll
-  for (int j = 0; j < ND; ++j) {  // parameter rows are zero-padded to 16
-    pp0[j] = p0[j];
-    pp1[j] = p1[j];
-  }
-  const T phase0 = p1[0];
+  const T phase0 = pp1[0];
   const int bs = blockDim.x;
   // an assembly comment naming the family, so that the per-point loop that
   // follows can be found in the assembly listing (it emits no instruction)
@@ -273,14 +360,34 @@ __global__ void __launch_bounds__(256) vegas_dosample_kernel(VegasArgs A) {
 
   const int tend = A.tile_first + A.tile_count;
   for (int tt = A.tile_first + blockIdx.x; tt < tend; tt += gridDim.x) {
-    const int jb = A.tile_job[tt];
-    const VJob J = A.jobs[jb];
+    // the descriptor as one vector load (a word per lane); with one job in
+    // the launch its index needs no lookup
+    const int jb = A.njobs == 1 ? 0 : A.tile_job[tt];
+    const VJob J = from_words<VJob>(load_words<kJobWords>(A.jobs + jb, lane));
     if (J.prec != myprec || ((J.ndim + 3) >> 2) != NB ||
         ((J.nbins & (J.nbins - 1)) == 0) != POW2 || (J.ndim == 4 * NB) != FULL)
       continue;
-    const VState st = *J.state;
-    if (st.done) continue;
-    const int d = J.ndim, N = J.nbins, dN = d * N, row = N + 1;
+    const int d = J.ndim, N = J.nbins, dN = d * N;
+    // One round trip to memory for: the state (a word per lane), the
+    // integrand's parameters (rows zero-padded to 16) and the grid cells
+    // (staged into LDS whether or not the integral turns out to be done).
+    uint32_t sw = load_words<kStateWords>(J.state, lane);
+    constexpr int ND = 4 * NB;
+    T pp0[ND], pp1[ND];
+    {
+      const gbl<T> *p0 = gload(param_ptr<T>(J, 0)), *p1 = gload(param_ptr<T>(J, 1));
+#pragma unroll
+      for (int j = 0; j < ND; ++j) {
+        pp0[j] = p0[j];
+        pp1[j] = p1[j];
+      }
+    }
+    stage_cells<T, POW2>(J.grid, d, N, sC);
+    // the state words are first used here, after the cells' loads are issued
+    // (without this the compiler waits for them before issuing those loads)
+    asm volatile("" : "+v"(sw)::"memory");
+    const VState st = from_words<VState>(sw);
+    if (st.done) continue;  // the same for the whole block: nothing read the cells yet
     const int lt = tt - J.tile0;
     const long long n_t = J.nstart + (long long)st.T * J.nincrease;
     const long long i0 = (long long)lt * J.tile_pts;
@@ -288,7 +395,6 @@ __global__ void __launch_bounds__(256) vegas_dosample_kernel(VegasArgs A) {
     c = c < 0 ? 0 : (c > J.tile_pts ? J.tile_pts : c);
     const int cnt = (int)c;
 
-    stage_cells<T, POW2>(J.grid + (long long)(st.T & 1) * d * row, d, N, sC);
     for (int e = tid; e < dN; e += bs) sH[e] = (HT)0;
     double *sHx = (double *)(sH + dN);  // fixed point: the FP64 histogram above the cap
     if constexpr (FixedHist<HT>::value) {
@@ -297,8 +403,6 @@ __global__ void __launch_bounds__(256) vegas_dosample_kernel(VegasArgs A) {
     }
     __syncthreads();
 
-    const T *p0 = param_ptr<T>(J, 0);
-    const T *p1 = param_ptr<T>(J, 1);
     int E = 0;
     float cap = 0.0f;
     if constexpr (FixedHist<HT>::value) {
@@ -321,7 +425,7 @@ __global__ void __launch_bounds__(256) vegas_dosample_kernel(VegasArgs A) {
           float w = 1.0f, q = 1.0f;
           for (int j = 0; j < d; ++j) w = w * __uint_as_float(smax[j]);
           if (J.family == PRODUCT_PEAK) {
-            for (int j = 0; j < d; ++j) q = q * (float)p0[j];
+            for (int j = 0; j < d; ++j) q = q * (float)pp0[j];
             q = 1.0f / q;
           }
           const float v = w * q;
@@ -340,11 +444,11 @@ __global__ void __launch_bounds__(256) vegas_dosample_kernel(VegasArgs A) {
     }
     double S1 = 0.0, S2 = 0.0;
     switch (J.family) {
-      case GAUSSIAN: sample_tile<T, HT, GAUSSIAN, NB, ILP, POW2, FULL>(J, st.T, i0, cnt, sC, sH, p0, p1, E, cap, sHx, S1, S2); break;
-      case OSCILLATORY: sample_tile<T, HT, OSCILLATORY, NB, ILP, POW2, FULL>(J, st.T, i0, cnt, sC, sH, p0, p1, E, cap, sHx, S1, S2); break;
-      case PRODUCT_PEAK: sample_tile<T, HT, PRODUCT_PEAK, NB, ILP, POW2, FULL>(J, st.T, i0, cnt, sC, sH, p0, p1, E, cap, sHx, S1, S2); break;
-      case CORNER_PEAK: sample_tile<T, HT, CORNER_PEAK, NB, ILP, POW2, FULL>(J, st.T, i0, cnt, sC, sH, p0, p1, E, cap, sHx, S1, S2); break;
-      default: sample_tile<T, HT, C0, NB, ILP, POW2, FULL>(J, st.T, i0, cnt, sC, sH, p0, p1, E, cap, sHx, S1, S2); break;
+      case GAUSSIAN: sample_tile<T, HT, GAUSSIAN, NB, ILP, POW2, FULL>(J, st.T, i0, cnt, sC, sH, pp0, pp1, E, cap, sHx, S1, S2); break;
+      case OSCILLATORY: sample_tile<T, HT, OSCILLATORY, NB, ILP, POW2, FULL>(J, st.T, i0, cnt, sC, sH, pp0, pp1, E, cap, sHx, S1, S2); break;
+      case PRODUCT_PEAK: sample_tile<T, HT, PRODUCT_PEAK, NB, ILP, POW2, FULL>(J, st.T, i0, cnt, sC, sH, pp0, pp1, E, cap, sHx, S1, S2); break;
+      case CORNER_PEAK: sample_tile<T, HT, CORNER_PEAK, NB, ILP, POW2, FULL>(J, st.T, i0, cnt, sC, sH, pp0, pp1, E, cap, sHx, S1, S2); break;
+      default: sample_tile<T, HT, C0, NB, ILP, POW2, FULL>(J, st.T, i0, cnt, sC, sH, pp0, pp1, E, cap, sHx, S1, S2); break;
     }
     S1 = wave_sum(S1);
     S2 = wave_sum(S2);
