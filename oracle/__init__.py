@@ -113,7 +113,8 @@ def genz(family, a, u, precision=FP64):
 
 
 def python_integrand(func):
-    """Wrap ``func(x[nvec, ndim]) -> f[nvec]`` (or -999 to abort) as integrand_t."""
+    """Wrap ``func(x[nvec, ndim]) -> f[nvec]`` or ``f[nvec, ncomp]`` (or -999 to
+    abort) as integrand_t."""
 
     def cb(ndim, x, ncomp, f, userdata, nvec, core):
         nd, nv, nc = ndim[0], nvec[0], ncomp[0]
@@ -121,9 +122,9 @@ def python_integrand(func):
         r = func(xs.copy())
         if isinstance(r, int) and r == -999:
             return -999
-        r = np.asarray(r, dtype=np.float64).reshape(nv)
-        for p in range(nv):
-            f[p * nc] = float(r[p])
+        r = np.asarray(r, dtype=np.float64).reshape(nv, nc)
+        fs = np.ctypeslib.as_array(f, shape=(nv * nc,))
+        fs[:] = r.reshape(-1)
         return 0
 
     cfn = INTEGRAND_T(cb)
@@ -170,26 +171,31 @@ def refine_dim(H, E):
 
 def vegas(integrand, ndim, *, epsrel=0.0, epsabs=0.0, flags=0, seed=1,
           mineval=0, maxeval=10**5, nstart=10**4, nincrease=0, nbatch=1000,
-          nbins=128, stream_id=0, nvec=1000, max_iter=4096):
+          nbins=128, stream_id=0, nvec=1000, max_iter=4096, ncomp=1):
+    """Serial Vegas.  With ncomp > 1 integral/error/prob are arrays of ncomp
+    values; iter_I, iter_var, chi2, dof and the grid are component 0's."""
     neval = C.c_longlong()
     fail = C.c_int()
-    integral = np.zeros(1)
-    error = np.zeros(1)
-    prob = np.zeros(1)
+    integral = np.zeros(ncomp)
+    error = np.zeros(ncomp)
+    prob = np.zeros(ncomp)
     It = np.zeros(max_iter)
     Vt = np.zeros(max_iter)
     grid = np.zeros(ndim * (nbins + 1))
     hist = np.zeros(ndim * nbins)
     tr = _VegasTrace(max_iter, 0, _dptr(It), _dptr(Vt), 0.0, 0, _dptr(grid), _dptr(hist))
-    rc = lib().oracle_vegas(ndim, 1, integrand.fn, integrand.userdata, nvec, epsrel,
+    rc = lib().oracle_vegas(ndim, ncomp, integrand.fn, integrand.userdata, nvec, epsrel,
                             epsabs, flags, seed, mineval, maxeval, nstart, nincrease,
                             nbatch, nbins, stream_id, C.byref(neval), C.byref(fail),
                             _dptr(integral), _dptr(error), _dptr(prob), C.byref(tr))
     if rc != 0:
         raise ValueError("oracle_vegas: bad arguments")
     n = tr.n_iter
-    return dict(neval=neval.value, fail=fail.value, integral=float(integral[0]),
-                error=float(error[0]), prob=float(prob[0]), iter_I=It[:n].copy(),
+    one = ncomp == 1
+    return dict(neval=neval.value, fail=fail.value,
+                integral=float(integral[0]) if one else integral.copy(),
+                error=float(error[0]) if one else error.copy(),
+                prob=float(prob[0]) if one else prob.copy(), iter_I=It[:n].copy(),
                 iter_var=Vt[:n].copy(), chi2=tr.chi2, dof=tr.dof,
                 grid=grid.reshape(ndim, nbins + 1), hist=hist.reshape(ndim, nbins))
 

@@ -100,7 +100,9 @@ typedef struct {
 
 /* Vegas integrator with the paper's argument list (Sect. 3.2.2) plus the
  * bin count and the Philox stream id.  Returns 0, or -1 for bad arguments.
- * fail: 0 accuracy reached, 1 maxeval reached first, -99 integrand aborted. */
+ * fail: 0 accuracy reached, 1 maxeval reached first, -99 integrand aborted.
+ * 1 <= ncomp <= 16: integral/error/prob hold ncomp values; the grid adapts to
+ * component 0; the trace records component 0. */
 int oracle_vegas(int ndim, int ncomp, oracle_integrand_t integrand,
                  void *userdata, int nvec, double epsrel, double epsabs,
                  int flags, unsigned long long seed, long long mineval,

@@ -28,7 +28,11 @@
 //    nstart + t nincrease points that would take neval past maxeval, stop
 //    with fail 1;
 //  * nbatch only partitions the sampling internally (Sect. 3.2.7) and has no
-//    effect on any result, so it is only validated here.
+//    effect on any result, so it is only validated here;
+//  * several components (ncomp > 1): every component has its own sums,
+//    iteration results, combination, chi^2 and probability over the same
+//    points; the one grid adapts to the histogram of component 0; the
+//    accuracy test needs every component within its tolerance.
 // All sums are Neumaier-compensated FP64 in point order.
 #include <cmath>
 #include <vector>
@@ -224,7 +228,7 @@ extern "C" int oracle_vegas(int ndim, int ncomp, oracle_integrand_t integrand,
                             int *fail, double integral[], double error[],
                             double prob[], oracle_vegas_trace *trace) {
   const int precision = flags & ORACLE_PRECISION_MASK;
-  if (ndim < 1 || ndim > 16 || ncomp != 1 || nvec < 1 || nbins < 2 ||
+  if (ndim < 1 || ndim > 16 || ncomp < 1 || ncomp > 16 || nvec < 1 || nbins < 2 ||
       nbins > 256 || nstart < 2 || nincrease < 0 || nbatch < 1 ||
       (precision != ORACLE_FP64 && precision != ORACLE_FP32_EVAL) ||
       !integrand)
@@ -235,8 +239,8 @@ extern "C" int oracle_vegas(int ndim, int ncomp, oracle_integrand_t integrand,
     for (int k = 0; k <= N; ++k) grid[(size_t)j * (N + 1) + k] = (double)k / N;
 
   std::vector<double> hist((size_t)ndim * N);
-  std::vector<double> It, vart;
-  Combined res{0.0, 0.0, 0.0, 0.0, -1};
+  std::vector<std::vector<double>> It(ncomp), vart(ncomp);
+  std::vector<Combined> res(ncomp, Combined{0.0, 0.0, 0.0, 0.0, -1});
   long long nev = 0;
   int status_fail = 1;
   std::vector<double> xbuf((size_t)nvec * ndim), fbuf((size_t)nvec * ncomp),
@@ -248,7 +252,7 @@ extern "C" int oracle_vegas(int ndim, int ncomp, oracle_integrand_t integrand,
     const long long n = nstart + (long long)t * nincrease;
     if (n >= (1ll << 32) || t >= (1 << 24)) break;
     if (nev + n > maxeval) break;
-    Neumaier s1, s2;
+    std::vector<Neumaier> s1(ncomp), s2(ncomp);
     std::vector<Neumaier> h((size_t)ndim * N);
     bool aborted = false;
     for (long long i0 = 0; i0 < n; i0 += nvec) {
@@ -265,37 +269,43 @@ extern "C" int oracle_vegas(int ndim, int ncomp, oracle_integrand_t integrand,
         nev += i0 + cnt;  // every point handed to the integrand counts
         break;
       }
-      for (int p = 0; p < cnt; ++p) {
-        double v;
-        if (precision == ORACLE_FP32_EVAL)
-          v = (double)((float)wbuf[p] * (float)fbuf[(size_t)p * ncomp]);
-        else
-          v = wbuf[p] * fbuf[(size_t)p * ncomp];
-        const double v2 = v * v;
-        s1.add(v);
-        s2.add(v2);
-        for (int j = 0; j < ndim; ++j)
-          h[(size_t)j * N + kbuf[(size_t)p * ndim + j]].add(v2);
-      }
+      for (int p = 0; p < cnt; ++p)
+        for (int c = 0; c < ncomp; ++c) {
+          double v;
+          if (precision == ORACLE_FP32_EVAL)
+            v = (double)((float)wbuf[p] * (float)fbuf[(size_t)p * ncomp + c]);
+          else
+            v = wbuf[p] * fbuf[(size_t)p * ncomp + c];
+          const double v2 = v * v;
+          s1[c].add(v);
+          s2[c].add(v2);
+          if (c == 0)
+            for (int j = 0; j < ndim; ++j)
+              h[(size_t)j * N + kbuf[(size_t)p * ndim + j]].add(v2);
+        }
     }
     if (aborted) {
       *neval = nev;
       *fail = -99;
-      integral[0] = error[0] = prob[0] = 0.0;
-      if (trace) trace->n_iter = (int)It.size();
+      for (int c = 0; c < ncomp; ++c) integral[c] = error[c] = prob[c] = 0.0;
+      if (trace) trace->n_iter = (int)It[0].size();
       return 0;
     }
     nev += n;
-    const double I = s1.value() / (double)n;
-    double var = s2.value() / (double)n - I * I;
-    if (var < 0.0) var = 0.0;
-    var /= (double)(n - 1);
-    It.push_back(I);
-    vart.push_back(var);
+    bool all = nev >= mineval;
+    for (int c = 0; c < ncomp; ++c) {
+      const double I = s1[c].value() / (double)n;
+      double var = s2[c].value() / (double)n - I * I;
+      if (var < 0.0) var = 0.0;
+      var /= (double)(n - 1);
+      It[c].push_back(I);
+      vart[c].push_back(var);
+      res[c] = combine(It[c], vart[c]);
+      const double tol = std::fmax(epsabs, epsrel * std::fabs(res[c].integral));
+      all = all && res[c].error <= tol;
+    }
     for (size_t q = 0; q < hist.size(); ++q) hist[q] = h[q].value();
-    res = combine(It, vart);
-    const double tol = std::fmax(epsabs, epsrel * std::fabs(res.integral));
-    if (nev >= mineval && res.error <= tol) {
+    if (all) {
       status_fail = 0;
       break;
     }
@@ -310,17 +320,19 @@ extern "C" int oracle_vegas(int ndim, int ncomp, oracle_integrand_t integrand,
   }
   *neval = nev;
   *fail = status_fail;
-  integral[0] = res.integral;
-  error[0] = res.error;
-  prob[0] = res.prob;
-  if (trace) {
-    trace->n_iter = (int)It.size();
-    for (int t = 0; t < (int)It.size() && t < trace->max_iter; ++t) {
-      if (trace->iter_I) trace->iter_I[t] = It[t];
-      if (trace->iter_var) trace->iter_var[t] = vart[t];
+  for (int c = 0; c < ncomp; ++c) {
+    integral[c] = res[c].integral;
+    error[c] = res[c].error;
+    prob[c] = res[c].prob;
+  }
+  if (trace) {  // component 0
+    trace->n_iter = (int)It[0].size();
+    for (int t = 0; t < (int)It[0].size() && t < trace->max_iter; ++t) {
+      if (trace->iter_I) trace->iter_I[t] = It[0][t];
+      if (trace->iter_var) trace->iter_var[t] = vart[0][t];
     }
-    trace->chi2 = res.chi2;
-    trace->dof = res.dof;
+    trace->chi2 = res[0].chi2;
+    trace->dof = res[0].dof;
     if (trace->grid)
       for (size_t q = 0; q < grid.size(); ++q) trace->grid[q] = grid[q];
     if (trace->hist)

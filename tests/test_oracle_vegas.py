@@ -156,3 +156,71 @@ def test_bad_arguments():
             O.vegas(one, 2, **kw)
     with pytest.raises(ValueError):
         O.vegas(one, 17)
+
+
+# ---------------------------------------------------------------------------
+# Several components (ncomp > 1): one set of points, per-component sums,
+# results and chi^2, the grid adapted to component 0, and an accuracy test
+# that needs every component.
+
+def _genz_py(fam, a, u):
+    return lambda x: O.genz_eval(fam, a, u, x)
+
+
+def test_components_scaled_by_two_are_exactly_twice():
+    # v_1 = w (2 g) = 2 v_0 exactly, so every sum, estimate, weight and error
+    # scales by a power of two (exact in binary floating point)
+    a, u = W.genz_params(1, 3, 4)
+    g = _genz_py(1, a, u)
+    one = O.vegas(O.python_integrand(g), 3, nstart=2000, maxeval=10000, nbins=32)
+    two = O.vegas(O.python_integrand(lambda x: np.stack([g(x), 2.0 * g(x)], 1)), 3,
+                  nstart=2000, maxeval=10000, nbins=32, ncomp=2)
+    assert two["integral"][0] == one["integral"] and two["error"][0] == one["error"]
+    assert two["integral"][1] == 2.0 * two["integral"][0]
+    assert two["error"][1] == 2.0 * two["error"][0]
+    assert two["prob"][1] == two["prob"][0]
+    assert np.array_equal(two["grid"], one["grid"])  # component 0 drives the grid
+    assert np.array_equal(two["iter_I"], one["iter_I"])
+
+
+def test_constant_component_is_exact():
+    # on the first (uniform) grid every weight is exactly 1, so a constant
+    # component has zero variance there, and the combination of a
+    # zero-variance iteration is exact: 1 with error 0, whatever the grid
+    # does afterwards
+    a, u = W.genz_params(0, 4, 5)
+    g = _genz_py(0, a, u)
+    r = O.vegas(O.python_integrand(lambda x: np.stack([g(x), np.ones(len(x))], 1)), 4,
+                nstart=1000, maxeval=5000, nbins=16, ncomp=2)
+    assert r["integral"][1] == 1.0 and r["error"][1] == 0.0 and r["prob"][1] == 0.0
+    assert r["neval"] == 5000 and r["fail"] == 1  # component 0 never met epsrel = 0
+
+
+def test_every_component_must_converge():
+    # component 0 alone stops early; a hard second component keeps the run
+    # going, and component 0's iterations are the same as far as both go
+    a, u = W.genz_params(2, 2, 6)
+    g = _genz_py(2, a, u)
+    h = lambda x: g(x) ** 1.5  # the same peak, sharper: needs more points
+    alone = O.vegas(O.python_integrand(g), 2, epsrel=1e-3, nstart=2000, maxeval=10**6,
+                    nbins=32)
+    both = O.vegas(O.python_integrand(lambda x: np.stack([g(x), h(x)], 1)), 2,
+                   epsrel=1e-3, nstart=2000, maxeval=10**6, nbins=32, ncomp=2)
+    n1 = len(alone["iter_I"])
+    assert alone["fail"] == 0 and both["fail"] == 0
+    assert len(both["iter_I"]) > n1
+    assert np.array_equal(both["iter_I"][:n1], alone["iter_I"])
+    for c in range(2):
+        assert both["error"][c] <= 1e-3 * abs(both["integral"][c])
+
+
+def test_abort_reports_every_component_zero():
+    calls = []
+
+    def f(x):
+        calls.append(1)
+        return -999 if len(calls) == 2 else np.ones((len(x), 3))
+
+    r = O.vegas(O.python_integrand(f), 2, nstart=3000, maxeval=10**5, nvec=1000, ncomp=3)
+    assert r["fail"] == -99 and r["neval"] == 2000
+    assert np.all(r["integral"] == 0) and np.all(r["error"] == 0)
