@@ -165,6 +165,43 @@ int ccuba_vegas_ex(ccuba_ctx **ctx, int ndim, int ncomp, const ccuba_integrand *
                    int *fail, double integral[], double error[], double prob[],
                    ccuba_vegas_trace *trace);
 
+/* ---- caller-evaluated integrands ---------------------------------------
+ * The integrand declaration of Sect. 3.2.2 with its nvec and core arguments:
+ * x[*nvec][*ndim] points, f[*nvec][*ncomp] values for the integrand to fill.
+ * Returning -999 aborts the integration at once; any other value goes on.
+ * core is -1: the points come in the accelerator strategy of Sect. 3.2.5. */
+typedef int (*ccuba_batch_integrand)(const int *ndim, const double x[], const int *ncomp,
+                                     double f[], void *userdata, const int *nvec,
+                                     const int *core);
+
+/* where the batch's x and f live during the integrand call */
+enum { CCUBA_POINTS_HOST = 0, CCUBA_POINTS_DEVICE = 1 };
+
+/* Vegas of a caller's integrand (the same sampling, combination and stop rule
+ * as ccuba_vegas, over ncomp components).  Each iteration's points are made
+ * on the GPU and handed to the integrand in batches of exactly nvec points
+ * (fewer only in an iteration's last batch; Sect. 3.2.5).  With
+ * CCUBA_POINTS_HOST x and f are host arrays the library owns; with
+ * CCUBA_POINTS_DEVICE they are device arrays on the context's GPU, and the
+ * integrand's writes to f must be complete when it returns (for work it
+ * launches itself, it synchronises first).  The integrand runs while the
+ * context is held and must not call back into the same context.
+ * Components: every one has its own sums, estimate, combination, chi^2 and
+ * prob over the same points; the grid adapts to component 0's histogram;
+ * the accuracy test needs every component within its tolerance.
+ * fail: 0 accuracy reached, 1 maxeval reached first, -99 the integrand
+ * returned -999 (then neval counts every point handed to it and the results
+ * are 0).  Ranges: 1 <= ndim <= 16, 1 <= ncomp <= 16, 2 <= nbins <= 256,
+ * nvec >= 1, nstart >= 2, nincrease >= 0, every n_t < 2^32.  integral, error
+ * and prob have ncomp entries.  Errors: CCUBA_EINVAL, CCUBA_EHIP,
+ * CCUBA_ENOMEM. */
+int ccuba_vegas_batched(ccuba_ctx **ctx, int ndim, int ncomp, ccuba_batch_integrand integrand,
+                        void *userdata, int nvec, int where, double epsrel, double epsabs,
+                        int flags, unsigned long long seed, long long mineval,
+                        long long maxeval, long long nstart, long long nincrease, int nbins,
+                        unsigned int stream_id, long long *neval, int *fail, double integral[],
+                        double error[], double prob[]);
+
 /* Cuhre (Sect. 3.2.2 prototype) with the degree-7 Genz-Malik rule and its
  * embedded degree-5 rule (Genz & Malik 1980), error |I7 - I5|, bisection of
  * each selected region along its largest fourth difference.  Each step splits

@@ -85,6 +85,15 @@ _sig("ccuba_vegas_dosample_raw", C.c_int, [_CTXP, C.c_int, C.c_int, C.POINTER(In
                                            C.c_longlong, C.c_void_p, C.c_void_p, C.c_void_p,
                                            C.c_void_p])
 _sig("ccuba_vegas_batch", C.c_int, [_CTXP, C.c_int, C.POINTER(Job), C.POINTER(Result)])
+# int integrand(const int *ndim, const double x[], const int *ncomp, double f[],
+#               void *userdata, const int *nvec, const int *core)
+BATCH_INTEGRAND = C.CFUNCTYPE(C.c_int, _ip, C.c_void_p, _ip, C.c_void_p, C.c_void_p, _ip, _ip)
+POINTS_HOST, POINTS_DEVICE = 0, 1
+_sig("ccuba_vegas_batched", C.c_int, [C.POINTER(_CTXP), C.c_int, C.c_int, BATCH_INTEGRAND,
+                                      C.c_void_p, C.c_int, C.c_int, C.c_double, C.c_double,
+                                      C.c_int, C.c_ulonglong, C.c_longlong, C.c_longlong,
+                                      C.c_longlong, C.c_longlong, C.c_int, C.c_uint, _llp, _ip,
+                                      _dp, _dp, _dp])
 if hasattr(_lib, "ccuba_cuhre"):
     _sig("ccuba_cuhre", C.c_int, [C.POINTER(_CTXP), C.c_int, C.c_int, C.POINTER(Integrand),
                                   C.c_double, C.c_double, C.c_int, C.c_longlong, C.c_longlong,
@@ -100,7 +109,7 @@ SYMBOLS = ["ccuba_init", "ccuba_shutdown", "ccuba_config", "ccuba_config_get",
            "ccuba_strerror", "ccuba_vegas",
            "ccuba_vegas_ex", "ccuba_cuhre", "ccuba_cuhre_rule", "ccuba_vegas_batch",
            "ccuba_submit", "ccuba_poll", "ccuba_drain", "ccuba_vegas_dosample_raw",
-           "ccuba_vegas_points", "ccuba_vegas_refine"]
+           "ccuba_vegas_points", "ccuba_vegas_refine", "ccuba_vegas_batched"]
 
 
 class CcubaError(RuntimeError):
@@ -244,6 +253,71 @@ def vegas_dosample_raw(ctx, family, a, u, nbins, iteration, npts, grid_ptr, sums
                                          C.c_void_p(hist_ptr),
                                          C.c_void_p(stream_ptr) if stream_ptr else None),
            "ccuba_vegas_dosample_raw")
+
+
+class _DeviceArray:
+    """A library-owned device buffer, seen through the array interface that
+    torch.as_tensor accepts (no copy)."""
+
+    def __init__(self, ptr, shape):
+        self.__cuda_array_interface__ = {"shape": shape, "typestr": "<f8",
+                                         "data": (ptr, False), "version": 2, "strides": None}
+
+
+def vegas_batched(func, ndim, ncomp=1, *, where="host", nvec=10000, ctx=None, epsrel=0.0,
+                  epsabs=0.0, flags=FP64, seed=1, mineval=0, maxeval=10**5, nstart=10**4,
+                  nincrease=0, nbins=128, stream_id=0):
+    """ccuba_vegas_batched: Vegas of a caller's integrand, in batches of nvec points.
+
+    where="host": ``func(x)`` gets a numpy array x of shape (m, ndim) and returns
+    f of shape (m,) or (m, ncomp), or -999 to abort.  where="device": ``func(x, f)``
+    gets torch tensors on the GPU, x of shape (m, ndim) and f of shape (m, ncomp),
+    fills f in place and may return -999; the binding waits for torch's current
+    stream after the call.  An exception raised by func aborts the run and is
+    raised again here.  Returns a dict with neval, fail, integral, error, prob
+    (floats for ncomp == 1, arrays otherwise)."""
+    if where not in ("host", "device"):
+        raise ValueError("where must be 'host' or 'device'")
+    raised = []
+
+    def cb(nd_p, x, nc_p, f, userdata, nv_p, core):
+        try:
+            nd, nc, nv = nd_p[0], nc_p[0], nv_p[0]
+            if where == "host":
+                xs = np.ctypeslib.as_array(C.cast(C.c_void_p(x), _dp), shape=(nv, nd))
+                r = func(xs)
+                if isinstance(r, int) and r == -999:
+                    return -999
+                fs = np.ctypeslib.as_array(C.cast(C.c_void_p(f), _dp), shape=(nv, nc))
+                fs[:] = np.asarray(r, dtype=np.float64).reshape(nv, nc)
+                return 0
+            import torch
+            xt = torch.as_tensor(_DeviceArray(x, (nv, nd)), device="cuda")
+            ft = torch.as_tensor(_DeviceArray(f, (nv, nc)), device="cuda")
+            r = func(xt, ft)
+            torch.cuda.current_stream().synchronize()
+            return -999 if (isinstance(r, int) and r == -999) else 0
+        except BaseException as e:  # reported after the library returns
+            raised.append(e)
+            return -999
+
+    cfn = BATCH_INTEGRAND(cb)
+    neval = C.c_longlong()
+    fail = C.c_int()
+    res = [np.zeros(ncomp) for _ in range(3)]
+    rc = _lib.ccuba_vegas_batched(_ctx_arg(ctx), ndim, ncomp, cfn, None, nvec,
+                                  POINTS_HOST if where == "host" else POINTS_DEVICE, epsrel,
+                                  epsabs, flags, seed, mineval, maxeval, nstart, nincrease,
+                                  nbins, stream_id, C.byref(neval), C.byref(fail),
+                                  _ptr(res[0]), _ptr(res[1]), _ptr(res[2]))
+    if raised:
+        raise raised[0]
+    _check(rc, "ccuba_vegas_batched")
+    one = ncomp == 1
+    out = dict(neval=neval.value, fail=fail.value)
+    for k, v in zip(("integral", "error", "prob"), res):
+        out[k] = float(v[0]) if one else v.copy()
+    return out
 
 
 def _struct_dtype(st):

@@ -11,6 +11,7 @@
 #include "cuhre_engine.h"
 #include "serve.h"
 #include "tune.h"
+#include "vegas_batched.h"
 #include "vegas_engine.h"
 
 using namespace ccuba;
@@ -297,6 +298,44 @@ int ccuba_stats_get(ccuba_ctx *ctx, ccuba_stats *out, int reset) {
   *out = ctx->stats;
   if (reset) ctx->stats = ccuba_stats{};
   return CCUBA_OK;
+}
+
+int ccuba_vegas_batched(ccuba_ctx **ctxp, int ndim, int ncomp, ccuba_batch_integrand integrand,
+                        void *userdata, int nvec, int where, double epsrel, double epsabs,
+                        int flags, unsigned long long seed, long long mineval,
+                        long long maxeval, long long nstart, long long nincrease, int nbins,
+                        unsigned int stream_id, long long *neval, int *fail, double integral[],
+                        double error[], double prob[]) {
+  const int prec = flags & CCUBA_PRECISION_MASK;
+  if (!integrand || !neval || !fail || !integral || !error || !prob || ndim < 1 ||
+      ndim > kMaxDim || ncomp < 1 || ncomp > kMaxComp || nbins < 2 || nbins > kMaxBins ||
+      nvec < 1 || (where != CCUBA_POINTS_HOST && where != CCUBA_POINTS_DEVICE) ||
+      (prec != CCUBA_FP64 && prec != CCUBA_FP32_EVAL) || nstart < 2 ||
+      nstart >= (1ll << 32) || nincrease < 0 || maxeval < 0 || mineval < 0 ||
+      !(epsrel >= 0) || !(epsabs >= 0))
+    return CCUBA_EINVAL;
+  BatchedSpec sp;
+  sp.ndim = ndim;
+  sp.ncomp = ncomp;
+  sp.nbins = nbins;
+  sp.prec = prec == CCUBA_FP32_EVAL ? FP32 : FP64;
+  sp.flags = flags;
+  sp.nvec = nvec;
+  sp.where = where;
+  sp.seed = seed;
+  sp.sid = stream_id;
+  sp.nstart = nstart;
+  sp.nincrease = nincrease;
+  sp.mineval = mineval;
+  sp.maxeval = maxeval;
+  sp.epsrel = epsrel;
+  sp.epsabs = epsabs;
+  CtxScope scope(ctxp);
+  if (scope.rc) return scope.rc;
+  ccuba_ctx *ctx = scope.ctx;
+  std::lock_guard<std::mutex> g(ctx->lock);
+  CCUBA_HIP(hipSetDevice(ctx->device));
+  return vegas_batched(ctx, sp, integrand, userdata, neval, fail, integral, error, prob);
 }
 
 int ccuba_vegas_ex(ccuba_ctx **ctxp, int ndim, int ncomp, const ccuba_integrand *f,

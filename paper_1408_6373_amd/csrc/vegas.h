@@ -42,6 +42,36 @@ struct PointsArgs {
   int *bin;            // npts * ndim
 };
 
+// Caller-evaluated integrands (points in batches; see vegas_batched.cpp).
+constexpr int kMaxComp = 16;  // integrand components
+struct BatchedArgs {
+  int ndim, nbins, ncomp, prec;
+  long long npts;       // points of this batch
+  int tile_pts;         // points per tile row
+  int tile_base;        // row of the batch's first tile
+  const double *w;      // [npts]
+  const double *f;      // [npts][ncomp]
+  const int *bin;       // [npts][ndim]
+  double *rows;         // [tiles][2 ncomp + ndim nbins]: S1, S2 per component, H
+};
+struct BatchedFinishArgs {
+  int ndim, nbins, ncomp, flags;
+  int ngroups;               // group rows of the iteration
+  const double *ghist;       // [ngroups][2 ncomp + ndim nbins]
+  double *grid;              // ndim (nbins + 1) edges, refined in place
+  VState *state;             // [ncomp]
+  double *iter_I, *iter_var; // [ncomp][hist_cap]
+  int hist_cap;
+  int pad;
+  long long nstart, nincrease, mineval, maxeval;
+  double epsrel, epsabs;
+};
+// One tile row per block of tile_pts points of the batch.
+hipError_t launch_batched_accumulate(const BatchedArgs &B, hipStream_t s);
+// The last fold level, every component's statistics, the joint stop rule and
+// the refinement of the grid from component 0's histogram (one workgroup).
+hipError_t launch_batched_finish(const BatchedFinishArgs &F, hipStream_t s);
+
 // Launch the DoSample instance of precision `prec', `nb' Philox blocks per
 // point, power-of-two bin count or not and d = 4 nb or not over the slice of
 // the tile list in A.

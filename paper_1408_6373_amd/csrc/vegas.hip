@@ -189,6 +189,135 @@ __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// a7, the iteration's statistics for one component: the estimate I_t and
+// variance sigma_t^2 of iteration t = st.T from its sums over n points,
+// folded into the running inverse-variance combination (sums added in
+// iteration order).  The stop rule and chi^2 are applied by finish_state.
+__device__ __forceinline__ void settle_component(VState &st, double S1, double S2, long long n,
+                                                 double &I, double &var) {
+  I = S1 / (double)n;
+  var = S2 / (double)n - I * I;
+  if (var < 0.0) var = 0.0;
+  var /= (double)(n - 1);
+  const int T = st.T + 1;
+  st.T = T;
+  st.neval += n;
+  if (var == 0.0) {
+    st.nzero += 1;
+    st.sum_zI += I;
+  } else {
+    st.sum_w += 1.0 / var;
+    st.sum_wI += I / var;
+  }
+  st.dof = T - 1;
+  if (st.nzero > 0) {
+    st.integral = st.sum_zI / st.nzero;
+    st.error = 0.0;
+  } else {
+    st.integral = st.sum_wI / st.sum_w;
+    st.error = sqrt(1.0 / st.sum_w);
+  }
+}
+
+// The stop rule's outcome (conv: the accuracy test passed; budget: the next
+// iteration would pass maxeval) and, once done, chi^2 over the history
+// hI/hV of the st.T iterations and its probability.
+__device__ __forceinline__ void finish_state(VState &st, bool conv, bool budget,
+                                             const double *hI, const double *hV) {
+  if (conv) {
+    st.done = 1;
+    st.fail = 0;
+  } else if (budget) {
+    st.done = 1;
+    st.fail = 1;
+  }
+  st.chi2 = 0.0;
+  st.prob = 0.0;
+  if (st.done && st.nzero == 0) {
+    double chi2 = 0.0;
+    for (int q = 0; q < st.T; ++q) {
+      const double dl = hI[q] - st.integral;
+      chi2 += dl * dl / hV[q];
+    }
+    st.chi2 = chi2;
+    st.prob = st.dof > 0 ? gamma_p(0.5 * st.dof, 0.5 * chi2) : 0.0;
+  }
+}
+
+// a7, the grid: one dimension's refinement by one wavefront.  The histogram
+// row h is smoothed, damped and prefix-summed (lanes own contiguous runs of
+// bins, wave-wide scans), and every new edge is placed by a binary search of
+// the prefix sums.  h, dd and Eo are LDS rows (h is overwritten with the
+// prefix sums); En receives the N + 1 new edges.
+__device__ __forceinline__ void rebin_dimension(double *h, double *dd, const double *Eo,
+                                                double *En, int N, int lane) {
+  const int per = (N + 63) >> 6;  // contiguous bins per lane
+  const int k0 = lane * per, k1 = min(k0 + per, N);
+  // smoothing and the two row sums
+  double hs = 0.0, ds = 0.0;
+  for (int k = k0; k < k1; ++k) {
+    double v;
+    if (k == 0)
+      v = (h[0] + h[1]) / 2.0;
+    else if (k == N - 1)
+      v = (h[N - 2] + h[N - 1]) / 2.0;
+    else
+      v = (h[k - 1] + h[k] + h[k + 1]) / 3.0;
+    hs += h[k];
+    ds += v;
+    dd[k] = v;
+  }
+  hs = wave_sum(hs);
+  ds = wave_sum(ds);
+  if (!(hs > 0.0)) {  // nothing sampled in this dimension: the edges are kept
+    for (int i = lane; i <= N; i += 64) En[i] = Eo[i];
+    return;
+  }
+  // damping, then prefix sums of m into h (the histogram is no longer needed)
+  wave_sync_lds();
+  double run = 0.0;
+  for (int k = k0; k < k1; ++k) {
+    const double r = dd[k] / ds;
+    double m;
+    if (r == 0.0)
+      m = 0.0;
+    else if (r == 1.0)
+      m = 1.0;
+    else {
+      const double q = (r - 1.0) / log(r);
+      m = q * sqrt(q);  // q^1.5
+    }
+    dd[k] = m;
+    run += m;
+  }
+  const double incl = wave_scan_incl(run, lane);
+  double acc = incl - run;
+  for (int k = k0; k < k1; ++k) {
+    acc += dd[k];
+    h[k] = acc;
+  }
+  wave_sync_lds();
+  const double share = h[N - 1] / N;
+  // new edge i: smallest old bin k with C_k >= i * share
+  for (int i = lane; i <= N; i += 64) {
+    if (i == 0 || i == N) {
+      En[i] = i == 0 ? 0.0 : 1.0;
+      continue;
+    }
+    const double target = i * share;
+    int lo = 0, hi = N - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (h[mid] < target)
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    const double before = lo > 0 ? h[lo - 1] : 0.0;
+    En[i] = Eo[lo] + (target - before) / dd[lo] * (Eo[lo + 1] - Eo[lo]);
+  }
+}
+
 // One workgroup per integral: finish the iteration (a7).  Thread 0 forms the
 // iteration's estimate and variance, the inverse-variance combination and
 // the convergence decision; chi^2 and its probability are formed only once
@@ -291,56 +420,18 @@ __global__ void __launch_bounds__(kRefineThreads) vegas_refine_kernel(VegasArgs 
     const long long nstart = JOB_FIELD(jw, nstart), ninc = JOB_FIELD(jw, nincrease);
     const long long n = nstart + (long long)t * ninc;
     const double S1 = s_sums[0], S2 = s_sums[1];
-    const double I = S1 / (double)n;
-    double var = S2 / (double)n - I * I;
-    if (var < 0.0) var = 0.0;
-    var /= (double)(n - 1);
+    double I, var;
+    settle_component(st, S1, S2, n, I, var);
     double *hI = JOB_FIELD(jw, iter_I), *hV = JOB_FIELD(jw, iter_var);
     hI[t] = I;
     hV[t] = var;
-    const int T = t + 1;
-    st.T = T;
-    st.neval += n;
-    // inverse-variance combination over all iterations (running sums, added
-    // in iteration order)
-    if (var == 0.0) {
-      st.nzero += 1;
-      st.sum_zI += I;
-    } else {
-      st.sum_w += 1.0 / var;
-      st.sum_wI += I / var;
-    }
-    const int nz = st.nzero;
-    st.dof = T - 1;
-    if (nz > 0) {
-      st.integral = st.sum_zI / nz;
-      st.error = 0.0;
-    } else {
-      st.integral = st.sum_wI / st.sum_w;
-      st.error = sqrt(1.0 / st.sum_w);
-    }
+    const int T = st.T;
     const double tol = fmax(JOB_FIELD(jw, epsabs), JOB_FIELD(jw, epsrel) * fabs(st.integral));
     const bool conv = st.neval >= JOB_FIELD(jw, mineval) && st.error <= tol;
     const long long nnext = nstart + (long long)T * ninc;
-    if (conv) {
-      st.done = 1;
-      st.fail = 0;
-    } else if (st.neval + nnext > JOB_FIELD(jw, maxeval) || T >= JOB_FIELD(jw, hist_cap) ||
-               nnext >= (1ll << 32)) {
-      st.done = 1;
-      st.fail = 1;
-    }
-    st.chi2 = 0.0;
-    st.prob = 0.0;
-    if (st.done && nz == 0) {
-      double chi2 = 0.0;
-      for (int q = 0; q < T; ++q) {
-        const double dl = hI[q] - st.integral;
-        chi2 += dl * dl / hV[q];
-      }
-      st.chi2 = chi2;
-      st.prob = st.dof > 0 ? gamma_p(0.5 * st.dof, 0.5 * chi2) : 0.0;
-    }
+    const bool budget = st.neval + nnext > JOB_FIELD(jw, maxeval) ||
+                        T >= JOB_FIELD(jw, hist_cap) || nnext >= (1ll << 32);
+    finish_state(st, conv, budget, hI, hV);
     st.hcap = (float)(1024.0 * (S2 / (double)n));
     *JOB_FIELD(jw, state) = st;
     s_mode = conv ? 0 : ((JOB_FIELD(jw, flags) & FLAG_FREEZE_GRID) ? 2 : 1);
@@ -353,76 +444,8 @@ __global__ void __launch_bounds__(kRefineThreads) vegas_refine_kernel(VegasArgs 
     for (int e = tid; e < drow; e += bs) Enew[e] = G[e];
     return;
   }
-  const int per = (N + 63) >> 6;  // contiguous bins per lane
-  for (int j = wv; j < d; j += nwv) {
-    double *h = H + j * N, *dd = D + j * N;
-    const double *Eo = G + j * row;
-    double *En = Enew + j * row;
-    const int k0 = lane * per, k1 = min(k0 + per, N);
-    // smoothing and the two row sums
-    double hs = 0.0, ds = 0.0;
-    for (int k = k0; k < k1; ++k) {
-      double v;
-      if (k == 0)
-        v = (h[0] + h[1]) / 2.0;
-      else if (k == N - 1)
-        v = (h[N - 2] + h[N - 1]) / 2.0;
-      else
-        v = (h[k - 1] + h[k] + h[k + 1]) / 3.0;
-      hs += h[k];
-      ds += v;
-      dd[k] = v;
-    }
-    hs = wave_sum(hs);
-    ds = wave_sum(ds);
-    if (!(hs > 0.0)) {
-      for (int i = lane; i <= N; i += 64) En[i] = Eo[i];
-      continue;
-    }
-    // damping, then prefix sums of m into h (the histogram is no longer needed)
-    wave_sync_lds();
-    double run = 0.0;
-    for (int k = k0; k < k1; ++k) {
-      const double r = dd[k] / ds;
-      double m;
-      if (r == 0.0)
-        m = 0.0;
-      else if (r == 1.0)
-        m = 1.0;
-      else {
-        const double q = (r - 1.0) / log(r);
-        m = q * sqrt(q);  // q^1.5
-      }
-      dd[k] = m;
-      run += m;
-    }
-    const double incl = wave_scan_incl(run, lane);
-    double acc = incl - run;
-    for (int k = k0; k < k1; ++k) {
-      acc += dd[k];
-      h[k] = acc;
-    }
-    wave_sync_lds();
-    const double share = h[N - 1] / N;
-    // new edge i: smallest old bin k with C_k >= i * share
-    for (int i = lane; i <= N; i += 64) {
-      if (i == 0 || i == N) {
-        En[i] = i == 0 ? 0.0 : 1.0;
-        continue;
-      }
-      const double target = i * share;
-      int lo = 0, hi = N - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (h[mid] < target)
-          lo = mid + 1;
-        else
-          hi = mid;
-      }
-      const double before = lo > 0 ? h[lo - 1] : 0.0;
-      En[i] = Eo[lo] + (target - before) / dd[lo] * (Eo[lo + 1] - Eo[lo]);
-    }
-  }
+  for (int j = wv; j < d; j += nwv)
+    rebin_dimension(H + j * N, D + j * N, G + j * row, Enew + j * row, N, lane);
 }
 
 // Uniform starting grids, E_j[k] = k/N, one workgroup per job (the same
@@ -474,7 +497,7 @@ __global__ void __launch_bounds__(256) vegas_points_kernel(PointsArgs P) {
                                P.key0, P.key1);
     const uint32_t rr[4] = {r.x, r.y, r.z, r.w};
     for (int c = 0; c < 4; ++c) {
-      P.words[(p * nblk + b) * 4 + c] = rr[c];
+      if (P.words) P.words[(p * nblk + b) * 4 + c] = rr[c];
       const int j = 4 * b + c;
       if (j >= d) continue;
       T fr;
@@ -491,6 +514,128 @@ __global__ void __launch_bounds__(256) vegas_points_kernel(PointsArgs P) {
     }
   }
   P.w[p] = (double)w;
+}
+
+// ---------------------------------------------------------------------------
+// Caller-evaluated integrands: the integrand values f of a batch of points
+// (made by the points kernel above) come from the caller; these kernels do
+// the rest of the iteration on the device.
+
+// a5/a6 over one batch: one workgroup per tile of tile_pts consecutive
+// points writes one row: per component c, S1_c = sum v_c and S2_c = sum v_c^2
+// with v_c = w f_c (per lane in point order, then wave and block sums in a
+// fixed order), then H_j[k_j] += v_0^2 (an LDS histogram: the grid follows
+// component 0).  With FP32 evaluation v_c is the binary32 product, as the
+// points were made in binary32.
+__global__ void __launch_bounds__(256) vegas_batched_accumulate_kernel(BatchedArgs B) {
+  extern __shared__ double hs[];  // ndim * nbins
+  __shared__ double red[4][2 * kMaxComp];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int d = B.ndim, N = B.nbins, dN = d * N, nc = B.ncomp;
+  const long long p0 = (long long)blockIdx.x * B.tile_pts;
+  const long long p1 = min(p0 + (long long)B.tile_pts, B.npts);
+  for (int e = tid; e < dN; e += blockDim.x) hs[e] = 0.0;
+  __syncthreads();
+  double s1[kMaxComp], s2[kMaxComp];
+#pragma unroll
+  for (int c = 0; c < kMaxComp; ++c) s1[c] = s2[c] = 0.0;
+  for (long long p = p0 + tid; p < p1; p += blockDim.x) {
+    const double w = B.w[p];
+    double v0 = 0.0;
+#pragma unroll
+    for (int c = 0; c < kMaxComp; ++c)
+      if (c < nc) {
+        const double f = B.f[p * nc + c];
+        const double v = B.prec == FP32 ? (double)((float)w * (float)f) : w * f;
+        s1[c] += v;
+        s2[c] = fma(v, v, s2[c]);
+        if (c == 0) v0 = v;
+      }
+    const double v2 = v0 * v0;
+    for (int j = 0; j < d; ++j) unsafeAtomicAdd(&hs[j * N + B.bin[p * d + j]], v2);
+  }
+#pragma unroll
+  for (int c = 0; c < kMaxComp; ++c)
+    if (c < nc) {
+      const double a = wave_sum(s1[c]), b = wave_sum(s2[c]);
+      if (lane == 0) {
+        red[wid][2 * c] = a;
+        red[wid][2 * c + 1] = b;
+      }
+    }
+  __syncthreads();
+  double *row = B.rows + (long long)(B.tile_base + blockIdx.x) * (2 * nc + dN);
+  if (tid < 2 * nc) {
+    double a = 0.0;
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) a += red[q][tid];
+    row[tid] = a;
+  }
+  for (int e = tid; e < dN; e += blockDim.x) row[2 * nc + e] = hs[e];
+}
+
+// a7 for caller-evaluated integrands: one workgroup sums the iteration's
+// group rows in group order, settles every component (its own estimate,
+// combination and chi^2), applies the stop rule to all components together
+// (accuracy needs every one) and refines the grid in place from component 0's
+// histogram, one wavefront per dimension.
+__global__ void __launch_bounds__(1024) vegas_batched_finish_kernel(BatchedFinishArgs F) {
+  extern __shared__ double fsm[];
+  __shared__ int s_conv[kMaxComp];
+  __shared__ int s_mode;
+  const int tid = threadIdx.x, bs = blockDim.x, lane = tid & 63, wv = tid >> 6, nwv = bs >> 6;
+  const int d = F.ndim, N = F.nbins, dN = d * N, nc = F.ncomp, row = N + 1, drow = d * row;
+  const int R = 2 * nc + dN;
+  if (F.state[0].done) return;  // the same for every thread (and every component)
+  double *S = fsm;              // the folded row: sums, then H
+  double *D = fsm + R;          // smoothed histogram, later m
+  double *G = fsm + R + dN;     // the grid
+  constexpr int kB = 16;        // group rows in flight per thread
+  for (int e = tid; e < R; e += bs) {
+    const double *src = F.ghist + e;
+    double h = 0.0;
+    for (int g0 = 0; g0 < F.ngroups; g0 += kB) {
+      double v[kB];
+#pragma unroll
+      for (int q = 0; q < kB; ++q) v[q] = g0 + q < F.ngroups ? src[(long long)(g0 + q) * R] : 0.0;
+      asm volatile("" ::: "memory");  // every load of the batch before the adds
+      if (g0 == 0) h = v[0];          // group order; the first row starts the sum
+#pragma unroll
+      for (int q = 0; q < kB; ++q)
+        if ((g0 > 0 || q > 0) && g0 + q < F.ngroups) h += v[q];
+    }
+    S[e] = h;
+  }
+  for (int e = tid; e < drow; e += bs) G[e] = F.grid[e];
+  __syncthreads();
+  VState st;
+  double I = 0.0, var = 0.0;
+  const int t = F.state[0].T;
+  const long long n = F.nstart + (long long)t * F.nincrease;
+  if (tid < nc) {
+    st = F.state[tid];
+    settle_component(st, S[2 * tid], S[2 * tid + 1], n, I, var);
+    F.iter_I[(long long)tid * F.hist_cap + t] = I;
+    F.iter_var[(long long)tid * F.hist_cap + t] = var;
+    const double tol = fmax(F.epsabs, F.epsrel * fabs(st.integral));
+    s_conv[tid] = st.neval >= F.mineval && st.error <= tol;
+  }
+  __syncthreads();
+  if (tid < nc) {
+    bool conv = true;
+    for (int c = 0; c < nc; ++c) conv = conv && s_conv[c] != 0;
+    const int T = st.T;
+    const long long nnext = F.nstart + (long long)T * F.nincrease;
+    const bool budget = st.neval + nnext > F.maxeval || T >= F.hist_cap || nnext >= (1ll << 32);
+    finish_state(st, conv, budget, F.iter_I + (long long)tid * F.hist_cap,
+                 F.iter_var + (long long)tid * F.hist_cap);
+    F.state[tid] = st;
+    if (tid == 0) s_mode = conv ? 0 : ((F.flags & FLAG_FREEZE_GRID) ? 2 : 1);
+  }
+  __syncthreads();
+  if (s_mode != 1) return;  // converged, or the grid is frozen (kept as it is)
+  double *H = S + 2 * nc;
+  for (int j = wv; j < d; j += nwv)
+    rebin_dimension(H + j * N, D + j * N, G + j * row, F.grid + j * row, N, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -550,12 +695,29 @@ hipError_t launch_points(const PointsArgs &P, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_batched_accumulate(const BatchedArgs &B, hipStream_t s) {
+  const long long tiles = (B.npts + B.tile_pts - 1) / B.tile_pts;
+  if (tiles <= 0) return hipSuccess;
+  const size_t lds = (size_t)B.ndim * B.nbins * sizeof(double);
+  hipLaunchKernelGGL(vegas_batched_accumulate_kernel, dim3((unsigned)tiles), dim3(256), lds, s,
+                     B);
+  return hipGetLastError();
+}
+
+hipError_t launch_batched_finish(const BatchedFinishArgs &F, hipStream_t s) {
+  const size_t dN = (size_t)F.ndim * F.nbins;
+  const size_t lds = (2 * (size_t)F.ncomp + 2 * dN + (size_t)F.ndim * (F.nbins + 1)) * 8;
+  hipLaunchKernelGGL(vegas_batched_finish_kernel, dim3(1), dim3(1024), lds, s, F);
+  return hipGetLastError();
+}
+
 hipError_t set_kernel_limits() {
   // allow the large-grid cases (d = 16, 256 bins: up to 96 KB of cells and
   // histogram) the LDS gfx950 has; a runtime that refuses keeps its default
   // limit and such launches report an error instead of running
   const int big = 160 * 1024;
   std::vector<const void *> fns = {(const void *)vegas_refine_kernel,
+                                   (const void *)vegas_batched_finish_kernel,
                                    (const void *)vegas_points_kernel<double>,
                                    (const void *)vegas_points_kernel<float>};
   dosample_fns_f64(fns);

@@ -69,6 +69,17 @@ def test_bad_arguments_are_rejected_on_the_host(cc):
         rc = L.ccuba_cuhre(None, nd, 1, C.byref(f), 1e-3, 0.0, 0, 0, 10**6, key, b,
                            C.byref(nr), C.byref(n), C.byref(fl), *ptrs)
         assert rc == cc.EINVAL
+    # caller-evaluated integrand: ndim, ncomp, nbins, nvec, where, precision
+    cb = cc.BATCH_INTEGRAND(lambda *args: 0)
+    r3 = [np.zeros(17) for _ in range(3)]
+    p3 = [cc._ptr(x) for x in r3]
+    for nd, nc, nb, nv, wh, fl_ in ((0, 1, 64, 10, 0, 0), (3, 0, 64, 10, 0, 0),
+                                    (3, 17, 64, 10, 0, 0), (3, 1, 1, 10, 0, 0),
+                                    (3, 1, 64, 0, 0, 0), (3, 1, 64, 10, 2, 0),
+                                    (3, 1, 64, 10, 0, 2)):
+        rc = L.ccuba_vegas_batched(None, nd, nc, cb, None, nv, wh, 0.0, 0.0, fl_, 1, 0, 1000,
+                                   100, 0, nb, 0, C.byref(n), C.byref(fl), *p3)
+        assert rc == cc.EINVAL
     assert L.ccuba_init(None, 0, 0) == cc.EINVAL
     assert L.ccuba_config(None, b"block", 256) == cc.EINVAL
     h = C.c_void_p()

@@ -1,0 +1,163 @@
+"""GPU parity of Vegas with a caller-evaluated integrand (points handed over
+in batches of nvec, Sect. 3.2.5; several components) against the CPU oracle,
+which calls the same Python integrand in the same batches.
+
+Bars: neval and fail equal; integral, error and prob within 1e-12 relative
+(FP64; the sums differ only in order); FP32 evaluation within 1e-10 (the
+points and the binary32 products are the same on both sides); the exact
+pins of the oracle's component tests hold exactly on the GPU too.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cc():
+    import paper_1408_6373_amd as cc
+    return cc
+
+
+@pytest.fixture(scope="module")
+def ctx(cc):
+    c = cc.Context()
+    yield c
+    c.close()
+
+
+def _rel(a, b):
+    return abs(a - b) / max(abs(b), 1e-300)
+
+
+def _gauss(a, u):
+    a2 = np.asarray(a) ** 2
+    return lambda x: np.exp(-np.sum(a2 * (x - u) ** 2, axis=1))
+
+
+def _oracle(func, d, ncomp=1, **kw):
+    return O.vegas(O.python_integrand(func), d, ncomp=ncomp, **kw)
+
+
+def _close(g, o, tol):
+    assert g["neval"] == o["neval"] and g["fail"] == o["fail"]
+    gi, oi = np.atleast_1d(g["integral"]), np.atleast_1d(o["integral"])
+    ge, oe = np.atleast_1d(g["error"]), np.atleast_1d(o["error"])
+    gp, op = np.atleast_1d(g["prob"]), np.atleast_1d(o["prob"])
+    for c in range(len(gi)):
+        assert _rel(gi[c], oi[c]) < tol, (c, gi[c], oi[c])
+        assert _rel(ge[c], oe[c]) < tol or ge[c] == oe[c] == 0.0
+        assert abs(gp[c] - op[c]) < max(tol, 1e-12)
+
+
+@pytest.mark.parametrize("nvec", [1000, 4096, 30000])
+def test_host_integrand_matches_oracle(cc, ctx, nvec):
+    a, u = W.genz_params(0, 4, 3)
+    f = _gauss(a, u)
+    kw = dict(nstart=10007, maxeval=5 * 10007, nbins=64, seed=5)
+    g = cc.vegas_batched(f, 4, ctx=ctx, nvec=nvec, **kw)
+    o = _oracle(f, 4, nvec=nvec, **kw)
+    _close(g, o, 1e-12)
+
+
+def test_components_match_oracle_and_pins(cc, ctx):
+    a, u = W.genz_params(0, 3, 4)
+    g0 = _gauss(a, u)
+    f = lambda x: np.stack([g0(x), 2.0 * g0(x), np.ones(len(x))], 1)
+    kw = dict(nstart=5000, maxeval=4 * 5000, nbins=32, seed=2)
+    g = cc.vegas_batched(f, 3, 3, ctx=ctx, nvec=2048, **kw)
+    o = _oracle(f, 3, ncomp=3, nvec=2048, **kw)
+    _close(g, o, 1e-12)
+    # exact on the GPU as in the oracle: a doubled component doubles exactly,
+    # a constant one is 1 with error 0 (zero variance on the uniform grid)
+    assert g["integral"][1] == 2.0 * g["integral"][0]
+    assert g["error"][1] == 2.0 * g["error"][0]
+    assert g["integral"][2] == 1.0 and g["error"][2] == 0.0
+
+
+def test_every_component_must_converge(cc, ctx):
+    a, u = W.genz_params(2, 2, 6)
+    a2 = np.asarray(a) ** -2.0
+    g0 = lambda x: 1.0 / np.prod(a2 + (x - u) ** 2, axis=1)  # product peak
+    f = lambda x: np.stack([g0(x), g0(x) ** 1.5], 1)
+    kw = dict(epsrel=1e-3, nstart=2000, maxeval=10**6, nbins=32)
+    alone = cc.vegas_batched(g0, 2, ctx=ctx, nvec=1000, **kw)
+    both = cc.vegas_batched(f, 2, 2, ctx=ctx, nvec=1000, **kw)
+    _close(both, _oracle(f, 2, ncomp=2, nvec=1000, **kw), 1e-12)
+    assert alone["fail"] == 0 and both["fail"] == 0 and both["neval"] > alone["neval"]
+
+
+def test_device_integrand_matches_host(cc, ctx):
+    import torch
+    a, u = W.genz_params(0, 5, 8)
+    at = torch.tensor(np.asarray(a) ** 2, dtype=torch.float64, device="cuda")
+    ut = torch.tensor(u, dtype=torch.float64, device="cuda")
+    sizes = []
+
+    def fdev(x, f):
+        sizes.append(x.shape[0])
+        assert x.is_cuda and f.is_cuda and x.dtype == torch.float64
+        f[:, 0] = torch.exp(-torch.sum(at * (x - ut) ** 2, dim=1))
+
+    kw = dict(nstart=8000, maxeval=3 * 8000, nbins=64, seed=9)
+    gd = cc.vegas_batched(fdev, 5, ctx=ctx, where="device", nvec=3000, **kw)
+    gh = cc.vegas_batched(_gauss(a, u), 5, ctx=ctx, nvec=3000, **kw)
+    assert sizes == [3000, 3000, 2000] * 3
+    _close(gd, gh, 1e-12)  # exp on the GPU and in numpy may differ in the last bit
+    _close(gd, _oracle(_gauss(a, u), 5, nvec=3000, **kw), 1e-12)
+
+
+def _aborting():
+    seen = []
+
+    def f(x):
+        seen.append(len(x))
+        return -999 if len(seen) == 5 else x[:, 0] + 0.5
+
+    return f, seen
+
+
+def test_batches_and_abort(cc, ctx):
+    kw = dict(nvec=1000, nstart=2500, maxeval=10**5, nbins=16)
+    f, seen = _aborting()
+    r = cc.vegas_batched(f, 2, ctx=ctx, **kw)
+    fo, seen_o = _aborting()
+    o = _oracle(fo, 2, **kw)
+    # batches of exactly nvec, fewer only in an iteration's last one; every
+    # point handed to the integrand counts, the aborting batch's too
+    assert seen == seen_o == [1000, 1000, 500, 1000, 1000]
+    assert r["fail"] == o["fail"] == -99 and r["neval"] == o["neval"] == 4500
+    assert r["integral"] == r["error"] == r["prob"] == 0.0
+
+
+def test_constant_converges_after_one_iteration(cc, ctx):
+    # on the uniform grid every weight is 1: zero variance meets any tolerance
+    g = cc.vegas_batched(lambda x: np.ones(len(x)), 2, ctx=ctx, nvec=1000, nstart=2500,
+                         maxeval=10**5, nbins=16)
+    assert g["neval"] == 2500 and g["fail"] == 0
+    assert g["integral"] == 1.0 and g["error"] == 0.0
+
+
+def test_exception_in_integrand_is_raised(cc, ctx):
+    def f(x):
+        raise ZeroDivisionError("from the integrand")
+
+    with pytest.raises(ZeroDivisionError):
+        cc.vegas_batched(f, 2, ctx=ctx, nvec=100, nstart=100, maxeval=1000)
+
+
+def test_fp32_evaluation_matches_oracle(cc, ctx):
+    a, u = W.genz_params(0, 6, 10)
+    f = _gauss(a, u)
+    kw = dict(nstart=6000, maxeval=4 * 6000, nbins=128, flags=cc.FP32_EVAL, seed=3)
+    g = cc.vegas_batched(f, 6, ctx=ctx, nvec=5000, **kw)
+    o = _oracle(f, 6, nvec=5000, **kw)
+    _close(g, o, 1e-10)
+
+
+def test_budget_too_small_for_one_iteration(cc, ctx):
+    r = cc.vegas_batched(lambda x: np.ones(len(x)), 2, ctx=ctx, nstart=1000, maxeval=999)
+    assert r["neval"] == 0 and r["fail"] == 1
