@@ -244,6 +244,43 @@ def _batch_leg(cc):
             "first_call_with_tuning_s": t_tune}
 
 
+def _caller_integrand_leg(cc):
+    """Vegas of caller-evaluated integrands (ccuba_vegas_batched): a Gaussian at
+    d = 8 written in torch on the GPU (points and values stay in HBM), and the
+    same Gaussian in numpy on the host (points and values cross PCIe)."""
+    import numpy as np
+    import torch
+    import workloads as W
+    a, u = W.genz_params(W.GAUSSIAN, 8, 1)
+    at = torch.tensor(np.asarray(a) ** 2, dtype=torch.float64, device="cuda")
+    ut = torch.tensor(np.asarray(u), dtype=torch.float64, device="cuda")
+    a2 = np.asarray(a) ** 2
+
+    def fdev(x, f):
+        f[:, 0] = torch.exp(-torch.sum(at * (x - ut) ** 2, dim=1))
+
+    def fhost(x):
+        return np.exp(-np.sum(a2 * (x - u) ** 2, axis=1))
+
+    ctx = cc.Context(device=0)
+    out = {"workload": "Vegas of a Gaussian d=8, 128 bins, FP64, ncomp 1: device integrand "
+                       "(torch) 10 x 1e7 points in batches of 1e6; host integrand (numpy) "
+                       "4 x 1e6 points in batches of 2.5e5", "unit": "evals/s"}
+    for where, func, n, iters, nvec in (("device", fdev, 10**7, 10, 10**6),
+                                        ("host", fhost, 10**6, 4, 250000)):
+        kw = dict(ctx=ctx, where=where, nvec=nvec, nstart=n, maxeval=iters * n, nbins=128)
+        cc.vegas_batched(func, 8, **dict(kw, maxeval=n))  # warm-up: allocations, torch
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = cc.vegas_batched(func, 8, **kw)
+        dt = time.perf_counter() - t0
+        out[where] = {"value": r["neval"] / dt, "seconds": dt, "neval": r["neval"],
+                      "nvec": nvec}
+    ctx.close()
+    out["value"] = out["device"]["value"]
+    return out
+
+
 def _cuhre_leg(cc, ctx):
     import workloads as W
     a, u = W.genz_params(W.CORNER_PEAK, 6, 1)
@@ -405,6 +442,7 @@ def main():
     out["roofline"] = _roofline(cc, ctx, params)
     if not args.no_extra:
         out["batch"] = _batch_leg(cc)
+        out["caller_integrand"] = _caller_integrand_leg(cc)
         out["cuhre"] = _cuhre_leg(cc, ctx)
     ctx.close()
     if not args.no_extra:

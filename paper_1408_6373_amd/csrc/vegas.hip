@@ -475,45 +475,71 @@ __global__ void __launch_bounds__(256) vegas_collect_kernel(VegasArgs A, double 
 // Parity kernel: the points of one iteration (a1-a3), computed with the
 // staging and the per-coordinate arithmetic of the DoSample kernel.
 template <typename T>
-__global__ void __launch_bounds__(256) vegas_points_kernel(PointsArgs P) {
+__host__ __device__ constexpr size_t points_cells_bytes(int d, int N) {
+  return ((size_t)d * N * sizeof(Cell<T>) + 15) / 16 * 16;
+}
+constexpr int kPointsPerThread = 4;
+constexpr int kPointsBlock = 256;
+
+// Each block makes kPointsPerThread rounds of kPointsBlock consecutive points.
+// A round's coordinates and bins go through LDS, so that its rows of
+// x[p][ndim] and bin[p][ndim] (contiguous in memory) are written with
+// coalesced stores, not one strided element per lane.
+template <typename T>
+__global__ void __launch_bounds__(kPointsBlock) vegas_points_kernel(PointsArgs P) {
   extern __shared__ __align__(16) unsigned char psm[];
-  Cell<T> *sC = (Cell<T> *)psm;
   const int d = P.ndim, N = P.nbins, nblk = (d + 3) >> 2;
+  Cell<T> *sC = (Cell<T> *)psm;
+  double *sX = (double *)(psm + points_cells_bytes<T>(d, N));  // [kPointsBlock][d]
+  int *sK = (int *)(sX + kPointsBlock * d);                     // [kPointsBlock][d]
   const bool pow2 = (N & (N - 1)) == 0;
   if (pow2)
     stage_cells<T, true>(P.grid, d, N, sC);
   else
     stage_cells<T, false>(P.grid, d, N, sC);
   __syncthreads();
-  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= P.npts) return;
-  const uint32_t i = (uint32_t)(P.i0 + p);
   const T Nt = (T)N;
   const int L = 31 - __clz(N);
   const T scale = pow2_scale<T>(L);
-  T w = (T)1;
-  for (int b = 0; b < nblk; ++b) {
-    const U4 r = philox4x32_10(U4{i, ((uint32_t)P.iteration << 8) | (uint32_t)b, P.sid, 0u},
-                               P.key0, P.key1);
-    const uint32_t rr[4] = {r.x, r.y, r.z, r.w};
-    for (int c = 0; c < 4; ++c) {
-      if (P.words) P.words[(p * nblk + b) * 4 + c] = rr[c];
-      const int j = 4 * b + c;
-      if (j >= d) continue;
-      T fr;
-      int k;
-      if (pow2)
-        bin_frac_pow2(rr[c], L, scale, fr, k);
-      else
-        bin_frac_any(rr[c], N, Nt, fr, k);
-      const Cell<T> cell = sC[j * N + k];
-      const T x = fma_t(fr, cell.span, cell.lo);
-      w = pow2 ? w * cell.span : w * (Nt * cell.span);
-      P.x[p * d + j] = (double)x;
-      P.bin[p * d + j] = k;
+  const int tid = threadIdx.x;
+  const long long first = (long long)blockIdx.x * kPointsBlock * kPointsPerThread;
+  const long long end = min(P.npts, first + (long long)kPointsBlock * kPointsPerThread);
+  for (long long base = first; base < end; base += kPointsBlock) {  // the same for the block
+    const long long p = base + tid;
+    if (p < end) {
+      const uint32_t i = (uint32_t)(P.i0 + p);
+      T w = (T)1;
+      for (int b = 0; b < nblk; ++b) {
+        const U4 r = philox4x32_10(U4{i, ((uint32_t)P.iteration << 8) | (uint32_t)b, P.sid, 0u},
+                                   P.key0, P.key1);
+        const uint32_t rr[4] = {r.x, r.y, r.z, r.w};
+        for (int c = 0; c < 4; ++c) {
+          if (P.words) P.words[(p * nblk + b) * 4 + c] = rr[c];
+          const int j = 4 * b + c;
+          if (j >= d) continue;
+          T fr;
+          int k;
+          if (pow2)
+            bin_frac_pow2(rr[c], L, scale, fr, k);
+          else
+            bin_frac_any(rr[c], N, Nt, fr, k);
+          const Cell<T> cell = sC[j * N + k];
+          const T x = fma_t(fr, cell.span, cell.lo);
+          w = pow2 ? w * cell.span : w * (Nt * cell.span);
+          sX[tid * d + j] = (double)x;
+          sK[tid * d + j] = k;
+        }
+      }
+      P.w[p] = (double)w;
     }
+    __syncthreads();
+    const int cnt = (int)(min(end - base, (long long)kPointsBlock) * d);
+    for (int e = tid; e < cnt; e += kPointsBlock) {
+      P.x[base * d + e] = sX[e];
+      P.bin[base * d + e] = sK[e];
+    }
+    __syncthreads();
   }
-  P.w[p] = (double)w;
 }
 
 // ---------------------------------------------------------------------------
@@ -527,9 +553,11 @@ __global__ void __launch_bounds__(256) vegas_points_kernel(PointsArgs P) {
 // fixed order), then H_j[k_j] += v_0^2 (an LDS histogram: the grid follows
 // component 0).  With FP32 evaluation v_c is the binary32 product, as the
 // points were made in binary32.
-__global__ void __launch_bounds__(256) vegas_batched_accumulate_kernel(BatchedArgs B) {
+constexpr int kAccumThreads = 1024;
+
+__global__ void __launch_bounds__(kAccumThreads) vegas_batched_accumulate_kernel(BatchedArgs B) {
   extern __shared__ double hs[];  // ndim * nbins
-  __shared__ double red[4][2 * kMaxComp];
+  __shared__ double red[kAccumThreads / 64][2 * kMaxComp];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int d = B.ndim, N = B.nbins, dN = d * N, nc = B.ncomp;
   const long long p0 = (long long)blockIdx.x * B.tile_pts;
@@ -682,16 +710,16 @@ hipError_t launch_collect(const VegasArgs &A, int njobs, double *sums, double *h
 }
 
 hipError_t launch_points(const PointsArgs &P, hipStream_t s) {
-  const int block = 256;
-  const long long grid = (P.npts + block - 1) / block;
+  const long long per = (long long)kPointsBlock * kPointsPerThread;
+  const long long grid = (P.npts + per - 1) / per;
   if (grid == 0) return hipSuccess;
-  const size_t cells = (size_t)P.ndim * P.nbins;
+  const size_t stage = (size_t)kPointsBlock * P.ndim * (sizeof(double) + sizeof(int));
   if (P.prec == FP64)
-    hipLaunchKernelGGL(vegas_points_kernel<double>, dim3((unsigned)grid), dim3(block),
-                       cells * sizeof(Cell<double>), s, P);
+    hipLaunchKernelGGL(vegas_points_kernel<double>, dim3((unsigned)grid), dim3(kPointsBlock),
+                       points_cells_bytes<double>(P.ndim, P.nbins) + stage, s, P);
   else
-    hipLaunchKernelGGL(vegas_points_kernel<float>, dim3((unsigned)grid), dim3(block),
-                       cells * sizeof(Cell<float>), s, P);
+    hipLaunchKernelGGL(vegas_points_kernel<float>, dim3((unsigned)grid), dim3(kPointsBlock),
+                       points_cells_bytes<float>(P.ndim, P.nbins) + stage, s, P);
   return hipGetLastError();
 }
 
@@ -699,8 +727,8 @@ hipError_t launch_batched_accumulate(const BatchedArgs &B, hipStream_t s) {
   const long long tiles = (B.npts + B.tile_pts - 1) / B.tile_pts;
   if (tiles <= 0) return hipSuccess;
   const size_t lds = (size_t)B.ndim * B.nbins * sizeof(double);
-  hipLaunchKernelGGL(vegas_batched_accumulate_kernel, dim3((unsigned)tiles), dim3(256), lds, s,
-                     B);
+  hipLaunchKernelGGL(vegas_batched_accumulate_kernel, dim3((unsigned)tiles), dim3(kAccumThreads),
+                     lds, s, B);
   return hipGetLastError();
 }
 
