@@ -165,6 +165,33 @@ int ccuba_vegas_ex(ccuba_ctx **ctx, int ndim, int ncomp, const ccuba_integrand *
                    int *fail, double integral[], double error[], double prob[],
                    ccuba_vegas_trace *trace);
 
+/* ---- device integrands compiled at run time ------------------------------
+ * Vegas of a caller's integrand written as HIP device code, evaluated per
+ * point inside DoSample like the built-in families (the integrand of
+ * Sect. 3.2.2, as GPU code).  `source' is a null-terminated string that
+ * defines
+ *   __device__ double ccuba_user(const double *x, int ndim, const double *a,
+ *                                const double *u);
+ * and, for CCUBA_FP32_EVAL, the same with float in place of double; x holds
+ * the point, a and u the ndim parameters given here (NULL: zeros; in float
+ * for FP32 evaluation).  The source may use the HIP device math functions
+ * but no headers.  The library compiles the DoSample kernel with it for the
+ * context's GPU on first use (hiprtc) and keeps it in the context until
+ * ccuba_shutdown.  All other arguments, outputs, ranges and results are
+ * those of ccuba_vegas.  Errors: CCUBA_EINVAL (also when the source does not
+ * compile: ccuba_rtc_log returns the compiler's message), CCUBA_EHIP,
+ * CCUBA_ENOMEM. */
+int ccuba_vegas_source(ccuba_ctx **ctx, int ndim, const char *source, const double *a,
+                       const double *u, double epsrel, double epsabs, int flags,
+                       unsigned long long seed, long long mineval, long long maxeval,
+                       long long nstart, long long nincrease, long long nbatch, int nbins,
+                       unsigned int stream_id, long long *neval, int *fail, double integral[],
+                       double error[], double prob[]);
+
+/* The compiler's message of ctx's last run-time compilation, null-terminated
+ * and cut to size bytes (empty if none).  Errors: CCUBA_EINVAL. */
+int ccuba_rtc_log(ccuba_ctx *ctx, char *buf, size_t size);
+
 /* ---- caller-evaluated integrands ---------------------------------------
  * The integrand declaration of Sect. 3.2.2 with its nvec and core arguments:
  * x[*nvec][*ndim] points, f[*nvec][*ncomp] values for the integrand to fill.

@@ -85,6 +85,11 @@ _sig("ccuba_vegas_dosample_raw", C.c_int, [_CTXP, C.c_int, C.c_int, C.POINTER(In
                                            C.c_longlong, C.c_void_p, C.c_void_p, C.c_void_p,
                                            C.c_void_p])
 _sig("ccuba_vegas_batch", C.c_int, [_CTXP, C.c_int, C.POINTER(Job), C.POINTER(Result)])
+_sig("ccuba_vegas_source", C.c_int, [C.POINTER(_CTXP), C.c_int, C.c_char_p, _dp, _dp,
+                                     C.c_double, C.c_double, C.c_int, C.c_ulonglong,
+                                     C.c_longlong, C.c_longlong, C.c_longlong, C.c_longlong,
+                                     C.c_longlong, C.c_int, C.c_uint, _llp, _ip, _dp, _dp, _dp])
+_sig("ccuba_rtc_log", C.c_int, [_CTXP, C.c_char_p, C.c_size_t])
 # int integrand(const int *ndim, const double x[], const int *ncomp, double f[],
 #               void *userdata, const int *nvec, const int *core)
 BATCH_INTEGRAND = C.CFUNCTYPE(C.c_int, _ip, C.c_void_p, _ip, C.c_void_p, C.c_void_p, _ip, _ip)
@@ -109,7 +114,8 @@ SYMBOLS = ["ccuba_init", "ccuba_shutdown", "ccuba_config", "ccuba_config_get",
            "ccuba_strerror", "ccuba_vegas",
            "ccuba_vegas_ex", "ccuba_cuhre", "ccuba_cuhre_rule", "ccuba_vegas_batch",
            "ccuba_submit", "ccuba_poll", "ccuba_drain", "ccuba_vegas_dosample_raw",
-           "ccuba_vegas_points", "ccuba_vegas_refine", "ccuba_vegas_batched"]
+           "ccuba_vegas_points", "ccuba_vegas_refine", "ccuba_vegas_batched",
+           "ccuba_vegas_source", "ccuba_rtc_log"]
 
 
 class CcubaError(RuntimeError):
@@ -253,6 +259,39 @@ def vegas_dosample_raw(ctx, family, a, u, nbins, iteration, npts, grid_ptr, sums
                                          C.c_void_p(hist_ptr),
                                          C.c_void_p(stream_ptr) if stream_ptr else None),
            "ccuba_vegas_dosample_raw")
+
+
+def rtc_log(ctx):
+    """The compiler's message of the context's last run-time compilation."""
+    buf = C.create_string_buffer(1 << 16)
+    _check(_lib.ccuba_rtc_log(ctx.handle, buf, len(buf)), "ccuba_rtc_log")
+    return buf.value.decode(errors="replace")
+
+
+def vegas_source(source, ndim, a=None, u=None, *, ctx=None, epsrel=0.0, epsabs=0.0, flags=FP64,
+                 seed=1, mineval=0, maxeval=10**5, nstart=10**4, nincrease=0, nbatch=1000,
+                 nbins=128, stream_id=0):
+    """ccuba_vegas_source: Vegas of a device integrand given as HIP source, which
+    defines ``__device__ double ccuba_user(const double *x, int ndim, const double *a,
+    const double *u)`` (and the float version for FP32_EVAL).  The library compiles
+    it into its DoSample kernel at run time.  A source that does not compile raises
+    CcubaError with the compiler's message."""
+    a = _f64(np.zeros(ndim) if a is None else a)
+    u = _f64(np.zeros(ndim) if u is None else u)
+    neval = C.c_longlong()
+    fail = C.c_int()
+    res = [np.zeros(1) for _ in range(3)]
+    rc = _lib.ccuba_vegas_source(_ctx_arg(ctx), ndim, source.encode(), _ptr(a), _ptr(u), epsrel,
+                                 epsabs, flags, seed, mineval, maxeval, nstart, nincrease,
+                                 nbatch, nbins, stream_id, C.byref(neval), C.byref(fail),
+                                 _ptr(res[0]), _ptr(res[1]), _ptr(res[2]))
+    if rc == EINVAL and ctx is not None:
+        log = rtc_log(ctx)
+        if log:
+            raise CcubaError(rc, "ccuba_vegas_source: the source does not compile:\n" + log)
+    _check(rc, "ccuba_vegas_source")
+    return dict(neval=neval.value, fail=fail.value, integral=float(res[0][0]),
+                error=float(res[1][0]), prob=float(res[2][0]))
 
 
 class _DeviceArray:

@@ -11,6 +11,7 @@
 #include "cuhre_engine.h"
 #include "serve.h"
 #include "tune.h"
+#include "rtc.h"
 #include "vegas_batched.h"
 #include "vegas_engine.h"
 
@@ -217,6 +218,7 @@ int ccuba_shutdown(ccuba_ctx **ctx) {
   delete c->server;  // stops the serving thread and frees its requests
   c->server = nullptr;
   drop_engine_cache(c);
+  rtc_release(c);
   pool_release(c);
   if (c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
@@ -297,6 +299,51 @@ int ccuba_stats_get(ccuba_ctx *ctx, ccuba_stats *out, int reset) {
   std::lock_guard<std::mutex> g(ctx->lock);
   *out = ctx->stats;
   if (reset) ctx->stats = ccuba_stats{};
+  return CCUBA_OK;
+}
+
+int ccuba_vegas_source(ccuba_ctx **ctxp, int ndim, const char *source, const double *a,
+                       const double *u, double epsrel, double epsabs, int flags,
+                       unsigned long long seed, long long mineval, long long maxeval,
+                       long long nstart, long long nincrease, long long nbatch, int nbins,
+                       unsigned int stream_id, long long *neval, int *fail, double integral[],
+                       double error[], double prob[]) {
+  if (!source || !neval || !fail || !integral || !error || !prob || ndim < 1 || ndim > kMaxDim)
+    return CCUBA_EINVAL;
+  // the parameters a and u (zeros when absent) reach the function as given
+  double za[kMaxDim] = {0}, zu[kMaxDim] = {0};
+  const ccuba_integrand f{GAUSSIAN, a ? a : za, u ? u : zu};
+  VegasSpec sp;
+  int rc = fill_spec(sp, ndim, 1, &f, epsrel, epsabs, flags, seed, mineval, maxeval, nstart,
+                     nincrease, nbatch, nbins, stream_id);
+  if (rc) return rc;
+  sp.family = USER;
+  CtxScope scope(ctxp);
+  if (scope.rc) return scope.rc;
+  ccuba_ctx *ctx = scope.ctx;
+  std::lock_guard<std::mutex> g(ctx->lock);
+  CCUBA_HIP(hipSetDevice(ctx->device));
+  if (ctx->autotune) maybe_autotune(ctx, sp.prec);
+  const VegasTune &t = ctx->tune[sp.prec];
+  const int nb = (ndim + 3) / 4;
+  hipFunction_t fn = nullptr;
+  rc = rtc_dosample(ctx, source, sp.prec, t.hist64, t.ilp, nb, (nbins & (nbins - 1)) == 0,
+                    ndim == 4 * nb, &fn);
+  if (rc) return rc;
+  // an engine of its own: the cached one's graphs hold the built-in kernels
+  VegasEngine eng(ctx);
+  eng.set_user_kernel(fn);
+  if ((rc = eng.setup({sp}, true, ctx->stream))) return rc;
+  return vegas_finish(ctx, eng, neval, fail, integral, error, prob, nullptr);
+}
+
+int ccuba_rtc_log(ccuba_ctx *ctx, char *buf, size_t size) {
+  if (!ctx || !buf || size == 0) return CCUBA_EINVAL;
+  std::lock_guard<std::mutex> g(ctx->lock);
+  const std::string &log = ctx->rtc ? ctx->rtc->log : std::string();
+  const size_t n = std::min(size - 1, log.size());
+  std::memcpy(buf, log.data(), n);
+  buf[n] = '\0';
   return CCUBA_OK;
 }
 

@@ -16,6 +16,7 @@
 namespace ccuba {
 class Server;
 class VegasEngine;
+struct RtcCache;
 }
 
 struct ccuba_ctx {
@@ -39,6 +40,8 @@ struct ccuba_ctx {
   // buffers and captured graphs) for the next call of the same shape
   ccuba::VegasEngine *vcache = nullptr;
   int engine_cache = 1;
+  // DoSample kernels compiled at run time for callers' device integrands
+  ccuba::RtcCache *rtc = nullptr;
   // freed device blocks kept for reuse, by size class (see dev_alloc)
   std::mutex pool_lock;
   std::multimap<size_t, void *> pool;

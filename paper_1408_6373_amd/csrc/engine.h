@@ -1,9 +1,13 @@
 // engine.h -- structures shared by the device kernels and the host drivers.
 #pragma once
+#ifndef CCUBA_RTC  // (hiprtc provides the HIP runtime and its integer types)
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#endif
 
+#ifndef CCUBA_RTC  // (absent when the kernels are compiled at run time)
 #include <vector>
+#endif
 
 namespace ccuba {
 
@@ -13,7 +17,9 @@ constexpr int kGroupTiles = 32;  // tiles folded by one wavefront of the fold ke
 constexpr int kParamRow = kMaxDim;
 
 enum Precision { FP64 = 0, FP32 = 1 };
-enum Family { GAUSSIAN = 0, OSCILLATORY = 1, PRODUCT_PEAK = 2, CORNER_PEAK = 3, C0 = 4 };
+enum Family { GAUSSIAN = 0, OSCILLATORY = 1, PRODUCT_PEAK = 2, CORNER_PEAK = 3, C0 = 4,
+              // a caller's device function, compiled at run time with the kernel
+              USER = 5 };
 
 struct VState;
 

@@ -22,7 +22,9 @@
 // that the hardware exp2 and a revolution-based cosine take the accumulated
 // argument directly.
 #pragma once
+#ifndef CCUBA_RTC  // (hiprtc provides the HIP runtime)
 #include <hip/hip_runtime.h>
+#endif
 
 #include "engine.h"
 

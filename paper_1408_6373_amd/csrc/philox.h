@@ -9,8 +9,10 @@
 //   (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1, lo(M0 c0)),
 // and the key advances by the Weyl increments between rounds.
 #pragma once
+#ifndef CCUBA_RTC  // (hiprtc provides the HIP runtime and its integer types)
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#endif
 
 namespace ccuba {
 

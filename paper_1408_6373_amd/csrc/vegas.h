@@ -1,6 +1,8 @@
 // vegas.h -- kernel arguments and launchers of the Vegas DoSample engine.
 #pragma once
+#ifndef CCUBA_RTC
 #include <vector>
+#endif
 
 #include "engine.h"
 
@@ -66,6 +68,7 @@ struct BatchedFinishArgs {
   long long nstart, nincrease, mineval, maxeval;
   double epsrel, epsabs;
 };
+#ifndef CCUBA_RTC  // host launchers (not part of a run-time compiled kernel)
 // One tile row per block of tile_pts points of the batch.
 hipError_t launch_batched_accumulate(const BatchedArgs &B, hipStream_t s);
 // The last fold level, every component's statistics, the joint stop rule and
@@ -100,5 +103,6 @@ hipError_t launch_collect(const VegasArgs &A, int njobs, double *sums, double *h
                           hipStream_t s);
 hipError_t launch_points(const PointsArgs &P, hipStream_t s);
 hipError_t set_kernel_limits();
+#endif
 
 }  // namespace ccuba

@@ -26,7 +26,7 @@ int upload(DevBuf<T> &b, const std::vector<T> &h, hipStream_t s) {
 
 int validate_vegas(const VegasSpec &s) {
   if (s.ndim < 1 || s.ndim > kMaxDim || s.nbins < 2 || s.nbins > kMaxBins ||
-      s.nstart < 2 || s.nincrease < 0 || s.family < 0 || s.family > 4 ||
+      s.nstart < 2 || s.nincrease < 0 || s.family < 0 || s.family > C0 ||
       (s.prec != FP64 && s.prec != FP32) || s.maxeval < 0 || s.nstart >= (1ll << 32) ||
       !(s.epsrel >= 0) || !(s.epsabs >= 0))
     return CCUBA_EINVAL;
@@ -78,6 +78,12 @@ void genz_constants(const VegasSpec &s, double p64[2][kParamRow], float p32[2][k
         p64[0][j] = a;
         p32[0][j] = (float)a;
         break;
+      case USER:  // a caller's function gets its a and u as given
+        p64[0][j] = a;
+        p64[1][j] = u;
+        p32[0][j] = (float)a;
+        p32[1][j] = (float)u;
+        break;
       default:  // C0
         p64[0][j] = a;
         p64[1][j] = u;
@@ -126,7 +132,7 @@ void plan_tile_groups(std::vector<VJob> &jobs, std::vector<int> &tiles,
 }
 
 int launch_tile_groups(ccuba_ctx *ctx, VegasArgs A, const std::vector<TileGroup> &groups,
-                       hipStream_t s) {
+                       hipStream_t s, hipFunction_t user) {
   for (const TileGroup &g : groups) {
     A.tile_first = g.first;
     A.tile_count = g.count;
@@ -134,8 +140,14 @@ int launch_tile_groups(ccuba_ctx *ctx, VegasArgs A, const std::vector<TileGroup>
     A.lds_hist_byte_off = (long long)g.grid_bytes;
     const long long B = (long long)ctx->ncu * ctx->tune[g.prec].blocks_per_cu;
     const int grid = (int)std::min<long long>(B, g.count);
-    CCUBA_HIP(launch_dosample(A, g.prec, g.nb, g.pow2 != 0, g.full != 0, grid,
-                              ctx->tune[g.prec].block, g.lds, s));
+    if (user) {
+      void *args[] = {&A};
+      CCUBA_HIP(hipModuleLaunchKernel(user, grid, 1, 1, ctx->tune[g.prec].block, 1, 1,
+                                      (unsigned)g.lds, s, args, nullptr));
+    } else {
+      CCUBA_HIP(launch_dosample(A, g.prec, g.nb, g.pow2 != 0, g.full != 0, grid,
+                                ctx->tune[g.prec].block, g.lds, s));
+    }
   }
   return CCUBA_OK;
 }
@@ -164,8 +176,11 @@ int VegasEngine::setup(const std::vector<VegasSpec> &specs, bool single, hipStre
   specs_ = specs;
   const int n = (int)specs.size();
   if (n == 0) return CCUBA_EINVAL;
-  for (const auto &sp : specs)
-    if (validate_vegas(sp) != CCUBA_OK) return CCUBA_EINVAL;
+  for (const auto &sp : specs) {
+    VegasSpec chk = sp;  // a caller's integrand needs its compiled kernel
+    if (chk.family == USER && user_fn_ && specs.size() == 1) chk.family = GAUSSIAN;
+    if (validate_vegas(chk) != CCUBA_OK) return CCUBA_EINVAL;
+  }
   hist64_ = ctx_->tune[FP32].hist64;
   for (int p = 0; p < 2; ++p) {
     block_[p] = ctx_->tune[p].block;
@@ -311,7 +326,8 @@ int VegasEngine::setup(const std::vector<VegasSpec> &specs, bool single, hipStre
   // is unchanged
   std::vector<long long> sig = {(long long)(intptr_t)jobs_.p, (long long)(intptr_t)state_.p,
                                 (long long)(intptr_t)tile_job_.p,
-                                (long long)(intptr_t)fold_end_.p, fold_total_, fold_total2_,
+                                (long long)(intptr_t)fold_end_.p, (long long)(intptr_t)user_fn_,
+                                fold_total_, fold_total2_,
                                 n, ntiles_, (long long)lds_refine_, hist64_};
   for (int p = 0; p < 2; ++p) {
     const VegasTune &t = ctx_->tune[p];
@@ -331,7 +347,7 @@ int VegasEngine::setup(const std::vector<VegasSpec> &specs, bool single, hipStre
 }
 
 int VegasEngine::dosample_only(hipStream_t s, bool level2, hipEvent_t between) {
-  const int rc = launch_tile_groups(ctx_, args_, tgroups_, s);
+  const int rc = launch_tile_groups(ctx_, args_, tgroups_, s, user_fn_);
   if (rc) return rc;
   if (between) CCUBA_HIP(hipEventRecord(between, s));
   FoldArgs F{jobs_.p, fold_end_.p, njobs(), fold_total_, fold_end_.p + njobs(), fold_total2_};

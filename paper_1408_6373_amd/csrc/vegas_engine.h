@@ -42,9 +42,10 @@ struct TileGroup {
 // its first tile, and describe the classes.  Also returns the refine LDS.
 void plan_tile_groups(std::vector<VJob> &jobs, std::vector<int> &tiles,
                       std::vector<TileGroup> &groups, int hist64, size_t *refine_lds);
-// One DoSample launch per class.
+// One DoSample launch per class; `user' (if given) is the run-time compiled
+// kernel of the one class of a caller's device integrand.
 int launch_tile_groups(ccuba_ctx *ctx, VegasArgs A, const std::vector<TileGroup> &groups,
-                       hipStream_t s);
+                       hipStream_t s, hipFunction_t user = nullptr);
 // Inclusive prefixes over jobs of their fold tasks, both levels (see
 // FoldArgs); ends holds level 1 then level 2 (2 * njobs entries).
 void fold_tasks(const std::vector<VJob> &jobs, std::vector<long long> &ends, long long *total,
@@ -72,6 +73,10 @@ class VegasEngine {
   int collect(double *sums_dev, double *hist_dev, hipStream_t s);
   // One refinement of job 0 from a given histogram and grid.
   int refine_only(const double *hist, const double *grid_in, double *grid_out, hipStream_t s);
+
+  // A caller's device integrand (family USER): its compiled DoSample kernel,
+  // set before setup.
+  void set_user_kernel(hipFunction_t f) { user_fn_ = f; }
 
   int njobs() const { return (int)specs_.size(); }
   int max_iters() const { return max_iters_; }
@@ -110,6 +115,7 @@ class VegasEngine {
   int nblocks_[2] = {0, 0}, block_[2] = {256, 256};
   size_t lds_refine_ = 0;
   int hist64_ = 0;
+  hipFunction_t user_fn_ = nullptr;
   int max_iters_ = 0;
   long long evals_iter_ = 0;
   // instantiated graphs of k consecutive iterations

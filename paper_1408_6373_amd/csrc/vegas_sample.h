@@ -5,9 +5,12 @@
 // its own translation unit (vegas_sample_*.hip), so that the instances build
 // in parallel; vegas.hip dispatches to them.
 #pragma once
+#ifndef CCUBA_RTC  // the run-time compiled build has no C++ library headers
 #include <cstddef>
-#include <type_traits>
 #include <vector>
+#else
+#define offsetof(type, member) __builtin_offsetof(type, member)
+#endif
 
 #include "engine.h"
 #include "genz.h"
@@ -238,9 +241,13 @@ __device__ __forceinline__ double pow2_scale<double>(int L) {
 // v^2 exceed that).
 
 template <typename HT>
-struct FixedHist : std::false_type {};
+struct FixedHist {
+  static constexpr bool value = false;
+};
 template <>
-struct FixedHist<unsigned long long> : std::true_type {};
+struct FixedHist<unsigned long long> {
+  static constexpr bool value = true;
+};
 
 // Sample the points [i0, i0 + cnt) of one tile; lane sums go to S1, S2.
 // NB = ceil(d/4) Philox blocks per point is a template argument so that the
@@ -266,7 +273,9 @@ __device__ __forceinline__ void sample_tile(const VJob &J, int t, long long i0, 
   const T scale = pow2_scale<T>(L);
   const uint32_t c1 = (uint32_t)t << 8;
   const uint32_t sid = J.sid, k0 = J.key0, k1 = J.key1;
+#ifndef CCUBA_RTC
   const T phase0 = pp1[0];
+#endif
   const int bs = blockDim.x;
   // an assembly comment naming the family, so that the per-point loop that
   // follows can be found in the assembly listing (it emits no instruction)
@@ -303,6 +312,21 @@ __device__ __forceinline__ void sample_tile(const VJob &J, int t, long long i0, 
 #pragma unroll
     for (int e = 0; e < ILP; ++e) {
       T w = (T)1;
+#ifdef CCUBA_RTC
+      // a caller's function of the whole point, compiled with this kernel:
+      // T ccuba_user(const T *x, int ndim, const T *a, const T *u)
+      T xs[ND];
+#pragma unroll
+      for (int j = 0; j < ND; ++j) {
+        if (FULL || j < 4 * (NB - 1) || j < d) {
+          xs[j] = fma_t(fr[e][j], sp[e][j], lo[e][j]);
+          w = POW2 ? w * sp[e][j] : w * (Nt * sp[e][j]);
+        } else {
+          xs[j] = (T)0;
+        }
+      }
+      const T v = w * ccuba_user(xs, d, pp0, pp1);
+#else
       T acc = Genz<T, FAM>::init(phase0);
 #pragma unroll
       for (int j = 0; j < ND; ++j) {
@@ -313,6 +337,7 @@ __device__ __forceinline__ void sample_tile(const VJob &J, int t, long long i0, 
         }
       }
       const T v = w * Genz<T, FAM>::finish(acc, d);
+#endif
       if (q0 + e * bs < cnt) {
         S1 += (double)v;
         S2 = fma((double)v, (double)v, S2);
@@ -443,6 +468,9 @@ __global__ void __launch_bounds__(256) vegas_dosample_kernel(VegasArgs A) {
       cap = __uint_as_float(smax[kMaxDim + 1]);
     }
     double S1 = 0.0, S2 = 0.0;
+#ifdef CCUBA_RTC
+    sample_tile<T, HT, USER, NB, ILP, POW2, FULL>(J, st.T, i0, cnt, sC, sH, pp0, pp1, E, cap, sHx, S1, S2);
+#else
     switch (J.family) {
       case GAUSSIAN: sample_tile<T, HT, GAUSSIAN, NB, ILP, POW2, FULL>(J, st.T, i0, cnt, sC, sH, pp0, pp1, E, cap, sHx, S1, S2); break;
       case OSCILLATORY: sample_tile<T, HT, OSCILLATORY, NB, ILP, POW2, FULL>(J, st.T, i0, cnt, sC, sH, pp0, pp1, E, cap, sHx, S1, S2); break;
@@ -450,6 +478,7 @@ __global__ void __launch_bounds__(256) vegas_dosample_kernel(VegasArgs A) {
       case CORNER_PEAK: sample_tile<T, HT, CORNER_PEAK, NB, ILP, POW2, FULL>(J, st.T, i0, cnt, sC, sH, pp0, pp1, E, cap, sHx, S1, S2); break;
       default: sample_tile<T, HT, C0, NB, ILP, POW2, FULL>(J, st.T, i0, cnt, sC, sH, pp0, pp1, E, cap, sHx, S1, S2); break;
     }
+#endif
     S1 = wave_sum(S1);
     S2 = wave_sum(S2);
     if (lane == 0) {
@@ -477,6 +506,7 @@ __global__ void __launch_bounds__(256) vegas_dosample_kernel(VegasArgs A) {
   }
 }
 
+#ifndef CCUBA_RTC
 // ---------------------------------------------------------------------------
 // launchers of the instances of one (precision, histogram type)
 
@@ -540,5 +570,7 @@ static void dosample_fns_t(std::vector<const void *> &fns) {
   dosample_fns_cls<T, HT, 2, 3>(fns);
   dosample_fns_cls<T, HT, 2, 4>(fns);
 }
+
+#endif  // CCUBA_RTC
 
 }  // namespace ccuba

@@ -80,6 +80,12 @@ def test_bad_arguments_are_rejected_on_the_host(cc):
         rc = L.ccuba_vegas_batched(None, nd, nc, cb, None, nv, wh, 0.0, 0.0, fl_, 1, 0, 1000,
                                    100, 0, nb, 0, C.byref(n), C.byref(fl), *p3)
         assert rc == cc.EINVAL
+    # device source: NULL source, ndim out of range
+    for nd, src in ((3, None), (0, b"x"), (17, b"x")):
+        rc = L.ccuba_vegas_source(None, nd, src, None, None, 0.0, 0.0, 0, 1, 0, 1000, 100, 0,
+                                  1, 64, 0, C.byref(n), C.byref(fl), *ptrs)
+        assert rc == cc.EINVAL
+    assert L.ccuba_rtc_log(None, C.create_string_buffer(8), 8) == cc.EINVAL
     assert L.ccuba_init(None, 0, 0) == cc.EINVAL
     assert L.ccuba_config(None, b"block", 256) == cc.EINVAL
     h = C.c_void_p()
