@@ -65,6 +65,7 @@ def lib():
                                    C.c_longlong, C.c_longlong, C.c_int, C.c_uint,
                                    C.POINTER(C.c_longlong), C.POINTER(C.c_int), dp, dp,
                                    dp, C.POINTER(_VegasTrace)]
+        L.oracle_vegas_from.argtypes = [dp] + L.oracle_vegas.argtypes
         L.oracle_gm_rule.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.c_int, dp, dp,
                                      dp, dp, dp, C.POINTER(C.c_int), dp]
         L.oracle_gm_npoints.argtypes = [C.c_int]
@@ -171,9 +172,13 @@ def refine_dim(H, E):
 
 def vegas(integrand, ndim, *, epsrel=0.0, epsabs=0.0, flags=0, seed=1,
           mineval=0, maxeval=10**5, nstart=10**4, nincrease=0, nbatch=1000,
-          nbins=128, stream_id=0, nvec=1000, max_iter=4096, ncomp=1):
+          nbins=128, stream_id=0, nvec=1000, max_iter=4096, ncomp=1, grid=None):
     """Serial Vegas.  With ncomp > 1 integral/error/prob are arrays of ncomp
-    values; iter_I, iter_var, chi2, dof and the grid are component 0's."""
+    values; iter_I, iter_var, chi2, dof and the grid are component 0's.  grid
+    (ndim x (nbins + 1)) starts the run from that grid instead of the uniform one."""
+    gin = None
+    if grid is not None:
+        gin = np.ascontiguousarray(grid, dtype=np.float64).reshape(ndim * (nbins + 1))
     neval = C.c_longlong()
     fail = C.c_int()
     integral = np.zeros(ncomp)
@@ -184,7 +189,8 @@ def vegas(integrand, ndim, *, epsrel=0.0, epsabs=0.0, flags=0, seed=1,
     grid = np.zeros(ndim * (nbins + 1))
     hist = np.zeros(ndim * nbins)
     tr = _VegasTrace(max_iter, 0, _dptr(It), _dptr(Vt), 0.0, 0, _dptr(grid), _dptr(hist))
-    rc = lib().oracle_vegas(ndim, ncomp, integrand.fn, integrand.userdata, nvec, epsrel,
+    rc = lib().oracle_vegas_from(None if gin is None else _dptr(gin),
+                                 ndim, ncomp, integrand.fn, integrand.userdata, nvec, epsrel,
                             epsabs, flags, seed, mineval, maxeval, nstart, nincrease,
                             nbatch, nbins, stream_id, C.byref(neval), C.byref(fail),
                             _dptr(integral), _dptr(error), _dptr(prob), C.byref(tr))

@@ -111,6 +111,16 @@ int oracle_vegas(int ndim, int ncomp, oracle_integrand_t integrand,
                  long long *neval, int *fail, double integral[],
                  double error[], double prob[], oracle_vegas_trace *trace);
 
+/* oracle_vegas started from grid_in (ndim rows of nbins + 1 edges) instead of
+ * the uniform grid; grid_in NULL is oracle_vegas. */
+int oracle_vegas_from(const double *grid_in, int ndim, int ncomp,
+                      oracle_integrand_t integrand, void *userdata, int nvec, double epsrel,
+                      double epsabs, int flags, unsigned long long seed, long long mineval,
+                      long long maxeval, long long nstart, long long nincrease,
+                      long long nbatch, int nbins, unsigned int stream_id, long long *neval,
+                      int *fail, double integral[], double error[], double prob[],
+                      oracle_vegas_trace *trace);
+
 /* Genz-Malik degree-7/5 rule over one region with centre c[ndim] and
  * half-widths h[ndim].  dfour[ndim] (may be NULL) receives the fourth
  * differences.  Returns 0, -1 bad arguments, -99 integrand aborted. */

@@ -218,6 +218,15 @@ extern "C" int oracle_vegas_points(int ndim, int nbins, int precision,
   return 0;
 }
 
+extern "C" int oracle_vegas_from(const double *grid_in, int ndim, int ncomp,
+                                 oracle_integrand_t integrand, void *userdata, int nvec,
+                                 double epsrel, double epsabs, int flags,
+                                 unsigned long long seed, long long mineval,
+                                 long long maxeval, long long nstart, long long nincrease,
+                                 long long nbatch, int nbins, unsigned int stream_id,
+                                 long long *neval, int *fail, double integral[],
+                                 double error[], double prob[], oracle_vegas_trace *trace);
+
 extern "C" int oracle_vegas(int ndim, int ncomp, oracle_integrand_t integrand,
                             void *userdata, int nvec, double epsrel,
                             double epsabs, int flags, unsigned long long seed,
@@ -227,6 +236,22 @@ extern "C" int oracle_vegas(int ndim, int ncomp, oracle_integrand_t integrand,
                             unsigned int stream_id, long long *neval,
                             int *fail, double integral[], double error[],
                             double prob[], oracle_vegas_trace *trace) {
+  return oracle_vegas_from(nullptr, ndim, ncomp, integrand, userdata, nvec, epsrel, epsabs,
+                           flags, seed, mineval, maxeval, nstart, nincrease, nbatch, nbins,
+                           stream_id, neval, fail, integral, error, prob, trace);
+}
+
+// The same run started from a given grid (ndim rows of nbins + 1 edges)
+// instead of the uniform one: the grid of an earlier integration reused for a
+// new one (iterations, sums and counters start afresh).
+extern "C" int oracle_vegas_from(const double *grid_in, int ndim, int ncomp,
+                                 oracle_integrand_t integrand, void *userdata, int nvec,
+                                 double epsrel, double epsabs, int flags,
+                                 unsigned long long seed, long long mineval,
+                                 long long maxeval, long long nstart, long long nincrease,
+                                 long long nbatch, int nbins, unsigned int stream_id,
+                                 long long *neval, int *fail, double integral[],
+                                 double error[], double prob[], oracle_vegas_trace *trace) {
   const int precision = flags & ORACLE_PRECISION_MASK;
   if (ndim < 1 || ndim > 16 || ncomp < 1 || ncomp > 16 || nvec < 1 || nbins < 2 ||
       nbins > 256 || nstart < 2 || nincrease < 0 || nbatch < 1 ||
@@ -236,7 +261,9 @@ extern "C" int oracle_vegas(int ndim, int ncomp, oracle_integrand_t integrand,
   const int N = nbins;
   std::vector<double> grid((size_t)ndim * (N + 1));
   for (int j = 0; j < ndim; ++j)
-    for (int k = 0; k <= N; ++k) grid[(size_t)j * (N + 1) + k] = (double)k / N;
+    for (int k = 0; k <= N; ++k)
+      grid[(size_t)j * (N + 1) + k] =
+          grid_in ? grid_in[(size_t)j * (N + 1) + k] : (double)k / N;
 
   std::vector<double> hist((size_t)ndim * N);
   std::vector<std::vector<double>> It(ncomp), vart(ncomp);

@@ -224,3 +224,33 @@ def test_abort_reports_every_component_zero():
     r = O.vegas(O.python_integrand(f), 2, nstart=3000, maxeval=10**5, nvec=1000, ncomp=3)
     assert r["fail"] == -99 and r["neval"] == 2000
     assert np.all(r["integral"] == 0) and np.all(r["error"] == 0)
+
+
+# ---------------------------------------------------------------------------
+# A run started from a given grid (a grid reused from an earlier integration)
+
+def test_uniform_start_grid_is_the_ordinary_run():
+    a, u = W.genz_params(1, 3, 8)
+    N = 32
+    uni = np.tile(np.arange(N + 1) / N, (3, 1))
+    r0 = O.vegas(O.genz(1, a, u), 3, nstart=3000, maxeval=9000, nbins=N)
+    r1 = O.vegas(O.genz(1, a, u), 3, nstart=3000, maxeval=9000, nbins=N, grid=uni)
+    assert r0["integral"] == r1["integral"] and r0["error"] == r1["error"]
+    assert np.array_equal(r0["grid"], r1["grid"])
+
+
+def test_first_iteration_from_a_grid_is_the_plain_mean():
+    # iteration 0 from grid G: I_0 = (1/n) sum w f over the points mapped
+    # through G, sigma_0^2 from the same sum of squares (brute force here)
+    import math
+    d, N, n = 3, 16, 4000
+    a, u = W.genz_params(0, d, 9)
+    prev = O.vegas(O.genz(0, a, u), d, nstart=2000, maxeval=6000, nbins=N)
+    G = prev["grid"]
+    r = O.vegas(O.genz(0, a, u), d, nstart=n, maxeval=n, nbins=N, grid=G, seed=3)
+    pts = O.vegas_points(d, N, G, 3, 0, 0, 0, n)
+    v = pts["w"] * O.genz_eval(0, a, u, pts["x"])
+    I = math.fsum(v) / n
+    var = (math.fsum(v * v) / n - I * I) / (n - 1)
+    assert abs(r["iter_I"][0] - I) <= 1e-15 * abs(I)
+    assert abs(r["iter_var"][0] - var) <= 1e-12 * var
