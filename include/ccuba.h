@@ -165,6 +165,31 @@ int ccuba_vegas_ex(ccuba_ctx **ctx, int ndim, int ncomp, const ccuba_integrand *
                    int *fail, double integral[], double error[], double prob[],
                    ccuba_vegas_trace *trace);
 
+/* ccuba_vegas_ex with the prototype's gridno and statefile (Sect. 3.2.2).
+ * gridno: a slot of the context's grid table.  With gridno != 0 the run
+ * starts from the grid kept in slot |gridno| when that grid has the same
+ * ndim and nbins (else from the uniform grid); with gridno > 0 the final grid
+ * is kept in the slot for later calls.  Iterations, sums and counters start
+ * afresh: only the grid is reused.
+ * statefile: a file path (NULL or "" for none).  After every iteration the
+ * state, grid and per-iteration history are written to it (atomically, by a
+ * rename).  A call that finds the file continues from it, provided it was
+ * written for the same ndim, nbins, integrand, precision and flags, seed,
+ * stream_id, nstart and nincrease (else CCUBA_EINVAL); tolerances, mineval
+ * and maxeval may differ, so a run stopped by maxeval continues under a
+ * larger one.  The file is removed once the integral converges (fail = 0).
+ * A resumed run samples the same points as an uninterrupted one.  With a
+ * state file iterations run one at a time (each is read back and saved).
+ * Errors: those of ccuba_vegas, and CCUBA_EINVAL for a state file that does
+ * not fit, cannot be read or cannot be written. */
+int ccuba_vegas_stateful(ccuba_ctx **ctx, int ndim, int ncomp, const ccuba_integrand *f,
+                         double epsrel, double epsabs, int flags, unsigned long long seed,
+                         long long mineval, long long maxeval, long long nstart,
+                         long long nincrease, long long nbatch, int gridno, const char *statefile,
+                         int nbins, unsigned int stream_id, long long *neval, int *fail,
+                         double integral[], double error[], double prob[],
+                         ccuba_vegas_trace *trace);
+
 /* ---- device integrands compiled at run time ------------------------------
  * Vegas of a caller's integrand written as HIP device code, evaluated per
  * point inside DoSample like the built-in families (the integrand of

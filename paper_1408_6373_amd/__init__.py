@@ -76,6 +76,8 @@ _VEGAS_ARGS = [C.POINTER(_CTXP), C.c_int, C.c_int, C.POINTER(Integrand), C.c_dou
                C.c_longlong, C.c_longlong, C.c_int, C.c_uint, _llp, _ip, _dp, _dp, _dp]
 _sig("ccuba_vegas", C.c_int, _VEGAS_ARGS)
 _sig("ccuba_vegas_ex", C.c_int, _VEGAS_ARGS + [C.POINTER(VegasTrace)])
+_sig("ccuba_vegas_stateful", C.c_int, _VEGAS_ARGS[:13] + [C.c_int, C.c_char_p] +
+     _VEGAS_ARGS[13:] + [C.POINTER(VegasTrace)])
 _sig("ccuba_vegas_points", C.c_int, [_CTXP, C.c_int, C.c_int, C.c_int, C.c_ulonglong, C.c_uint,
                                      C.c_int, _dp, C.c_longlong, C.c_longlong,
                                      C.POINTER(C.c_uint32), _dp, _dp, _ip])
@@ -115,7 +117,7 @@ SYMBOLS = ["ccuba_init", "ccuba_shutdown", "ccuba_config", "ccuba_config_get",
            "ccuba_vegas_ex", "ccuba_cuhre", "ccuba_cuhre_rule", "ccuba_vegas_batch",
            "ccuba_submit", "ccuba_poll", "ccuba_drain", "ccuba_vegas_dosample_raw",
            "ccuba_vegas_points", "ccuba_vegas_refine", "ccuba_vegas_batched",
-           "ccuba_vegas_source", "ccuba_rtc_log"]
+           "ccuba_vegas_source", "ccuba_rtc_log", "ccuba_vegas_stateful"]
 
 
 class CcubaError(RuntimeError):
@@ -194,9 +196,10 @@ def _ctx_arg(ctx):
 
 def vegas(family, a, u, *, ctx=None, epsrel=0.0, epsabs=0.0, flags=FP64, seed=1, mineval=0,
           maxeval=10**5, nstart=10**4, nincrease=0, nbatch=1000, nbins=128, stream_id=0,
-          trace=False, max_iter=4096):
-    """ccuba_vegas(_ex): returns a dict with neval, fail, integral, error, prob
-    (and iter_I, iter_var, chi2, dof, grid when trace=True)."""
+          trace=False, max_iter=4096, gridno=0, statefile=None):
+    """ccuba_vegas(_ex), or ccuba_vegas_stateful with gridno / statefile: returns a
+    dict with neval, fail, integral, error, prob (and iter_I, iter_var, chi2, dof,
+    grid when trace=True)."""
     f, keep = _integrand(family, a, u)
     ndim = len(keep[0])
     neval = C.c_longlong()
@@ -207,15 +210,23 @@ def vegas(family, a, u, *, ctx=None, epsrel=0.0, epsabs=0.0, flags=FP64, seed=1,
             nstart, nincrease, nbatch, nbins, stream_id, C.byref(neval), C.byref(fail),
             _ptr(res[0]), _ptr(res[1]), _ptr(res[2])]
     r = dict()
+    stateful = gridno != 0 or bool(statefile)
+    if stateful:
+        sargs = args[:13] + [int(gridno), statefile.encode() if statefile else None] + args[13:]
     if trace:
         It = np.zeros(max_iter)
         Vt = np.zeros(max_iter)
         grid = np.zeros(ndim * (nbins + 1))
         tr = VegasTrace(max_iter, 0, _ptr(It), _ptr(Vt), 0.0, 0, _ptr(grid))
-        _check(_lib.ccuba_vegas_ex(*args, C.byref(tr)), "ccuba_vegas_ex")
+        if stateful:
+            _check(_lib.ccuba_vegas_stateful(*sargs, C.byref(tr)), "ccuba_vegas_stateful")
+        else:
+            _check(_lib.ccuba_vegas_ex(*args, C.byref(tr)), "ccuba_vegas_ex")
         n = tr.n_iter
         r.update(iter_I=It[:n].copy(), iter_var=Vt[:n].copy(), chi2=tr.chi2, dof=tr.dof,
                  grid=grid.reshape(ndim, nbins + 1))
+    elif stateful:
+        _check(_lib.ccuba_vegas_stateful(*sargs, None), "ccuba_vegas_stateful")
     else:
         _check(_lib.ccuba_vegas(*args), "ccuba_vegas")
     del out

@@ -1,6 +1,7 @@
 // api.cpp -- the C ABI of libccuba (declared in include/ccuba.h).
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <memory>
@@ -12,6 +13,7 @@
 #include "serve.h"
 #include "tune.h"
 #include "rtc.h"
+#include "vegas_state.h"
 #include "vegas_batched.h"
 #include "vegas_engine.h"
 
@@ -123,6 +125,9 @@ void drop_engine_cache(ccuba_ctx *ctx) {
 // run a set-up single-integral engine to the end and read its results
 int vegas_finish(ccuba_ctx *ctx, VegasEngine &eng, long long *neval, int *fail,
                  double integral[], double error[], double prob[], ccuba_vegas_trace *trace);
+// The outputs of a finished run of job 0.
+int vegas_results(ccuba_ctx *ctx, VegasEngine &eng, long long *neval, int *fail,
+                  double integral[], double error[], double prob[], ccuba_vegas_trace *trace);
 
 int fill_spec(VegasSpec &sp, int ndim, int ncomp, const ccuba_integrand *f, double epsrel,
               double epsabs, int flags, unsigned long long seed, long long mineval,
@@ -302,6 +307,79 @@ int ccuba_stats_get(ccuba_ctx *ctx, ccuba_stats *out, int reset) {
   return CCUBA_OK;
 }
 
+int ccuba_vegas_stateful(ccuba_ctx **ctxp, int ndim, int ncomp, const ccuba_integrand *f,
+                         double epsrel, double epsabs, int flags, unsigned long long seed,
+                         long long mineval, long long maxeval, long long nstart,
+                         long long nincrease, long long nbatch, int gridno, const char *statefile,
+                         int nbins, unsigned int stream_id, long long *neval, int *fail,
+                         double integral[], double error[], double prob[],
+                         ccuba_vegas_trace *trace) {
+  if (!neval || !fail || !integral || !error || !prob) return CCUBA_EINVAL;
+  VegasSpec sp;
+  int rc = fill_spec(sp, ndim, ncomp, f, epsrel, epsabs, flags, seed, mineval, maxeval, nstart,
+                     nincrease, nbatch, nbins, stream_id);
+  if (rc) return rc;
+  const bool checkpoint = statefile && *statefile;
+  CtxScope scope(ctxp);
+  if (scope.rc) return scope.rc;
+  ccuba_ctx *ctx = scope.ctx;
+  std::lock_guard<std::mutex> g(ctx->lock);
+  CCUBA_HIP(hipSetDevice(ctx->device));
+  if (ctx->autotune) maybe_autotune(ctx, sp.prec);
+  hipStream_t s = ctx->stream;
+  VegasEngine eng(ctx);
+  if ((rc = eng.setup({sp}, true, s))) return rc;
+  const size_t row = (size_t)ndim * (nbins + 1);
+  bool resumed = false;
+  StateFile sf;
+  if (checkpoint) {
+    rc = state_read(statefile, sp, sf);
+    if (rc < 0) return rc;
+    if (rc == 0) {
+      if (sf.st.T > eng.max_iters()) return CCUBA_EINVAL;  // more than this budget allows
+      if (sf.st.done && sf.st.fail == 1 && sf.st.T < eng.max_iters()) {
+        // stopped by an earlier, smaller budget: this one allows more
+        sf.st.done = 0;
+        sf.st.fail = 0;
+        sf.st.chi2 = sf.st.prob = 0.0;
+      }
+      if ((rc = eng.load_checkpoint(sf.st, sf.grid.data(), sf.I.data(), sf.var.data(), s)))
+        return rc;
+      resumed = true;
+    }
+  }
+  if (!resumed && gridno != 0) {  // an earlier integration's grid, if its shape fits
+    auto it = ctx->grid_table.find(gridno > 0 ? gridno : -gridno);
+    if (it != ctx->grid_table.end() && it->second.first == std::make_pair(ndim, nbins))
+      if ((rc = eng.load_grid(0, it->second.second.data(), hipMemcpyHostToDevice, s))) return rc;
+  }
+  if (checkpoint) {
+    const int cap = eng.hist_cap();
+    std::vector<double> I(cap), var(cap);
+    rc = eng.run_each(s, [&](const VState &st) {
+      sf.st = st;
+      sf.grid.resize(row);
+      int r = eng.read_grid(0, sf.grid.data(), s);
+      if (r) return r;
+      if ((r = eng.read_history(0, st.T, I.data(), var.data(), s))) return r;
+      sf.I.assign(I.begin(), I.begin() + st.T);
+      sf.var.assign(var.begin(), var.begin() + st.T);
+      return state_write(statefile, sp, sf);
+    });
+  } else {
+    rc = eng.run(s);
+  }
+  if (rc) return rc;
+  if ((rc = vegas_results(ctx, eng, neval, fail, integral, error, prob, trace))) return rc;
+  if (checkpoint && *fail == 0) std::remove(statefile);  // converged: nothing to resume
+  if (gridno > 0) {
+    std::vector<double> grid(row);
+    if ((rc = eng.read_grid(0, grid.data(), s))) return rc;
+    ctx->grid_table[gridno] = {{ndim, nbins}, std::move(grid)};
+  }
+  return CCUBA_OK;
+}
+
 int ccuba_vegas_source(ccuba_ctx **ctxp, int ndim, const char *source, const double *a,
                        const double *u, double epsrel, double epsabs, int flags,
                        unsigned long long seed, long long mineval, long long maxeval,
@@ -433,10 +511,9 @@ int ccuba_vegas_ex(ccuba_ctx **ctxp, int ndim, int ncomp, const ccuba_integrand 
 }
 
 namespace {
-int vegas_finish(ccuba_ctx *ctx, VegasEngine &eng, long long *neval, int *fail,
-                 double integral[], double error[], double prob[], ccuba_vegas_trace *trace) {
+int vegas_results(ccuba_ctx *ctx, VegasEngine &eng, long long *neval, int *fail,
+                  double integral[], double error[], double prob[], ccuba_vegas_trace *trace) {
   int rc;
-  if ((rc = eng.run(ctx->stream))) return rc;
   std::vector<VState> st;
   if ((rc = eng.read_states(st, ctx->stream))) return rc;
   *neval = st[0].neval;
@@ -455,6 +532,13 @@ int vegas_finish(ccuba_ctx *ctx, VegasEngine &eng, long long *neval, int *fail,
       if ((rc = eng.read_grid(0, trace->grid, ctx->stream))) return rc;
   }
   return CCUBA_OK;
+}
+
+int vegas_finish(ccuba_ctx *ctx, VegasEngine &eng, long long *neval, int *fail,
+                 double integral[], double error[], double prob[], ccuba_vegas_trace *trace) {
+  const int rc = eng.run(ctx->stream);
+  if (rc) return rc;
+  return vegas_results(ctx, eng, neval, fail, integral, error, prob, trace);
 }
 }  // namespace
 

@@ -42,6 +42,8 @@ struct ccuba_ctx {
   int engine_cache = 1;
   // DoSample kernels compiled at run time for callers' device integrands
   ccuba::RtcCache *rtc = nullptr;
+  // Vegas grids kept between calls (gridno): slot -> ((ndim, nbins), edges)
+  std::map<int, std::pair<std::pair<int, int>, std::vector<double>>> grid_table;
   // freed device blocks kept for reuse, by size class (see dev_alloc)
   std::mutex pool_lock;
   std::multimap<size_t, void *> pool;

@@ -471,6 +471,35 @@ int VegasEngine::run(hipStream_t s) {
   return flush_timing();
 }
 
+int VegasEngine::run_each(hipStream_t s, const std::function<int(const VState &)> &after) {
+  std::vector<VState> st;
+  int rc = read_states(st, s);
+  if (rc) return rc;
+  // the budget counts every iteration from t = 0, resumed ones included
+  for (int t = st[0].T; t < max_iters_ && !st[0].done; ++t) {
+    if ((rc = launch_iteration(s))) return rc;
+    if ((rc = read_states(st, s))) return rc;
+    if ((rc = after(st[0]))) return rc;
+  }
+  CCUBA_HIP(hipStreamSynchronize(s));
+  return flush_timing();
+}
+
+int VegasEngine::load_checkpoint(const VState &st, const double *grid, const double *I,
+                                 const double *var, hipStream_t s) {
+  const VJob &J = hjobs_[0];
+  if (st.T > J.hist_cap) return CCUBA_EINVAL;
+  int rc = load_grid(0, grid, hipMemcpyHostToDevice, s);
+  if (rc) return rc;
+  if (st.T > 0) {
+    CCUBA_HIP(hipMemcpyAsync(J.iter_I, I, st.T * sizeof(double), hipMemcpyHostToDevice, s));
+    CCUBA_HIP(hipMemcpyAsync(J.iter_var, var, st.T * sizeof(double), hipMemcpyHostToDevice, s));
+  }
+  CCUBA_HIP(hipMemcpyAsync(state_.p, &st, sizeof(VState), hipMemcpyHostToDevice, s));
+  CCUBA_HIP(hipStreamSynchronize(s));  // the host copies are the caller's
+  return CCUBA_OK;
+}
+
 int VegasEngine::read_states(std::vector<VState> &out, hipStream_t s) {
   out.resize(njobs());
   CCUBA_HIP(hipMemcpyAsync(out.data(), state_.p, njobs() * sizeof(VState),

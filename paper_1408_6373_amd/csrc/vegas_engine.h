@@ -5,6 +5,7 @@
 // advances all of them one iteration per launch pair (DoSample + refine).
 // A single integral is an engine with one job.
 #pragma once
+#include <functional>
 #include <vector>
 
 #include "context.h"
@@ -60,6 +61,16 @@ class VegasEngine {
   int step(hipStream_t s);
   // Iterate until every job is done; replays a captured graph if enabled.
   int run(hipStream_t s);
+  // The same one iteration at a time, calling after(state of job 0) once each
+  // iteration is done (a checkpoint); a nonzero return from it stops the run
+  // with that status.
+  int run_each(hipStream_t s, const std::function<int(const VState &)> &after);
+  // Job 0 continues from a saved state, grid and history (T = st.T
+  // iterations done); call after setup.
+  int load_checkpoint(const VState &st, const double *grid, const double *I, const double *var,
+                      hipStream_t s);
+  // Job 0's history capacity (iterations the budget allows).
+  int hist_cap() const { return hjobs_.empty() ? 0 : hjobs_[0].hist_cap; }
   int read_states(std::vector<VState> &out, hipStream_t s);
   int read_history(int job, int n, double *I, double *var, hipStream_t s);
   int read_grid(int job, double *grid, hipStream_t s);

@@ -85,6 +85,15 @@ def test_bad_arguments_are_rejected_on_the_host(cc):
         rc = L.ccuba_vegas_source(None, nd, src, None, None, 0.0, 0.0, 0, 1, 0, 1000, 100, 0,
                                   1, 64, 0, C.byref(n), C.byref(fl), *ptrs)
         assert rc == cc.EINVAL
+    # checkpointed Vegas: the checks of ccuba_vegas, before any file is touched
+    for nd, nb in ((0, 64), (3, 1)):
+        rc = L.ccuba_vegas_stateful(None, nd, 1, C.byref(f), 0.0, 0.0, 0, 1, 0, 1000, 100, 0, 1,
+                                    2, b"/nonexistent/dir/state", nb, 0, C.byref(n),
+                                    C.byref(fl), *ptrs, None)
+        assert rc == cc.EINVAL
+    rc = L.ccuba_vegas_stateful(None, 3, 1, C.byref(f), 0.0, 0.0, 0, 1, 0, 1000, 100, 0, 1, 0,
+                                None, 64, 0, None, C.byref(fl), *ptrs, None)
+    assert rc == cc.EINVAL
     assert L.ccuba_rtc_log(None, C.create_string_buffer(8), 8) == cc.EINVAL
     assert L.ccuba_init(None, 0, 0) == cc.EINVAL
     assert L.ccuba_config(None, b"block", 256) == cc.EINVAL
