@@ -36,6 +36,16 @@ class _VegasTrace(C.Structure):
                 ("hist", C.POINTER(C.c_double))]
 
 
+class _SuaveTrace(C.Structure):
+    _fields_ = [("max_regions", C.c_int), ("max_splits", C.c_int),
+                ("nregions", C.c_int), ("nsplits", C.c_int),
+                ("chi2", C.c_double), ("dof", C.c_int),
+                ("lo", C.POINTER(C.c_double)), ("hi", C.POINTER(C.c_double)),
+                ("I", C.POINTER(C.c_double)), ("var", C.POINTER(C.c_double)),
+                ("inh_I", C.POINTER(C.c_double)), ("inh_var", C.POINTER(C.c_double)),
+                ("grid", C.POINTER(C.c_double)), ("cut", C.POINTER(C.c_int))]
+
+
 class _CuhreTrace(C.Structure):
     _fields_ = [("n_batches", C.c_int)]
 
@@ -76,6 +86,12 @@ def lib():
                                    C.POINTER(C.c_int), C.POINTER(C.c_longlong),
                                    C.POINTER(C.c_int), dp, dp, dp,
                                    C.POINTER(_CuhreTrace)]
+        L.oracle_suave.argtypes = [C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_int,
+                                   C.c_double, C.c_double, C.c_int, C.c_ulonglong,
+                                   C.c_longlong, C.c_longlong, C.c_longlong, C.c_double,
+                                   C.c_int, C.c_int, C.c_uint, C.POINTER(C.c_int),
+                                   C.POINTER(C.c_longlong), C.POINTER(C.c_int), dp, dp, dp,
+                                   C.POINTER(_SuaveTrace)]
         L.oracle_gammainc_lower.argtypes = [C.c_double, C.c_double]
         L.oracle_gammainc_lower.restype = C.c_double
         _lib = L
@@ -251,3 +267,39 @@ def cuhre(integrand, ndim, *, epsrel=1e-3, epsabs=0.0, flags=0, mineval=0,
 
 def gammainc_lower(a, x):
     return float(lib().oracle_gammainc_lower(a, x))
+
+
+def suave(integrand, ndim, *, epsrel=0.0, epsabs=0.0, flags=0, seed=1, mineval=0,
+          maxeval=10**5, nnew=1000, flatness=25.0, nbins=128, nsplit=1, stream_id=0,
+          nvec=1000):
+    """Serial Suave (ncomp = 1).  Returns the results plus every region in
+    position order (bounds, estimates, inherited estimates, grids) and the
+    dimension of every split."""
+    max_regions = 1 + max(0, maxeval // (2 * nnew))
+    d, N = ndim, nbins
+    lo = np.zeros((max_regions, d))
+    hi = np.zeros((max_regions, d))
+    I = np.zeros(max_regions)
+    var = np.zeros(max_regions)
+    inh_I = np.zeros(max_regions)
+    inh_var = np.zeros(max_regions)
+    grid = np.zeros((max_regions, d, N + 1))
+    cut = np.zeros(max_regions, dtype=np.int32)
+    tr = _SuaveTrace(max_regions, max_regions, 0, 0, 0.0, 0, _dptr(lo), _dptr(hi), _dptr(I),
+                     _dptr(var), _dptr(inh_I), _dptr(inh_var), _dptr(grid),
+                     cut.ctypes.data_as(C.POINTER(C.c_int)))
+    nreg, neval, fail = C.c_int(), C.c_longlong(), C.c_int()
+    integral, error, prob = np.zeros(1), np.zeros(1), np.zeros(1)
+    rc = lib().oracle_suave(ndim, 1, integrand.fn, integrand.userdata, nvec, epsrel, epsabs,
+                            flags, seed, mineval, maxeval, nnew, flatness, nbins, nsplit,
+                            stream_id, C.byref(nreg), C.byref(neval), C.byref(fail),
+                            _dptr(integral), _dptr(error), _dptr(prob), C.byref(tr))
+    if rc != 0:
+        raise ValueError("oracle_suave: bad arguments")
+    R = nreg.value
+    ns = tr.nsplits
+    return dict(integral=float(integral[0]), error=float(error[0]), prob=float(prob[0]),
+                neval=neval.value, fail=fail.value, nregions=R, chi2=tr.chi2, dof=tr.dof,
+                lo=lo[:R].copy(), hi=hi[:R].copy(), I=I[:R].copy(), var=var[:R].copy(),
+                inh_I=inh_I[:R].copy(), inh_var=inh_var[:R].copy(), grid=grid[:R].copy(),
+                cut=cut[:ns].copy())

@@ -145,6 +145,34 @@ int oracle_cuhre(int ndim, int ncomp, oracle_integrand_t integrand,
                  double error[], double prob[], oracle_cuhre_trace *trace);
 
 /* Lower regularized incomplete gamma function P(a, x). */
+/* Suave (subregion-adaptive Vegas; the steps are listed in suave.cpp).
+ * Regions are reported in position order. */
+typedef struct {
+  int max_regions;    /* capacity of the per-region arrays */
+  int max_splits;     /* capacity of cut */
+  int nregions;       /* out */
+  int nsplits;        /* out: splits done */
+  double chi2;        /* out: summed over regions */
+  int dof;            /* out */
+  double *lo, *hi;    /* out: [nregions][ndim] bounds */
+  double *I, *var;    /* out: each region's combined estimate and variance */
+  double *inh_I;      /* out: the estimate inherited from the parent (0: none) */
+  double *inh_var;    /* out: its variance (0: none kept) */
+  double *grid;       /* out: [nregions][ndim][nbins + 1] grids */
+  int *cut;           /* out: the dimension of every split, in order */
+} oracle_suave_trace;
+
+/* The Suave prototype of Sect. 3.2.2 with ncomp = 1 (FP64), plus the bin
+ * count, the regions split per step (nsplit = 1: one at a time) and the
+ * Philox stream id.  Returns 0, or -1 for bad arguments.  fail: 0 accuracy
+ * reached, 1 maxeval reached first, -99 integrand aborted. */
+int oracle_suave(int ndim, int ncomp, oracle_integrand_t integrand, void *userdata, int nvec,
+                 double epsrel, double epsabs, int flags, unsigned long long seed,
+                 long long mineval, long long maxeval, long long nnew, double flatness,
+                 int nbins, int nsplit, unsigned int stream_id, int *nregions,
+                 long long *neval, int *fail, double integral[], double error[],
+                 double prob[], oracle_suave_trace *trace);
+
 double oracle_gammainc_lower(double a, double x);
 
 #ifdef __cplusplus
