@@ -254,6 +254,48 @@ int ccuba_vegas_batched(ccuba_ctx **ctx, int ndim, int ncomp, ccuba_batch_integr
                         unsigned int stream_id, long long *neval, int *fail, double integral[],
                         double error[], double prob[]);
 
+/* ---- Suave -----------------------------------------------------------------
+ * Subregion-adaptive Vegas: the Suave prototype of Sect. 3.2.2 (nnew,
+ * flatness, nregions), whose steps the paper does not give.  Reading: every
+ * region keeps its own Vegas grid and the values of its own nnew-point
+ * sample.  The root [0,1]^d is sampled first; then each step bisects the K
+ * regions of largest variance (ties: lower position), K = min(nsplit,
+ * regions, (maxeval - neval) / (2 nnew)), at the midpoint of the dimension
+ * whose halves have the least total fluctuation
+ *   F_h = (n_h/n) ((1/n_h) sum_{i in h} |v_i - m_h|^p)^(1/p),  p = flatness.
+ * A child's grid is its parent's, with the map along the cut restricted to
+ * the child's half; its result combines (inverse-variance weights) the
+ * estimate from its parent's sample points inside it with that of its own
+ * nnew new points.  The j-th split of the run draws its children's points
+ * with Philox iteration numbers 2j+1 and 2j+2 (the root: 0).  Totals: the sums
+ * of the regions' estimates and variances; prob = P(dof/2, chi^2/2) over the
+ * regions' combinations.  Stop when neval >= mineval and error <=
+ * max(epsabs, epsrel |integral|) (fail 0), or when no split fits maxeval (fail
+ * 1; maxeval < nnew samples nothing).  nsplit = 1 is one region at a time.
+ * flags: CCUBA_FP64, optionally CCUBA_FREEZE_GRID.  Ranges: 1 <= ndim <= 16,
+ * ncomp == 1, 2 <= nbins <= 256, 2 <= nnew < 2^32, flatness > 0,
+ * 1 <= nsplit <= 1024, regions at most 2^23.  The device holds 10 bytes per
+ * sampled point plus each region's grid.  Errors: CCUBA_EINVAL, CCUBA_EHIP,
+ * CCUBA_ENOMEM (beyond the budget). */
+typedef struct {
+  int max_regions;    /* capacity of the per-region arrays */
+  int max_splits;     /* capacity of cut */
+  int nregions;       /* out */
+  int nsplits;        /* out */
+  double chi2;        /* out: summed over the regions */
+  int dof;            /* out */
+  double *lo, *hi;    /* out: [nregions][ndim] bounds, in position order */
+  double *I, *var;    /* out: each region's combined estimate and variance */
+  double *grid;       /* out: [nregions][ndim][nbins + 1] (may be NULL) */
+  int *cut;           /* out: the dimension of every split, in order */
+} ccuba_suave_trace;
+
+int ccuba_suave(ccuba_ctx **ctx, int ndim, int ncomp, const ccuba_integrand *f, double epsrel,
+                double epsabs, int flags, unsigned long long seed, long long mineval,
+                long long maxeval, long long nnew, double flatness, int nbins, int nsplit,
+                unsigned int stream_id, int *nregions, long long *neval, int *fail,
+                double integral[], double error[], double prob[], ccuba_suave_trace *trace);
+
 /* Cuhre (Sect. 3.2.2 prototype) with the degree-7 Genz-Malik rule and its
  * embedded degree-5 rule (Genz & Malik 1980), error |I7 - I5|, bisection of
  * each selected region along its largest fourth difference.  Each step splits

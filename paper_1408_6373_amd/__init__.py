@@ -107,6 +107,21 @@ if hasattr(_lib, "ccuba_cuhre"):
                                   C.c_int, C.c_longlong, _ip, _llp, _ip, _dp, _dp, _dp])
     _sig("ccuba_cuhre_rule", C.c_int, [_CTXP, C.c_int, C.POINTER(Integrand), C.c_longlong,
                                        _dp, _dp, _dp, _dp, _dp, _ip])
+
+
+class SuaveTrace(C.Structure):
+    _fields_ = [("max_regions", C.c_int), ("max_splits", C.c_int), ("nregions", C.c_int),
+                ("nsplits", C.c_int), ("chi2", C.c_double), ("dof", C.c_int),
+                ("lo", _dp), ("hi", _dp), ("I", _dp), ("var", _dp), ("grid", _dp),
+                ("cut", _ip)]
+
+
+if hasattr(_lib, "ccuba_suave"):
+    _sig("ccuba_suave", C.c_int, [C.POINTER(_CTXP), C.c_int, C.c_int, C.POINTER(Integrand),
+                                  C.c_double, C.c_double, C.c_int, C.c_ulonglong,
+                                  C.c_longlong, C.c_longlong, C.c_longlong, C.c_double,
+                                  C.c_int, C.c_int, C.c_uint, _ip, _llp, _ip, _dp, _dp, _dp,
+                                  C.POINTER(SuaveTrace)])
 if hasattr(_lib, "ccuba_submit"):
     _sig("ccuba_submit", C.c_int, [_CTXP, C.POINTER(Job), C.POINTER(C.c_ulonglong)])
     _sig("ccuba_poll", C.c_int, [_CTXP, C.c_ulonglong, C.POINTER(Result)])
@@ -117,7 +132,7 @@ SYMBOLS = ["ccuba_init", "ccuba_shutdown", "ccuba_config", "ccuba_config_get",
            "ccuba_vegas_ex", "ccuba_cuhre", "ccuba_cuhre_rule", "ccuba_vegas_batch",
            "ccuba_submit", "ccuba_poll", "ccuba_drain", "ccuba_vegas_dosample_raw",
            "ccuba_vegas_points", "ccuba_vegas_refine", "ccuba_vegas_batched",
-           "ccuba_vegas_source", "ccuba_rtc_log", "ccuba_vegas_stateful"]
+           "ccuba_vegas_source", "ccuba_rtc_log", "ccuba_vegas_stateful", "ccuba_suave"]
 
 
 class CcubaError(RuntimeError):
@@ -460,6 +475,38 @@ def cuhre(family, a, u, *, ctx=None, epsrel=1e-3, epsabs=0.0, flags=0, mineval=0
                             _ptr(res[2])), "ccuba_cuhre")
     return dict(nregions=nreg.value, neval=neval.value, fail=fail.value,
                 integral=float(res[0][0]), error=float(res[1][0]), prob=float(res[2][0]))
+
+
+def suave(family, a, u, *, ctx=None, epsrel=0.0, epsabs=0.0, flags=0, seed=1, mineval=0,
+          maxeval=10**5, nnew=1000, flatness=25.0, nbins=128, nsplit=1, stream_id=0,
+          trace=False):
+    """Suave of a Genz integrand.  With trace=True the result also holds every
+    region in position order (bounds, estimates, grids) and the cut dimensions."""
+    f, keep = _integrand(family, a, u)
+    d = len(keep[0])
+    nreg, neval, fail = C.c_int(), C.c_longlong(), C.c_int()
+    res = [np.zeros(1) for _ in range(3)]
+    tr = None
+    if trace:
+        m = 1 + max(0, int(maxeval) // (2 * int(nnew)))
+        arrs = dict(lo=np.zeros((m, d)), hi=np.zeros((m, d)), I=np.zeros(m), var=np.zeros(m),
+                    grid=np.zeros((m, d, nbins + 1)), cut=np.zeros(m, dtype=np.int32))
+        tr = SuaveTrace(m, m, 0, 0, 0.0, 0, _ptr(arrs["lo"]), _ptr(arrs["hi"]),
+                        _ptr(arrs["I"]), _ptr(arrs["var"]), _ptr(arrs["grid"]),
+                        arrs["cut"].ctypes.data_as(_ip))
+    _check(_lib.ccuba_suave(_ctx_arg(ctx), d, 1, C.byref(f), epsrel, epsabs, flags, seed,
+                            mineval, maxeval, nnew, flatness, nbins, nsplit, stream_id,
+                            C.byref(nreg), C.byref(neval), C.byref(fail), _ptr(res[0]),
+                            _ptr(res[1]), _ptr(res[2]), C.byref(tr) if tr is not None else None),
+           "ccuba_suave")
+    out = dict(nregions=nreg.value, neval=neval.value, fail=fail.value,
+               integral=float(res[0][0]), error=float(res[1][0]), prob=float(res[2][0]))
+    if tr is not None:
+        R = tr.nregions
+        out.update(chi2=tr.chi2, dof=tr.dof, lo=arrs["lo"][:R].copy(), hi=arrs["hi"][:R].copy(),
+                   I=arrs["I"][:R].copy(), var=arrs["var"][:R].copy(),
+                   grid=arrs["grid"][:R].copy(), cut=arrs["cut"][:tr.nsplits].copy())
+    return out
 
 
 def cuhre_rule(ctx, family, a, u, c, h):

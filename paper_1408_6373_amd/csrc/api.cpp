@@ -14,6 +14,7 @@
 #include "tune.h"
 #include "rtc.h"
 #include "vegas_state.h"
+#include "suave_engine.h"
 #include "vegas_batched.h"
 #include "vegas_engine.h"
 
@@ -196,6 +197,7 @@ int ccuba_init(ccuba_ctx **ctx, int device, size_t hbm_budget) {
   c->budget = hbm_budget;
   if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) return CCUBA_EHIP;
   if (set_kernel_limits() != hipSuccess) return CCUBA_EHIP;
+  if (suave_set_kernel_limits() != hipSuccess) return CCUBA_EHIP;
   for (int p = 0; p < 2; ++p) {
     c->tune[p].block = (int)env_ll("CCUBA_BLOCK", 256);
     c->tune[p].blocks_per_cu = (int)env_ll("CCUBA_BLOCKS_PER_CU", 3);
@@ -685,6 +687,74 @@ int ccuba_cuhre(ccuba_ctx **ctxp, int ndim, int ncomp, const ccuba_integrand *f,
   integral[0] = run.integral();
   error[0] = run.error();
   prob[0] = 0.0;
+  return CCUBA_OK;
+}
+
+int ccuba_suave(ccuba_ctx **ctxp, int ndim, int ncomp, const ccuba_integrand *f, double epsrel,
+                double epsabs, int flags, unsigned long long seed, long long mineval,
+                long long maxeval, long long nnew, double flatness, int nbins, int nsplit,
+                unsigned int stream_id, int *nregions, long long *neval, int *fail,
+                double integral[], double error[], double prob[], ccuba_suave_trace *trace) {
+  if (!f || !f->a || !f->u || ncomp != 1 || !nregions || !neval || !fail || !integral ||
+      !error || !prob || ndim < 1 || ndim > kMaxDim ||
+      (flags & CCUBA_PRECISION_MASK) != CCUBA_FP64 || (flags & ~(CCUBA_PRECISION_MASK |
+                                                                 CCUBA_FREEZE_GRID)))
+    return CCUBA_EINVAL;
+  SuaveSpec sp;
+  sp.ndim = ndim;
+  sp.nbins = nbins;
+  sp.family = f->family;
+  sp.flags = flags & CCUBA_FREEZE_GRID ? FLAG_FREEZE_GRID : 0;
+  for (int j = 0; j < ndim; ++j) {
+    sp.a[j] = f->a[j];
+    sp.u[j] = f->u[j];
+  }
+  sp.seed = seed;
+  sp.sid = stream_id;
+  sp.epsrel = epsrel;
+  sp.epsabs = epsabs;
+  sp.mineval = mineval;
+  sp.maxeval = maxeval;
+  sp.nnew = nnew;
+  sp.flatness = flatness;
+  sp.nsplit = nsplit;
+  if (validate_suave(sp)) return CCUBA_EINVAL;
+  if (trace && ((trace->max_regions > 0 && (!trace->lo || !trace->hi || !trace->I ||
+                                            !trace->var)) ||
+                (trace->max_splits > 0 && !trace->cut) || trace->max_regions < 0 ||
+                trace->max_splits < 0))
+    return CCUBA_EINVAL;
+  CtxScope scope(ctxp);
+  if (scope.rc) return scope.rc;
+  ccuba_ctx *ctx = scope.ctx;
+  std::lock_guard<std::mutex> g(ctx->lock);
+  CCUBA_HIP(hipSetDevice(ctx->device));
+  SuaveResult res;
+  SuaveTraceOut to;
+  if (trace) {
+    to.max_regions = trace->max_regions;
+    to.max_splits = trace->max_splits;
+    to.lo = trace->lo;
+    to.hi = trace->hi;
+    to.I = trace->I;
+    to.var = trace->var;
+    to.grid = trace->grid;
+    to.cut = trace->cut;
+  }
+  int rc = run_suave(ctx, sp, res, trace ? &to : nullptr, ctx->stream);
+  if (rc) return rc;
+  *nregions = res.nregions;
+  *neval = res.neval;
+  *fail = res.fail;
+  integral[0] = res.integral;
+  error[0] = res.error;
+  prob[0] = res.prob;
+  if (trace) {
+    trace->nregions = res.nregions;
+    trace->nsplits = (int)res.nsplits;
+    trace->chi2 = res.chi2;
+    trace->dof = res.dof;
+  }
   return CCUBA_OK;
 }
 

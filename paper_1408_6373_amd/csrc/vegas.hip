@@ -24,45 +24,11 @@
 #include "philox.h"
 #include "vegas.h"
 #include "vegas_sample.h"
+#include "refine.h"
 
 #include <vector>
 
 namespace ccuba {
-
-// ---------------------------------------------------------------------------
-// a7: lower regularized incomplete gamma P(a, x) for the chi^2 probability,
-// by its power series below a+1 and Legendre's continued fraction for Q = 1-P
-// above (Abramowitz & Stegun 6.5.29, 6.5.31; Lentz's evaluation).
-
-__device__ double gamma_p(double a, double x) {
-  if (x <= 0.0) return 0.0;
-  if (isinf(x)) return 1.0;
-  const double lead = exp(-x + a * log(x) - lgamma(a));
-  if (x < a + 1.0) {
-    double term = 1.0 / a, sum = term;
-    for (int n = 1; n < 100000; ++n) {
-      term *= x / (a + n);
-      sum += term;
-      if (fabs(term) < fabs(sum) * 1e-17) break;
-    }
-    return sum * lead;
-  }
-  const double tiny = 1e-300;
-  double b = x + 1.0 - a, c = 1.0 / tiny, dd = 1.0 / b, h = dd;
-  for (int i = 1; i < 100000; ++i) {
-    const double an = -i * (i - a);
-    b += 2.0;
-    dd = an * dd + b;
-    if (fabs(dd) < tiny) dd = tiny;
-    c = b + an / c;
-    if (fabs(c) < tiny) c = tiny;
-    dd = 1.0 / dd;
-    const double delta = dd * c;
-    h *= delta;
-    if (fabs(delta - 1.0) < 1e-17) break;
-  }
-  return 1.0 - lead * h;
-}
 
 static_assert(kGroupTiles % 32 == 0, "a group's tile sums fill whole wavefronts");
 constexpr int kFoldBatch = kGroupTiles < 64 ? kGroupTiles : 64;  // rows in flight per lane
@@ -174,21 +140,6 @@ __global__ void __launch_bounds__(256) vegas_fold2_kernel(FoldArgs F) {
   }
 }
 
-__device__ __forceinline__ double wave_scan_incl(double v, int lane) {
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const double t = __shfl_up(v, o, 64);
-    if (lane >= o) v += t;
-  }
-  return v;
-}
-
-__device__ __forceinline__ void wave_sync_lds() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // a7, the iteration's statistics for one component: the estimate I_t and
 // variance sigma_t^2 of iteration t = st.T from its sums over n points,
 // folded into the running inverse-variance combination (sums added in
@@ -241,80 +192,6 @@ __device__ __forceinline__ void finish_state(VState &st, bool conv, bool budget,
     }
     st.chi2 = chi2;
     st.prob = st.dof > 0 ? gamma_p(0.5 * st.dof, 0.5 * chi2) : 0.0;
-  }
-}
-
-// a7, the grid: one dimension's refinement by one wavefront.  The histogram
-// row h is smoothed, damped and prefix-summed (lanes own contiguous runs of
-// bins, wave-wide scans), and every new edge is placed by a binary search of
-// the prefix sums.  h, dd and Eo are LDS rows (h is overwritten with the
-// prefix sums); En receives the N + 1 new edges.
-__device__ __forceinline__ void rebin_dimension(double *h, double *dd, const double *Eo,
-                                                double *En, int N, int lane) {
-  const int per = (N + 63) >> 6;  // contiguous bins per lane
-  const int k0 = lane * per, k1 = min(k0 + per, N);
-  // smoothing and the two row sums
-  double hs = 0.0, ds = 0.0;
-  for (int k = k0; k < k1; ++k) {
-    double v;
-    if (k == 0)
-      v = (h[0] + h[1]) / 2.0;
-    else if (k == N - 1)
-      v = (h[N - 2] + h[N - 1]) / 2.0;
-    else
-      v = (h[k - 1] + h[k] + h[k + 1]) / 3.0;
-    hs += h[k];
-    ds += v;
-    dd[k] = v;
-  }
-  hs = wave_sum(hs);
-  ds = wave_sum(ds);
-  if (!(hs > 0.0)) {  // nothing sampled in this dimension: the edges are kept
-    for (int i = lane; i <= N; i += 64) En[i] = Eo[i];
-    return;
-  }
-  // damping, then prefix sums of m into h (the histogram is no longer needed)
-  wave_sync_lds();
-  double run = 0.0;
-  for (int k = k0; k < k1; ++k) {
-    const double r = dd[k] / ds;
-    double m;
-    if (r == 0.0)
-      m = 0.0;
-    else if (r == 1.0)
-      m = 1.0;
-    else {
-      const double q = (r - 1.0) / log(r);
-      m = q * sqrt(q);  // q^1.5
-    }
-    dd[k] = m;
-    run += m;
-  }
-  const double incl = wave_scan_incl(run, lane);
-  double acc = incl - run;
-  for (int k = k0; k < k1; ++k) {
-    acc += dd[k];
-    h[k] = acc;
-  }
-  wave_sync_lds();
-  const double share = h[N - 1] / N;
-  // new edge i: smallest old bin k with C_k >= i * share
-  for (int i = lane; i <= N; i += 64) {
-    if (i == 0 || i == N) {
-      En[i] = i == 0 ? 0.0 : 1.0;
-      continue;
-    }
-    const double target = i * share;
-    int lo = 0, hi = N - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (h[mid] < target)
-        lo = mid + 1;
-      else
-        hi = mid;
-    }
-    const double before = lo > 0 ? h[lo - 1] : 0.0;
-    En[i] = Eo[lo] + (target - before) / dd[lo] * (Eo[lo + 1] - Eo[lo]);
   }
 }
 

@@ -1,0 +1,138 @@
+"""GPU parity of Suave (ccuba_suave) against the oracle.
+
+Bar: the same regions (bounds bit-exact, the same cut of every split), neval,
+fail and region count; integral within 1e-12 relative, error within 1e-10,
+per-region estimates within 1e-11, prob within 1e-9.  The two sides differ
+only in rounding order (the device sums tile partials and LDS-atomic
+histograms; the oracle sums every point in order with Neumaier), so
+selection and cut decisions agree unless two candidates tie to ~1e-15.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from closed_forms import exact
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cc():
+    import paper_1408_6373_amd as cc
+    return cc
+
+
+@pytest.fixture(scope="module")
+def ctx(cc):
+    c = cc.Context()
+    yield c
+    c.close()
+
+
+def _rel(a, b):
+    return abs(a - b) / max(abs(b), 1e-300)
+
+
+def _compare(g, o, tol=1e-12):
+    print("regions", g["nregions"], o["nregions"], "neval", g["neval"], o["neval"], flush=True)
+    assert g["nregions"] == o["nregions"] and g["neval"] == o["neval"]
+    assert g["fail"] == o["fail"]
+    assert np.array_equal(g["cut"], o["cut"])
+    assert np.array_equal(g["lo"], o["lo"]) and np.array_equal(g["hi"], o["hi"])
+    assert np.allclose(g["I"], o["I"], rtol=tol * 10, atol=0)
+    assert np.allclose(g["var"], o["var"], rtol=tol * 100, atol=0)
+    assert _rel(g["integral"], o["integral"]) < tol
+    assert _rel(g["error"], o["error"]) < tol * 100
+    assert abs(g["prob"] - o["prob"]) < 1e-9
+    assert g["dof"] == o["dof"]
+
+
+def _both(cc, ctx, fam, d, seed=1, **kw):
+    a, u = W.genz_params(fam, d, seed)
+    g = cc.suave(fam, a, u, ctx=ctx, trace=True, seed=seed, **kw)
+    o = O.suave(O.genz(fam, a, u), d, seed=seed, **kw)
+    return g, o
+
+
+@pytest.mark.parametrize("fam", range(5))
+@pytest.mark.parametrize("d", [3, 6])
+def test_matches_oracle(cc, ctx, fam, d):
+    # 5000 points: one full tile of 4096 and a ragged one
+    g, o = _both(cc, ctx, fam, d, seed=fam + 10 * d, nnew=5000, maxeval=120000, nbins=32)
+    assert g["nregions"] > 5
+    _compare(g, o)
+    assert np.allclose(g["grid"], o["grid"], rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("nsplit", [2, 8, 64])
+def test_batched_splits_match_oracle(cc, ctx, nsplit):
+    g, o = _both(cc, ctx, W.PRODUCT_PEAK, 4, seed=3, nnew=3000, maxeval=600000, nbins=64,
+                 nsplit=nsplit, flatness=5.0)
+    assert g["nregions"] > 2 * nsplit or g["nregions"] == 1 + len(o["cut"])
+    _compare(g, o)
+
+
+@pytest.mark.parametrize("d,N,nnew", [(1, 2, 2), (1, 7, 50), (2, 3, 4097), (16, 256, 1000),
+                                      (13, 128, 8192)])
+def test_extreme_shapes(cc, ctx, d, N, nnew):
+    g, o = _both(cc, ctx, W.C0, d, seed=d, nnew=nnew, maxeval=9 * nnew, nbins=N)
+    _compare(g, o)
+
+
+def test_budget_edges(cc, ctx):
+    a, u = W.genz_params(W.GAUSSIAN, 3, 4)
+    r = cc.suave(W.GAUSSIAN, a, u, ctx=ctx, nnew=1000, maxeval=999)
+    assert r["neval"] == 0 and r["nregions"] == 0 and r["fail"] == 1 and r["integral"] == 0
+    g, o = _both(cc, ctx, W.GAUSSIAN, 3, seed=4, nnew=1000, maxeval=2999)
+    assert g["nregions"] == 1
+    _compare(g, o)
+    # more splits asked for than regions exist, and a budget cut short
+    g, o = _both(cc, ctx, W.GAUSSIAN, 3, seed=4, nnew=1000, maxeval=11000, nsplit=4)
+    assert g["nregions"] == 6
+    _compare(g, o)
+
+
+def test_frozen_grid_and_flatness(cc, ctx):
+    for kw in (dict(flags=cc.FREEZE_GRID), dict(flatness=1.0), dict(flatness=700.0)):
+        g, o = _both(cc, ctx, W.CORNER_PEAK, 4, seed=5, nnew=2000, maxeval=60000, nbins=16, **kw)
+        _compare(g, o)
+        if "flags" in kw:
+            assert np.all(g["grid"] == np.arange(17) / 16)
+
+
+def test_constant_integrand(cc, ctx):
+    r = cc.suave(W.GAUSSIAN, np.zeros(5), np.full(5, 0.5), ctx=ctx, nnew=4000, epsrel=1e-3,
+                 maxeval=10**6)
+    assert r["integral"] == 1.0 and r["error"] == 0.0
+    assert r["fail"] == 0 and r["neval"] == 4000 and r["nregions"] == 1
+
+
+@pytest.mark.parametrize("fam", range(5))
+def test_converges_to_the_closed_form(cc, ctx, fam):
+    d = 5
+    a, u = W.genz_params(fam, d, 21)
+    ex = exact(fam, a, u)
+    # the oscillatory family gains little from grids or cuts: a looser goal
+    eps = 1e-3 if fam == W.OSCILLATORY else 1e-4
+    r = cc.suave(fam, a, u, ctx=ctx, nnew=20000, nsplit=16, maxeval=5 * 10**7, epsrel=eps)
+    assert r["fail"] == 0 and r["error"] <= eps * abs(r["integral"])
+    assert abs(r["integral"] - ex) <= 4 * r["error"]
+
+
+def test_bench_shape_first_steps_match_oracle(cc, ctx):
+    # d = 8 Gaussian, nnew = 2^16 points per region, 64 splits per step:
+    # steps split 1, 2, 4, ..., 64 regions, then the one the budget leaves
+    g, o = _both(cc, ctx, W.GAUSSIAN, 8, seed=2, nnew=1 << 16, nsplit=64,
+                 maxeval=257 * (1 << 16), nbins=128)
+    assert g["nregions"] == 129 and g["neval"] == 257 * (1 << 16)
+    _compare(g, o)
+
+
+def test_bad_arguments(cc, ctx):
+    a, u = W.genz_params(W.GAUSSIAN, 3, 4)
+    for kw in (dict(nnew=1), dict(flatness=0.0), dict(flatness=float("inf")), dict(nsplit=0),
+               dict(nsplit=1025), dict(nbins=1), dict(nbins=257), dict(flags=cc.FP32_EVAL)):
+        with pytest.raises(cc.CcubaError) as e:
+            cc.suave(W.GAUSSIAN, a, u, ctx=ctx, **kw)
+        assert e.value.rc == cc.EINVAL
