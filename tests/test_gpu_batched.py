@@ -50,7 +50,10 @@ def _close(g, o, tol):
     for c in range(len(gi)):
         assert _rel(gi[c], oi[c]) < tol, (c, gi[c], oi[c])
         assert _rel(ge[c], oe[c]) < tol or ge[c] == oe[c] == 0.0
-        assert abs(gp[c] - op[c]) < max(tol, 1e-12)
+        # prob = P(dof/2, chi^2/2) moves by the chi^2 density times the chi^2
+        # rounding difference; over tens of iterations summed in another
+        # order (and LDS-atomic histograms) that reaches ~1e-12 absolute
+        assert abs(gp[c] - op[c]) < max(tol, 1e-10)
 
 
 @pytest.mark.parametrize("nvec", [1000, 4096, 30000])
