@@ -332,6 +332,48 @@ def _cuhre_leg(cc, ctx):
             "rule_launches": st.rule_launches}
 
 
+SUAVE_NNEW, SUAVE_SPLIT, SUAVE_STEPS = 1 << 17, 64, 30
+
+
+def _suave_maxeval(nnew, K, steps):
+    """Budget of the root sampling plus `steps` steps (K regions split per step
+    once that many exist)."""
+    m, R = nnew, 1
+    for _ in range(steps):
+        k = min(K, R)
+        m += 2 * k * nnew
+        R += k
+    return m
+
+
+def _suave_leg(cc, ctx, cpu=True):
+    import workloads as W
+    a, u = W.genz_params(W.GAUSSIAN, 8, 1)
+    kw = dict(nnew=SUAVE_NNEW, nsplit=SUAVE_SPLIT, nbins=128, flatness=25.0,
+              maxeval=_suave_maxeval(SUAVE_NNEW, SUAVE_SPLIT, SUAVE_STEPS))
+    cc.suave(W.GAUSSIAN, a, u, ctx=ctx, **kw)  # warm-up (buffers, code objects)
+    best = None
+    for _ in range(3):  # the call returns once its results are on the host
+        t0 = time.perf_counter()
+        r = cc.suave(W.GAUSSIAN, a, u, ctx=ctx, **kw)
+        dt = time.perf_counter() - t0
+        best = dt if best is None else min(best, dt)
+    out = {"workload": "Suave Gaussian d=8, 128 bins, nnew=2^17 points per region, 64 splits "
+                       "per step, flatness 25, 30 steps, FP64",
+           "value": r["neval"] / best, "unit": "evals/s", "seconds": best,
+           "neval": r["neval"], "nregions": r["nregions"],
+           "rel_error": r["error"] / abs(r["integral"])}
+    if cpu:  # the oracle on the first 4 steps of the same workload (about 4e6 points)
+        import oracle as O
+        okw = dict(kw, maxeval=_suave_maxeval(SUAVE_NNEW, SUAVE_SPLIT, 4))
+        t0 = time.perf_counter()
+        o = O.suave(O.genz(W.GAUSSIAN, a, u), 8, **okw)
+        odt = time.perf_counter() - t0
+        out["cpu_oracle"] = {"value": o["neval"] / odt, "unit": "evals/s", "cores": 1,
+                             "kind": "oracle", "sample": "root + 4 steps (%d points)" % o["neval"]}
+    return out
+
+
 def _serving_specs(cc, reqs):
     specs = []
     for r in reqs:
@@ -410,6 +452,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip batch/cuhre/serving legs")
     ap.add_argument("--serving-requests", type=int, default=300)
+    ap.add_argument("--suave-only", action="store_true",
+                    help="run only the Suave leg and print its JSON line (for profiling)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="for PMC runs: one 1 GiB device copy (calibration), then one FP32 "
                          "integral of the headline workload; prints a JSON line")
@@ -451,6 +495,10 @@ def main():
         print(json.dumps({"traffic_probe": True, "copy_bytes": 1 << 30, "neval": r["neval"]}))
         return
     ctx = cc.Context(device=0)
+    if args.suave_only:
+        print(json.dumps({"suave": _suave_leg(cc, ctx, cpu=False)}))
+        ctx.close()
+        return
 
     ev32, t32 = _timed(cc, ctx, params, cc.FP32_EVAL, args.steps, args.warmup)
     value = ev32 / t32
@@ -474,6 +522,7 @@ def main():
         out["batch"] = _batch_leg(cc)
         out["caller_integrand"] = _caller_integrand_leg(cc)
         out["cuhre"] = _cuhre_leg(cc, ctx)
+        out["suave"] = _suave_leg(cc, ctx, cpu=not args.no_cpu_baseline)
     ctx.close()
     if not args.no_extra:
         out["serving"] = _serving_leg(cc, args.serving_requests)

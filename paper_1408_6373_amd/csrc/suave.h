@@ -44,6 +44,8 @@ struct SuaveArgs {
   int ntiles;             // sampling tiles per child
   int nchunks;            // split-statistics chunks per region
   double flatness;
+  int ipow;               // flatness when it is a whole number in [1, 4096], else 0
+  int pad;
   const double *p64;      // [2][kParamRow] integrand constants
   int *sel;               // [K] selected positions in selection order
   int *chpos, *chser;     // [2K] children's positions and sampling serials

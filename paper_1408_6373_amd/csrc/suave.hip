@@ -68,26 +68,6 @@ __device__ __forceinline__ unsigned long long var_key(double x) {
   return (unsigned long long)__double_as_longlong(x);  // variances are >= 0
 }
 
-// (M, q) with q = sum (a_i / M)^p: the p-th power sum scaled by its largest term
-struct PowSum {
-  double M, q;
-};
-__device__ __forceinline__ void pow_add(PowSum &s, double a, double p) {
-  if (a > s.M) {
-    s.q = (s.M > 0.0 ? s.q * pow(s.M / a, p) : 0.0) + 1.0;
-    s.M = a;
-  } else if (s.M > 0.0) {
-    s.q += pow(a / s.M, p);
-  }
-}
-__device__ __forceinline__ PowSum pow_merge(PowSum x, PowSum y, double p) {
-  const double M = fmax(x.M, y.M);
-  PowSum r{M, 0.0};
-  if (x.M > 0.0) r.q += x.q * pow(x.M / M, p);
-  if (y.M > 0.0) r.q += y.q * pow(y.M / M, p);
-  return r;
-}
-
 }  // namespace
 
 __global__ void __launch_bounds__(256) suave_root_kernel(SuaveArgs A) {
@@ -223,75 +203,95 @@ __global__ void __launch_bounds__(1024) suave_select_kernel(SuaveArgs A, int R, 
 //   pass 2, per (dimension, half): sum (|v - m_h| / M_h)^p.
 // Chunk partials are reduced in chunk order wherever they are needed.
 constexpr int kP1 = 9;       // per (chunk, dimension): cnt1, S1_0, S2_0, S1_1, S2_1, min0, max0, min1, max1
-constexpr int kP1Dims = 2;   // dimensions per pass-1 workgroup
-constexpr int kP2Dims = 4;   // dimensions per pass-2 workgroup
 
-__device__ __forceinline__ double wave_min(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-  return v;
-}
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
+// Both passes stage their chunk in LDS once; then G threads per dimension
+// (G = 256 over d rounded up to a power of two, at most 64) accumulate over
+// it, two points at a time into independent partial sums, and reduce with
+// shuffles within their G-lane group.
+__device__ __forceinline__ int lanes_per_dim(int d) {
+  int dp = 1;
+  while (dp < d) dp <<= 1;
+  return min(64, 256 / dp);
 }
 
-__global__ void __launch_bounds__(256) suave_fluct1_kernel(SuaveArgs A) {
-  __shared__ double red[kP1Dims][kP1][4];
-  const int ch = blockIdx.x, j0 = blockIdx.y * kP1Dims, s = blockIdx.z, tid = threadIdx.x;
-  const int pos = A.sel[s], d = A.d;
-  const long long n = A.nnew;
-  const long long i0 = (long long)ch * kSuaveChunk, i1 = min(i0 + (long long)kSuaveChunk, n);
-  const double *v = A.R.v + (size_t)pos * n;
-  const uint16_t *sd = A.R.side + (size_t)pos * n;
-  double acc[kP1Dims][kP1];
+__device__ __forceinline__ int stage_chunk(const double *vall, const uint16_t *sall, int pos,
+                                           long long n, int ch, double *sv, uint16_t *sb) {
+  const long long i0 = (long long)ch * kSuaveChunk;
+  const int cnt = (int)min((long long)kSuaveChunk, n - i0);
+  const double *v = vall + (size_t)pos * n + i0;
+  const uint16_t *sd = sall + (size_t)pos * n + i0;
+  // all of a thread's loads in flight at once (kSuaveChunk / 256 each)
+  constexpr int kPer = kSuaveChunk / 256;
+  double tv[kPer];
+  uint16_t tb[kPer];
 #pragma unroll
-  for (int g = 0; g < kP1Dims; ++g) {
-#pragma unroll
-    for (int q = 0; q < 5; ++q) acc[g][q] = 0.0;
-    acc[g][5] = acc[g][7] = INFINITY;
-    acc[g][6] = acc[g][8] = -INFINITY;
+  for (int k = 0; k < kPer; ++k) {
+    const int i = threadIdx.x + 256 * k;
+    tv[k] = i < cnt ? v[i] : 0.0;
+    tb[k] = i < cnt ? sd[i] : (uint16_t)0;
   }
-  for (long long i = i0 + tid; i < i1; i += 256) {
-    const double x = v[i];
-    const unsigned bits = sd[i];
 #pragma unroll
-    for (int g = 0; g < kP1Dims; ++g) {
-      if ((bits >> (j0 + g)) & 1u) {
-        acc[g][0] += 1.0;
-        acc[g][3] += x;
-        acc[g][4] += x * x;
-        acc[g][7] = fmin(acc[g][7], x);
-        acc[g][8] = fmax(acc[g][8], x);
-      } else {
-        acc[g][1] += x;
-        acc[g][2] += x * x;
-        acc[g][5] = fmin(acc[g][5], x);
-        acc[g][6] = fmax(acc[g][6], x);
-      }
-    }
+  for (int k = 0; k < kPer; ++k) {
+    sv[threadIdx.x + 256 * k] = tv[k];
+    sb[threadIdx.x + 256 * k] = tb[k];
   }
-  const int w = tid >> 6, lane = tid & 63;
-#pragma unroll
-  for (int g = 0; g < kP1Dims; ++g)
-#pragma unroll
-    for (int q = 0; q < kP1; ++q) {
-      double r = acc[g][q];
-      r = (q == 5 || q == 7) ? wave_min(r) : (q == 6 || q == 8) ? wave_max(r) : wave_sum(r);
-      if (lane == 0) red[g][q][w] = r;
-    }
   __syncthreads();
-  if (tid < kP1Dims * kP1) {
-    const int g = tid / kP1, q = tid % kP1;
-    if (j0 + g < d) {
-      double r = red[g][q][0];
-      for (int u = 1; u < 4; ++u) {
-        const double t = red[g][q][u];
-        r = (q == 5 || q == 7) ? fmin(r, t) : (q == 6 || q == 8) ? fmax(r, t) : r + t;
-      }
-      A.fl1[(((size_t)s * A.nchunks + ch) * d + j0 + g) * kP1 + q] = r;
-    }
+  return cnt;
+}
+
+// pass-1 partial sums: cnt1, S1_0, S2_0, S1_1, S2_1, min0, max0, min1, max1
+__device__ __forceinline__ void p1_init(double (&a)[kP1]) {
+#pragma unroll
+  for (int q = 0; q < 5; ++q) a[q] = 0.0;
+  a[5] = a[7] = INFINITY;
+  a[6] = a[8] = -INFINITY;
+}
+__device__ __forceinline__ void p1_add(double (&a)[kP1], double x, bool up) {
+  // branch-free (a branch here sends both partials to scratch); adding 0.0
+  // to the other half's sums leaves them unchanged
+  const double xu = up ? x : 0.0, xl = up ? 0.0 : x;
+  a[0] += up ? 1.0 : 0.0;
+  a[1] += xl;
+  a[2] += xl * xl;
+  a[3] += xu;
+  a[4] += xu * xu;
+  a[5] = up ? a[5] : fmin(a[5], x);
+  a[6] = up ? a[6] : fmax(a[6], x);
+  a[7] = up ? fmin(a[7], x) : a[7];
+  a[8] = up ? fmax(a[8], x) : a[8];
+}
+__device__ __forceinline__ double p1_merge(int q, double x, double y) {
+  return (q == 5 || q == 7) ? fmin(x, y) : (q == 6 || q == 8) ? fmax(x, y) : x + y;
+}
+
+// Pass 1 over one chunk: grid (chunk, selected region).
+__global__ void __launch_bounds__(256) suave_fluct1_kernel(SuaveArgs A) {
+  __shared__ double sv[kSuaveChunk];
+  __shared__ uint16_t sb[kSuaveChunk];
+  const int ch = blockIdx.x, s = blockIdx.y, tid = threadIdx.x, d = A.d;
+  const int cnt = stage_chunk(A.R.v, A.R.side, A.sel[s], A.nnew, ch, sv, sb);
+  const int G = lanes_per_dim(d);
+  const int j = tid / G, sub = tid % G;
+  if (j >= d) return;
+  double x0[kP1], x1[kP1];
+  p1_init(x0);
+  p1_init(x1);
+  int i = sub;
+  for (; i + G < cnt; i += 2 * G) {
+    p1_add(x0, sv[i], (sb[i] >> j) & 1u);
+    p1_add(x1, sv[i + G], (sb[i + G] >> j) & 1u);
+  }
+  if (i < cnt) p1_add(x0, sv[i], (sb[i] >> j) & 1u);
+#pragma unroll
+  for (int q = 0; q < kP1; ++q) {
+    double r = p1_merge(q, x0[q], x1[q]);
+    for (int o = G >> 1; o > 0; o >>= 1) r = p1_merge(q, r, __shfl_xor(r, o, G));
+    x0[q] = r;
+  }
+  if (sub == 0) {
+    double *r = A.fl1 + (((size_t)s * A.nchunks + ch) * d + j) * kP1;
+#pragma unroll
+    for (int q = 0; q < kP1; ++q) r[q] = x0[q];
   }
 }
 
@@ -304,6 +304,7 @@ struct HalfStats {
 __device__ HalfStats half_stats(const SuaveArgs &A, int s, int j) {
   double c1 = 0.0, a0 = 0.0, q0 = 0.0, a1 = 0.0, q1 = 0.0;
   double mn0 = INFINITY, mx0 = -INFINITY, mn1 = INFINITY, mx1 = -INFINITY;
+#pragma unroll 8
   for (int ch = 0; ch < A.nchunks; ++ch) {
     const double *r = A.fl1 + (((size_t)s * A.nchunks + ch) * A.d + j) * kP1;
     c1 += r[0];
@@ -332,63 +333,66 @@ __device__ HalfStats half_stats(const SuaveArgs &A, int s, int j) {
 
 }  // namespace
 
+namespace {
+
+// r^p for r in [0, 1] (0^p = 0): by squaring for a whole p
+__device__ __forceinline__ double pow01(double r, double p, int ip) {
+  if (ip > 0) {
+    double t = 1.0, b = r;
+    for (int e = ip; e; e >>= 1) {
+      if (e & 1) t *= b;
+      b *= b;
+    }
+    return t;
+  }
+  return r > 0.0 ? exp2(p * log2(r)) : 0.0;
+}
+
+}  // namespace
+
+// Pass 2 over one chunk: grid (chunk, selected region).
 __global__ void __launch_bounds__(256) suave_fluct2_kernel(SuaveArgs A) {
-  __shared__ double sm[kP2Dims][2], sinv[kP2Dims][2];
-  __shared__ double red[kP2Dims][2][4];
-  const int ch = blockIdx.x, j0 = blockIdx.y * kP2Dims, s = blockIdx.z, tid = threadIdx.x;
-  const int pos = A.sel[s], d = A.d;
-  if (tid < kP2Dims && j0 + tid < d) {
-    const HalfStats h = half_stats(A, s, j0 + tid);
+  __shared__ double sv[kSuaveChunk];
+  __shared__ uint16_t sb[kSuaveChunk];
+  __shared__ double sm[kMaxDim][2], sinv[kMaxDim][2];
+  const int ch = blockIdx.x, s = blockIdx.y, tid = threadIdx.x, d = A.d;
+  if (tid < d) {
+    const HalfStats h = half_stats(A, s, tid);
     for (int k = 0; k < 2; ++k) {
       sm[tid][k] = h.m[k];
       sinv[tid][k] = h.M[k] > 0.0 ? 1.0 / h.M[k] : 0.0;
     }
   }
-  __syncthreads();
+  const int cnt = stage_chunk(A.R.v, A.R.side, A.sel[s], A.nnew, ch, sv, sb);
+  const int G = lanes_per_dim(d);
+  const int j = tid / G, sub = tid % G;
+  if (j >= d) return;
   const double p = A.flatness;
-  const long long n = A.nnew;
-  const long long i0 = (long long)ch * kSuaveChunk, i1 = min(i0 + (long long)kSuaveChunk, n);
-  const double *v = A.R.v + (size_t)pos * n;
-  const uint16_t *sd = A.R.side + (size_t)pos * n;
-  double m[kP2Dims][2], inv[kP2Dims][2], q[kP2Dims][2];
-#pragma unroll
-  for (int g = 0; g < kP2Dims; ++g)
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      const bool live = j0 + g < d;
-      m[g][k] = live ? sm[g][k] : 0.0;
-      inv[g][k] = live ? sinv[g][k] : 0.0;
-      q[g][k] = 0.0;
-    }
-  for (long long i = i0 + tid; i < i1; i += 256) {
-    const double x = v[i];
-    const unsigned bits = sd[i];
-#pragma unroll
-    for (int g = 0; g < kP2Dims; ++g) {
-      const int k = (bits >> (j0 + g)) & 1u;
-      const double r = fabs(x - (k ? m[g][1] : m[g][0])) * (k ? inv[g][1] : inv[g][0]);
-      // r^p for r in [0, 1] (0^p = 0)
-      const double t = r > 0.0 ? exp2(p * log2(r)) : 0.0;
-      if (k)
-        q[g][1] += t;
-      else
-        q[g][0] += t;
-    }
+  const int ip = A.ipow;
+  const double m0 = sm[j][0], m1 = sm[j][1], i0v = sinv[j][0], i1v = sinv[j][1];
+  double q00 = 0.0, q01 = 0.0, q10 = 0.0, q11 = 0.0;  // [partial][half]
+  int i = sub;
+  for (; i + G < cnt; i += 2 * G) {
+    const bool ua = (sb[i] >> j) & 1u, ub = (sb[i + G] >> j) & 1u;
+    const double ta = pow01(fabs(sv[i] - (ua ? m1 : m0)) * (ua ? i1v : i0v), p, ip);
+    const double tb = pow01(fabs(sv[i + G] - (ub ? m1 : m0)) * (ub ? i1v : i0v), p, ip);
+    if (ua) q01 += ta; else q00 += ta;
+    if (ub) q11 += tb; else q10 += tb;
   }
-  const int w = tid >> 6, lane = tid & 63;
-#pragma unroll
-  for (int g = 0; g < kP2Dims; ++g)
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      const double r = wave_sum(q[g][k]);
-      if (lane == 0) red[g][k][w] = r;
-    }
-  __syncthreads();
-  if (tid < 2 * kP2Dims) {
-    const int g = tid >> 1, k = tid & 1;
-    if (j0 + g < d)
-      A.fl2[(((size_t)s * A.nchunks + ch) * d + j0 + g) * 2 + k] =
-          ((red[g][k][0] + red[g][k][1]) + red[g][k][2]) + red[g][k][3];
+  if (i < cnt) {
+    const bool ua = (sb[i] >> j) & 1u;
+    const double ta = pow01(fabs(sv[i] - (ua ? m1 : m0)) * (ua ? i1v : i0v), p, ip);
+    if (ua) q01 += ta; else q00 += ta;
+  }
+  double q0 = q00 + q10, q1 = q01 + q11;
+  for (int o = G >> 1; o > 0; o >>= 1) {
+    q0 += __shfl_xor(q0, o, G);
+    q1 += __shfl_xor(q1, o, G);
+  }
+  if (sub == 0) {
+    double *r = A.fl2 + (((size_t)s * A.nchunks + ch) * d + j) * 2;
+    r[0] = q0;
+    r[1] = q1;
   }
 }
 
@@ -439,6 +443,7 @@ __global__ void __launch_bounds__(256) suave_split_kernel(SuaveArgs A, int R, lo
     double score = 0.0;
     for (int k = 0; k < 2; ++k) {
       double q = 0.0;
+#pragma unroll 8
       for (int ch = 0; ch < A.nchunks; ++ch)
         q += A.fl2[(((size_t)s * A.nchunks + ch) * d + tid) * 2 + k];
       if (h.cnt[k] > 0.0 && h.M[k] > 0.0)
@@ -518,7 +523,7 @@ __global__ void __launch_bounds__(256) suave_split_kernel(SuaveArgs A, int R, lo
 }
 
 // DoSample of every child: one workgroup per (tile of kSuaveTile points, child).
-template <int FAM>
+template <int FAM, int NB>
 __global__ void __launch_bounds__(kSuaveBlock) suave_sample_kernel(SuaveArgs A) {
   extern __shared__ double lds[];
   __shared__ double sBlo[kMaxDim], sBw[kMaxDim], sP0[kMaxDim], sP1[kMaxDim];
@@ -557,10 +562,10 @@ __global__ void __launch_bounds__(kSuaveBlock) suave_sample_kernel(SuaveArgs A) 
     double w = 1.0;
     double acc = Genz<double, FAM>::init(phase0);
     uint32_t bits = 0;
-    int cell[kMaxDim];
+    int cell[4 * NB];
 #pragma unroll
-    for (int b = 0; b < kMaxDim / 4; ++b) {
-      if (4 * b < d) {
+    for (int b = 0; b < NB; ++b) {
+      {
         const U4 W = philox4x32_10(
             U4{(uint32_t)i, ((uint32_t)serial << 8) | (uint32_t)b, A.sid, 0u}, A.key0, A.key1);
         const uint32_t wd[4] = {W.x, W.y, W.z, W.w};
@@ -583,9 +588,6 @@ __global__ void __launch_bounds__(kSuaveBlock) suave_sample_kernel(SuaveArgs A) 
             cell[j] = e;
           }
         }
-      } else {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) cell[4 * b + q] = 0;
       }
     }
     const double v = (w * V) * Genz<double, FAM>::finish(acc, d);
@@ -595,7 +597,7 @@ __global__ void __launch_bounds__(kSuaveBlock) suave_sample_kernel(SuaveArgs A) 
     S1 += v;
     S2 += v2;
 #pragma unroll
-    for (int j = 0; j < kMaxDim; ++j)
+    for (int j = 0; j < 4 * NB; ++j)
       if (j < d) atomicAdd(&sH[cell[j]], v2);
   }
   S1 = block_sum(S1, red);
@@ -627,6 +629,7 @@ __global__ void __launch_bounds__(1024) suave_fold_kernel(SuaveArgs A) {
   const double *th = A.thist + (size_t)c * nt * dN;
   for (int e = tid; e < dN; e += 1024) {
     double h = 0.0;
+#pragma unroll 8
     for (int t = 0; t < nt; ++t) h += th[(size_t)t * dN + e];
     H[e] = h;
   }
@@ -711,11 +714,13 @@ size_t suave_fold_lds(int d, int N) {
 hipError_t suave_set_kernel_limits() {
   const int big = 160 * 1024;
   const void *fns[] = {(const void *)suave_fold_kernel,
-                       (const void *)suave_sample_kernel<GAUSSIAN>,
-                       (const void *)suave_sample_kernel<OSCILLATORY>,
-                       (const void *)suave_sample_kernel<PRODUCT_PEAK>,
-                       (const void *)suave_sample_kernel<CORNER_PEAK>,
-                       (const void *)suave_sample_kernel<C0>};
+#define CCUBA_SUAVE_FNS(F)                                                            \
+  (const void *)suave_sample_kernel<F, 1>, (const void *)suave_sample_kernel<F, 2>, \
+      (const void *)suave_sample_kernel<F, 3>, (const void *)suave_sample_kernel<F, 4>
+                       CCUBA_SUAVE_FNS(GAUSSIAN), CCUBA_SUAVE_FNS(OSCILLATORY),
+                       CCUBA_SUAVE_FNS(PRODUCT_PEAK), CCUBA_SUAVE_FNS(CORNER_PEAK),
+                       CCUBA_SUAVE_FNS(C0)};
+#undef CCUBA_SUAVE_FNS
   for (const void *f : fns)
     if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, big) != hipSuccess)
       (void)hipGetLastError();
@@ -733,10 +738,8 @@ hipError_t launch_suave_select(const SuaveArgs &A, int R, int K, hipStream_t s) 
 }
 
 hipError_t launch_suave_fluct(const SuaveArgs &A, int K, hipStream_t s) {
-  hipLaunchKernelGGL(suave_fluct1_kernel, dim3(A.nchunks, (A.d + kP1Dims - 1) / kP1Dims, K),
-                     dim3(256), 0, s, A);
-  hipLaunchKernelGGL(suave_fluct2_kernel, dim3(A.nchunks, (A.d + kP2Dims - 1) / kP2Dims, K),
-                     dim3(256), 0, s, A);
+  hipLaunchKernelGGL(suave_fluct1_kernel, dim3(A.nchunks, K), dim3(256), 0, s, A);
+  hipLaunchKernelGGL(suave_fluct2_kernel, dim3(A.nchunks, K), dim3(256), 0, s, A);
   return hipGetLastError();
 }
 
@@ -745,24 +748,46 @@ hipError_t launch_suave_split(const SuaveArgs &A, int R, long long Q, int K, hip
   return hipGetLastError();
 }
 
+namespace {
+
+template <int FAM>
+void launch_sample_fam(const SuaveArgs &A, dim3 grid, size_t lds, hipStream_t s) {
+  switch ((A.d + 3) / 4) {
+    case 1:
+      hipLaunchKernelGGL((suave_sample_kernel<FAM, 1>), grid, dim3(kSuaveBlock), lds, s, A);
+      break;
+    case 2:
+      hipLaunchKernelGGL((suave_sample_kernel<FAM, 2>), grid, dim3(kSuaveBlock), lds, s, A);
+      break;
+    case 3:
+      hipLaunchKernelGGL((suave_sample_kernel<FAM, 3>), grid, dim3(kSuaveBlock), lds, s, A);
+      break;
+    default:
+      hipLaunchKernelGGL((suave_sample_kernel<FAM, 4>), grid, dim3(kSuaveBlock), lds, s, A);
+      break;
+  }
+}
+
+}  // namespace
+
 hipError_t launch_suave_sample(const SuaveArgs &A, int nchild, hipStream_t s) {
   const dim3 grid(A.ntiles, nchild);
   const size_t lds = suave_sample_lds(A.d, A.N);
   switch (A.family) {
     case GAUSSIAN:
-      hipLaunchKernelGGL(suave_sample_kernel<GAUSSIAN>, grid, dim3(kSuaveBlock), lds, s, A);
+      launch_sample_fam<GAUSSIAN>(A, grid, lds, s);
       break;
     case OSCILLATORY:
-      hipLaunchKernelGGL(suave_sample_kernel<OSCILLATORY>, grid, dim3(kSuaveBlock), lds, s, A);
+      launch_sample_fam<OSCILLATORY>(A, grid, lds, s);
       break;
     case PRODUCT_PEAK:
-      hipLaunchKernelGGL(suave_sample_kernel<PRODUCT_PEAK>, grid, dim3(kSuaveBlock), lds, s, A);
+      launch_sample_fam<PRODUCT_PEAK>(A, grid, lds, s);
       break;
     case CORNER_PEAK:
-      hipLaunchKernelGGL(suave_sample_kernel<CORNER_PEAK>, grid, dim3(kSuaveBlock), lds, s, A);
+      launch_sample_fam<CORNER_PEAK>(A, grid, lds, s);
       break;
     default:
-      hipLaunchKernelGGL(suave_sample_kernel<C0>, grid, dim3(kSuaveBlock), lds, s, A);
+      launch_sample_fam<C0>(A, grid, lds, s);
       break;
   }
   return hipGetLastError();

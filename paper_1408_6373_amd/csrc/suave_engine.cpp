@@ -93,6 +93,7 @@ int run_suave(ccuba_ctx *ctx, const SuaveSpec &sp, SuaveResult &res, const Suave
   A.ntiles = ntiles;
   A.nchunks = nchunks;
   A.flatness = sp.flatness;
+  A.ipow = (sp.flatness == std::floor(sp.flatness) && sp.flatness <= 4096.0) ? (int)sp.flatness : 0;
   A.p64 = B.p64.p;
   A.sel = B.sel.p;
   A.chpos = B.chpos.p;
