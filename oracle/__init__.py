@@ -46,6 +46,15 @@ class _SuaveTrace(C.Structure):
                 ("grid", C.POINTER(C.c_double)), ("cut", C.POINTER(C.c_int))]
 
 
+class _PartitionTrace(C.Structure):
+    _fields_ = [("max_regions", C.c_int), ("max_splits", C.c_int),
+                ("nregions", C.c_int), ("nsplits", C.c_int),
+                ("lo", C.POINTER(C.c_double)), ("hi", C.POINTER(C.c_double)),
+                ("xmin", C.POINTER(C.c_double)), ("xmax", C.POINTER(C.c_double)),
+                ("fmin", C.POINTER(C.c_double)), ("fmax", C.POINTER(C.c_double)),
+                ("spread", C.POINTER(C.c_double)), ("cut", C.POINTER(C.c_int))]
+
+
 class _CuhreTrace(C.Structure):
     _fields_ = [("n_batches", C.c_int)]
 
@@ -92,6 +101,10 @@ def lib():
                                    C.c_int, C.c_int, C.c_uint, C.POINTER(C.c_int),
                                    C.POINTER(C.c_longlong), C.POINTER(C.c_int), dp, dp, dp,
                                    C.POINTER(_SuaveTrace)]
+        L.oracle_divonne_partition.argtypes = [
+            C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_ulonglong, C.c_uint, C.c_int,
+            C.c_int, C.c_int, C.c_int, C.c_double, C.POINTER(C.c_int),
+            C.POINTER(C.c_longlong), C.POINTER(C.c_int), dp, C.POINTER(_PartitionTrace)]
         L.oracle_gammainc_lower.argtypes = [C.c_double, C.c_double]
         L.oracle_gammainc_lower.restype = C.c_double
         _lib = L
@@ -303,3 +316,29 @@ def suave(integrand, ndim, *, epsrel=0.0, epsabs=0.0, flags=0, seed=1, mineval=0
                 lo=lo[:R].copy(), hi=hi[:R].copy(), I=I[:R].copy(), var=var[:R].copy(),
                 inh_I=inh_I[:R].copy(), inh_var=inh_var[:R].copy(), grid=grid[:R].copy(),
                 cut=cut[:ns].copy())
+
+
+def divonne_partition(integrand, ndim, *, seed=1, stream_id=0, nsearch=256, niter=32,
+                      maxregions=64, nsplit=1, spread_tol=0.0, nvec=1000):
+    """Divonne's partitioning phase.  Returns the regions in position order with
+    their extrema and spreads, and the dimension of every split."""
+    d, m = ndim, maxregions
+    arr = dict(lo=np.zeros((m, d)), hi=np.zeros((m, d)), xmin=np.zeros((m, d)),
+               xmax=np.zeros((m, d)), fmin=np.zeros(m), fmax=np.zeros(m), spread=np.zeros(m),
+               cut=np.zeros(m, dtype=np.int32))
+    tr = _PartitionTrace(m, m, 0, 0, *[_dptr(arr[k]) for k in
+                                       ("lo", "hi", "xmin", "xmax", "fmin", "fmax", "spread")],
+                         arr["cut"].ctypes.data_as(C.POINTER(C.c_int)))
+    nreg, neval, fail, tot = C.c_int(), C.c_longlong(), C.c_int(), C.c_double()
+    rc = lib().oracle_divonne_partition(ndim, integrand.fn, integrand.userdata, nvec, seed,
+                                        stream_id, nsearch, niter, maxregions, nsplit,
+                                        spread_tol, C.byref(nreg), C.byref(neval),
+                                        C.byref(fail), C.byref(tot), C.byref(tr))
+    if rc != 0:
+        raise ValueError("oracle_divonne_partition: bad arguments")
+    R = nreg.value
+    out = dict(nregions=R, neval=neval.value, fail=fail.value, total_spread=tot.value,
+               cut=arr["cut"][:tr.nsplits].copy())
+    for k in ("lo", "hi", "xmin", "xmax", "fmin", "fmax", "spread"):
+        out[k] = arr[k][:R].copy()
+    return out

@@ -8,7 +8,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["philox.cpp", "genz.cpp", "special.cpp", "vegas.cpp", "cuhre.cpp", "suave.cpp"]
+SOURCES = ["philox.cpp", "genz.cpp", "special.cpp", "vegas.cpp", "cuhre.cpp", "suave.cpp", "divonne.cpp"]
 LIB = os.path.join(HERE, "liboracle.so")
 
 

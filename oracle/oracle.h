@@ -173,6 +173,23 @@ int oracle_suave(int ndim, int ncomp, oracle_integrand_t integrand, void *userda
                  long long *neval, int *fail, double integral[], double error[],
                  double prob[], oracle_suave_trace *trace);
 
+/* Divonne's partitioning phase (Sect. 2.2; the steps are listed in
+ * divonne.cpp).  Regions are reported in position order. */
+typedef struct {
+  int max_regions, max_splits;
+  int nregions, nsplits;        /* out */
+  double *lo, *hi;              /* out: [nregions][ndim] */
+  double *xmin, *xmax;          /* out: [nregions][ndim] the extrema's points */
+  double *fmin, *fmax, *spread; /* out: [nregions] */
+  int *cut;                     /* out: the dimension of every split */
+} oracle_partition_trace;
+
+int oracle_divonne_partition(int ndim, oracle_integrand_t integrand, void *userdata, int nvec,
+                             unsigned long long seed, unsigned int stream_id, int nsearch,
+                             int niter, int maxregions, int nsplit, double spread_tol,
+                             int *nregions, long long *neval, int *fail, double *total_spread,
+                             oracle_partition_trace *trace);
+
 double oracle_gammainc_lower(double a, double x);
 
 #ifdef __cplusplus
