@@ -296,6 +296,43 @@ int ccuba_suave(ccuba_ctx **ctx, int ndim, int ncomp, const ccuba_integrand *f, 
                 unsigned int stream_id, int *nregions, long long *neval, int *fail,
                 double integral[], double error[], double prob[], ccuba_suave_trace *trace);
 
+/* ---- Divonne's partitioning phase ------------------------------------------
+ * Sect. 2.2: the integration region is split into subregions of about equal
+ * spread, Spread(r) = 1/2 Vol(r) (sup_r f - inf_r f), with the extrema
+ * sought by numerical optimisation; the parallel version gives each worker a
+ * whole region to search and subdivide (here: one workgroup per region, all
+ * regions of a step in one launch).  Reading of the unstated steps: a
+ * region's extrema start from the largest and smallest value of nsearch
+ * Philox points in it (search serial q: counter (i, (q<<8)|b, stream_id, 0))
+ * and are refined by two compass searches of niter iterations (steps w/4,
+ * 2d clipped candidates x +- h_j e_j, the best taken if it improves, else
+ * all steps halve).  Each step bisects the K = min(nsplit, regions,
+ * maxregions - regions) regions of largest spread (ties: lower position) at
+ * the midpoint of the dimension j maximising fmax - f(xmax with x_j :=
+ * xmin_j); the j-th split searches its children with serials 2j+1 and 2j+2
+ * (the root: 0).  fail = 0 once every spread is <= spread_tol, 1 when
+ * maxregions ends the phase.  neval counts every evaluation: nsearch + 4 d
+ * niter per search and d per split.  total_spread is the sum of the spreads.
+ * Ranges: 1 <= ndim <= 16, nsearch >= 1, 0 <= niter <= 4096,
+ * 1 <= maxregions <= 2^23, 1 <= nsplit <= 1024, spread_tol >= 0.  Errors:
+ * CCUBA_EINVAL, CCUBA_EHIP, CCUBA_ENOMEM. */
+typedef struct {
+  int max_regions;           /* capacity of the per-region arrays */
+  int max_splits;            /* capacity of cut */
+  int nregions, nsplits;     /* out */
+  double *lo, *hi;           /* out: [nregions][ndim] bounds, in position order */
+  double *xmin, *xmax;       /* out: [nregions][ndim] the extrema's points */
+  double *fmin, *fmax;       /* out: [nregions] */
+  double *spread;            /* out: [nregions] */
+  int *cut;                  /* out: the dimension of every split, in order */
+} ccuba_partition_trace;
+
+int ccuba_divonne_partition(ccuba_ctx **ctx, int ndim, const ccuba_integrand *f,
+                            unsigned long long seed, unsigned int stream_id, int nsearch,
+                            int niter, int maxregions, int nsplit, double spread_tol,
+                            int *nregions, long long *neval, int *fail, double *total_spread,
+                            ccuba_partition_trace *trace);
+
 /* Cuhre (Sect. 3.2.2 prototype) with the degree-7 Genz-Malik rule and its
  * embedded degree-5 rule (Genz & Malik 1980), error |I7 - I5|, bisection of
  * each selected region along its largest fourth difference.  Each step splits

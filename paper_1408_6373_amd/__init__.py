@@ -122,6 +122,19 @@ if hasattr(_lib, "ccuba_suave"):
                                   C.c_longlong, C.c_longlong, C.c_longlong, C.c_double,
                                   C.c_int, C.c_int, C.c_uint, _ip, _llp, _ip, _dp, _dp, _dp,
                                   C.POINTER(SuaveTrace)])
+
+
+class PartitionTrace(C.Structure):
+    _fields_ = [("max_regions", C.c_int), ("max_splits", C.c_int), ("nregions", C.c_int),
+                ("nsplits", C.c_int), ("lo", _dp), ("hi", _dp), ("xmin", _dp), ("xmax", _dp),
+                ("fmin", _dp), ("fmax", _dp), ("spread", _dp), ("cut", _ip)]
+
+
+if hasattr(_lib, "ccuba_divonne_partition"):
+    _sig("ccuba_divonne_partition", C.c_int,
+         [C.POINTER(_CTXP), C.c_int, C.POINTER(Integrand), C.c_ulonglong, C.c_uint, C.c_int,
+          C.c_int, C.c_int, C.c_int, C.c_double, _ip, _llp, _ip, _dp,
+          C.POINTER(PartitionTrace)])
 if hasattr(_lib, "ccuba_submit"):
     _sig("ccuba_submit", C.c_int, [_CTXP, C.POINTER(Job), C.POINTER(C.c_ulonglong)])
     _sig("ccuba_poll", C.c_int, [_CTXP, C.c_ulonglong, C.POINTER(Result)])
@@ -132,7 +145,8 @@ SYMBOLS = ["ccuba_init", "ccuba_shutdown", "ccuba_config", "ccuba_config_get",
            "ccuba_vegas_ex", "ccuba_cuhre", "ccuba_cuhre_rule", "ccuba_vegas_batch",
            "ccuba_submit", "ccuba_poll", "ccuba_drain", "ccuba_vegas_dosample_raw",
            "ccuba_vegas_points", "ccuba_vegas_refine", "ccuba_vegas_batched",
-           "ccuba_vegas_source", "ccuba_rtc_log", "ccuba_vegas_stateful", "ccuba_suave"]
+           "ccuba_vegas_source", "ccuba_rtc_log", "ccuba_vegas_stateful", "ccuba_suave",
+           "ccuba_divonne_partition"]
 
 
 class CcubaError(RuntimeError):
@@ -506,6 +520,38 @@ def suave(family, a, u, *, ctx=None, epsrel=0.0, epsabs=0.0, flags=0, seed=1, mi
         out.update(chi2=tr.chi2, dof=tr.dof, lo=arrs["lo"][:R].copy(), hi=arrs["hi"][:R].copy(),
                    I=arrs["I"][:R].copy(), var=arrs["var"][:R].copy(),
                    grid=arrs["grid"][:R].copy(), cut=arrs["cut"][:tr.nsplits].copy())
+    return out
+
+
+def divonne_partition(family, a, u, *, ctx=None, seed=1, stream_id=0, nsearch=256, niter=32,
+                      maxregions=64, nsplit=1, spread_tol=0.0, trace=False):
+    """Divonne's partitioning phase for a Genz integrand.  With trace=True the
+    result also holds every region (bounds, extrema and their points, spread)
+    and the cut dimensions."""
+    f, keep = _integrand(family, a, u)
+    d = len(keep[0])
+    nreg, neval, fail, tot = C.c_int(), C.c_longlong(), C.c_int(), C.c_double()
+    tr = None
+    if trace:
+        m = int(maxregions)
+        arrs = dict(lo=np.zeros((m, d)), hi=np.zeros((m, d)), xmin=np.zeros((m, d)),
+                    xmax=np.zeros((m, d)), fmin=np.zeros(m), fmax=np.zeros(m),
+                    spread=np.zeros(m), cut=np.zeros(m, dtype=np.int32))
+        tr = PartitionTrace(m, m, 0, 0, *[_ptr(arrs[k]) for k in
+                                          ("lo", "hi", "xmin", "xmax", "fmin", "fmax",
+                                           "spread")], arrs["cut"].ctypes.data_as(_ip))
+    _check(_lib.ccuba_divonne_partition(_ctx_arg(ctx), d, C.byref(f), seed, stream_id, nsearch,
+                                        niter, maxregions, nsplit, spread_tol, C.byref(nreg),
+                                        C.byref(neval), C.byref(fail), C.byref(tot),
+                                        C.byref(tr) if tr is not None else None),
+           "ccuba_divonne_partition")
+    out = dict(nregions=nreg.value, neval=neval.value, fail=fail.value,
+               total_spread=tot.value)
+    if tr is not None:
+        R = tr.nregions
+        for k in ("lo", "hi", "xmin", "xmax", "fmin", "fmax", "spread"):
+            out[k] = arrs[k][:R].copy()
+        out["cut"] = arrs["cut"][:tr.nsplits].copy()
     return out
 
 

@@ -15,6 +15,7 @@
 #include "rtc.h"
 #include "vegas_state.h"
 #include "suave_engine.h"
+#include "divonne_engine.h"
 #include "vegas_batched.h"
 #include "vegas_engine.h"
 
@@ -754,6 +755,64 @@ int ccuba_suave(ccuba_ctx **ctxp, int ndim, int ncomp, const ccuba_integrand *f,
     trace->nsplits = (int)res.nsplits;
     trace->chi2 = res.chi2;
     trace->dof = res.dof;
+  }
+  return CCUBA_OK;
+}
+
+int ccuba_divonne_partition(ccuba_ctx **ctxp, int ndim, const ccuba_integrand *f,
+                            unsigned long long seed, unsigned int stream_id, int nsearch,
+                            int niter, int maxregions, int nsplit, double spread_tol,
+                            int *nregions, long long *neval, int *fail, double *total_spread,
+                            ccuba_partition_trace *trace) {
+  if (!f || !f->a || !f->u || !nregions || !neval || !fail || !total_spread || ndim < 1 ||
+      ndim > kMaxDim)
+    return CCUBA_EINVAL;
+  PartitionSpec sp;
+  sp.ndim = ndim;
+  sp.family = f->family;
+  for (int j = 0; j < ndim; ++j) {
+    sp.a[j] = f->a[j];
+    sp.u[j] = f->u[j];
+  }
+  sp.seed = seed;
+  sp.sid = stream_id;
+  sp.nsearch = nsearch;
+  sp.niter = niter;
+  sp.maxregions = maxregions;
+  sp.nsplit = nsplit;
+  sp.spread_tol = spread_tol;
+  if (validate_partition(sp)) return CCUBA_EINVAL;
+  if (trace && (trace->max_regions < 0 || trace->max_splits < 0 ||
+                (trace->max_splits > 0 && !trace->cut)))
+    return CCUBA_EINVAL;
+  CtxScope scope(ctxp);
+  if (scope.rc) return scope.rc;
+  ccuba_ctx *ctx = scope.ctx;
+  std::lock_guard<std::mutex> g(ctx->lock);
+  CCUBA_HIP(hipSetDevice(ctx->device));
+  PartitionResult res;
+  PartitionTraceOut to;
+  if (trace) {
+    to.max_regions = trace->max_regions;
+    to.max_splits = trace->max_splits;
+    to.lo = trace->lo;
+    to.hi = trace->hi;
+    to.xmin = trace->xmin;
+    to.xmax = trace->xmax;
+    to.fmin = trace->fmin;
+    to.fmax = trace->fmax;
+    to.spread = trace->spread;
+    to.cut = trace->cut;
+  }
+  int rc = run_partition(ctx, sp, res, trace ? &to : nullptr, ctx->stream);
+  if (rc) return rc;
+  *nregions = res.nregions;
+  *neval = res.neval;
+  *fail = res.fail;
+  *total_spread = res.total_spread;
+  if (trace) {
+    trace->nregions = res.nregions;
+    trace->nsplits = (int)res.nsplits;
   }
   return CCUBA_OK;
 }

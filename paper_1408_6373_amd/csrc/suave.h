@@ -63,6 +63,9 @@ hipError_t suave_set_kernel_limits();
 // the root region [0,1]^d with the uniform grid, to be sampled as child 0
 hipError_t launch_suave_root(const SuaveArgs &A, hipStream_t s);
 hipError_t launch_suave_select(const SuaveArgs &A, int R, int K, hipStream_t s);
+// sel[0..K) = positions of the K largest of key[0..R) (all >= 0), largest
+// first, ties to the lower position; 1 <= K <= min(R, kSuaveMaxSplit)
+hipError_t launch_topk(const double *key, int R, int K, int *sel, hipStream_t s);
 hipError_t launch_suave_fluct(const SuaveArgs &A, int K, hipStream_t s);
 hipError_t launch_suave_split(const SuaveArgs &A, int R, long long Q, int K, hipStream_t s);
 hipError_t launch_suave_sample(const SuaveArgs &A, int nchild, hipStream_t s);

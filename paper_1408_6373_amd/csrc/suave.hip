@@ -1,9 +1,9 @@
 // suave.hip -- Suave's steps on gfx950.
 //
 // One step of subregion-adaptive Vegas over the regions of one integral:
-//   select  the K regions of largest variance (radix select on the variance
-//           bits, then a bitonic sort of the K winners by (variance desc,
-//           position asc)); one workgroup
+//   select  the K regions of largest variance (topk: radix select on the
+//           variance bits, then a bitonic sort of the K winners by (variance
+//           desc, position asc)); one workgroup
 //   fluct   per (selected region, dimension, chunk of its stored sample): the
 //           two halves' counts, sums and extremes, then the p-th power sums of
 //           the deviations from each half's mean (p = flatness), for the L_p
@@ -86,8 +86,10 @@ __global__ void __launch_bounds__(256) suave_root_kernel(SuaveArgs A) {
   }
 }
 
-// The K regions of largest variance, ties to the lower position, in that order.
-__global__ void __launch_bounds__(1024) suave_select_kernel(SuaveArgs A, int R, int K) {
+// The K largest of R non-negative keys, ties to the lower position, in that
+// order (the regions of largest variance here, of largest spread in the
+// Divonne partition).
+__global__ void __launch_bounds__(1024) topk_kernel(const double *key, int R, int K, int *sel) {
   __shared__ unsigned hist[256];
   __shared__ int red[16];
   __shared__ unsigned long long s_prefix, s_mask;
@@ -108,7 +110,7 @@ __global__ void __launch_bounds__(1024) suave_select_kernel(SuaveArgs A, int R, 
     __syncthreads();
     const unsigned long long pre = s_prefix, mask = s_mask;
     for (int i = b0; i < b1; ++i) {
-      const unsigned long long k = var_key(A.R.var[i]);
+      const unsigned long long k = var_key(key[i]);
       if ((k & mask) == pre) atomicAdd(&hist[(k >> shift) & 255], 1u);
     }
     __syncthreads();
@@ -143,7 +145,7 @@ __global__ void __launch_bounds__(1024) suave_select_kernel(SuaveArgs A, int R, 
   const int take_eq = s_krem;  // keys equal to T taken, the lowest positions first
   int ngt = 0, neq = 0;
   for (int i = b0; i < b1; ++i) {
-    const unsigned long long k = var_key(A.R.var[i]);
+    const unsigned long long k = var_key(key[i]);
     ngt += k > T;
     neq += k == T;
   }
@@ -151,7 +153,7 @@ __global__ void __launch_bounds__(1024) suave_select_kernel(SuaveArgs A, int R, 
   int gbase = block_scan_excl(ngt, red, &tot);
   int ebase = block_scan_excl(neq, red, &tot);
   for (int i = b0; i < b1; ++i) {
-    const unsigned long long k = var_key(A.R.var[i]);
+    const unsigned long long k = var_key(key[i]);
     if (k > T) {
       skey[gbase] = k;
       spos[gbase] = i;
@@ -191,7 +193,7 @@ __global__ void __launch_bounds__(1024) suave_select_kernel(SuaveArgs A, int R, 
       }
       __syncthreads();
     }
-  for (int i = tid; i < K; i += 1024) A.sel[i] = spos[i];
+  for (int i = tid; i < K; i += 1024) sel[i] = spos[i];
 }
 
 // Split statistics in two passes over each selected region's sample, both
@@ -732,9 +734,13 @@ hipError_t launch_suave_root(const SuaveArgs &A, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_suave_select(const SuaveArgs &A, int R, int K, hipStream_t s) {
-  hipLaunchKernelGGL(suave_select_kernel, dim3(1), dim3(1024), 0, s, A, R, K);
+hipError_t launch_topk(const double *key, int R, int K, int *sel, hipStream_t s) {
+  hipLaunchKernelGGL(topk_kernel, dim3(1), dim3(1024), 0, s, key, R, K, sel);
   return hipGetLastError();
+}
+
+hipError_t launch_suave_select(const SuaveArgs &A, int R, int K, hipStream_t s) {
+  return launch_topk(A.R.var, R, K, A.sel, s);
 }
 
 hipError_t launch_suave_fluct(const SuaveArgs &A, int K, hipStream_t s) {
