@@ -57,10 +57,21 @@ __global__ void __launch_bounds__(64) div_root_kernel(DivArgs A) {
   }
 }
 
-template <int FAM>
+// a double of lane l (l wave-uniform) to every lane
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// D = 4 NB coordinates in registers (d <= D): the point and the steps of the
+// compass search live in every lane, and a move is broadcast from the
+// winning lane, so an iteration needs no LDS and no barrier.
+template <int FAM, int NB>
 __global__ void __launch_bounds__(kDivBlock) div_search_kernel(DivArgs A) {
+  constexpr int D = 4 * NB;
   __shared__ double sLo[kMaxDim], sW[kMaxDim], sP0[kMaxDim], sP1[kMaxDim];
-  __shared__ double sX[2][kMaxDim], sH[2][kMaxDim];
   __shared__ double sv[2][2], sF[2];
   __shared__ int si[2][2];
   const int c = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -73,29 +84,40 @@ __global__ void __launch_bounds__(kDivBlock) div_search_kernel(DivArgs A) {
     sP1[tid] = A.p64[kParamRow + tid];
   }
   __syncthreads();
+  double p0[D], p1[D], lo[D], wd[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    p0[j] = j < d ? sP0[j] : 0.0;
+    p1[j] = j < d ? sP1[j] : 0.0;
+    lo[j] = j < d ? sLo[j] : 0.0;
+    wd[j] = j < d ? sW[j] : 0.0;
+  }
+  // the point of search-sample index i
+  auto point = [&](int i, double (&x)[D]) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const U4 W = philox4x32_10(U4{(uint32_t)i, ((uint32_t)q << 8) | (uint32_t)b, A.sid, 0u},
+                                 A.key0, A.key1);
+      const uint32_t r[4] = {W.x, W.y, W.z, W.w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) x[4 * b + k] = fma((double)r[k] * 0x1p-32 + 0x1p-33,
+                                                      wd[4 * b + k], lo[4 * b + k]);
+    }
+  };
+  auto value = [&](const double (&x)[D]) {
+    double acc = Genz<double, FAM>::init(p1[0]);
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+      if (j < d) acc = Genz<double, FAM>::step(acc, x[j], p0[j], p1[j]);
+    return Genz<double, FAM>::finish(acc, d);
+  };
   // the search sample
   double bmax = -INFINITY, bmin = INFINITY;
   int imax = 0x7fffffff, imin = 0x7fffffff;
   for (int i = tid; i < A.nsearch; i += kDivBlock) {
-    double x[kMaxDim];
-#pragma unroll
-    for (int b = 0; b < kMaxDim / 4; ++b) {
-      if (4 * b < d) {
-        const U4 W = philox4x32_10(U4{(uint32_t)i, ((uint32_t)q << 8) | (uint32_t)b, A.sid, 0u},
-                                   A.key0, A.key1);
-        const uint32_t wd[4] = {W.x, W.y, W.z, W.w};
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int j = 4 * b + k;
-          if (j < d) x[j] = fma((double)wd[k] * 0x1p-32 + 0x1p-33, sW[j], sLo[j]);
-        }
-      }
-    }
-    double acc = Genz<double, FAM>::init(sP1[0]);
-#pragma unroll
-    for (int j = 0; j < kMaxDim; ++j)
-      if (j < d) acc = Genz<double, FAM>::step(acc, x[j], sP0[j], sP1[j]);
-    const double f = Genz<double, FAM>::finish(acc, d);
+    double x[D];
+    point(i, x);
+    const double f = value(x);
     if (f > bmax) {  // i grows, so a tie keeps the lower index
       bmax = f;
       imax = i;
@@ -124,50 +146,54 @@ __global__ void __launch_bounds__(kDivBlock) div_search_kernel(DivArgs A) {
     const int j0 = si[0][k], j1 = si[1][k];
     const bool second = sign * v1 > sign * v0 || (v1 == v0 && j1 < j0);
     fx = second ? v1 : v0;
-    i0 = second ? j1 : j0;
+    i0 = __builtin_amdgcn_readfirstlane(second ? j1 : j0);
   }
-  if (lane < d) {  // regenerate the winning point's coordinate lane
-    const int b = lane >> 2;
-    const U4 W = philox4x32_10(U4{(uint32_t)i0, ((uint32_t)q << 8) | (uint32_t)b, A.sid, 0u},
-                               A.key0, A.key1);
-    const uint32_t wd[4] = {W.x, W.y, W.z, W.w};
-    sX[k][lane] = fma((double)wd[lane & 3] * 0x1p-32 + 0x1p-33, sW[lane], sLo[lane]);
-    sH[k][lane] = sW[lane] / 4.0;
-  }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  double x[D], h[D];
+  point(i0, x);
+#pragma unroll
+  for (int j = 0; j < D; ++j) h[j] = wd[j] / 4.0;
+  // lane c < 2d owns candidate c: coordinate jc = c/2, + for even c
   const int jc = lane >> 1;
-  const bool plus = (lane & 1) == 0;
+  const bool plus = (lane & 1) == 0, live = lane < 2 * d;
+  double loj = 0.0, hij = 0.0;
+#pragma unroll
+  for (int j = 0; j < D; ++j)
+    if (j == jc) {
+      loj = lo[j];
+      hij = lo[j] + wd[j];
+    }
   for (int t = 0; t < A.niter; ++t) {
-    double fc = sign * -INFINITY;
-    double zc = 0.0;
-    if (lane < 2 * d) {
-      const double xj = sX[k][jc], hj = sH[k][jc];
-      zc = fmin(fmax(plus ? xj + hj : xj - hj, sLo[jc]), sLo[jc] + sW[jc]);
-      double acc = Genz<double, FAM>::init(sP1[0]);
-      for (int j = 0; j < d; ++j)
-        acc = Genz<double, FAM>::step(acc, j == jc ? zc : sX[k][j], sP0[j], sP1[j]);
-      fc = Genz<double, FAM>::finish(acc, d);
-    }
-    int bi = lane < 2 * d ? lane : 0x7fffffff;
-    double bv = fc;
+    double xj = 0.0, hj = 0.0;
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+      if (j == jc) {
+        xj = x[j];
+        hj = h[j];
+      }
+    const double zc = fmin(fmax(plus ? xj + hj : xj - hj, loj), hij);
+    double acc = Genz<double, FAM>::init(p1[0]);
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+      if (j < d) acc = Genz<double, FAM>::step(acc, j == jc ? zc : x[j], p0[j], p1[j]);
+    double bv = live ? Genz<double, FAM>::finish(acc, d) : sign * -INFINITY;
+    int bi = live ? lane : 0x7fffffff;
     wave_best(bv, bi, sign);
-    const bool better = sign * bv > sign * fx;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if (better) {
+    if (sign * bv > sign * fx) {
+      const int win = __builtin_amdgcn_readfirstlane(bi);
+      const double znew = readlane_d(zc, win);
+      const int jw = win >> 1;
       fx = bv;
-      if (lane == bi) sX[k][jc] = zc;
-    } else if (lane < d) {
-      sH[k][lane] *= 0.5;
+#pragma unroll
+      for (int j = 0; j < D; ++j) x[j] = j == jw ? znew : x[j];
+    } else {
+#pragma unroll
+      for (int j = 0; j < D; ++j) h[j] *= 0.5;
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
-  if (lane < d) (k == 0 ? A.R.xmax : A.R.xmin)[(size_t)pos * d + lane] = sX[k][lane];
+  double* xo = (k == 0 ? A.R.xmax : A.R.xmin) + (size_t)pos * d;
+#pragma unroll
+  for (int j = 0; j < D; ++j)
+    if (j < d && lane == j) xo[j] = x[j];
   if (lane == 0) {
     (k == 0 ? A.R.fmax : A.R.fmin)[pos] = fx;
     sF[k] = fx;
@@ -282,8 +308,45 @@ hipError_t launch_div_root(const DivArgs &A, hipStream_t s) {
       break;                                                                            \
   }
 
+template <int NB>
+static void launch_search_nb(const DivArgs &A, int nchild, hipStream_t s) {
+  switch (A.family) {
+    case GAUSSIAN:
+      hipLaunchKernelGGL((div_search_kernel<GAUSSIAN, NB>), dim3(nchild), dim3(kDivBlock), 0, s, A);
+      break;
+    case OSCILLATORY:
+      hipLaunchKernelGGL((div_search_kernel<OSCILLATORY, NB>), dim3(nchild), dim3(kDivBlock), 0, s,
+                         A);
+      break;
+    case PRODUCT_PEAK:
+      hipLaunchKernelGGL((div_search_kernel<PRODUCT_PEAK, NB>), dim3(nchild), dim3(kDivBlock), 0, s,
+                         A);
+      break;
+    case CORNER_PEAK:
+      hipLaunchKernelGGL((div_search_kernel<CORNER_PEAK, NB>), dim3(nchild), dim3(kDivBlock), 0, s,
+                         A);
+      break;
+    default:
+      hipLaunchKernelGGL((div_search_kernel<C0, NB>), dim3(nchild), dim3(kDivBlock), 0, s, A);
+      break;
+  }
+}
+
 hipError_t launch_div_search(const DivArgs &A, int nchild, hipStream_t s) {
-  CCUBA_DIV_FAMILY_SWITCH(div_search_kernel, dim3(nchild), dim3(kDivBlock), A)
+  switch ((A.d + 3) / 4) {
+    case 1:
+      launch_search_nb<1>(A, nchild, s);
+      break;
+    case 2:
+      launch_search_nb<2>(A, nchild, s);
+      break;
+    case 3:
+      launch_search_nb<3>(A, nchild, s);
+      break;
+    default:
+      launch_search_nb<4>(A, nchild, s);
+      break;
+  }
   return hipGetLastError();
 }
 
