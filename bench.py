@@ -374,6 +374,38 @@ def _suave_leg(cc, ctx, cpu=True):
     return out
 
 
+DIV_NSEARCH, DIV_NITER, DIV_REGIONS, DIV_SPLIT = 1024, 64, 16384, 1024
+
+
+def _divonne_leg(cc, ctx, cpu=True):
+    import workloads as W
+    a, u = W.genz_params(W.GAUSSIAN, 8, 1)
+    kw = dict(nsearch=DIV_NSEARCH, niter=DIV_NITER, maxregions=DIV_REGIONS, nsplit=DIV_SPLIT)
+    cc.divonne_partition(W.GAUSSIAN, a, u, ctx=ctx, **kw)  # warm-up
+    best = None
+    for _ in range(3):  # the call returns once its results are on the host
+        t0 = time.perf_counter()
+        r = cc.divonne_partition(W.GAUSSIAN, a, u, ctx=ctx, **kw)
+        dt = time.perf_counter() - t0
+        best = dt if best is None else min(best, dt)
+    searches = 2 * r["nregions"] - 1
+    out = {"workload": "Divonne partitioning phase, Gaussian d=8, 1024 search points and 64 "
+                       "compass iterations per extremum, 1024 splits per step, to 16384 regions",
+           "value": r["neval"] / best, "unit": "evals/s", "seconds": best,
+           "region_searches_per_s": searches / best, "neval": r["neval"],
+           "nregions": r["nregions"], "total_spread": r["total_spread"]}
+    if cpu:  # the oracle on the same workload up to 4096 regions
+        import oracle as O
+        t0 = time.perf_counter()
+        o = O.divonne_partition(O.genz(W.GAUSSIAN, a, u), 8, **dict(kw, maxregions=4096))
+        odt = time.perf_counter() - t0
+        out["cpu_oracle"] = {"value": o["neval"] / odt, "unit": "evals/s", "cores": 1,
+                             "kind": "oracle",
+                             "sample": "the same partition to 4096 regions (%d evaluations)"
+                                       % o["neval"]}
+    return out
+
+
 def _serving_specs(cc, reqs):
     specs = []
     for r in reqs:
@@ -454,6 +486,8 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=300)
     ap.add_argument("--suave-only", action="store_true",
                     help="run only the Suave leg and print its JSON line (for profiling)")
+    ap.add_argument("--divonne-only", action="store_true",
+                    help="run only the Divonne-partition leg and print its JSON line")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="for PMC runs: one 1 GiB device copy (calibration), then one FP32 "
                          "integral of the headline workload; prints a JSON line")
@@ -495,8 +529,10 @@ def main():
         print(json.dumps({"traffic_probe": True, "copy_bytes": 1 << 30, "neval": r["neval"]}))
         return
     ctx = cc.Context(device=0)
-    if args.suave_only:
-        print(json.dumps({"suave": _suave_leg(cc, ctx, cpu=False)}))
+    if args.suave_only or args.divonne_only:
+        leg = ({"suave": _suave_leg(cc, ctx, cpu=False)} if args.suave_only else
+               {"divonne_partition": _divonne_leg(cc, ctx, cpu=False)})
+        print(json.dumps(leg))
         ctx.close()
         return
 
@@ -523,6 +559,7 @@ def main():
         out["caller_integrand"] = _caller_integrand_leg(cc)
         out["cuhre"] = _cuhre_leg(cc, ctx)
         out["suave"] = _suave_leg(cc, ctx, cpu=not args.no_cpu_baseline)
+        out["divonne_partition"] = _divonne_leg(cc, ctx, cpu=not args.no_cpu_baseline)
     ctx.close()
     if not args.no_extra:
         out["serving"] = _serving_leg(cc, args.serving_requests)
