@@ -111,3 +111,31 @@ def test_bad_arguments(cc, ctx):
         with pytest.raises(cc.CcubaError) as e:
             cc.divonne_partition(W.GAUSSIAN, a, u, ctx=ctx, **kw)
         assert e.value.rc == cc.EINVAL
+
+
+def test_full_bench_shape_properties(cc, ctx):
+    # the benchmark's partition (d = 8 Gaussian to 16384 regions), checked
+    # through what holds at any size; every extremum is recomputed from its
+    # point by the oracle's integrand
+    d = 8
+    a, u = W.genz_params(W.GAUSSIAN, d, 1)
+    kw = dict(nsearch=1024, niter=64, maxregions=16384, nsplit=1024)
+    r = cc.divonne_partition(W.GAUSSIAN, a, u, ctx=ctx, trace=True, **kw)
+    R = r["nregions"]
+    assert R == 16384 and r["fail"] == 1 and len(r["cut"]) == R - 1
+    assert r["neval"] == (2 * R - 1) * (1024 + 4 * d * 64) + d * (R - 1)
+    lo, hi = r["lo"], r["hi"]
+    vol = np.prod(hi - lo, axis=1)
+    assert vol.sum() == 1.0 and np.all(vol > 0)
+    x = np.random.default_rng(2).random((4000, d))
+    inside = ((x[:, None, :] >= lo[None]) & (x[:, None, :] < hi[None])).all(axis=2)
+    assert np.all(inside.sum(axis=1) == 1)
+    for k in ("xmin", "xmax"):
+        assert np.all(r[k] >= lo) and np.all(r[k] <= hi)
+    assert np.array_equal(r["spread"], 0.5 * vol * (r["fmax"] - r["fmin"]))
+    pick = np.random.default_rng(3).choice(R, 256, replace=False)
+    assert np.allclose(O.genz_eval(W.GAUSSIAN, a, u, r["xmax"][pick]), r["fmax"][pick],
+                       rtol=1e-14, atol=0)
+    assert np.allclose(O.genz_eval(W.GAUSSIAN, a, u, r["xmin"][pick]), r["fmin"][pick],
+                       rtol=1e-14, atol=0)
+    assert abs(r["total_spread"] - r["spread"].sum()) <= 1e-12 * r["total_spread"]

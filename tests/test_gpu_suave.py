@@ -136,3 +136,33 @@ def test_bad_arguments(cc, ctx):
         with pytest.raises(cc.CcubaError) as e:
             cc.suave(W.GAUSSIAN, a, u, ctx=ctx, **kw)
         assert e.value.rc == cc.EINVAL
+
+
+def test_full_bench_shape_properties(cc, ctx):
+    # the benchmark's Suave run (d = 8 Gaussian, 2^17 points per region, 64
+    # splits per step, 30 steps): partition invariants, the budget
+    # accounting, the totals as sums of the regions, and the closed form
+    d, n, K = 8, 1 << 17, 64
+    a, u = W.genz_params(W.GAUSSIAN, d, 1)
+    maxeval, R = n, 1
+    for _ in range(30):
+        k = min(K, R)
+        maxeval += 2 * k * n
+        R += k
+    r = cc.suave(W.GAUSSIAN, a, u, ctx=ctx, nnew=n, nsplit=K, nbins=128, flatness=25.0,
+                 maxeval=maxeval, trace=True)
+    assert r["nregions"] == R == 1600 and r["neval"] == maxeval and r["fail"] == 1
+    assert len(r["cut"]) == R - 1
+    lo, hi = r["lo"], r["hi"]
+    assert np.prod(hi - lo, axis=1).sum() == 1.0
+    x = np.random.default_rng(4).random((4000, d))
+    inside = ((x[:, None, :] >= lo[None]) & (x[:, None, :] < hi[None])).all(axis=2)
+    assert np.all(inside.sum(axis=1) == 1)
+    assert abs(r["integral"] - r["I"].sum()) <= 1e-13 * abs(r["integral"])
+    assert abs(r["error"] ** 2 - r["var"].sum()) <= 1e-12 * r["error"] ** 2
+    assert 0 < r["dof"] <= R  # one per region that holds an inherited estimate
+    g = r["grid"]
+    assert np.all(g[:, :, 0] == 0.0) and np.all(g[:, :, -1] == 1.0)
+    assert np.all(np.diff(g, axis=2) >= 0.0)
+    ex = exact(W.GAUSSIAN, a, u)
+    assert abs(r["integral"] - ex) <= 5 * r["error"]
