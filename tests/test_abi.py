@@ -94,6 +94,25 @@ def test_bad_arguments_are_rejected_on_the_host(cc):
     rc = L.ccuba_vegas_stateful(None, 3, 1, C.byref(f), 0.0, 0.0, 0, 1, 0, 1000, 100, 0, 1, 0,
                                 None, 64, 0, None, C.byref(fl), *ptrs, None)
     assert rc == cc.EINVAL
+    # Suave: ndim, ncomp, nnew, flatness, nsplit, nbins, precision
+    nr = C.c_int()
+    for nd, nc, nn, fl_, ns, nb, flg in ((0, 1, 100, 25.0, 1, 64, 0), (17, 1, 100, 25.0, 1, 64, 0),
+                                          (3, 2, 100, 25.0, 1, 64, 0), (3, 1, 1, 25.0, 1, 64, 0),
+                                          (3, 1, 100, 0.0, 1, 64, 0), (3, 1, 100, 25.0, 0, 64, 0),
+                                          (3, 1, 100, 25.0, 1025, 64, 0),
+                                          (3, 1, 100, 25.0, 1, 1, 0), (3, 1, 100, 25.0, 1, 64, 1)):
+        rc = L.ccuba_suave(None, nd, nc, C.byref(f), 0.0, 0.0, flg, 1, 0, 1000, nn, fl_, nb, ns, 0,
+                           C.byref(nr), C.byref(n), C.byref(fl), *ptrs, None)
+        assert rc == cc.EINVAL
+    # Divonne partition: ndim, nsearch, niter, maxregions, nsplit, spread_tol
+    tot = C.c_double()
+    for nd, nse, nit, mr, ns, tol in ((0, 10, 1, 4, 1, 0.0), (17, 10, 1, 4, 1, 0.0),
+                                      (3, 0, 1, 4, 1, 0.0), (3, 10, -1, 4, 1, 0.0),
+                                      (3, 10, 1, 0, 1, 0.0), (3, 10, 1, 4, 0, 0.0),
+                                      (3, 10, 1, 4, 1, -1.0)):
+        rc = L.ccuba_divonne_partition(None, nd, C.byref(f), 1, 0, nse, nit, mr, ns, tol,
+                                       C.byref(nr), C.byref(n), C.byref(fl), C.byref(tot), None)
+        assert rc == cc.EINVAL
     assert L.ccuba_rtc_log(None, C.create_string_buffer(8), 8) == cc.EINVAL
     assert L.ccuba_init(None, 0, 0) == cc.EINVAL
     assert L.ccuba_config(None, b"block", 256) == cc.EINVAL
