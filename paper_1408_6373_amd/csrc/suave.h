@@ -51,6 +51,7 @@ struct SuaveArgs {
   int *chpos, *chser;     // [2K] children's positions and sampling serials
   double *fl1;            // [K][nchunks][d][9] pass-1 split statistics
   double *fl2;            // [K][nchunks][d][2] pass-2 power sums
+  double *hs;             // [K][d][10] pass 1 over all chunks: cnt, S1, S2, m, M per half
   double *tsum;           // [2K][ntiles][2] tile sums
   double *thist;          // [2K][ntiles][d N] tile histograms
   int *cut;               // [splits] dimension of every split, in order

@@ -86,6 +86,8 @@ __global__ void __launch_bounds__(256) suave_root_kernel(SuaveArgs A) {
   }
 }
 
+constexpr int kKeyBatch = 8;  // key loads issued together by the selection
+
 // The K largest of R non-negative keys, ties to the lower position, in that
 // order (the regions of largest variance here, of largest spread in the
 // Divonne partition).
@@ -109,9 +111,13 @@ __global__ void __launch_bounds__(1024) topk_kernel(const double *key, int R, in
     if (tid < 256) hist[tid] = 0;
     __syncthreads();
     const unsigned long long pre = s_prefix, mask = s_mask;
-    for (int i = b0; i < b1; ++i) {
-      const unsigned long long k = var_key(key[i]);
-      if ((k & mask) == pre) atomicAdd(&hist[(k >> shift) & 255], 1u);
+    for (int i0 = b0; i0 < b1; i0 += kKeyBatch) {  // a batch of loads in flight
+      unsigned long long kk[kKeyBatch];
+#pragma unroll
+      for (int q = 0; q < kKeyBatch; ++q) kk[q] = i0 + q < b1 ? var_key(key[i0 + q]) : 0;
+#pragma unroll
+      for (int q = 0; q < kKeyBatch; ++q)
+        if (i0 + q < b1 && (kk[q] & mask) == pre) atomicAdd(&hist[(kk[q] >> shift) & 255], 1u);
     }
     __syncthreads();
     if (tid < 64) {  // one wavefront: lane l owns digits 4l .. 4l+3
@@ -144,26 +150,38 @@ __global__ void __launch_bounds__(1024) topk_kernel(const double *key, int R, in
   const unsigned long long T = s_prefix;
   const int take_eq = s_krem;  // keys equal to T taken, the lowest positions first
   int ngt = 0, neq = 0;
-  for (int i = b0; i < b1; ++i) {
-    const unsigned long long k = var_key(key[i]);
-    ngt += k > T;
-    neq += k == T;
+  for (int i0 = b0; i0 < b1; i0 += kKeyBatch) {
+    unsigned long long kk[kKeyBatch];
+#pragma unroll
+    for (int q = 0; q < kKeyBatch; ++q) kk[q] = i0 + q < b1 ? var_key(key[i0 + q]) : 0;
+#pragma unroll
+    for (int q = 0; q < kKeyBatch; ++q)
+      if (i0 + q < b1) {
+        ngt += kk[q] > T;
+        neq += kk[q] == T;
+      }
   }
   int tot;
   int gbase = block_scan_excl(ngt, red, &tot);
   int ebase = block_scan_excl(neq, red, &tot);
-  for (int i = b0; i < b1; ++i) {
-    const unsigned long long k = var_key(key[i]);
-    if (k > T) {
-      skey[gbase] = k;
-      spos[gbase] = i;
-      ++gbase;
-    } else if (k == T) {
-      if (ebase < take_eq) {
-        skey[K - take_eq + ebase] = k;
-        spos[K - take_eq + ebase] = i;
+  for (int i0 = b0; i0 < b1; i0 += kKeyBatch) {
+    unsigned long long kk[kKeyBatch];
+#pragma unroll
+    for (int q = 0; q < kKeyBatch; ++q) kk[q] = i0 + q < b1 ? var_key(key[i0 + q]) : 0;
+    for (int q = 0; q < kKeyBatch && i0 + q < b1; ++q) {
+      const unsigned long long k = kk[q];
+      const int i = i0 + q;
+      if (k > T) {
+        skey[gbase] = k;
+        spos[gbase] = i;
+        ++gbase;
+      } else if (k == T) {
+        if (ebase < take_eq) {
+          skey[K - take_eq + ebase] = k;
+          spos[K - take_eq + ebase] = i;
+        }
+        ++ebase;
       }
-      ++ebase;
     }
   }
   int P = 1;
@@ -207,13 +225,16 @@ __global__ void __launch_bounds__(1024) topk_kernel(const double *key, int R, in
 constexpr int kP1 = 9;       // per (chunk, dimension): cnt1, S1_0, S2_0, S1_1, S2_1, min0, max0, min1, max1
 
 // Both passes stage their chunk in LDS once; then G threads per dimension
-// (G = 256 over d rounded up to a power of two, at most 64) accumulate over
+// (G = kFlBlock over d rounded up to a power of two, at most 64) accumulate over
 // it, two points at a time into independent partial sums, and reduce with
 // shuffles within their G-lane group.
+constexpr int kFlBlock = 512;  // threads of the split-statistics workgroups
+static_assert(kSuaveChunk % kFlBlock == 0, "a chunk stages evenly over the workgroup");
+
 __device__ __forceinline__ int lanes_per_dim(int d) {
   int dp = 1;
   while (dp < d) dp <<= 1;
-  return min(64, 256 / dp);
+  return min(64, kFlBlock / dp);
 }
 
 __device__ __forceinline__ int stage_chunk(const double *vall, const uint16_t *sall, int pos,
@@ -222,20 +243,20 @@ __device__ __forceinline__ int stage_chunk(const double *vall, const uint16_t *s
   const int cnt = (int)min((long long)kSuaveChunk, n - i0);
   const double *v = vall + (size_t)pos * n + i0;
   const uint16_t *sd = sall + (size_t)pos * n + i0;
-  // all of a thread's loads in flight at once (kSuaveChunk / 256 each)
-  constexpr int kPer = kSuaveChunk / 256;
+  // all of a thread's loads in flight at once (kSuaveChunk / kFlBlock each)
+  constexpr int kPer = kSuaveChunk / kFlBlock;
   double tv[kPer];
   uint16_t tb[kPer];
 #pragma unroll
   for (int k = 0; k < kPer; ++k) {
-    const int i = threadIdx.x + 256 * k;
+    const int i = threadIdx.x + kFlBlock * k;
     tv[k] = i < cnt ? v[i] : 0.0;
     tb[k] = i < cnt ? sd[i] : (uint16_t)0;
   }
 #pragma unroll
   for (int k = 0; k < kPer; ++k) {
-    sv[threadIdx.x + 256 * k] = tv[k];
-    sb[threadIdx.x + 256 * k] = tb[k];
+    sv[threadIdx.x + kFlBlock * k] = tv[k];
+    sb[threadIdx.x + kFlBlock * k] = tb[k];
   }
   __syncthreads();
   return cnt;
@@ -267,7 +288,7 @@ __device__ __forceinline__ double p1_merge(int q, double x, double y) {
 }
 
 // Pass 1 over one chunk: grid (chunk, selected region).
-__global__ void __launch_bounds__(256) suave_fluct1_kernel(SuaveArgs A) {
+__global__ void __launch_bounds__(kFlBlock) suave_fluct1_kernel(SuaveArgs A) {
   __shared__ double sv[kSuaveChunk];
   __shared__ uint16_t sb[kSuaveChunk];
   const int ch = blockIdx.x, s = blockIdx.y, tid = threadIdx.x, d = A.d;
@@ -352,17 +373,34 @@ __device__ __forceinline__ double pow01(double r, double p, int ip) {
 
 }  // namespace
 
+// Pass 1 reduced over the chunks, once per (selected region, dimension):
+// grid (selected region), lane j < d.
+constexpr int kHs = 10;  // per (region, dimension): cnt, S1, S2, m, M of each half
+__global__ void __launch_bounds__(64) suave_fluct_reduce_kernel(SuaveArgs A) {
+  const int s = blockIdx.x, j = threadIdx.x;
+  if (j >= A.d) return;
+  const HalfStats h = half_stats(A, s, j);
+  double *o = A.hs + ((size_t)s * A.d + j) * kHs;
+  for (int k = 0; k < 2; ++k) {
+    o[5 * k + 0] = h.cnt[k];
+    o[5 * k + 1] = h.S1[k];
+    o[5 * k + 2] = h.S2[k];
+    o[5 * k + 3] = h.m[k];
+    o[5 * k + 4] = h.M[k];
+  }
+}
+
 // Pass 2 over one chunk: grid (chunk, selected region).
-__global__ void __launch_bounds__(256) suave_fluct2_kernel(SuaveArgs A) {
+__global__ void __launch_bounds__(kFlBlock) suave_fluct2_kernel(SuaveArgs A) {
   __shared__ double sv[kSuaveChunk];
   __shared__ uint16_t sb[kSuaveChunk];
   __shared__ double sm[kMaxDim][2], sinv[kMaxDim][2];
   const int ch = blockIdx.x, s = blockIdx.y, tid = threadIdx.x, d = A.d;
   if (tid < d) {
-    const HalfStats h = half_stats(A, s, tid);
+    const double *h = A.hs + ((size_t)s * d + tid) * kHs;
     for (int k = 0; k < 2; ++k) {
-      sm[tid][k] = h.m[k];
-      sinv[tid][k] = h.M[k] > 0.0 ? 1.0 / h.M[k] : 0.0;
+      sm[tid][k] = h[5 * k + 3];
+      sinv[tid][k] = h[5 * k + 4] > 0.0 ? 1.0 / h[5 * k + 4] : 0.0;
     }
   }
   const int cnt = stage_chunk(A.R.v, A.R.side, A.sel[s], A.nnew, ch, sv, sb);
@@ -440,7 +478,7 @@ __global__ void __launch_bounds__(256) suave_split_kernel(SuaveArgs A, int R, lo
   const int pos = A.sel[s], up = R + s;
   __shared__ double s_score[kMaxDim], s_S[kMaxDim][4];
   if (tid < d) {  // F_0 + F_1 of a cut along dimension tid
-    const HalfStats h = half_stats(A, s, tid);
+    const double *h = A.hs + ((size_t)s * d + tid) * kHs;
     const double nd = (double)A.nnew, p = A.flatness;
     double score = 0.0;
     for (int k = 0; k < 2; ++k) {
@@ -448,14 +486,14 @@ __global__ void __launch_bounds__(256) suave_split_kernel(SuaveArgs A, int R, lo
 #pragma unroll 8
       for (int ch = 0; ch < A.nchunks; ++ch)
         q += A.fl2[(((size_t)s * A.nchunks + ch) * d + tid) * 2 + k];
-      if (h.cnt[k] > 0.0 && h.M[k] > 0.0)
-        score += (h.cnt[k] / nd) * h.M[k] * pow(q / h.cnt[k], 1.0 / p);
+      const double cnt = h[5 * k], M = h[5 * k + 4];
+      if (cnt > 0.0 && M > 0.0) score += (cnt / nd) * M * pow(q / cnt, 1.0 / p);
     }
     s_score[tid] = score;
-    s_S[tid][0] = h.S1[0];
-    s_S[tid][1] = h.S2[0];
-    s_S[tid][2] = h.S1[1];
-    s_S[tid][3] = h.S2[1];
+    s_S[tid][0] = h[1];
+    s_S[tid][1] = h[2];
+    s_S[tid][2] = h[6];
+    s_S[tid][3] = h[7];
   }
   __syncthreads();
   if (tid == 0) {
@@ -744,8 +782,9 @@ hipError_t launch_suave_select(const SuaveArgs &A, int R, int K, hipStream_t s) 
 }
 
 hipError_t launch_suave_fluct(const SuaveArgs &A, int K, hipStream_t s) {
-  hipLaunchKernelGGL(suave_fluct1_kernel, dim3(A.nchunks, K), dim3(256), 0, s, A);
-  hipLaunchKernelGGL(suave_fluct2_kernel, dim3(A.nchunks, K), dim3(256), 0, s, A);
+  hipLaunchKernelGGL(suave_fluct1_kernel, dim3(A.nchunks, K), dim3(kFlBlock), 0, s, A);
+  hipLaunchKernelGGL(suave_fluct_reduce_kernel, dim3(K), dim3(64), 0, s, A);
+  hipLaunchKernelGGL(suave_fluct2_kernel, dim3(A.nchunks, K), dim3(kFlBlock), 0, s, A);
   return hipGetLastError();
 }
 

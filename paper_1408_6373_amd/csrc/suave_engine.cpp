@@ -30,7 +30,7 @@ int validate_suave(const SuaveSpec &s) {
 namespace {
 
 struct Buffers {
-  DevBuf<double> lo, hi, grid, I, var, chi2, inh_I, inh_var, v, fl1, fl2, tsum, thist, p64;
+  DevBuf<double> lo, hi, grid, I, var, chi2, inh_I, inh_var, v, fl1, fl2, hs, tsum, thist, p64;
   DevBuf<int> dof, sel, chpos, chser, cut;
   DevBuf<uint16_t> side;
   DevBuf<SState> state;
@@ -60,6 +60,7 @@ int run_suave(ccuba_ctx *ctx, const SuaveSpec &sp, SuaveResult &res, const Suave
       (rc = B.dof.alloc(ctx, Rmax)) || (rc = B.v.alloc(ctx, Rmax * n)) ||
       (rc = B.side.alloc(ctx, Rmax * n)) || (rc = B.fl1.alloc(ctx, (size_t)Kmax * nchunks * d * 9)) ||
       (rc = B.fl2.alloc(ctx, (size_t)Kmax * nchunks * d * 2)) ||
+      (rc = B.hs.alloc(ctx, (size_t)Kmax * d * 10)) ||
       (rc = B.tsum.alloc(ctx, (size_t)2 * Kmax * ntiles * 2)) ||
       (rc = B.thist.alloc(ctx, (size_t)2 * Kmax * ntiles * dN)) ||
       (rc = B.p64.alloc(ctx, 2 * kParamRow)) || (rc = B.sel.alloc(ctx, Kmax)) ||
@@ -100,6 +101,7 @@ int run_suave(ccuba_ctx *ctx, const SuaveSpec &sp, SuaveResult &res, const Suave
   A.chser = B.chser.p;
   A.fl1 = B.fl1.p;
   A.fl2 = B.fl2.p;
+  A.hs = B.hs.p;
   A.tsum = B.tsum.p;
   A.thist = B.thist.p;
   A.cut = B.cut.p;
