@@ -30,18 +30,39 @@ __device__ __forceinline__ double eval_at(const double *x, int d, const double *
   return Genz<double, FAM>::finish(acc, d);
 }
 
-// (value, index) reduction over a wavefront: the larger sign*value, ties to
-// the lower index; every lane gets the winner
-__device__ __forceinline__ void wave_best(double &v, int &idx, double sign) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const double ov = __shfl_xor(v, o, 64);
-    const int oi = __shfl_xor(idx, o, 64);
-    if (sign * ov > sign * v || (ov == v && oi < idx)) {
-      v = ov;
-      idx = oi;
-    }
+// one DPP step of the reduction below: each lane compares itself with the
+// lane the control selects (lanes without a source compare with themselves)
+template <int CTRL, int ROWS, int BANKS>
+__device__ __forceinline__ void best_step(double &v, int &idx, double sign) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp((int)b, (int)b, CTRL, ROWS, BANKS, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(b >> 32), (int)(b >> 32), CTRL, ROWS, BANKS,
+                                             false);
+  const int oi = __builtin_amdgcn_update_dpp(idx, idx, CTRL, ROWS, BANKS, false);
+  const double ov = __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+  if (sign * ov > sign * v || (ov == v && oi < idx)) {
+    v = ov;
+    idx = oi;
   }
+}
+
+// (value, index) reduction over a wavefront: the larger sign*value, ties to
+// the lower index; every lane gets the winner.  "Best of" is idempotent, so
+// the DPP pattern may count a lane twice: row shifts by 1, 2, 4 and 8 leave
+// each row's best in its lane 15, the row broadcasts carry it to lane 63,
+// whose result readlane hands to every lane.
+__device__ __forceinline__ void wave_best(double &v, int &idx, double sign) {
+  best_step<0x111, 0xf, 0xf>(v, idx, sign);  // row_shr:1
+  best_step<0x112, 0xf, 0xf>(v, idx, sign);  // row_shr:2
+  best_step<0x114, 0xf, 0xf>(v, idx, sign);  // row_shr:4
+  best_step<0x118, 0xf, 0xf>(v, idx, sign);  // row_shr:8
+  best_step<0x142, 0xa, 0xf>(v, idx, sign);  // row_bcast:15 into rows 1 and 3
+  best_step<0x143, 0xc, 0xf>(v, idx, sign);  // row_bcast:31 into rows 2 and 3
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  v = __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+  idx = __builtin_amdgcn_readlane(idx, 63);
 }
 
 }  // namespace
