@@ -313,7 +313,7 @@ int ccuba_suave(ccuba_ctx **ctx, int ndim, int ncomp, const ccuba_integrand *f, 
  * (the root: 0).  fail = 0 once every spread is <= spread_tol, 1 when
  * maxregions ends the phase.  neval counts every evaluation: nsearch + 4 d
  * niter per search and d per split.  total_spread is the sum of the spreads.
- * Ranges: 1 <= ndim <= 16, nsearch >= 1, 0 <= niter <= 4096,
+ * Ranges: 1 <= ndim <= 16, 1 <= nsearch <= 2^30, 0 <= niter <= 4096,
  * 1 <= maxregions <= 2^23, 1 <= nsplit <= 1024, spread_tol >= 0.  Errors:
  * CCUBA_EINVAL, CCUBA_EHIP, CCUBA_ENOMEM. */
 typedef struct {

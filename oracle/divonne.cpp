@@ -129,7 +129,8 @@ extern "C" int oracle_divonne_partition(int ndim, oracle_integrand_t integrand, 
                                         int maxregions, int nsplit, double spread_tol,
                                         int *nregions, long long *neval, int *fail,
                                         double *total_spread, oracle_partition_trace *trace) {
-  if (ndim < 1 || ndim > 16 || !integrand || nvec < 1 || nsearch < 1 || niter < 0 ||
+  if (ndim < 1 || ndim > 16 || !integrand || nvec < 1 || nsearch < 1 || nsearch > (1 << 30) ||
+      niter < 0 ||
       niter > 4096 || maxregions < 1 || maxregions > (1 << 23) || nsplit < 1 ||
       !(spread_tol >= 0.0) || !nregions || !neval || !fail || !total_spread)
     return -1;

@@ -15,6 +15,7 @@ namespace ccuba {
 
 int validate_partition(const PartitionSpec &s) {
   if (s.ndim < 1 || s.ndim > kMaxDim || s.family < 0 || s.family > C0 || s.nsearch < 1 ||
+      s.nsearch > (1 << 30) ||  // the search loops step an int index
       s.niter < 0 || s.niter > 4096 || s.maxregions < 1 || s.maxregions > (1 << 23) ||
       s.nsplit < 1 || s.nsplit > kSuaveMaxSplit || !(s.spread_tol >= 0.0))
     return CCUBA_EINVAL;

@@ -109,7 +109,7 @@ def test_bad_arguments_are_rejected_on_the_host(cc):
     for nd, nse, nit, mr, ns, tol in ((0, 10, 1, 4, 1, 0.0), (17, 10, 1, 4, 1, 0.0),
                                       (3, 0, 1, 4, 1, 0.0), (3, 10, -1, 4, 1, 0.0),
                                       (3, 10, 1, 0, 1, 0.0), (3, 10, 1, 4, 0, 0.0),
-                                      (3, 10, 1, 4, 1, -1.0)):
+                                      (3, 10, 1, 4, 1, -1.0), (3, (1 << 30) + 1, 1, 4, 1, 0.0)):
         rc = L.ccuba_divonne_partition(None, nd, C.byref(f), 1, 0, nse, nit, mr, ns, tol,
                                        C.byref(nr), C.byref(n), C.byref(fl), C.byref(tot), None)
         assert rc == cc.EINVAL
