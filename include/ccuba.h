@@ -133,7 +133,10 @@ int ccuba_config_get(ccuba_ctx *ctx, const char *key, int precision, long long *
  * weights; prob = P(dof/2, chi2/2) with dof = iterations - 1.  The run stops
  * when neval >= mineval and error <= max(epsabs, epsrel |integral|)
  * (fail = 0), or before an iteration that would take neval past maxeval, or
- * after 4096 iterations (fail = 1).  nbatch only partitions the sampling
+ * after 4096 iterations (fail = 1).  An iteration whose sums are not finite
+ * (an integrand value that is not) ends the run with fail = -4 and zero
+ * results; this applies to every integrator below, after the step whose
+ * totals are not finite.  nbatch only partitions the sampling
  * internally and has no bearing on the results (Sect. 3.2.7); it must be
  * >= 1.  Ranges: 1 <= ndim <= 16, ncomp == 1, 2 <= nbins <= 256,
  * nstart >= 2, nincrease >= 0, every n_t < 2^32.  Outputs have ncomp = 1
@@ -241,7 +244,8 @@ enum { CCUBA_POINTS_HOST = 0, CCUBA_POINTS_DEVICE = 1 };
  * Components: every one has its own sums, estimate, combination, chi^2 and
  * prob over the same points; the grid adapts to component 0's histogram;
  * the accuracy test needs every component within its tolerance.
- * fail: 0 accuracy reached, 1 maxeval reached first, -99 the integrand
+ * fail: 0 accuracy reached, 1 maxeval reached first, -4 a value that is
+ * not finite, -99 the integrand
  * returned -999 (then neval counts every point handed to it and the results
  * are 0).  Ranges: 1 <= ndim <= 16, 1 <= ncomp <= 16, 2 <= nbins <= 256,
  * nvec >= 1, nstart >= 2, nincrease >= 0, every n_t < 2^32.  integral, error

@@ -30,7 +30,9 @@
 //    reaches 0 the run stops with fail 1;
 //  * region ids in creation order: the root is 0; the j-th selected parent in
 //    ascending id order gets children next+2j (lower half) and next+2j+1;
-//  * prob = 0 (Cuhre has no chi^2 here).
+//  * prob = 0 (Cuhre has no chi^2 here);
+//  * a non-finite total after the rule (a non-finite integrand value) ends
+//    the run with fail -4 and zero results.
 // Totals are Neumaier-compensated FP64 sums in ascending id order.
 #include <algorithm>
 #include <cmath>
@@ -235,6 +237,7 @@ extern "C" int oracle_cuhre(int ndim, int ncomp, oracle_integrand_t integrand,
       tE.add(r.err);
     }
     const double I = tI.value(), E = tE.value();
+    if (!std::isfinite(I) || !std::isfinite(E)) return finish(-4, 0.0, 0.0);
     if (nev >= mineval && E <= std::fmax(epsabs, epsrel * std::fabs(I)))
       return finish(0, I, E);
     long long K = std::min(max_regions_per_batch / 2, (long long)leaves.size());

@@ -10,7 +10,7 @@
 //     q): nsearch points x_j = fma(y_j, w_j, lo_j), y from the Philox words
 //     of counter (i, (q<<8)|b, sid, 0) (word j%4 of block j/4, FP64 uniform
 //     y = r 2^-32 + 2^-33); the largest and the smallest value, ties to the
-//     lower i, start two compass searches.
+//     lower i (a NaN is never taken), start two compass searches.
 //  2. Compass search (for the maximum; the minimum mirrors it): steps
 //     h_j = w_j/4; each of niter iterations evaluates the 2d candidates
 //     x +- h_j e_j (candidate 2j is +, 2j+1 is -; each clipped to
@@ -29,7 +29,8 @@
 //     regions in order of selection; the j-th split of the run searches its
 //     children with serials 2j+1 and 2j+2 (the root: 0).  fail is 0 when the
 //     spreads end below spread_tol, 1 when the region budget ends the phase.
-// The spreads' total is a Neumaier sum in position order.
+// A non-finite spread (a non-finite integrand value) ends the phase with
+// fail -4.  The spreads' total is a Neumaier sum in position order.
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -106,15 +107,21 @@ struct Search {
       }
     }
     eval(xs, nsearch, fv);
-    int imax = 0, imin = 0;
-    for (int i = 1; i < nsearch; ++i) {
-      if (fv[i] > fv[imax]) imax = i;
-      if (fv[i] < fv[imin]) imin = i;
+    // a NaN value is never an extremum (it compares false with everything);
+    // with no other value the searches start from -inf and +inf
+    int imax = -1, imin = -1;
+    for (int i = 0; i < nsearch; ++i) {
+      if (std::isnan(fv[i])) continue;
+      if (imax < 0 || fv[i] > fv[imax]) imax = i;
+      if (imin < 0 || fv[i] < fv[imin]) imin = i;
     }
+    const double f0max = imax < 0 ? -INFINITY : fv[imax], f0min = imin < 0 ? INFINITY : fv[imin];
+    imax = std::max(imax, 0);
+    imin = std::max(imin, 0);
     r.xmax.assign(xs.begin() + (size_t)imax * d, xs.begin() + (size_t)(imax + 1) * d);
     r.xmin.assign(xs.begin() + (size_t)imin * d, xs.begin() + (size_t)(imin + 1) * d);
-    r.fmax = compass(r, r.xmax, fv[imax], +1);
-    r.fmin = compass(r, r.xmin, fv[imin], -1);
+    r.fmax = compass(r, r.xmax, f0max, +1);
+    r.fmin = compass(r, r.xmin, f0min, -1);
     double V = 1.0;
     for (int j = 0; j < d; ++j) V *= r.hi[j] - r.lo[j];
     r.spread = 0.5 * V * (r.fmax - r.fmin);
@@ -145,7 +152,15 @@ extern "C" int oracle_divonne_partition(int ndim, oracle_integrand_t integrand, 
   int status;
   for (;;) {
     double top = 0.0;
-    for (const Region &r : R) top = std::max(top, r.spread);
+    bool finite = true;
+    for (const Region &r : R) {
+      top = std::max(top, r.spread);
+      finite = finite && std::isfinite(r.spread);
+    }
+    if (!finite) {
+      status = -4;
+      break;
+    }
     if (top <= spread_tol) {
       status = 0;
       break;
@@ -196,7 +211,7 @@ extern "C" int oracle_divonne_partition(int ndim, oracle_integrand_t integrand, 
   *nregions = (int)R.size();
   *neval = S.neval;
   *fail = status;
-  *total_spread = tot + comp;
+  *total_spread = status == -4 ? 0.0 : tot + comp;
   if (trace) {
     trace->nregions = (int)R.size();
     trace->nsplits = (int)cuts.size();

@@ -44,7 +44,9 @@
 //     split of the run (counted from 0 over all steps) samples its children
 //     with serials 2j+1 (lower) and 2j+2 (upper).  All splits of a step are
 //     decided before any child is sampled.
-// All sums are Neumaier-compensated FP64 in point (or position) order.
+// A non-finite total (a non-finite integrand value) ends the run with fail -4
+// and zero results.  All sums are Neumaier-compensated FP64 in point (or
+// position) order.
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -299,7 +301,12 @@ extern "C" int oracle_suave(int ndim, int ncomp, oracle_integrand_t integrand, v
       totals();
     }
   }
+  bool nonfinite = false;
   while (!aborted && !R.empty()) {
+    if (!std::isfinite(I) || !std::isfinite(var)) {
+      nonfinite = true;
+      break;
+    }
     if (nev >= mineval && std::sqrt(var) <= std::max(epsabs, epsrel * std::fabs(I))) {
       status = 0;
       break;
@@ -347,6 +354,13 @@ extern "C" int oracle_suave(int ndim, int ncomp, oracle_integrand_t integrand, v
     *nregions = (int)R.size();
     *neval = nev;
     *fail = -99;
+    integral[0] = error[0] = prob[0] = 0.0;
+    return 0;
+  }
+  if (nonfinite) {
+    *nregions = (int)R.size();
+    *neval = nev;
+    *fail = -4;
     integral[0] = error[0] = prob[0] = 0.0;
     return 0;
   }

@@ -29,6 +29,8 @@
 //    with fail 1;
 //  * nbatch only partitions the sampling internally (Sect. 3.2.7) and has no
 //    effect on any result, so it is only validated here;
+//  * an iteration whose sums are not finite (a non-finite integrand value)
+//    ends the run with fail -4 and zero results; neval counts it;
 //  * several components (ncomp > 1): every component has its own sums,
 //    iteration results, combination, chi^2 and probability over the same
 //    points; the one grid adapts to the histogram of component 0; the
@@ -319,6 +321,16 @@ extern "C" int oracle_vegas_from(const double *grid_in, int ndim, int ncomp,
       return 0;
     }
     nev += n;
+    bool bad = false;
+    for (int c = 0; c < ncomp; ++c)
+      bad = bad || !std::isfinite(s1[c].value()) || !std::isfinite(s2[c].value());
+    if (bad) {
+      *neval = nev;
+      *fail = -4;
+      for (int c = 0; c < ncomp; ++c) integral[c] = error[c] = prob[c] = 0.0;
+      if (trace) trace->n_iter = (int)It[0].size();
+      return 0;
+    }
     bool all = nev >= mineval;
     for (int c = 0; c < ncomp; ++c) {
       const double I = s1[c].value() / (double)n;

@@ -303,6 +303,12 @@ int CuhreRun::read_totals(hipStream_t s) {
 int CuhreRun::plan_and_split(hipStream_t s) {
   pendK_ = 0;
   if (done_) return 0;
+  if (!std::isfinite(I_) || !std::isfinite(E_)) {  // a non-finite integrand value
+    done_ = true;
+    fail_ = -4;
+    I_ = E_ = 0.0;
+    return 0;
+  }
   if (neval_ >= spec_.mineval && E_ <= std::max(spec_.epsabs, spec_.epsrel * std::fabs(I_))) {
     done_ = true;
     fail_ = 0;

@@ -81,6 +81,11 @@ int run_partition(ccuba_ctx *ctx, const PartitionSpec &sp, PartitionResult &res,
   for (;;) {
     CCUBA_HIP(hipMemcpyAsync(&st, state.p, sizeof(st), hipMemcpyDeviceToHost, s));
     CCUBA_HIP(hipStreamSynchronize(s));
+    if (!std::isfinite(st.total_spread)) {  // a non-finite integrand value
+      fail = -4;
+      st = DState{};
+      break;
+    }
     if (st.max_spread <= sp.spread_tol) {
       fail = 0;
       break;

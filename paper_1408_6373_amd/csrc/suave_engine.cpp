@@ -118,6 +118,11 @@ int run_suave(ccuba_ctx *ctx, const SuaveSpec &sp, SuaveResult &res, const Suave
   for (;;) {
     CCUBA_HIP(hipMemcpyAsync(&st, B.state.p, sizeof(st), hipMemcpyDeviceToHost, s));
     CCUBA_HIP(hipStreamSynchronize(s));
+    if (!std::isfinite(st.I) || !std::isfinite(st.var)) {  // a non-finite integrand value
+      fail = -4;
+      st = SState{};
+      break;
+    }
     if (neval >= sp.mineval &&
         std::sqrt(st.var) <= std::max(sp.epsabs, sp.epsrel * std::fabs(st.I))) {
       fail = 0;

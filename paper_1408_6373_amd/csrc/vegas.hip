@@ -170,11 +170,18 @@ __device__ __forceinline__ void settle_component(VState &st, double S1, double S
   }
 }
 
-// The stop rule's outcome (conv: the accuracy test passed; budget: the next
-// iteration would pass maxeval) and, once done, chi^2 over the history
-// hI/hV of the st.T iterations and its probability.
-__device__ __forceinline__ void finish_state(VState &st, bool conv, bool budget,
+// The stop rule's outcome (bad: the iteration's sums are not finite, which
+// ends the integral with fail -4 and zero results; conv: the accuracy test
+// passed; budget: the next iteration would pass maxeval) and, once done,
+// chi^2 over the history hI/hV of the st.T iterations and its probability.
+__device__ __forceinline__ void finish_state(VState &st, bool bad, bool conv, bool budget,
                                              const double *hI, const double *hV) {
+  if (bad) {
+    st.done = 1;
+    st.fail = -4;
+    st.integral = st.error = st.chi2 = st.prob = 0.0;
+    return;
+  }
   if (conv) {
     st.done = 1;
     st.fail = 0;
@@ -308,10 +315,11 @@ __global__ void __launch_bounds__(kRefineThreads) vegas_refine_kernel(VegasArgs 
     const long long nnext = nstart + (long long)T * ninc;
     const bool budget = st.neval + nnext > JOB_FIELD(jw, maxeval) ||
                         T >= JOB_FIELD(jw, hist_cap) || nnext >= (1ll << 32);
-    finish_state(st, conv, budget, hI, hV);
+    const bool bad = !isfinite(S1) || !isfinite(S2);
+    finish_state(st, bad, conv, budget, hI, hV);
     st.hcap = (float)(1024.0 * (S2 / (double)n));
     *JOB_FIELD(jw, state) = st;
-    s_mode = conv ? 0 : ((JOB_FIELD(jw, flags) & FLAG_FREEZE_GRID) ? 2 : 1);
+    s_mode = conv || bad ? 0 : ((JOB_FIELD(jw, flags) & FLAG_FREEZE_GRID) ? 2 : 1);
   }
   __syncthreads();
   const int mode = s_mode;
@@ -485,7 +493,7 @@ __global__ void __launch_bounds__(kAccumThreads) vegas_batched_accumulate_kernel
 // histogram, one wavefront per dimension.
 __global__ void __launch_bounds__(1024) vegas_batched_finish_kernel(BatchedFinishArgs F) {
   extern __shared__ double fsm[];
-  __shared__ int s_conv[kMaxComp];
+  __shared__ int s_conv[kMaxComp], s_bad[kMaxComp];
   __shared__ int s_mode;
   const int tid = threadIdx.x, bs = blockDim.x, lane = tid & 63, wv = tid >> 6, nwv = bs >> 6;
   const int d = F.ndim, N = F.nbins, dN = d * N, nc = F.ncomp, row = N + 1, drow = d * row;
@@ -523,18 +531,22 @@ __global__ void __launch_bounds__(1024) vegas_batched_finish_kernel(BatchedFinis
     F.iter_var[(long long)tid * F.hist_cap + t] = var;
     const double tol = fmax(F.epsabs, F.epsrel * fabs(st.integral));
     s_conv[tid] = st.neval >= F.mineval && st.error <= tol;
+    s_bad[tid] = !isfinite(S[2 * tid]) || !isfinite(S[2 * tid + 1]);
   }
   __syncthreads();
   if (tid < nc) {
-    bool conv = true;
-    for (int c = 0; c < nc; ++c) conv = conv && s_conv[c] != 0;
+    bool conv = true, bad = false;
+    for (int c = 0; c < nc; ++c) {
+      conv = conv && s_conv[c] != 0;
+      bad = bad || s_bad[c] != 0;
+    }
     const int T = st.T;
     const long long nnext = F.nstart + (long long)T * F.nincrease;
     const bool budget = st.neval + nnext > F.maxeval || T >= F.hist_cap || nnext >= (1ll << 32);
-    finish_state(st, conv, budget, F.iter_I + (long long)tid * F.hist_cap,
+    finish_state(st, bad, conv, budget, F.iter_I + (long long)tid * F.hist_cap,
                  F.iter_var + (long long)tid * F.hist_cap);
     F.state[tid] = st;
-    if (tid == 0) s_mode = conv ? 0 : ((F.flags & FLAG_FREEZE_GRID) ? 2 : 1);
+    if (tid == 0) s_mode = conv || bad ? 0 : ((F.flags & FLAG_FREEZE_GRID) ? 2 : 1);
   }
   __syncthreads();
   if (s_mode != 1) return;  // converged, or the grid is frozen (kept as it is)

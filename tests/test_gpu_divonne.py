@@ -133,9 +133,11 @@ def test_full_bench_shape_properties(cc, ctx):
     for k in ("xmin", "xmax"):
         assert np.all(r[k] >= lo) and np.all(r[k] <= hi)
     assert np.array_equal(r["spread"], 0.5 * vol * (r["fmax"] - r["fmin"]))
+    # f = exp(-s) with s up to ~100 at the minima: a few ulps of s, summed in
+    # another order by the oracle's integrand, are ~1e-14 relative in f
     pick = np.random.default_rng(3).choice(R, 256, replace=False)
     assert np.allclose(O.genz_eval(W.GAUSSIAN, a, u, r["xmax"][pick]), r["fmax"][pick],
-                       rtol=1e-14, atol=0)
+                       rtol=1e-12, atol=0)
     assert np.allclose(O.genz_eval(W.GAUSSIAN, a, u, r["xmin"][pick]), r["fmin"][pick],
-                       rtol=1e-14, atol=0)
+                       rtol=1e-12, atol=0)
     assert abs(r["total_spread"] - r["spread"].sum()) <= 1e-12 * r["total_spread"]
