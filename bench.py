@@ -374,6 +374,51 @@ def _suave_leg(cc, ctx, cpu=True):
     return out
 
 
+def _checkpoint_leg(cc, ctx):
+    """Vegas at the headline shape (oscillatory d=8, 128 bins, 20 x 1e7 points,
+    FP32 evaluation) without and with a state file written after every
+    iteration, and started from a kept grid (gridno)."""
+    import tempfile
+    import workloads as W
+    a, u = W.genz_params(W.OSCILLATORY, D, 1)
+    kw = dict(ctx=ctx, flags=cc.FP32_EVAL, nbins=NBINS, nstart=NPTS, maxeval=ITERS * NPTS, seed=1)
+    cc.vegas(W.OSCILLATORY, a, u, **kw)  # warm-up
+
+    def best(**extra):
+        t = None
+        for _ in range(3):
+            t0 = time.perf_counter()
+            r = cc.vegas(W.OSCILLATORY, a, u, **dict(kw, **extra))
+            dt = time.perf_counter() - t0
+            t = dt if t is None else min(t, dt)
+        return r, t
+
+    plain, tp = best()
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "vegas.state")
+        t = None
+        for _ in range(3):
+            if os.path.exists(path):
+                os.remove(path)
+            t0 = time.perf_counter()
+            r = cc.vegas(W.OSCILLATORY, a, u, statefile=path, **kw)
+            dt = time.perf_counter() - t0
+            t = dt if t is None else min(t, dt)
+        ts, state_bytes = t, os.path.getsize(path)
+    cc.vegas(W.OSCILLATORY, a, u, gridno=7, **kw)  # keeps its final grid in slot 7
+    reused, tg = best(gridno=-7)
+    return {"workload": "Vegas oscillatory d=8, 128 bins, 20 x 1e7 points, FP32 evaluation",
+            "unit": "evals/s",
+            "plain": {"value": plain["neval"] / tp, "seconds": tp},
+            "statefile": {"value": plain["neval"] / ts, "seconds": ts,
+                          "per_iteration_us": 1e6 * (ts - tp) / ITERS,
+                          "file_bytes": state_bytes,
+                          "rel_diff_from_plain": abs(r["integral"] - plain["integral"]) / abs(plain["integral"])},
+            "gridno_reuse": {"value": reused["neval"] / tg, "seconds": tg,
+                             "rel_error": reused["error"] / abs(reused["integral"]),
+                             "plain_rel_error": plain["error"] / abs(plain["integral"])}}
+
+
 DIV_NSEARCH, DIV_NITER, DIV_REGIONS, DIV_SPLIT = 1024, 64, 16384, 1024
 
 
@@ -488,6 +533,8 @@ def main():
                     help="run only the Suave leg and print its JSON line (for profiling)")
     ap.add_argument("--divonne-only", action="store_true",
                     help="run only the Divonne-partition leg and print its JSON line")
+    ap.add_argument("--checkpoint-only", action="store_true",
+                    help="run only the state-file / grid-reuse leg and print its JSON line")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="for PMC runs: one 1 GiB device copy (calibration), then one FP32 "
                          "integral of the headline workload; prints a JSON line")
@@ -529,9 +576,10 @@ def main():
         print(json.dumps({"traffic_probe": True, "copy_bytes": 1 << 30, "neval": r["neval"]}))
         return
     ctx = cc.Context(device=0)
-    if args.suave_only or args.divonne_only:
+    if args.suave_only or args.divonne_only or args.checkpoint_only:
         leg = ({"suave": _suave_leg(cc, ctx, cpu=False)} if args.suave_only else
-               {"divonne_partition": _divonne_leg(cc, ctx, cpu=False)})
+               {"divonne_partition": _divonne_leg(cc, ctx, cpu=False)} if args.divonne_only
+               else {"checkpoint": _checkpoint_leg(cc, ctx)})
         print(json.dumps(leg))
         ctx.close()
         return
@@ -557,6 +605,7 @@ def main():
     if not args.no_extra:
         out["batch"] = _batch_leg(cc)
         out["caller_integrand"] = _caller_integrand_leg(cc)
+        out["checkpoint"] = _checkpoint_leg(cc, ctx)
         out["cuhre"] = _cuhre_leg(cc, ctx)
         out["suave"] = _suave_leg(cc, ctx, cpu=not args.no_cpu_baseline)
         out["divonne_partition"] = _divonne_leg(cc, ctx, cpu=not args.no_cpu_baseline)
