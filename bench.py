@@ -58,14 +58,25 @@ def _stats(cc, ctx, reset=True):
     return st
 
 
+_JOBS = {}
+
+
+def _headline_jobs(cc, params, prec):
+    """The step's integrals as one batch: every iteration samples both in one
+    DoSample launch, and one fold and one refine launch finish both."""
+    if prec not in _JOBS:
+        specs = [dict(method=0, family=fam, a=params[fam][0], u=params[fam][1], flags=prec,
+                      seed=1, stream_id=0, nstart=NPTS, maxeval=ITERS * NPTS, nbins=NBINS)
+                 for fam in FAMILIES]
+        _JOBS[prec] = cc.make_jobs(specs)
+    return _JOBS[prec]
+
+
 def _step(cc, ctx, params, prec):
     ev = 0
-    for fam in FAMILIES:
-        a, u = params[fam]
-        r = cc.vegas(fam, a, u, ctx=ctx, flags=prec, nbins=NBINS, nstart=NPTS,
-                     maxeval=ITERS * NPTS, seed=1)
-        if r["neval"] != ITERS * NPTS:
-            raise RuntimeError("unexpected neval %d" % r["neval"])
+    for r in cc.vegas_batch(ctx, _headline_jobs(cc, params, prec)):
+        if r["neval"] != ITERS * NPTS or r["status"] != 0:
+            raise RuntimeError("unexpected result %r" % (r,))
         ev += r["neval"]
     return ev
 
@@ -102,18 +113,13 @@ def _roofline(cc, ctx, params):
     # lane per trip, 2 Philox blocks per point, power-of-two bin count,
     # d = 4 x blocks
     key = "f32hfx_ilp2_nb2_pow2_full"
-    for fam in FAMILIES:
-        a, u = params[fam]
-        cc.vegas(fam, a, u, ctx=ctx, flags=cc.FP32_EVAL, nbins=NBINS, nstart=NPTS,
-                 maxeval=ITERS * NPTS, seed=1)
-        st = _stats(cc, ctx)
-        ms += st.dosample_ms
-        fold_ms += st.fold_ms
-        evals += st.evals
-        launches += st.dosample_launches
-        refine_ms += st.refine_ms
+    _step(cc, ctx, params, cc.FP32_EVAL)
+    st = _stats(cc, ctx)
+    ms, fold_ms, refine_ms = st.dosample_ms, st.fold_ms, st.refine_ms
+    evals, launches = st.evals, st.dosample_launches
+    for fam in FAMILIES:  # each integral contributes ITERS x NPTS points
         per = table.get(key, {}).get(FAMILY_KEYS[fam])
-        slots = None if (per is None or slots is None) else slots + per * st.evals
+        slots = None if (per is None or slots is None) else slots + per * ITERS * NPTS
     ctx.config("profile", 0)
     n = max(launches, 1)
     out = {"bound": "alu", "kernel": "vegas_dosample_kernel<float,unsigned long long,2,2,true,true>",
@@ -181,10 +187,11 @@ def summarize_pmc(fetch_csv, write_csv, out_path, commands):
         raise SystemExit("no 1 GiB copy dispatch in the counter files")
     gib = float(1 << 30)
     fs, ws = gib / (cf * 1024), gib / (cw * 1024)
-    rec = {"what": "HBM bytes per dispatch of the FP32 DoSample kernels (Vegas d=8 "
-                   "oscillatory, 128 bins, 1e7 points per iteration, 20 iterations) from "
-                   "rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by the same counters on a "
-                   "1 GiB device-to-device copy",
+    rec = {"what": "HBM bytes per dispatch of the FP32 DoSample kernels (one headline "
+                   "step: Vegas d=8 oscillatory and product peak as one batch, 128 bins, "
+                   "2 x 1e7 points per launch, 20 iterations) from rocprofv3 FETCH_SIZE "
+                   "and WRITE_SIZE, scaled by the same counters on a 1 GiB "
+                   "device-to-device copy",
            "commands": commands,
            "copy_calibration": {"bytes": 1 << 30, "fetch_kib": cf, "write_kib": cw,
                                 "fetch_scale": fs, "write_scale": ws}}
@@ -537,7 +544,7 @@ def main():
                     help="run only the state-file / grid-reuse leg and print its JSON line")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="for PMC runs: one 1 GiB device copy (calibration), then one FP32 "
-                         "integral of the headline workload; prints a JSON line")
+                         "step of the headline workload; prints a JSON line")
     ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT"),
                     help="write the traffic summary of two --traffic-probe counter runs")
     ap.add_argument("--stats-summary", nargs=2, metavar=("STATS_CSV", "OUT"),
@@ -569,11 +576,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         ctx = cc.Context(device=0)
-        a, u = params[1]
-        r = cc.vegas(1, a, u, ctx=ctx, flags=cc.FP32_EVAL, nbins=NBINS, nstart=NPTS,
-                     maxeval=ITERS * NPTS, seed=1)
+        ev = _step(cc, ctx, params, cc.FP32_EVAL)
         ctx.close()
-        print(json.dumps({"traffic_probe": True, "copy_bytes": 1 << 30, "neval": r["neval"]}))
+        print(json.dumps({"traffic_probe": True, "copy_bytes": 1 << 30, "neval": ev}))
         return
     ctx = cc.Context(device=0)
     if args.suave_only or args.divonne_only or args.checkpoint_only:
