@@ -119,6 +119,28 @@ struct CtxScope {
   }
 };
 
+}  // namespace
+
+namespace ccuba {
+int pinned_block(ccuba_ctx *ctx, double **host, double **dev) {
+  if (!ctx->pinned_host) {
+    void *h = nullptr, *d = nullptr;
+    if (hipHostMalloc(&h, ccuba_ctx::kPinnedBytes, 0) != hipSuccess) return CCUBA_EHIP;
+    if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess) {
+      (void)hipHostFree(h);
+      return CCUBA_EHIP;
+    }
+    ctx->pinned_host = (double *)h;
+    ctx->pinned_dev = (double *)d;
+  }
+  *host = ctx->pinned_host;
+  *dev = ctx->pinned_dev;
+  return CCUBA_OK;
+}
+}  // namespace ccuba
+
+namespace {
+
 void drop_engine_cache(ccuba_ctx *ctx) {
   delete ctx->vcache;
   ctx->vcache = nullptr;
@@ -227,6 +249,7 @@ int ccuba_shutdown(ccuba_ctx **ctx) {
   c->server = nullptr;
   drop_engine_cache(c);
   rtc_release(c);
+  if (c->pinned_host) (void)hipHostFree(c->pinned_host);
   pool_release(c);
   if (c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
@@ -681,6 +704,9 @@ int ccuba_cuhre(ccuba_ctx **ctxp, int ndim, int ncomp, const ccuba_integrand *f,
   CCUBA_HIP(hipSetDevice(ctx->device));
   CuhreRun run(ctx);
   int rc;
+  double *ph = nullptr, *pd = nullptr;
+  if ((rc = pinned_block(ctx, &ph, &pd))) return rc;
+  run.set_mapped_totals(ph, pd);
   if ((rc = run.start(sp, ctx->stream)) || (rc = run.run(ctx->stream))) return rc;
   *nregions = (int)std::min<long long>(run.nregions(), 0x7fffffff);
   *neval = run.neval();

@@ -42,6 +42,12 @@ struct ccuba_ctx {
   int engine_cache = 1;
   // DoSample kernels compiled at run time for callers' device integrands
   ccuba::RtcCache *rtc = nullptr;
+  // a small mapped pinned host block (host and device addresses) that the
+  // step-wise integrators' totals kernels write into, so that the host reads
+  // a step's totals after a stream synchronisation without a copy; calls on
+  // one context are serialised by `lock', so one block serves them all
+  double *pinned_host = nullptr, *pinned_dev = nullptr;
+  static constexpr size_t kPinnedBytes = 256;
   // Vegas grids kept between calls (gridno): slot -> ((ndim, nbins), edges)
   std::map<int, std::pair<std::pair<int, int>, std::vector<double>>> grid_table;
   // freed device blocks kept for reuse, by size class (see dev_alloc)
@@ -63,6 +69,9 @@ int dev_alloc(ccuba_ctx *ctx, void **p, size_t bytes);
 void dev_free(ccuba_ctx *ctx, void *p, size_t bytes);
 // Return every pooled block to the device.
 void pool_release(ccuba_ctx *ctx);
+// The context's mapped pinned block (allocated on first use).  Returns
+// CCUBA_OK or CCUBA_EHIP.
+int pinned_block(ccuba_ctx *ctx, double **host, double **dev);
 
 // A typed device buffer that returns its bytes to the context on release.
 template <typename T>

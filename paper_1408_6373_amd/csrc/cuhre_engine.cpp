@@ -355,6 +355,7 @@ int CuhreRun::run(hipStream_t s) {
   for (;;) {
     int rc = launch_totals(s);
     if (rc) return rc;
+    if (mapped_host_) CCUBA_HIP(hipStreamSynchronize(s));  // totals written to host memory
     if ((rc = read_totals(s))) return rc;
     rc = plan_and_split(s);
     if (rc < 0) return rc;

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 
 #include "suave.h"
 #include "vegas_engine.h"
@@ -34,15 +35,15 @@ int run_partition(ccuba_ctx *ctx, const PartitionSpec &sp, PartitionResult &res,
   const int Kmax = (int)std::min<long long>(sp.nsplit, std::max<long long>(1, Rmax - 1));
   DevBuf<double> lo, hi, xmin, xmax, fmin, fmax, spread, p64;
   DevBuf<int> sel, chpos, chser, cut;
-  DevBuf<DState> state;
   if ((rc = lo.alloc(ctx, Rmax * d)) || (rc = hi.alloc(ctx, Rmax * d)) ||
       (rc = xmin.alloc(ctx, Rmax * d)) || (rc = xmax.alloc(ctx, Rmax * d)) ||
       (rc = fmin.alloc(ctx, Rmax)) || (rc = fmax.alloc(ctx, Rmax)) ||
       (rc = spread.alloc(ctx, Rmax)) || (rc = p64.alloc(ctx, 2 * kParamRow)) ||
       (rc = sel.alloc(ctx, Kmax)) || (rc = chpos.alloc(ctx, 2 * Kmax)) ||
-      (rc = chser.alloc(ctx, 2 * Kmax)) || (rc = cut.alloc(ctx, std::max<long long>(1, Rmax - 1))) ||
-      (rc = state.alloc(ctx, 1)))
+      (rc = chser.alloc(ctx, 2 * Kmax)) || (rc = cut.alloc(ctx, std::max<long long>(1, Rmax - 1))))
     return rc;
+  double *pin_host = nullptr, *pin_dev = nullptr;  // the totals land in host memory
+  if ((rc = pinned_block(ctx, &pin_host, &pin_dev))) return rc;
   VegasSpec vs;
   vs.ndim = d;
   vs.family = sp.family;
@@ -69,7 +70,7 @@ int run_partition(ccuba_ctx *ctx, const PartitionSpec &sp, PartitionResult &res,
   A.chpos = chpos.p;
   A.chser = chser.p;
   A.cut = cut.p;
-  A.state = state.p;
+  A.state = (DState *)pin_dev;
   const long long per_search = sp.nsearch + 4ll * d * sp.niter;
 
   CCUBA_HIP(launch_div_root(A, s));
@@ -79,8 +80,8 @@ int run_partition(ccuba_ctx *ctx, const PartitionSpec &sp, PartitionResult &res,
   DState st{};
   int fail = 1;
   for (;;) {
-    CCUBA_HIP(hipMemcpyAsync(&st, state.p, sizeof(st), hipMemcpyDeviceToHost, s));
     CCUBA_HIP(hipStreamSynchronize(s));
+    std::memcpy(&st, pin_host, sizeof(st));
     if (!std::isfinite(st.total_spread)) {  // a non-finite integrand value
       fail = -4;
       st = DState{};

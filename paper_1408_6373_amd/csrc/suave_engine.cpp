@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 #include "vegas_engine.h"
@@ -33,7 +34,6 @@ struct Buffers {
   DevBuf<double> lo, hi, grid, I, var, chi2, inh_I, inh_var, v, fl1, fl2, hs, tsum, thist, p64;
   DevBuf<int> dof, sel, chpos, chser, cut;
   DevBuf<uint16_t> side;
-  DevBuf<SState> state;
 };
 
 }  // namespace
@@ -65,8 +65,10 @@ int run_suave(ccuba_ctx *ctx, const SuaveSpec &sp, SuaveResult &res, const Suave
       (rc = B.thist.alloc(ctx, (size_t)2 * Kmax * ntiles * dN)) ||
       (rc = B.p64.alloc(ctx, 2 * kParamRow)) || (rc = B.sel.alloc(ctx, Kmax)) ||
       (rc = B.chpos.alloc(ctx, 2 * Kmax)) || (rc = B.chser.alloc(ctx, 2 * Kmax)) ||
-      (rc = B.cut.alloc(ctx, std::max<long long>(1, Rmax - 1))) || (rc = B.state.alloc(ctx, 1)))
+      (rc = B.cut.alloc(ctx, std::max<long long>(1, Rmax - 1))))
     return rc;
+  double *pin_host = nullptr, *pin_dev = nullptr;  // the totals land in host memory
+  if ((rc = pinned_block(ctx, &pin_host, &pin_dev))) return rc;
 
   VegasSpec vs;
   vs.ndim = d;
@@ -105,7 +107,7 @@ int run_suave(ccuba_ctx *ctx, const SuaveSpec &sp, SuaveResult &res, const Suave
   A.tsum = B.tsum.p;
   A.thist = B.thist.p;
   A.cut = B.cut.p;
-  A.state = B.state.p;
+  A.state = (SState *)pin_dev;
 
   // the root region
   CCUBA_HIP(launch_suave_root(A, s));
@@ -116,8 +118,8 @@ int run_suave(ccuba_ctx *ctx, const SuaveSpec &sp, SuaveResult &res, const Suave
   SState st{};
   int fail = 1;
   for (;;) {
-    CCUBA_HIP(hipMemcpyAsync(&st, B.state.p, sizeof(st), hipMemcpyDeviceToHost, s));
     CCUBA_HIP(hipStreamSynchronize(s));
+    std::memcpy(&st, pin_host, sizeof(st));
     if (!std::isfinite(st.I) || !std::isfinite(st.var)) {  // a non-finite integrand value
       fail = -4;
       st = SState{};
