@@ -380,16 +380,20 @@ int ccuba_vegas_stateful(ccuba_ctx **ctxp, int ndim, int ncomp, const ccuba_inte
       if ((rc = eng.load_grid(0, it->second.second.data(), hipMemcpyHostToDevice, s))) return rc;
   }
   if (checkpoint) {
-    const int cap = eng.hist_cap();
-    std::vector<double> I(cap), var(cap);
+    // the history is kept on the host (a resumed file's first) and grows by
+    // the one iteration just done
+    if (!resumed) {
+      sf.I.clear();
+      sf.var.clear();
+    }
     rc = eng.run_each(s, [&](const VState &st) {
       sf.st = st;
       sf.grid.resize(row);
-      int r = eng.read_grid(0, sf.grid.data(), s);
+      sf.I.resize(st.T);
+      sf.var.resize(st.T);
+      const int t = st.T - 1;
+      const int r = eng.read_step(0, t, sf.grid.data(), &sf.I[t], &sf.var[t], s);
       if (r) return r;
-      if ((r = eng.read_history(0, st.T, I.data(), var.data(), s))) return r;
-      sf.I.assign(I.begin(), I.begin() + st.T);
-      sf.var.assign(var.begin(), var.begin() + st.T);
       return state_write(statefile, sp, sf);
     });
   } else {

@@ -531,6 +531,18 @@ int VegasEngine::read_grid(int job, double *grid, hipStream_t s) {
   return CCUBA_OK;
 }
 
+int VegasEngine::read_step(int job, int t, double *grid, double *I, double *var,
+                           hipStream_t s) {
+  if (job < 0 || job >= njobs() || t < 0 || t >= hjobs_[job].hist_cap) return CCUBA_EINVAL;
+  const VJob &J = hjobs_[job];
+  const long long row = (long long)J.ndim * (J.nbins + 1);
+  CCUBA_HIP(hipMemcpyAsync(grid, J.grid, row * sizeof(double), hipMemcpyDeviceToHost, s));
+  CCUBA_HIP(hipMemcpyAsync(I, J.iter_I + t, sizeof(double), hipMemcpyDeviceToHost, s));
+  CCUBA_HIP(hipMemcpyAsync(var, J.iter_var + t, sizeof(double), hipMemcpyDeviceToHost, s));
+  CCUBA_HIP(hipStreamSynchronize(s));
+  return CCUBA_OK;
+}
+
 int VegasEngine::set_iteration(int job, int t, hipStream_t s) {
   if (job < 0 || job >= njobs()) return CCUBA_EINVAL;
   VState st{};

@@ -74,6 +74,9 @@ class VegasEngine {
   int read_states(std::vector<VState> &out, hipStream_t s);
   int read_history(int job, int n, double *I, double *var, hipStream_t s);
   int read_grid(int job, double *grid, hipStream_t s);
+  // The grid and iteration t's estimate and variance of one job, read with
+  // one synchronisation (what a checkpoint needs after each iteration).
+  int read_step(int job, int t, double *grid, double *I, double *var, hipStream_t s);
   // Raw pieces: set iteration index of job 0, run DoSample only, and sum the
   // group partials into caller buffers.
   int set_iteration(int job, int t, hipStream_t s);
