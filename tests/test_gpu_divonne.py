@@ -141,3 +141,11 @@ def test_full_bench_shape_properties(cc, ctx):
     assert np.allclose(O.genz_eval(W.GAUSSIAN, a, u, r["xmin"][pick]), r["fmin"][pick],
                        rtol=1e-12, atol=0)
     assert abs(r["total_spread"] - r["spread"].sum()) <= 1e-12 * r["total_spread"]
+
+
+def test_stream_id_and_large_seed_match_oracle(cc, ctx):
+    a, u = W.genz_params(W.C0, 4, 32)
+    kw = dict(nsearch=200, niter=12, maxregions=30, nsplit=3, stream_id=9)
+    g = cc.divonne_partition(W.C0, a, u, ctx=ctx, trace=True, seed=(5 << 33) + 1, **kw)
+    o = O.divonne_partition(O.genz(W.C0, a, u), 4, seed=(5 << 33) + 1, **kw)
+    _compare(g, o)

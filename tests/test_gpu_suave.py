@@ -166,3 +166,14 @@ def test_full_bench_shape_properties(cc, ctx):
     assert np.all(np.diff(g, axis=2) >= 0.0)
     ex = exact(W.GAUSSIAN, a, u)
     assert abs(r["integral"] - ex) <= 5 * r["error"]
+
+
+def test_stream_id_and_large_seed_match_oracle(cc, ctx):
+    # the stream id is Philox counter word 2 and the seed's high half key word 1
+    a, u = W.genz_params(W.OSCILLATORY, 4, 31)
+    kw = dict(nnew=3000, maxeval=40000, nbins=16, seed=(7 << 40) + 3, stream_id=5, nsplit=2)
+    g = cc.suave(W.OSCILLATORY, a, u, ctx=ctx, trace=True, **kw)
+    o = O.suave(O.genz(W.OSCILLATORY, a, u), 4, **kw)
+    _compare(g, o)
+    other = cc.suave(W.OSCILLATORY, a, u, ctx=ctx, **dict(kw, stream_id=6))
+    assert other["integral"] != g["integral"]
