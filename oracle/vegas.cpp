@@ -13,8 +13,12 @@
 //    exact in its precision and never 0 or 1;
 //  * map: z = y N, k = min(floor z, N-1), x = E[k] + (z-k)(E[k+1]-E[k]) (one
 //    fused multiply-add), weight w = prod_j N (E_j[k+1]-E_j[k]);
-//  * estimator: v = w f, S1 = sum v, S2 = sum v^2, I_t = S1/n,
-//    sigma_t^2 = max(0, S2/n - I_t^2)/(n-1); histogram H_j[k_j] += v^2;
+//  * estimator: v = w f, I_t = the mean of v, sigma_t^2 = max(0, mean of v^2
+//    - I_t^2)/(n-1); histogram H_j[k_j] += v^2.  The sums are taken about
+//    c = I_{t-1} (0 for t = 0): S1 = sum (v - c), S2 = sum (v - c)^2,
+//    I_t = c + S1/n, sigma_t^2 = max(0, S2/n - (S1/n)^2)/(n-1), which is the
+//    same quantity, evaluated without the cancellation between the mean of
+//    v^2 and I_t^2 that costs log10(mean v^2 / variance) digits;
 //  * refinement (each dimension with sum H > 0): 3-point smoothing, damping
 //    m_k = ((r_k-1)/ln r_k)^1.5 with r_k the normalised smoothed histogram,
 //    then new edges that give every new bin the same share of sum m, with m_k
@@ -276,6 +280,7 @@ extern "C" int oracle_vegas_from(const double *grid_in, int ndim, int ncomp,
       wbuf(nvec);
   std::vector<int> kbuf((size_t)nvec * ndim);
   const int core = 32768;  // the master samples (serial mode)
+  std::vector<double> shift(ncomp, 0.0);  // I_{t-1} of every component (0 at t = 0)
 
   for (int t = 0;; ++t) {
     const long long n = nstart + (long long)t * nincrease;
@@ -306,8 +311,9 @@ extern "C" int oracle_vegas_from(const double *grid_in, int ndim, int ncomp,
           else
             v = wbuf[p] * fbuf[(size_t)p * ncomp + c];
           const double v2 = v * v;
-          s1[c].add(v);
-          s2[c].add(v2);
+          const double dv = v - shift[c];
+          s1[c].add(dv);
+          s2[c].add(dv * dv);
           if (c == 0)
             for (int j = 0; j < ndim; ++j)
               h[(size_t)j * N + kbuf[(size_t)p * ndim + j]].add(v2);
@@ -333,10 +339,12 @@ extern "C" int oracle_vegas_from(const double *grid_in, int ndim, int ncomp,
     }
     bool all = nev >= mineval;
     for (int c = 0; c < ncomp; ++c) {
-      const double I = s1[c].value() / (double)n;
-      double var = s2[c].value() / (double)n - I * I;
+      const double m = s1[c].value() / (double)n;
+      const double I = shift[c] + m;
+      double var = s2[c].value() / (double)n - m * m;
       if (var < 0.0) var = 0.0;
       var /= (double)(n - 1);
+      shift[c] = I;
       It[c].push_back(I);
       vart[c].push_back(var);
       res[c] = combine(It[c], vart[c]);

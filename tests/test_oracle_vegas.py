@@ -254,3 +254,27 @@ def test_first_iteration_from_a_grid_is_the_plain_mean():
     var = (math.fsum(v * v) / n - I * I) / (n - 1)
     assert abs(r["iter_I"][0] - I) <= 1e-15 * abs(I)
     assert abs(r["iter_var"][0] - var) <= 1e-12 * var
+
+
+@pytest.mark.parametrize("t", [4, 8])
+def test_later_iteration_variance_is_the_sample_variance(t):
+    # iteration t of a product peak in d = 8 whose grid has adapted, so that
+    # the variance is about 1/2000 of the mean of v^2: I_t and sigma_t^2 equal
+    # the mean and the two-pass sample variance of the iteration's v = w f,
+    # summed by brute force (math.fsum) over the points mapped through the
+    # grid that enters iteration t.  Evaluating sigma_t^2 from plain sums of v
+    # and v^2 loses about 3 of its digits to cancellation here (off by about
+    # 1e-13); the bar 1e-14 needs the cancellation-free form.
+    import math
+    d, N, n, seed = 8, 64, 100000, 5
+    a, u = W.genz_params(2, d, 1)
+    G = O.vegas(O.genz(2, a, u), d, nstart=n, maxeval=t * n, nbins=N, seed=seed)["grid"]
+    r = O.vegas(O.genz(2, a, u), d, nstart=n, maxeval=(t + 1) * n, nbins=N, seed=seed)
+    pts = O.vegas_points(d, N, G, seed, 0, t, 0, n)
+    v = pts["w"] * O.genz_eval(2, a, u, pts["x"])
+    I = math.fsum(v) / n
+    dv = v - I
+    var = (math.fsum(dv * dv) / n - (math.fsum(dv) / n) ** 2) / (n - 1)
+    assert math.fsum(v * v) / n > 1000 * var * (n - 1)  # the cancellation is there
+    assert abs(r["iter_I"][t] - I) <= 1e-15 * abs(I)
+    assert abs(r["iter_var"][t] - var) <= 1e-14 * var
