@@ -228,7 +228,12 @@ int ccuba_init(ccuba_ctx **ctx, int device, size_t hbm_budget) {
     // measured best on gfx950: two points per lane for FP32, one for FP64
     c->tune[p].ilp = (int)env_ll("CCUBA_ILP", p == FP32 ? 2 : 1) == 2 ? 2 : 1;
   }
+  // LDS histogram: the exact fixed-point one for FP32 evaluation (faster
+  // than FP64 LDS adds); FP64 LDS adds for FP64 evaluation, where the exact
+  // one (two integer adds per bin, and order-independent, so reruns give the
+  // same bits) measured 12% slower per step; CCUBA_HIST64 sets both
   c->tune[FP32].hist64 = (int)env_ll("CCUBA_HIST64", 0);
+  c->tune[FP64].hist64 = (int)env_ll("CCUBA_HIST64", 1);
   c->use_graph = (int)env_ll("CCUBA_GRAPH", 1);
   c->autotune = (int)env_ll("CCUBA_AUTOTUNE", 0);
   c->serve_slots = (int)env_ll("CCUBA_SERVE_SLOTS", 256);
@@ -300,7 +305,7 @@ int ccuba_config(ccuba_ctx *ctx, const char *key, long long value) {
     ctx->tune[0].blocks_per_cu = ctx->tune[1].blocks_per_cu = (int)value;
   } else if (k == "hist64") {
     if (value != 0 && value != 1) return CCUBA_EINVAL;
-    ctx->tune[FP32].hist64 = (int)value;
+    ctx->tune[0].hist64 = ctx->tune[1].hist64 = (int)value;
   } else if (k == "ilp") {
     if (value != 1 && value != 2) return CCUBA_EINVAL;
     ctx->tune[0].ilp = ctx->tune[1].ilp = (int)value;
@@ -435,7 +440,9 @@ int ccuba_vegas_source(ccuba_ctx **ctxp, int ndim, const char *source, const dou
   const VegasTune &t = ctx->tune[sp.prec];
   const int nb = (ndim + 3) / 4;
   hipFunction_t fn = nullptr;
-  rc = rtc_dosample(ctx, source, sp.prec, t.hist64, t.ilp, nb, (nbins & (nbins - 1)) == 0,
+  // the histogram type the engine's tile group of this class will take
+  const int h64 = fixed_hist(sp.prec, t.hist64, (long long)ndim * nbins) ? 0 : 1;
+  rc = rtc_dosample(ctx, source, sp.prec, h64, t.ilp, nb, (nbins & (nbins - 1)) == 0,
                     ndim == 4 * nb, &fn);
   if (rc) return rc;
   // an engine of its own: the cached one's graphs hold the built-in kernels

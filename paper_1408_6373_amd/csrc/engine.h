@@ -66,6 +66,12 @@ struct VState {
   // first
   float hcap;
   int pad2;
+  // the value the next iteration's sums are taken about: its lanes sum
+  // v - shift and (v - shift)^2, and shift is the last iteration's estimate
+  // (0 before the first), so that the variance S2/n - (S1/n)^2 does not lose
+  // the digits that the plain sums of v and v^2 lose to cancellation when
+  // the variance is small against I^2
+  double shift;
 };
 
 __host__ __device__ inline int ngroups_of(int ntiles) { return (ntiles + kGroupTiles - 1) / kGroupTiles; }
@@ -77,7 +83,7 @@ enum { FLAG_FREEZE_GRID = 1 << 4 };
 struct VegasTune {
   int block = 256;        // threads per block
   int blocks_per_cu = 3;  // persistent blocks per compute unit
-  int hist64 = 0;         // FP32 path: 1 = FP64 LDS histogram, 0 = 64-bit fixed point
+  int hist64 = 0;         // 1 = FP64 LDS histogram, 0 = the exact 64-bit fixed-point one
   int ilp = 1;            // points per lane per trip (1 or 2)
   int tiles_per_job = 0;  // 0 = automatic (one tile per persistent block)
   long long min_tile = 4096;

@@ -40,7 +40,7 @@ int rtc_dosample(ccuba_ctx *ctx, const char *source, int prec, int hist64, int i
   if (!ctx->rtc) ctx->rtc = new RtcCache;
   RtcCache &cache = *ctx->rtc;
   const char *T = prec == FP64 ? "double" : "float";
-  const char *HT = prec == FP64 ? "double" : (hist64 ? "double" : "unsigned long long");
+  const char *HT = hist64 ? "double" : "unsigned long long";
   char inst[256];
   std::snprintf(inst, sizeof(inst), "ccuba::vegas_dosample_kernel<%s, %s, %d, %d, %s, %s>", T,
                 HT, ilp, nb, pow2 ? "true" : "false", full ? "true" : "false");

@@ -325,7 +325,8 @@ int Server::tick() {
     if (r->job.method == 0 && !r->vdone) table.push_back(r->hj);
   if (!table.empty()) {
     size_t refb = 0;
-    plan_tile_groups(table, tiles, groups, ctx_->tune[FP32].hist64, &refb);
+    const int h64[2] = {ctx_->tune[0].hist64, ctx_->tune[1].hist64};
+    plan_tile_groups(table, tiles, groups, h64, &refb);
     if (jobs_.n < table.size() && (rc = jobs_.alloc(ctx_, table.size() * 2))) return rc;
     if (tiles_.n < tiles.size() && (rc = tiles_.alloc(ctx_, tiles.size() * 2))) return rc;
     CCUBA_HIP(hipMemcpyAsync(jobs_.p, table.data(), table.size() * sizeof(VJob),
@@ -337,7 +338,6 @@ int Server::tick() {
     VegasArgs A{};
     A.jobs = jobs_.p;
     A.tile_job = tiles_.p;
-    A.hist64 = ctx_->tune[FP32].hist64;
     A.njobs = (int)table.size();
     if ((rc = launch_tile_groups(ctx_, A, groups, s))) return rc;
     long long ftot = 0, ftot2 = 0;

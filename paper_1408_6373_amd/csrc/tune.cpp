@@ -115,12 +115,12 @@ void maybe_autotune(ccuba_ctx *ctx, int prec) {
   for (int b : blocks)
     for (int bpc : bpcs)
       for (int ilp = 1; ilp <= 2; ++ilp)
-      for (int h = 0; h < (prec == FP32 ? 2 : 1); ++h) {
+      for (int h = 0; h < 2; ++h) {
         VegasTune c = ctx->tune[prec];
         c.block = b;
         c.blocks_per_cu = b == 128 ? 2 * bpc : bpc;
         c.ilp = ilp;
-        c.hist64 = prec == FP32 ? h : 1;
+        c.hist64 = h;
         const double ms = time_candidate(ctx, prec, c);
         if (ms < best_ms) {
           best_ms = ms;
@@ -176,12 +176,12 @@ void autotune_batch(ccuba_ctx *ctx, const std::vector<VegasSpec> &specs) {
     for (int bpc : bpcs)
       for (int ilp = 1; ilp <= 2; ++ilp)
         for (long long mt : tiles)
-          for (int h = 0; h < (prec == FP32 ? 2 : 1); ++h) {
+          for (int h = 0; h < 2; ++h) {
             VegasTune c = saved;
             c.blocks_per_cu = bpc;
             c.ilp = ilp;
             c.min_tile = mt;
-            if (prec == FP32) c.hist64 = h;
+            c.hist64 = h;
             ctx->tune[prec] = c;
             const double ms = time_batch(ctx, mine);
             if (ms < best_ms) {

@@ -15,7 +15,7 @@ struct VegasArgs {
   const int *tile_job;  // job of each tile
   int tile_first;       // the launch's slice of the tile list
   int tile_count;
-  int hist64;           // FP32 path: FP64 LDS histogram (else 64-bit fixed point)
+  int hist64;           // FP64 LDS histogram (else the exact 64-bit fixed-point one)
   int ilp;              // points per lane per trip (1 or 2)
   long long lds_hist_byte_off;
   int njobs;  // jobs in the table (1: every tile is job 0's)
@@ -55,6 +55,7 @@ struct BatchedArgs {
   const double *f;      // [npts][ncomp]
   const int *bin;       // [npts][ndim]
   double *rows;         // [tiles][2 ncomp + ndim nbins]: S1, S2 per component, H
+  const VState *state;  // [ncomp]: the shift of each component's sums
 };
 struct BatchedFinishArgs {
   int ndim, nbins, ncomp, flags;
@@ -85,12 +86,15 @@ hipError_t launch_dosample_f64(const VegasArgs &A, int nb, bool pow2, bool full,
                                int block, size_t lds, hipStream_t s);
 hipError_t launch_dosample_f32h64(const VegasArgs &A, int nb, bool pow2, bool full, int grid,
                                   int block, size_t lds, hipStream_t s);
+hipError_t launch_dosample_f64hfx(const VegasArgs &A, int nb, bool pow2, bool full, int grid,
+                                  int block, size_t lds, hipStream_t s);
 hipError_t launch_dosample_f32hfx(const VegasArgs &A, int nb, bool pow2, bool full, int grid,
                                   int block, size_t lds, hipStream_t s);
 // every DoSample instance of a translation unit (for launch attributes)
 void dosample_fns_f64(std::vector<const void *> &fns);
 void dosample_fns_f32h64(std::vector<const void *> &fns);
 void dosample_fns_f32hfx(std::vector<const void *> &fns);
+void dosample_fns_f64hfx(std::vector<const void *> &fns);
 // First fold level (tile rows -> group rows); with level2 also the second
 // (group rows -> hsum), which only the raw DoSample entry point needs.
 hipError_t launch_fold(const FoldArgs &F, bool level2, hipStream_t s);

@@ -143,13 +143,19 @@ __global__ void __launch_bounds__(256) vegas_fold2_kernel(FoldArgs F) {
 // a7, the iteration's statistics for one component: the estimate I_t and
 // variance sigma_t^2 of iteration t = st.T from its sums over n points,
 // folded into the running inverse-variance combination (sums added in
-// iteration order).  The stop rule and chi^2 are applied by finish_state.
+// iteration order).  The sums are taken about c = st.shift, S1 = sum (v - c)
+// and S2 = sum (v - c)^2, so I_t = c + S1/n and sigma_t^2 =
+// max(0, S2/n - (S1/n)^2)/(n - 1), the same quantities as from plain sums;
+// the estimate becomes the next iteration's shift.  The stop rule and chi^2
+// are applied by finish_state.
 __device__ __forceinline__ void settle_component(VState &st, double S1, double S2, long long n,
                                                  double &I, double &var) {
-  I = S1 / (double)n;
-  var = S2 / (double)n - I * I;
+  const double m = S1 / (double)n;
+  I = st.shift + m;
+  var = S2 / (double)n - m * m;
   if (var < 0.0) var = 0.0;
   var /= (double)(n - 1);
+  st.shift = I;
   const int T = st.T + 1;
   st.T = T;
   st.neval += n;
@@ -304,6 +310,7 @@ __global__ void __launch_bounds__(kRefineThreads) vegas_refine_kernel(VegasArgs 
     const long long nstart = JOB_FIELD(jw, nstart), ninc = JOB_FIELD(jw, nincrease);
     const long long n = nstart + (long long)t * ninc;
     const double S1 = s_sums[0], S2 = s_sums[1];
+    const double c = st.shift;  // the sums' shift (settle_component moves it on)
     double I, var;
     settle_component(st, S1, S2, n, I, var);
     double *hI = JOB_FIELD(jw, iter_I), *hV = JOB_FIELD(jw, iter_var);
@@ -317,7 +324,8 @@ __global__ void __launch_bounds__(kRefineThreads) vegas_refine_kernel(VegasArgs 
                         T >= JOB_FIELD(jw, hist_cap) || nnext >= (1ll << 32);
     const bool bad = !isfinite(S1) || !isfinite(S2);
     finish_state(st, bad, conv, budget, hI, hV);
-    st.hcap = (float)(1024.0 * (S2 / (double)n));
+    // the mean v^2 of the iteration, (S2 + 2 c S1)/n + c^2
+    st.hcap = (float)(1024.0 * (fma(2.0 * c, S1, S2) / (double)n + c * c));
     *JOB_FIELD(jw, state) = st;
     s_mode = conv || bad ? 0 : ((JOB_FIELD(jw, flags) & FLAG_FREEZE_GRID) ? 2 : 1);
   }
@@ -449,9 +457,12 @@ __global__ void __launch_bounds__(kAccumThreads) vegas_batched_accumulate_kernel
   const long long p1 = min(p0 + (long long)B.tile_pts, B.npts);
   for (int e = tid; e < dN; e += blockDim.x) hs[e] = 0.0;
   __syncthreads();
-  double s1[kMaxComp], s2[kMaxComp];
+  double s1[kMaxComp], s2[kMaxComp], sh[kMaxComp];
 #pragma unroll
-  for (int c = 0; c < kMaxComp; ++c) s1[c] = s2[c] = 0.0;
+  for (int c = 0; c < kMaxComp; ++c) {
+    s1[c] = s2[c] = 0.0;
+    sh[c] = c < nc ? B.state[c].shift : 0.0;  // every component's sums have their own shift
+  }
   for (long long p = p0 + tid; p < p1; p += blockDim.x) {
     const double w = B.w[p];
     double v0 = 0.0;
@@ -460,8 +471,9 @@ __global__ void __launch_bounds__(kAccumThreads) vegas_batched_accumulate_kernel
       if (c < nc) {
         const double f = B.f[p * nc + c];
         const double v = B.prec == FP32 ? (double)((float)w * (float)f) : w * f;
-        s1[c] += v;
-        s2[c] = fma(v, v, s2[c]);
+        const double dv = v - sh[c];
+        s1[c] += dv;
+        s2[c] = fma(dv, dv, s2[c]);
         if (c == 0) v0 = v;
       }
     const double v2 = v0 * v0;
@@ -561,7 +573,9 @@ __global__ void __launch_bounds__(1024) vegas_batched_finish_kernel(BatchedFinis
 hipError_t launch_dosample(const VegasArgs &A, int prec, int nb, bool pow2, bool full,
                            int grid, int block, size_t lds, hipStream_t s) {
   if (A.tile_count <= 0 || grid <= 0) return hipSuccess;
-  if (prec == FP64) return launch_dosample_f64(A, nb, pow2, full, grid, block, lds, s);
+  if (prec == FP64)
+    return A.hist64 ? launch_dosample_f64(A, nb, pow2, full, grid, block, lds, s)
+                    : launch_dosample_f64hfx(A, nb, pow2, full, grid, block, lds, s);
   if (A.hist64) return launch_dosample_f32h64(A, nb, pow2, full, grid, block, lds, s);
   return launch_dosample_f32hfx(A, nb, pow2, full, grid, block, lds, s);
 }
@@ -629,7 +643,7 @@ hipError_t launch_batched_finish(const BatchedFinishArgs &F, hipStream_t s) {
 }
 
 hipError_t set_kernel_limits() {
-  // allow the large-grid cases (d = 16, 256 bins: up to 96 KB of cells and
+  // allow the large-grid cases (d = 16, 256 bins: up to 128 KB of cells and
   // histogram) the LDS gfx950 has; a runtime that refuses keeps its default
   // limit and such launches report an error instead of running
   const int big = 160 * 1024;
@@ -640,6 +654,7 @@ hipError_t set_kernel_limits() {
   dosample_fns_f64(fns);
   dosample_fns_f32h64(fns);
   dosample_fns_f32hfx(fns);
+  dosample_fns_f64hfx(fns);
   for (const void *f : fns)
     if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, big) != hipSuccess)
       (void)hipGetLastError();

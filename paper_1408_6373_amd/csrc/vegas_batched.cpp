@@ -131,7 +131,8 @@ int vegas_batched(ccuba_ctx *ctx, const BatchedSpec &sp, ccuba_batch_integrand f
       }
       if (host)
         CCUBA_HIP(hipMemcpyAsync(f.p, fh.p, m * nc * sizeof(double), hipMemcpyHostToDevice, s));
-      BatchedArgs ba{d, N, nc, sp.prec, m, kBatchedTile, tiles, w.p, f.p, bin.p, rows.p};
+      BatchedArgs ba{d, N, nc, sp.prec, m, kBatchedTile, tiles, w.p, f.p, bin.p, rows.p,
+                     states.p};
       CCUBA_HIP(launch_batched_accumulate(ba, s));
       tiles += (int)ceil_div(m, kBatchedTile);
     }

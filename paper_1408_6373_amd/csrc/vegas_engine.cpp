@@ -98,34 +98,47 @@ void genz_constants(const VegasSpec &s, double p64[2][kParamRow], float p32[2][k
   }
 }
 
+bool fixed_hist(int prec, int hist64, long long dN) {
+  // the DoSample kernel's static LDS (block sums, per-dimension maxima) is
+  // well below the 1 KB left for it
+  constexpr long long kLds = 160 * 1024 - 1024;
+  return !hist64 && (prec == FP32 || dN * (16 + 3 * 8) <= kLds);
+}
+
 void plan_tile_groups(std::vector<VJob> &jobs, std::vector<int> &tiles,
-                      std::vector<TileGroup> &groups, int hist64, size_t *refine_lds) {
+                      std::vector<TileGroup> &groups, const int hist64[2], size_t *refine_lds) {
   tiles.clear();
   groups.clear();
   size_t ref = 0;
   // one class per (precision, Philox blocks, power-of-two bins, d = 4 nb)
   for (int cls = 0; cls < 32; ++cls) {
     const int p = cls >> 4, nb = ((cls >> 2) & 3) + 1, pw = (cls >> 1) & 1, full = cls & 1;
-    TileGroup g{p, nb, pw, full, (int)tiles.size(), 0, 0, 0};
-    size_t hb = 0;
+    TileGroup g{p, nb, pw, full, (int)tiles.size(), 0, 0, 0, 0};
+    auto mine = [&](const VJob &J) {
+      const int jp = (J.nbins & (J.nbins - 1)) == 0, jf = J.ndim == 4 * nb;
+      return J.prec == p && ((J.ndim + 3) >> 2) == nb && jp == pw && jf == full;
+    };
+    long long dNmax = 0;
+    for (const VJob &J : jobs)
+      if (mine(J)) dNmax = std::max(dNmax, (long long)J.ndim * J.nbins);
+    g.hfx = fixed_hist(p, hist64[p], dNmax) ? 1 : 0;
     for (int j = 0; j < (int)jobs.size(); ++j) {
       VJob &J = jobs[j];
-      const int jp = (J.nbins & (J.nbins - 1)) == 0, jf = J.ndim == 4 * nb;
-      if (J.prec != p || ((J.ndim + 3) >> 2) != nb || jp != pw || jf != full) continue;
+      if (!mine(J)) continue;
       J.tile0 = (int)tiles.size();
       for (int q = 0; q < J.ntiles; ++q) tiles.push_back(j);
       const size_t dN = (size_t)J.ndim * J.nbins;
-      // LDS: one (lower edge, span) cell per bin, then the histogram
-      // (the fixed-point histogram has an FP64 one beside it for the values
-      // above its cap)
-      const size_t csz = p == FP64 ? 16 : 8, hsz = (p == FP32 && !hist64) ? 16 : 8;
-      g.grid_bytes = std::max(g.grid_bytes, align16(dN * csz));
-      hb = std::max(hb, dN * hsz);
       // refine: histogram, smoothed histogram and the current grid
       ref = std::max(ref, (2 * dN + (size_t)J.ndim * (J.nbins + 1)) * 8);
     }
+    // LDS: one (lower edge, span) cell per bin, then the histogram (the
+    // fixed-point one holds one integer sum per bin, two with FP64
+    // evaluation, and an FP64 histogram beside them for the other values)
+    const size_t csz = p == FP64 ? 16 : 8;
+    const size_t hsz = !g.hfx ? 8 : (p == FP64 ? 24 : 16);
+    g.grid_bytes = align16((size_t)dNmax * csz);
     g.count = (int)tiles.size() - g.first;
-    g.lds = g.grid_bytes + hb;
+    g.lds = g.grid_bytes + (size_t)dNmax * hsz;
     if (g.count > 0) groups.push_back(g);
   }
   *refine_lds = ref;
@@ -137,6 +150,7 @@ int launch_tile_groups(ccuba_ctx *ctx, VegasArgs A, const std::vector<TileGroup>
     A.tile_first = g.first;
     A.tile_count = g.count;
     A.ilp = ctx->tune[g.prec].ilp;
+    A.hist64 = g.hfx ? 0 : 1;
     A.lds_hist_byte_off = (long long)g.grid_bytes;
     const long long B = (long long)ctx->ncu * ctx->tune[g.prec].blocks_per_cu;
     const int grid = (int)std::min<long long>(B, g.count);
@@ -181,8 +195,8 @@ int VegasEngine::setup(const std::vector<VegasSpec> &specs, bool single, hipStre
     if (chk.family == USER && user_fn_ && specs.size() == 1) chk.family = GAUSSIAN;
     if (validate_vegas(chk) != CCUBA_OK) return CCUBA_EINVAL;
   }
-  hist64_ = ctx_->tune[FP32].hist64;
   for (int p = 0; p < 2; ++p) {
+    hist64_[p] = ctx_->tune[p].hist64;
     block_[p] = ctx_->tune[p].block;
     has_prec_[p] = 0;
   }
@@ -318,7 +332,7 @@ int VegasEngine::setup(const std::vector<VegasSpec> &specs, bool single, hipStre
   args_.tile_job = tile_job_.p;
   args_.tile_first = 0;
   args_.tile_count = ntiles_;
-  args_.hist64 = hist64_;
+  args_.hist64 = 0;  // set per tile group at launch
   args_.njobs = n;
   pending_.clear();
   iter_launched_ = 0;
@@ -328,14 +342,14 @@ int VegasEngine::setup(const std::vector<VegasSpec> &specs, bool single, hipStre
                                 (long long)(intptr_t)tile_job_.p,
                                 (long long)(intptr_t)fold_end_.p, (long long)(intptr_t)user_fn_,
                                 fold_total_, fold_total2_,
-                                n, ntiles_, (long long)lds_refine_, hist64_};
+                                n, ntiles_, (long long)lds_refine_, hist64_[0], hist64_[1]};
   for (int p = 0; p < 2; ++p) {
     const VegasTune &t = ctx_->tune[p];
     sig.insert(sig.end(), {t.block, t.blocks_per_cu, t.ilp, t.hist64, ctx_->ncu});
   }
   for (const TileGroup &g : tgroups_)
     sig.insert(sig.end(), {g.prec, g.nb, g.pow2, g.full, g.first, g.count,
-                           (long long)g.grid_bytes, (long long)g.lds});
+                           (long long)g.grid_bytes, (long long)g.lds, g.hfx});
   if (sig != graph_sig_) {
     for (auto &g : graphs_) (void)hipGraphExecDestroy(g.exec);
     graphs_.clear();

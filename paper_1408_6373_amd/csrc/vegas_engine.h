@@ -37,12 +37,18 @@ void genz_constants(const VegasSpec &s, double p64[2][kParamRow], float p32[2][k
 struct TileGroup {
   int prec, nb, pow2, full, first, count;
   size_t grid_bytes, lds;
+  int hfx;  // 1: the fixed-point LDS histogram instance
 };
+
+// Whether the DoSample launch of a class takes the fixed-point LDS histogram:
+// unless hist64 asks for the FP64 one, or (FP64 evaluation: 16-byte cells and
+// three histogram words per bin) the class's largest d N would not fit the LDS.
+bool fixed_hist(int prec, int hist64, long long dN);
 
 // Order the tiles of `jobs' by class, set each job's tile0 to the position of
 // its first tile, and describe the classes.  Also returns the refine LDS.
 void plan_tile_groups(std::vector<VJob> &jobs, std::vector<int> &tiles,
-                      std::vector<TileGroup> &groups, int hist64, size_t *refine_lds);
+                      std::vector<TileGroup> &groups, const int hist64[2], size_t *refine_lds);
 // One DoSample launch per class; `user' (if given) is the run-time compiled
 // kernel of the one class of a caller's device integrand.
 int launch_tile_groups(ccuba_ctx *ctx, VegasArgs A, const std::vector<TileGroup> &groups,
@@ -128,7 +134,7 @@ class VegasEngine {
   int has_prec_[2] = {0, 0};
   int nblocks_[2] = {0, 0}, block_[2] = {256, 256};
   size_t lds_refine_ = 0;
-  int hist64_ = 0;
+  int hist64_[2] = {0, 0};  // per precision: the FP64 LDS histogram asked for
   hipFunction_t user_fn_ = nullptr;
   int max_iters_ = 0;
   long long evals_iter_ = 0;

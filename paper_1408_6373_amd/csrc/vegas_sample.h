@@ -216,7 +216,7 @@ __device__ __forceinline__ double pow2_scale<double>(int L) {
 }
 
 // ---------------------------------------------------------------------------
-// a6 with FP32 evaluation: the histogram in 64-bit fixed point, exactly.
+// a6: the histogram in 64-bit fixed point, exactly.
 //
 // LDS integer adds are several times cheaper than FP64 adds on gfx950 (and
 // FP32 LDS atomics far slower still).  With FP32 evaluation every v^2 has a
@@ -239,6 +239,14 @@ __device__ __forceinline__ double pow2_scale<double>(int L) {
 // occur (it takes every dimension's widest bin), so later iterations take
 // c = 1024 times the mean v^2 of the previous one (at most 1 in 1024 of the
 // v^2 exceed that).
+//
+// With FP64 evaluation v^2 has a 53-bit mantissa M, v^2 = M 2^(e - 1075) for
+// the biased exponent e.  In units U = 2^(E - 91) it is the integer
+// X = M 2^s, s = e - 984 - E, whenever s >= 0, and X < 2^90: its low 32 bits
+// and X >> 32 go to two 64-bit sums (below 2^46 and 2^57 for a tile of any
+// size), so the FP64 histogram too is exact and does not depend on the order
+// of the adds, for two integer LDS adds that cost about what one FP64 LDS
+// add does.  Every other v^2 goes to the FP64 histogram beside them.
 
 template <typename HT>
 struct FixedHist {
@@ -249,7 +257,8 @@ struct FixedHist<unsigned long long> {
   static constexpr bool value = true;
 };
 
-// Sample the points [i0, i0 + cnt) of one tile; lane sums go to S1, S2.
+// Sample the points [i0, i0 + cnt) of one tile; lane sums of v - shift and
+// (v - shift)^2 go to S1, S2.
 // NB = ceil(d/4) Philox blocks per point is a template argument so that the
 // per-dimension loop is fully unrolled with only the last block guarded, and
 // FULL (d = 4 NB) drops that guard too.
@@ -264,7 +273,7 @@ template <typename T, typename HT, int FAM, int NB, int ILP, bool POW2, bool FUL
 __device__ __forceinline__ void sample_tile(const VJob &J, int t, long long i0, int cnt,
                                             const Cell<T> *__restrict__ sC, HT *sH,
                                             const T (&pp0)[4 * NB], const T (&pp1)[4 * NB],
-                                            int E, float cap,
+                                            int E, float cap, double shift,
                                             double *sHx, double &S1, double &S2) {
   constexpr int ND = 4 * NB;
   const int d = J.ndim, N = J.nbins;
@@ -339,19 +348,41 @@ __device__ __forceinline__ void sample_tile(const VJob &J, int t, long long i0, 
       const T v = w * Genz<T, FAM>::finish(acc, d);
 #endif
       if (q0 + e * bs < cnt) {
-        S1 += (double)v;
-        S2 = fma((double)v, (double)v, S2);
-        if constexpr (FixedHist<HT>::value) {
+        const double dv = (double)v - shift;
+        S1 += dv;
+        S2 = fma(dv, dv, S2);
+        if constexpr (FixedHist<HT>::value && sizeof(T) == 8) {
+          const double v2 = v * v;
+          const unsigned long long b = (unsigned long long)__double_as_longlong(v2);
+          const int eb = (int)(b >> 52);
+          const int s = eb - (984 + E);  // v2 = M 2^s units; s <= 37 below the cap
+          if (v2 <= (double)cap && s >= 0 && eb >= 1) {
+            const unsigned long long M = (b & 0xFFFFFFFFFFFFFull) | (1ull << 52);
+            const unsigned long long xlo = (M << s) & 0xFFFFFFFFull;
+            const unsigned long long xhi = (M << 11) >> (43 - s);  // floor(M 2^(s-32))
+            HT *sHh = sH + d * N;
+#pragma unroll
+            for (int j = 0; j < ND; ++j)
+              if (FULL || j < 4 * (NB - 1) || j < d) {
+                atomicAdd(&sH[idx[e][j]], xlo);
+                atomicAdd(&sHh[idx[e][j]], xhi);
+              }
+          } else {  // not a normal whole multiple of the unit, above the cap, or not finite
+#pragma unroll
+            for (int j = 0; j < ND; ++j)
+              if (FULL || j < 4 * (NB - 1) || j < d) unsafeAtomicAdd(&sHx[idx[e][j]], v2);
+          }
+        } else if constexpr (FixedHist<HT>::value) {
           const float v2f = (float)(v * v);
           const uint32_t b = __float_as_uint(v2f);
           const int sh = (int)(b >> 23) - (88 + E);  // v2 = m 2^sh units
-          if (v2f <= cap && sh >= 0) {
+          if (v2f <= cap && sh >= 0 && b >= 0x800000u) {  // (zeros and subnormals: below)
             const unsigned long long v2 = (unsigned long long)((b & 0x7FFFFFu) | 0x800000u)
                                           << sh;
 #pragma unroll
             for (int j = 0; j < ND; ++j)
               if (FULL || j < 4 * (NB - 1) || j < d) atomicAdd(&sH[idx[e][j]], v2);
-          } else {  // not a whole multiple of the unit, above the cap, or not finite
+          } else {  // not a normal whole multiple of the unit, above the cap, or not finite
             const double v2 = (double)v2f;
 #pragma unroll
             for (int j = 0; j < ND; ++j)
@@ -420,8 +451,11 @@ __global__ void __launch_bounds__(256) vegas_dosample_kernel(VegasArgs A) {
     c = c < 0 ? 0 : (c > J.tile_pts ? J.tile_pts : c);
     const int cnt = (int)c;
 
-    for (int e = tid; e < dN; e += bs) sH[e] = (HT)0;
-    double *sHx = (double *)(sH + dN);  // fixed point: the FP64 histogram above the cap
+    // fixed point: the integer sums (two per bin with FP64 evaluation), then
+    // the FP64 histogram of the rest
+    constexpr int kFixWords = (FixedHist<HT>::value && sizeof(T) == 8) ? 2 : 1;
+    for (int e = tid; e < kFixWords * dN; e += bs) sH[e] = (HT)0;
+    double *sHx = (double *)(sH + kFixWords * dN);
     if constexpr (FixedHist<HT>::value) {
       for (int e = tid; e < dN; e += bs) sHx[e] = 0.0;
       if (tid <= kMaxDim) smax[tid] = 0u;
@@ -456,6 +490,9 @@ __global__ void __launch_bounds__(256) vegas_dosample_kernel(VegasArgs A) {
           const float v = w * q;
           cv = v * v;
         }
+        // a cap that is not finite or too large for the sums' exponent range
+        // (an integrand far above 1) sends every value to the FP64 histogram
+        if (!(cv <= 0x1p100f)) cv = 0.0f;
         // 2^E >= 4 cnt c bounds the fixed-point total of every bin
         const double B = 4.0 * (double)cv * (double)(cnt > 0 ? cnt : 1);
         int ex = 0;
@@ -469,14 +506,14 @@ __global__ void __launch_bounds__(256) vegas_dosample_kernel(VegasArgs A) {
     }
     double S1 = 0.0, S2 = 0.0;
 #ifdef CCUBA_RTC
-    sample_tile<T, HT, USER, NB, ILP, POW2, FULL>(J, st.T, i0, cnt, sC, sH, pp0, pp1, E, cap, sHx, S1, S2);
+    sample_tile<T, HT, USER, NB, ILP, POW2, FULL>(J, st.T, i0, cnt, sC, sH, pp0, pp1, E, cap, st.shift, sHx, S1, S2);
 #else
     switch (J.family) {
-      case GAUSSIAN: sample_tile<T, HT, GAUSSIAN, NB, ILP, POW2, FULL>(J, st.T, i0, cnt, sC, sH, pp0, pp1, E, cap, sHx, S1, S2); break;
-      case OSCILLATORY: sample_tile<T, HT, OSCILLATORY, NB, ILP, POW2, FULL>(J, st.T, i0, cnt, sC, sH, pp0, pp1, E, cap, sHx, S1, S2); break;
-      case PRODUCT_PEAK: sample_tile<T, HT, PRODUCT_PEAK, NB, ILP, POW2, FULL>(J, st.T, i0, cnt, sC, sH, pp0, pp1, E, cap, sHx, S1, S2); break;
-      case CORNER_PEAK: sample_tile<T, HT, CORNER_PEAK, NB, ILP, POW2, FULL>(J, st.T, i0, cnt, sC, sH, pp0, pp1, E, cap, sHx, S1, S2); break;
-      default: sample_tile<T, HT, C0, NB, ILP, POW2, FULL>(J, st.T, i0, cnt, sC, sH, pp0, pp1, E, cap, sHx, S1, S2); break;
+      case GAUSSIAN: sample_tile<T, HT, GAUSSIAN, NB, ILP, POW2, FULL>(J, st.T, i0, cnt, sC, sH, pp0, pp1, E, cap, st.shift, sHx, S1, S2); break;
+      case OSCILLATORY: sample_tile<T, HT, OSCILLATORY, NB, ILP, POW2, FULL>(J, st.T, i0, cnt, sC, sH, pp0, pp1, E, cap, st.shift, sHx, S1, S2); break;
+      case PRODUCT_PEAK: sample_tile<T, HT, PRODUCT_PEAK, NB, ILP, POW2, FULL>(J, st.T, i0, cnt, sC, sH, pp0, pp1, E, cap, st.shift, sHx, S1, S2); break;
+      case CORNER_PEAK: sample_tile<T, HT, CORNER_PEAK, NB, ILP, POW2, FULL>(J, st.T, i0, cnt, sC, sH, pp0, pp1, E, cap, st.shift, sHx, S1, S2); break;
+      default: sample_tile<T, HT, C0, NB, ILP, POW2, FULL>(J, st.T, i0, cnt, sC, sH, pp0, pp1, E, cap, st.shift, sHx, S1, S2); break;
     }
 #endif
     S1 = wave_sum(S1);
@@ -496,7 +533,10 @@ __global__ void __launch_bounds__(256) vegas_dosample_kernel(VegasArgs A) {
       J.tsums[2 * lt + 1] = b;
     }
     double *th = J.thist + (long long)lt * dN;
-    if constexpr (FixedHist<HT>::value) {
+    if constexpr (FixedHist<HT>::value && sizeof(T) == 8) {
+      for (int e = tid; e < dN; e += bs)
+        th[e] = ldexp((double)sH[dN + e], E - 59) + ldexp((double)sH[e], E - 91) + sHx[e];
+    } else if constexpr (FixedHist<HT>::value) {
       for (int e = tid; e < dN; e += bs) th[e] = ldexp((double)sH[e], E - 62) + sHx[e];
     } else {
       for (int e = tid; e < dN; e += bs) th[e] = (double)sH[e];

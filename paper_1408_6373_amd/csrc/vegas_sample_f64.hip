@@ -1,4 +1,6 @@
-// vegas_sample_f64.hip -- DoSample instances with FP64 evaluation, FP64 LDS histogram.
+// vegas_sample_f64.hip -- DoSample instances with FP64 evaluation, FP64 LDS histogram
+// (the grids whose fixed-point histogram would not fit the LDS, and the
+// hist64 setting).
 #include "vegas_sample.h"
 
 namespace ccuba {

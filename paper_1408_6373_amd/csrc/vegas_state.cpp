@@ -34,7 +34,7 @@ Header header_of(const VegasSpec &sp, int T) {
   Header h;
   std::memset(&h, 0, sizeof(h));
   std::memcpy(h.magic, kMagic, sizeof(kMagic));
-  h.version = 1;
+  h.version = 2;  // 2: the state holds the shift of the sums
   h.state_bytes = (int)sizeof(VState);
   h.ndim = sp.ndim;
   h.nbins = sp.nbins;

@@ -56,7 +56,7 @@ def test_batch_equals_alone(cc, ctx):
         a = _alone(cc, ctx, s)
         assert r["status"] == 0 and r["neval"] == a["neval"] and r["fail"] == a["fail"]
         assert _rel(r["integral"], a["integral"]) < 1e-12
-        assert _rel(r["error"], a["error"]) < 1e-11
+        assert _rel(r["error"], a["error"]) < 1e-12
 
 
 def test_batch_with_convergence_drops_jobs(cc, ctx):
@@ -80,7 +80,7 @@ def test_batch_matches_oracle(cc, ctx):
                     nstart=s["nstart"], maxeval=s["maxeval"], nbins=128)
         tol = 1e-12 if s["flags"] == 0 else 1e-6
         assert _rel(r["integral"], o["integral"]) < tol
-        assert _rel(r["error"], o["error"]) < (1e-11 if s["flags"] == 0 else 1e-5)
+        assert _rel(r["error"], o["error"]) < (1e-12 if s["flags"] == 0 else 1e-5)
 
 
 def test_invalid_job_gets_its_own_status(cc, ctx):
@@ -133,5 +133,5 @@ def test_autotuned_batch_equals_default(cc):
     for r, b in zip(tuned, base):
         assert r["status"] == 0 and r["neval"] == b["neval"]
         assert _rel(r["integral"], b["integral"]) < 1e-12
-        assert _rel(r["error"], b["error"]) < 1e-11
+        assert _rel(r["error"], b["error"]) < 1e-12
 

@@ -4,8 +4,10 @@ DoSample kernel (ccuba_vegas_source).
 Bars: a source that computes a built-in Genz family with the same operations
 gives that family's results (1e-13 relative: the runs differ only in the
 order of FP64 histogram additions); any other source agrees with the oracle
-calling the same function in Python within 1e-12 (FP64) or 1e-5 (FP32
-evaluation against the FP64 oracle); a bad source is refused with the
+calling the same function in Python within 1e-12 (FP64), or, with FP32
+evaluation, the oracle's FP32 emulation of the family within 1e-6 (integral)
+and 1e-5 (error: the two evaluate it in binary32 with different roundings,
+which the error estimate is sensitive to); a bad source is refused with the
 compiler's message.
 """
 import numpy as np
@@ -79,7 +81,7 @@ def test_source_gaussian_equals_builtin_family(cc, ctx, d, N):
     b = cc.vegas(W.GAUSSIAN, a, u, **kw)
     assert s["neval"] == b["neval"] and s["fail"] == b["fail"]
     assert _rel(s["integral"], b["integral"]) < 1e-13
-    assert _rel(s["error"], b["error"]) < 1e-11
+    assert _rel(s["error"], b["error"]) < 1e-12
     assert abs(s["prob"] - b["prob"]) < 1e-11
 
 
@@ -92,7 +94,7 @@ def test_source_matches_oracle(cc, ctx):
     o = O.vegas(O.python_integrand(_odd_py(a, u)), d, **kw)
     assert g["neval"] == o["neval"] and g["fail"] == o["fail"]
     assert _rel(g["integral"], o["integral"]) < 1e-12
-    assert _rel(g["error"], o["error"]) < 1e-11
+    assert _rel(g["error"], o["error"]) < 1e-12
 
 
 def test_source_fp32_evaluation(cc, ctx):
@@ -100,9 +102,10 @@ def test_source_fp32_evaluation(cc, ctx):
     a, u = W.genz_params(W.GAUSSIAN, d, 2)
     kw = dict(nbins=128, nstart=100003, maxeval=4 * 100003, seed=8)
     g = cc.vegas_source(GAUSS_SRC, d, a, u, ctx=ctx, flags=cc.FP32_EVAL, **kw)
-    o = O.vegas(O.genz(W.GAUSSIAN, a, u), d, **kw)
+    o = O.vegas(O.genz(W.GAUSSIAN, a, u, precision=O.FP32_EVAL), d, flags=O.FP32_EVAL, **kw)
     assert g["neval"] == o["neval"]
-    assert _rel(g["integral"], o["integral"]) < 1e-5
+    assert _rel(g["integral"], o["integral"]) < 1e-6
+    assert _rel(g["error"], o["error"]) < 1e-5
 
 
 def test_source_converges(cc, ctx):

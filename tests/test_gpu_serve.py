@@ -54,7 +54,7 @@ def _check(cc, ctx, specs, results):
         if s["method"] == 1:
             assert r["nregions"] == a["nregions"]
         assert _rel(r["integral"], a["integral"]) < 1e-12
-        assert _rel(r["error"], a["error"]) < 1e-10
+        assert _rel(r["error"], a["error"]) < 1e-12
 
 
 def test_mixed_requests_equal_alone(cc):

@@ -3,8 +3,9 @@
 Bars: Philox words and bins bit-exact; FP64 points, weights and (for equal
 inputs) refined grids bit-exact or within a few ulps; FP64 integral, error,
 chi^2 probability and iteration history within 1e-12 relative; the
-FP32-evaluate path within 1e-6 relative of the oracle's FP32 emulation and
-of its FP64 result.
+FP32-evaluate path's integral within 1e-6 relative of the oracle's FP32
+emulation and of its FP64 result, its error estimate within 1e-5 (the
+FP32 path's definition fixes it only to a few 1e-6: test_oracle_conditioning).
 """
 import numpy as np
 import pytest
@@ -124,7 +125,7 @@ def test_families_fp32_eval(cc, fam, hist64):
     o64 = O.vegas(O.genz(fam, a, u), d, nbins=128, nstart=30000, maxeval=6 * 30000, seed=3)
     assert g["neval"] == o32["neval"]
     assert _rel(g["integral"], o32["integral"]) < 1e-6
-    assert _rel(g["error"], o32["error"]) < 1e-5
+    assert _rel(g["error"], o32["error"]) < 1e-5  # see test_oracle_conditioning
     assert _rel(g["integral"], o64["integral"]) < 1e-6
 
 
@@ -135,7 +136,7 @@ def test_ragged_and_degenerate_sizes(cc, ctx):
         g = cc.vegas(2, a, u, ctx=ctx, nstart=nstart, nincrease=ninc, maxeval=maxev, nbins=16,
                      trace=True)
         o = O.vegas(O.genz(2, a, u), 3, nstart=nstart, nincrease=ninc, maxeval=maxev, nbins=16)
-        _assert_vegas_close(g, o, 1e-12, 1e-10)
+        _assert_vegas_close(g, o, 1e-12)
     # maxeval below nstart: no iteration at all
     g = cc.vegas(2, a, u, ctx=ctx, nstart=1000, maxeval=999)
     assert g["fail"] == 1 and g["neval"] == 0 and g["integral"] == 0.0
@@ -153,7 +154,7 @@ def test_extreme_dims_and_bins(cc, ctx, d, N, prec):
     o = O.vegas(O.genz(2, a, u, precision=prec), d, flags=prec, nbins=N, nstart=n,
                 maxeval=4 * n, seed=9)
     if prec == 0:
-        _assert_vegas_close(g, o, 1e-12, 1e-11)
+        _assert_vegas_close(g, o, 1e-12)
         assert np.max(np.abs(g["grid"] - o["grid"])) < 1e-12
     else:
         assert g["neval"] == o["neval"]
@@ -161,24 +162,54 @@ def test_extreme_dims_and_bins(cc, ctx, d, N, prec):
         assert _rel(g["error"], o["error"]) < 1e-5
 
 
-@pytest.mark.parametrize("fam,d,N", [(0, 5, 128), (2, 8, 128), (1, 12, 50), (4, 3, 256)])
-def test_fixed_point_histogram_equals_fp64_histogram(cc, fam, d, N):
+@pytest.mark.parametrize("prec", [1, 0], ids=["fp32_eval", "fp64"])
+@pytest.mark.parametrize("fam,d,N", [(0, 5, 128), (2, 8, 128), (1, 12, 50), (4, 3, 256),
+                                     (2, 16, 256)])
+def test_fixed_point_histogram_equals_fp64_histogram(cc, fam, d, N, prec):
     # The fixed-point histogram sums exactly what it holds and sends every
-    # other v^2 to an FP64 histogram, so the two FP32-path histograms differ
-    # by summation order only: the runs agree to FP64 rounding.
+    # other v^2 to an FP64 histogram, so the two histograms of either
+    # precision differ by summation order only: the runs agree to FP64
+    # rounding.  (d = 16 with 256 bins in FP64 takes the FP64 histogram in
+    # both runs: its fixed-point one would not fit the LDS.)
     a, u = W.genz_params(fam, d, 6)
     out = []
     for h in (1, 0):
         c = cc.Context()
         c.config("hist64", h)
-        out.append(cc.vegas(fam, a, u, ctx=c, flags=cc.FP32_EVAL, nbins=N, nstart=50021,
+        out.append(cc.vegas(fam, a, u, ctx=c, flags=prec, nbins=N, nstart=50021,
                             maxeval=8 * 50021, seed=5, trace=True))
         c.close()
     r64, rfx = out
     assert rfx["neval"] == r64["neval"]
     assert _rel(rfx["integral"], r64["integral"]) < 1e-12
-    assert _rel(rfx["error"], r64["error"]) < 1e-11
+    assert _rel(rfx["error"], r64["error"]) < 1e-12
     assert np.max(np.abs(rfx["grid"] - r64["grid"])) < 1e-12
+
+
+@pytest.mark.parametrize("prec", [1, 0], ids=["fp32_eval", "fp64"])
+def test_rerun_is_bit_identical(cc, prec):
+    # With every v^2 inside the fixed-point window (a flat product peak, whose
+    # v^2 stay within a factor 2^23 of each other) the histogram is an
+    # integer sum, independent of the order of the LDS adds, and every other
+    # sum is taken in a fixed order: two runs give the same bits.  Each run
+    # has its own context (and so its own buffers and graphs).  (FP64
+    # evaluation takes the fixed-point histogram when asked: by default it
+    # adds in FP64.)
+    d = 6
+    a, u = np.full(d, 0.5), W.genz_params(2, d, 3)[1]
+    out = []
+    for _ in range(2):
+        c = cc.Context()
+        c.config("hist64", 0)
+        out.append(cc.vegas(2, a, u, ctx=c, flags=prec, nbins=128, nstart=300007,
+                            maxeval=6 * 300007, seed=9, trace=True))
+        c.close()
+    r0, r1 = out
+    for k in ("integral", "error", "prob", "neval", "chi2"):
+        assert r0[k] == r1[k], k
+    assert np.array_equal(r0["iter_I"], r1["iter_I"])
+    assert np.array_equal(r0["iter_var"], r1["iter_var"])
+    assert np.array_equal(r0["grid"], r1["grid"])
 
 
 def test_zero_variance_frozen_grid(cc, ctx):
@@ -197,20 +228,24 @@ def test_epsrel_convergence_matches_oracle(cc, ctx):
     _assert_vegas_close(g, o, 1e-12)
 
 
-def test_geometry_invariance(cc):
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32_eval"])
+def test_geometry_invariance(cc, prec):
+    # block size, blocks per CU and points per lane per trip (ILP) change the
+    # tiles and the order of the sums, not the points
     a, u = W.genz_params(1, 8, 3)
     base = None
-    for block, bpc in ((256, 4), (128, 2), (64, 8), (256, 1)):
+    for block, bpc, ilp in ((256, 4, 1), (128, 2, 2), (64, 8, 1), (256, 1, 2), (256, 3, 2)):
         c = cc.Context()
         c.config("block", block)
         c.config("blocks_per_cu", bpc)
-        r = cc.vegas(1, a, u, ctx=c, nstart=200003, maxeval=3 * 200003)
+        c.config("ilp", ilp)
+        r = cc.vegas(1, a, u, ctx=c, flags=prec, nstart=200003, maxeval=3 * 200003)
         c.close()
         if base is None:
             base = r
         else:
             assert _rel(r["integral"], base["integral"]) < 1e-13
-            assert _rel(r["error"], base["error"]) < 1e-11
+            assert _rel(r["error"], base["error"]) < 1e-12
 
 
 def test_spin_semantics(cc):
@@ -253,7 +288,7 @@ def test_full_size_first_iteration_fp64(cc, ctx):
     g = cc.vegas(1, a, u, ctx=ctx, nbins=128, nstart=n, maxeval=n, seed=1, trace=True)
     o = O.vegas(O.genz(1, a, u), 8, nbins=128, nstart=n, maxeval=n, seed=1)
     assert _rel(g["iter_I"][0], o["iter_I"][0]) < 1e-12
-    assert _rel(g["iter_var"][0], o["iter_var"][0]) < 1e-11
+    assert _rel(g["iter_var"][0], o["iter_var"][0]) < 1e-12
     assert np.max(np.abs(g["grid"] - o["grid"])) < 1e-12
 
 
