@@ -420,6 +420,26 @@ int ccuba_vegas_dosample_raw(ccuba_ctx *ctx, int ndim, int nbins,
                              int iteration, long long npts, const double *grid_dev,
                              double *sums_dev, double *hist_dev, void *hip_stream);
 
+/* ccuba_vegas_dosample_raw for callers that cannot allocate: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation.  The
+ * same pass, arguments and outputs, but it calls no hipMalloc, hipFree or
+ * other allocating routine and does not synchronise: the descriptors and the
+ * partial sums (one row of 2 + ndim*nbins doubles per tile and per group of
+ * 32 tiles) live in a 16 MiB device array that the library holds on every
+ * GPU it runs on until the process ends, found at ccuba_init.  Tiles are
+ * those of ccuba_vegas_dosample_raw, or fewer and larger when their rows
+ * would not fit the array; a call that would need more (fewer than one tile
+ * per compute unit) returns CCUBA_ENOMEM and launches nothing.  Every call on
+ * a GPU uses that GPU's one array, which keeps the last call's contents, so
+ * calls that overlap on one GPU (other streams, other contexts, other host
+ * threads) race: serialise them, e.g. on one stream.  Errors: CCUBA_EINVAL,
+ * CCUBA_EHIP, CCUBA_ENOMEM. */
+int ccuba_vegas_dosample_raw_noalloc(ccuba_ctx *ctx, int ndim, int nbins,
+                                     const ccuba_integrand *f, int flags,
+                                     unsigned long long seed, unsigned int stream_id,
+                                     int iteration, long long npts, const double *grid_dev,
+                                     double *sums_dev, double *hist_dev, void *hip_stream);
+
 /* The points DoSample draws (steps: Philox words, uniform, grid map, weight)
  * for points [i0, i0+npts) of iteration `iteration' on the host grid
  * grid[ndim*(nbins+1)], computed on the device by the same code.  Outputs

@@ -82,10 +82,10 @@ _sig("ccuba_vegas_points", C.c_int, [_CTXP, C.c_int, C.c_int, C.c_int, C.c_ulong
                                      C.c_int, _dp, C.c_longlong, C.c_longlong,
                                      C.POINTER(C.c_uint32), _dp, _dp, _ip])
 _sig("ccuba_vegas_refine", C.c_int, [_CTXP, C.c_int, C.c_int, _dp, _dp, _dp])
-_sig("ccuba_vegas_dosample_raw", C.c_int, [_CTXP, C.c_int, C.c_int, C.POINTER(Integrand),
-                                           C.c_int, C.c_ulonglong, C.c_uint, C.c_int,
-                                           C.c_longlong, C.c_void_p, C.c_void_p, C.c_void_p,
-                                           C.c_void_p])
+_RAW_ARGS = [_CTXP, C.c_int, C.c_int, C.POINTER(Integrand), C.c_int, C.c_ulonglong, C.c_uint,
+             C.c_int, C.c_longlong, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+_sig("ccuba_vegas_dosample_raw", C.c_int, _RAW_ARGS)
+_sig("ccuba_vegas_dosample_raw_noalloc", C.c_int, _RAW_ARGS)
 _sig("ccuba_vegas_batch", C.c_int, [_CTXP, C.c_int, C.POINTER(Job), C.POINTER(Result)])
 _sig("ccuba_vegas_source", C.c_int, [C.POINTER(_CTXP), C.c_int, C.c_char_p, _dp, _dp,
                                      C.c_double, C.c_double, C.c_int, C.c_ulonglong,
@@ -144,6 +144,7 @@ SYMBOLS = ["ccuba_init", "ccuba_shutdown", "ccuba_config", "ccuba_config_get",
            "ccuba_strerror", "ccuba_vegas",
            "ccuba_vegas_ex", "ccuba_cuhre", "ccuba_cuhre_rule", "ccuba_vegas_batch",
            "ccuba_submit", "ccuba_poll", "ccuba_drain", "ccuba_vegas_dosample_raw",
+           "ccuba_vegas_dosample_raw_noalloc",
            "ccuba_vegas_points", "ccuba_vegas_refine", "ccuba_vegas_batched",
            "ccuba_vegas_source", "ccuba_rtc_log", "ccuba_vegas_stateful", "ccuba_suave",
            "ccuba_divonne_partition"]
@@ -289,16 +290,17 @@ def vegas_refine(ctx, hist, grid):
 
 
 def vegas_dosample_raw(ctx, family, a, u, nbins, iteration, npts, grid_ptr, sums_ptr, hist_ptr,
-                       stream_ptr=None, flags=FP64, seed=1, stream_id=0):
+                       stream_ptr=None, flags=FP64, seed=1, stream_id=0, noalloc=False):
     """Device-buffer DoSample: pointers are device addresses (e.g. torch
-    tensor .data_ptr()), stream_ptr a HIP stream handle (or None)."""
+    tensor .data_ptr()), stream_ptr a HIP stream handle (or None).  noalloc
+    calls ccuba_vegas_dosample_raw_noalloc, which allocates nothing and
+    returns without waiting for the stream."""
     f, keep = _integrand(family, a, u)
-    _check(_lib.ccuba_vegas_dosample_raw(ctx.handle, len(keep[0]), nbins, C.byref(f), flags,
-                                         seed, stream_id, iteration, npts,
-                                         C.c_void_p(grid_ptr), C.c_void_p(sums_ptr),
-                                         C.c_void_p(hist_ptr),
-                                         C.c_void_p(stream_ptr) if stream_ptr else None),
-           "ccuba_vegas_dosample_raw")
+    name = "ccuba_vegas_dosample_raw_noalloc" if noalloc else "ccuba_vegas_dosample_raw"
+    _check(getattr(_lib, name)(ctx.handle, len(keep[0]), nbins, C.byref(f), flags, seed,
+                               stream_id, iteration, npts, C.c_void_p(grid_ptr),
+                               C.c_void_p(sums_ptr), C.c_void_p(hist_ptr),
+                               C.c_void_p(stream_ptr) if stream_ptr else None), name)
 
 
 def rtc_log(ctx):

@@ -18,6 +18,7 @@
 #include "divonne_engine.h"
 #include "vegas_batched.h"
 #include "vegas_engine.h"
+#include "noalloc.h"
 
 using namespace ccuba;
 
@@ -220,6 +221,8 @@ int ccuba_init(ccuba_ctx **ctx, int device, size_t hbm_budget) {
   c->budget = hbm_budget;
   if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) return CCUBA_EHIP;
   if (set_kernel_limits() != hipSuccess) return CCUBA_EHIP;
+  // the allocation-free entry point's scratch: its address on this device
+  if (noalloc_init(device) != CCUBA_OK) return CCUBA_EHIP;
   if (suave_set_kernel_limits() != hipSuccess) return CCUBA_EHIP;
   for (int p = 0; p < 2; ++p) {
     c->tune[p].block = (int)env_ll("CCUBA_BLOCK", 256);
@@ -684,6 +687,115 @@ int ccuba_vegas_dosample_raw(ccuba_ctx *ctx, int ndim, int nbins, const ccuba_in
   if ((rc = eng.collect(sums_dev, hist_dev, s))) return rc;
   // the engine's buffers are released on return: finish before that
   CCUBA_HIP(hipStreamSynchronize(s));
+  return CCUBA_OK;
+}
+
+int ccuba_vegas_dosample_raw_noalloc(ccuba_ctx *ctx, int ndim, int nbins,
+                                     const ccuba_integrand *f, int flags,
+                                     unsigned long long seed, unsigned int stream_id,
+                                     int iteration, long long npts, const double *grid_dev,
+                                     double *sums_dev, double *hist_dev, void *hip_stream) {
+  if (!ctx || !grid_dev || !sums_dev || !hist_dev || iteration < 0 || iteration >= (1 << 24) ||
+      npts < 2)
+    return CCUBA_EINVAL;
+  VegasSpec sp;
+  int rc = fill_spec(sp, ndim, 1, f, 0.0, 0.0, flags & CCUBA_PRECISION_MASK, seed, 0,
+                     1ll << 62, npts, 0, 1, nbins, stream_id);
+  if (rc) return rc;
+  if (validate_vegas(sp) != CCUBA_OK) return CCUBA_EINVAL;
+  std::lock_guard<std::mutex> g(ctx->lock);
+  unsigned char *base = (unsigned char *)noalloc_scratch(ctx->device);
+  if (!base) return CCUBA_EHIP;
+  CCUBA_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)hip_stream;
+  const int p = sp.prec;
+  const VegasTune &t = ctx->tune[p];
+  const long long dN = (long long)ndim * nbins, row = (2 + dN) * 8;
+  // Layout, 256-byte aligned: descriptor, state, fold ends, parameters, the
+  // folded sums, then per tile and per group of 32 tiles a row of sums and
+  // histogram.  Tiles as the allocating entry point takes them (one per
+  // persistent block); fewer and larger when their rows would not fit.
+  auto a256 = [](long long b) { return (b + 255) / 256 * 256; };
+  static_assert(sizeof(VJob) <= 256 && sizeof(VState) <= 256 &&
+                    2 * kParamRow * sizeof(double) <= 256 && 2 * kParamRow * sizeof(float) <= 256,
+                "the scratch header's slots");
+  static_assert(sizeof(NoallocSetup) <= 4096, "kernel arguments");
+  const long long o_st = 256, o_end = 512, o_p64 = 768, o_p32 = 1024, o_hsum = 1280;
+  const long long o_rows = o_hsum + a256(row);
+  const long long avail = (long long)kNoallocScratchBytes - o_rows - 1024;
+  const long long bs = t.block, B = (long long)ctx->ncu * t.blocks_per_cu;
+  auto round_up = [](long long v, long long m) { return (v + m - 1) / m * m; };
+  auto bytes_for = [&](long long nt) {
+    return a256(nt * 16) + a256(nt * dN * 8) + a256((long long)ngroups_of((int)nt) * row);
+  };
+  long long P = std::max(round_up((npts + B - 1) / B, bs), bs);
+  long long nt = (npts + P - 1) / P;
+  for (long long fit = avail / (row + row / kGroupTiles + 64); bytes_for(nt) > avail;
+       fit -= std::max(1ll, fit / 64)) {
+    if (fit < ctx->ncu) return CCUBA_ENOMEM;  // not even one tile per compute unit
+    P = std::max(round_up((npts + fit - 1) / fit, bs), bs);
+    nt = (npts + P - 1) / P;
+  }
+  if (P > 0x7fffffffll) return CCUBA_ENOMEM;
+  const int ng = ngroups_of((int)nt);
+  const long long o_tsums = o_rows, o_thist = o_tsums + a256(nt * 16);
+  const long long o_gsums = o_thist + a256(nt * dN * 8), o_ghist = o_gsums + a256(ng * 16);
+
+  NoallocSetup S{};
+  VJob &J = S.job;
+  J.ndim = ndim;
+  J.nbins = nbins;
+  J.family = sp.family;
+  J.prec = p;
+  J.flags = sp.flags;
+  J.key0 = (uint32_t)(sp.seed & 0xffffffffull);
+  J.key1 = (uint32_t)(sp.seed >> 32);
+  J.sid = sp.sid;
+  J.nstart = npts;
+  J.maxeval = sp.maxeval;
+  J.tile0 = 0;
+  J.ntiles = (int)nt;
+  J.tile_pts = P;
+  J.hist_cap = 1;
+  J.state = (VState *)(base + o_st);
+  J.grid = const_cast<double *>(grid_dev);  // read only: no refinement here
+  J.tsums = (double *)(base + o_tsums);
+  J.thist = (double *)(base + o_thist);
+  J.gsums = (double *)(base + o_gsums);
+  J.ghist = (double *)(base + o_ghist);
+  J.hsum = (double *)(base + o_hsum);
+  J.p64 = (const double *)(base + o_p64);
+  J.p32 = (const float *)(base + o_p32);
+  S.st.T = iteration;  // the rest zero: the state before its first iteration
+  genz_constants(sp, S.p64, S.p32);
+  const long long nch = (dN + 63) / 64;
+  S.ends[0] = (long long)ng * nch;
+  S.ends[1] = nch;
+  S.job_dst = (VJob *)base;
+  S.st_dst = J.state;
+  S.p64_dst = (double *)(base + o_p64);
+  S.p32_dst = (float *)(base + o_p32);
+  S.ends_dst = (long long *)(base + o_end);
+  CCUBA_HIP(launch_noalloc_setup(S, s));
+
+  VegasArgs A{};
+  A.jobs = S.job_dst;
+  A.tile_job = nullptr;  // one job: the kernels look no tile up
+  A.tile_first = 0;
+  A.tile_count = (int)nt;
+  A.njobs = 1;
+  A.ilp = t.ilp;
+  A.hist64 = fixed_hist(p, t.hist64, dN) ? 0 : 1;
+  const size_t grid_bytes = (size_t)(dN * (p == FP64 ? 16 : 8) + 15) / 16 * 16;
+  const size_t hsz = A.hist64 ? 8 : (p == FP64 ? 24 : 16);
+  A.lds_hist_byte_off = (long long)grid_bytes;
+  const int nb = (ndim + 3) / 4;
+  CCUBA_HIP(launch_dosample(A, p, nb, (nbins & (nbins - 1)) == 0, ndim == 4 * nb,
+                            (int)std::min<long long>(B, nt), (int)bs,
+                            grid_bytes + (size_t)dN * hsz, s));
+  FoldArgs F{S.job_dst, S.ends_dst, 1, S.ends[0], S.ends_dst + 1, S.ends[1]};
+  CCUBA_HIP(launch_fold(F, true, s));
+  CCUBA_HIP(launch_collect(A, 1, sums_dev, hist_dev, s));
   return CCUBA_OK;
 }
 

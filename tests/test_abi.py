@@ -113,6 +113,13 @@ def test_bad_arguments_are_rejected_on_the_host(cc):
         rc = L.ccuba_divonne_partition(None, nd, C.byref(f), 1, 0, nse, nit, mr, ns, tol,
                                        C.byref(nr), C.byref(n), C.byref(fl), C.byref(tot), None)
         assert rc == cc.EINVAL
+    # device-buffer DoSample, both entry points: no context, no buffers, npts < 2
+    for name in ("ccuba_vegas_dosample_raw", "ccuba_vegas_dosample_raw_noalloc"):
+        fn = getattr(L, name)
+        assert fn(None, 3, 64, C.byref(f), 0, 1, 0, 0, 1000, 8, 8, 8, None) == cc.EINVAL
+        hc = C.c_void_p(1)  # never dereferenced: the buffer checks come first
+        assert fn(hc, 3, 64, C.byref(f), 0, 1, 0, 0, 1000, None, 8, 8, None) == cc.EINVAL
+        assert fn(hc, 3, 64, C.byref(f), 0, 1, 0, 0, 1, 8, 8, 8, None) == cc.EINVAL
     assert L.ccuba_rtc_log(None, C.create_string_buffer(8), 8) == cc.EINVAL
     assert L.ccuba_init(None, 0, 0) == cc.EINVAL
     assert L.ccuba_config(None, b"block", 256) == cc.EINVAL
