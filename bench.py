@@ -37,9 +37,13 @@ sys.path.insert(0, ROOT)
 D, NBINS, NPTS, ITERS = 8, 128, 10**7, 20
 FAMILIES = (1, 2)  # oscillatory, product peak
 FAMILY_KEYS = {1: "oscillatory", 2: "product_peak"}
-# VALU issue peak: 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz = 78.6 T lane-ops/s
-# (the published 157.3 TFLOP/s FP32 vector rate at 2 flops per FMA)
-PEAK_VALU = 256 * 4 * 32 * 2.4e9
+# VALU issue peak: one wave64 instruction per SIMD per quad-cycle (16 lanes a
+# clock): 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-slots/s
+PEAK_VALU = 256 * 4 * 16 * 2.4e9
+# a transcendental holds the VALU for two quad-cycles (19.6 T measured)
+PEAK_TRANS = PEAK_VALU / 2
+PEAK_FP32_FLOPS = 157.3e12  # published dense FP32 vector rate (packed FMA)
+PEAK_FP64_FLOPS = 78.6e12   # published FP64 vector rate
 
 
 class Stats(C.Structure):
@@ -72,6 +76,34 @@ def _headline_jobs(cc, params, prec):
     return _JOBS[prec]
 
 
+def _tune_cache():
+    """The autotuner's cache file (CCUBA_TUNE_CACHE; a file in the temporary
+    directory unless set)."""
+    path = os.environ.get("CCUBA_TUNE_CACHE")
+    if not path:
+        import tempfile
+        path = os.path.join(tempfile.gettempdir(), "ccuba_tune_cache.txt")
+        os.environ["CCUBA_TUNE_CACHE"] = path
+    return path
+
+
+def _ensure_tuned():
+    """Tune the headline batch in a child process (untimed, and outside any
+    profiler that wraps a later run once the cache exists), so that this
+    process's headline context finds its settings in the cache."""
+    import subprocess
+    path = _tune_cache()
+    if os.path.exists(path) and ":batch:" in open(path).read():
+        return
+    subprocess.run([sys.executable, os.path.abspath(__file__), "--tune-only"], check=True,
+                   stdout=subprocess.DEVNULL)
+
+
+def _tuned_settings(ctx, prec):
+    return {k: ctx.config_get(k, prec) for k in ("block", "blocks_per_cu", "ilp", "min_tile",
+                                                 "hist64")}
+
+
 def _step(cc, ctx, params, prec):
     ev = 0
     for r in cc.vegas_batch(ctx, _headline_jobs(cc, params, prec)):
@@ -94,49 +126,152 @@ def _timed(cc, ctx, params, prec, steps, warmup):
     return ev, time.perf_counter() - t0
 
 
-def _roofline(cc, ctx, params):
-    """Event-timed DoSample sampling launches of one profiled FP32 step.
+def _counters():
+    """The committed VALU counter summary, with each kernel's entry kept only
+    while the sources it was taken on are unchanged."""
+    path = os.path.join(ROOT, "profiles", "valu_counters.json")
+    if not os.path.exists(path):
+        return {}
+    rec = json.load(open(path))
+    ks = rec.get("kernels", {})
+    out = {}
+    if rec.get("kernel_source_sha256") == kernel_source_hash(rec.get("kernel_sources", [])):
+        out.update({k: v for k, v in ks.items() if k.startswith("dosample")})
+    if rec.get("cuhre_source_sha256") == kernel_source_hash(rec.get("cuhre_sources", [])):
+        if "cuhre_rule" in ks:
+            out["cuhre_rule"] = dict(ks["cuhre_rule"], evals=rec["probe"]["cuhre_evals"])
+    return out
+
+
+def _valu_fields(c, units, seconds, flops_peak):
+    """Roofline fields from counter totals `c' over `units' points (or
+    evaluations) and the live seconds those units take: VALU slot rate against
+    the issue peak, FP32/FP64 FLOP rate, transcendental rate, dual issue."""
+    k = c["counters"]
+    g = lambda n: k.get(n, 0.0)
+    lanes = 64.0
+    slots = g("SQ_ACTIVE_INST_VALU") * lanes / units  # quad-cycle slots per unit
+    instrs = g("SQ_INSTS_VALU") * lanes / units
+    f32 = lanes * (2 * g("SQ_INSTS_VALU_FMA_F32") + g("SQ_INSTS_VALU_ADD_F32") +
+                   g("SQ_INSTS_VALU_MUL_F32")) / units
+    f64 = lanes * (2 * g("SQ_INSTS_VALU_FMA_F64") + g("SQ_INSTS_VALU_ADD_F64") +
+                   g("SQ_INSTS_VALU_MUL_F64")) / units
+    trans = lanes * (g("SQ_INSTS_VALU_TRANS_F32") + g("SQ_INSTS_VALU_TRANS_F64")) / units
+    rate = units / seconds
+    achieved = slots * rate
+    # VALU busy over the counter run alone (rocprof's VALUBusy: busy
+    # quad-cycles per CU over the active clocks of one XCD's 32 CUs)
+    disp = max(c.get("dispatches", 1), 1)
+    grbm = g("GRBM_GUI_ACTIVE") / disp / 8
+    busy = (g("SQ_ACTIVE_INST_VALU") / disp) / (256 * grbm) if grbm > 0 else None
+    out = {"achieved": achieved / 1e12, "frac": achieved / PEAK_VALU,
+           "slots_per_unit": slots, "valu_instructions_per_unit": instrs,
+           "valu_busy_counter_run": busy,
+           "dual_issue_quad_cycle_frac": (g("SQ_ACTIVE_INST_VALU2") / g("SQ_ACTIVE_INST_VALU")
+                                          if g("SQ_ACTIVE_INST_VALU") else None),
+           "int32_per_unit": lanes * g("SQ_INSTS_VALU_INT32") / units,
+           "int64_per_unit": lanes * g("SQ_INSTS_VALU_INT64") / units,
+           "lds_per_unit": lanes * g("SQ_INSTS_LDS") / units,
+           "fp32_flops_per_unit": f32, "fp64_flops_per_unit": f64,
+           "trans_per_unit": trans,
+           "trans_per_s": trans * rate, "trans_frac": trans * rate / PEAK_TRANS}
+    if flops_peak == PEAK_FP32_FLOPS:
+        out.update(fp32_tflops=f32 * rate / 1e12, fp32_flop_frac=f32 * rate / PEAK_FP32_FLOPS)
+    else:
+        out.update(fp64_tflops=f64 * rate / 1e12, fp64_flop_frac=f64 * rate / PEAK_FP64_FLOPS)
+    return out
+
+
+def _roofline(cc, ctx, params, prec):
+    """Event-timed DoSample sampling launches of one profiled headline step.
 
     The library records HIP events on its own stream around the sampling
     kernel, the fold of its partial sums and the refine kernel of every
     iteration; the sampling kernel is the dominant one and the roofline is
-    its VALU issue rate: ISA-counted slots per point x points per launch /
-    average launch duration."""
+    its VALU issue rate: the VALU quad-cycles per point that rocprofv3's SQ
+    counters measured on this kernel (SQ_ACTIVE_INST_VALU, committed under
+    profiles/) x points per launch / the average launch duration, against
+    one wave64 instruction per SIMD per quad-cycle.  The slot model counted
+    from the assembly (isa_slots.py) is reported beside it."""
     from paper_1408_6373_amd import isa_slots
     table = isa_slots.load() or {}
     _stats(cc, ctx)
     ctx.config("profile", 1)
-    ms = fold_ms = refine_ms = 0.0
-    evals = launches = 0
-    slots = 0.0
-    # the defaults at d = 8, 128 bins: fixed-point LDS histogram, 2 points per
-    # lane per trip, 2 Philox blocks per point, power-of-two bin count,
-    # d = 4 x blocks
-    key = "f32hfx_ilp2_nb2_pow2_full"
-    _step(cc, ctx, params, cc.FP32_EVAL)
+    _step(cc, ctx, params, prec)
     st = _stats(cc, ctx)
+    ctx.config("profile", 0)
     ms, fold_ms, refine_ms = st.dosample_ms, st.fold_ms, st.refine_ms
     evals, launches = st.evals, st.dosample_launches
+    n = max(launches, 1)
+    fp32 = prec == cc.FP32_EVAL
+    # the instance at d = 8, 128 bins: 2 Philox blocks per point, power-of-two
+    # bin count, d = 4 x blocks; histogram type and points per lane as set
+    t = _tuned_settings(ctx, prec)
+    h64, ilp = t["hist64"], t["ilp"]
+    key = "%s%s_ilp%d_nb2_pow2_full" % ("f32" if fp32 else "f64", "h64" if h64 else "hfx", ilp)
+    name = "vegas_dosample_kernel<%s,%s,%d,2,true,true>" % (
+        "float" if fp32 else "double", "double" if h64 else "unsigned long long", ilp)
+    model = 0.0
     for fam in FAMILIES:  # each integral contributes ITERS x NPTS points
         per = table.get(key, {}).get(FAMILY_KEYS[fam])
-        slots = None if (per is None or slots is None) else slots + per * ITERS * NPTS
-    ctx.config("profile", 0)
-    n = max(launches, 1)
-    out = {"bound": "alu", "kernel": "vegas_dosample_kernel<float,unsigned long long,2,2,true,true>",
-           "unit": "T VALU-slots/s", "peak": PEAK_VALU / 1e12,
+        model = None if (per is None or model is None) else model + per * ITERS * NPTS
+    out = {"bound": "alu", "kernel": name, "launch": t, "unit": "T VALU-slots/s",
+           "peak": PEAK_VALU / 1e12,
            "avg_launch_ms": ms / n, "launches": launches,
            "points_per_launch": evals / n,
            "kernel_evals_per_s": evals / (ms * 1e-3),
            "fold_ms_per_launch": fold_ms / n,
            "refine_ms_per_launch": refine_ms / n,
            "sample_fold_refine_evals_per_s": evals / ((ms + fold_ms + refine_ms) * 1e-3),
-           "slots_per_point": None if slots is None else slots / evals,
-           "traffic": _traffic()}
-    if slots is not None:
-        out["achieved"] = slots / (ms * 1e-3) / 1e12
-        out["frac"] = out["achieved"] / out["peak"]
+           "achieved": None, "frac": None,
+           "slot_model": None if model is None else {
+               "slots_per_point": model / evals,
+               "achieved": model / (ms * 1e-3) / 1e12,
+               "frac": model / (ms * 1e-3) / PEAK_VALU}}
+    c = _counters().get("dosample_fp32" if fp32 else "dosample_fp64")
+    # counters taken on this precision and histogram type; when they were
+    # taken on another instance (points per lane per trip), their slots per
+    # point are scaled by the assembly counts of the two instances' loops
+    scale = None
+    if c and len(c.get("instances", [])) == 1:
+        import re
+        m = re.search(r"vegas_dosample_kernel<(\w+), ([\w ]+), (\d), 2, true, true>",
+                      c["instances"][0])
+        if m and (m.group(1) == "float") == fp32 and (m.group(2) == "double") == bool(h64):
+            ckey = key.replace("_ilp%d_" % ilp, "_ilp%s_" % m.group(3))
+            mk = [table.get(k, {}).get(FAMILY_KEYS[f]) for k in (key, ckey) for f in FAMILIES]
+            scale = (1.0 if ckey == key else
+                     None if None in mk else (mk[0] + mk[1]) / (mk[2] + mk[3]))
+            out["counters_instance"] = c["instances"][0]
+    if c and scale is not None:
+        c = dict(c, counters={k: v * (scale if k.startswith("SQ_ACTIVE_INST_VALU") or
+                                      k == "SQ_INSTS_VALU" else 1.0)
+                              for k, v in c["counters"].items()})
+        out["counters_isa_scale"] = scale
     else:
-        out["achieved"] = out["frac"] = None
+        c = None
+    if c:
+        units = float(c["dispatches"] * len(FAMILIES) * NPTS)  # points of the counter run
+        out.update(_valu_fields(c, units, (ms * 1e-3) / evals * units,
+                                PEAK_FP32_FLOPS if fp32 else PEAK_FP64_FLOPS))
+        out["counters"] = "profiles/valu_counters.json"
+    if fp32:
+        out["traffic"] = _traffic()
+    return out
+
+
+def _cuhre_roofline(st):
+    """Cuhre's rule kernels: counter slots per evaluation x the evaluations per
+    second that the library's HIP events measured around the rule launches of
+    the cuhre leg."""
+    c = _counters().get("cuhre_rule")
+    if not c or st.rule_ms <= 0:
+        return None
+    rate = st.rule_evals / (st.rule_ms * 1e-3)
+    out = {"bound": "alu", "kernel": "gm_rule_lane_kernel<CORNER_PEAK,6> + gm_rule_kernel",
+           "unit": "T VALU-slots/s", "peak": PEAK_VALU / 1e12, "evals_per_s": rate,
+           "counters": "profiles/valu_counters.json"}
+    out.update(_valu_fields(c, float(c["evals"]), c["evals"] / rate, PEAK_FP64_FLOPS))
     return out
 
 
@@ -145,10 +280,10 @@ KERNEL_SOURCES = ("vegas_sample.h", "vegas_sample_f32hfx.hip", "philox.h", "genz
                   "engine.h", "vegas.h")
 
 
-def kernel_source_hash():
+def kernel_source_hash(names=KERNEL_SOURCES):
     import hashlib
     h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
+    for name in names:
         h.update(open(os.path.join(ROOT, "paper_1408_6373_amd", "csrc", name), "rb").read())
     return h.hexdigest()
 
@@ -207,6 +342,64 @@ def summarize_pmc(fetch_csv, write_csv, out_path, commands):
     rec["kernel_sources"] = list(KERNEL_SOURCES)
     rec["kernel_source_sha256"] = kernel_source_hash()
     rec["bytes_per_launch"] = rec["dosample"]["bytes"]
+    with open(out_path, "w") as f:
+        json.dump(rec, f, indent=1)
+    return rec
+
+
+# the kernels whose VALU counters the roofline uses: the headline DoSample
+# instance in both precisions, and Cuhre's rule kernels
+COUNTER_KERNELS = {
+    # (a headline step launches one DoSample instance per precision)
+    "dosample_fp32": "vegas_dosample_kernel<float",
+    "dosample_fp64": "vegas_dosample_kernel<double",
+    "cuhre_rule": "gm_rule",
+}
+# sources of the Cuhre rule kernels (the counter summary holds for them only
+# while these are unchanged)
+CUHRE_SOURCES = ("cuhre.hip", "genz.h", "engine.h")
+
+
+def _read_counters(path):
+    """{kernel name: {counter: [value per dispatch]}} from a rocprofv3 counter CSV."""
+    import csv
+    out = {}
+    with open(path, newline="") as f:
+        for row in csv.DictReader(f):
+            d = out.setdefault(row["Kernel_Name"], {})
+            d.setdefault(row["Counter_Name"], []).append(float(row["Counter_Value"]))
+    return out
+
+
+def summarize_counters(csvs, out_path, commands, probe):
+    """Write the VALU counter summary of --counter-probe runs: for each kernel
+    of COUNTER_KERNELS, every counter's total over its dispatches and the
+    dispatch count; `probe' is the probe's JSON line (its evaluation counts)."""
+    rec = {"what": "rocprofv3 --pmc SQ counters of the DoSample kernels of one headline step "
+                   "in each precision (Vegas d=8, oscillatory and product peak as one batch, 128 "
+                   "bins, 2 x 1e7 points per launch, 20 launches) and of Cuhre's rule kernels "
+                   "over one corner-peak d=6 run (batches of 1e5 regions to epsrel 1e-6); "
+                   "counter values are totals over the dispatches (the SQ_ counters summed over "
+                   "the shader engines by rocprofv3)",
+           "commands": commands, "probe": probe, "kernels": {}}
+    for path in csvs:
+        for name, counters in _read_counters(path).items():
+            for key, pat in COUNTER_KERNELS.items():
+                if pat not in name:
+                    continue
+                k = rec["kernels"].setdefault(key, {"name": pat, "counters": {},
+                                                    "dispatches": {}})
+                for cn, vals in counters.items():
+                    k["counters"][cn] = k["counters"].get(cn, 0.0) + sum(vals)
+                    # dispatches of each matching kernel (the same in every pass)
+                    k["dispatches"][name] = len(vals)
+    for k in rec["kernels"].values():
+        k["instances"] = sorted(k["dispatches"])
+        k["dispatches"] = sum(k["dispatches"].values())
+    rec["kernel_sources"] = list(KERNEL_SOURCES) + ["vegas_sample_f64.hip"]
+    rec["kernel_source_sha256"] = kernel_source_hash(rec["kernel_sources"])
+    rec["cuhre_sources"] = list(CUHRE_SOURCES)
+    rec["cuhre_source_sha256"] = kernel_source_hash(CUHRE_SOURCES)
     with open(out_path, "w") as f:
         json.dump(rec, f, indent=1)
     return rec
@@ -336,7 +529,7 @@ def _cuhre_leg(cc, ctx):
             "value": r["neval"] / dt, "unit": "evals/s", "seconds": dt, "neval": r["neval"],
             "nregions": r["nregions"], "fail": r["fail"],
             "rule_kernel_evals_per_s": st.rule_evals / max(st.rule_ms * 1e-3, 1e-12),
-            "rule_launches": st.rule_launches}
+            "rule_launches": st.rule_launches, "roofline": _cuhre_roofline(st)}
 
 
 SUAVE_NNEW, SUAVE_SPLIT, SUAVE_STEPS = 1 << 17, 64, 30
@@ -473,21 +666,9 @@ def _serving_specs(cc, reqs):
     return specs
 
 
-def _serving_leg(cc, n):
-    import numpy as np
-    import workloads as W
-    # saturation throughput: every request queued at once
-    ctx = cc.Context(device=0)
-    specs = _serving_specs(cc, W.serving_requests(n, rate=1.0, seed=7))
-    t0 = time.perf_counter()
-    tickets = [cc.submit(ctx, s) for s in specs]
-    cc.drain(ctx)
-    t_sat = time.perf_counter() - t0
-    for t in tickets:
-        cc.poll(ctx, t)
-    ctx.close()
-    rate = 0.7 * n / t_sat
-    # timed: Poisson arrivals at 0.7 of saturation
+def _serving_run(cc, W, n, rate):
+    """n requests of the stream arriving at `rate' per second (Poisson), on a
+    fresh context; returns the per-request results."""
     reqs = W.serving_requests(n, rate=rate, seed=7)
     specs = _serving_specs(cc, reqs)
     ctx = cc.Context(device=0)
@@ -501,30 +682,114 @@ def _serving_leg(cc, n):
     cc.drain(ctx)
     res = [cc.poll(ctx, t) for t in tickets]
     ctx.close()
+    return reqs, res
+
+
+def _latency_rows(res):
+    import numpy as np
     lat = np.array([r["t_done"] - r["t_submit"] for r in res]) * 1e3
-    ev = sum(r["neval"] for r in res)
-    span = max(r["t_done"] for r in res) - min(r["t_submit"] for r in res)
-    return {"workload": "Poisson arrivals, 70%% Vegas (FP32) / 30%% Cuhre (FP64), d 2..16, "
-                        "epsrel logU[1e-5,1e-3], maxeval 1e8, %d requests" % n,
-            "rate_per_s": rate, "saturation_per_s": n / t_sat,
-            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-            "evals_per_s": ev / span, "failed_status": sum(r["status"] != 0 for r in res),
-            "not_converged": sum(r["fail"] != 0 for r in res)}
+    fail = np.array([r["fail"] for r in res])
+    out = {}
+    for key, m in (("all", np.ones(len(res), bool)), ("converged", fail == 0),
+                   ("budget_capped", fail == 1)):
+        if m.any():
+            out[key] = {"count": int(m.sum()), "p50_ms": float(np.percentile(lat[m], 50)),
+                        "p99_ms": float(np.percentile(lat[m], 99))}
+    return out
 
 
-def _cpu_baseline(params, iters_sample=4):
-    import oracle as O
+def _serving_leg(cc, n, fracs=(0.3, 0.5, 0.7, 0.9)):
+    import workloads as W
+    # saturation throughput: every request queued at once
+    ctx = cc.Context(device=0)
+    specs = _serving_specs(cc, W.serving_requests(n, rate=1.0, seed=7))
     t0 = time.perf_counter()
-    ev = 0
-    for fam in FAMILIES:
+    tickets = [cc.submit(ctx, s) for s in specs]
+    cc.drain(ctx)
+    t_sat = time.perf_counter() - t0
+    for t in tickets:
+        cc.poll(ctx, t)
+    ctx.close()
+    sat = n / t_sat
+    rows = []
+    for frac in fracs:  # Poisson arrivals at fractions of saturation
+        reqs, res = _serving_run(cc, W, n, frac * sat)
+        ev = sum(r["neval"] for r in res)
+        span = max(r["t_done"] for r in res) - min(r["t_submit"] for r in res)
+        rows.append({"load": frac, "rate_per_s": frac * sat, "requests": n,
+                     "latency": _latency_rows(res), "evals_per_s": ev / span,
+                     "failed_status": sum(r["status"] != 0 for r in res)})
+    head = next(r for r in rows if r["load"] == 0.7)
+    return {"workload": "Poisson arrivals, 70%% Vegas (FP32) / 30%% Cuhre (FP64), d 2..16, "
+                        "epsrel logU[1e-5,1e-3], maxeval 1e8, %d requests per load" % n,
+            "saturation_per_s": sat, "rates": rows,
+            "rate_per_s": head["rate_per_s"], "p50_ms": head["latency"]["all"]["p50_ms"],
+            "p99_ms": head["latency"]["all"]["p99_ms"], "evals_per_s": head["evals_per_s"]}
+
+
+def _host():
+    """The host CPU's model name and the cores this process may use."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "cores_available": avail}
+
+
+def _cpu_baseline(cc, params, iters_sample=4, max_threads=16):
+    """The oracle on the first `iters_sample` of the 20 iterations of both
+    headline integrals (FP64): once in one thread, then as one independent
+    oracle run per thread on all the cores the process may use (up to
+    max_threads; the oracle is plain C behind ctypes, which releases the
+    GIL).  The same sample is also run on the GPU in both precisions, and
+    every result is compared with the single-thread oracle's (parity)."""
+    import concurrent.futures as cf
+    import oracle as O
+
+    def one(fam):
         a, u = params[fam]
-        r = O.vegas(O.genz(fam, a, u), D, nbins=NBINS, nstart=NPTS,
-                    maxeval=iters_sample * NPTS, seed=1)
-        ev += r["neval"]
-    dt = time.perf_counter() - t0
-    return dict(value=ev / dt, unit="evals/s", cores=1, kind="oracle",
-                sample="first %d of 20 iterations (10^7 points each) of both integrals, "
-                       "FP64, single thread: %d evals in %.1f s" % (iters_sample, ev, dt))
+        return O.vegas(O.genz(fam, a, u), D, nbins=NBINS, nstart=NPTS,
+                       maxeval=iters_sample * NPTS, seed=1)
+    host = _host()
+    t0 = time.perf_counter()
+    ref = {fam: one(fam) for fam in FAMILIES}
+    dt1 = time.perf_counter() - t0
+    ev1 = sum(r["neval"] for r in ref.values())
+    T = max(1, min(host["cores_available"] or 1, max_threads))
+    fams = [FAMILIES[q % len(FAMILIES)] for q in range(T)]
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=T) as ex:
+        runs = list(ex.map(one, fams))
+    dtT = time.perf_counter() - t0
+    evT = sum(r["neval"] for r in runs)
+    # the GPU on the same sample: the headline batch path, both precisions
+    parity = {}
+    ctx = cc.Context(device=0)
+    try:
+        for prec, tag in ((cc.FP32_EVAL, "fp32_eval"), (cc.FP64, "fp64")):
+            specs = [dict(method=0, family=fam, a=params[fam][0], u=params[fam][1], flags=prec,
+                          seed=1, stream_id=0, nstart=NPTS, maxeval=iters_sample * NPTS,
+                          nbins=NBINS) for fam in FAMILIES]
+            for fam, r in zip(FAMILIES, cc.vegas_batch(ctx, specs)):
+                o = ref[fam]
+                parity.setdefault(FAMILY_KEYS[fam], {})[tag] = {
+                    "integral_rel_diff": abs(r["integral"] - o["integral"]) / abs(o["integral"]),
+                    "error_rel_diff": abs(r["error"] - o["error"]) / abs(o["error"]),
+                    "prob_abs_diff": abs(r["prob"] - o["prob"])}
+    finally:
+        ctx.close()
+    sample = ("first %d of 20 iterations (10^7 points each) of both integrals, FP64; %d threads "
+              "each run the oracle on one of them (%d evals in %.1f s)"
+              % (iters_sample, T, evT, dtT))
+    return dict(value=evT / dtT, unit="evals/s", cores=T, kind="oracle", sample=sample,
+                host=host,
+                single_thread={"value": ev1 / dt1, "cores": 1, "evals": ev1, "seconds": dt1},
+                parity_vs_fp64_oracle=parity)
 
 
 def main():
@@ -535,11 +800,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip batch/cuhre/serving legs")
-    ap.add_argument("--serving-requests", type=int, default=300)
+    ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--suave-only", action="store_true",
                     help="run only the Suave leg and print its JSON line (for profiling)")
     ap.add_argument("--divonne-only", action="store_true",
                     help="run only the Divonne-partition leg and print its JSON line")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="run only the serving leg and print its JSON line")
     ap.add_argument("--checkpoint-only", action="store_true",
                     help="run only the state-file / grid-reuse leg and print its JSON line")
     ap.add_argument("--traffic-probe", action="store_true",
@@ -547,6 +814,15 @@ def main():
                          "step of the headline workload; prints a JSON line")
     ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT"),
                     help="write the traffic summary of two --traffic-probe counter runs")
+    ap.add_argument("--tune-only", action="store_true",
+                    help="autotune the headline batch in both precisions into the tune cache "
+                         "(CCUBA_TUNE_CACHE) and exit")
+    ap.add_argument("--counter-probe", action="store_true",
+                    help="for PMC runs: one headline step in each precision and one Cuhre run "
+                         "of the corner peak at d = 6; prints a JSON line")
+    ap.add_argument("--counter-summary", nargs="+", metavar="ARG",
+                    help="OUT PROBE_JSON CSV...: write the VALU counter summary of "
+                         "--counter-probe runs")
     ap.add_argument("--stats-summary", nargs=2, metavar=("STATS_CSV", "OUT"),
                     help="write a text table of a rocprofv3 kernel_stats.csv")
     ap.add_argument("--command", default="", help="command recorded in a summary")
@@ -559,10 +835,20 @@ def main():
     if args.stats_summary:
         summarize_stats(args.stats_summary[0], args.stats_summary[1], args.command, args.note)
         return
+    if args.counter_summary:
+        out, probe, csvs = args.counter_summary[0], args.counter_summary[1], args.counter_summary[2:]
+        cmds = [c for c in args.command.split(";;") if c]
+        rec = summarize_counters(csvs, out, cmds, json.load(open(probe)))
+        print(json.dumps({k: v.get("dispatches") for k, v in rec["kernels"].items()}))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (--gpus 1); no multi-GPU path exists",
               file=sys.stderr)
         sys.exit(2)
+
+    if not (args.tune_only or args.counter_probe or args.traffic_probe or args.suave_only or
+            args.divonne_only or args.checkpoint_only or args.serving_only):
+        _ensure_tuned()
 
     import torch
     import paper_1408_6373_amd as cc
@@ -575,10 +861,40 @@ def main():
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
+        _tune_cache()
         ctx = cc.Context(device=0)
+        ctx.config("autotune", 1)  # the tuned settings, from the cache
         ev = _step(cc, ctx, params, cc.FP32_EVAL)
         ctx.close()
         print(json.dumps({"traffic_probe": True, "copy_bytes": 1 << 30, "neval": ev}))
+        return
+    if args.tune_only:
+        _tune_cache()
+        ctx = cc.Context(device=0)
+        ctx.config("autotune", 1)
+        for prec in (cc.FP32_EVAL, cc.FP64):
+            _step(cc, ctx, params, prec)
+        print(json.dumps({p: _tuned_settings(ctx, p) for p in (cc.FP32_EVAL, cc.FP64)}))
+        ctx.close()
+        return
+    if args.counter_probe:
+        # the tuned headline settings, read from the cache that a plain run of
+        # the benchmark (or --tune-only) wrote before
+        _tune_cache()
+        ctx = cc.Context(device=0)
+        ctx.config("autotune", 1)
+        ev32 = _step(cc, ctx, params, cc.FP32_EVAL)
+        ev64 = _step(cc, ctx, params, cc.FP64)
+        a, u = W.genz_params(W.CORNER_PEAK, 6, 1)
+        r = cc.cuhre(W.CORNER_PEAK, a, u, ctx=ctx, epsrel=1e-6, maxeval=10**10,
+                     max_regions_per_batch=10**5)
+        ctx.close()
+        print(json.dumps({"counter_probe": True, "dosample_fp32_points": ev32,
+                          "dosample_fp64_points": ev64, "cuhre_evals": r["neval"],
+                          "cuhre_regions": r["nregions"]}))
+        return
+    if args.serving_only:
+        print(json.dumps({"serving": _serving_leg(cc, args.serving_requests)}))
         return
     ctx = cc.Context(device=0)
     if args.suave_only or args.divonne_only or args.checkpoint_only:
@@ -589,7 +905,11 @@ def main():
         ctx.close()
         return
 
-    ev32, t32 = _timed(cc, ctx, params, cc.FP32_EVAL, args.steps, args.warmup)
+    # the headline on its own context, with the launch settings the autotuner
+    # picked for this batch (read from its cache)
+    hctx = cc.Context(device=0)
+    hctx.config("autotune", 1)
+    ev32, t32 = _timed(cc, hctx, params, cc.FP32_EVAL, args.steps, args.warmup)
     value = ev32 / t32
     out = {
         "metric": "integrand evals/s (Vegas d=8, FP32 vs FP64) + p50/p99 solve latency",
@@ -602,11 +922,16 @@ def main():
                    "iterations": ITERS, "integrals_per_step": len(FAMILIES)},
     }
     if not args.no_fp64:
-        ev64, t64 = _timed(cc, ctx, params, cc.FP64, args.steps, args.warmup)
+        ev64, t64 = _timed(cc, hctx, params, cc.FP64, args.steps, args.warmup)
         out["fp64"] = {"value": ev64 / t64, "unit": "evals/s",
                        "ms_per_step": 1e3 * t64 / args.steps,
                        "fp32_speedup": value / (ev64 / t64)}
-    out["roofline"] = _roofline(cc, ctx, params)
+    out["launch"] = {"fp32": _tuned_settings(hctx, cc.FP32_EVAL),
+                     "fp64": _tuned_settings(hctx, cc.FP64), "autotuned": True}
+    out["roofline"] = _roofline(cc, hctx, params, cc.FP32_EVAL)
+    if not args.no_fp64:
+        out["fp64"]["roofline"] = _roofline(cc, hctx, params, cc.FP64)
+    hctx.close()
     if not args.no_extra:
         out["batch"] = _batch_leg(cc)
         out["caller_integrand"] = _caller_integrand_leg(cc)
@@ -620,7 +945,10 @@ def main():
         out["p50_ms"] = out["serving"]["p50_ms"]
         out["p99_ms"] = out["serving"]["p99_ms"]
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = _cpu_baseline(params)
+        out["cpu_baseline"] = _cpu_baseline(cc, params)
+        out["parity"] = {"against": "the FP64 oracle on the cpu_baseline sample (4 of 20 "
+                                    "iterations of both headline integrals)",
+                         "results": out["cpu_baseline"]["parity_vs_fp64_oracle"]}
     print(json.dumps(out))
 
 

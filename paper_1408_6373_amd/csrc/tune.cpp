@@ -6,7 +6,10 @@
 // FP32 histogram precision)
 // and keeps the fastest.  Results do not depend on the choice beyond
 // floating-point summation order.  The cache file holds one line per
-// (device name, precision): "name prec block blocks_per_cu hist64 ilp".
+// (device name, precision): "name prec block blocks_per_cu hist64 ilp", and
+// one per (device name, batch signature, precision) for batches:
+// "name:batch:signature prec block blocks_per_cu hist64 ilp min_tile", where
+// the signature hashes the shapes of the batch's jobs of that precision.
 #include "tune.h"
 
 #include <cstdio>
@@ -32,29 +35,59 @@ std::string device_key(ccuba_ctx *ctx) {
   return s;
 }
 
-bool load_cache(const char *path, const std::string &key, int prec, VegasTune &t) {
+bool load_cache(const char *path, const std::string &key, int prec, VegasTune &t,
+                bool with_tile = false) {
   std::ifstream f(path);
   std::string line;
-  while (std::getline(f, line)) {
+  bool found = false;
+  while (std::getline(f, line)) {  // the last matching line wins
     std::istringstream is(line);
     std::string k;
     int p, b, bpc, h, ilp;
+    long long mt = 0;
     if (!(is >> k >> p >> b >> bpc >> h >> ilp)) continue;
+    if (with_tile && !(is >> mt)) continue;
     if (k == key && p == prec) {
       t.block = b;
       t.blocks_per_cu = bpc;
       t.hist64 = h;
       t.ilp = ilp;
-      return true;
+      if (with_tile) t.min_tile = mt;
+      found = true;
     }
   }
-  return false;
+  return found;
 }
 
-void store_cache(const char *path, const std::string &key, int prec, const VegasTune &t) {
+void store_cache(const char *path, const std::string &key, int prec, const VegasTune &t,
+                 bool with_tile = false) {
   std::ofstream f(path, std::ios::app);
   f << key << " " << prec << " " << t.block << " " << t.blocks_per_cu << " " << t.hist64 << " "
-    << t.ilp << "\n";
+    << t.ilp;
+  if (with_tile) f << " " << t.min_tile;
+  f << "\n";
+}
+
+// FNV-1a over the shapes of a batch's jobs: what the launch settings depend on
+std::string batch_signature(const std::vector<VegasSpec> &specs) {
+  unsigned long long h = 1469598103934665603ull;
+  auto mix = [&](long long v) {
+    for (int b = 0; b < 8; ++b) {
+      h ^= (unsigned long long)((v >> (8 * b)) & 0xff);
+      h *= 1099511628211ull;
+    }
+  };
+  for (const VegasSpec &s : specs) {
+    mix(s.ndim);
+    mix(s.nbins);
+    mix(s.family);
+    mix(s.nstart);
+    mix(s.nincrease);
+    mix(s.maxeval);
+  }
+  char buf[32];
+  std::snprintf(buf, sizeof(buf), "%016llx", h);
+  return buf;
 }
 
 double time_candidate(ccuba_ctx *ctx, int prec, const VegasTune &cand) {
@@ -168,6 +201,13 @@ void autotune_batch(ccuba_ctx *ctx, const std::vector<VegasSpec> &specs) {
       if (sp.prec == prec) mine.push_back(sp);
     if (mine.empty()) continue;
     ctx->tuned_batch[prec] = 1;
+    const char *path = std::getenv("CCUBA_TUNE_CACHE");
+    const std::string key = device_key(ctx) + ":batch:" + batch_signature(mine);
+    VegasTune cached = ctx->tune[prec];
+    if (path && *path && load_cache(path, key, prec, cached, true)) {
+      ctx->tune[prec] = cached;
+      continue;
+    }
     const VegasTune saved = ctx->tune[prec];
     VegasTune best = saved;
     double best_ms = 1e30;
@@ -190,6 +230,7 @@ void autotune_batch(ccuba_ctx *ctx, const std::vector<VegasSpec> &specs) {
             }
           }
     ctx->tune[prec] = best;
+    if (path && *path) store_cache(path, key, prec, best, true);
   }
 }
 

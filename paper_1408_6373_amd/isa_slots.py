@@ -1,21 +1,29 @@
 """VALU issue slots per sample point of the DoSample kernels, counted from the
-gfx950 assembly of this build.
+gfx950 assembly of this build (a static model, beside the rocprofv3 counters
+the benchmark reads).
 
 The roofline of the Vegas DoSample kernel is the VALU issue rate: every
 point is produced in registers, so HBM traffic is negligible and there is
 no matrix contraction.  This script compiles the DoSample translation
 units (``csrc/vegas_sample_*.hip``) to gfx950 assembly with the library's
 flags, finds the per-point loop of each kernel instance and family, and
-weighs its VALU instructions by their issue cost
-relative to a full-rate FP32 operation (78.6 T lane-ops/s on MI355X = the
-published 157.3 TFLOP/s FP32 vector peak / 2 flops per FMA):
+weighs its VALU instructions by the quad-cycles (4 clocks, one wave64
+instruction on a 16-lane SIMD) they hold the VALU for, as the SQ counters
+count them (SQ_ACTIVE_INST_VALU is SQ_INSTS_VALU plus one more quad-cycle
+per transcendental on the headline kernel):
 
-  * FP32 / 32-bit integer operations              1 slot
-  * FP64 operations (half rate)                   2 slots
-  * 64-bit integer multiply-add, transcendentals  4 slots (quarter rate)
+  * every VALU instruction, FP64 and 64-bit integer multiply-add included,
+    1 slot (measured issue rates on MI355X with independent chains: FP32 FMA
+    37.6 T, FP64 FMA 35.7 T, v_mad_u64_u32 31.2 T lane-ops/s, against
+    39.3 T = 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz)
+  * transcendentals and v_mul_hi_u32                2 slots (19.6 T measured)
 
 A loop's slots divided by the points it handles per trip (ILP) is the
-work per point; times the points of a launch it is the launch's work.
+work per point; times the points of a launch and divided by the launch's
+duration and 39.3 T slots/s it is the fraction of the VALU issue peak.
+(Simple 32-bit integer and bit operations can issue two per quad-cycle on
+gfx950 -- v_add_u32 60.4 T, v_bitop3_b32 55.3 T measured -- so the peak is
+not a hard ceiling for every mix.)
 
 Usage: ``python paper_1408_6373_amd/isa_slots.py`` writes ``kernel_slots.json``
 next to this file (also done by build.py) and prints it.
@@ -33,12 +41,9 @@ FAMILIES = ["gaussian", "oscillatory", "product_peak", "corner_peak", "c0"]
 
 
 def _weight(op):
-    if op.startswith(("v_mad_u64_u32", "v_mad_i64_i32")):
-        return 4
-    if any(t in op for t in ("v_exp_", "v_log_", "v_rcp_", "v_rsq_", "v_sqrt_", "v_sin_",
-                             "v_cos_")):
-        return 4
-    if "f64" in op:
+    if op.startswith("v_mul_hi_") or any(t in op for t in ("v_exp_", "v_log_", "v_rcp_",
+                                                            "v_rsq_", "v_sqrt_", "v_sin_",
+                                                            "v_cos_")):
         return 2
     return 1
 

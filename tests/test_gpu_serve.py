@@ -126,3 +126,138 @@ def test_invalid_request_status(cc):
     cc.drain(ctx)
     assert cc.poll(ctx, t)["status"] == cc.EINVAL
     ctx.close()
+
+
+# ---------------------------------------------------------------------------
+# Served results against the oracle, and mixed == alone on the benchmark's own
+# request distribution (d up to 16, epsrel down to 1e-5, Cuhre batches of
+# 10^5 regions, the bench's budgets).
+
+def _oracle(s):
+    import oracle as O
+    if s["method"] == 0:
+        return O.vegas(O.genz(s["family"], s["a"], s["u"], precision=s["flags"]), len(s["a"]),
+                       flags=s["flags"], seed=s["seed"], stream_id=s["stream_id"],
+                       epsrel=s["epsrel"], nstart=s["nstart"], nincrease=s["nincrease"],
+                       maxeval=s["maxeval"], nbins=s["nbins"])
+    return O.cuhre(O.genz(s["family"], s["a"], s["u"]), len(s["a"]), epsrel=s["epsrel"],
+                   maxeval=s["maxeval"], max_regions_per_batch=s["max_regions_per_batch"])
+
+
+def _check_oracle(s, r, o):
+    """Bars: Vegas FP64 integral 1e-12 and error 5e-12 (an adapting grid's
+    edges drift apart by ulps between the two sides, which moves the error
+    estimate by up to a few 1e-12: test_gpu_headline); FP32 evaluation
+    integral 1e-6 and error 1e-5 (test_oracle_conditioning); Cuhre integral
+    1e-12, error 1e-10 of itself plus 1e-14 of the integral (sum |I7 - I5|
+    over the regions: the difference cancels digits of I7)."""
+    assert r["status"] == 0
+    assert r["neval"] == o["neval"] and r["fail"] == o["fail"], (s["method"], s["ndim"])
+    if s["method"] == 1:
+        assert r["nregions"] == o["nregions"]
+        assert _rel(r["integral"], o["integral"]) <= 1e-12
+        assert abs(r["error"] - o["error"]) <= 1e-10 * o["error"] + 1e-14 * abs(o["integral"])
+    elif s["flags"] == 0:
+        assert _rel(r["integral"], o["integral"]) <= 1e-12
+        assert _rel(r["error"], o["error"]) <= 5e-12
+    else:
+        assert _rel(r["integral"], o["integral"]) <= 1e-6
+        assert _rel(r["error"], o["error"]) <= 1e-5
+
+
+def _oracle_mix(n, seed):
+    # d 2..16 and epsrel 1e-5..1e-3 as the benchmark draws them, with budgets
+    # the oracle finishes in about a second per request
+    reqs = W.serving_requests(n, rate=1000.0, seed=seed)
+    specs = []
+    for q, r in enumerate(reqs):
+        if r["method"] == 0:
+            specs.append(dict(method=0, ndim=r["ndim"], family=r["family"], a=r["a"], u=r["u"],
+                              seed=r["seed"], stream_id=r["stream_id"], epsrel=r["epsrel"],
+                              nstart=20000, nincrease=10000, maxeval=10**6, nbins=128,
+                              flags=q % 2))
+        else:
+            specs.append(dict(method=1, ndim=r["ndim"], family=r["family"], a=r["a"], u=r["u"],
+                              epsrel=r["epsrel"], maxeval=2 * 10**6,
+                              max_regions_per_batch=5000, flags=0))
+    return specs
+
+
+def test_served_results_match_oracle(cc):
+    import concurrent.futures as cf
+    specs = _oracle_mix(24, 17)
+    assert {s["method"] for s in specs} == {0, 1} and max(s["ndim"] for s in specs) >= 12
+    with cf.ThreadPoolExecutor(max_workers=8) as ex:  # the oracle runs meanwhile
+        futs = [ex.submit(_oracle, s) for s in specs]
+        ctx = cc.Context()
+        tickets = [cc.submit(ctx, s) for s in specs]
+        cc.drain(ctx)
+        results = [cc.poll(ctx, t) for t in tickets]
+        ctx.close()
+        oracle = [f.result() for f in futs]
+    for s, r, o in zip(specs, results, oracle):
+        _check_oracle(s, r, o)
+
+
+def _bench_mix(n, seed=7):
+    # the benchmark's request stream and budgets (bench.py _serving_specs)
+    reqs = W.serving_requests(n, rate=1000.0, seed=seed)
+    specs = []
+    for r in reqs:
+        if r["method"] == 0:
+            specs.append(dict(method=0, ndim=r["ndim"], family=r["family"], a=r["a"], u=r["u"],
+                              seed=r["seed"], stream_id=r["stream_id"], epsrel=r["epsrel"],
+                              nstart=200000, nincrease=100000, maxeval=10**8, nbins=128,
+                              flags=1))
+        else:
+            specs.append(dict(method=1, ndim=r["ndim"], family=r["family"], a=r["a"], u=r["u"],
+                              epsrel=r["epsrel"], maxeval=10**8, max_regions_per_batch=10**5,
+                              flags=0))
+    return specs
+
+
+def test_bench_mix_equals_alone(cc):
+    # the first 40 requests of the benchmark's stream (d up to 16, epsrel
+    # down to 1e-5, Cuhre batches of 1e5 regions), served together, each
+    # against its own run alone
+    specs = _bench_mix(40)
+    ds = [s["ndim"] for s in specs]
+    eps = [s["epsrel"] for s in specs]
+    assert max(ds) >= 14 and min(eps) < 3e-5
+    ctx = cc.Context()
+    tickets = [cc.submit(ctx, s) for s in specs]
+    cc.drain(ctx)
+    results = [cc.poll(ctx, t) for t in tickets]
+    for s, r in zip(specs, results):
+        assert r["status"] == 0 and r["t_done"] >= r["t_submit"]
+        a = _alone(cc, ctx, s)
+        assert r["neval"] == a["neval"] and r["fail"] == a["fail"]
+        if s["method"] == 1:
+            assert r["nregions"] == a["nregions"]
+            assert _rel(r["integral"], a["integral"]) < 1e-12
+            assert _rel(r["error"], a["error"]) < 1e-12
+        else:  # FP32 evaluation: the same points, FP64 sums in another order
+            assert _rel(r["integral"], a["integral"]) < 1e-12
+            assert _rel(r["error"], a["error"]) < 1e-10
+    ctx.close()
+
+
+def test_bench_mix_cuhre_against_oracle(cc):
+    # five of the benchmark stream's Cuhre requests, served together, against
+    # the oracle: requests 4, 11 and 50 converge (d = 11, 13, 9), 29 and 26
+    # run into the 1e8 budget (d = 9 and 16) in batches of up to 1e5 regions
+    import concurrent.futures as cf
+    mix = _bench_mix(60)
+    specs = [mix[q] for q in (4, 11, 26, 29, 50)]
+    assert all(s["method"] == 1 for s in specs) and max(s["ndim"] for s in specs) == 16
+    with cf.ThreadPoolExecutor(max_workers=len(specs)) as ex:  # the oracle runs meanwhile
+        futs = [ex.submit(_oracle, s) for s in specs]
+        ctx = cc.Context()
+        tickets = [cc.submit(ctx, s) for s in specs]
+        cc.drain(ctx)
+        results = [cc.poll(ctx, t) for t in tickets]
+        ctx.close()
+        oracle = [f.result() for f in futs]
+    assert sum(o["fail"] == 1 for o in oracle) == 2
+    for s, r, o in zip(specs, results, oracle):
+        _check_oracle(s, r, o)
