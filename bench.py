@@ -805,6 +805,8 @@ def main():
                     help="run only the Suave leg and print its JSON line (for profiling)")
     ap.add_argument("--divonne-only", action="store_true",
                     help="run only the Divonne-partition leg and print its JSON line")
+    ap.add_argument("--cuhre-only", action="store_true",
+                    help="run only the Cuhre leg and print its JSON line")
     ap.add_argument("--serving-only", action="store_true",
                     help="run only the serving leg and print its JSON line")
     ap.add_argument("--checkpoint-only", action="store_true",
@@ -847,7 +849,8 @@ def main():
         sys.exit(2)
 
     if not (args.tune_only or args.counter_probe or args.traffic_probe or args.suave_only or
-            args.divonne_only or args.checkpoint_only or args.serving_only):
+            args.divonne_only or args.checkpoint_only or args.serving_only or
+            args.cuhre_only):
         _ensure_tuned()
 
     import torch
@@ -897,8 +900,9 @@ def main():
         print(json.dumps({"serving": _serving_leg(cc, args.serving_requests)}))
         return
     ctx = cc.Context(device=0)
-    if args.suave_only or args.divonne_only or args.checkpoint_only:
+    if args.suave_only or args.divonne_only or args.checkpoint_only or args.cuhre_only:
         leg = ({"suave": _suave_leg(cc, ctx, cpu=False)} if args.suave_only else
+               {"cuhre": _cuhre_leg(cc, ctx)} if args.cuhre_only else
                {"divonne_partition": _divonne_leg(cc, ctx, cpu=False)} if args.divonne_only
                else {"checkpoint": _checkpoint_leg(cc, ctx)})
         print(json.dumps(leg))

@@ -224,6 +224,7 @@ int ccuba_init(ccuba_ctx **ctx, int device, size_t hbm_budget) {
   // the allocation-free entry point's scratch: its address on this device
   if (noalloc_init(device) != CCUBA_OK) return CCUBA_EHIP;
   if (suave_set_kernel_limits() != hipSuccess) return CCUBA_EHIP;
+  if (cuhre_set_kernel_limits() != hipSuccess) return CCUBA_EHIP;
   for (int p = 0; p < 2; ++p) {
     c->tune[p].block = (int)env_ll("CCUBA_BLOCK", 256);
     c->tune[p].blocks_per_cu = (int)env_ll("CCUBA_BLOCKS_PER_CU", 3);

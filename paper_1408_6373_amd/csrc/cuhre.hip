@@ -306,20 +306,26 @@ __device__ void rule_region_lane(const RuleArgs &A, const CSeg &S, long long r) 
 
 }  // namespace
 
-__global__ void cuhre_root_kernel(CRegions R, int d) {
+__global__ void cuhre_root_kernel(CRegions R, int d, int *done) {
   const int j = threadIdx.x;
   if (j < d) {
     R.c[j * R.cap] = 0.5;
     R.h[j * R.cap] = 0.5;
   }
-  if (j == 0) R.id[0] = 0;
+  if (j == 0) {
+    R.id[0] = 0;
+    if (done) *done = 0;
+  }
 }
+
+// a run's launches do nothing once its stop flag is set
+__device__ __forceinline__ bool stopped(const int *done) { return done && *done != 0; }
 
 // One integral (A.one), dimension D: one lane per region.
 template <int FAM, int D>
 __global__ void __launch_bounds__(256) gm_rule_lane_kernel(RuleArgs A) {
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= A.total) return;
+  if (g >= A.total || stopped(A.done)) return;
   rule_region_lane<FAM, D>(A, A.one, A.one.first + g);
 }
 
@@ -329,7 +335,7 @@ __global__ void __launch_bounds__(256) gm_rule_kernel(RuleArgs A) {
   __shared__ double sx[4][2 * kMaxDim];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const long long g = (long long)blockIdx.x * 4 + w;
-  if (g >= A.total) return;  // only whole waves leave; no block barrier below
+  if (g >= A.total || stopped(A.done)) return;  // only whole waves leave; no block barrier below
   CSeg S;
   long long before = 0;
   if (A.nseg == 1) {
@@ -380,38 +386,11 @@ __device__ __forceinline__ long long block_excl_scan(long long v, long long *tot
   return off + incl - v;
 }
 
-// count of flag-like predicate per scan tile
-__global__ void __launch_bounds__(kScanBlock) eq_count_kernel(const double *err, long long n,
-                                                              const unsigned long long *prefix,
-                                                              long long *bsum) {
-  const unsigned long long thr = prefix[0];
-  const long long base = (long long)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
-  long long c = 0;
-  for (int q = 0; q < kScanItems; ++q) {
-    const long long i = base + q;
-    if (i < n && key_of(err[i]) == thr) ++c;
-  }
-  long long tot;
-  (void)block_excl_scan(c, &tot);
-  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
-}
-
-__global__ void __launch_bounds__(kScanBlock) flag_count_kernel(const int *flag, long long n,
-                                                                long long *bsum) {
-  const long long base = (long long)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
-  long long c = 0;
-  for (int q = 0; q < kScanItems; ++q) {
-    const long long i = base + q;
-    if (i < n && flag[i]) ++c;
-  }
-  long long tot;
-  (void)block_excl_scan(c, &tot);
-  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
-}
-
 // exclusive scan of nb block sums in one workgroup (sequential carry over
 // chunks of 256)
-__global__ void __launch_bounds__(kScanBlock) scan_bsum_kernel(long long *bsum, long long nb) {
+__global__ void __launch_bounds__(kScanBlock) scan_bsum_kernel(long long *bsum, long long nb,
+                                                               const int *done) {
+  if (stopped(done)) return;
   __shared__ long long carry;
   if (threadIdx.x == 0) carry = 0;
   __syncthreads();
@@ -428,110 +407,14 @@ __global__ void __launch_bounds__(kScanBlock) scan_bsum_kernel(long long *bsum, 
   }
 }
 
-// radix select ----------------------------------------------------------------
-
-__global__ void sel_init_kernel(unsigned long long *prefix, long long *krem, unsigned *hist,
-                                long long K) {
-  prefix[0] = 0ull;
-  prefix[1] = 0ull;
-  krem[0] = K;
-  krem[1] = 0;
-  for (int q = threadIdx.x; q < 256; q += blockDim.x) hist[q] = 0u;
-}
-
-__global__ void __launch_bounds__(256) sel_hist_kernel(const double *err, long long n,
-                                                       const unsigned long long *prefix,
-                                                       unsigned *hist, int shift) {
-  __shared__ unsigned lh[256];
-  lh[threadIdx.x] = 0u;
-  __syncthreads();
-  const unsigned long long pre = prefix[0], mask = prefix[1];
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (long long)gridDim.x * blockDim.x) {
-    const unsigned long long k = key_of(err[i]);
-    if ((k & mask) == pre) atomicAdd(&lh[(k >> shift) & 255ull], 1u);
-  }
-  __syncthreads();
-  if (lh[threadIdx.x]) atomicAdd(&hist[threadIdx.x], lh[threadIdx.x]);
-}
-
-// One workgroup of 256 threads: the digit of the K-th largest key among the
-// keys with the current prefix, from the pass's histogram.  Thread t holds
-// digit 255 - t; an inclusive scan over threads gives, for each digit, the
-// count of keys at or above it.  The digit is the top one where that count
-// reaches the remaining need, or 0 if none does; the need left within it is
-// the need less the keys above it.
-__global__ void __launch_bounds__(256) sel_pick_kernel(unsigned long long *prefix,
-                                                       long long *krem, unsigned *hist,
-                                                       int shift) {
-  __shared__ long long wsum[4];
-  __shared__ int s_dg;
-  __shared__ long long s_need;
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int dg = 255 - t;
-  const long long need = krem[0];
-  const long long c = hist[dg];
-  hist[dg] = 0u;  // ready for the next pass
-  long long incl = c;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const long long v = __shfl_up(incl, o, 64);
-    if (lane >= o) incl += v;
-  }
-  if (lane == 63) wsum[w] = incl;
-  __syncthreads();
-  for (int q = 0; q < w; ++q) incl += wsum[q];
-  const long long excl = incl - c;  // keys above this digit
-  if (excl < need && (incl >= need || dg == 0)) {  // exactly one thread
-    s_dg = dg;
-    s_need = need - excl;
-  }
-  __syncthreads();
-  if (t == 0) {
-    krem[0] = s_need;
-    prefix[0] |= (unsigned long long)s_dg << shift;
-    prefix[1] |= 255ull << shift;
-  }
-}
-
-// flag[i] = key > threshold, or key == threshold and among the first krem
-// such positions
-__global__ void __launch_bounds__(kScanBlock) sel_flag_kernel(const double *err, long long n,
-                                                              const unsigned long long *prefix,
-                                                              const long long *krem,
-                                                              const long long *bsum, int *flag) {
-  const unsigned long long thr = prefix[0];
-  const long long take = krem[0];
-  const long long base = (long long)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
-  unsigned long long k[kScanItems];
-  long long c = 0;
-  for (int q = 0; q < kScanItems; ++q) {
-    const long long i = base + q;
-    k[q] = i < n ? key_of(err[i]) : 0ull;
-    if (i < n && k[q] == thr) ++c;
-  }
-  long long tot;
-  long long rank = bsum[blockIdx.x] + block_excl_scan(c, &tot);
-  for (int q = 0; q < kScanItems; ++q) {
-    const long long i = base + q;
-    if (i >= n) break;
-    int f = 0;
-    if (k[q] > thr) {
-      f = 1;
-    } else if (k[q] == thr) {
-      f = rank < take;
-      ++rank;
-    }
-    flag[i] = f;
-  }
-}
-
 // scatter: keep unselected regions in order, append the halves of selected
 __global__ void __launch_bounds__(kScanBlock) split_kernel(CRegions src, CRegions dst, int d,
                                                            long long n, long long K,
                                                            long long next_id, int all,
                                                            const int *flag,
-                                                           const long long *bsum) {
+                                                           const long long *bsum,
+                                                           const int *done) {
+  if (stopped(done)) return;
   const long long base = (long long)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
   int f[kScanItems];
   long long c = 0;
@@ -583,12 +466,272 @@ __global__ void __launch_bounds__(kScanBlock) split_kernel(CRegions src, CRegion
   }
 }
 
+// top-K by a 16-bit first digit ------------------------------------------------
+//
+// The same selection as the radix select above (the K largest keys, ties to
+// the lower position), in four launches instead of nineteen: the histogram of
+// the keys' top 16 bits (sign, exponent and 4 mantissa bits of the error),
+// the digit that holds the K-th key, the keys and positions of that digit's
+// regions gathered, and the exact K-th (key, position) among them.
+
+constexpr int kTopBins = 1 << 16;
+constexpr int kTopThreads = 1024;
+constexpr int kTopPerThread = kTopBins / kTopThreads;  // 64
+
+// Per block a histogram of 16-bit counters in LDS (two to a 32-bit word: a
+// block sees fewer than 2^16 keys, so a half never carries into the other),
+// added into the global histogram.
+__global__ void __launch_bounds__(kTopThreads) topk_hist_kernel(const double *err, long long n,
+                                                                unsigned *ghist,
+                                                                const int *done) {
+  if (stopped(done)) return;
+  extern __shared__ unsigned lh[];  // kTopBins / 2 words
+  for (int q = threadIdx.x; q < kTopBins / 2; q += kTopThreads) lh[q] = 0u;
+  __syncthreads();
+  for (long long i = (long long)blockIdx.x * kTopThreads + threadIdx.x; i < n;
+       i += (long long)gridDim.x * kTopThreads) {
+    const unsigned b = (unsigned)(key_of(err[i]) >> 48);
+    atomicAdd(&lh[b >> 1], 1u << ((b & 1u) << 4));
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < kTopBins / 2; q += kTopThreads) {
+    const unsigned w = lh[q];
+    if (w & 0xFFFFu) atomicAdd(&ghist[2 * q], w & 0xFFFFu);
+    if (w >> 16) atomicAdd(&ghist[2 * q + 1], w >> 16);
+  }
+}
+
+__device__ __forceinline__ long long block_excl_scan_1024(long long v, long long *total) {
+  __shared__ long long wtot[kTopThreads / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  long long incl = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const long long t = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += t;
+  }
+  if (lane == 63) wtot[w] = incl;
+  __syncthreads();
+  long long off = 0, tot = 0;
+  for (int q = 0; q < kTopThreads / 64; ++q) {
+    if (q < w) off += wtot[q];
+    tot += wtot[q];
+  }
+  __syncthreads();
+  *total = tot;
+  return off + incl - v;
+}
+
+// One workgroup: the digit that holds the K-th largest key (thread t holds
+// the 64 digits below 2^16 - 64 t, in descending order), the rank wanted
+// within it, and the histogram cleared for the next use.
+__global__ void __launch_bounds__(kTopThreads) topk_pick_kernel(unsigned *ghist, long long K,
+                                                                unsigned long long *prefix,
+                                                                long long *krem,
+                                                                unsigned long long *cnt,
+                                                                const int *done) {
+  if (stopped(done)) return;
+  const int t = threadIdx.x;
+  unsigned c[kTopPerThread];
+  long long sum = 0;
+#pragma unroll
+  for (int q = 0; q < kTopPerThread; ++q) {
+    const int b = kTopBins - 1 - (kTopPerThread * t + q);
+    c[q] = ghist[b];
+    sum += c[q];
+  }
+#pragma unroll
+  for (int q = 0; q < kTopPerThread; ++q) ghist[kTopBins - 1 - (kTopPerThread * t + q)] = 0u;
+  long long tot;
+  long long acc = block_excl_scan_1024(sum, &tot);  // keys in digits above this thread's
+  if (acc < K && acc + sum >= K) {  // exactly one thread
+#pragma unroll
+    for (int q = 0; q < kTopPerThread; ++q) {
+      if (acc + (long long)c[q] >= K) {
+        prefix[0] = (unsigned long long)(kTopBins - 1 - (kTopPerThread * t + q));
+        krem[0] = K - acc;  // rank (from 1) wanted within the digit
+        cnt[0] = 0ull;
+        break;
+      }
+      acc += c[q];
+    }
+  }
+}
+
+// The keys and positions of the boundary digit's regions (any order), one
+// atomic add per wavefront.
+__global__ void __launch_bounds__(256) topk_gather_kernel(const double *err, long long n,
+                                                          const unsigned long long *prefix,
+                                                          unsigned long long *ckey,
+                                                          long long *cpos,
+                                                          unsigned long long *cnt,
+                                                          const int *done) {
+  if (stopped(done)) return;
+  const unsigned long long dg = prefix[0];
+  const int lane = threadIdx.x & 63;
+  for (long long i0 = (long long)blockIdx.x * 256; i0 < n; i0 += (long long)gridDim.x * 256) {
+    const long long i = i0 + threadIdx.x;
+    const unsigned long long k = i < n ? key_of(err[i]) : 0ull;
+    const bool m = i < n && (k >> 48) == dg;
+    const unsigned long long bal = __ballot(m);
+    if (bal == 0ull) continue;
+    unsigned long long base = 0;
+    if (lane == (int)__ffsll((long long)bal) - 1) base = atomicAdd(cnt, (unsigned long long)__popcll(bal));
+    base = __shfl(base, __ffsll((long long)bal) - 1, 64);
+    if (m) {
+      const unsigned long long o = base + __popcll(bal & ((1ull << lane) - 1ull));
+      ckey[o] = k;
+      cpos[o] = i;
+    }
+  }
+}
+
+// One workgroup: among the gathered regions, the one of rank krem[0] (from 1)
+// in the order key descending, position ascending, by radix passes of 8 bits
+// over the key's low 48 bits (descending) and then over the position's low
+// 32 bits (ascending).  Writes its key to prefix[0] and its position to
+// krem[0].
+__global__ void __launch_bounds__(kTopThreads) topk_exact_kernel(const unsigned long long *ckey,
+                                                                 const long long *cpos,
+                                                                 const unsigned long long *cnt,
+                                                                 unsigned long long *prefix,
+                                                                 long long *krem,
+                                                                 const int *done) {
+  if (stopped(done)) return;
+  __shared__ unsigned h[256];
+  __shared__ long long s_need;
+  __shared__ int s_dg;
+  const int t = threadIdx.x;
+  const long long m = (long long)cnt[0];
+  long long need = krem[0];
+  unsigned long long pre = prefix[0] << 48, mask = 0xFFFFull << 48;  // key bits fixed so far
+  // key passes: descending digits
+  for (int shift = 40; shift >= 0; shift -= 8) {
+    if (t < 256) h[t] = 0u;
+    __syncthreads();
+    for (long long i = t; i < m; i += kTopThreads) {
+      const unsigned long long k = ckey[i];
+      if ((k & mask) == pre) atomicAdd(&h[(k >> shift) & 255ull], 1u);
+    }
+    __syncthreads();
+    if (t < 64) {  // one wavefront scans the 256 counts from the top digit down
+      unsigned c4[4];
+      long long s4 = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        c4[q] = h[255 - (4 * t + q)];
+        s4 += c4[q];
+      }
+      long long incl = s4;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const long long v = __shfl_up(incl, o, 64);
+        if (t >= o) incl += v;
+      }
+      long long acc = incl - s4;
+      if (acc < need && incl >= need) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (acc + (long long)c4[q] >= need) {
+            s_dg = 255 - (4 * t + q);
+            s_need = need - acc;
+            break;
+          }
+          acc += c4[q];
+        }
+      }
+    }
+    __syncthreads();
+    need = s_need;
+    pre |= (unsigned long long)s_dg << shift;
+    mask |= 255ull << shift;
+    __syncthreads();
+  }
+  // position passes among the regions with the threshold key: ascending
+  // (positions are below 2^32: a region store of 2^32 regions would need
+  // over 500 GB)
+  unsigned long long ppre = 0ull, pmask = 0xFFFFFFFF00000000ull;
+  for (int shift = 24; shift >= 0; shift -= 8) {
+    if (t < 256) h[t] = 0u;
+    __syncthreads();
+    for (long long i = t; i < m; i += kTopThreads) {
+      const unsigned long long p = (unsigned long long)cpos[i];
+      if (ckey[i] == pre && (p & pmask) == ppre) atomicAdd(&h[(p >> shift) & 255ull], 1u);
+    }
+    __syncthreads();
+    if (t < 64) {  // from the lowest digit up
+      unsigned c4[4];
+      long long s4 = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        c4[q] = h[4 * t + q];
+        s4 += c4[q];
+      }
+      long long incl = s4;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const long long v = __shfl_up(incl, o, 64);
+        if (t >= o) incl += v;
+      }
+      long long acc = incl - s4;
+      if (acc < need && incl >= need) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (acc + (long long)c4[q] >= need) {
+            s_dg = 4 * t + q;
+            s_need = need - acc;
+            break;
+          }
+          acc += c4[q];
+        }
+      }
+    }
+    __syncthreads();
+    need = s_need;
+    ppre |= (unsigned long long)s_dg << shift;
+    pmask |= 255ull << shift;
+    __syncthreads();
+  }
+  if (t == 0) {
+    prefix[0] = pre;
+    krem[0] = (long long)ppre;
+  }
+}
+
+// flag[i] = (key, position) at or above the threshold in the selection order,
+// and the per-tile counts of launch_split
+__global__ void __launch_bounds__(kScanBlock) thr_flag_count_kernel(const double *err, long long n,
+                                                                    const unsigned long long *prefix,
+                                                                    const long long *krem,
+                                                                    int *flag, long long *bsum,
+                                                                    const int *done) {
+  if (stopped(done)) return;
+  const unsigned long long thr = prefix[0];
+  const long long tpos = krem[0];
+  const long long base = (long long)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+  long long c = 0;
+  for (int q = 0; q < kScanItems; ++q) {
+    const long long i = base + q;
+    if (i < n) {
+      const unsigned long long k = key_of(err[i]);
+      const int f = k > thr || (k == thr && i <= tpos);
+      flag[i] = f;
+      c += f;
+    }
+  }
+  long long tot;
+  (void)block_excl_scan(c, &tot);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
 // totals ---------------------------------------------------------------------
 
 __global__ void __launch_bounds__(kScanBlock) totals_partial_kernel(const double *I7,
                                                                     const double *err,
                                                                     long long n, double *part,
-                                                                    long long nb) {
+                                                                    long long nb,
+                                                                    const int *done) {
+  if (stopped(done)) return;
   __shared__ double s7[kScanBlock], se[kScanBlock];
   const long long base = (long long)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
   double a = 0.0, b = 0.0;
@@ -639,6 +782,41 @@ __global__ void __launch_bounds__(kScanBlock) totals_final_kernel(const double *
   }
 }
 
+// totals_final, then the stop rule (launch_totals_decide)
+__global__ void __launch_bounds__(kScanBlock) totals_decide_kernel(const double *part, long long nb,
+                                                                   double *out, int *done,
+                                                                   CStop stop) {
+  if (stopped(done)) return;
+  __shared__ double s7[kScanBlock], se[kScanBlock];
+  double a = 0.0, b = 0.0;
+  for (long long i = threadIdx.x; i < nb; i += kScanBlock) {
+    a += part[i];
+    b += part[nb + i];
+  }
+  s7[threadIdx.x] = a;
+  se[threadIdx.x] = b;
+  __syncthreads();
+  for (int o = kScanBlock / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      s7[threadIdx.x] += s7[threadIdx.x + o];
+      se[threadIdx.x] += se[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double I = s7[0], E = se[0];
+    int code = 0;
+    if (!isfinite(I) || !isfinite(E))
+      code = 2;
+    else if (stop.neval >= stop.mineval && E <= fmax(stop.epsabs, stop.epsrel * fabs(I)))
+      code = 1;
+    out[0] = I;
+    out[1] = E;
+    out[2] = (double)code;
+    if (code) *done = 1;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 
@@ -658,7 +836,12 @@ static void launch_rule_lane_d(const RuleArgs &A, unsigned grid, hipStream_t s) 
 }
 
 hipError_t launch_root(const CRegions &R, int ndim, hipStream_t s) {
-  hipLaunchKernelGGL(cuhre_root_kernel, dim3(1), dim3(64), 0, s, R, ndim);
+  hipLaunchKernelGGL(cuhre_root_kernel, dim3(1), dim3(64), 0, s, R, ndim, (int *)nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_root_clear(const CRegions &R, int ndim, int *done, hipStream_t s) {
+  hipLaunchKernelGGL(cuhre_root_kernel, dim3(1), dim3(64), 0, s, R, ndim, done);
   return hipGetLastError();
 }
 
@@ -683,23 +866,22 @@ hipError_t launch_rule(const RuleArgs &A, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_select(const CRegions &R, long long n, long long K, const CScratch &S,
-                         hipStream_t s) {
-  const long long nb = scratch_blocks(n);
-  hipLaunchKernelGGL(sel_init_kernel, dim3(1), dim3(256), 0, s, S.prefix, S.krem, S.hist, K);
-  const int hgrid = (int)std::min<long long>(4096, (n + 255) / 256);
-  for (int pass = 0; pass < 8; ++pass) {
-    const int shift = 56 - 8 * pass;
-    hipLaunchKernelGGL(sel_hist_kernel, dim3(hgrid), dim3(256), 0, s, R.err, n, S.prefix, S.hist,
-                       shift);
-    hipLaunchKernelGGL(sel_pick_kernel, dim3(1), dim3(256), 0, s, S.prefix, S.krem, S.hist,
-                       shift);
-  }
-  hipLaunchKernelGGL(eq_count_kernel, dim3((unsigned)nb), dim3(kScanBlock), 0, s, R.err, n,
-                     S.prefix, S.bsum);
-  hipLaunchKernelGGL(scan_bsum_kernel, dim3(1), dim3(kScanBlock), 0, s, S.bsum, nb);
-  hipLaunchKernelGGL(sel_flag_kernel, dim3((unsigned)nb), dim3(kScanBlock), 0, s, R.err, n,
-                     S.prefix, S.krem, S.bsum, S.flag);
+hipError_t launch_select16(const CRegions &R, long long n, long long K, const CScratch &S,
+                           hipStream_t s) {
+  // blocks see fewer than 2^16 keys each (the LDS counters are 16-bit)
+  const long long per = 32768;
+  const int hgrid = (int)std::max<long long>(std::min<long long>(256, (n + kTopThreads - 1) /
+                                                                          kTopThreads),
+                                             (n + per - 1) / per);
+  hipLaunchKernelGGL(topk_hist_kernel, dim3(hgrid), dim3(kTopThreads), (kTopBins / 2) * 4, s,
+                     R.err, n, S.hist16, (const int *)S.done);
+  hipLaunchKernelGGL(topk_pick_kernel, dim3(1), dim3(kTopThreads), 0, s, S.hist16, K, S.prefix,
+                     S.krem, S.cand_cnt, (const int *)S.done);
+  const int ggrid = (int)std::min<long long>(2048, (n + 255) / 256);
+  hipLaunchKernelGGL(topk_gather_kernel, dim3(ggrid), dim3(256), 0, s, R.err, n, S.prefix,
+                     S.cand_key, S.cand_pos, S.cand_cnt, (const int *)S.done);
+  hipLaunchKernelGGL(topk_exact_kernel, dim3(1), dim3(kTopThreads), 0, s, S.cand_key,
+                     S.cand_pos, S.cand_cnt, S.prefix, S.krem, (const int *)S.done);
   return hipGetLastError();
 }
 
@@ -708,12 +890,13 @@ hipError_t launch_split(const CRegions &src, const CRegions &dst, int ndim, long
                         hipStream_t s) {
   const long long nb = scratch_blocks(n);
   if (!all) {
-    hipLaunchKernelGGL(flag_count_kernel, dim3((unsigned)nb), dim3(kScanBlock), 0, s, S.flag, n,
-                       S.bsum);
-    hipLaunchKernelGGL(scan_bsum_kernel, dim3(1), dim3(kScanBlock), 0, s, S.bsum, nb);
+    hipLaunchKernelGGL(thr_flag_count_kernel, dim3((unsigned)nb), dim3(kScanBlock), 0, s, src.err,
+                       n, S.prefix, S.krem, S.flag, S.bsum, (const int *)S.done);
+    hipLaunchKernelGGL(scan_bsum_kernel, dim3(1), dim3(kScanBlock), 0, s, S.bsum, nb,
+                       (const int *)S.done);
   }
   hipLaunchKernelGGL(split_kernel, dim3((unsigned)nb), dim3(kScanBlock), 0, s, src, dst, ndim, n,
-                     K, next_id, all ? 1 : 0, S.flag, S.bsum);
+                     K, next_id, all ? 1 : 0, S.flag, S.bsum, (const int *)S.done);
   return hipGetLastError();
 }
 
@@ -721,11 +904,25 @@ hipError_t launch_totals(const CRegions &R, long long n, const CScratch &S, doub
                          hipStream_t s) {
   const long long nb = scratch_blocks(n);
   hipLaunchKernelGGL(totals_partial_kernel, dim3((unsigned)nb), dim3(kScanBlock), 0, s, R.I7,
-                     R.err, n, S.tot, nb);
+                     R.err, n, S.tot, nb, (const int *)S.done);
   hipLaunchKernelGGL(totals_final_kernel, dim3(1), dim3(kScanBlock), 0, s, S.tot, nb, out);
   return hipGetLastError();
 }
 
-hipError_t cuhre_set_kernel_limits() { return hipSuccess; }
+hipError_t launch_totals_decide(const CRegions &R, long long n, const CScratch &S, double *out,
+                                const CStop &stop, hipStream_t s) {
+  const long long nb = scratch_blocks(n);
+  hipLaunchKernelGGL(totals_partial_kernel, dim3((unsigned)nb), dim3(kScanBlock), 0, s, R.I7,
+                     R.err, n, S.tot, nb, (const int *)S.done);
+  hipLaunchKernelGGL(totals_decide_kernel, dim3(1), dim3(kScanBlock), 0, s, S.tot, nb, out,
+                     S.done, stop);
+  return hipGetLastError();
+}
+
+hipError_t cuhre_set_kernel_limits() {
+  // the top-K histogram keeps 2^16 16-bit counters in LDS (128 KB)
+  return hipFuncSetAttribute((const void *)topk_hist_kernel,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (kTopBins / 2) * 4);
+}
 
 }  // namespace ccuba

@@ -131,9 +131,12 @@ int CuhreRun::ensure(long long need, hipStream_t s) {
   if ((rc = alloc_store(R_[1], c_[1], h_[1], vals_[1], axis_[1], id_[1], cap))) return rc;
   const long long nb = scratch_blocks(cap);
   if ((rc = flag_.alloc(ctx_, cap)) || (rc = bsum_.alloc(ctx_, nb)) ||
-      (rc = tot_.alloc(ctx_, 2 * nb)))
+      (rc = tot_.alloc(ctx_, 2 * nb)) || (rc = cand_key_.alloc(ctx_, cap)) ||
+      (rc = cand_pos_.alloc(ctx_, cap)))
     return rc;
   cap_ = cap;
+  S_.cand_key = cand_key_.p;
+  S_.cand_pos = cand_pos_.p;
   S_.flag = flag_.p;
   S_.bsum = bsum_.p;
   S_.tot = tot_.p;
@@ -155,14 +158,19 @@ int CuhreRun::start(const CuhreSpec &spec, hipStream_t s) {
   cap_ = 0;
   int rc;
   if ((rc = prefix_.alloc(ctx_, 2)) || (rc = krem_.alloc(ctx_, 2)) ||
-      (rc = hist_.alloc(ctx_, 256)) || (rc = out_.alloc(ctx_, 2)) ||
+      (rc = out_.alloc(ctx_, 2)) ||
       (rc = params_.alloc(ctx_, 2 * kParamRow)) || (rc = w7_.alloc(ctx_, 17 * 5)) ||
       (rc = w5_.alloc(ctx_, 17 * 5)) || (rc = seg_.alloc(ctx_, 1)) ||
-      (rc = seg_end_.alloc(ctx_, 1)))
+      (rc = seg_end_.alloc(ctx_, 1)) || (rc = stop_.alloc(ctx_, 1)) ||
+      (rc = hist16_.alloc(ctx_, 1 << 16)) || (rc = cand_cnt_.alloc(ctx_, 1)))
     return rc;
+  S_.done = stop_.p;
+  S_.hist16 = hist16_.p;
+  S_.cand_cnt = cand_cnt_.p;
+  // (the top-K kernels leave the histogram cleared after every use)
+  CCUBA_HIP(hipMemsetAsync(hist16_.p, 0, (1 << 16) * sizeof(unsigned), s));
   S_.prefix = prefix_.p;
   S_.krem = krem_.p;
-  S_.hist = hist_.p;
   // room for the first few batches, so that the store rarely grows (growing
   // means new allocations and a copy)
   const long long first_cap = std::max<long long>(
@@ -183,8 +191,11 @@ int CuhreRun::start(const CuhreSpec &spec, hipStream_t s) {
   cap_ = cap0;
   const long long nb = scratch_blocks(cap_);
   if ((rc = flag_.alloc(ctx_, cap_)) || (rc = bsum_.alloc(ctx_, nb)) ||
-      (rc = tot_.alloc(ctx_, 2 * nb)))
+      (rc = tot_.alloc(ctx_, 2 * nb)) || (rc = cand_key_.alloc(ctx_, cap_)) ||
+      (rc = cand_pos_.alloc(ctx_, cap_)))
     return rc;
+  S_.cand_key = cand_key_.p;
+  S_.cand_pos = cand_pos_.p;
   S_.flag = flag_.p;
   S_.bsum = bsum_.p;
   S_.tot = tot_.p;
@@ -205,8 +216,8 @@ int CuhreRun::start(const CuhreSpec &spec, hipStream_t s) {
   CCUBA_HIP(hipMemcpyAsync(params_.p, hp64_, sizeof(hp64_), hipMemcpyHostToDevice, s));
   CCUBA_HIP(hipMemcpyAsync(w7_.p, T.w7, sizeof(T.w7), hipMemcpyHostToDevice, s));
   CCUBA_HIP(hipMemcpyAsync(w5_.p, T.w5, sizeof(T.w5), hipMemcpyHostToDevice, s));
-  // root region [0,1]^d: centre 1/2, half-width 1/2, id 0
-  CCUBA_HIP(launch_root(R_[0], d, s));
+  // root region [0,1]^d: centre 1/2, half-width 1/2, id 0; the stop flag clear
+  CCUBA_HIP(launch_root_clear(R_[0], d, stop_.p, s));
   CSeg seg{};
   seg.ndim = d;
   seg.family = spec.family;
@@ -220,12 +231,12 @@ int CuhreRun::start(const CuhreSpec &spec, hipStream_t s) {
 }
 
 int CuhreRun::launch_rule_alone(const CSeg &seg, hipStream_t s) {
-  return launch_rule_segments(ctx_, &seg, 1, seg_, seg_end_, w7_.p, w5_.p, s);
+  return launch_rule_segments(ctx_, &seg, 1, seg_, seg_end_, w7_.p, w5_.p, s, stop_.p);
 }
 
 int launch_rule_segments(ccuba_ctx *ctx, const CSeg *segs, int nseg, DevBuf<CSeg> &dsegs,
                          DevBuf<long long> &dends, const double *w7_dev, const double *w5_dev,
-                         hipStream_t s) {
+                         hipStream_t s, const int *done) {
   if (nseg <= 0) return CCUBA_OK;
   int rc;
   std::vector<long long> ends(nseg);
@@ -251,6 +262,7 @@ int launch_rule_segments(ccuba_ctx *ctx, const CSeg *segs, int nseg, DevBuf<CSeg
   }
   A.w7 = w7_dev;
   A.w5 = w5_dev;
+  A.done = done;
   A.l2 = T.l2;
   A.l3 = T.l3;
   A.l4 = T.l4;
@@ -325,7 +337,7 @@ int CuhreRun::plan_and_split(hipStream_t s) {
   int rc = ensure(n_ + K, s);
   if (rc) return rc < 0 ? rc : CCUBA_EHIP;
   const bool all = K == n_;
-  if (!all) CCUBA_HIP(launch_select(R_[cur_], n_, K, S_, s));
+  if (!all) CCUBA_HIP(launch_select16(R_[cur_], n_, K, S_, s));
   CCUBA_HIP(launch_split(R_[cur_], R_[1 - cur_], spec_.ndim, n_, K, next_id_, all, S_, s));
   cur_ = 1 - cur_;
   pendK_ = K;
@@ -352,18 +364,129 @@ void CuhreRun::commit_pending() {
 }
 
 int CuhreRun::run(hipStream_t s) {
-  for (;;) {
-    int rc = launch_totals(s);
+  // The host state of a step before its totals: what the host plans is
+  // deterministic (K depends on n and the budget only); only the end of the
+  // run is decided on the device.
+  struct Plan {
+    long long n, neval, next_id;
+    int cur, batches;
+  };
+  // totals of step t go to slot t % 2: 4 doubles (I, err, decision, -) in
+  // mapped pinned memory if the caller gave it, else in out_
+  double *dev_slots = nullptr, *host_slots = nullptr;
+  DevBuf<double> slots;
+  if (mapped_host_) {
+    dev_slots = mapped_dev_;
+    host_slots = mapped_host_;
+  } else {
+    int rc = slots.alloc(ctx_, 8);
     if (rc) return rc;
-    if (mapped_host_) CCUBA_HIP(hipStreamSynchronize(s));  // totals written to host memory
-    if ((rc = read_totals(s))) return rc;
-    rc = plan_and_split(s);
-    if (rc < 0) return rc;
-    if (rc == 0) break;
-    if ((rc = launch_rule_alone(pending_segment(), s))) return rc;
-    commit_pending();
+    dev_slots = slots.p;
   }
-  return CCUBA_OK;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  CCUBA_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+  if (hipEventCreateWithFlags(&ev[1], hipEventDisableTiming) != hipSuccess) {
+    (void)hipEventDestroy(ev[0]);
+    return CCUBA_EHIP;
+  }
+  struct Events {
+    hipEvent_t *e;
+    ~Events() {
+      (void)hipEventDestroy(e[0]);
+      (void)hipEventDestroy(e[1]);
+    }
+  } guard{ev};
+  // the outcome of step t's totals: 0 go on, 1 converged, 2 not finite.
+  // The event is polled: a blocking wait adds a wake-up of ~10 us to every
+  // step, longer than a small step's work.
+  auto outcome = [&](int t, double *I, double *E) -> int {
+    hipError_t q;
+    while ((q = hipEventQuery(ev[t & 1])) == hipErrorNotReady) {
+    }
+    if (q != hipSuccess) return CCUBA_EHIP;
+    double v[4];
+    if (host_slots) {
+      for (int k = 0; k < 4; ++k) v[k] = host_slots[4 * (t & 1) + k];
+    } else {
+      CCUBA_HIP(hipMemcpy(v, dev_slots + 4 * (t & 1), sizeof(v), hipMemcpyDeviceToHost));
+    }
+    *I = v[0];
+    *E = v[1];
+    return (int)v[2];
+  };
+  // finish with the state of step t (its totals decided the end)
+  auto finish = [&](const Plan &p, int code, double I, double E) -> int {
+    CCUBA_HIP(hipStreamSynchronize(s));  // queued launches run empty; the last ones end
+    n_ = p.n;
+    neval_ = p.neval;
+    next_id_ = p.next_id;
+    cur_ = p.cur;
+    batches_ = p.batches;
+    done_ = true;
+    pendK_ = 0;
+    if (code == 2) {  // a non-finite integrand value
+      fail_ = -4;
+      I_ = E_ = 0.0;
+    } else {
+      fail_ = code == 1 ? 0 : 1;
+      I_ = I;
+      E_ = E;
+    }
+    return CCUBA_OK;
+  };
+  // Outcomes are learned in step order; `known' is the last step learned
+  // (all of them "go on"), with its totals.
+  int known = -1;
+  double kI = 0.0, kE = 0.0;
+  // learn step q's outcome (the state before its work is p); true when it
+  // ended the run, which is then finished
+  auto learn = [&](int q, const Plan &p, int *rc) -> bool {
+    double I, E;
+    const int code = outcome(q, &I, &E);
+    if (code < 0) {
+      *rc = code;
+      return true;
+    }
+    known = q;
+    kI = I;
+    kE = E;
+    if (code == 0) return false;
+    *rc = finish(p, code, I, E);
+    return true;
+  };
+  Plan prev{};
+  for (int t = 0;; ++t) {
+    const Plan cur{n_, neval_, next_id_, cur_, batches_};
+    const CStop stop{spec_.epsrel, spec_.epsabs, spec_.mineval, neval_};
+    CCUBA_HIP(launch_totals_decide(R_[cur_], n_, S_, dev_slots + 4 * (t & 1), stop, s));
+    CCUBA_HIP(hipEventRecord(ev[t & 1], s));
+    long long K = std::min(spec_.batch / 2, n_);
+    const long long budget = spec_.maxeval > neval_ ? (spec_.maxeval - neval_) / (2 * np_) : 0;
+    K = std::min(K, budget);
+    int rc = 0;
+    if (K > 0 && n_ + K > cap_) {
+      // the store must grow (a synchronisation and a copy): only for a step
+      // known to run, so learn steps t - 1 and t first
+      if (t - 1 > known && learn(t - 1, prev, &rc)) return rc;
+      if (learn(t, cur, &rc)) return rc;
+      if ((rc = ensure(n_ + K, s))) return rc < 0 ? rc : CCUBA_EHIP;
+    }
+    if (K > 0) {  // queue step t's work, possibly before learning step t - 1's outcome
+      const bool all = K == n_;
+      if (!all) CCUBA_HIP(launch_select16(R_[cur_], n_, K, S_, s));
+      CCUBA_HIP(launch_split(R_[cur_], R_[1 - cur_], spec_.ndim, n_, K, next_id_, all, S_, s));
+      cur_ = 1 - cur_;
+      pendK_ = K;
+      if ((rc = launch_rule_alone(pending_segment(), s))) return rc;
+      commit_pending();
+    }
+    if (t - 1 > known && learn(t - 1, prev, &rc)) return rc;
+    if (K <= 0) {  // out of budget after step t, unless its totals ended it first
+      if (t > known && learn(t, cur, &rc)) return rc;
+      return finish(cur, 0, kI, kE);  // fail 1
+    }
+    prev = cur;
+  }
 }
 
 int CuhreRun::rule_only(long long nreg, const double *c, const double *h, double *I7, double *I5,

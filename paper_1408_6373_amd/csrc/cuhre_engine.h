@@ -46,7 +46,11 @@ class CuhreRun {
     mapped_host_ = host;
     mapped_dev_ = dev;
   }
-  // Run to completion alone.
+  // Run to completion alone.  The host queues each step's selection, split
+  // and rule launch before it learns whether the step's totals end the run
+  // (the totals kernel decides on the device and sets the run's stop flag,
+  // which turns the queued launches into empty ones), so the device does not
+  // wait for the host between steps.
   int run(hipStream_t s);
   int rule_only(long long nreg, const double *c, const double *h, double *I7, double *I5,
                 double *err, int *axis, hipStream_t s);
@@ -80,9 +84,12 @@ class CuhreRun {
   DevBuf<long long> id_[2];
   DevBuf<unsigned long long> prefix_;
   DevBuf<long long> krem_, bsum_;
-  DevBuf<unsigned> hist_;
   DevBuf<int> flag_;
   DevBuf<double> tot_, out_, params_, w7_, w5_;
+  DevBuf<int> stop_;  // the run's stop flag (CScratch::done)
+  DevBuf<unsigned> hist16_;  // the top-K digit histogram (CScratch::hist16)
+  DevBuf<unsigned long long> cand_key_, cand_cnt_;
+  DevBuf<long long> cand_pos_;
   DevBuf<CSeg> seg_;
   DevBuf<long long> seg_end_;
   CScratch S_{};
@@ -94,6 +101,6 @@ class CuhreRun {
 // and ends are host arrays copied to the device buffers given.
 int launch_rule_segments(ccuba_ctx *ctx, const CSeg *segs, int nseg, DevBuf<CSeg> &dsegs,
                          DevBuf<long long> &dends, const double *w7_dev, const double *w5_dev,
-                         hipStream_t s);
+                         hipStream_t s, const int *done = nullptr);
 
 }  // namespace ccuba
