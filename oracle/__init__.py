@@ -65,9 +65,12 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_build.LIB):
-            _build.build()
-        L = C.CDLL(_build.LIB)
+        # ORACLE_SANITIZE=1: the AddressSanitizer/UBSan build (oracle/sanitize.py)
+        san = os.environ.get("ORACLE_SANITIZE") == "1"
+        path = _build.SAN_LIB if san else _build.LIB
+        if not os.path.exists(path):
+            _build.build(sanitize=san)
+        L = C.CDLL(path)
         dp = C.POINTER(C.c_double)
         L.oracle_philox4x32_10.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
                                            C.POINTER(C.c_uint32)]
