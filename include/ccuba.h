@@ -15,8 +15,9 @@
  *    point; nvec and userdata therefore disappear;
  *  - the `spin' argument (Sect. 3.2.3) becomes a context handle with the same
  *    three cases (see ccuba_ctx);
- *  - two entry points are added: a batch of independent Vegas integrals in one
- *    persistent launch, and a submit/poll pair for a serving loop.
+ *  - two entry points are added: a batch of independent Vegas integrals that
+ *    share the device launches of every iteration, and a submit/poll pair
+ *    for a serving loop.
  *
  * Conventions for every function:
  *  - return value: CCUBA_OK (0) or a negative CCUBA_E* status; nothing is
@@ -119,7 +120,9 @@ int ccuba_shutdown(ccuba_ctx **ctx);
  * Returns CCUBA_ENOENT for an unknown key, CCUBA_EINVAL for a bad value. */
 int ccuba_config(ccuba_ctx *ctx, const char *key, long long value);
 
-/* Read one setting into *value: the keys of ccuba_config; the DoSample
+/* Read one setting into *value (the settings take the place of the
+ * environment variables and cubaaccel/cubacores calls of Sect. 3.2.4, so a
+ * caller can see what is in force): the keys of ccuba_config; the DoSample
  * launch settings ("block", "blocks_per_cu", "hist64", "ilp", "min_tile") are
  * those of `precision' (CCUBA_FP64 or CCUBA_FP32_EVAL), e.g. after an
  * autotuned batch.  Returns CCUBA_ENOENT for an unknown key. */
@@ -159,7 +162,10 @@ typedef struct {
   double *grid;     /* out: final grid, ndim * (nbins + 1) */
 } ccuba_vegas_trace;
 
-/* ccuba_vegas with a trace (trace may be NULL). */
+/* ccuba_vegas with a trace (trace may be NULL): besides the outputs of the
+ * Sect. 3.2.2 prototype, each iteration's estimate and variance, the chi^2
+ * that prob is taken from, and the final grid, written before return into
+ * the caller's arrays (capacities as given in the struct). */
 int ccuba_vegas_ex(ccuba_ctx **ctx, int ndim, int ncomp, const ccuba_integrand *f,
                    double epsrel, double epsabs, int flags,
                    unsigned long long seed, long long mineval, long long maxeval,
@@ -216,15 +222,17 @@ int ccuba_vegas_source(ccuba_ctx **ctx, int ndim, const char *source, const doub
                        unsigned int stream_id, long long *neval, int *fail, double integral[],
                        double error[], double prob[]);
 
-/* The compiler's message of ctx's last run-time compilation, null-terminated
- * and cut to size bytes (empty if none).  Errors: CCUBA_EINVAL. */
+/* The compiler's message of ctx's last run-time compilation of a caller's
+ * integrand (the Sect. 3.2.2 integrand as device code), null-terminated and
+ * cut to size bytes (empty if none), written into the caller's buf.
+ * Errors: CCUBA_EINVAL. */
 int ccuba_rtc_log(ccuba_ctx *ctx, char *buf, size_t size);
 
 /* ---- caller-evaluated integrands ---------------------------------------
  * The integrand declaration of Sect. 3.2.2 with its nvec and core arguments:
  * x[*nvec][*ndim] points, f[*nvec][*ncomp] values for the integrand to fill.
  * Returning -999 aborts the integration at once; any other value goes on.
- * core is -1: the points come in the accelerator strategy of Sect. 3.2.5. */
+ * core is -1: the points come in the accelerator strategy of Sect. 3.2.4. */
 typedef int (*ccuba_batch_integrand)(const int *ndim, const double x[], const int *ncomp,
                                      double f[], void *userdata, const int *nvec,
                                      const int *core);
@@ -235,7 +243,7 @@ enum { CCUBA_POINTS_HOST = 0, CCUBA_POINTS_DEVICE = 1 };
 /* Vegas of a caller's integrand (the same sampling, combination and stop rule
  * as ccuba_vegas, over ncomp components).  Each iteration's points are made
  * on the GPU and handed to the integrand in batches of exactly nvec points
- * (fewer only in an iteration's last batch; Sect. 3.2.5).  With
+ * (fewer only in an iteration's last batch; Sect. 3.2.4).  With
  * CCUBA_POINTS_HOST x and f are host arrays the library owns; with
  * CCUBA_POINTS_DEVICE they are device arrays on the context's GPU, and the
  * integrand's writes to f must be complete when it returns (for work it
@@ -353,7 +361,9 @@ int ccuba_cuhre(ccuba_ctx **ctx, int ndim, int ncomp, const ccuba_integrand *f,
                 int *nregions, long long *neval, int *fail, double integral[],
                 double error[], double prob[]);
 
-/* The Cuhre rule alone on a batch of regions (the DoSample of Cuhre).
+/* The Cuhre rule alone on a batch of regions: the DoSample of Cuhre
+ * (Sect. 2.1: the sampling routine every integrator calls), one launch for
+ * all nreg regions.
  * c[ndim*nreg] and h[ndim*nreg] are host arrays of centres and half-widths,
  * structure-of-arrays (dimension-major: c[j*nreg + r]).  Outputs per region:
  * I7, I5, err = |I7 - I5|, split axis.  Any output may be NULL.
@@ -383,37 +393,74 @@ typedef struct {
   double t_submit, t_done;    /* seconds on the context's steady clock */
 } ccuba_result;
 
-/* Run njobs independent Vegas integrals together: every iteration of every
- * job still running is one persistent DoSample launch over a work list of
- * (integral, point range) tiles, followed by one refine launch; the
- * iteration pair is replayed from a captured hipGraph.  Each job's result is
- * the one ccuba_vegas gives for it alone (same points; sums within
- * rounding).  out[njobs].  Jobs with method != 0 get status CCUBA_EINVAL.
- * Errors: CCUBA_EINVAL, CCUBA_EHIP, CCUBA_ENOMEM. */
+/* Run njobs independent Vegas integrals together.  DoSample (Sect. 2.1) is
+ * the one routine every integrator samples through, and the paper splits one
+ * call's n points into batches for N workers; here the points of all jobs'
+ * current iterations are split into tiles of (job, point range), and the
+ * tiles of every job still running go out together: one sampling launch per
+ * class of tile shape (precision, Philox blocks per point, bins a power of
+ * two or not, tile full or ragged), each a persistent grid over that class's
+ * tile list, then one fold of the partial sums and one refine launch for all
+ * jobs.  The launches of an iteration are replayed from a captured hipGraph.
+ * Like nbatch (Sect. 3.2.7), the tiling partitions the sampling internally
+ * and changes neither the points nor what the integrand sees: each job's
+ * result is the one ccuba_vegas gives for it alone (same points; sums in
+ * another order, within rounding).
+ * jobs[njobs]: host array, read during the call; jobs[j].f's arrays are
+ * copied.  out[njobs]: host array, written before the call returns; a job
+ * that fails on its own (method != 0, or an argument out of range) gets
+ * status CCUBA_EINVAL in its out[j] while the others run.
+ * Errors: CCUBA_EINVAL (njobs < 0, a NULL array), CCUBA_EHIP, CCUBA_ENOMEM
+ * (the jobs' grids and partial sums exceed the context's budget). */
 int ccuba_vegas_batch(ccuba_ctx *ctx, int njobs, const ccuba_job jobs[],
                       ccuba_result out[]);
 
 /* ---- serving loop -------------------------------------------------------
- * ccuba_submit queues one Vegas or Cuhre request and returns a ticket; a
- * background thread of the context admits queued requests while slots and
- * the HBM budget allow, keeps their grids and region heaps resident, runs the
- * next Vegas iteration of every resident Vegas request in one batched launch
- * and the next region batch of every resident Cuhre request in one batched
- * rule launch per tick, and retires finished requests.  ccuba_poll returns
- * 0 and fills *out once the ticket is done (the ticket is then forgotten),
- * 1 while pending, CCUBA_ENOENT for an unknown ticket.  ccuba_drain waits
- * until every submitted request is done. */
+ * The spinning workers of Sect. 3.2.3 carried further: the context keeps a
+ * background thread that stays up between integrations (it starts at the
+ * first ccuba_submit and stops in ccuba_shutdown, the cubawait analog), and
+ * requests reach it while others run, as batches reach the next free worker
+ * in Sect. 3.2.4.  Each tick the thread admits queued requests while slots
+ * and the HBM budget allow, keeps their grids and region heaps resident, runs
+ * the next Vegas iteration of every resident Vegas request as one batch
+ * (ccuba_vegas_batch's launches) and the next region batch of every resident
+ * Cuhre request in one rule launch, and retires finished requests.  A
+ * request's outputs are those of the Sect. 3.2.2 prototypes and equal what
+ * ccuba_vegas or ccuba_cuhre gives it alone.
+ *
+ * ccuba_submit: *job is read during the call (its integrand arrays copied);
+ * *ticket receives the request's id.  Errors: CCUBA_EINVAL (a NULL pointer,
+ * method not 0 or 1, ndim outside 1..16), CCUBA_ENOMEM (host allocation of
+ * the loop).  A request whose other arguments are out of range, or whose
+ * memory can never fit the budget, is accepted and finishes with status
+ * CCUBA_EINVAL or CCUBA_ENOMEM in its result.
+ * ccuba_poll: returns 0 and fills *out once the ticket is done (the ticket is
+ * then forgotten), 1 while pending, CCUBA_ENOENT for an unknown or already
+ * collected ticket.
+ * ccuba_drain: blocks until every submitted request is done (at once if
+ * nothing was ever submitted).  If a tick of the loop fails on the device,
+ * the requests it held finish with that status (CCUBA_EHIP, CCUBA_ENOMEM) in
+ * their results. */
 int ccuba_submit(ccuba_ctx *ctx, const ccuba_job *job, unsigned long long *ticket);
 int ccuba_poll(ccuba_ctx *ctx, unsigned long long ticket, ccuba_result *out);
 int ccuba_drain(ccuba_ctx *ctx);
 
 /* ---- device-buffer entry points (for callers that own memory/streams) ---
- * One DoSample pass of Vegas iteration `iteration' over n points on the FP64
- * grid grid_dev[ndim*(nbins+1)] (device memory), on the caller's HIP stream
- * (NULL: the default stream).  Writes sums_dev[2] = (sum w f, sum (w f)^2)
- * and hist_dev[ndim*nbins] = per-bin sums of (w f)^2, all FP64 device memory
- * owned by the caller and never freed here.  Asynchronous on the stream.
- * Errors: CCUBA_EINVAL, CCUBA_EHIP, CCUBA_ENOMEM. */
+ * One DoSample pass (Sect. 2.1: sample n points, here over every compute
+ * unit at once) of Vegas iteration `iteration' over npts points on the FP64
+ * grid grid_dev[ndim*(nbins+1)] (device memory, dimension-major, each row
+ * nbins+1 ascending edges from 0 to 1), on the caller's HIP stream (NULL: the
+ * default stream).  Writes sums_dev[2] = (sum w f, sum (w f)^2) and
+ * hist_dev[ndim*nbins] = per-bin sums of (w f)^2, all FP64 device memory
+ * owned by the caller and never freed here.  The job is given by its fields
+ * (ndim, nbins, f, flags, seed, stream_id) rather than a ccuba_job, since
+ * one pass needs none of the convergence settings.  Work already on the
+ * stream runs first; the call returns once the pass has finished on it (the
+ * partial sums it allocates are freed on return).
+ * Ranges: 1 <= ndim <= 16, 2 <= nbins <= 256, npts >= 2,
+ * 0 <= iteration < 2^24.
+ * Errors: CCUBA_EINVAL (a range or a NULL pointer), CCUBA_EHIP,
+ * CCUBA_ENOMEM. */
 int ccuba_vegas_dosample_raw(ccuba_ctx *ctx, int ndim, int nbins,
                              const ccuba_integrand *f, int flags,
                              unsigned long long seed, unsigned int stream_id,
@@ -440,24 +487,32 @@ int ccuba_vegas_dosample_raw_noalloc(ccuba_ctx *ctx, int ndim, int nbins,
                                      int iteration, long long npts, const double *grid_dev,
                                      double *sums_dev, double *hist_dev, void *hip_stream);
 
-/* The points DoSample draws (steps: Philox words, uniform, grid map, weight)
- * for points [i0, i0+npts) of iteration `iteration' on the host grid
- * grid[ndim*(nbins+1)], computed on the device by the same code.  Outputs
- * (host, any may be NULL): words[npts*4*ceil(ndim/4)], x[npts*ndim], w[npts],
- * bin[npts*ndim].  Errors: CCUBA_EINVAL, CCUBA_EHIP. */
+/* The points DoSample draws (Sect. 2.1; steps: Philox words, uniform, grid
+ * map, weight) for points [i0, i0+npts) of iteration `iteration' on the
+ * host grid grid[ndim*(nbins+1)], computed on the device by the same code
+ * as the sampling kernels.  The paper's master alone generates the samples,
+ * so that no random number is used twice (Sect. 2); here point i's words
+ * are a pure function of (seed, stream_id, iteration, i), which gives the
+ * same guarantee without a master.  Outputs (host, any may be NULL, written
+ * before return): words[npts*4*ceil(ndim/4)], x[npts*ndim] (point-major),
+ * w[npts], bin[npts*ndim].  Errors: CCUBA_EINVAL, CCUBA_EHIP. */
 int ccuba_vegas_points(ccuba_ctx *ctx, int ndim, int nbins, int flags,
                        unsigned long long seed, unsigned int stream_id,
                        int iteration, const double *grid, long long i0,
                        long long npts, uint32_t *words, double *x, double *w,
                        int *bin);
 
-/* One Lepage grid refinement on the device: hist[ndim*nbins] accumulated
- * (w f)^2 per bin, grid_in[ndim*(nbins+1)] -> grid_out (host arrays).
+/* One Lepage grid refinement on the device, the step between two DoSample
+ * passes of Vegas (Sect. 2.1 leaves the integrator's own algorithm
+ * unchanged; the refinement is Lepage's): hist[ndim*nbins] accumulated
+ * (w f)^2 per bin, grid_in[ndim*(nbins+1)] -> grid_out (host arrays, read
+ * and written during the call; grid_out may equal grid_in).
  * Errors: CCUBA_EINVAL, CCUBA_EHIP. */
 int ccuba_vegas_refine(ccuba_ctx *ctx, int ndim, int nbins, const double *hist,
                        const double *grid_in, double *grid_out);
 
-/* Kernel timing of the context, measured with HIP events recorded on the
+/* Kernel timing of the context, for timing measurements like those of
+ * Sect. 4.2 taken on the device side; measured with HIP events recorded on the
  * stream each kernel is launched on, around the sampling kernels, the fold of
  * their partial sums and the refine launch of every Vegas iteration, and
  * around every Cuhre rule launch, while the context's "profile" setting is 1
@@ -475,10 +530,13 @@ typedef struct {
   double fold_ms;          /* summed time of the partial-sum folds */
 } ccuba_stats;
 
-/* Copy the context's counters to *out and reset them when reset != 0. */
+/* Copy the context's counters to *out (host, written before return) and reset
+ * them when reset != 0.  Errors: CCUBA_EINVAL (NULL argument). */
 int ccuba_stats_get(ccuba_ctx *ctx, ccuba_stats *out, int reset);
 
-/* Name of a status code. */
+/* Name of a status code: a static string, never freed; "unknown status" for a
+ * value that is no CCUBA_E* code.  The statuses are this library's; the
+ * integrators' own outcome stays in `fail' (Sect. 3.2.2). */
 const char *ccuba_strerror(int status);
 
 #ifdef __cplusplus

@@ -1,6 +1,6 @@
 // vegas_batched.cpp -- Vegas with a caller-evaluated integrand.
 //
-// The accelerator strategy of Sect. 3.2.5: the integrand receives batches of
+// The accelerator strategy of Sect. 3.2.4: the integrand receives batches of
 // exactly nvec points, fewer only in an iteration's last batch, as
 // x[nvec][ndim] with f[nvec][ncomp] to fill (the integrand declaration of
 // Sect. 3.2.2, core < 0 for an accelerator).  The library makes each batch's
@@ -102,7 +102,7 @@ int vegas_batched(ccuba_ctx *ctx, const BatchedSpec &sp, ccuba_batch_integrand f
   long long tend = 0;
   VState st0{};
   long long handed = 0;  // points given to the integrand
-  const int core = -1;   // an accelerator (Sect. 3.2.5)
+  const int core = -1;   // an accelerator (Sect. 3.2.4)
   for (int t = 0; t < iters; ++t) {
     const long long n = sp.nstart + (long long)t * sp.nincrease;
     int tiles = 0;

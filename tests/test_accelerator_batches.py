@@ -1,4 +1,4 @@
-"""The accelerator batching example of Sect. 3.2.5 (tests/golden/
+"""The accelerator batching example of Sect. 3.2.4 (tests/golden/
 accelerator_batches.txt): 2400 points with p_accel = 1000 go out as batches
 of 1000, 1000 and 400.  The oracle's integrand calls (CPU) and the device
 path's caller-integrand batches (GPU) must both reproduce it."""

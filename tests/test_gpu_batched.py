@@ -1,5 +1,5 @@
 """GPU parity of Vegas with a caller-evaluated integrand (points handed over
-in batches of nvec, Sect. 3.2.5; several components) against the CPU oracle,
+in batches of nvec, Sect. 3.2.4; several components) against the CPU oracle,
 which calls the same Python integrand in the same batches.
 
 Bars: neval and fail equal; integral, error and prob within 1e-12 relative
