@@ -5,12 +5,16 @@
 namespace ccuba {
 
 // Structure-of-arrays store of the subregions of one integral (the resident
-// region heap).  c and h are dimension-major: c[j * cap + r].
+// region heap).  c and h are dimension-major: c[j * cap + r].  The store only
+// grows, so a region's position is its id: the root is 0, and the children
+// of the j-th region split in a step (in position order) go to next + 2j and
+// next + 2j + 1, next being the store's length before the step.  A region
+// that has been split stays where it is, retired: its error is set to -1,
+// which no live region's |I7 - I5| can be.
 struct CRegions {
   double *c, *h;
   double *I7, *I5, *err;
   int *axis;
-  long long *id;
   long long cap;
 };
 
@@ -20,6 +24,22 @@ struct CSeg {
   const double *par;  // [2][kParamRow] Genz constants of the integral (FP64 row)
   long long first, count;
   CRegions regs;
+  // children != 0 (count even): regions first + 2j and first + 2j + 1 are
+  // the lower and upper halves, along its split axis, of the region at
+  // position parent[j] (parent set) or pbase + j (parent null); the rule
+  // launch forms and stores their centres and widths first.  With retire,
+  // the lower child's thread also retires the parent.  children == 0: the
+  // regions' centres and widths are already in the store.
+  int children, retire;
+  const long long *parent;
+  long long pbase;
+};
+
+// What ends a run after a step's totals: the accuracy test (neval >= mineval
+// and err <= max(epsabs, epsrel |I|)) or a total that is not finite.
+struct CStop {
+  double epsrel, epsabs;
+  long long mineval, neval;
 };
 
 struct RuleArgs {
@@ -33,65 +53,59 @@ struct RuleArgs {
   const int *done;           // a run's stop flag (null: none): set, the launch does nothing
 };
 
-// Per-integral scratch for selection, compaction and totals.
+// Per-integral scratch for selection, splitting and totals.
 struct CScratch {
-  unsigned long long *prefix;  // [2]: selected key prefix, mask; then the threshold key
-  long long *krem;             // [2]: remaining K, count of keys == threshold to take;
-                               // then the threshold position
-  int *flag;                   // [cap] selection flags
-  long long *bsum;             // [nblocks] block sums for scans
-  double *tot;                 // [nblocks*2] partial totals, [2] final (I, err)
+  unsigned long long *prefix;  // [1]: the boundary digit, then the threshold key
+  long long *krem;             // [1]: the rank wanted within the digit, then the
+                               // threshold position
+  long long *bsum;             // [nblocks] block counts, then their exclusive scan
+  double *tot;                 // [nblocks*2] partial totals
   long long nbmax;
+  long long *parent;           // [cap / 2] positions of the regions split in a step
   // The run's stop flag, set on the device when a step's totals end the run
   // (null: none).  Every selection, split, totals and rule kernel launched
   // with it does nothing once it is set, so that a host that has queued the
   // next step before learning the outcome of this one loses nothing but the
   // empty launches.
   int *done;
-  // top-K by a 16-bit first digit: the digit histogram (zero between uses),
-  // and the keys and positions of the boundary digit's regions ([cap] each)
+  // top-K by a 16-bit first digit: the digit histogram and the histogram of
+  // its top 8 bits (zero between uses), and the keys and positions of the
+  // boundary digit's regions ([cap] each)
   unsigned *hist16;
+  unsigned *coarse;
   unsigned long long *cand_key;
   long long *cand_pos;
   unsigned long long *cand_cnt;  // [1]
 };
 
-// What ends a run after a step's totals: the accuracy test (neval >= mineval
-// and err <= max(epsabs, epsrel |I|)) or a total that is not finite.
-struct CStop {
-  double epsrel, epsabs;
-  long long mineval, neval;
-};
-
 hipError_t launch_rule(const RuleArgs &A, hipStream_t s);
-// The root region of [0,1]^d (centre 1/2, half-width 1/2, id 0) at position 0.
-hipError_t launch_root(const CRegions &R, int ndim, hipStream_t s);
-// Top-K selection of n regions by (err desc, position asc), positions in
-// ascending id order: a histogram of the keys' top 16 bits finds the boundary
-// digit, then an exact rank among the boundary digit's regions only gives the
-// threshold (key, position), written to S.prefix[0], S.krem[0]; launch_split's
-// counting pass sets the flags of the K chosen.
-hipError_t launch_select16(const CRegions &R, long long n, long long K, const CScratch &S,
+// Top-K selection among the m regions of a store (retired ones never
+// qualify) by (err desc, position asc): a histogram of the keys' top 16 bits
+// finds the boundary digit, then an exact rank among the boundary digit's
+// regions only gives the threshold (key, position), written to S.prefix[0],
+// S.krem[0].
+hipError_t launch_select16(const CRegions &R, long long m, long long K, const CScratch &S,
                            hipStream_t s);
-// Copy unselected regions of `src' to the front of `dst' in order, the two
-// children of the j-th selected region (ascending position) to
-// dst[n - K + 2j], dst[n - K + 2j + 1], with ids next_id + 2j, + 2j + 1.
-// Unless all regions split, the selection is the threshold that
-// launch_select16 left in S.
-hipError_t launch_split(const CRegions &src, const CRegions &dst, int ndim, long long n,
-                        long long K, long long next_id, bool all, const CScratch &S,
+// The split of the K regions at or above the threshold that launch_select16
+// left in S: each is retired and its position written to S.parent[j], j its
+// rank in position order.  A rule launch in children mode (CSeg::parent =
+// S.parent) then forms and evaluates the children.
+hipError_t launch_split(const CRegions &R, long long m, long long K, const CScratch &S,
                         hipStream_t s);
-// Fixed-order totals of I7 and err over n regions into out[0], out[1].
-hipError_t launch_totals(const CRegions &R, long long n, const CScratch &S, double *out,
+// Fixed-order totals of I7 and err over the live regions among the m of a
+// store into out[0], out[1].
+hipError_t launch_totals(const CRegions &R, long long m, const CScratch &S, double *out,
                          hipStream_t s);
 // The same, then the stop rule of `stop': out[2] = 0 (go on), 1 (converged)
 // or 2 (a total is not finite), and in the last two cases S.done is set.
 // Nothing is written once S.done is set.
-hipError_t launch_totals_decide(const CRegions &R, long long n, const CScratch &S, double *out,
+hipError_t launch_totals_decide(const CRegions &R, long long m, const CScratch &S, double *out,
                                 const CStop &stop, hipStream_t s);
-// The root region, and the run's stop flag cleared.
+// The root region of [0,1]^d (centre 1/2, half-width 1/2) at position 0, and
+// the run's stop flag cleared (done may be null).
 hipError_t launch_root_clear(const CRegions &R, int ndim, int *done, hipStream_t s);
 long long scratch_blocks(long long n);
+
 hipError_t cuhre_set_kernel_limits();
 
 }  // namespace ccuba

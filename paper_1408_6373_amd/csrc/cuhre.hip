@@ -14,12 +14,21 @@
 //             - (l2^2/l3^2)(f(c+l3 h_j e_j) + f(c-l3 h_j e_j) - 2 f(c))|,
 //    whose arg-max (lowest j on ties) is the split axis.  A launch takes a
 //    list of segments, so regions of several integrals share one launch.
-// a9 (region step): radix select of the K largest errors (8 passes of 8
-//    bits over the IEEE bit pattern, which orders non-negative doubles;
-//    ties go to the lower position, i.e. the lower region id), then one
-//    scan-and-scatter pass that keeps the unselected regions in order and
-//    writes the two halves of every selected region at the end, and a
-//    fixed-order reduction for the totals.  No step waits on another block.
+// a9 (region step): the store of regions only grows (a region's position is
+//    its id) and a split region is retired in place.  Selection of the K
+//    largest errors by a 16-bit digit histogram and an exact rank within the
+//    boundary digit (ties go to the lower position, i.e. the lower region
+//    id); a counting pass and a scan give each selected region its rank j,
+//    and the rule launch forms the two halves of the j-th at the end of the
+//    store before it evaluates them; a fixed-order reduction gives the
+//    totals.  Where a step needs the whole grid's results (a scan of block
+//    counts, a reduction of block sums, a pick from the histogram), a
+//    one-workgroup kernel follows: no block ever waits for another, and no
+//    block fences for another (a device-scope release writes back the L2
+//    of its XCD, ~0.7 us each, serialised per XCD, which costs more per
+//    block than a kernel boundary costs once).
+#include <algorithm>
+
 #include "cuhre.h"
 #include "genz.h"
 
@@ -29,6 +38,7 @@ namespace {
 
 constexpr int kLaneRuleMaxDim = 8;          // lane-per-region rule up to this d
 constexpr long long kLaneRuleMinRegions = 16384;  // and from this many regions on
+constexpr long long kWaveRuleBlocks = 2048;       // most blocks of a wave-per-region launch
 constexpr int kScanItems = 4;
 constexpr int kScanBlock = 256;
 constexpr int kScanTile = kScanItems * kScanBlock;  // elements per scan block
@@ -39,8 +49,38 @@ __device__ __forceinline__ double wsum(double v) {
   return v;
 }
 
+// Selection key of a region: the IEEE bit pattern of its error plus one,
+// which orders the non-negative doubles; 0 for a retired region (negative
+// error), below every live one.
 __device__ __forceinline__ unsigned long long key_of(double e) {
-  return (unsigned long long)__double_as_longlong(e);
+  const unsigned long long b = (unsigned long long)__double_as_longlong(e);
+  return (b >> 63) ? 0ull : b + 1ull;
+}
+
+__device__ __forceinline__ bool retired(double e) { return signbit(e); }
+
+// The geometry of region r of a segment: loaded, or formed from its parent
+// (children mode) and stored.  Lane `j' (< d) handles coordinate j.
+__device__ __forceinline__ void child_coord(const CSeg &S, long long r, int j, double *cj,
+                                            double *hj) {
+  const long long cap = S.regs.cap;
+  if (!S.children) {
+    *cj = S.regs.c[j * cap + r];
+    *hj = S.regs.h[j * cap + r];
+    return;
+  }
+  const long long k = r - S.first;
+  const long long p = S.parent ? S.parent[k >> 1] : S.pbase + (k >> 1);
+  double c = S.regs.c[j * cap + p], h = S.regs.h[j * cap + p];
+  if (j == S.regs.axis[p]) {
+    h = h / 2.0;
+    c = (k & 1) ? c + h : c - h;
+  }
+  S.regs.c[j * cap + r] = c;
+  S.regs.h[j * cap + r] = h;
+  if (S.retire && j == 0 && !(k & 1)) S.regs.err[p] = -1.0;
+  *cj = c;
+  *hj = h;
 }
 
 // Evaluate the Genz family FAM at the rule point described by (cls, i, jj,
@@ -75,16 +115,13 @@ __device__ __forceinline__ double rule_point_f(int d, const double *c, const dou
   return Genz<double, FAM>::finish(acc, d);
 }
 
+// One region per wavefront; returns (I7, err) in lane 0.
 template <int FAM>
-__device__ void rule_region(const RuleArgs &A, const CSeg &S, long long r, int w, int lane,
-                            double (*sc)[kMaxDim], double (*sh)[kMaxDim],
-                            double (*sf)[4 * kMaxDim + 1], double (*sx)[2 * kMaxDim]) {
+__device__ double2 rule_region(const RuleArgs &A, const CSeg &S, long long r, int w, int lane,
+                               double (*sc)[kMaxDim], double (*sh)[kMaxDim],
+                               double (*sf)[4 * kMaxDim + 1], double (*sx)[2 * kMaxDim]) {
   const int d = S.ndim;
-  const long long cap = S.regs.cap;
-  if (lane < d) {
-    sc[w][lane] = S.regs.c[lane * cap + r];
-    sh[w][lane] = S.regs.h[lane * cap + r];
-  }
+  if (lane < d) child_coord(S, r, lane, &sc[w][lane], &sh[w][lane]);
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -193,7 +230,9 @@ __device__ void rule_region(const RuleArgs &A, const CSeg &S, long long r, int w
     S.regs.I5[r] = I5;
     S.regs.err[r] = fabs(I7 - I5);
     S.regs.axis[r] = best;
+    return make_double2(I7, fabs(I7 - I5));
   }
+  return make_double2(0.0, 0.0);
 }
 
 // One lane per region, for a single integral of dimension D <= 8: every lane
@@ -221,13 +260,31 @@ __device__ __forceinline__ double lane_point(const double (&c)[D], const double 
 }
 
 template <int FAM, int D>
-__device__ void rule_region_lane(const RuleArgs &A, const CSeg &S, long long r) {
+__device__ double2 rule_region_lane(const RuleArgs &A, const CSeg &S, long long r) {
   const long long cap = S.regs.cap;
   double c[D], h[D];
+  if (!S.children) {
 #pragma unroll
-  for (int j = 0; j < D; ++j) {
-    c[j] = S.regs.c[j * cap + r];
-    h[j] = S.regs.h[j * cap + r];
+    for (int j = 0; j < D; ++j) {
+      c[j] = S.regs.c[j * cap + r];
+      h[j] = S.regs.h[j * cap + r];
+    }
+  } else {  // a child: formed from its parent, as child_coord does per axis
+    const long long k = r - S.first;
+    const long long p = S.parent ? S.parent[k >> 1] : S.pbase + (k >> 1);
+    const int ax = S.regs.axis[p];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      c[j] = S.regs.c[j * cap + p];
+      h[j] = S.regs.h[j * cap + p];
+      if (j == ax) {
+        h[j] = h[j] / 2.0;
+        c[j] = (k & 1) ? c[j] + h[j] : c[j] - h[j];
+      }
+      S.regs.c[j * cap + r] = c[j];
+      S.regs.h[j * cap + r] = h[j];
+    }
+    if (S.retire && !(k & 1)) S.regs.err[p] = -1.0;
   }
   const double *p0 = S.par;
   const double *p1 = S.par + kParamRow;
@@ -302,6 +359,7 @@ __device__ void rule_region_lane(const RuleArgs &A, const CSeg &S, long long r) 
   S.regs.I5[r] = I5;
   S.regs.err[r] = fabs(I7 - I5);
   S.regs.axis[r] = best;
+  return make_double2(I7, fabs(I7 - I5));
 }
 
 }  // namespace
@@ -312,53 +370,92 @@ __global__ void cuhre_root_kernel(CRegions R, int d, int *done) {
     R.c[j * R.cap] = 0.5;
     R.h[j * R.cap] = 0.5;
   }
-  if (j == 0) {
-    R.id[0] = 0;
-    if (done) *done = 0;
-  }
+  if (j == 0 && done) *done = 0;
 }
 
 // a run's launches do nothing once its stop flag is set
 __device__ __forceinline__ bool stopped(const int *done) { return done && *done != 0; }
 
+namespace {
+
+// Sums over a 256-thread block in a fixed order (a butterfly in each
+// wavefront, lane 0's result, then the four wavefronts in order); every
+// thread gets the sums.
+__device__ __forceinline__ double2 block_sum2(double a, double b) {
+  __shared__ double s[2][4];
+  a = wsum(a);
+  b = wsum(b);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();  // an earlier call's readers are done with s
+  if ((threadIdx.x & 63) == 0) {
+    s[0][w] = a;
+    s[1][w] = b;
+  }
+  __syncthreads();
+  return make_double2((s[0][0] + s[0][1]) + (s[0][2] + s[0][3]),
+                      (s[1][0] + s[1][1]) + (s[1][2] + s[1][3]));
+}
+
+// The stop rule on a step's totals (one thread).
+__device__ __forceinline__ void decide(double I, double E, const CStop &stop, double *out,
+                                       int *done) {
+  int code = 0;
+  if (!isfinite(I) || !isfinite(E))
+    code = 2;
+  else if (stop.neval >= stop.mineval && E <= fmax(stop.epsabs, stop.epsrel * fabs(I)))
+    code = 1;
+  out[0] = I;
+  out[1] = E;
+  out[2] = (double)code;
+  if (code && done) *done = 1;
+}
+
+}  // namespace
+
 // One integral (A.one), dimension D: one lane per region.
 template <int FAM, int D>
 __global__ void __launch_bounds__(256) gm_rule_lane_kernel(RuleArgs A) {
+  if (stopped(A.done)) return;
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= A.total || stopped(A.done)) return;
-  rule_region_lane<FAM, D>(A, A.one, A.one.first + g);
+  if (g < A.total) (void)rule_region_lane<FAM, D>(A, A.one, A.one.first + g);
 }
 
+// A wavefront per region, the regions of a launch taken in turn by the grid's
+// wavefronts (a launch has at most kWaveRuleBlocks blocks).
 __global__ void __launch_bounds__(256) gm_rule_kernel(RuleArgs A) {
   __shared__ double sc[4][kMaxDim], sh[4][kMaxDim];
   __shared__ double sf[4][4 * kMaxDim + 1];
   __shared__ double sx[4][2 * kMaxDim];
+  if (stopped(A.done)) return;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const long long g = (long long)blockIdx.x * 4 + w;
-  if (g >= A.total || stopped(A.done)) return;  // only whole waves leave; no block barrier below
-  CSeg S;
-  long long before = 0;
-  if (A.nseg == 1) {
-    S = A.one;
-  } else {
-    int lo = 0, hi = A.nseg - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (A.seg_end[mid] > g)
-        hi = mid;
-      else
-        lo = mid + 1;
+  for (long long g = (long long)blockIdx.x * 4 + w; g < A.total; g += (long long)gridDim.x * 4) {
+    CSeg S;
+    long long before = 0;
+    if (A.nseg == 1) {
+      S = A.one;
+    } else {
+      int lo = 0, hi = A.nseg - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (A.seg_end[mid] > g)
+          hi = mid;
+        else
+          lo = mid + 1;
+      }
+      S = A.segs[lo];
+      before = lo > 0 ? A.seg_end[lo - 1] : 0;
     }
-    S = A.segs[lo];
-    before = lo > 0 ? A.seg_end[lo - 1] : 0;
-  }
-  const long long r = S.first + (g - before);
-  switch (S.family) {
-    case GAUSSIAN: rule_region<GAUSSIAN>(A, S, r, w, lane, sc, sh, sf, sx); break;
-    case OSCILLATORY: rule_region<OSCILLATORY>(A, S, r, w, lane, sc, sh, sf, sx); break;
-    case PRODUCT_PEAK: rule_region<PRODUCT_PEAK>(A, S, r, w, lane, sc, sh, sf, sx); break;
-    case CORNER_PEAK: rule_region<CORNER_PEAK>(A, S, r, w, lane, sc, sh, sf, sx); break;
-    default: rule_region<C0>(A, S, r, w, lane, sc, sh, sf, sx); break;
+    const long long r = S.first + (g - before);
+    switch (S.family) {
+      case GAUSSIAN: rule_region<GAUSSIAN>(A, S, r, w, lane, sc, sh, sf, sx); break;
+      case OSCILLATORY: rule_region<OSCILLATORY>(A, S, r, w, lane, sc, sh, sf, sx); break;
+      case PRODUCT_PEAK: rule_region<PRODUCT_PEAK>(A, S, r, w, lane, sc, sh, sf, sx); break;
+      case CORNER_PEAK: rule_region<CORNER_PEAK>(A, S, r, w, lane, sc, sh, sf, sx); break;
+      default: rule_region<C0>(A, S, r, w, lane, sc, sh, sf, sx); break;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();  // the LDS rows are reused by the next region
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
 
@@ -386,120 +483,109 @@ __device__ __forceinline__ long long block_excl_scan(long long v, long long *tot
   return off + incl - v;
 }
 
-// exclusive scan of nb block sums in one workgroup (sequential carry over
-// chunks of 256)
+// Whether the region at position i is at or above the threshold (key thr,
+// position tpos) in the selection order (key descending, position
+// ascending).
+__device__ __forceinline__ bool selected(double e, long long i, unsigned long long thr,
+                                         long long tpos) {
+  const unsigned long long k = key_of(e);
+  return k > thr || (k == thr && i <= tpos);
+}
+
+// Per tile of kScanTile positions, the count of selected regions.
+__global__ void __launch_bounds__(kScanBlock) sel_count_kernel(const double *err, long long m,
+                                                               const unsigned long long *prefix,
+                                                               const long long *krem,
+                                                               long long *bsum, const int *done) {
+  if (stopped(done)) return;
+  const unsigned long long thr = prefix[0];
+  const long long tpos = krem[0];
+  const long long base = (long long)blockIdx.x * kScanTile;
+  long long c = 0;
+#pragma unroll
+  for (int q = 0; q < kScanItems; ++q) {
+    const long long i = base + q * kScanBlock + threadIdx.x;
+    if (i < m && selected(err[i], i, thr, tpos)) ++c;
+  }
+  long long tot;
+  (void)block_excl_scan(c, &tot);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+// One workgroup: the exclusive scan of the nb tile counts, in chunks of 256
+// with a carry.
 __global__ void __launch_bounds__(kScanBlock) scan_bsum_kernel(long long *bsum, long long nb,
                                                                const int *done) {
   if (stopped(done)) return;
-  __shared__ long long carry;
-  if (threadIdx.x == 0) carry = 0;
-  __syncthreads();
+  long long carry = 0;
   for (long long c0 = 0; c0 < nb; c0 += kScanBlock) {
     const long long i = c0 + threadIdx.x;
     const long long v = i < nb ? bsum[i] : 0;
-    long long tot;
-    const long long ex = block_excl_scan(v, &tot);
-    const long long cr = carry;
-    if (i < nb) bsum[i] = cr + ex;
-    __syncthreads();
-    if (threadIdx.x == 0) carry = cr + tot;
-    __syncthreads();
+    long long t2;
+    const long long ex = block_excl_scan(v, &t2);
+    if (i < nb) bsum[i] = carry + ex;
+    carry += t2;
   }
 }
 
-// scatter: keep unselected regions in order, append the halves of selected
-__global__ void __launch_bounds__(kScanBlock) split_kernel(CRegions src, CRegions dst, int d,
-                                                           long long n, long long K,
-                                                           long long next_id, int all,
-                                                           const int *flag,
-                                                           const long long *bsum,
-                                                           const int *done) {
+// Each selected region is retired and its position written to parent[j],
+// j its rank in position order: the tile's scanned count plus the selected
+// positions before it in the tile (the tile's kScanItems chunks of 256 in
+// order, within a chunk the wavefronts in order, within a wavefront the
+// lanes below).
+__global__ void __launch_bounds__(kScanBlock) split_mark_kernel(double *err, long long m,
+                                                                const unsigned long long *prefix,
+                                                                const long long *krem,
+                                                                const long long *bsum,
+                                                                long long *parent, long long K,
+                                                                const int *done) {
   if (stopped(done)) return;
-  const long long base = (long long)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
-  int f[kScanItems];
-  long long c = 0;
+  __shared__ int cnt[kScanItems][kScanBlock / 64];
+  const unsigned long long thr = prefix[0];
+  const long long tpos = krem[0];
+  const long long base = (long long)blockIdx.x * kScanTile;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  bool f[kScanItems];
+  unsigned long long bal[kScanItems];
+#pragma unroll
   for (int q = 0; q < kScanItems; ++q) {
-    const long long i = base + q;
-    f[q] = i < n ? (all ? 1 : flag[i]) : 0;
-    c += f[q];
+    const long long i = base + q * kScanBlock + threadIdx.x;
+    f[q] = i < m && selected(err[i], i, thr, tpos);
+    bal[q] = __ballot(f[q]);
+    if (lane == 0) cnt[q][w] = __popcll(bal[q]);
   }
-  long long tot;
-  long long rank = (all ? (long long)blockIdx.x * kScanTile : bsum[blockIdx.x]) +
-                   block_excl_scan(c, &tot);
-  const long long cbase = n - K;
+  __syncthreads();
+  const unsigned long long below = (1ull << lane) - 1ull;
+  long long rank = bsum[blockIdx.x];
+#pragma unroll
   for (int q = 0; q < kScanItems; ++q) {
-    const long long i = base + q;
-    if (i >= n) break;
-    if (!f[q]) {
-      const long long o = i - rank;
-      for (int j = 0; j < d; ++j) {
-        dst.c[j * dst.cap + o] = src.c[j * src.cap + i];
-        dst.h[j * dst.cap + o] = src.h[j * src.cap + i];
-      }
-      dst.I7[o] = src.I7[i];
-      dst.I5[o] = src.I5[i];
-      dst.err[o] = src.err[i];
-      dst.axis[o] = src.axis[i];
-      dst.id[o] = src.id[i];
-    } else {
-      const long long o0 = cbase + 2 * rank, o1 = o0 + 1;
-      const int s = src.axis[i];
-      for (int j = 0; j < d; ++j) {
-        const double cj = src.c[j * src.cap + i], hj = src.h[j * src.cap + i];
-        if (j == s) {
-          const double hh = hj / 2.0;
-          dst.c[j * dst.cap + o0] = cj - hh;
-          dst.c[j * dst.cap + o1] = cj + hh;
-          dst.h[j * dst.cap + o0] = hh;
-          dst.h[j * dst.cap + o1] = hh;
-        } else {
-          dst.c[j * dst.cap + o0] = cj;
-          dst.c[j * dst.cap + o1] = cj;
-          dst.h[j * dst.cap + o0] = hj;
-          dst.h[j * dst.cap + o1] = hj;
-        }
-      }
-      dst.id[o0] = next_id + 2 * rank;
-      dst.id[o1] = next_id + 2 * rank + 1;
-      ++rank;
+    long long pre = 0, all = 0;
+#pragma unroll
+    for (int v = 0; v < kScanBlock / 64; ++v) {
+      if (v < w) pre += cnt[q][v];
+      all += cnt[q][v];
     }
+    const long long j = rank + pre + __popcll(bal[q] & below);
+    if (f[q] && j < K) {  // (exactly K are selected)
+      const long long i = base + q * kScanBlock + threadIdx.x;
+      parent[j] = i;
+      err[i] = -1.0;
+    }
+    rank += all;
   }
 }
 
 // top-K by a 16-bit first digit ------------------------------------------------
 //
-// The same selection as the radix select above (the K largest keys, ties to
-// the lower position), in four launches instead of nineteen: the histogram of
-// the keys' top 16 bits (sign, exponent and 4 mantissa bits of the error),
-// the digit that holds the K-th key, the keys and positions of that digit's
-// regions gathered, and the exact K-th (key, position) among them.
+// The K largest keys, ties to the lower position, in four launches: the
+// histogram of the keys' top 16 bits (sign, exponent and 4 mantissa bits of
+// the error) and of their top 8 bits; the digit that holds the K-th key (the
+// 8-bit digit first, then the 16-bit one within it); the keys and positions
+// of that digit's regions gathered; the exact K-th (key, position) among
+// them.
 
 constexpr int kTopBins = 1 << 16;
 constexpr int kTopThreads = 1024;
-constexpr int kTopPerThread = kTopBins / kTopThreads;  // 64
-
-// Per block a histogram of 16-bit counters in LDS (two to a 32-bit word: a
-// block sees fewer than 2^16 keys, so a half never carries into the other),
-// added into the global histogram.
-__global__ void __launch_bounds__(kTopThreads) topk_hist_kernel(const double *err, long long n,
-                                                                unsigned *ghist,
-                                                                const int *done) {
-  if (stopped(done)) return;
-  extern __shared__ unsigned lh[];  // kTopBins / 2 words
-  for (int q = threadIdx.x; q < kTopBins / 2; q += kTopThreads) lh[q] = 0u;
-  __syncthreads();
-  for (long long i = (long long)blockIdx.x * kTopThreads + threadIdx.x; i < n;
-       i += (long long)gridDim.x * kTopThreads) {
-    const unsigned b = (unsigned)(key_of(err[i]) >> 48);
-    atomicAdd(&lh[b >> 1], 1u << ((b & 1u) << 4));
-  }
-  __syncthreads();
-  for (int q = threadIdx.x; q < kTopBins / 2; q += kTopThreads) {
-    const unsigned w = lh[q];
-    if (w & 0xFFFFu) atomicAdd(&ghist[2 * q], w & 0xFFFFu);
-    if (w >> 16) atomicAdd(&ghist[2 * q + 1], w >> 16);
-  }
-}
 
 __device__ __forceinline__ long long block_excl_scan_1024(long long v, long long *total) {
   __shared__ long long wtot[kTopThreads / 64];
@@ -522,63 +608,109 @@ __device__ __forceinline__ long long block_excl_scan_1024(long long v, long long
   return off + incl - v;
 }
 
-// One workgroup: the digit that holds the K-th largest key (thread t holds
-// the 64 digits below 2^16 - 64 t, in descending order), the rank wanted
-// within it, and the histogram cleared for the next use.
-__global__ void __launch_bounds__(kTopThreads) topk_pick_kernel(unsigned *ghist, long long K,
+// Among 256 counts (thread t < 256 holds cnt, the count of digit 255 - t, so
+// the threads run from the top digit down), the digit where the running
+// count reaches `need': its number and the need left within it.
+__device__ __forceinline__ void pick_digit(long long cnt, long long need, int *dg,
+                                           long long *left) {
+  __shared__ int s_dg;
+  __shared__ long long s_left;
+  const int t = threadIdx.x;
+  if (t == 0) {  // (not reached while need <= the total, as it always is)
+    s_dg = 0;
+    s_left = 1;
+  }
+  long long tot;
+  const long long above = block_excl_scan_1024(t < 256 ? cnt : 0, &tot);
+  if (t < 256 && above < need && above + cnt >= need) {
+    s_dg = 255 - t;
+    s_left = need - above;
+  }
+  __syncthreads();
+  *dg = s_dg;
+  *left = s_left;
+  __syncthreads();
+}
+
+// Per block a histogram of 16-bit counters in LDS (two to a 32-bit word: a
+// block sees fewer than 2^16 keys, so a half never carries into the other),
+// added into the global 16-bit-digit histogram and its 8-bit-digit one.
+__global__ void __launch_bounds__(kTopThreads) topk_hist_kernel(const double *err, long long m,
+                                                                unsigned *ghist,
+                                                                unsigned *gcoarse,
+                                                                const int *done) {
+  if (stopped(done)) return;
+  extern __shared__ unsigned lh[];  // kTopBins / 2 words, then 256 coarse counters
+  unsigned *lc = lh + kTopBins / 2;
+  for (int q = threadIdx.x; q < kTopBins / 2 + 256; q += kTopThreads) lh[q] = 0u;
+  __syncthreads();
+  for (long long i = (long long)blockIdx.x * kTopThreads + threadIdx.x; i < m;
+       i += (long long)gridDim.x * kTopThreads) {
+    const unsigned b = (unsigned)(key_of(err[i]) >> 48);
+    atomicAdd(&lh[b >> 1], 1u << ((b & 1u) << 4));
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < kTopBins / 2; q += kTopThreads) {
+    const unsigned w = lh[q], lo = w & 0xFFFFu, hi = w >> 16;
+    if (lo) atomicAdd(&ghist[2 * q], lo);
+    if (hi) atomicAdd(&ghist[2 * q + 1], hi);
+    if (w) atomicAdd(&lc[q >> 7], lo + hi);  // words q hold digits 2q, 2q + 1
+  }
+  __syncthreads();
+  if (threadIdx.x < 256 && lc[threadIdx.x]) atomicAdd(&gcoarse[threadIdx.x], lc[threadIdx.x]);
+}
+
+// One workgroup: the boundary digit to prefix[0] and the rank wanted within
+// it (from 1) to krem[0]; the 8-bit histogram and the candidate count are
+// cleared (the 16-bit one by the gather).
+__global__ void __launch_bounds__(kTopThreads) topk_pick_kernel(unsigned *ghist,
+                                                                unsigned *gcoarse, long long K,
                                                                 unsigned long long *prefix,
                                                                 long long *krem,
                                                                 unsigned long long *cnt,
                                                                 const int *done) {
   if (stopped(done)) return;
   const int t = threadIdx.x;
-  unsigned c[kTopPerThread];
-  long long sum = 0;
-#pragma unroll
-  for (int q = 0; q < kTopPerThread; ++q) {
-    const int b = kTopBins - 1 - (kTopPerThread * t + q);
-    c[q] = ghist[b];
-    sum += c[q];
-  }
-#pragma unroll
-  for (int q = 0; q < kTopPerThread; ++q) ghist[kTopBins - 1 - (kTopPerThread * t + q)] = 0u;
-  long long tot;
-  long long acc = block_excl_scan_1024(sum, &tot);  // keys in digits above this thread's
-  if (acc < K && acc + sum >= K) {  // exactly one thread
-#pragma unroll
-    for (int q = 0; q < kTopPerThread; ++q) {
-      if (acc + (long long)c[q] >= K) {
-        prefix[0] = (unsigned long long)(kTopBins - 1 - (kTopPerThread * t + q));
-        krem[0] = K - acc;  // rank (from 1) wanted within the digit
-        cnt[0] = 0ull;
-        break;
-      }
-      acc += c[q];
-    }
+  int hi8, lo8;
+  long long need;
+  pick_digit(t < 256 ? (long long)gcoarse[255 - t] : 0, K, &hi8, &need);
+  pick_digit(t < 256 ? (long long)ghist[(hi8 << 8) + 255 - t] : 0, need, &lo8, &need);
+  if (t < 256) gcoarse[t] = 0u;
+  if (t == 0) {
+    prefix[0] = (unsigned long long)((hi8 << 8) | lo8);
+    krem[0] = need;
+    cnt[0] = 0ull;
   }
 }
 
 // The keys and positions of the boundary digit's regions (any order), one
-// atomic add per wavefront.
-__global__ void __launch_bounds__(256) topk_gather_kernel(const double *err, long long n,
-                                                          const unsigned long long *prefix,
-                                                          unsigned long long *ckey,
-                                                          long long *cpos,
-                                                          unsigned long long *cnt,
-                                                          const int *done) {
+// atomic add per wavefront; the 16-bit histogram is cleared for the next
+// selection.
+__global__ void __launch_bounds__(kTopThreads) topk_gather_kernel(const double *err, long long m,
+                                                                  const unsigned long long *prefix,
+                                                                  unsigned long long *ckey,
+                                                                  long long *cpos,
+                                                                  unsigned long long *cnt,
+                                                                  unsigned *ghist,
+                                                                  const int *done) {
   if (stopped(done)) return;
   const unsigned long long dg = prefix[0];
   const int lane = threadIdx.x & 63;
-  for (long long i0 = (long long)blockIdx.x * 256; i0 < n; i0 += (long long)gridDim.x * 256) {
+  for (long long i = (long long)blockIdx.x * kTopThreads + threadIdx.x; i < kTopBins;
+       i += (long long)gridDim.x * kTopThreads)
+    ghist[i] = 0u;
+  for (long long i0 = (long long)blockIdx.x * kTopThreads; i0 < m;
+       i0 += (long long)gridDim.x * kTopThreads) {
     const long long i = i0 + threadIdx.x;
-    const unsigned long long k = i < n ? key_of(err[i]) : 0ull;
-    const bool m = i < n && (k >> 48) == dg;
-    const unsigned long long bal = __ballot(m);
+    const unsigned long long k = i < m ? key_of(err[i]) : 0ull;
+    const bool sel = i < m && (k >> 48) == dg;
+    const unsigned long long bal = __ballot(sel);
     if (bal == 0ull) continue;
+    const int first = (int)__ffsll((long long)bal) - 1;
     unsigned long long base = 0;
-    if (lane == (int)__ffsll((long long)bal) - 1) base = atomicAdd(cnt, (unsigned long long)__popcll(bal));
-    base = __shfl(base, __ffsll((long long)bal) - 1, 64);
-    if (m) {
+    if (lane == first) base = atomicAdd(cnt, (unsigned long long)__popcll(bal));
+    base = __shfl(base, first, 64);
+    if (sel) {
       const unsigned long long o = base + __popcll(bal & ((1ull << lane) - 1ull));
       ckey[o] = k;
       cpos[o] = i;
@@ -586,11 +718,10 @@ __global__ void __launch_bounds__(256) topk_gather_kernel(const double *err, lon
   }
 }
 
-// One workgroup: among the gathered regions, the one of rank krem[0] (from 1)
-// in the order key descending, position ascending, by radix passes of 8 bits
-// over the key's low 48 bits (descending) and then over the position's low
-// 32 bits (ascending).  Writes its key to prefix[0] and its position to
-// krem[0].
+// One workgroup: among the gathered regions, the one of rank krem[0] (from
+// 1) in the order key descending, position ascending, by radix passes of 8
+// bits over the key's low 48 bits (descending) and then over the position's
+// low 32 bits (ascending); its key to prefix[0], its position to krem[0].
 __global__ void __launch_bounds__(kTopThreads) topk_exact_kernel(const unsigned long long *ckey,
                                                                  const long long *cpos,
                                                                  const unsigned long long *cnt,
@@ -599,98 +730,40 @@ __global__ void __launch_bounds__(kTopThreads) topk_exact_kernel(const unsigned 
                                                                  const int *done) {
   if (stopped(done)) return;
   __shared__ unsigned h[256];
-  __shared__ long long s_need;
-  __shared__ int s_dg;
   const int t = threadIdx.x;
-  const long long m = (long long)cnt[0];
+  const unsigned long long dg = prefix[0];
+  const long long mc = (long long)cnt[0];
   long long need = krem[0];
-  unsigned long long pre = prefix[0] << 48, mask = 0xFFFFull << 48;  // key bits fixed so far
+  unsigned long long pre = dg << 48, mask = 0xFFFFull << 48;  // key bits fixed so far
+  int dig;
   // key passes: descending digits
   for (int shift = 40; shift >= 0; shift -= 8) {
     if (t < 256) h[t] = 0u;
     __syncthreads();
-    for (long long i = t; i < m; i += kTopThreads) {
+    for (long long i = t; i < mc; i += kTopThreads) {
       const unsigned long long k = ckey[i];
       if ((k & mask) == pre) atomicAdd(&h[(k >> shift) & 255ull], 1u);
     }
     __syncthreads();
-    if (t < 64) {  // one wavefront scans the 256 counts from the top digit down
-      unsigned c4[4];
-      long long s4 = 0;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        c4[q] = h[255 - (4 * t + q)];
-        s4 += c4[q];
-      }
-      long long incl = s4;
-#pragma unroll
-      for (int o = 1; o < 64; o <<= 1) {
-        const long long v = __shfl_up(incl, o, 64);
-        if (t >= o) incl += v;
-      }
-      long long acc = incl - s4;
-      if (acc < need && incl >= need) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          if (acc + (long long)c4[q] >= need) {
-            s_dg = 255 - (4 * t + q);
-            s_need = need - acc;
-            break;
-          }
-          acc += c4[q];
-        }
-      }
-    }
-    __syncthreads();
-    need = s_need;
-    pre |= (unsigned long long)s_dg << shift;
+    pick_digit(t < 256 ? (long long)h[255 - t] : 0, need, &dig, &need);
+    pre |= (unsigned long long)dig << shift;
     mask |= 255ull << shift;
-    __syncthreads();
   }
   // position passes among the regions with the threshold key: ascending
   // (positions are below 2^32: a region store of 2^32 regions would need
-  // over 500 GB)
+  // over 500 GB), so thread t holds digit t, counted from the top as 255 - t
   unsigned long long ppre = 0ull, pmask = 0xFFFFFFFF00000000ull;
   for (int shift = 24; shift >= 0; shift -= 8) {
     if (t < 256) h[t] = 0u;
     __syncthreads();
-    for (long long i = t; i < m; i += kTopThreads) {
+    for (long long i = t; i < mc; i += kTopThreads) {
       const unsigned long long p = (unsigned long long)cpos[i];
       if (ckey[i] == pre && (p & pmask) == ppre) atomicAdd(&h[(p >> shift) & 255ull], 1u);
     }
     __syncthreads();
-    if (t < 64) {  // from the lowest digit up
-      unsigned c4[4];
-      long long s4 = 0;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        c4[q] = h[4 * t + q];
-        s4 += c4[q];
-      }
-      long long incl = s4;
-#pragma unroll
-      for (int o = 1; o < 64; o <<= 1) {
-        const long long v = __shfl_up(incl, o, 64);
-        if (t >= o) incl += v;
-      }
-      long long acc = incl - s4;
-      if (acc < need && incl >= need) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          if (acc + (long long)c4[q] >= need) {
-            s_dg = 4 * t + q;
-            s_need = need - acc;
-            break;
-          }
-          acc += c4[q];
-        }
-      }
-    }
-    __syncthreads();
-    need = s_need;
-    ppre |= (unsigned long long)s_dg << shift;
+    pick_digit(t < 256 ? (long long)h[t] : 0, need, &dig, &need);
+    ppre |= (unsigned long long)(255 - dig) << shift;
     pmask |= 255ull << shift;
-    __syncthreads();
   }
   if (t == 0) {
     prefix[0] = pre;
@@ -698,122 +771,53 @@ __global__ void __launch_bounds__(kTopThreads) topk_exact_kernel(const unsigned 
   }
 }
 
-// flag[i] = (key, position) at or above the threshold in the selection order,
-// and the per-tile counts of launch_split
-__global__ void __launch_bounds__(kScanBlock) thr_flag_count_kernel(const double *err, long long n,
-                                                                    const unsigned long long *prefix,
-                                                                    const long long *krem,
-                                                                    int *flag, long long *bsum,
-                                                                    const int *done) {
-  if (stopped(done)) return;
-  const unsigned long long thr = prefix[0];
-  const long long tpos = krem[0];
-  const long long base = (long long)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
-  long long c = 0;
-  for (int q = 0; q < kScanItems; ++q) {
-    const long long i = base + q;
-    if (i < n) {
-      const unsigned long long k = key_of(err[i]);
-      const int f = k > thr || (k == thr && i <= tpos);
-      flag[i] = f;
-      c += f;
-    }
-  }
-  long long tot;
-  (void)block_excl_scan(c, &tot);
-  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
-}
-
 // totals ---------------------------------------------------------------------
 
+// Sums of I7 and err over the live regions among positions [0, m), per tile
+// in a fixed order.
 __global__ void __launch_bounds__(kScanBlock) totals_partial_kernel(const double *I7,
                                                                     const double *err,
-                                                                    long long n, double *part,
-                                                                    long long nb,
+                                                                    long long m, double *part,
                                                                     const int *done) {
   if (stopped(done)) return;
-  __shared__ double s7[kScanBlock], se[kScanBlock];
-  const long long base = (long long)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+  const long long base = (long long)blockIdx.x * kScanTile;
   double a = 0.0, b = 0.0;
+#pragma unroll
   for (int q = 0; q < kScanItems; ++q) {
-    const long long i = base + q;
-    if (i < n) {
-      a += I7[i];
-      b += err[i];
+    const long long i = base + q * kScanBlock + threadIdx.x;
+    if (i < m) {
+      const double e = err[i];
+      if (!retired(e)) {
+        a += I7[i];
+        b += e;
+      }
     }
   }
-  s7[threadIdx.x] = a;
-  se[threadIdx.x] = b;
-  __syncthreads();
-  for (int o = kScanBlock / 2; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) {
-      s7[threadIdx.x] += s7[threadIdx.x + o];
-      se[threadIdx.x] += se[threadIdx.x + o];
-    }
-    __syncthreads();
-  }
+  const double2 t = block_sum2(a, b);
   if (threadIdx.x == 0) {
-    part[blockIdx.x] = s7[0];
-    part[nb + blockIdx.x] = se[0];
+    part[blockIdx.x] = t.x;
+    part[gridDim.x + blockIdx.x] = t.y;
   }
 }
 
+// One workgroup: the tiles' sums in tile order; with `dec', the stop rule,
+// else out[0..1] only.
 __global__ void __launch_bounds__(kScanBlock) totals_final_kernel(const double *part, long long nb,
-                                                                  double *out) {
-  __shared__ double s7[kScanBlock], se[kScanBlock];
-  double a = 0.0, b = 0.0;
-  for (long long i = threadIdx.x; i < nb; i += kScanBlock) {
-    a += part[i];
-    b += part[nb + i];
-  }
-  s7[threadIdx.x] = a;
-  se[threadIdx.x] = b;
-  __syncthreads();
-  for (int o = kScanBlock / 2; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) {
-      s7[threadIdx.x] += s7[threadIdx.x + o];
-      se[threadIdx.x] += se[threadIdx.x + o];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    out[0] = s7[0];
-    out[1] = se[0];
-  }
-}
-
-// totals_final, then the stop rule (launch_totals_decide)
-__global__ void __launch_bounds__(kScanBlock) totals_decide_kernel(const double *part, long long nb,
-                                                                   double *out, int *done,
-                                                                   CStop stop) {
+                                                                  double *out, int *done,
+                                                                  CStop stop, int dec) {
   if (stopped(done)) return;
-  __shared__ double s7[kScanBlock], se[kScanBlock];
-  double a = 0.0, b = 0.0;
+  double x = 0.0, y = 0.0;
   for (long long i = threadIdx.x; i < nb; i += kScanBlock) {
-    a += part[i];
-    b += part[nb + i];
+    x += part[i];
+    y += part[nb + i];
   }
-  s7[threadIdx.x] = a;
-  se[threadIdx.x] = b;
-  __syncthreads();
-  for (int o = kScanBlock / 2; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) {
-      s7[threadIdx.x] += s7[threadIdx.x + o];
-      se[threadIdx.x] += se[threadIdx.x + o];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    const double I = s7[0], E = se[0];
-    int code = 0;
-    if (!isfinite(I) || !isfinite(E))
-      code = 2;
-    else if (stop.neval >= stop.mineval && E <= fmax(stop.epsabs, stop.epsrel * fabs(I)))
-      code = 1;
-    out[0] = I;
-    out[1] = E;
-    out[2] = (double)code;
-    if (code) *done = 1;
+  const double2 T = block_sum2(x, y);
+  if (threadIdx.x != 0) return;
+  if (dec) {
+    decide(T.x, T.y, stop, out, done);
+  } else {
+    out[0] = T.x;
+    out[1] = T.y;
   }
 }
 
@@ -833,11 +837,6 @@ static void launch_rule_lane_d(const RuleArgs &A, unsigned grid, hipStream_t s) 
     case 7: hipLaunchKernelGGL((gm_rule_lane_kernel<FAM, 7>), dim3(grid), dim3(256), 0, s, A); break;
     default: hipLaunchKernelGGL((gm_rule_lane_kernel<FAM, 8>), dim3(grid), dim3(256), 0, s, A); break;
   }
-}
-
-hipError_t launch_root(const CRegions &R, int ndim, hipStream_t s) {
-  hipLaunchKernelGGL(cuhre_root_kernel, dim3(1), dim3(64), 0, s, R, ndim, (int *)nullptr);
-  return hipGetLastError();
 }
 
 hipError_t launch_root_clear(const CRegions &R, int ndim, int *done, hipStream_t s) {
@@ -861,68 +860,69 @@ hipError_t launch_rule(const RuleArgs &A, hipStream_t s) {
     }
     return hipGetLastError();
   }
-  const long long grid = (A.total + 3) / 4;
+  const long long grid = std::min<long long>((A.total + 3) / 4, kWaveRuleBlocks);
   hipLaunchKernelGGL(gm_rule_kernel, dim3((unsigned)grid), dim3(256), 0, s, A);
   return hipGetLastError();
 }
 
-hipError_t launch_select16(const CRegions &R, long long n, long long K, const CScratch &S,
+hipError_t launch_select16(const CRegions &R, long long m, long long K, const CScratch &S,
                            hipStream_t s) {
   // blocks see fewer than 2^16 keys each (the LDS counters are 16-bit)
   const long long per = 32768;
-  const int hgrid = (int)std::max<long long>(std::min<long long>(256, (n + kTopThreads - 1) /
+  const int hgrid = (int)std::max<long long>(std::min<long long>(256, (m + kTopThreads - 1) /
                                                                           kTopThreads),
-                                             (n + per - 1) / per);
-  hipLaunchKernelGGL(topk_hist_kernel, dim3(hgrid), dim3(kTopThreads), (kTopBins / 2) * 4, s,
-                     R.err, n, S.hist16, (const int *)S.done);
-  hipLaunchKernelGGL(topk_pick_kernel, dim3(1), dim3(kTopThreads), 0, s, S.hist16, K, S.prefix,
-                     S.krem, S.cand_cnt, (const int *)S.done);
-  const int ggrid = (int)std::min<long long>(2048, (n + 255) / 256);
-  hipLaunchKernelGGL(topk_gather_kernel, dim3(ggrid), dim3(256), 0, s, R.err, n, S.prefix,
-                     S.cand_key, S.cand_pos, S.cand_cnt, (const int *)S.done);
-  hipLaunchKernelGGL(topk_exact_kernel, dim3(1), dim3(kTopThreads), 0, s, S.cand_key,
-                     S.cand_pos, S.cand_cnt, S.prefix, S.krem, (const int *)S.done);
+                                             (m + per - 1) / per);
+  hipLaunchKernelGGL(topk_hist_kernel, dim3(hgrid), dim3(kTopThreads), (kTopBins / 2 + 256) * 4,
+                     s, R.err, m, S.hist16, S.coarse, (const int *)S.done);
+  hipLaunchKernelGGL(topk_pick_kernel, dim3(1), dim3(kTopThreads), 0, s, S.hist16, S.coarse, K,
+                     S.prefix, S.krem, S.cand_cnt, (const int *)S.done);
+  const int ggrid = (int)std::max<long long>(
+      kTopBins / kTopThreads, std::min<long long>(512, (m + kTopThreads - 1) / kTopThreads));
+  hipLaunchKernelGGL(topk_gather_kernel, dim3(ggrid), dim3(kTopThreads), 0, s, R.err, m,
+                     S.prefix, S.cand_key, S.cand_pos, S.cand_cnt, S.hist16, (const int *)S.done);
+  hipLaunchKernelGGL(topk_exact_kernel, dim3(1), dim3(kTopThreads), 0, s, S.cand_key, S.cand_pos,
+                     S.cand_cnt, S.prefix, S.krem, (const int *)S.done);
   return hipGetLastError();
 }
 
-hipError_t launch_split(const CRegions &src, const CRegions &dst, int ndim, long long n,
-                        long long K, long long next_id, bool all, const CScratch &S,
+hipError_t launch_split(const CRegions &R, long long m, long long K, const CScratch &S,
                         hipStream_t s) {
-  const long long nb = scratch_blocks(n);
-  if (!all) {
-    hipLaunchKernelGGL(thr_flag_count_kernel, dim3((unsigned)nb), dim3(kScanBlock), 0, s, src.err,
-                       n, S.prefix, S.krem, S.flag, S.bsum, (const int *)S.done);
-    hipLaunchKernelGGL(scan_bsum_kernel, dim3(1), dim3(kScanBlock), 0, s, S.bsum, nb,
-                       (const int *)S.done);
-  }
-  hipLaunchKernelGGL(split_kernel, dim3((unsigned)nb), dim3(kScanBlock), 0, s, src, dst, ndim, n,
-                     K, next_id, all ? 1 : 0, S.flag, S.bsum, (const int *)S.done);
+  const long long nb = scratch_blocks(m);
+  hipLaunchKernelGGL(sel_count_kernel, dim3((unsigned)nb), dim3(kScanBlock), 0, s, R.err, m,
+                     S.prefix, S.krem, S.bsum, (const int *)S.done);
+  hipLaunchKernelGGL(scan_bsum_kernel, dim3(1), dim3(kScanBlock), 0, s, S.bsum, nb,
+                     (const int *)S.done);
+  hipLaunchKernelGGL(split_mark_kernel, dim3((unsigned)nb), dim3(kScanBlock), 0, s, R.err, m,
+                     S.prefix, S.krem, S.bsum, S.parent, K, (const int *)S.done);
   return hipGetLastError();
 }
 
-hipError_t launch_totals(const CRegions &R, long long n, const CScratch &S, double *out,
+static hipError_t launch_totals_any(const CRegions &R, long long m, const CScratch &S,
+                                    double *out, const CStop &stop, int dec, hipStream_t s) {
+  const long long nb = scratch_blocks(m);
+  hipLaunchKernelGGL(totals_partial_kernel, dim3((unsigned)nb), dim3(kScanBlock), 0, s, R.I7,
+                     R.err, m, S.tot, (const int *)S.done);
+  hipLaunchKernelGGL(totals_final_kernel, dim3(1), dim3(kScanBlock), 0, s, S.tot, nb, out,
+                     S.done, stop, dec);
+  return hipGetLastError();
+}
+
+hipError_t launch_totals(const CRegions &R, long long m, const CScratch &S, double *out,
                          hipStream_t s) {
-  const long long nb = scratch_blocks(n);
-  hipLaunchKernelGGL(totals_partial_kernel, dim3((unsigned)nb), dim3(kScanBlock), 0, s, R.I7,
-                     R.err, n, S.tot, nb, (const int *)S.done);
-  hipLaunchKernelGGL(totals_final_kernel, dim3(1), dim3(kScanBlock), 0, s, S.tot, nb, out);
-  return hipGetLastError();
+  return launch_totals_any(R, m, S, out, CStop{}, 0, s);
 }
 
-hipError_t launch_totals_decide(const CRegions &R, long long n, const CScratch &S, double *out,
+hipError_t launch_totals_decide(const CRegions &R, long long m, const CScratch &S, double *out,
                                 const CStop &stop, hipStream_t s) {
-  const long long nb = scratch_blocks(n);
-  hipLaunchKernelGGL(totals_partial_kernel, dim3((unsigned)nb), dim3(kScanBlock), 0, s, R.I7,
-                     R.err, n, S.tot, nb, (const int *)S.done);
-  hipLaunchKernelGGL(totals_decide_kernel, dim3(1), dim3(kScanBlock), 0, s, S.tot, nb, out,
-                     S.done, stop);
-  return hipGetLastError();
+  return launch_totals_any(R, m, S, out, stop, 1, s);
 }
 
 hipError_t cuhre_set_kernel_limits() {
-  // the top-K histogram keeps 2^16 16-bit counters in LDS (128 KB)
+  // the top-K histogram keeps 2^16 16-bit counters and 256 32-bit ones in
+  // LDS (129 KB)
   return hipFuncSetAttribute((const void *)topk_hist_kernel,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (kTopBins / 2) * 4);
+                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (kTopBins / 2 + 256) * 4);
 }
 
 }  // namespace ccuba

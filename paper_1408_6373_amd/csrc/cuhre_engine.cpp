@@ -56,19 +56,18 @@ const GMTables &gm_tables() {
   return T;
 }
 
-size_t CuhreRun::bytes() const {
-  const int d = spec_.ndim;
-  return (size_t)cap_ * 2 * (2 * d * 8 + 3 * 8 + 4 + 8) + (size_t)cap_ * 4;
-}
+// bytes of store per region (centre, width, I7, I5, err, axis) and of the
+// selection scratch (candidate key and position, parent position)
+static double region_bytes(int d) { return (2.0 * d + 3.0) * 8.0 + 4.0 + 16.0 + 4.0; }
+
+size_t CuhreRun::bytes() const { return (size_t)((double)cap_ * region_bytes(spec_.ndim)); }
 
 int CuhreRun::alloc_store(CRegions &R, DevBuf<double> &cb, DevBuf<double> &hb,
-                          DevBuf<double> &vals, DevBuf<int> &ax, DevBuf<long long> &ids,
-                          long long cap) {
+                          DevBuf<double> &vals, DevBuf<int> &ax, long long cap) {
   const int d = spec_.ndim;
   int rc;
   if ((rc = cb.alloc(ctx_, (size_t)d * cap)) || (rc = hb.alloc(ctx_, (size_t)d * cap)) ||
-      (rc = vals.alloc(ctx_, (size_t)3 * cap)) || (rc = ax.alloc(ctx_, cap)) ||
-      (rc = ids.alloc(ctx_, cap)))
+      (rc = vals.alloc(ctx_, (size_t)3 * cap)) || (rc = ax.alloc(ctx_, cap)))
     return rc;
   R.c = cb.p;
   R.h = hb.p;
@@ -76,71 +75,69 @@ int CuhreRun::alloc_store(CRegions &R, DevBuf<double> &cb, DevBuf<double> &hb,
   R.I5 = vals.p + cap;
   R.err = vals.p + 2 * cap;
   R.axis = ax.p;
-  R.id = ids.p;
   R.cap = cap;
   return CCUBA_OK;
 }
 
-// Grow both stores to hold `need' regions, keeping the leaves in store cur_.
+// Scratch sized for a store of cap regions.
+int CuhreRun::alloc_scratch(long long cap) {
+  int rc;
+  const long long nb = scratch_blocks(cap);
+  if ((rc = bsum_.alloc(ctx_, nb)) || (rc = tot_.alloc(ctx_, 2 * nb)) ||
+      (rc = parent_.alloc(ctx_, cap / 2 + 1)) || (rc = cand_key_.alloc(ctx_, cap)) ||
+      (rc = cand_pos_.alloc(ctx_, cap)))
+    return rc;
+  // (positions read by a rule launch are always in the store)
+  CCUBA_HIP(hipMemset(parent_.p, 0, parent_.n * sizeof(long long)));
+  S_.cand_key = cand_key_.p;
+  S_.cand_pos = cand_pos_.p;
+  S_.parent = parent_.p;
+  S_.bsum = bsum_.p;
+  S_.tot = tot_.p;
+  S_.nbmax = nb;
+  return CCUBA_OK;
+}
+
+// Grow the store to hold `need' regions, keeping the first next_id_.
 int CuhreRun::ensure(long long need, hipStream_t s) {
   if (need <= cap_) return CCUBA_OK;
   long long cap = std::max<long long>(cap_ * 4, need);
   const long long limit = spec_.maxeval / np_ + 2;  // no run can hold more regions
   cap = std::max(need, std::min(cap, limit));
   const int d = spec_.ndim;
-  // new store for the leaves, copy, then a fresh second store
-  // a tight budget: grow only as needed (two new stores must fit beside
-  // what the context holds now; the bytes per region with size-class slack)
-  const double per = ((2.0 * d + 3.0) * 8.0 + 12.0) * 1.25;
-  if ((double)ctx_->used.load() + 2.0 * per * (double)cap + 65536.0 > (double)ctx_->budget)
-    cap = need;
+  // a tight budget: grow only as needed (the new store must fit beside what
+  // the context holds now, the old store included; size-class slack 1.25)
+  const double per = region_bytes(d) * 1.25;
+  if ((double)ctx_->used.load() + per * (double)cap + 65536.0 > (double)ctx_->budget) cap = need;
   CRegions R{};
   DevBuf<double> cb, hb, vals;
   DevBuf<int> ax;
-  DevBuf<long long> ids;
-  int rc = alloc_store(R, cb, hb, vals, ax, ids, cap);
+  int rc = alloc_store(R, cb, hb, vals, ax, cap);
   if (rc) return rc;
-  const CRegions &O = R_[cur_];
-  if (n_ > 0) {
+  const CRegions &O = R_;
+  const long long m = next_id_;
+  if (m > 0) {
     for (int j = 0; j < d; ++j) {
-      CCUBA_HIP(hipMemcpyAsync(R.c + j * cap, O.c + j * O.cap, n_ * 8, hipMemcpyDeviceToDevice, s));
-      CCUBA_HIP(hipMemcpyAsync(R.h + j * cap, O.h + j * O.cap, n_ * 8, hipMemcpyDeviceToDevice, s));
+      CCUBA_HIP(hipMemcpyAsync(R.c + j * cap, O.c + j * O.cap, m * 8, hipMemcpyDeviceToDevice, s));
+      CCUBA_HIP(hipMemcpyAsync(R.h + j * cap, O.h + j * O.cap, m * 8, hipMemcpyDeviceToDevice, s));
     }
-    CCUBA_HIP(hipMemcpyAsync(R.I7, O.I7, n_ * 8, hipMemcpyDeviceToDevice, s));
-    CCUBA_HIP(hipMemcpyAsync(R.I5, O.I5, n_ * 8, hipMemcpyDeviceToDevice, s));
-    CCUBA_HIP(hipMemcpyAsync(R.err, O.err, n_ * 8, hipMemcpyDeviceToDevice, s));
-    CCUBA_HIP(hipMemcpyAsync(R.axis, O.axis, n_ * 4, hipMemcpyDeviceToDevice, s));
-    CCUBA_HIP(hipMemcpyAsync(R.id, O.id, n_ * 8, hipMemcpyDeviceToDevice, s));
+    CCUBA_HIP(hipMemcpyAsync(R.I7, O.I7, m * 8, hipMemcpyDeviceToDevice, s));
+    CCUBA_HIP(hipMemcpyAsync(R.I5, O.I5, m * 8, hipMemcpyDeviceToDevice, s));
+    CCUBA_HIP(hipMemcpyAsync(R.err, O.err, m * 8, hipMemcpyDeviceToDevice, s));
+    CCUBA_HIP(hipMemcpyAsync(R.axis, O.axis, m * 4, hipMemcpyDeviceToDevice, s));
   }
   CCUBA_HIP(hipStreamSynchronize(s));
-  // release the old stores before taking the second new one
-  for (int q = 0; q < 2; ++q) {
-    c_[q].release();
-    h_[q].release();
-    vals_[q].release();
-    axis_[q].release();
-    id_[q].release();
-  }
-  c_[0].swap(cb);
-  h_[0].swap(hb);
-  vals_[0].swap(vals);
-  axis_[0].swap(ax);
-  id_[0].swap(ids);
-  R_[0] = R;
-  cur_ = 0;
-  if ((rc = alloc_store(R_[1], c_[1], h_[1], vals_[1], axis_[1], id_[1], cap))) return rc;
-  const long long nb = scratch_blocks(cap);
-  if ((rc = flag_.alloc(ctx_, cap)) || (rc = bsum_.alloc(ctx_, nb)) ||
-      (rc = tot_.alloc(ctx_, 2 * nb)) || (rc = cand_key_.alloc(ctx_, cap)) ||
-      (rc = cand_pos_.alloc(ctx_, cap)))
-    return rc;
+  c_.swap(cb);
+  h_.swap(hb);
+  vals_.swap(vals);
+  axis_.swap(ax);
+  R_ = R;
+  cb.release();
+  hb.release();
+  vals.release();
+  ax.release();
+  if ((rc = alloc_scratch(cap))) return rc;
   cap_ = cap;
-  S_.cand_key = cand_key_.p;
-  S_.cand_pos = cand_pos_.p;
-  S_.flag = flag_.p;
-  S_.bsum = bsum_.p;
-  S_.tot = tot_.p;
-  S_.nbmax = nb;
   return CCUBA_OK;
 }
 
@@ -154,53 +151,45 @@ int CuhreRun::start(const CuhreSpec &spec, hipStream_t s) {
   neval_ = 0;
   batches_ = 0;
   done_ = false;
+  contig_ = true;
   fail_ = 1;
   cap_ = 0;
   int rc;
-  if ((rc = prefix_.alloc(ctx_, 2)) || (rc = krem_.alloc(ctx_, 2)) ||
+  if ((rc = prefix_.alloc(ctx_, 1)) || (rc = krem_.alloc(ctx_, 1)) ||
       (rc = out_.alloc(ctx_, 2)) ||
       (rc = params_.alloc(ctx_, 2 * kParamRow)) || (rc = w7_.alloc(ctx_, 17 * 5)) ||
       (rc = w5_.alloc(ctx_, 17 * 5)) || (rc = seg_.alloc(ctx_, 1)) ||
       (rc = seg_end_.alloc(ctx_, 1)) || (rc = stop_.alloc(ctx_, 1)) ||
-      (rc = hist16_.alloc(ctx_, 1 << 16)) || (rc = cand_cnt_.alloc(ctx_, 1)))
+      (rc = hist16_.alloc(ctx_, 1 << 16)) || (rc = coarse_.alloc(ctx_, 256)) ||
+      (rc = cand_cnt_.alloc(ctx_, 1)))
     return rc;
   S_.done = stop_.p;
   S_.hist16 = hist16_.p;
+  S_.coarse = coarse_.p;
   S_.cand_cnt = cand_cnt_.p;
-  // (the top-K kernels leave the histogram cleared after every use)
+  // (the top-K kernels leave the histograms cleared after every use)
   CCUBA_HIP(hipMemsetAsync(hist16_.p, 0, (1 << 16) * sizeof(unsigned), s));
+  CCUBA_HIP(hipMemsetAsync(coarse_.p, 0, 256 * sizeof(unsigned), s));
   S_.prefix = prefix_.p;
   S_.krem = krem_.p;
   // room for the first few batches, so that the store rarely grows (growing
-  // means new allocations and a copy)
+  // means a new allocation and a copy)
   const long long first_cap = std::max<long long>(
-      16, std::min<long long>(std::min<long long>(4 * spec.batch + 1, 1 << 22),
+      16, std::min<long long>(std::min<long long>(8 * spec.batch + 1, 1 << 23),
                               spec.maxeval / np_ + 2));
-  // initial stores (room for one batch only if a tight budget refuses more)
+  // the initial store (room for one batch only if a tight budget refuses more)
   long long cap0 = first_cap;
   for (;;) {
-    rc = alloc_store(R_[0], c_[0], h_[0], vals_[0], axis_[0], id_[0], cap0);
-    if (!rc) rc = alloc_store(R_[1], c_[1], h_[1], vals_[1], axis_[1], id_[1], cap0);
+    rc = alloc_store(R_, c_, h_, vals_, axis_, cap0);
     if (rc != CCUBA_ENOMEM) break;
     const long long small = std::max<long long>(
-        16, std::min<long long>(spec.batch + 1, spec.maxeval / np_ + 2));
+        16, std::min<long long>(2 * spec.batch + 1, spec.maxeval / np_ + 2));
     if (cap0 <= small) break;
     cap0 = small;
   }
   if (rc) return rc;
+  if ((rc = alloc_scratch(cap0))) return rc;
   cap_ = cap0;
-  const long long nb = scratch_blocks(cap_);
-  if ((rc = flag_.alloc(ctx_, cap_)) || (rc = bsum_.alloc(ctx_, nb)) ||
-      (rc = tot_.alloc(ctx_, 2 * nb)) || (rc = cand_key_.alloc(ctx_, cap_)) ||
-      (rc = cand_pos_.alloc(ctx_, cap_)))
-    return rc;
-  S_.cand_key = cand_key_.p;
-  S_.cand_pos = cand_pos_.p;
-  S_.flag = flag_.p;
-  S_.bsum = bsum_.p;
-  S_.tot = tot_.p;
-  S_.nbmax = nb;
-  cur_ = 0;
   // constants
   VegasSpec vs;
   vs.ndim = d;
@@ -217,14 +206,14 @@ int CuhreRun::start(const CuhreSpec &spec, hipStream_t s) {
   CCUBA_HIP(hipMemcpyAsync(w7_.p, T.w7, sizeof(T.w7), hipMemcpyHostToDevice, s));
   CCUBA_HIP(hipMemcpyAsync(w5_.p, T.w5, sizeof(T.w5), hipMemcpyHostToDevice, s));
   // root region [0,1]^d: centre 1/2, half-width 1/2, id 0; the stop flag clear
-  CCUBA_HIP(launch_root_clear(R_[0], d, stop_.p, s));
+  CCUBA_HIP(launch_root_clear(R_, d, stop_.p, s));
   CSeg seg{};
   seg.ndim = d;
   seg.family = spec.family;
   seg.par = params_.p;
   seg.first = 0;
   seg.count = 1;
-  seg.regs = R_[0];
+  seg.regs = R_;
   n_ = 1;
   neval_ = np_;
   return launch_rule_alone(seg, s);
@@ -294,7 +283,7 @@ int launch_rule_segments(ccuba_ctx *ctx, const CSeg *segs, int nseg, DevBuf<CSeg
 }
 
 int CuhreRun::launch_totals(hipStream_t s) {
-  CCUBA_HIP(ccuba::launch_totals(R_[cur_], n_, S_, mapped_dev_ ? mapped_dev_ : out_.p, s));
+  CCUBA_HIP(ccuba::launch_totals(R_, next_id_, S_, mapped_dev_ ? mapped_dev_ : out_.p, s));
   return CCUBA_OK;
 }
 
@@ -310,6 +299,24 @@ int CuhreRun::read_totals(hipStream_t s) {
   I_ = t[0];
   E_ = t[1];
   return CCUBA_OK;
+}
+
+CSeg CuhreRun::children_segment(long long K, bool from_range) const {
+  CSeg seg{};
+  seg.ndim = spec_.ndim;
+  seg.family = spec_.family;
+  seg.par = params_.p;
+  seg.first = next_id_;
+  seg.count = 2 * K;
+  seg.regs = R_;
+  seg.children = 1;
+  if (from_range) {  // every live region splits, and they are the last n_
+    seg.pbase = next_id_ - n_;
+    seg.retire = 1;
+  } else {  // launch_split retired them and wrote their positions
+    seg.parent = parent_.p;
+  }
+  return seg;
 }
 
 int CuhreRun::plan_and_split(hipStream_t s) {
@@ -334,26 +341,19 @@ int CuhreRun::plan_and_split(hipStream_t s) {
     fail_ = 1;
     return 0;
   }
-  int rc = ensure(n_ + K, s);
+  int rc = ensure(next_id_ + 2 * K, s);
   if (rc) return rc < 0 ? rc : CCUBA_EHIP;
-  const bool all = K == n_;
-  if (!all) CCUBA_HIP(launch_select16(R_[cur_], n_, K, S_, s));
-  CCUBA_HIP(launch_split(R_[cur_], R_[1 - cur_], spec_.ndim, n_, K, next_id_, all, S_, s));
-  cur_ = 1 - cur_;
+  pend_range_ = K == n_ && contig_;
+  if (!pend_range_) {
+    CCUBA_HIP(launch_select16(R_, next_id_, K, S_, s));
+    CCUBA_HIP(launch_split(R_, next_id_, K, S_, s));
+    contig_ = false;
+  }
   pendK_ = K;
   return 1;
 }
 
-CSeg CuhreRun::pending_segment() const {
-  CSeg seg{};
-  seg.ndim = spec_.ndim;
-  seg.family = spec_.family;
-  seg.par = params_.p;
-  seg.first = n_ - pendK_;
-  seg.count = 2 * pendK_;
-  seg.regs = R_[cur_];
-  return seg;
-}
+CSeg CuhreRun::pending_segment() const { return children_segment(pendK_, pend_range_); }
 
 void CuhreRun::commit_pending() {
   n_ += pendK_;
@@ -369,20 +369,23 @@ int CuhreRun::run(hipStream_t s) {
   // run is decided on the device.
   struct Plan {
     long long n, neval, next_id;
-    int cur, batches;
+    int batches;
   };
-  // totals of step t go to slot t % 2: 4 doubles (I, err, decision, -) in
-  // mapped pinned memory if the caller gave it, else in out_
+  // the totals of the state before step t go to slot t % 2: 4 doubles (I,
+  // err, decision, -) in mapped pinned memory if the caller gave it, else in
+  // device memory
+  constexpr int kSlots = 2;
   double *dev_slots = nullptr, *host_slots = nullptr;
   DevBuf<double> slots;
   if (mapped_host_) {
     dev_slots = mapped_dev_;
     host_slots = mapped_host_;
   } else {
-    int rc = slots.alloc(ctx_, 8);
+    int rc = slots.alloc(ctx_, 4 * kSlots);
     if (rc) return rc;
     dev_slots = slots.p;
   }
+  auto slot = [&](int t) { return 4 * (t % kSlots); };
   hipEvent_t ev[2] = {nullptr, nullptr};
   CCUBA_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
   if (hipEventCreateWithFlags(&ev[1], hipEventDisableTiming) != hipSuccess) {
@@ -406,9 +409,9 @@ int CuhreRun::run(hipStream_t s) {
     if (q != hipSuccess) return CCUBA_EHIP;
     double v[4];
     if (host_slots) {
-      for (int k = 0; k < 4; ++k) v[k] = host_slots[4 * (t & 1) + k];
+      for (int k = 0; k < 4; ++k) v[k] = host_slots[slot(t) + k];
     } else {
-      CCUBA_HIP(hipMemcpy(v, dev_slots + 4 * (t & 1), sizeof(v), hipMemcpyDeviceToHost));
+      CCUBA_HIP(hipMemcpy(v, dev_slots + slot(t), sizeof(v), hipMemcpyDeviceToHost));
     }
     *I = v[0];
     *E = v[1];
@@ -420,7 +423,6 @@ int CuhreRun::run(hipStream_t s) {
     n_ = p.n;
     neval_ = p.neval;
     next_id_ = p.next_id;
-    cur_ = p.cur;
     batches_ = p.batches;
     done_ = true;
     pendK_ = 0;
@@ -456,28 +458,31 @@ int CuhreRun::run(hipStream_t s) {
   };
   Plan prev{};
   for (int t = 0;; ++t) {
-    const Plan cur{n_, neval_, next_id_, cur_, batches_};
+    const Plan cur{n_, neval_, next_id_, batches_};
     const CStop stop{spec_.epsrel, spec_.epsabs, spec_.mineval, neval_};
-    CCUBA_HIP(launch_totals_decide(R_[cur_], n_, S_, dev_slots + 4 * (t & 1), stop, s));
+    CCUBA_HIP(launch_totals_decide(R_, next_id_, S_, dev_slots + slot(t), stop, s));
     CCUBA_HIP(hipEventRecord(ev[t & 1], s));
     long long K = std::min(spec_.batch / 2, n_);
     const long long budget = spec_.maxeval > neval_ ? (spec_.maxeval - neval_) / (2 * np_) : 0;
     K = std::min(K, budget);
     int rc = 0;
-    if (K > 0 && n_ + K > cap_) {
+    if (K > 0 && next_id_ + 2 * K > cap_) {
       // the store must grow (a synchronisation and a copy): only for a step
       // known to run, so learn steps t - 1 and t first
       if (t - 1 > known && learn(t - 1, prev, &rc)) return rc;
       if (learn(t, cur, &rc)) return rc;
-      if ((rc = ensure(n_ + K, s))) return rc < 0 ? rc : CCUBA_EHIP;
+      if ((rc = ensure(next_id_ + 2 * K, s))) return rc < 0 ? rc : CCUBA_EHIP;
     }
     if (K > 0) {  // queue step t's work, possibly before learning step t - 1's outcome
-      const bool all = K == n_;
-      if (!all) CCUBA_HIP(launch_select16(R_[cur_], n_, K, S_, s));
-      CCUBA_HIP(launch_split(R_[cur_], R_[1 - cur_], spec_.ndim, n_, K, next_id_, all, S_, s));
-      cur_ = 1 - cur_;
+      if (K == n_ && contig_) {  // every region splits: no selection
+        if ((rc = launch_rule_alone(children_segment(K, true), s))) return rc;
+      } else {
+        CCUBA_HIP(launch_select16(R_, next_id_, K, S_, s));
+        CCUBA_HIP(launch_split(R_, next_id_, K, S_, s));
+        if ((rc = launch_rule_alone(children_segment(K, false), s))) return rc;
+        contig_ = false;
+      }
       pendK_ = K;
-      if ((rc = launch_rule_alone(pending_segment(), s))) return rc;
       commit_pending();
     }
     if (t - 1 > known && learn(t - 1, prev, &rc)) return rc;
@@ -494,7 +499,7 @@ int CuhreRun::rule_only(long long nreg, const double *c, const double *h, double
   const int d = spec_.ndim;
   int rc = ensure(nreg, s);
   if (rc) return rc;
-  const CRegions &R = R_[cur_];
+  const CRegions &R = R_;
   for (int j = 0; j < d; ++j) {
     CCUBA_HIP(hipMemcpyAsync(R.c + j * R.cap, c + (size_t)j * nreg, nreg * 8,
                              hipMemcpyHostToDevice, s));

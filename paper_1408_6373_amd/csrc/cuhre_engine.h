@@ -58,7 +58,7 @@ class CuhreRun {
   bool done() const { return done_; }
   int fail() const { return fail_; }
   long long neval() const { return neval_; }
-  long long nregions() const { return n_; }
+  long long nregions() const { return n_; }  // live regions
   double integral() const { return I_; }
   double error() const { return E_; }
   int batches() const { return batches_; }
@@ -70,21 +70,27 @@ class CuhreRun {
  private:
   int ensure(long long need, hipStream_t s);
   int alloc_store(CRegions &R, DevBuf<double> &cb, DevBuf<double> &hb, DevBuf<double> &vals,
-                  DevBuf<int> &ax, DevBuf<long long> &ids, long long cap);
+                  DevBuf<int> &ax, long long cap);
+  int alloc_scratch(long long cap);
+  // The segment of the 2K children of step with K splits: formed from the
+  // live regions [next_id_ - n_, next_id_) when all split and they are
+  // contiguous, else from the positions launch_split wrote.
+  CSeg children_segment(long long K, bool from_range) const;
   ccuba_ctx *ctx_;
   CuhreSpec spec_;
+  // n_ live regions among the next_id_ of the store (positions are ids)
   long long np_ = 0, n_ = 0, next_id_ = 1, neval_ = 0, cap_ = 0, pendK_ = 0;
   int fail_ = 1, batches_ = 0;
   bool done_ = false;
+  bool contig_ = true;       // the live regions are the last n_ of the store
+  bool pend_range_ = false;  // the pending children come from a range of parents
   double I_ = 0, E_ = 0;
-  int cur_ = 0;  // which store holds the leaves
-  CRegions R_[2]{};
-  DevBuf<double> c_[2], h_[2], vals_[2];
-  DevBuf<int> axis_[2];
-  DevBuf<long long> id_[2];
+  CRegions R_{};
+  DevBuf<double> c_, h_, vals_;
+  DevBuf<int> axis_;
   DevBuf<unsigned long long> prefix_;
-  DevBuf<long long> krem_, bsum_;
-  DevBuf<int> flag_;
+  DevBuf<long long> krem_, bsum_, parent_;
+  DevBuf<unsigned> coarse_;
   DevBuf<double> tot_, out_, params_, w7_, w5_;
   DevBuf<int> stop_;  // the run's stop flag (CScratch::done)
   DevBuf<unsigned> hist16_;  // the top-K digit histogram (CScratch::hist16)
