@@ -126,7 +126,11 @@ namespace ccuba {
 int pinned_block(ccuba_ctx *ctx, double **host, double **dev) {
   if (!ctx->pinned_host) {
     void *h = nullptr, *d = nullptr;
-    if (hipHostMalloc(&h, ccuba_ctx::kPinnedBytes, 0) != hipSuccess) return CCUBA_EHIP;
+    // host-coherent: the device's system-scope stores to it are seen by a
+    // polling host while the kernel runs
+    if (hipHostMalloc(&h, ccuba_ctx::kPinnedBytes, hipHostMallocMapped | hipHostMallocCoherent) !=
+        hipSuccess)
+      return CCUBA_EHIP;
     if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess) {
       (void)hipHostFree(h);
       return CCUBA_EHIP;

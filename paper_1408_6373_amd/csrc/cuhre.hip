@@ -378,36 +378,65 @@ __device__ __forceinline__ bool stopped(const int *done) { return done && *done 
 
 namespace {
 
-// Sums over a 256-thread block in a fixed order (a butterfly in each
-// wavefront, lane 0's result, then the four wavefronts in order); every
+// Sums over a block of up to 1024 threads in a fixed order (a butterfly in
+// each wavefront, lane 0's result, then the wavefronts in order); every
 // thread gets the sums.
 __device__ __forceinline__ double2 block_sum2(double a, double b) {
-  __shared__ double s[2][4];
+  __shared__ double s[2][16];
   a = wsum(a);
   b = wsum(b);
-  const int w = threadIdx.x >> 6;
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
   __syncthreads();  // an earlier call's readers are done with s
   if ((threadIdx.x & 63) == 0) {
     s[0][w] = a;
     s[1][w] = b;
   }
   __syncthreads();
-  return make_double2((s[0][0] + s[0][1]) + (s[0][2] + s[0][3]),
-                      (s[1][0] + s[1][1]) + (s[1][2] + s[1][3]));
+  double x = 0.0, y = 0.0;
+  for (int q = 0; q < nw; ++q) {
+    x += s[0][q];
+    y += s[1][q];
+  }
+  return make_double2(x, y);
 }
 
-// The stop rule on a step's totals (one thread).
-__device__ __forceinline__ void decide(double I, double E, const CStop &stop, double *out,
-                                       int *done) {
-  int code = 0;
-  if (!isfinite(I) || !isfinite(E))
-    code = 2;
-  else if (stop.neval >= stop.mineval && E <= fmax(stop.epsabs, stop.epsrel * fabs(I)))
-    code = 1;
-  out[0] = I;
-  out[1] = E;
-  out[2] = (double)code;
-  if (code && done) *done = 1;
+// The stop rule on a step's totals: 0 go on, 1 converged, 2 not finite.
+__device__ __forceinline__ int stop_code(double I, double E, const CStop &stop) {
+  if (!isfinite(I) || !isfinite(E)) return 2;
+  if (stop.neval >= stop.mineval && E <= fmax(stop.epsabs, stop.epsrel * fabs(I))) return 1;
+  return 0;
+}
+
+// The opening of a step (CRows): true if the run goes on.  Every thread of
+// the block must call it.
+__device__ __forceinline__ bool open_step(const CRows &R, int *done) {
+  if (!R.in) return true;
+  double x = 0.0, y = 0.0;
+  for (long long i = threadIdx.x; i < R.nin; i += blockDim.x) {
+    x += R.in[i];
+    y += R.in[R.stride + i];
+  }
+  const double2 T = block_sum2(x, y);
+  const int code = stop_code(T.x, T.y, R.stop);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    R.slot[0] = T.x;
+    R.slot[1] = T.y;
+    __hip_atomic_store((unsigned long long *)(R.slot + 2),
+                       ((unsigned long long)R.seq << 8) | (unsigned long long)code,
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    if (code && done) *done = 1;
+  }
+  return code == 0;
+}
+
+// One row of the next state: the block's sums (every thread calls it).
+__device__ __forceinline__ void put_row(const CRows &R, double a, double b) {
+  if (!R.out) return;
+  const double2 t = block_sum2(a, b);
+  if (threadIdx.x == 0) {
+    R.out[R.out0 + blockIdx.x] = t.x;
+    R.out[R.stride + R.out0 + blockIdx.x] = t.y;
+  }
 }
 
 }  // namespace
@@ -415,9 +444,11 @@ __device__ __forceinline__ void decide(double I, double E, const CStop &stop, do
 // One integral (A.one), dimension D: one lane per region.
 template <int FAM, int D>
 __global__ void __launch_bounds__(256) gm_rule_lane_kernel(RuleArgs A) {
-  if (stopped(A.done)) return;
+  if (stopped(A.done) || !open_step(A.rows, A.done)) return;
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g < A.total) (void)rule_region_lane<FAM, D>(A, A.one, A.one.first + g);
+  double2 v = make_double2(0.0, 0.0);
+  if (g < A.total) v = rule_region_lane<FAM, D>(A, A.one, A.one.first + g);
+  put_row(A.rows, v.x, v.y);
 }
 
 // A wavefront per region, the regions of a launch taken in turn by the grid's
@@ -426,8 +457,9 @@ __global__ void __launch_bounds__(256) gm_rule_kernel(RuleArgs A) {
   __shared__ double sc[4][kMaxDim], sh[4][kMaxDim];
   __shared__ double sf[4][4 * kMaxDim + 1];
   __shared__ double sx[4][2 * kMaxDim];
-  if (stopped(A.done)) return;
+  if (stopped(A.done) || !open_step(A.rows, A.done)) return;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double a = 0.0, b = 0.0;
   for (long long g = (long long)blockIdx.x * 4 + w; g < A.total; g += (long long)gridDim.x * 4) {
     CSeg S;
     long long before = 0;
@@ -446,17 +478,27 @@ __global__ void __launch_bounds__(256) gm_rule_kernel(RuleArgs A) {
       before = lo > 0 ? A.seg_end[lo - 1] : 0;
     }
     const long long r = S.first + (g - before);
+    double2 v;
     switch (S.family) {
-      case GAUSSIAN: rule_region<GAUSSIAN>(A, S, r, w, lane, sc, sh, sf, sx); break;
-      case OSCILLATORY: rule_region<OSCILLATORY>(A, S, r, w, lane, sc, sh, sf, sx); break;
-      case PRODUCT_PEAK: rule_region<PRODUCT_PEAK>(A, S, r, w, lane, sc, sh, sf, sx); break;
-      case CORNER_PEAK: rule_region<CORNER_PEAK>(A, S, r, w, lane, sc, sh, sf, sx); break;
-      default: rule_region<C0>(A, S, r, w, lane, sc, sh, sf, sx); break;
+      case GAUSSIAN: v = rule_region<GAUSSIAN>(A, S, r, w, lane, sc, sh, sf, sx); break;
+      case OSCILLATORY: v = rule_region<OSCILLATORY>(A, S, r, w, lane, sc, sh, sf, sx); break;
+      case PRODUCT_PEAK: v = rule_region<PRODUCT_PEAK>(A, S, r, w, lane, sc, sh, sf, sx); break;
+      case CORNER_PEAK: v = rule_region<CORNER_PEAK>(A, S, r, w, lane, sc, sh, sf, sx); break;
+      default: v = rule_region<C0>(A, S, r, w, lane, sc, sh, sf, sx); break;
     }
+    a += v.x;  // lane 0 only: the others hold 0
+    b += v.y;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();  // the LDS rows are reused by the next region
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
+  put_row(A.rows, a, b);
+}
+
+// A step opened alone (one block).
+__global__ void __launch_bounds__(256) cuhre_decide_kernel(CRows R, int *done) {
+  if (stopped(done)) return;
+  (void)open_step(R, done);
 }
 
 // ---------------------------------------------------------------------------
@@ -492,12 +534,25 @@ __device__ __forceinline__ bool selected(double e, long long i, unsigned long lo
   return k > thr || (k == thr && i <= tpos);
 }
 
-// Per tile of kScanTile positions, the count of selected regions.
+constexpr int kTopBins = 1 << 16;
+constexpr int kTopThreads = 1024;
+
+// Per tile of kScanTile positions, the count of selected regions.  Also
+// clears the top-K histograms, which this step's selection has used.
 __global__ void __launch_bounds__(kScanBlock) sel_count_kernel(const double *err, long long m,
                                                                const unsigned long long *prefix,
                                                                const long long *krem,
-                                                               long long *bsum, const int *done) {
+                                                               long long *bsum, unsigned *ghist,
+                                                               unsigned *gcoarse,
+                                                               const int *done) {
   if (stopped(done)) return;
+  for (long long i = (long long)blockIdx.x * kScanBlock + threadIdx.x; i < kTopBins + 256;
+       i += (long long)gridDim.x * kScanBlock) {
+    if (i < kTopBins)
+      ghist[i] = 0u;
+    else
+      gcoarse[i - kTopBins] = 0u;
+  }
   const unsigned long long thr = prefix[0];
   const long long tpos = krem[0];
   const long long base = (long long)blockIdx.x * kScanTile;
@@ -512,51 +567,48 @@ __global__ void __launch_bounds__(kScanBlock) sel_count_kernel(const double *err
   if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
 }
 
-// One workgroup: the exclusive scan of the nb tile counts, in chunks of 256
-// with a carry.
-__global__ void __launch_bounds__(kScanBlock) scan_bsum_kernel(long long *bsum, long long nb,
-                                                               const int *done) {
-  if (stopped(done)) return;
-  long long carry = 0;
-  for (long long c0 = 0; c0 < nb; c0 += kScanBlock) {
-    const long long i = c0 + threadIdx.x;
-    const long long v = i < nb ? bsum[i] : 0;
-    long long t2;
-    const long long ex = block_excl_scan(v, &t2);
-    if (i < nb) bsum[i] = carry + ex;
-    carry += t2;
-  }
-}
-
 // Each selected region is retired and its position written to parent[j],
-// j its rank in position order: the tile's scanned count plus the selected
-// positions before it in the tile (the tile's kScanItems chunks of 256 in
-// order, within a chunk the wavefronts in order, within a wavefront the
-// lanes below).
-__global__ void __launch_bounds__(kScanBlock) split_mark_kernel(double *err, long long m,
+// j its rank in position order: the counts of the tiles before this one
+// (summed by every block itself) plus the selected positions before it in
+// the tile (the tile's kScanItems chunks of 256 in order, within a chunk the
+// wavefronts in order, within a wavefront the lanes below).  With rows, the
+// block's sums over the regions that stay live.
+__global__ void __launch_bounds__(kScanBlock) split_mark_kernel(double *err, const double *I7,
+                                                                long long m,
                                                                 const unsigned long long *prefix,
                                                                 const long long *krem,
                                                                 const long long *bsum,
                                                                 long long *parent, long long K,
-                                                                const int *done) {
+                                                                CRows rows, const int *done) {
   if (stopped(done)) return;
   __shared__ int cnt[kScanItems][kScanBlock / 64];
   const unsigned long long thr = prefix[0];
   const long long tpos = krem[0];
   const long long base = (long long)blockIdx.x * kScanTile;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  long long before = 0;
+  for (long long q = threadIdx.x; q < blockIdx.x; q += kScanBlock) before += bsum[q];
   bool f[kScanItems];
   unsigned long long bal[kScanItems];
+  double a = 0.0, b = 0.0;
 #pragma unroll
   for (int q = 0; q < kScanItems; ++q) {
     const long long i = base + q * kScanBlock + threadIdx.x;
-    f[q] = i < m && selected(err[i], i, thr, tpos);
+    f[q] = false;
+    if (i < m) {
+      const double e = err[i];
+      f[q] = selected(e, i, thr, tpos);
+      if (!f[q] && !retired(e)) {
+        a += I7[i];
+        b += e;
+      }
+    }
     bal[q] = __ballot(f[q]);
     if (lane == 0) cnt[q][w] = __popcll(bal[q]);
   }
-  __syncthreads();
+  long long rank;
+  (void)block_excl_scan(before, &rank);  // (also orders cnt's writes before the reads)
   const unsigned long long below = (1ull << lane) - 1ull;
-  long long rank = bsum[blockIdx.x];
 #pragma unroll
   for (int q = 0; q < kScanItems; ++q) {
     long long pre = 0, all = 0;
@@ -573,19 +625,17 @@ __global__ void __launch_bounds__(kScanBlock) split_mark_kernel(double *err, lon
     }
     rank += all;
   }
+  put_row(rows, a, b);
 }
 
 // top-K by a 16-bit first digit ------------------------------------------------
 //
-// The K largest keys, ties to the lower position, in four launches: the
+// The K largest keys, ties to the lower position, in three launches: the
 // histogram of the keys' top 16 bits (sign, exponent and 4 mantissa bits of
 // the error) and of their top 8 bits; the digit that holds the K-th key (the
-// 8-bit digit first, then the 16-bit one within it); the keys and positions
-// of that digit's regions gathered; the exact K-th (key, position) among
-// them.
-
-constexpr int kTopBins = 1 << 16;
-constexpr int kTopThreads = 1024;
+// 8-bit digit first, then the 16-bit one within it, found by every block)
+// and the keys and positions of that digit's regions gathered; the exact
+// K-th (key, position) among them.
 
 __device__ __forceinline__ long long block_excl_scan_1024(long long v, long long *total) {
   __shared__ long long wtot[kTopThreads / 64];
@@ -608,40 +658,58 @@ __device__ __forceinline__ long long block_excl_scan_1024(long long v, long long
   return off + incl - v;
 }
 
-// Among 256 counts (thread t < 256 holds cnt, the count of digit 255 - t, so
-// the threads run from the top digit down), the digit where the running
-// count reaches `need': its number and the need left within it.
-__device__ __forceinline__ void pick_digit(long long cnt, long long need, int *dg,
-                                           long long *left) {
+// Among nb = 256 * PER digit counts, thread t of 1024 holding the PER
+// counts of digits nb - 1 - (PER t + q), q = 0 .. PER - 1 (from the top
+// digit down; threads past nb hold none): the digit where the running count
+// reaches `need', the need left within it, and its count.
+template <int PER>
+__device__ __forceinline__ void pick_digit(const long long (&c)[PER], long long need, int nb,
+                                           int *dg, long long *left, long long *count) {
   __shared__ int s_dg;
-  __shared__ long long s_left;
+  __shared__ long long s_left, s_cnt;
   const int t = threadIdx.x;
-  if (t == 0) {  // (not reached while need <= the total, as it always is)
+  if (t == 0) {  // (not kept while need <= the total, as it always is)
     s_dg = 0;
     s_left = 1;
+    s_cnt = 1;
   }
+  long long sum = 0;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) sum += c[q];
   long long tot;
-  const long long above = block_excl_scan_1024(t < 256 ? cnt : 0, &tot);
-  if (t < 256 && above < need && above + cnt >= need) {
-    s_dg = 255 - t;
-    s_left = need - above;
+  long long above = block_excl_scan_1024(sum, &tot);
+  if (above < need && above + sum >= need) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      if (above + c[q] >= need) {
+        s_dg = nb - 1 - (PER * t + q);
+        s_left = need - above;
+        s_cnt = c[q];
+        break;
+      }
+      above += c[q];
+    }
   }
   __syncthreads();
   *dg = s_dg;
   *left = s_left;
+  *count = s_cnt;
   __syncthreads();
 }
 
 // Per block a histogram of 16-bit counters in LDS (two to a 32-bit word: a
 // block sees fewer than 2^16 keys, so a half never carries into the other),
 // added into the global 16-bit-digit histogram and its 8-bit-digit one.
+// Opens the step (open) and clears the candidate count.
 __global__ void __launch_bounds__(kTopThreads) topk_hist_kernel(const double *err, long long m,
                                                                 unsigned *ghist,
                                                                 unsigned *gcoarse,
-                                                                const int *done) {
-  if (stopped(done)) return;
+                                                                unsigned long long *cnt,
+                                                                CRows open, int *done) {
+  if (stopped(done) || !open_step(open, done)) return;
   extern __shared__ unsigned lh[];  // kTopBins / 2 words, then 256 coarse counters
   unsigned *lc = lh + kTopBins / 2;
+  if (blockIdx.x == 0 && threadIdx.x == 0) cnt[0] = 0ull;
   for (int q = threadIdx.x; q < kTopBins / 2 + 256; q += kTopThreads) lh[q] = 0u;
   __syncthreads();
   for (long long i = (long long)blockIdx.x * kTopThreads + threadIdx.x; i < m;
@@ -660,68 +728,69 @@ __global__ void __launch_bounds__(kTopThreads) topk_hist_kernel(const double *er
   if (threadIdx.x < 256 && lc[threadIdx.x]) atomicAdd(&gcoarse[threadIdx.x], lc[threadIdx.x]);
 }
 
-// One workgroup: the boundary digit to prefix[0] and the rank wanted within
-// it (from 1) to krem[0]; the 8-bit histogram and the candidate count are
-// cleared (the 16-bit one by the gather).
-__global__ void __launch_bounds__(kTopThreads) topk_pick_kernel(unsigned *ghist,
-                                                                unsigned *gcoarse, long long K,
-                                                                unsigned long long *prefix,
-                                                                long long *krem,
-                                                                unsigned long long *cnt,
-                                                                const int *done) {
-  if (stopped(done)) return;
-  const int t = threadIdx.x;
-  int hi8, lo8;
-  long long need;
-  pick_digit(t < 256 ? (long long)gcoarse[255 - t] : 0, K, &hi8, &need);
-  pick_digit(t < 256 ? (long long)ghist[(hi8 << 8) + 255 - t] : 0, need, &lo8, &need);
-  if (t < 256) gcoarse[t] = 0u;
-  if (t == 0) {
-    prefix[0] = (unsigned long long)((hi8 << 8) | lo8);
-    krem[0] = need;
-    cnt[0] = 0ull;
-  }
-}
-
-// The keys and positions of the boundary digit's regions (any order), one
-// atomic add per wavefront; the 16-bit histogram is cleared for the next
-// selection.
+// Every block finds the boundary digit (the 8-bit digit holding the K-th
+// key, then the 16-bit digit within it) from the histograms; block 0 writes
+// it to prefix[0] and the rank wanted within it (from 1) to krem[0].  Then
+// the keys and positions of the digit's regions are gathered (any order),
+// one atomic add per block and pass.
 __global__ void __launch_bounds__(kTopThreads) topk_gather_kernel(const double *err, long long m,
-                                                                  const unsigned long long *prefix,
+                                                                  long long K,
+                                                                  const unsigned *ghist,
+                                                                  const unsigned *gcoarse,
+                                                                  unsigned long long *prefix,
+                                                                  long long *krem,
                                                                   unsigned long long *ckey,
                                                                   long long *cpos,
                                                                   unsigned long long *cnt,
-                                                                  unsigned *ghist,
                                                                   const int *done) {
   if (stopped(done)) return;
-  const unsigned long long dg = prefix[0];
-  const int lane = threadIdx.x & 63;
-  for (long long i = (long long)blockIdx.x * kTopThreads + threadIdx.x; i < kTopBins;
-       i += (long long)gridDim.x * kTopThreads)
-    ghist[i] = 0u;
+  __shared__ unsigned wc[kTopThreads / 64];
+  __shared__ unsigned long long s_base;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  int hi8, lo8;
+  long long need, c8;
+  {
+    const long long c1[1] = {t < 256 ? (long long)gcoarse[255 - t] : 0};
+    pick_digit<1>(c1, K, 256, &hi8, &need, &c8);
+    const long long c2[1] = {t < 256 ? (long long)ghist[(hi8 << 8) + 255 - t] : 0};
+    pick_digit<1>(c2, need, 256, &lo8, &need, &c8);
+  }
+  // (pick_digit counts digit 255 - t for thread t; threads from 256 on hold 0)
+  const unsigned long long dg = (unsigned long long)((hi8 << 8) | lo8);
+  if (blockIdx.x == 0 && t == 0) {
+    prefix[0] = dg;
+    krem[0] = need;
+  }
   for (long long i0 = (long long)blockIdx.x * kTopThreads; i0 < m;
        i0 += (long long)gridDim.x * kTopThreads) {
-    const long long i = i0 + threadIdx.x;
+    const long long i = i0 + t;
     const unsigned long long k = i < m ? key_of(err[i]) : 0ull;
     const bool sel = i < m && (k >> 48) == dg;
     const unsigned long long bal = __ballot(sel);
-    if (bal == 0ull) continue;
-    const int first = (int)__ffsll((long long)bal) - 1;
-    unsigned long long base = 0;
-    if (lane == first) base = atomicAdd(cnt, (unsigned long long)__popcll(bal));
-    base = __shfl(base, first, 64);
+    if (lane == 0) wc[w] = (unsigned)__popcll(bal);
+    __syncthreads();
+    unsigned off = 0, all = 0;
+    for (int q = 0; q < kTopThreads / 64; ++q) {
+      if (q < w) off += wc[q];
+      all += wc[q];
+    }
+    if (t == 0 && all) s_base = atomicAdd(cnt, (unsigned long long)all);
+    __syncthreads();
     if (sel) {
-      const unsigned long long o = base + __popcll(bal & ((1ull << lane) - 1ull));
+      const unsigned long long o = s_base + off + __popcll(bal & ((1ull << lane) - 1ull));
       ckey[o] = k;
       cpos[o] = i;
     }
+    __syncthreads();  // wc and s_base are rewritten by the next pass
   }
 }
 
 // One workgroup: among the gathered regions, the one of rank krem[0] (from
-// 1) in the order key descending, position ascending, by radix passes of 8
-// bits over the key's low 48 bits (descending) and then over the position's
-// low 32 bits (ascending); its key to prefix[0], its position to krem[0].
+// 1) in the order key descending, position ascending: radix passes of 12
+// bits over the key's low 48 bits (descending); then, if the regions with
+// that key are not all taken (a tie across the threshold), passes of 8 bits
+// over the positions (ascending), else the largest of their positions.  Its
+// key to prefix[0], its position to krem[0].
 __global__ void __launch_bounds__(kTopThreads) topk_exact_kernel(const unsigned long long *ckey,
                                                                  const long long *cpos,
                                                                  const unsigned long long *cnt,
@@ -729,45 +798,63 @@ __global__ void __launch_bounds__(kTopThreads) topk_exact_kernel(const unsigned 
                                                                  long long *krem,
                                                                  const int *done) {
   if (stopped(done)) return;
-  __shared__ unsigned h[256];
+  __shared__ unsigned h[4096];
+  __shared__ unsigned long long s_max;
   const int t = threadIdx.x;
   const unsigned long long dg = prefix[0];
   const long long mc = (long long)cnt[0];
-  long long need = krem[0];
+  long long need = krem[0], group = 0;
   unsigned long long pre = dg << 48, mask = 0xFFFFull << 48;  // key bits fixed so far
   int dig;
-  // key passes: descending digits
-  for (int shift = 40; shift >= 0; shift -= 8) {
-    if (t < 256) h[t] = 0u;
+  for (int shift = 36; shift >= 0; shift -= 12) {
+    for (int q = t; q < 4096; q += kTopThreads) h[q] = 0u;
     __syncthreads();
     for (long long i = t; i < mc; i += kTopThreads) {
       const unsigned long long k = ckey[i];
-      if ((k & mask) == pre) atomicAdd(&h[(k >> shift) & 255ull], 1u);
+      if ((k & mask) == pre) atomicAdd(&h[(k >> shift) & 4095ull], 1u);
     }
     __syncthreads();
-    pick_digit(t < 256 ? (long long)h[255 - t] : 0, need, &dig, &need);
+    long long c4[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) c4[q] = h[4095 - (4 * t + q)];
+    pick_digit<4>(c4, need, 4096, &dig, &need, &group);
     pre |= (unsigned long long)dig << shift;
-    mask |= 255ull << shift;
+    mask |= 4095ull << shift;
   }
-  // position passes among the regions with the threshold key: ascending
-  // (positions are below 2^32: a region store of 2^32 regions would need
-  // over 500 GB), so thread t holds digit t, counted from the top as 255 - t
-  unsigned long long ppre = 0ull, pmask = 0xFFFFFFFF00000000ull;
-  for (int shift = 24; shift >= 0; shift -= 8) {
-    if (t < 256) h[t] = 0u;
+  unsigned long long tpos;
+  if (need == group) {  // every region with the threshold key is taken
+    if (t == 0) s_max = 0ull;
     __syncthreads();
-    for (long long i = t; i < mc; i += kTopThreads) {
-      const unsigned long long p = (unsigned long long)cpos[i];
-      if (ckey[i] == pre && (p & pmask) == ppre) atomicAdd(&h[(p >> shift) & 255ull], 1u);
+    unsigned long long mx = 0ull;
+    for (long long i = t; i < mc; i += kTopThreads)
+      if (ckey[i] == pre) mx = max(mx, (unsigned long long)cpos[i]);
+    atomicMax(&s_max, mx);
+    __syncthreads();
+    tpos = s_max;
+  } else {
+    // positions are below 2^32 (a store of 2^32 regions would need over
+    // 500 GB); thread t counts position digit t, which pick_digit sees as
+    // digit 255 - t
+    unsigned long long ppre = 0ull, pmask = 0xFFFFFFFF00000000ull;
+    long long gc;
+    for (int shift = 24; shift >= 0; shift -= 8) {
+      if (t < 256) h[t] = 0u;
+      __syncthreads();
+      for (long long i = t; i < mc; i += kTopThreads) {
+        const unsigned long long p = (unsigned long long)cpos[i];
+        if (ckey[i] == pre && (p & pmask) == ppre) atomicAdd(&h[(p >> shift) & 255ull], 1u);
+      }
+      __syncthreads();
+      const long long c1[1] = {t < 256 ? (long long)h[t] : 0};
+      pick_digit<1>(c1, need, 256, &dig, &need, &gc);
+      ppre |= (unsigned long long)(255 - dig) << shift;
+      pmask |= 255ull << shift;
     }
-    __syncthreads();
-    pick_digit(t < 256 ? (long long)h[t] : 0, need, &dig, &need);
-    ppre |= (unsigned long long)(255 - dig) << shift;
-    pmask |= 255ull << shift;
+    tpos = ppre;
   }
   if (t == 0) {
     prefix[0] = pre;
-    krem[0] = (long long)ppre;
+    krem[0] = (long long)tpos;
   }
 }
 
@@ -800,11 +887,9 @@ __global__ void __launch_bounds__(kScanBlock) totals_partial_kernel(const double
   }
 }
 
-// One workgroup: the tiles' sums in tile order; with `dec', the stop rule,
-// else out[0..1] only.
+// One workgroup: the tiles' sums in tile order into out[0..1].
 __global__ void __launch_bounds__(kScanBlock) totals_final_kernel(const double *part, long long nb,
-                                                                  double *out, int *done,
-                                                                  CStop stop, int dec) {
+                                                                  double *out, const int *done) {
   if (stopped(done)) return;
   double x = 0.0, y = 0.0;
   for (long long i = threadIdx.x; i < nb; i += kScanBlock) {
@@ -812,10 +897,7 @@ __global__ void __launch_bounds__(kScanBlock) totals_final_kernel(const double *
     y += part[nb + i];
   }
   const double2 T = block_sum2(x, y);
-  if (threadIdx.x != 0) return;
-  if (dec) {
-    decide(T.x, T.y, stop, out, done);
-  } else {
+  if (threadIdx.x == 0) {
     out[0] = T.x;
     out[1] = T.y;
   }
@@ -825,6 +907,10 @@ __global__ void __launch_bounds__(kScanBlock) totals_final_kernel(const double *
 // launchers
 
 long long scratch_blocks(long long n) { return (n + kScanTile - 1) / kScanTile; }
+long long split_rows(long long m) { return scratch_blocks(m); }
+long long step_rows(long long cap) {
+  return scratch_blocks(cap) + std::max<long long>((cap + 255) / 256, kWaveRuleBlocks);
+}
 
 template <int FAM>
 static void launch_rule_lane_d(const RuleArgs &A, unsigned grid, hipStream_t s) {
@@ -844,77 +930,80 @@ hipError_t launch_root_clear(const CRegions &R, int ndim, int *done, hipStream_t
   return hipGetLastError();
 }
 
+// A lane per region needs enough regions to fill the device; below that,
+// and above 8 dimensions (the registers a lane holds grow with d, and the
+// 2^d corners with it), a wavefront per region.
+static bool lane_rule(const RuleArgs &A) {
+  return A.nseg == 1 && A.one.ndim <= kLaneRuleMaxDim && A.total >= kLaneRuleMinRegions;
+}
+
+long long rule_blocks(const RuleArgs &A) {
+  if (A.total <= 0) return 0;
+  if (lane_rule(A)) return (A.total + 255) / 256;
+  return std::min<long long>((A.total + 3) / 4, kWaveRuleBlocks);
+}
+
 hipError_t launch_rule(const RuleArgs &A, hipStream_t s) {
-  if (A.total <= 0) return hipSuccess;
-  // A lane per region needs enough regions to fill the device; below that,
-  // and above 8 dimensions (the registers a lane holds grow with d, and the
-  // 2^d corners with it), a wavefront per region.
-  if (A.nseg == 1 && A.one.ndim <= kLaneRuleMaxDim && A.total >= kLaneRuleMinRegions) {
-    const unsigned grid = (unsigned)((A.total + 255) / 256);
+  const long long grid = rule_blocks(A);
+  if (grid <= 0) return hipSuccess;
+  if (lane_rule(A)) {
     switch (A.one.family) {
-      case GAUSSIAN: launch_rule_lane_d<GAUSSIAN>(A, grid, s); break;
-      case OSCILLATORY: launch_rule_lane_d<OSCILLATORY>(A, grid, s); break;
-      case PRODUCT_PEAK: launch_rule_lane_d<PRODUCT_PEAK>(A, grid, s); break;
-      case CORNER_PEAK: launch_rule_lane_d<CORNER_PEAK>(A, grid, s); break;
-      default: launch_rule_lane_d<C0>(A, grid, s); break;
+      case GAUSSIAN: launch_rule_lane_d<GAUSSIAN>(A, (unsigned)grid, s); break;
+      case OSCILLATORY: launch_rule_lane_d<OSCILLATORY>(A, (unsigned)grid, s); break;
+      case PRODUCT_PEAK: launch_rule_lane_d<PRODUCT_PEAK>(A, (unsigned)grid, s); break;
+      case CORNER_PEAK: launch_rule_lane_d<CORNER_PEAK>(A, (unsigned)grid, s); break;
+      default: launch_rule_lane_d<C0>(A, (unsigned)grid, s); break;
     }
     return hipGetLastError();
   }
-  const long long grid = std::min<long long>((A.total + 3) / 4, kWaveRuleBlocks);
   hipLaunchKernelGGL(gm_rule_kernel, dim3((unsigned)grid), dim3(256), 0, s, A);
   return hipGetLastError();
 }
 
 hipError_t launch_select16(const CRegions &R, long long m, long long K, const CScratch &S,
-                           hipStream_t s) {
+                           hipStream_t s, const CRows *open) {
   // blocks see fewer than 2^16 keys each (the LDS counters are 16-bit)
   const long long per = 32768;
   const int hgrid = (int)std::max<long long>(std::min<long long>(256, (m + kTopThreads - 1) /
                                                                           kTopThreads),
                                              (m + per - 1) / per);
+  const CRows none{};
   hipLaunchKernelGGL(topk_hist_kernel, dim3(hgrid), dim3(kTopThreads), (kTopBins / 2 + 256) * 4,
-                     s, R.err, m, S.hist16, S.coarse, (const int *)S.done);
-  hipLaunchKernelGGL(topk_pick_kernel, dim3(1), dim3(kTopThreads), 0, s, S.hist16, S.coarse, K,
-                     S.prefix, S.krem, S.cand_cnt, (const int *)S.done);
-  const int ggrid = (int)std::max<long long>(
-      kTopBins / kTopThreads, std::min<long long>(512, (m + kTopThreads - 1) / kTopThreads));
-  hipLaunchKernelGGL(topk_gather_kernel, dim3(ggrid), dim3(kTopThreads), 0, s, R.err, m,
-                     S.prefix, S.cand_key, S.cand_pos, S.cand_cnt, S.hist16, (const int *)S.done);
+                     s, R.err, m, S.hist16, S.coarse, S.cand_cnt, open ? *open : none, S.done);
+  const int ggrid = (int)std::min<long long>(256, (m + kTopThreads - 1) / kTopThreads);
+  hipLaunchKernelGGL(topk_gather_kernel, dim3(ggrid), dim3(kTopThreads), 0, s, R.err, m, K,
+                     S.hist16, S.coarse, S.prefix, S.krem, S.cand_key, S.cand_pos, S.cand_cnt,
+                     (const int *)S.done);
   hipLaunchKernelGGL(topk_exact_kernel, dim3(1), dim3(kTopThreads), 0, s, S.cand_key, S.cand_pos,
                      S.cand_cnt, S.prefix, S.krem, (const int *)S.done);
   return hipGetLastError();
 }
 
 hipError_t launch_split(const CRegions &R, long long m, long long K, const CScratch &S,
-                        hipStream_t s) {
+                        hipStream_t s, const CRows *rows) {
   const long long nb = scratch_blocks(m);
+  const CRows none{};
   hipLaunchKernelGGL(sel_count_kernel, dim3((unsigned)nb), dim3(kScanBlock), 0, s, R.err, m,
-                     S.prefix, S.krem, S.bsum, (const int *)S.done);
-  hipLaunchKernelGGL(scan_bsum_kernel, dim3(1), dim3(kScanBlock), 0, s, S.bsum, nb,
+                     S.prefix, S.krem, S.bsum, S.hist16, S.coarse, (const int *)S.done);
+  hipLaunchKernelGGL(split_mark_kernel, dim3((unsigned)nb), dim3(kScanBlock), 0, s, R.err, R.I7,
+                     m, S.prefix, S.krem, S.bsum, S.parent, K, rows ? *rows : none,
                      (const int *)S.done);
-  hipLaunchKernelGGL(split_mark_kernel, dim3((unsigned)nb), dim3(kScanBlock), 0, s, R.err, m,
-                     S.prefix, S.krem, S.bsum, S.parent, K, (const int *)S.done);
   return hipGetLastError();
 }
 
-static hipError_t launch_totals_any(const CRegions &R, long long m, const CScratch &S,
-                                    double *out, const CStop &stop, int dec, hipStream_t s) {
-  const long long nb = scratch_blocks(m);
-  hipLaunchKernelGGL(totals_partial_kernel, dim3((unsigned)nb), dim3(kScanBlock), 0, s, R.I7,
-                     R.err, m, S.tot, (const int *)S.done);
-  hipLaunchKernelGGL(totals_final_kernel, dim3(1), dim3(kScanBlock), 0, s, S.tot, nb, out,
-                     S.done, stop, dec);
+hipError_t launch_decide(const CRows &rows, int *done, hipStream_t s) {
+  hipLaunchKernelGGL(cuhre_decide_kernel, dim3(1), dim3(256), 0, s, rows, done);
   return hipGetLastError();
 }
 
 hipError_t launch_totals(const CRegions &R, long long m, const CScratch &S, double *out,
                          hipStream_t s) {
-  return launch_totals_any(R, m, S, out, CStop{}, 0, s);
-}
-
-hipError_t launch_totals_decide(const CRegions &R, long long m, const CScratch &S, double *out,
-                                const CStop &stop, hipStream_t s) {
-  return launch_totals_any(R, m, S, out, stop, 1, s);
+  const long long nb = scratch_blocks(m);
+  hipLaunchKernelGGL(totals_partial_kernel, dim3((unsigned)nb), dim3(kScanBlock), 0, s, R.I7,
+                     R.err, m, S.tot, (const int *)S.done);
+  hipLaunchKernelGGL(totals_final_kernel, dim3(1), dim3(kScanBlock), 0, s, S.tot, nb, out,
+                     (const int *)S.done);
+  return hipGetLastError();
 }
 
 hipError_t cuhre_set_kernel_limits() {

@@ -11,6 +11,7 @@
 #include "cuhre_engine.h"
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <vector>
 
@@ -83,7 +84,9 @@ int CuhreRun::alloc_store(CRegions &R, DevBuf<double> &cb, DevBuf<double> &hb,
 int CuhreRun::alloc_scratch(long long cap) {
   int rc;
   const long long nb = scratch_blocks(cap);
-  if ((rc = bsum_.alloc(ctx_, nb)) || (rc = tot_.alloc(ctx_, 2 * nb)) ||
+  rows_stride_ = step_rows(cap);
+  // two halves of rows (this state's and the next), each I rows then err rows
+  if ((rc = bsum_.alloc(ctx_, nb)) || (rc = tot_.alloc(ctx_, 4 * rows_stride_)) ||
       (rc = parent_.alloc(ctx_, cap / 2 + 1)) || (rc = cand_key_.alloc(ctx_, cap)) ||
       (rc = cand_pos_.alloc(ctx_, cap)))
     return rc;
@@ -216,16 +219,21 @@ int CuhreRun::start(const CuhreSpec &spec, hipStream_t s) {
   seg.regs = R_;
   n_ = 1;
   neval_ = np_;
-  return launch_rule_alone(seg, s);
+  // the root's totals: rows of half 0
+  const CRows rows{nullptr, 0, tot_.p, 0, rows_stride_, nullptr, 0, CStop{}};
+  rows_par_ = 0;
+  return launch_rule_alone(seg, s, &rows, &rows_n_);
 }
 
-int CuhreRun::launch_rule_alone(const CSeg &seg, hipStream_t s) {
-  return launch_rule_segments(ctx_, &seg, 1, seg_, seg_end_, w7_.p, w5_.p, s, stop_.p);
+int CuhreRun::launch_rule_alone(const CSeg &seg, hipStream_t s, const CRows *rows,
+                                long long *blocks) {
+  return launch_rule_segments(ctx_, &seg, 1, seg_, seg_end_, w7_.p, w5_.p, s, stop_.p, rows,
+                              blocks);
 }
 
 int launch_rule_segments(ccuba_ctx *ctx, const CSeg *segs, int nseg, DevBuf<CSeg> &dsegs,
                          DevBuf<long long> &dends, const double *w7_dev, const double *w5_dev,
-                         hipStream_t s, const int *done) {
+                         hipStream_t s, int *done, const CRows *rows, long long *blocks) {
   if (nseg <= 0) return CCUBA_OK;
   int rc;
   std::vector<long long> ends(nseg);
@@ -256,6 +264,8 @@ int launch_rule_segments(ccuba_ctx *ctx, const CSeg *segs, int nseg, DevBuf<CSeg
   A.l3 = T.l3;
   A.l4 = T.l4;
   A.l5 = T.l5;
+  if (rows) A.rows = *rows;
+  if (blocks) *blocks = rule_blocks(A);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (ctx->profile) {
     CCUBA_HIP(hipEventCreate(&e0));
@@ -371,54 +381,51 @@ int CuhreRun::run(hipStream_t s) {
     long long n, neval, next_id;
     int batches;
   };
-  // the totals of the state before step t go to slot t % 2: 4 doubles (I,
-  // err, decision, -) in mapped pinned memory if the caller gave it, else in
-  // device memory
+  // the totals of the state before step t go to slot t % 2 of host-coherent
+  // pinned memory: I, err and the word seq << 8 | outcome (CRows), which the
+  // host polls; the caller's mapped block if given, else one of our own
   constexpr int kSlots = 2;
-  double *dev_slots = nullptr, *host_slots = nullptr;
-  DevBuf<double> slots;
-  if (mapped_host_) {
-    dev_slots = mapped_dev_;
-    host_slots = mapped_host_;
-  } else {
-    int rc = slots.alloc(ctx_, 4 * kSlots);
-    if (rc) return rc;
-    dev_slots = slots.p;
+  double *dev_slots = mapped_dev_, *host_slots = mapped_host_;
+  struct Pinned {
+    void *p = nullptr;
+    ~Pinned() {
+      if (p) (void)hipHostFree(p);
+    }
+  } own;
+  if (!host_slots) {
+    CCUBA_HIP(hipHostMalloc(&own.p, 4 * kSlots * sizeof(double),
+                            hipHostMallocMapped | hipHostMallocCoherent));
+    void *d = nullptr;
+    CCUBA_HIP(hipHostGetDevicePointer(&d, own.p, 0));
+    host_slots = (double *)own.p;
+    dev_slots = (double *)d;
   }
   auto slot = [&](int t) { return 4 * (t % kSlots); };
-  hipEvent_t ev[2] = {nullptr, nullptr};
-  CCUBA_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
-  if (hipEventCreateWithFlags(&ev[1], hipEventDisableTiming) != hipSuccess) {
-    (void)hipEventDestroy(ev[0]);
-    return CCUBA_EHIP;
-  }
-  struct Events {
-    hipEvent_t *e;
-    ~Events() {
-      (void)hipEventDestroy(e[0]);
-      (void)hipEventDestroy(e[1]);
-    }
-  } guard{ev};
-  // the outcome of step t's totals: 0 go on, 1 converged, 2 not finite.
-  // The event is polled: a blocking wait adds a wake-up of ~10 us to every
-  // step, longer than a small step's work.
-  auto outcome = [&](int t, double *I, double *E) -> int {
-    hipError_t q;
-    while ((q = hipEventQuery(ev[t & 1])) == hipErrorNotReady) {
-    }
-    if (q != hipSuccess) return CCUBA_EHIP;
-    double v[4];
-    if (host_slots) {
-      for (int k = 0; k < 4; ++k) v[k] = host_slots[slot(t) + k];
-    } else {
-      CCUBA_HIP(hipMemcpy(v, dev_slots + slot(t), sizeof(v), hipMemcpyDeviceToHost));
-    }
-    *I = v[0];
-    *E = v[1];
-    return (int)v[2];
+  auto word = [&](int t) {
+    return (volatile unsigned long long *)(host_slots + slot(t) + 2);
   };
-  // finish with the state of step t (its totals decided the end)
-  auto finish = [&](const Plan &p, int code, double I, double E) -> int {
+  for (int q = 0; q < kSlots; ++q) *word(q) = ~0ull;  // no state's word
+  // the outcome of state t: 0 go on, 1 converged, 2 not finite.  Polled: a
+  // blocking wait adds a wake-up of ~10 us to every step, longer than a
+  // small step's work, and an event recorded per step costs the device ~5 us
+  // (a system-scope release).  If the word does not come within a second,
+  // the stream is drained and it is read once more.
+  auto outcome = [&](int t) -> int {
+    const unsigned long long want = (unsigned long long)t;
+    auto t0 = std::chrono::steady_clock::now();
+    for (unsigned spin = 0;; ++spin) {
+      const unsigned long long w = *word(t);
+      if ((w >> 8) == want) return (int)(w & 0xFFull);
+      if ((spin & 4095u) == 4095u &&
+          std::chrono::steady_clock::now() - t0 > std::chrono::seconds(1)) {
+        CCUBA_HIP(hipStreamSynchronize(s));
+        const unsigned long long w2 = *word(t);
+        return (w2 >> 8) == want ? (int)(w2 & 0xFFull) : CCUBA_EHIP;
+      }
+    }
+  };
+  // finish with state q, whose outcome (code) ended the run
+  auto finish = [&](const Plan &p, int q, int code) -> int {
     CCUBA_HIP(hipStreamSynchronize(s));  // queued launches run empty; the last ones end
     n_ = p.n;
     neval_ = p.neval;
@@ -431,64 +438,77 @@ int CuhreRun::run(hipStream_t s) {
       I_ = E_ = 0.0;
     } else {
       fail_ = code == 1 ? 0 : 1;
-      I_ = I;
-      E_ = E;
+      I_ = host_slots[slot(q)];
+      E_ = host_slots[slot(q) + 1];
     }
     return CCUBA_OK;
   };
   // Outcomes are learned in step order; `known' is the last step learned
-  // (all of them "go on"), with its totals.
+  // (all of them "go on").
   int known = -1;
-  double kI = 0.0, kE = 0.0;
-  // learn step q's outcome (the state before its work is p); true when it
-  // ended the run, which is then finished
+  // learn state q's outcome (p: the plan of state q); true when it ended
+  // the run, which is then finished
   auto learn = [&](int q, const Plan &p, int *rc) -> bool {
-    double I, E;
-    const int code = outcome(q, &I, &E);
+    const int code = outcome(q);
     if (code < 0) {
       *rc = code;
       return true;
     }
     known = q;
-    kI = I;
-    kE = E;
     if (code == 0) return false;
-    *rc = finish(p, code, I, E);
+    *rc = finish(p, q, code);
     return true;
   };
   Plan prev{};
   for (int t = 0;; ++t) {
     const Plan cur{n_, neval_, next_id_, batches_};
     const CStop stop{spec_.epsrel, spec_.epsabs, spec_.mineval, neval_};
-    CCUBA_HIP(launch_totals_decide(R_, next_id_, S_, dev_slots + slot(t), stop, s));
-    CCUBA_HIP(hipEventRecord(ev[t & 1], s));
+    // this state's rows; the step's first launch decides on them
+    CRows open{tot_.p + 2 * rows_stride_ * rows_par_, rows_n_, nullptr, 0, rows_stride_,
+               dev_slots + slot(t), t, stop};
     long long K = std::min(spec_.batch / 2, n_);
     const long long budget = spec_.maxeval > neval_ ? (spec_.maxeval - neval_) / (2 * np_) : 0;
     K = std::min(K, budget);
     int rc = 0;
-    if (K > 0 && next_id_ + 2 * K > cap_) {
-      // the store must grow (a synchronisation and a copy): only for a step
-      // known to run, so learn steps t - 1 and t first
+    const bool grow = K > 0 && next_id_ + 2 * K > cap_;
+    bool opened = false;
+    if (K <= 0 || grow) {  // decided by a launch of its own
+      CCUBA_HIP(launch_decide(open, stop_.p, s));
+      opened = true;
+    }
+    if (grow) {
+      // the store must grow (a synchronisation and a copy; the rows move
+      // too): only for a step known to run, so learn steps t - 1 and t first
       if (t - 1 > known && learn(t - 1, prev, &rc)) return rc;
       if (learn(t, cur, &rc)) return rc;
       if ((rc = ensure(next_id_ + 2 * K, s))) return rc < 0 ? rc : CCUBA_EHIP;
     }
     if (K > 0) {  // queue step t's work, possibly before learning step t - 1's outcome
+      const int npar = 1 - rows_par_;
+      double *next = tot_.p + 2 * rows_stride_ * npar;
+      long long rb = 0;
       if (K == n_ && contig_) {  // every region splits: no selection
-        if ((rc = launch_rule_alone(children_segment(K, true), s))) return rc;
+        CRows rows{opened ? nullptr : open.in, open.nin, next, 0, rows_stride_, open.slot, t, stop};
+        if ((rc = launch_rule_alone(children_segment(K, true), s, &rows, &rb))) return rc;
+        rows_n_ = rb;
       } else {
-        CCUBA_HIP(launch_select16(R_, next_id_, K, S_, s));
-        CCUBA_HIP(launch_split(R_, next_id_, K, S_, s));
-        if ((rc = launch_rule_alone(children_segment(K, false), s))) return rc;
+        CCUBA_HIP(launch_select16(R_, next_id_, K, S_, s, opened ? nullptr : &open));
+        const long long sr = split_rows(next_id_);
+        const CRows keep{nullptr, 0, next, 0, rows_stride_, nullptr, 0, CStop{}};
+        CCUBA_HIP(launch_split(R_, next_id_, K, S_, s, &keep));
+        const CRows kids{nullptr, 0, next, sr, rows_stride_, nullptr, 0, CStop{}};
+        if ((rc = launch_rule_alone(children_segment(K, false), s, &kids, &rb))) return rc;
+        rows_n_ = sr + rb;
         contig_ = false;
       }
+      rows_par_ = npar;
       pendK_ = K;
       commit_pending();
     }
     if (t - 1 > known && learn(t - 1, prev, &rc)) return rc;
     if (K <= 0) {  // out of budget after step t, unless its totals ended it first
       if (t > known && learn(t, cur, &rc)) return rc;
-      return finish(cur, 0, kI, kE);  // fail 1
+      return finish(cur, t, 0);  // fail 1
     }
     prev = cur;
   }

@@ -64,7 +64,10 @@ class CuhreRun {
   int batches() const { return batches_; }
   const CuhreSpec &spec() const { return spec_; }
   size_t bytes() const;
-  int launch_rule_alone(const CSeg &seg, hipStream_t s);
+  // (rows: step opening and rows of the next state; *blocks: the launch's
+  // blocks, one row each)
+  int launch_rule_alone(const CSeg &seg, hipStream_t s, const CRows *rows = nullptr,
+                        long long *blocks = nullptr);
   const double *params_dev() const { return params_.p; }
 
  private:
@@ -84,6 +87,9 @@ class CuhreRun {
   bool done_ = false;
   bool contig_ = true;       // the live regions are the last n_ of the store
   bool pend_range_ = false;  // the pending children come from a range of parents
+  // the current state's totals as rows (CRows) in half rows_par_ of tot_
+  int rows_par_ = 0;
+  long long rows_n_ = 0, rows_stride_ = 0;
   double I_ = 0, E_ = 0;
   CRegions R_{};
   DevBuf<double> c_, h_, vals_;
@@ -107,6 +113,7 @@ class CuhreRun {
 // and ends are host arrays copied to the device buffers given.
 int launch_rule_segments(ccuba_ctx *ctx, const CSeg *segs, int nseg, DevBuf<CSeg> &dsegs,
                          DevBuf<long long> &dends, const double *w7_dev, const double *w5_dev,
-                         hipStream_t s, const int *done = nullptr);
+                         hipStream_t s, int *done = nullptr, const CRows *rows = nullptr,
+                         long long *blocks = nullptr);
 
 }  // namespace ccuba
