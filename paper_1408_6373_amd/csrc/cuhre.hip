@@ -37,7 +37,7 @@ namespace ccuba {
 namespace {
 
 constexpr int kLaneRuleMaxDim = 8;          // lane-per-region rule up to this d
-constexpr long long kLaneRuleMinRegions = 16384;  // and from this many regions on
+constexpr long long kLaneRuleMinRegions = 512;  // and from this many regions on
 constexpr long long kWaveRuleBlocks = 2048;       // most blocks of a wave-per-region launch
 constexpr int kScanItems = 4;
 constexpr int kScanBlock = 256;
@@ -259,17 +259,28 @@ __device__ __forceinline__ double lane_point(const double (&c)[D], const double 
   return Genz<double, FAM>::finish(acc, D);
 }
 
+// The rule points of one region split over the four wavefronts of a block
+// (lane l of every wavefront holds region l of the block's 64): wavefront 0
+// takes the centre, classes 1 and 2 and the fourth differences; classes 3
+// (the pairs of axes, in order, dealt round-robin to wavefronts 1-3) and 4
+// (corner sg to wavefront sg mod 4) are shared.  Each wavefront's class sums
+// go to LDS (sums[w][k][lane]); wavefront 0 adds the four in wavefront order
+// and forms I7, I5, err and the split axis.  Returns (I7, err) in
+// wavefront 0's lanes of live regions.
 template <int FAM, int D>
-__device__ double2 rule_region_lane(const RuleArgs &A, const CSeg &S, long long r) {
+__device__ double2 rule_region_quad(const RuleArgs &A, const CSeg &S, long long r, bool live,
+                                    int w, int lane, double (*sums)[5][64]) {
   const long long cap = S.regs.cap;
   double c[D], h[D];
-  if (!S.children) {
+#pragma unroll
+  for (int j = 0; j < D; ++j) c[j] = h[j] = 0.5;  // (a lane past the end computes on these)
+  if (live && !S.children) {
 #pragma unroll
     for (int j = 0; j < D; ++j) {
       c[j] = S.regs.c[j * cap + r];
       h[j] = S.regs.h[j * cap + r];
     }
-  } else {  // a child: formed from its parent, as child_coord does per axis
+  } else if (live) {  // a child: formed from its parent, as child_coord does per axis
     const long long k = r - S.first;
     const long long p = S.parent ? S.parent[k >> 1] : S.pbase + (k >> 1);
     const int ax = S.regs.axis[p];
@@ -281,59 +292,66 @@ __device__ double2 rule_region_lane(const RuleArgs &A, const CSeg &S, long long 
         h[j] = h[j] / 2.0;
         c[j] = (k & 1) ? c[j] + h[j] : c[j] - h[j];
       }
-      S.regs.c[j * cap + r] = c[j];
-      S.regs.h[j * cap + r] = h[j];
+      if (w == 0) {
+        S.regs.c[j * cap + r] = c[j];
+        S.regs.h[j * cap + r] = h[j];
+      }
     }
-    if (S.retire && !(k & 1)) S.regs.err[p] = -1.0;
+    if (w == 0 && S.retire && !(k & 1)) S.regs.err[p] = -1.0;
   }
   const double *p0 = S.par;
   const double *p1 = S.par + kParamRow;
   const double phase0 = p1[0];
-  double Sk[5];
-  // class 0: the centre
-  const double f0 = lane_point<FAM, D>(c, h, p0, p1, phase0, -1, false, -1, false, 0.0);
-  Sk[0] = f0;
-  // classes 1 and 2: +-lambda on one axis; the fourth differences
-  double s1 = 0.0, s2 = 0.0, Dmax = -1.0;
+  double Sk[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   int best = 0;
-  double a2[D];
+  if (w == 0) {
+    // class 0: the centre
+    const double f0 = lane_point<FAM, D>(c, h, p0, p1, phase0, -1, false, -1, false, 0.0);
+    Sk[0] = f0;
+    // classes 1 and 2: +-lambda on one axis; the fourth differences
+    double s1 = 0.0, s2 = 0.0, Dmax = -1.0;
+    double a2[D];
 #pragma unroll
-  for (int i = 0; i < D; ++i) {
-    const double fp = lane_point<FAM, D>(c, h, p0, p1, phase0, i, false, -1, false, A.l2);
-    const double fm = lane_point<FAM, D>(c, h, p0, p1, phase0, i, true, -1, false, A.l2);
-    s1 += fp;
-    s1 += fm;
-    a2[i] = fp + fm - 2.0 * f0;
-  }
-  const double ratio = (A.l2 * A.l2) / (A.l3 * A.l3);
-#pragma unroll
-  for (int i = 0; i < D; ++i) {
-    const double fp = lane_point<FAM, D>(c, h, p0, p1, phase0, i, false, -1, false, A.l3);
-    const double fm = lane_point<FAM, D>(c, h, p0, p1, phase0, i, true, -1, false, A.l3);
-    s2 += fp;
-    s2 += fm;
-    const double a3 = fp + fm - 2.0 * f0;
-    const double Dj = fabs(a2[i] - ratio * a3);
-    if (Dj > Dmax) {  // strictly greater: the lowest axis wins ties
-      Dmax = Dj;
-      best = i;
+    for (int i = 0; i < D; ++i) {
+      const double fp = lane_point<FAM, D>(c, h, p0, p1, phase0, i, false, -1, false, A.l2);
+      const double fm = lane_point<FAM, D>(c, h, p0, p1, phase0, i, true, -1, false, A.l2);
+      s1 += fp;
+      s1 += fm;
+      a2[i] = fp + fm - 2.0 * f0;
     }
+    const double ratio = (A.l2 * A.l2) / (A.l3 * A.l3);
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      const double fp = lane_point<FAM, D>(c, h, p0, p1, phase0, i, false, -1, false, A.l3);
+      const double fm = lane_point<FAM, D>(c, h, p0, p1, phase0, i, true, -1, false, A.l3);
+      s2 += fp;
+      s2 += fm;
+      const double a3 = fp + fm - 2.0 * f0;
+      const double Dj = fabs(a2[i] - ratio * a3);
+      if (Dj > Dmax) {  // strictly greater: the lowest axis wins ties
+        Dmax = Dj;
+        best = i;
+      }
+    }
+    Sk[1] = s1;
+    Sk[2] = s2;
+  } else {
+    // class 3: +-lambda4 on two axes i < jj, pair q to wavefront 1 + q mod 3
+    double s3 = 0.0;
+    int q = 0;
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int jj = i + 1; jj < D; ++jj, ++q)
+        if (q % 3 == w - 1)
+#pragma unroll
+          for (int sg = 0; sg < 4; ++sg)
+            s3 += lane_point<FAM, D>(c, h, p0, p1, phase0, i, sg & 1, jj, (sg >> 1) & 1, A.l4);
+    Sk[3] = s3;
   }
-  Sk[1] = s1;
-  Sk[2] = s2;
-  // class 3: +-lambda4 on two axes i < jj
-  double s3 = 0.0;
-#pragma unroll
-  for (int i = 0; i < D; ++i)
-#pragma unroll
-    for (int jj = i + 1; jj < D; ++jj)
-#pragma unroll
-      for (int sg = 0; sg < 4; ++sg)
-        s3 += lane_point<FAM, D>(c, h, p0, p1, phase0, i, sg & 1, jj, (sg >> 1) & 1, A.l4);
-  Sk[3] = s3;
-  // class 4: every corner at +-lambda5
+  // class 4: the corners at +-lambda5, corner sg to wavefront sg mod 4
   double s4 = 0.0;
-  for (unsigned sg = 0; sg < (1u << D); ++sg) {
+  for (unsigned sg = (unsigned)w; sg < (1u << D); sg += 4u) {
     double acc = Genz<double, FAM>::init(phase0);
 #pragma unroll
     for (int j = 0; j < D; ++j) {
@@ -344,6 +362,13 @@ __device__ double2 rule_region_lane(const RuleArgs &A, const CSeg &S, long long 
     s4 += Genz<double, FAM>::finish(acc, D);
   }
   Sk[4] = s4;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) sums[w][k][lane] = Sk[k];
+  __syncthreads();
+  if (w != 0 || !live) return make_double2(0.0, 0.0);
+#pragma unroll
+  for (int k = 0; k < 5; ++k)
+    Sk[k] = ((sums[0][k][lane] + sums[1][k][lane]) + sums[2][k][lane]) + sums[3][k][lane];
   double vol = 1.0;
 #pragma unroll
   for (int j = 0; j < D; ++j) vol *= h[j];
@@ -441,13 +466,16 @@ __device__ __forceinline__ void put_row(const CRows &R, double a, double b) {
 
 }  // namespace
 
-// One integral (A.one), dimension D: one lane per region.
+// One integral (A.one), dimension D: 64 regions per block, one lane of each
+// of the block's four wavefronts per region (rule_region_quad).
 template <int FAM, int D>
 __global__ void __launch_bounds__(256) gm_rule_lane_kernel(RuleArgs A) {
+  __shared__ double sums[4][5][64];
   if (stopped(A.done) || !open_step(A.rows, A.done)) return;
-  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  double2 v = make_double2(0.0, 0.0);
-  if (g < A.total) v = rule_region_lane<FAM, D>(A, A.one, A.one.first + g);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const long long g = (long long)blockIdx.x * 64 + lane;
+  const double2 v =
+      rule_region_quad<FAM, D>(A, A.one, A.one.first + g, g < A.total, w, lane, sums);
   put_row(A.rows, v.x, v.y);
 }
 
@@ -806,12 +834,29 @@ __global__ void __launch_bounds__(kTopThreads) topk_exact_kernel(const unsigned 
   long long need = krem[0], group = 0;
   unsigned long long pre = dg << 48, mask = 0xFFFFull << 48;  // key bits fixed so far
   int dig;
+  // up to kExactReg keys per thread stay in registers across the passes (the
+  // padding ~0 has top digit 0xFFFF, which no live key has: the sign bit of
+  // a live error is clear)
+  constexpr int kExactReg = 16;
+  const bool inreg = mc <= (long long)kExactReg * kTopThreads;
+  unsigned long long kr[kExactReg];
+#pragma unroll
+  for (int q = 0; q < kExactReg; ++q) {
+    const long long i = t + (long long)q * kTopThreads;
+    kr[q] = inreg && i < mc ? ckey[i] : ~0ull;
+  }
   for (int shift = 36; shift >= 0; shift -= 12) {
     for (int q = t; q < 4096; q += kTopThreads) h[q] = 0u;
     __syncthreads();
-    for (long long i = t; i < mc; i += kTopThreads) {
-      const unsigned long long k = ckey[i];
-      if ((k & mask) == pre) atomicAdd(&h[(k >> shift) & 4095ull], 1u);
+    if (inreg) {
+#pragma unroll
+      for (int q = 0; q < kExactReg; ++q)
+        if ((kr[q] & mask) == pre) atomicAdd(&h[(kr[q] >> shift) & 4095ull], 1u);
+    } else {
+      for (long long i = t; i < mc; i += kTopThreads) {
+        const unsigned long long k = ckey[i];
+        if ((k & mask) == pre) atomicAdd(&h[(k >> shift) & 4095ull], 1u);
+      }
     }
     __syncthreads();
     long long c4[4];
@@ -826,8 +871,14 @@ __global__ void __launch_bounds__(kTopThreads) topk_exact_kernel(const unsigned 
     if (t == 0) s_max = 0ull;
     __syncthreads();
     unsigned long long mx = 0ull;
-    for (long long i = t; i < mc; i += kTopThreads)
-      if (ckey[i] == pre) mx = max(mx, (unsigned long long)cpos[i]);
+    if (inreg) {
+#pragma unroll
+      for (int q = 0; q < kExactReg; ++q)
+        if (kr[q] == pre) mx = max(mx, (unsigned long long)cpos[t + (long long)q * kTopThreads]);
+    } else {
+      for (long long i = t; i < mc; i += kTopThreads)
+        if (ckey[i] == pre) mx = max(mx, (unsigned long long)cpos[i]);
+    }
     atomicMax(&s_max, mx);
     __syncthreads();
     tpos = s_max;
@@ -909,7 +960,7 @@ __global__ void __launch_bounds__(kScanBlock) totals_final_kernel(const double *
 long long scratch_blocks(long long n) { return (n + kScanTile - 1) / kScanTile; }
 long long split_rows(long long m) { return scratch_blocks(m); }
 long long step_rows(long long cap) {
-  return scratch_blocks(cap) + std::max<long long>((cap + 255) / 256, kWaveRuleBlocks);
+  return scratch_blocks(cap) + std::max<long long>((cap + 63) / 64, kWaveRuleBlocks);
 }
 
 template <int FAM>
@@ -939,7 +990,7 @@ static bool lane_rule(const RuleArgs &A) {
 
 long long rule_blocks(const RuleArgs &A) {
   if (A.total <= 0) return 0;
-  if (lane_rule(A)) return (A.total + 255) / 256;
+  if (lane_rule(A)) return (A.total + 63) / 64;
   return std::min<long long>((A.total + 3) / 4, kWaveRuleBlocks);
 }
 
@@ -964,8 +1015,8 @@ hipError_t launch_select16(const CRegions &R, long long m, long long K, const CS
                            hipStream_t s, const CRows *open) {
   // blocks see fewer than 2^16 keys each (the LDS counters are 16-bit)
   const long long per = 32768;
-  const int hgrid = (int)std::max<long long>(std::min<long long>(256, (m + kTopThreads - 1) /
-                                                                          kTopThreads),
+  const int hgrid = (int)std::max<long long>(std::min<long long>(64, (m + kTopThreads - 1) /
+                                                                         kTopThreads),
                                              (m + per - 1) / per);
   const CRows none{};
   hipLaunchKernelGGL(topk_hist_kernel, dim3(hgrid), dim3(kTopThreads), (kTopBins / 2 + 256) * 4,
