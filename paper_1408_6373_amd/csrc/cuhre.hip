@@ -38,6 +38,7 @@ namespace {
 
 constexpr int kLaneRuleMaxDim = 8;          // lane-per-region rule up to this d
 constexpr long long kLaneRuleMinRegions = 512;  // and from this many regions on
+constexpr long long kOneLaneRuleMinRegions = 49152;  // one lane per region from here
 constexpr long long kWaveRuleBlocks = 2048;       // most blocks of a wave-per-region launch
 constexpr int kScanItems = 4;
 constexpr int kScanBlock = 256;
@@ -259,6 +260,111 @@ __device__ __forceinline__ double lane_point(const double (&c)[D], const double 
   return Genz<double, FAM>::finish(acc, D);
 }
 
+// All the rule points of one region in one lane, in point order (the
+// arithmetic of rule_region's points); returns (I7, err).
+template <int FAM, int D>
+__device__ double2 rule_region_lane(const RuleArgs &A, const CSeg &S, long long r) {
+  const long long cap = S.regs.cap;
+  double c[D], h[D];
+  if (!S.children) {
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      c[j] = S.regs.c[j * cap + r];
+      h[j] = S.regs.h[j * cap + r];
+    }
+  } else {  // a child: formed from its parent, as child_coord does per axis
+    const long long k = r - S.first;
+    const long long p = S.parent ? S.parent[k >> 1] : S.pbase + (k >> 1);
+    const int ax = S.regs.axis[p];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      c[j] = S.regs.c[j * cap + p];
+      h[j] = S.regs.h[j * cap + p];
+      if (j == ax) {
+        h[j] = h[j] / 2.0;
+        c[j] = (k & 1) ? c[j] + h[j] : c[j] - h[j];
+      }
+      S.regs.c[j * cap + r] = c[j];
+      S.regs.h[j * cap + r] = h[j];
+    }
+    if (S.retire && !(k & 1)) S.regs.err[p] = -1.0;
+  }
+  const double *p0 = S.par;
+  const double *p1 = S.par + kParamRow;
+  const double phase0 = p1[0];
+  double Sk[5];
+  // class 0: the centre
+  const double f0 = lane_point<FAM, D>(c, h, p0, p1, phase0, -1, false, -1, false, 0.0);
+  Sk[0] = f0;
+  // classes 1 and 2: +-lambda on one axis; the fourth differences
+  double s1 = 0.0, s2 = 0.0, Dmax = -1.0;
+  int best = 0;
+  double a2[D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    const double fp = lane_point<FAM, D>(c, h, p0, p1, phase0, i, false, -1, false, A.l2);
+    const double fm = lane_point<FAM, D>(c, h, p0, p1, phase0, i, true, -1, false, A.l2);
+    s1 += fp;
+    s1 += fm;
+    a2[i] = fp + fm - 2.0 * f0;
+  }
+  const double ratio = (A.l2 * A.l2) / (A.l3 * A.l3);
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    const double fp = lane_point<FAM, D>(c, h, p0, p1, phase0, i, false, -1, false, A.l3);
+    const double fm = lane_point<FAM, D>(c, h, p0, p1, phase0, i, true, -1, false, A.l3);
+    s2 += fp;
+    s2 += fm;
+    const double a3 = fp + fm - 2.0 * f0;
+    const double Dj = fabs(a2[i] - ratio * a3);
+    if (Dj > Dmax) {  // strictly greater: the lowest axis wins ties
+      Dmax = Dj;
+      best = i;
+    }
+  }
+  Sk[1] = s1;
+  Sk[2] = s2;
+  // class 3: +-lambda4 on two axes i < jj
+  double s3 = 0.0;
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int jj = i + 1; jj < D; ++jj)
+#pragma unroll
+      for (int sg = 0; sg < 4; ++sg)
+        s3 += lane_point<FAM, D>(c, h, p0, p1, phase0, i, sg & 1, jj, (sg >> 1) & 1, A.l4);
+  Sk[3] = s3;
+  // class 4: every corner at +-lambda5
+  double s4 = 0.0;
+  for (unsigned sg = 0; sg < (1u << D); ++sg) {
+    double acc = Genz<double, FAM>::init(phase0);
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      const double t = A.l5 * h[j];
+      const double x = ((sg >> j) & 1u) ? c[j] - t : c[j] + t;
+      acc = Genz<double, FAM>::step(acc, x, p0[j], p1[j]);
+    }
+    s4 += Genz<double, FAM>::finish(acc, D);
+  }
+  Sk[4] = s4;
+  double vol = 1.0;
+#pragma unroll
+  for (int j = 0; j < D; ++j) vol *= h[j];
+  const double *w7 = A.w7 + D * 5, *w5 = A.w5 + D * 5;
+  double r7 = 0.0, r5 = 0.0;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    r7 += w7[k] * Sk[k];
+    r5 += w5[k] * Sk[k];
+  }
+  const double I7 = vol * r7, I5 = vol * r5;
+  S.regs.I7[r] = I7;
+  S.regs.I5[r] = I5;
+  S.regs.err[r] = fabs(I7 - I5);
+  S.regs.axis[r] = best;
+  return make_double2(I7, fabs(I7 - I5));
+}
+
 // The rule points of one region split over the four wavefronts of a block
 // (lane l of every wavefront holds region l of the block's 64): wavefront 0
 // takes the centre, classes 1 and 2 and the fourth differences; classes 3
@@ -465,6 +571,17 @@ __device__ __forceinline__ void put_row(const CRows &R, double a, double b) {
 }
 
 }  // namespace
+
+// One integral (A.one), dimension D, one lane per region: for launches large
+// enough to fill the device with a wavefront per 64 regions.
+template <int FAM, int D>
+__global__ void __launch_bounds__(256) gm_rule_lane1_kernel(RuleArgs A) {
+  if (stopped(A.done) || !open_step(A.rows, A.done)) return;
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  double2 v = make_double2(0.0, 0.0);
+  if (g < A.total) v = rule_region_lane<FAM, D>(A, A.one, A.one.first + g);
+  put_row(A.rows, v.x, v.y);
+}
 
 // One integral (A.one), dimension D: 64 regions per block, one lane of each
 // of the block's four wavefronts per region (rule_region_quad).
@@ -963,16 +1080,24 @@ long long step_rows(long long cap) {
   return scratch_blocks(cap) + std::max<long long>((cap + 63) / 64, kWaveRuleBlocks);
 }
 
+template <int FAM, int D>
+static void launch_rule_lane_dd(const RuleArgs &A, unsigned grid, bool one_lane, hipStream_t s) {
+  if (one_lane)
+    hipLaunchKernelGGL((gm_rule_lane1_kernel<FAM, D>), dim3(grid), dim3(256), 0, s, A);
+  else
+    hipLaunchKernelGGL((gm_rule_lane_kernel<FAM, D>), dim3(grid), dim3(256), 0, s, A);
+}
+
 template <int FAM>
-static void launch_rule_lane_d(const RuleArgs &A, unsigned grid, hipStream_t s) {
+static void launch_rule_lane_d(const RuleArgs &A, unsigned grid, bool one_lane, hipStream_t s) {
   switch (A.one.ndim) {
-    case 2: hipLaunchKernelGGL((gm_rule_lane_kernel<FAM, 2>), dim3(grid), dim3(256), 0, s, A); break;
-    case 3: hipLaunchKernelGGL((gm_rule_lane_kernel<FAM, 3>), dim3(grid), dim3(256), 0, s, A); break;
-    case 4: hipLaunchKernelGGL((gm_rule_lane_kernel<FAM, 4>), dim3(grid), dim3(256), 0, s, A); break;
-    case 5: hipLaunchKernelGGL((gm_rule_lane_kernel<FAM, 5>), dim3(grid), dim3(256), 0, s, A); break;
-    case 6: hipLaunchKernelGGL((gm_rule_lane_kernel<FAM, 6>), dim3(grid), dim3(256), 0, s, A); break;
-    case 7: hipLaunchKernelGGL((gm_rule_lane_kernel<FAM, 7>), dim3(grid), dim3(256), 0, s, A); break;
-    default: hipLaunchKernelGGL((gm_rule_lane_kernel<FAM, 8>), dim3(grid), dim3(256), 0, s, A); break;
+    case 2: launch_rule_lane_dd<FAM, 2>(A, grid, one_lane, s); break;
+    case 3: launch_rule_lane_dd<FAM, 3>(A, grid, one_lane, s); break;
+    case 4: launch_rule_lane_dd<FAM, 4>(A, grid, one_lane, s); break;
+    case 5: launch_rule_lane_dd<FAM, 5>(A, grid, one_lane, s); break;
+    case 6: launch_rule_lane_dd<FAM, 6>(A, grid, one_lane, s); break;
+    case 7: launch_rule_lane_dd<FAM, 7>(A, grid, one_lane, s); break;
+    default: launch_rule_lane_dd<FAM, 8>(A, grid, one_lane, s); break;
   }
 }
 
@@ -988,9 +1113,13 @@ static bool lane_rule(const RuleArgs &A) {
   return A.nseg == 1 && A.one.ndim <= kLaneRuleMaxDim && A.total >= kLaneRuleMinRegions;
 }
 
+// From this many regions on, one lane per region fills the device (a wavefront
+// per SIMD and more) without the four-way split's combine.
+static bool one_lane_rule(const RuleArgs &A) { return A.total >= kOneLaneRuleMinRegions; }
+
 long long rule_blocks(const RuleArgs &A) {
   if (A.total <= 0) return 0;
-  if (lane_rule(A)) return (A.total + 63) / 64;
+  if (lane_rule(A)) return one_lane_rule(A) ? (A.total + 255) / 256 : (A.total + 63) / 64;
   return std::min<long long>((A.total + 3) / 4, kWaveRuleBlocks);
 }
 
@@ -998,12 +1127,13 @@ hipError_t launch_rule(const RuleArgs &A, hipStream_t s) {
   const long long grid = rule_blocks(A);
   if (grid <= 0) return hipSuccess;
   if (lane_rule(A)) {
+    const bool one = one_lane_rule(A);
     switch (A.one.family) {
-      case GAUSSIAN: launch_rule_lane_d<GAUSSIAN>(A, (unsigned)grid, s); break;
-      case OSCILLATORY: launch_rule_lane_d<OSCILLATORY>(A, (unsigned)grid, s); break;
-      case PRODUCT_PEAK: launch_rule_lane_d<PRODUCT_PEAK>(A, (unsigned)grid, s); break;
-      case CORNER_PEAK: launch_rule_lane_d<CORNER_PEAK>(A, (unsigned)grid, s); break;
-      default: launch_rule_lane_d<C0>(A, (unsigned)grid, s); break;
+      case GAUSSIAN: launch_rule_lane_d<GAUSSIAN>(A, (unsigned)grid, one, s); break;
+      case OSCILLATORY: launch_rule_lane_d<OSCILLATORY>(A, (unsigned)grid, one, s); break;
+      case PRODUCT_PEAK: launch_rule_lane_d<PRODUCT_PEAK>(A, (unsigned)grid, one, s); break;
+      case CORNER_PEAK: launch_rule_lane_d<CORNER_PEAK>(A, (unsigned)grid, one, s); break;
+      default: launch_rule_lane_d<C0>(A, (unsigned)grid, one, s); break;
     }
     return hipGetLastError();
   }
