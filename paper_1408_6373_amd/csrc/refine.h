@@ -58,9 +58,11 @@ __device__ inline double gamma_p(double a, double x) {
 
 // a7, the grid: one dimension's refinement by one wavefront.  The histogram
 // row h is smoothed, damped and prefix-summed (lanes own contiguous runs of
-// bins, wave-wide scans), and every new edge is placed by a binary search of
-// the prefix sums.  h, dd and Eo are LDS rows (h is overwritten with the
-// prefix sums); En receives the N + 1 new edges.
+// bins, wave-wide scans), and every new edge is placed in the old bin whose
+// prefix-sum interval holds its share, by the lane that owns that bin (the
+// bin a binary search of the prefix sums would find).  h, dd and Eo are LDS
+// rows (h is overwritten with the prefix sums); En receives the N + 1 new
+// edges.
 __device__ __forceinline__ void rebin_dimension(double *h, double *dd, const double *Eo,
                                                 double *En, int N, int lane) {
   const int per = (N + 63) >> 6;  // contiguous bins per lane
@@ -110,23 +112,28 @@ __device__ __forceinline__ void rebin_dimension(double *h, double *dd, const dou
   }
   wave_sync_lds();
   const double share = h[N - 1] / N;
-  // new edge i: smallest old bin k with C_k >= i * share
-  for (int i = lane; i <= N; i += 64) {
-    if (i == 0 || i == N) {
-      En[i] = i == 0 ? 0.0 : 1.0;
-      continue;
+  // new edge i (0 < i < N) lies in the smallest old bin k with C_k >= i *
+  // share (the last bin if there is none): each lane places the edges of its
+  // own bins, those with C_{k-1} < i * share <= C_k, a contiguous run of i
+  if (lane == 0) {
+    En[0] = 0.0;
+    En[N] = 1.0;
+  }
+  for (int k = k0; k < k1; ++k) {
+    const bool last = k == N - 1;
+    const double below = k > 0 ? h[k - 1] : 0.0;  // C_{k-1}; targets are > 0
+    const double above = h[k];
+    if (!last && !(above > below)) continue;  // an empty bin holds no edge
+    // the first i with i * share > C_{k-1}: an estimate, then corrected
+    int i = k > 0 ? (int)fmin(below / share, (double)N) : 1;
+    if (i < 1) i = 1;
+    while (i > 1 && (double)(i - 1) * share > below) --i;
+    while (i < N && !((double)i * share > below)) ++i;
+    for (; i < N; ++i) {
+      const double target = i * share;
+      if (!last && !(target <= above)) break;
+      En[i] = Eo[k] + (target - below) / dd[k] * (Eo[k + 1] - Eo[k]);
     }
-    const double target = i * share;
-    int lo = 0, hi = N - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (h[mid] < target)
-        lo = mid + 1;
-      else
-        hi = mid;
-    }
-    const double before = lo > 0 ? h[lo - 1] : 0.0;
-    En[i] = Eo[lo] + (target - before) / dd[lo] * (Eo[lo + 1] - Eo[lo]);
   }
 }
 

@@ -214,8 +214,8 @@ __device__ __forceinline__ void finish_state(VState &st, bool bad, bool conv, bo
 // the integral is done (no intermediate value is ever observed).  Then, if
 // the grid is to be refined, each wavefront takes whole dimensions: the
 // histogram row is smoothed, damped and prefix-summed with wave-wide scans
-// (lanes own contiguous runs of bins), and every new edge is placed by a
-// binary search of the prefix sums.
+// (lanes own contiguous runs of bins), and every new edge is placed in the
+// old bin whose prefix-sum interval holds its share.
 constexpr int kRefineThreads = 1024;  // the refine kernel's block (launch_refine)
 
 __global__ void __launch_bounds__(kRefineThreads) vegas_refine_kernel(VegasArgs A) {
