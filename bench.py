@@ -268,7 +268,7 @@ def _cuhre_roofline(st):
     if not c or st.rule_ms <= 0:
         return None
     rate = st.rule_evals / (st.rule_ms * 1e-3)
-    out = {"bound": "alu", "kernel": "gm_rule_lane_kernel<CORNER_PEAK,6> + gm_rule_kernel",
+    out = {"bound": "alu", "kernel": "gm_rule_lane1_kernel<CORNER_PEAK,6> + gm_rule_lane_kernel<CORNER_PEAK,6> + gm_rule_kernel",
            "unit": "T VALU-slots/s", "peak": PEAK_VALU / 1e12, "evals_per_s": rate,
            "counters": "profiles/valu_counters.json"}
     out.update(_valu_fields(c, float(c["evals"]), c["evals"] / rate, PEAK_FP64_FLOPS))
@@ -882,8 +882,13 @@ def main():
         return
     if args.counter_probe:
         # the tuned headline settings, read from the cache that a plain run of
-        # the benchmark (or --tune-only) wrote before
-        _tune_cache()
+        # the benchmark (or --tune-only) wrote before; tuning here would add
+        # its own DoSample dispatches to the counted ones
+        path = _tune_cache()
+        if not (os.path.exists(path) and ":batch:" in open(path).read()):
+            print("bench.py --counter-probe: no tuned settings in %s; run bench.py --tune-only "
+                  "first, outside the profiler" % path, file=sys.stderr)
+            sys.exit(2)
         ctx = cc.Context(device=0)
         ctx.config("autotune", 1)
         ev32 = _step(cc, ctx, params, cc.FP32_EVAL)
