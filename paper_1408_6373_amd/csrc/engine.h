@@ -36,6 +36,10 @@ struct VJob {
   int hist_cap;           // capacity of the per-iteration history
   int pad;
   VState *state;
+  // the state as the iteration's fold found it (null: no refine follows):
+  // the refine kernel's workgroups read it, so that none of them reads a
+  // state that another one has already advanced
+  VState *snap;
   double *grid;           // ndim * (nbins + 1) edges, refined in place
   double *tsums;          // [ntiles][2]
   double *thist;          // [ntiles][ndim * nbins]

@@ -224,6 +224,7 @@ int Server::activate(Req &r) {
   J.tile_pts = P;
   J.hist_cap = cap;
   J.state = states_.p + r.slot;
+  J.snap = states_.p + states_.n / 2 + r.slot;
   J.grid = r.grid.p;
   J.tsums = r.tsums.p;
   J.thist = r.thist.p;
@@ -280,7 +281,8 @@ int Server::tick() {
   int rc;
   if (!tables_ready_) {
     const int slots = ctx_->serve_slots;
-    if ((rc = states_.alloc(ctx_, slots)) || (rc = jobs_.alloc(ctx_, slots)) ||
+    // (the states, then their snapshots for the refine kernel)
+    if ((rc = states_.alloc(ctx_, 2 * slots)) || (rc = jobs_.alloc(ctx_, slots)) ||
         (rc = w7_.alloc(ctx_, 17 * 5)) || (rc = w5_.alloc(ctx_, 17 * 5)))
       return rc;
     for (int q = slots - 1; q >= 0; --q) free_slots_.push_back(q);
@@ -347,7 +349,9 @@ int Server::tick() {
                              hipMemcpyHostToDevice, s));
     FoldArgs F{jobs_.p, fold_end_.p, (int)table.size(), ftot, fold_end_.p + table.size(), ftot2};
     CCUBA_HIP(launch_fold(F, false, s));
-    CCUBA_HIP(launch_refine(A, (int)table.size(), refb, s));
+    int dmax = 1;
+    for (const VJob &J : table) dmax = std::max(dmax, J.ndim);
+    CCUBA_HIP(launch_refine(A, (int)table.size(), dmax, s));
   }
   // Cuhre: one rule launch over the children of every stepping request
   if (!segs.empty()) {
@@ -364,7 +368,7 @@ int Server::tick() {
   // retire finished requests
   std::vector<VState> st;
   if (!table.empty()) {
-    st.resize(states_.n);
+    st.resize(states_.n / 2);  // (the states; their snapshots follow)
     CCUBA_HIP(hipMemcpy(st.data(), states_.p, st.size() * sizeof(VState), hipMemcpyDeviceToHost));
   }
   std::vector<std::unique_ptr<Req>> keep;

@@ -98,7 +98,9 @@ void dosample_fns_f64hfx(std::vector<const void *> &fns);
 // First fold level (tile rows -> group rows); with level2 also the second
 // (group rows -> hsum), which only the raw DoSample entry point needs.
 hipError_t launch_fold(const FoldArgs &F, bool level2, hipStream_t s);
-hipError_t launch_refine(const VegasArgs &A, int njobs, size_t lds, hipStream_t s);
+// The refine kernel over njobs integrals, one workgroup per (integral,
+// dimension); dmax: the largest dimension among them.
+hipError_t launch_refine(const VegasArgs &A, int njobs, int dmax, hipStream_t s);
 // Uniform starting grids of jobs[0, njobs) (device table).
 hipError_t launch_init_grids(const VJob *jobs, int njobs, hipStream_t s);
 // The same for one grid of ndim rows of nbins + 1 edges.

@@ -64,6 +64,10 @@ __global__ void __launch_bounds__(256) vegas_fold_kernel(FoldArgs F) {
   // round trip to memory.  (The rows are allocated whether or not the
   // integral is done.)
   const int done = *gload(&JOB_FIELD(jw, state)->done);
+  // the state as this iteration's sampling left it, for the refine launch
+  VState *snap = JOB_FIELD(jw, snap);
+  const uint32_t stw = (snap && grp == 0 && ch == 0)
+                           ? load_words<kStateWords>(JOB_FIELD(jw, state), lane) : 0u;
   const gbl<double> *src = gload(JOB_FIELD(jw, thist)) + (long long)t0 * dN + (bin < dN ? bin : 0);
   const gbl<double> *tsp = gload(JOB_FIELD(jw, tsums)) + 2ll * t0;
   double ts[kTsPer];
@@ -79,6 +83,8 @@ __global__ void __launch_bounds__(256) vegas_fold_kernel(FoldArgs F) {
     // keeps the compiler from folding each add into its load's branch, which
     // would wait for every load before issuing the next
     asm volatile("" ::: "memory");
+    if (q0 == 0 && snap && grp == 0 && ch == 0 && lane < kStateWords)
+      ((uint32_t *)snap)[lane] = stw;  // (also once the integral is done)
     if (done) return;
     // tile order; the first row starts the sum (a group has at least one
     // tile; starting from 0.0 would put the first add, and a wait, inside
@@ -208,54 +214,54 @@ __device__ __forceinline__ void finish_state(VState &st, bool bad, bool conv, bo
   }
 }
 
-// One workgroup per integral: finish the iteration (a7).  Thread 0 forms the
-// iteration's estimate and variance, the inverse-variance combination and
-// the convergence decision; chi^2 and its probability are formed only once
-// the integral is done (no intermediate value is ever observed).  Then, if
-// the grid is to be refined, each wavefront takes whole dimensions: the
-// histogram row is smoothed, damped and prefix-summed with wave-wide scans
-// (lanes own contiguous runs of bins), and every new edge is placed in the
-// old bin whose prefix-sum interval holds its share.
-constexpr int kRefineThreads = 1024;  // the refine kernel's block (launch_refine)
+// One workgroup per (integral, dimension): finish the iteration (a7).  Every
+// workgroup reads the state as the iteration's fold left it (the snapshot:
+// the live state is rewritten by this launch) and the iteration's sums, and
+// thread 0 forms the iteration's estimate and variance, the inverse-variance
+// combination and the convergence decision -- the same in every workgroup of
+// the integral; only dimension 0's writes the state and the history, with
+// chi^2 and its probability once the integral is done (no intermediate value
+// is ever observed).  Meanwhile wavefront 1 refines its dimension of the grid
+// into LDS: the histogram row is smoothed, damped
+// and prefix-summed with wave-wide scans (lanes own contiguous runs of
+// bins), and every new edge is placed in the old bin whose prefix-sum
+// interval holds its share.  The new edges are written out if the decision
+// is to refine.
+constexpr int kRefineThreads = 256;  // the refine kernel's block (launch_refine)
 
 __global__ void __launch_bounds__(kRefineThreads) vegas_refine_kernel(VegasArgs A) {
-  extern __shared__ __align__(16) double rsm[];
+  __shared__ double H[kMaxBins];      // histogram row, later prefix sums of m
+  __shared__ double D[kMaxBins];      // smoothed row, later m
+  __shared__ double G[kMaxBins + 1];  // the current edges
+  __shared__ double Gn[kMaxBins + 1];  // the refined edges
   __shared__ int s_mode;
   __shared__ double s_sums[2];
   __shared__ __align__(16) uint32_t s_stw[kStateWords];  // the state, word by word
   // (a constant block size: reading blockDim would be one more wait)
-  constexpr int bs = kRefineThreads, nwv = kRefineThreads / 64;
-  const int jb = blockIdx.x, tid = threadIdx.x;
+  constexpr int bs = kRefineThreads;
+  const int jb = blockIdx.x, dim = blockIdx.y, tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   // Every wavefront holds the job descriptor, one word per lane.
   const uint32_t jw = load_words<kJobWords>(A.jobs + jb, lane);
   const int d = JOB_FIELD(jw, ndim), N = JOB_FIELD(jw, nbins);
-  const int dN = d * N, row = N + 1, drow = d * row;
+  if (dim >= d) return;  // (a launch covers the largest d of its integrals)
+  const int dN = d * N, row = N + 1;
   const int ng = ngroups_of(JOB_FIELD(jw, ntiles));
-  double *grid = JOB_FIELD(jw, grid);
+  double *grow = JOB_FIELD(jw, grid) + (long long)dim * row;
   const double *gsums = JOB_FIELD(jw, gsums);
-  double *H = rsm;           // histogram, later prefix sums of m
-  double *D = rsm + dN;      // smoothed histogram, later m
-  double *G = rsm + 2 * dN;  // the current grid
   // One round trip to memory for all of: the state (a word per lane of the
-  // first wavefront), the first 32 groups' sums (a value per lane), the
-  // grid and the group rows.  (The grid is staged in LDS before any of it is
-  // rewritten: the new edges replace the old ones in place.)
-  const uint32_t stw = wv == 0 ? load_words<kStateWords>(JOB_FIELD(jw, state), lane) : 0u;
+  // first wavefront), the first 32 groups' sums (a value per lane), this
+  // dimension's edges and its bins' group rows.  (The edges are staged in
+  // LDS before any of them is rewritten.)
+  const uint32_t stw = wv == 0 ? load_words<kStateWords>(JOB_FIELD(jw, snap), lane) : 0u;
   const double gsv = (tid < 2 * min(ng, 32)) ? gload(gsums)[tid] : 0.0;
-  constexpr int kGridPer = (kMaxDim * (kMaxBins + 1) + kRefineThreads - 1) / kRefineThreads;
-  double g0[kGridPer];
-#pragma unroll
-  for (int q = 0; q < kGridPer; ++q) {
-    const int e = tid + q * bs;
-    g0[q] = e < drow ? gload(grid)[e] : 0.0;
-  }
+  const double e0 = tid < row ? gload(grow)[tid] : 0.0;
+  const double e1 = (tid == 0 && row > bs) ? gload(grow)[bs] : 0.0;
   // the last fold level: the group rows in group order (the order of the
   // separate second-level fold, so both give the same sums)
   constexpr int kBatch = 32;  // loads in flight per thread before the adds
-  const gbl<double> *ghist = gload(JOB_FIELD(jw, ghist));
-  for (int e = tid; e < dN; e += bs) {
-    const gbl<double> *src = ghist + e;
+  if (tid < N) {
+    const gbl<double> *src = gload(JOB_FIELD(jw, ghist)) + (long long)dim * N + tid;
     double h = 0.0;
     for (int q0 = 0; q0 < ng; q0 += kBatch) {
       double v[kBatch];
@@ -268,7 +274,7 @@ __global__ void __launch_bounds__(kRefineThreads) vegas_refine_kernel(VegasArgs 
       for (int q = 0; q < kBatch; ++q)
         if ((q0 > 0 || q > 0) && q0 + q < ng) h += v[q];
     }
-    H[e] = h;
+    H[tid] = h;
   }
   if (wv == 0) {
     if (lane < kStateWords) s_stw[lane] = stw;
@@ -299,11 +305,10 @@ __global__ void __launch_bounds__(kRefineThreads) vegas_refine_kernel(VegasArgs 
   // (state words read as written, uint32_t; the whole state by memcpy below)
   if (s_stw[offsetof(VState, done) / 4] != 0u) return;  // the same for the whole block
   const int t = (int)s_stw[offsetof(VState, T) / 4];
-#pragma unroll
-  for (int q = 0; q < kGridPer; ++q) {
-    const int e = tid + q * bs;
-    if (e < drow) G[e] = g0[q];
-  }
+  if (tid < row) G[tid] = e0;
+  if (tid == 0 && row > bs) G[bs] = e1;
+  __syncthreads();  // G complete
+  if (wv == 1) rebin_dimension(H, D, G, Gn, N, lane);
   if (tid == 0) {
     VState st;
     __builtin_memcpy(&st, s_stw, sizeof(VState));
@@ -313,9 +318,6 @@ __global__ void __launch_bounds__(kRefineThreads) vegas_refine_kernel(VegasArgs 
     const double c = st.shift;  // the sums' shift (settle_component moves it on)
     double I, var;
     settle_component(st, S1, S2, n, I, var);
-    double *hI = JOB_FIELD(jw, iter_I), *hV = JOB_FIELD(jw, iter_var);
-    hI[t] = I;
-    hV[t] = var;
     const int T = st.T;
     const double tol = fmax(JOB_FIELD(jw, epsabs), JOB_FIELD(jw, epsrel) * fabs(st.integral));
     const bool conv = st.neval >= JOB_FIELD(jw, mineval) && st.error <= tol;
@@ -323,22 +325,20 @@ __global__ void __launch_bounds__(kRefineThreads) vegas_refine_kernel(VegasArgs 
     const bool budget = st.neval + nnext > JOB_FIELD(jw, maxeval) ||
                         T >= JOB_FIELD(jw, hist_cap) || nnext >= (1ll << 32);
     const bool bad = !isfinite(S1) || !isfinite(S2);
-    finish_state(st, bad, conv, budget, hI, hV);
-    // the mean v^2 of the iteration, (S2 + 2 c S1)/n + c^2
-    st.hcap = (float)(1024.0 * (fma(2.0 * c, S1, S2) / (double)n + c * c));
-    *JOB_FIELD(jw, state) = st;
+    if (dim == 0) {
+      double *hI = JOB_FIELD(jw, iter_I), *hV = JOB_FIELD(jw, iter_var);
+      hI[t] = I;
+      hV[t] = var;
+      finish_state(st, bad, conv, budget, hI, hV);
+      // the mean v^2 of the iteration, (S2 + 2 c S1)/n + c^2
+      st.hcap = (float)(1024.0 * (fma(2.0 * c, S1, S2) / (double)n + c * c));
+      *JOB_FIELD(jw, state) = st;
+    }
     s_mode = conv || bad ? 0 : ((JOB_FIELD(jw, flags) & FLAG_FREEZE_GRID) ? 2 : 1);
   }
   __syncthreads();
-  const int mode = s_mode;
-  if (mode == 0) return;
-  double *Enew = grid;  // in place: every old edge is read from G
-  if (mode == 2) {
-    for (int e = tid; e < drow; e += bs) Enew[e] = G[e];
-    return;
-  }
-  for (int j = wv; j < d; j += nwv)
-    rebin_dimension(H + j * N, D + j * N, G + j * row, Enew + j * row, N, lane);
+  if (s_mode != 1) return;  // converged, or the grid is frozen (kept as it is)
+  for (int e = tid; e < row; e += bs) grow[e] = Gn[e];
 }
 
 // Uniform starting grids, E_j[k] = k/N, one workgroup per job (the same
@@ -589,9 +589,9 @@ hipError_t launch_fold(const FoldArgs &F, bool level2, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_refine(const VegasArgs &A, int njobs, size_t lds, hipStream_t s) {
-  // one wavefront per dimension (up to 16)
-  hipLaunchKernelGGL(vegas_refine_kernel, dim3(njobs), dim3(kRefineThreads), lds, s, A);
+hipError_t launch_refine(const VegasArgs &A, int njobs, int dmax, hipStream_t s) {
+  // one workgroup per (integral, dimension)
+  hipLaunchKernelGGL(vegas_refine_kernel, dim3(njobs, dmax), dim3(kRefineThreads), 0, s, A);
   return hipGetLastError();
 }
 
@@ -647,8 +647,7 @@ hipError_t set_kernel_limits() {
   // histogram) the LDS gfx950 has; a runtime that refuses keeps its default
   // limit and such launches report an error instead of running
   const int big = 160 * 1024;
-  std::vector<const void *> fns = {(const void *)vegas_refine_kernel,
-                                   (const void *)vegas_batched_finish_kernel,
+  std::vector<const void *> fns = {(const void *)vegas_batched_finish_kernel,
                                    (const void *)vegas_points_kernel<double>,
                                    (const void *)vegas_points_kernel<float>};
   dosample_fns_f64(fns);

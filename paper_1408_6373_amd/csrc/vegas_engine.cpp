@@ -205,6 +205,8 @@ int VegasEngine::setup(const std::vector<VegasSpec> &specs, bool single, hipStre
   long long total[2] = {0, 0};
   max_iters_ = 0;
   evals_iter_ = 0;
+  dmax_ = 1;
+  for (int j = 0; j < n; ++j) dmax_ = std::max(dmax_, specs[j].ndim);
   for (int j = 0; j < n; ++j) {
     vegas_budget(specs[j], &iters[j], &nmax[j]);
     max_iters_ = std::max(max_iters_, iters[j]);
@@ -277,7 +279,8 @@ int VegasEngine::setup(const std::vector<VegasSpec> &specs, bool single, hipStre
   // buffers of an earlier setup are kept when large enough (an engine that
   // is set up again for the same shape keeps its device addresses)
   int rc;
-  if ((rc = jobs_.reserve(ctx_, n)) || (rc = state_.reserve(ctx_, n)) ||
+  // (the states, then their snapshots for the refine kernel)
+  if ((rc = jobs_.reserve(ctx_, n)) || (rc = state_.reserve(ctx_, 2 * (size_t)n)) ||
       (rc = tile_job_.reserve(ctx_, ntiles_)) || (rc = grids_.reserve(ctx_, goff)) ||
       (rc = p64_.reserve(ctx_, (size_t)n * 2 * kParamRow)) ||
       (rc = p32_.reserve(ctx_, (size_t)n * 2 * kParamRow)) ||
@@ -292,6 +295,7 @@ int VegasEngine::setup(const std::vector<VegasSpec> &specs, bool single, hipStre
   for (int j = 0; j < n; ++j) {
     VJob &J = hjobs_[j];
     J.state = state_.p + j;
+    J.snap = state_.p + n + j;
     J.grid = grids_.p + off[j].grid;
     J.tsums = tile_sums_.p + 2ll * off[j].tile0;
     J.thist = tile_hist_.p + off[j].thist;
@@ -379,14 +383,14 @@ int VegasEngine::launch_iteration(hipStream_t s) {
     int rc = dosample_only(s, false, ev[1]);
     if (rc) return rc;
     CCUBA_HIP(hipEventRecord(ev[2], s));
-    CCUBA_HIP(launch_refine(args_, njobs(), lds_refine_, s));
+    CCUBA_HIP(launch_refine(args_, njobs(), dmax_, s));
     CCUBA_HIP(hipEventRecord(ev[3], s));
     pending_.push_back({ev[0], ev[1], ev[2], ev[3], iter_launched_++});
     return CCUBA_OK;
   }
   int rc = dosample_only(s);
   if (rc) return rc;
-  CCUBA_HIP(launch_refine(args_, njobs(), lds_refine_, s));
+  CCUBA_HIP(launch_refine(args_, njobs(), dmax_, s));
   ++iter_launched_;
   return CCUBA_OK;
 }
@@ -598,7 +602,10 @@ int VegasEngine::refine_only(const double *hist, const double *grid_in, double *
   CCUBA_HIP(hipStreamSynchronize(s));
   rc = set_iteration(0, 0, s);
   if (rc) return rc;
-  CCUBA_HIP(launch_refine(args_, 1, lds_refine_, s));
+  // (the refine kernel reads the state through the snapshot the fold takes)
+  CCUBA_HIP(hipMemcpyAsync(hjobs_[0].snap, hjobs_[0].state, sizeof(VState),
+                           hipMemcpyDeviceToDevice, s));
+  CCUBA_HIP(launch_refine(args_, 1, dmax_, s));
   return read_grid(0, grid_out, s);
 }
 

@@ -137,6 +137,7 @@ class VegasEngine {
   int hist64_[2] = {0, 0};  // per precision: the FP64 LDS histogram asked for
   hipFunction_t user_fn_ = nullptr;
   int max_iters_ = 0;
+  int dmax_ = 1;  // the largest dimension among the jobs (refine launch)
   long long evals_iter_ = 0;
   // instantiated graphs of k consecutive iterations
   struct ChunkGraph {
