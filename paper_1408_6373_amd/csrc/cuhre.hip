@@ -932,10 +932,12 @@ __global__ void __launch_bounds__(kTopThreads) topk_gather_kernel(const double *
 
 // One workgroup: among the gathered regions, the one of rank krem[0] (from
 // 1) in the order key descending, position ascending: radix passes of 12
-// bits over the key's low 48 bits (descending); then, if the regions with
-// that key are not all taken (a tie across the threshold), passes of 8 bits
-// over the positions (ascending), else the largest of their positions.  Its
-// key to prefix[0], its position to krem[0].
+// bits over the key's low 48 bits (descending), until at most 1024
+// candidates share the bits fixed so far, which then rank themselves
+// directly; if all 48 bits get fixed first: when the regions with that key
+// are not all taken (a tie across the threshold), passes of 8 bits over the
+// positions (ascending), else the largest of their positions.  Its key to
+// prefix[0], its position to krem[0].
 __global__ void __launch_bounds__(kTopThreads) topk_exact_kernel(const unsigned long long *ckey,
                                                                  const long long *cpos,
                                                                  const unsigned long long *cnt,
@@ -955,6 +957,7 @@ __global__ void __launch_bounds__(kTopThreads) topk_exact_kernel(const unsigned 
   // padding ~0 has top digit 0xFFFF, which no live key has: the sign bit of
   // a live error is clear)
   constexpr int kExactReg = 16;
+  constexpr long long kDirect = kTopThreads;  // candidates ranked directly
   const bool inreg = mc <= (long long)kExactReg * kTopThreads;
   unsigned long long kr[kExactReg];
 #pragma unroll
@@ -982,9 +985,54 @@ __global__ void __launch_bounds__(kTopThreads) topk_exact_kernel(const unsigned 
     pick_digit<4>(c4, need, 4096, &dig, &need, &group);
     pre |= (unsigned long long)dig << shift;
     mask |= 4095ull << shift;
+    if (group <= kDirect) break;  // (group is the same in every thread)
   }
   unsigned long long tpos;
-  if (need == group) {  // every region with the threshold key is taken
+  if (group <= kDirect) {
+    // few candidates left with the bits fixed so far: each takes its own
+    // rank among them directly, (key desc, position asc), and the one of
+    // rank need - 1 is the threshold
+    __shared__ unsigned long long gk[kDirect];
+    __shared__ long long gp[kDirect];
+    __shared__ int gcnt;
+    __shared__ unsigned long long s_key;
+    __shared__ long long s_pos;
+    if (t == 0) gcnt = 0;
+    __syncthreads();
+    if (inreg) {
+#pragma unroll
+      for (int q = 0; q < kExactReg; ++q)
+        if ((kr[q] & mask) == pre) {
+          const int o = atomicAdd(&gcnt, 1);
+          gk[o] = kr[q];
+          gp[o] = cpos[t + (long long)q * kTopThreads];
+        }
+    } else {
+      for (long long i = t; i < mc; i += kTopThreads) {
+        const unsigned long long k = ckey[i];
+        if ((k & mask) == pre) {
+          const int o = atomicAdd(&gcnt, 1);
+          gk[o] = k;
+          gp[o] = cpos[i];
+        }
+      }
+    }
+    __syncthreads();
+    const int c = gcnt;
+    if (t < c) {
+      const unsigned long long mk = gk[t];
+      const long long mp = gp[t];
+      long long r = 0;
+      for (int i = 0; i < c; ++i) r += gk[i] > mk || (gk[i] == mk && gp[i] < mp);
+      if (r == need - 1) {
+        s_key = mk;
+        s_pos = mp;
+      }
+    }
+    __syncthreads();
+    pre = s_key;
+    tpos = (unsigned long long)s_pos;
+  } else if (need == group) {  // every region with the threshold key is taken
     if (t == 0) s_max = 0ull;
     __syncthreads();
     unsigned long long mx = 0ull;
