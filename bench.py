@@ -51,7 +51,7 @@ class Stats(C.Structure):
                 ("refine_launches", C.c_longlong), ("refine_ms", C.c_double),
                 ("evals", C.c_longlong), ("rule_launches", C.c_longlong),
                 ("rule_ms", C.c_double), ("rule_evals", C.c_longlong),
-                ("fold_ms", C.c_double)]
+                ("fold_ms", C.c_double), ("dosample_busy_ms", C.c_double)]
 
 
 def _stats(cc, ctx, reset=True):
@@ -101,7 +101,7 @@ def _ensure_tuned():
 
 def _tuned_settings(ctx, prec):
     return {k: ctx.config_get(k, prec) for k in ("block", "blocks_per_cu", "ilp", "min_tile",
-                                                 "hist64")}
+                                                 "hist64", "batch_streams")}
 
 
 def _step(cc, ctx, params, prec):
@@ -136,7 +136,11 @@ def _counters():
     ks = rec.get("kernels", {})
     out = {}
     if rec.get("kernel_source_sha256") == kernel_source_hash(rec.get("kernel_sources", [])):
-        out.update({k: v for k, v in ks.items() if k.startswith("dosample")})
+        for k, v in ks.items():
+            if k.startswith("dosample"):
+                # the points the probe's step sampled in this kernel
+                pts = rec.get("probe", {}).get(k + "_points")
+                out[k] = dict(v, points=pts)
     if rec.get("cuhre_source_sha256") == kernel_source_hash(rec.get("cuhre_sources", [])):
         if "cuhre_rule" in ks:
             out["cuhre_rule"] = dict(ks["cuhre_rule"], evals=rec["probe"]["cuhre_evals"])
@@ -185,14 +189,18 @@ def _valu_fields(c, units, seconds, flops_peak):
 def _roofline(cc, ctx, params, prec):
     """Event-timed DoSample sampling launches of one profiled headline step.
 
-    The library records HIP events on its own stream around the sampling
-    kernel, the fold of its partial sums and the refine kernel of every
-    iteration; the sampling kernel is the dominant one and the roofline is
-    its VALU issue rate: the VALU quad-cycles per point that rocprofv3's SQ
+    The library records HIP events on the stream each kernel runs on around
+    the sampling kernel, the fold of its partial sums and the refine kernel
+    of every iteration.  The step runs as the timed steps do: its two
+    integrals as two halves on two streams, whose sampling launches overlap
+    in time, so the library also reports the time during which at least one
+    sampling launch ran (the union of their intervals, from the same
+    events).  The sampling kernel is the dominant one and the roofline is its
+    VALU issue rate: the VALU quad-cycles per point that rocprofv3's SQ
     counters measured on this kernel (SQ_ACTIVE_INST_VALU, committed under
-    profiles/) x points per launch / the average launch duration, against
-    one wave64 instruction per SIMD per quad-cycle.  The slot model counted
-    from the assembly (isa_slots.py) is reported beside it."""
+    profiles/) x the step's points / that busy time, against one wave64
+    instruction per SIMD per quad-cycle.  The slot model counted from the
+    assembly (isa_slots.py) is reported beside it."""
     from paper_1408_6373_amd import isa_slots
     table = isa_slots.load() or {}
     _stats(cc, ctx)
@@ -201,6 +209,7 @@ def _roofline(cc, ctx, params, prec):
     st = _stats(cc, ctx)
     ctx.config("profile", 0)
     ms, fold_ms, refine_ms = st.dosample_ms, st.fold_ms, st.refine_ms
+    busy = st.dosample_busy_ms
     evals, launches = st.evals, st.dosample_launches
     n = max(launches, 1)
     fp32 = prec == cc.FP32_EVAL
@@ -219,15 +228,15 @@ def _roofline(cc, ctx, params, prec):
            "peak": PEAK_VALU / 1e12,
            "avg_launch_ms": ms / n, "launches": launches,
            "points_per_launch": evals / n,
-           "kernel_evals_per_s": evals / (ms * 1e-3),
+           "busy_ms": busy, "launch_overlap": ms / busy if busy > 0 else None,
+           "kernel_evals_per_s": evals / (busy * 1e-3),
            "fold_ms_per_launch": fold_ms / n,
            "refine_ms_per_launch": refine_ms / n,
-           "sample_fold_refine_evals_per_s": evals / ((ms + fold_ms + refine_ms) * 1e-3),
            "achieved": None, "frac": None,
            "slot_model": None if model is None else {
                "slots_per_point": model / evals,
-               "achieved": model / (ms * 1e-3) / 1e12,
-               "frac": model / (ms * 1e-3) / PEAK_VALU}}
+               "achieved": model / (busy * 1e-3) / 1e12,
+               "frac": model / (busy * 1e-3) / PEAK_VALU}}
     c = _counters().get("dosample_fp32" if fp32 else "dosample_fp64")
     # counters taken on this precision and histogram type; when they were
     # taken on another instance (points per lane per trip), their slots per
@@ -251,8 +260,9 @@ def _roofline(cc, ctx, params, prec):
     else:
         c = None
     if c:
-        units = float(c["dispatches"] * len(FAMILIES) * NPTS)  # points of the counter run
-        out.update(_valu_fields(c, units, (ms * 1e-3) / evals * units,
+        # points of the counter run (one headline step)
+        units = float(c.get("points") or ITERS * len(FAMILIES) * NPTS)
+        out.update(_valu_fields(c, units, (busy * 1e-3) / evals * units,
                                 PEAK_FP32_FLOPS if fp32 else PEAK_FP64_FLOPS))
         out["counters"] = "profiles/valu_counters.json"
     if fp32:
@@ -405,10 +415,28 @@ def summarize_counters(csvs, out_path, commands, probe):
     return rec
 
 
+def _union_ns(intervals):
+    """Length of the union of (start, end) intervals."""
+    total, hi, lo = 0, None, None
+    for a, b in sorted(intervals):
+        if hi is not None and a <= hi:
+            hi = max(hi, b)
+            continue
+        if hi is not None:
+            total += hi - lo
+        lo, hi = a, b
+    return total + (hi - lo if hi is not None else 0)
+
+
 def summarize_stats(stats_csv, out_path, command, note):
-    """Write a short text table from a rocprofv3 --stats kernel_stats.csv."""
+    """Write a short text table from a rocprofv3 --stats kernel_stats.csv;
+    with the run's kernel_trace.csv beside it, also each DoSample kernel's
+    busy time: the union of its dispatches' intervals (launches on two
+    streams overlap)."""
     import csv
+    import glob
     rows = list(csv.DictReader(open(stats_csv, newline="")))
+    traces = glob.glob(os.path.join(os.path.dirname(stats_csv), "*kernel_trace.csv"))
     with open(out_path, "w") as f:
         f.write("rocprofv3 kernel statistics (MI355X, gfx950)\n")
         f.write("command: %s\n%s\n\n" % (command, note))
@@ -418,6 +446,21 @@ def summarize_stats(stats_csv, out_path, command, note):
             f.write("%-72s %7d %11.1f %11.2f %7.2f\n" % (
                 name[:72], int(r["Calls"]), float(r["AverageNs"]) / 1e3,
                 float(r["TotalDurationNs"]) / 1e6, float(r["Percentage"])))
+        if traces:
+            iv = {}
+            for r in csv.DictReader(open(traces[0], newline="")):
+                if "vegas_dosample_kernel" in r["Kernel_Name"]:
+                    iv.setdefault(r["Kernel_Name"], []).append(
+                        (int(r["Start_Timestamp"]), int(r["End_Timestamp"])))
+            f.write("\nDoSample busy time (union of the dispatch intervals; calls overlap when "
+                    "a batch runs as two halves on two streams)\n")
+            f.write("%-72s %7s %11s %11s %9s\n" % ("kernel", "calls", "busy_ms", "sum_ms",
+                                                   "overlap"))
+            for name, v in sorted(iv.items()):
+                u, t = _union_ns(v), sum(b - a for a, b in v)
+                f.write("%-72s %7d %11.2f %11.2f %9.2f\n" % (
+                    name.replace("ccuba::", "")[:72], len(v), u / 1e6, t / 1e6,
+                    t / u if u else 0.0))
 
 
 def _batch_leg(cc):

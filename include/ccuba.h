@@ -109,12 +109,16 @@ int ccuba_shutdown(ccuba_ctx **ctx);
  *   "autotune"       1 = pick the settings above by measurement: a single
  *                    integral times a fixed synthetic integral (cached in the
  *                    file named by CCUBA_TUNE_CACHE, if set); a batch times
- *                    DoSample passes over its own jobs, once per context and
- *                    precision
+ *                    a few iterations of its own jobs, with and without the
+ *                    split into halves, once per context and precision
  *   "graph"          1 = replay iterations from a captured hipGraph
  *   "engine_cache"   1 = keep the engine of the last single-integral Vegas call
  *                    (its buffers and graphs) for the next call of its shape
  *   "serve_slots"    maximum requests resident in the serving loop
+ *   "batch_streams"  2 = a ccuba_vegas_batch of two or more integrals runs as
+ *                    two halves on two streams (default; CCUBA_BATCH_STREAMS),
+ *                    1 = as one; per precision like the keys above (the
+ *                    batch splits when all its precisions ask for it)
  *   "profile"        1 = time every kernel launch with HIP events (see
  *                    ccuba_stats_get)
  * Returns CCUBA_ENOENT for an unknown key, CCUBA_EINVAL for a bad value. */
@@ -123,7 +127,8 @@ int ccuba_config(ccuba_ctx *ctx, const char *key, long long value);
 /* Read one setting into *value (the settings take the place of the
  * environment variables and cubaaccel/cubacores calls of Sect. 3.2.4, so a
  * caller can see what is in force): the keys of ccuba_config; the DoSample
- * launch settings ("block", "blocks_per_cu", "hist64", "ilp", "min_tile") are
+ * launch settings ("block", "blocks_per_cu", "hist64", "ilp", "min_tile",
+ * "batch_streams") are
  * those of `precision' (CCUBA_FP64 or CCUBA_FP32_EVAL), e.g. after an
  * autotuned batch.  Returns CCUBA_ENOENT for an unknown key. */
 int ccuba_config_get(ccuba_ctx *ctx, const char *key, int precision, long long *value);
@@ -402,6 +407,11 @@ typedef struct {
  * two or not, tile full or ragged), each a persistent grid over that class's
  * tile list, then one fold of the partial sums and one refine launch for all
  * jobs.  The launches of an iteration are replayed from a captured hipGraph.
+ * A batch of two or more jobs can be split into two halves of about equal
+ * evaluations, each run so on a stream of its own (the context's and a
+ * second one), so that one half's sampling has the compute units while the
+ * other half folds and refines ("batch_streams"; the autotuner measures
+ * both); the call returns when both are done.
  * Like nbatch (Sect. 3.2.7), the tiling partitions the sampling internally
  * and changes neither the points nor what the integrand sees: each job's
  * result is the one ccuba_vegas gives for it alone (same points; sums in
@@ -517,7 +527,11 @@ int ccuba_vegas_refine(ccuba_ctx *ctx, int ndim, int nbins, const double *hist,
  * their partial sums and the refine launch of every Vegas iteration, and
  * around every Cuhre rule launch, while the context's "profile" setting is 1
  * (iterations are then launched one by one rather than replayed from a
- * graph).  evals counts the points sampled by the timed sampling launches. */
+ * graph).  evals counts the points sampled by the timed sampling launches.
+ * dosample_busy_ms is the time during which at least one sampling launch
+ * ran: the sum of their durations, except for a batch run as two halves on
+ * two streams, whose sampling launches can overlap: there it is the length of
+ * the union of their intervals. */
 typedef struct {
   long long dosample_launches; /* sampling kernel launches (one per tile class) */
   double dosample_ms;      /* summed sampling kernel time */
@@ -528,6 +542,7 @@ typedef struct {
   double rule_ms;
   long long rule_evals;
   double fold_ms;          /* summed time of the partial-sum folds */
+  double dosample_busy_ms; /* time with a sampling launch running (see above) */
 } ccuba_stats;
 
 /* Copy the context's counters to *out (host, written before return) and reset

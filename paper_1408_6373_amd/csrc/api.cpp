@@ -6,6 +6,8 @@
 #include <cstring>
 #include <memory>
 #include <new>
+#include <mutex>
+#include <thread>
 
 #include "ccuba.h"
 #include "context.h"
@@ -19,6 +21,11 @@
 #include "vegas_batched.h"
 #include "vegas_engine.h"
 #include "noalloc.h"
+
+void ccuba::note_hip_error(hipError_t e, const char *file, int line) {
+  static const bool on = std::getenv("CCUBA_DEBUG") != nullptr;
+  if (on) std::fprintf(stderr, "ccuba: %s at %s:%d\n", hipGetErrorString(e), file, line);
+}
 
 using namespace ccuba;
 
@@ -224,6 +231,7 @@ int ccuba_init(ccuba_ctx **ctx, int device, size_t hbm_budget) {
   }
   c->budget = hbm_budget;
   if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) return CCUBA_EHIP;
+  if (hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking) != hipSuccess) return CCUBA_EHIP;
   if (set_kernel_limits() != hipSuccess) return CCUBA_EHIP;
   // the allocation-free entry point's scratch: its address on this device
   if (noalloc_init(device) != CCUBA_OK) return CCUBA_EHIP;
@@ -235,6 +243,7 @@ int ccuba_init(ccuba_ctx **ctx, int device, size_t hbm_budget) {
     c->tune[p].min_tile = env_ll("CCUBA_MIN_TILE", 16384);
     // measured best on gfx950: two points per lane for FP32, one for FP64
     c->tune[p].ilp = (int)env_ll("CCUBA_ILP", p == FP32 ? 2 : 1) == 2 ? 2 : 1;
+    c->tune[p].streams = env_ll("CCUBA_BATCH_STREAMS", 2) == 1 ? 1 : 2;
   }
   // LDS histogram: the exact fixed-point one for FP32 evaluation (faster
   // than FP64 LDS adds); FP64 LDS adds for FP64 evaluation, where the exact
@@ -265,6 +274,7 @@ int ccuba_shutdown(ccuba_ctx **ctx) {
   if (c->pinned_host) (void)hipHostFree(c->pinned_host);
   pool_release(c);
   if (c->stream) (void)hipStreamDestroy(c->stream);
+  if (c->stream2) (void)hipStreamDestroy(c->stream2);
   delete c;
   *ctx = nullptr;
   return CCUBA_OK;
@@ -296,6 +306,8 @@ int ccuba_config_get(ccuba_ctx *ctx, const char *key, int precision, long long *
     *value = ctx->serve_slots;
   else if (k == "engine_cache")
     *value = ctx->engine_cache;
+  else if (k == "batch_streams")
+    *value = t.streams;
   else
     return CCUBA_ENOENT;
   return CCUBA_OK;
@@ -332,6 +344,9 @@ int ccuba_config(ccuba_ctx *ctx, const char *key, long long value) {
   } else if (k == "serve_slots") {
     if (value < 1 || value > 1 << 20) return CCUBA_EINVAL;
     ctx->serve_slots = (int)value;
+  } else if (k == "batch_streams") {
+    if (value != 1 && value != 2) return CCUBA_EINVAL;
+    ctx->tune[0].streams = ctx->tune[1].streams = (int)value;
   } else {
     return CCUBA_ENOENT;
   }
@@ -995,6 +1010,88 @@ int ccuba_cuhre_rule(ccuba_ctx *ctx, int ndim, const ccuba_integrand *f, long lo
   return run.rule_only(nreg, c, h, I7, I5, err, axis, ctx->stream);
 }
 
+namespace {
+
+// One engine over a batch's integrals, on the context's stream: the states
+// after the last iteration into st.
+int run_batch_engine(ccuba_ctx *ctx, const std::vector<VegasSpec> &specs,
+                     std::vector<VState> &st) {
+  VegasEngine eng(ctx);
+  int rc;
+  // one integral: the single-integral tile plan (a tile per block)
+  if ((rc = eng.setup(specs, specs.size() == 1, ctx->stream))) return rc;
+  if ((rc = eng.run(ctx->stream))) return rc;
+  return eng.read_states(st, ctx->stream);
+}
+
+// A batch's two halves side by side, one on each of the context's streams.
+// When every job runs its whole budget both are launched from this thread,
+// the second's graphs queued right after the first's, so that their first
+// sampling launches start together; otherwise each runs from a thread of
+// its own (its chunks wait on host checks of the states).  With ref
+// (profile mode) the halves' sampling intervals go to iv.
+int run_halves(ccuba_ctx *ctx, const std::vector<VegasSpec> &h0,
+               const std::vector<VegasSpec> &h1, std::vector<VState> &st0,
+               std::vector<VState> &st1, hipEvent_t ref,
+               std::vector<std::pair<double, double>> &iv) {
+  VegasEngine e0(ctx), e1(ctx);
+  int rc;
+  if ((rc = e0.setup(h0, h0.size() == 1, ctx->stream))) return rc;
+  if ((rc = e1.setup(h1, h1.size() == 1, ctx->stream2))) return rc;
+  e0.set_time_reference(ref);
+  e1.set_time_reference(ref);
+  int r0 = CCUBA_OK, r1 = CCUBA_OK;
+  if (e0.fixed() && e1.fixed()) {
+    r0 = e0.launch_run(ctx->stream);
+    if (!r0) r1 = e1.launch_run(ctx->stream2);
+    // (what was queued is waited for, also after a failed launch)
+    const int f0 = e0.finish_run(ctx->stream);
+    const int f1 = r0 ? CCUBA_OK : e1.finish_run(ctx->stream2);
+    if (!r0) r0 = f0;
+    if (!r1) r1 = f1;
+  } else {
+    std::thread other;
+    try {
+      other = std::thread([&] {
+        r1 = hipSetDevice(ctx->device) == hipSuccess ? e1.run(ctx->stream2) : CCUBA_EHIP;
+      });
+    } catch (...) {  // no thread: the halves run one after the other
+    }
+    r0 = e0.run(ctx->stream);
+    if (other.joinable())
+      other.join();
+    else
+      r1 = e1.run(ctx->stream2);
+  }
+  for (const VegasEngine *e : {&e0, &e1})
+    iv.insert(iv.end(), e->dosample_intervals().begin(), e->dosample_intervals().end());
+  if (r0) return r0;
+  if (r1) return r1;
+  if ((rc = e0.read_states(st0, ctx->stream))) return rc;
+  return e1.read_states(st1, ctx->stream2);
+}
+
+// Length of the union of intervals.
+double union_length(std::vector<std::pair<double, double>> iv) {
+  std::sort(iv.begin(), iv.end());
+  double total = 0.0, lo = 0.0, hi = 0.0;
+  bool open = false;
+  for (const auto &x : iv) {
+    if (open && x.first <= hi) {
+      hi = std::max(hi, x.second);
+      continue;
+    }
+    if (open) total += hi - lo;
+    lo = x.first;
+    hi = x.second;
+    open = true;
+  }
+  if (open) total += hi - lo;
+  return total;
+}
+
+}  // namespace
+
 int ccuba_vegas_batch(ccuba_ctx *ctx, int njobs, const ccuba_job jobs[], ccuba_result out[]) {
   if (!ctx || njobs < 0 || (njobs > 0 && (!jobs || !out))) return CCUBA_EINVAL;
   if (njobs == 0) return CCUBA_OK;
@@ -1020,13 +1117,46 @@ int ccuba_vegas_batch(ccuba_ctx *ctx, int njobs, const ccuba_job jobs[], ccuba_r
     }
   }
   if (specs.empty()) return CCUBA_OK;
+  // Two halves on two streams (Sect. 2.1 makes each integral's iterations a
+  // sequence, and separate integrals independent): every iteration of a half
+  // ends in its fold and refine launches, a few workgroups that wait on
+  // memory, and the other half's sampling launch has the compute units
+  // meanwhile.  The split balances the halves' evaluations; it is taken when
+  // the setting of every precision in the batch asks for it (the autotuner
+  // measures both ways).
   if (ctx->autotune) autotune_batch(ctx, specs);
-  VegasEngine eng(ctx);
-  int rc;
-  if ((rc = eng.setup(specs, specs.size() == 1, ctx->stream))) return rc;
-  if ((rc = eng.run(ctx->stream))) return rc;
-  std::vector<VState> st;
-  if ((rc = eng.read_states(st, ctx->stream))) return rc;
+  bool split = specs.size() >= 2;
+  for (const auto &sp : specs) split = split && ctx->tune[sp.prec].streams > 1;
+  const size_t cut = split ? batch_cut(specs) : specs.size();
+  const std::vector<VegasSpec> half0(specs.begin(), specs.begin() + cut),
+      half1(specs.begin() + cut, specs.end());
+  std::vector<VState> st, st1;
+  int rc = CCUBA_OK;
+  if (!split) {
+    rc = run_batch_engine(ctx, half0, st);
+  } else {
+    // In profile mode the halves' sampling launches are timed against one
+    // reference event that both streams start after, and the context's busy
+    // time gets the union of their intervals.
+    hipEvent_t ref = nullptr;
+    std::vector<std::pair<double, double>> iv;
+    if (ctx->profile) {
+      CCUBA_HIP(hipEventCreate(&ref));
+      if (hipEventRecord(ref, ctx->stream) != hipSuccess ||
+          hipStreamWaitEvent(ctx->stream2, ref, 0) != hipSuccess) {
+        (void)hipEventDestroy(ref);
+        return CCUBA_EHIP;
+      }
+    }
+    rc = run_halves(ctx, half0, half1, st, st1, ref, iv);
+    if (ref) {
+      std::lock_guard<std::mutex> g(ctx->stats_lock);
+      ctx->stats.dosample_busy_ms += union_length(iv);
+      (void)hipEventDestroy(ref);
+    }
+  }
+  if (rc) return rc;
+  st.insert(st.end(), st1.begin(), st1.end());
   const double t_done = ctx->now();
   for (int q = 0; q < njobs; ++q) {
     if (index[q] < 0) continue;

@@ -25,6 +25,8 @@ struct ccuba_ctx {
   size_t budget = 0;                // bytes the context may hold on the device
   std::atomic<size_t> used{0};      // bytes currently held
   hipStream_t stream = nullptr;     // the context's own stream (default priority)
+  // a second stream (default priority) for the second half of a Vegas batch
+  hipStream_t stream2 = nullptr;
   ccuba::VegasTune tune[2];         // per precision: [FP64], [FP32]
   int use_graph = 1;
   int autotune = 0;
@@ -33,6 +35,7 @@ struct ccuba_ctx {
   int serve_slots = 256;
   int profile = 0;
   ccuba_stats stats{};
+  std::mutex stats_lock;            // guards stats (a batch's halves run in two threads)
   std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
   std::mutex lock;                  // serialises engine use with the server thread
   ccuba::Server *server = nullptr;  // the serving loop, started by the first submit
@@ -113,7 +116,16 @@ struct DevBuf {
 
 }  // namespace ccuba
 
-#define CCUBA_HIP(call)                       \
-  do {                                        \
-    if ((call) != hipSuccess) return CCUBA_EHIP; \
+namespace ccuba {
+// With CCUBA_DEBUG set in the environment, a failed HIP call is reported on
+// stderr (its error and source line) before CCUBA_EHIP is returned.
+void note_hip_error(hipError_t e, const char *file, int line);
+}  // namespace ccuba
+#define CCUBA_HIP(call)                                 \
+  do {                                                  \
+    const hipError_t ccuba_e_ = (call);                 \
+    if (ccuba_e_ != hipSuccess) {                       \
+      ccuba::note_hip_error(ccuba_e_, __FILE__, __LINE__); \
+      return CCUBA_EHIP;                                \
+    }                                                   \
   } while (0)

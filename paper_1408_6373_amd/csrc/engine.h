@@ -91,6 +91,7 @@ struct VegasTune {
   int ilp = 1;            // points per lane per trip (1 or 2)
   int tiles_per_job = 0;  // 0 = automatic (one tile per persistent block)
   long long min_tile = 4096;
+  int streams = 2;        // a batch of 2+ integrals: 2 = two halves on two streams
 };
 
 }  // namespace ccuba

@@ -8,8 +8,9 @@
 // floating-point summation order.  The cache file holds one line per
 // (device name, precision): "name prec block blocks_per_cu hist64 ilp", and
 // one per (device name, batch signature, precision) for batches:
-// "name:batch:signature prec block blocks_per_cu hist64 ilp min_tile", where
-// the signature hashes the shapes of the batch's jobs of that precision.
+// "name:batch:signature prec block blocks_per_cu hist64 ilp min_tile streams",
+// where the signature hashes the shapes of the batch's jobs of that
+// precision and streams is 2 when the batch runs as two halves.
 #include "tune.h"
 
 #include <cstdio>
@@ -43,16 +44,20 @@ bool load_cache(const char *path, const std::string &key, int prec, VegasTune &t
   while (std::getline(f, line)) {  // the last matching line wins
     std::istringstream is(line);
     std::string k;
-    int p, b, bpc, h, ilp;
+    int p, b, bpc, h, ilp, ns = 2;
     long long mt = 0;
     if (!(is >> k >> p >> b >> bpc >> h >> ilp)) continue;
     if (with_tile && !(is >> mt)) continue;
+    if (with_tile && !(is >> ns)) ns = 2;
     if (k == key && p == prec) {
       t.block = b;
       t.blocks_per_cu = bpc;
       t.hist64 = h;
       t.ilp = ilp;
-      if (with_tile) t.min_tile = mt;
+      if (with_tile) {
+        t.min_tile = mt;
+        t.streams = ns == 1 ? 1 : 2;
+      }
       found = true;
     }
   }
@@ -64,7 +69,7 @@ void store_cache(const char *path, const std::string &key, int prec, const Vegas
   std::ofstream f(path, std::ios::app);
   f << key << " " << prec << " " << t.block << " " << t.blocks_per_cu << " " << t.hist64 << " "
     << t.ilp;
-  if (with_tile) f << " " << t.min_tile;
+  if (with_tile) f << " " << t.min_tile << " " << t.streams;
   f << "\n";
 }
 
@@ -166,28 +171,51 @@ void maybe_autotune(ccuba_ctx *ctx, int prec) {
 
 namespace {
 
-double time_batch(ccuba_ctx *ctx, const std::vector<VegasSpec> &specs) {
+// Full iterations (sampling, fold, refine) of specs as the batch call runs
+// them: as one engine on the context's stream, or with split as two halves
+// side by side on its two streams, both launched from this thread (each
+// half with the single-integral tile plan if it holds one integral).  Three
+// iterations after one of warm-up, twice; the better time in ms.
+double time_batch(ccuba_ctx *ctx, const std::vector<VegasSpec> &specs, bool split) {
   double best = 1e30;
-  VegasEngine eng(ctx);
-  if (eng.setup(specs, false, ctx->stream) != 0) return best;
-  hipEvent_t a, b;
+  const size_t cut = split ? batch_cut(specs) : specs.size();
+  const std::vector<VegasSpec> h0(specs.begin(), specs.begin() + cut),
+      h1(specs.begin() + cut, specs.end());
+  VegasEngine e0(ctx), e1(ctx);
+  if (e0.setup(h0, h0.size() == 1, ctx->stream) != 0) return best;
+  if (!h1.empty() && e1.setup(h1, h1.size() == 1, ctx->stream2) != 0) return best;
+  hipEvent_t a, b, j;
   if (hipEventCreate(&a) != hipSuccess) return best;
   if (hipEventCreate(&b) != hipSuccess) {
     (void)hipEventDestroy(a);
     return best;
   }
-  (void)eng.dosample_only(ctx->stream);  // warm-up
-  for (int r = 0; r < 2; ++r) {
-    (void)hipEventRecord(a, ctx->stream);
-    (void)eng.dosample_only(ctx->stream);
-    (void)hipEventRecord(b, ctx->stream);
-    if (hipEventSynchronize(b) != hipSuccess) break;
+  if (hipEventCreateWithFlags(&j, hipEventDisableTiming) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return best;
+  }
+  for (int r = 0; r < 3; ++r) {  // pass 0 warms up
+    const int iters = r == 0 ? 1 : 3;
+    bool ok = hipEventRecord(a, ctx->stream) == hipSuccess;
+    if (!h1.empty()) ok = ok && hipStreamWaitEvent(ctx->stream2, a, 0) == hipSuccess;
+    for (int q = 0; q < iters && ok; ++q) {
+      ok = e0.step(ctx->stream) == CCUBA_OK;
+      if (!h1.empty()) ok = ok && e1.step(ctx->stream2) == CCUBA_OK;
+    }
+    if (!h1.empty())
+      ok = ok && hipEventRecord(j, ctx->stream2) == hipSuccess &&
+           hipStreamWaitEvent(ctx->stream, j, 0) == hipSuccess;
+    ok = ok && hipEventRecord(b, ctx->stream) == hipSuccess;
+    if (!ok || hipEventSynchronize(b) != hipSuccess) break;
     float ms = 0;
     (void)hipEventElapsedTime(&ms, a, b);
-    if (ms < best) best = ms;
+    if (r > 0 && ms < best) best = ms;
   }
+  (void)hipStreamSynchronize(ctx->stream2);
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
+  (void)hipEventDestroy(j);
   return best;
 }
 
@@ -213,22 +241,32 @@ void autotune_batch(ccuba_ctx *ctx, const std::vector<VegasSpec> &specs) {
     double best_ms = 1e30;
     const int bpcs[] = {2, 3, 4, 6};
     const long long tiles[] = {4096, 16384, 65536};
-    for (int bpc : bpcs)
-      for (int ilp = 1; ilp <= 2; ++ilp)
-        for (long long mt : tiles)
-          for (int h = 0; h < 2; ++h) {
-            VegasTune c = saved;
-            c.blocks_per_cu = bpc;
-            c.ilp = ilp;
-            c.min_tile = mt;
-            c.hist64 = h;
-            ctx->tune[prec] = c;
-            const double ms = time_batch(ctx, mine);
-            if (ms < best_ms) {
-              best_ms = ms;
-              best = c;
+    // one engine, or two halves (2+ integrals); a tile plan that holds one
+    // integral is the single-integral one, which does not use the minimum
+    // tile size
+    for (int streams = 1; streams <= (mine.size() >= 2 ? 2 : 1); ++streams) {
+      const bool split = streams == 2;
+      const size_t cut = split ? batch_cut(mine) : mine.size();
+      const bool single = split ? (cut == 1 && mine.size() == 2) : mine.size() == 1;
+      const int ntiles = single ? 1 : 3;
+      for (int bpc : bpcs)
+        for (int ilp = 1; ilp <= 2; ++ilp)
+          for (int ti = 0; ti < ntiles; ++ti)
+            for (int h = 0; h < 2; ++h) {
+              VegasTune c = saved;
+              c.blocks_per_cu = bpc;
+              c.ilp = ilp;
+              c.min_tile = single ? saved.min_tile : tiles[ti];
+              c.hist64 = h;
+              c.streams = streams;
+              ctx->tune[prec] = c;
+              const double ms = time_batch(ctx, mine, split);
+              if (ms < best_ms) {
+                best_ms = ms;
+                best = c;
+              }
             }
-          }
+    }
     ctx->tune[prec] = best;
     if (path && *path) store_cache(path, key, prec, best, true);
   }

@@ -98,6 +98,32 @@ void genz_constants(const VegasSpec &s, double p64[2][kParamRow], float p32[2][k
   }
 }
 
+size_t batch_cut(const std::vector<VegasSpec> &specs) {
+  if (specs.size() < 2) return specs.size();
+  std::vector<double> work(specs.size());
+  double total = 0.0;
+  for (size_t j = 0; j < specs.size(); ++j) {
+    int it = 0;
+    long long nmax = 0;
+    vegas_budget(specs[j], &it, &nmax);
+    const VegasSpec &sp = specs[j];
+    work[j] = (double)it * (double)sp.nstart +
+              (double)sp.nincrease * (double)it * (double)(it - 1) / 2.0;
+    total += work[j];
+  }
+  size_t best = 1;
+  double acc = 0.0, gap = -1.0;
+  for (size_t k = 1; k < specs.size(); ++k) {
+    acc += work[k - 1];
+    const double g = std::fabs(2.0 * acc - total);
+    if (gap < 0.0 || g < gap) {
+      gap = g;
+      best = k;
+    }
+  }
+  return best;
+}
+
 bool fixed_hist(int prec, int hist64, long long dN) {
   // the DoSample kernel's static LDS (block sums, per-dimension maxima) is
   // well below the 1 KB left for it
@@ -421,13 +447,19 @@ int VegasEngine::launch_iteration(hipStream_t s) {
 
 int VegasEngine::flush_timing() {
   for (auto &p : pending_) {
-    float a = 0, b = 0, c = 0;
+    float a = 0, b = 0, c = 0, t0 = 0;
     CCUBA_HIP(hipEventSynchronize(p.e3));
     CCUBA_HIP(hipEventElapsedTime(&a, p.e0, p.e1));
     CCUBA_HIP(hipEventElapsedTime(&b, p.e1, p.e2));
     CCUBA_HIP(hipEventElapsedTime(&c, p.e2, p.e3));
+    if (ref_) {
+      CCUBA_HIP(hipEventElapsedTime(&t0, ref_, p.e0));
+      ds_iv_.push_back({(double)t0, (double)t0 + a});
+    }
+    std::lock_guard<std::mutex> g(ctx_->stats_lock);
     ctx_->stats.dosample_launches += (long long)tgroups_.size();
     ctx_->stats.dosample_ms += a;
+    if (!ref_) ctx_->stats.dosample_busy_ms += a;
     ctx_->stats.fold_ms += b;
     ctx_->stats.refine_launches += 1;
     ctx_->stats.refine_ms += c;
@@ -466,10 +498,19 @@ int VegasEngine::graph_for(int k, hipStream_t s, hipGraphExec_t *out) {
   return CCUBA_OK;
 }
 
-int VegasEngine::run(hipStream_t s) {
-  bool fixed = true;
+bool VegasEngine::fixed() const {
   for (const auto &sp : specs_)
-    if (sp.epsrel > 0 || sp.epsabs > 0) fixed = false;
+    if (sp.epsrel > 0 || sp.epsabs > 0) return false;
+  return true;
+}
+
+int VegasEngine::run(hipStream_t s) {
+  const int rc = launch_run(s);
+  return rc ? rc : finish_run(s);
+}
+
+int VegasEngine::launch_run(hipStream_t s) {
+  const bool fixed = this->fixed();
   int remaining = max_iters_;
   if (remaining == 0) return CCUBA_OK;
   // Iterations are launched in chunks between host checks of the states:
@@ -503,11 +544,18 @@ int VegasEngine::run(hipStream_t s) {
       chunk = std::min(chunk * 2, kMaxGraphIters);
     }
   }
+  return CCUBA_OK;
+}
+
+int VegasEngine::finish_run(hipStream_t s) {
+  if (max_iters_ == 0) return CCUBA_OK;
   CCUBA_HIP(hipStreamSynchronize(s));
+  std::vector<VState> st;
   if (ctx_->profile) {
     // every point a timed DoSample launch sampled is in some job's neval
     int rc = read_states(st, s);
     if (rc) return rc;
+    std::lock_guard<std::mutex> g(ctx_->stats_lock);
     for (const auto &x : st) ctx_->stats.evals += x.neval;
   }
   return flush_timing();

@@ -6,6 +6,7 @@
 // A single integral is an engine with one job.
 #pragma once
 #include <functional>
+#include <utility>
 #include <vector>
 
 #include "context.h"
@@ -29,6 +30,10 @@ struct VegasSpec {
 int validate_vegas(const VegasSpec &s);
 // Iterations the budget allows and the largest n_t among them.
 void vegas_budget(const VegasSpec &s, int *iters, long long *nmax);
+// Where a batch splits into two halves of about equal evaluations (the
+// budget's iterations): the first `cut' integrals and the rest, each holding
+// at least one; specs.size() for fewer than two.
+size_t batch_cut(const std::vector<VegasSpec> &specs);
 // The per-dimension constants of the device Genz code (see genz.h).
 void genz_constants(const VegasSpec &s, double p64[2][kParamRow], float p32[2][kParamRow]);
 
@@ -66,7 +71,15 @@ class VegasEngine {
   // One iteration of every unfinished job (async on s).
   int step(hipStream_t s);
   // Iterate until every job is done; replays a captured graph if enabled.
+  // run = launch_run then finish_run.
   int run(hipStream_t s);
+  // Launch the iterations: all without waiting when every job runs its
+  // whole budget (fixed()), else in chunks with host checks of the states.
+  int launch_run(hipStream_t s);
+  // Wait for what launch_run queued; the profile-mode timings.
+  int finish_run(hipStream_t s);
+  // No job can stop before its budget (no epsrel or epsabs).
+  bool fixed() const;
   // The same one iteration at a time, calling after(state of job 0) once each
   // iteration is done (a checkpoint); a nonzero return from it stops the run
   // with that status.
@@ -98,6 +111,14 @@ class VegasEngine {
   // set before setup.
   void set_user_kernel(hipFunction_t f) { user_fn_ = f; }
 
+  // Profile mode with a reference event recorded before this engine's work
+  // (on its stream or one it waits on): each iteration's sampling interval,
+  // in ms after the reference, goes to dosample_intervals() instead of the
+  // context's busy time, so that a caller running engines side by side can
+  // take the union.
+  void set_time_reference(hipEvent_t ref) { ref_ = ref; }
+  const std::vector<std::pair<double, double>> &dosample_intervals() const { return ds_iv_; }
+
   int njobs() const { return (int)specs_.size(); }
   int max_iters() const { return max_iters_; }
   long long evals_per_iteration() const { return evals_iter_; }
@@ -114,6 +135,8 @@ class VegasEngine {
     int iter;
   };
   std::vector<Timed> pending_;
+  hipEvent_t ref_ = nullptr;
+  std::vector<std::pair<double, double>> ds_iv_;
   bool capturing_ = false;
   int iter_launched_ = 0;
   ccuba_ctx *ctx_;
