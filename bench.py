@@ -266,7 +266,7 @@ def _roofline(cc, ctx, params, prec):
                                 PEAK_FP32_FLOPS if fp32 else PEAK_FP64_FLOPS))
         out["counters"] = "profiles/valu_counters.json"
     if fp32:
-        out["traffic"] = _traffic()
+        out["traffic"] = _traffic(evals / n, t)
     return out
 
 
@@ -298,14 +298,25 @@ def kernel_source_hash(names=KERNEL_SOURCES):
     return h.hexdigest()
 
 
-def _traffic():
+# the settings that shape a DoSample launch's tile plan (and so its bytes)
+_PLAN_KEYS = ("block", "blocks_per_cu", "min_tile", "batch_streams")
+
+
+def _traffic(points_per_launch, launch):
     """HBM bytes per DoSample launch from the committed PMC summary, if it was
-    taken on the current kernel source."""
+    taken on the current kernel source, on launches of this size and with the
+    same tile plan settings."""
     path = os.path.join(ROOT, "profiles", "vegas_dosample_d8_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
     if rec.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    ppd = rec.get("dosample", {}).get("points_per_dispatch")
+    if ppd is None or abs(ppd - points_per_launch) > 0.5:
+        return None
+    taken = rec.get("launch")
+    if not taken or any(taken.get(k) != launch.get(k) for k in _PLAN_KEYS):
         return None
     return rec.get("bytes_per_launch")
 
@@ -320,7 +331,7 @@ def _read_pmc(path):
     return out
 
 
-def summarize_pmc(fetch_csv, write_csv, out_path, commands):
+def summarize_pmc(fetch_csv, write_csv, out_path, commands, launch=None):
     """Write the HBM-traffic summary of the DoSample kernels of a
     --traffic-probe run: FETCH_SIZE and WRITE_SIZE (KiB per dispatch, summed
     over the XCDs by rocprofv3), each scaled by what the same counter reads
@@ -333,10 +344,10 @@ def summarize_pmc(fetch_csv, write_csv, out_path, commands):
     gib = float(1 << 30)
     fs, ws = gib / (cf * 1024), gib / (cw * 1024)
     rec = {"what": "HBM bytes per dispatch of the FP32 DoSample kernels (one headline "
-                   "step: Vegas d=8 oscillatory and product peak as one batch, 128 bins, "
-                   "2 x 1e7 points per launch, 20 iterations) from rocprofv3 FETCH_SIZE "
-                   "and WRITE_SIZE, scaled by the same counters on a 1 GiB "
-                   "device-to-device copy",
+                   "step: Vegas d=8 oscillatory and product peak, 128 bins, 20 iterations "
+                   "of 1e7 points each, launched as the tuned batch runs them) from "
+                   "rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by the same counters on a "
+                   "1 GiB device-to-device copy",
            "commands": commands,
            "copy_calibration": {"bytes": 1 << 30, "fetch_kib": cf, "write_kib": cw,
                                 "fetch_scale": fs, "write_scale": ws}}
@@ -349,9 +360,13 @@ def summarize_pmc(fetch_csv, write_csv, out_path, commands):
         f_avg, w_avg = sum(fk) / len(fk), sum(wk) / len(wk)
         rec[key] = {"dispatches": len(fk), "fetch_kib": f_avg, "write_kib": w_avg,
                     "bytes": 1024 * (f_avg * fs + w_avg * ws)}
+        if key == "dosample":  # the probe samples one headline step
+            rec[key]["points_per_dispatch"] = ITERS * len(FAMILIES) * NPTS / len(fk)
     rec["kernel_sources"] = list(KERNEL_SOURCES)
     rec["kernel_source_sha256"] = kernel_source_hash()
     rec["bytes_per_launch"] = rec["dosample"]["bytes"]
+    if launch:
+        rec["launch"] = launch  # the tuned settings the probe ran with
     with open(out_path, "w") as f:
         json.dump(rec, f, indent=1)
     return rec
@@ -452,6 +467,8 @@ def summarize_stats(stats_csv, out_path, command, note):
                 if "vegas_dosample_kernel" in r["Kernel_Name"]:
                     iv.setdefault(r["Kernel_Name"], []).append(
                         (int(r["Start_Timestamp"]), int(r["End_Timestamp"])))
+            if not iv:
+                return
             f.write("\nDoSample busy time (union of the dispatch intervals; calls overlap when "
                     "a batch runs as two halves on two streams)\n")
             f.write("%-72s %7s %11s %11s %9s\n" % ("kernel", "calls", "busy_ms", "sum_ms",
@@ -859,6 +876,9 @@ def main():
                          "step of the headline workload; prints a JSON line")
     ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT"),
                     help="write the traffic summary of two --traffic-probe counter runs")
+    ap.add_argument("--probe-line", default="",
+                    help="with --pmc-summary: a file holding the probe's JSON line (its "
+                         "launch settings are recorded)")
     ap.add_argument("--tune-only", action="store_true",
                     help="autotune the headline batch in both precisions into the tune cache "
                          "(CCUBA_TUNE_CACHE) and exit")
@@ -875,7 +895,11 @@ def main():
     args = ap.parse_args()
     if args.pmc_summary:
         cmds = [c for c in args.command.split(";;") if c]
-        print(json.dumps(summarize_pmc(*args.pmc_summary[:2], args.pmc_summary[2], cmds)))
+        probe = {}
+        if args.probe_line:
+            probe = json.loads([x for x in open(args.probe_line) if x.startswith("{")][0])
+        print(json.dumps(summarize_pmc(*args.pmc_summary[:2], args.pmc_summary[2], cmds,
+                                       probe.get("launch"))))
         return
     if args.stats_summary:
         summarize_stats(args.stats_summary[0], args.stats_summary[1], args.command, args.note)
@@ -911,8 +935,10 @@ def main():
         ctx = cc.Context(device=0)
         ctx.config("autotune", 1)  # the tuned settings, from the cache
         ev = _step(cc, ctx, params, cc.FP32_EVAL)
+        launch = _tuned_settings(ctx, cc.FP32_EVAL)
         ctx.close()
-        print(json.dumps({"traffic_probe": True, "copy_bytes": 1 << 30, "neval": ev}))
+        print(json.dumps({"traffic_probe": True, "copy_bytes": 1 << 30, "neval": ev,
+                          "launch": launch}))
         return
     if args.tune_only:
         _tune_cache()

@@ -1026,9 +1026,9 @@ int run_batch_engine(ccuba_ctx *ctx, const std::vector<VegasSpec> &specs,
 
 // A batch's two halves side by side, one on each of the context's streams.
 // When every job runs its whole budget both are launched from this thread,
-// the second's graphs queued right after the first's, so that their first
-// sampling launches start together; otherwise each runs from a thread of
-// its own (its chunks wait on host checks of the states).  With ref
+// their graphs captured first and then queued one right after the other, so
+// that their first sampling launches start together; otherwise each runs
+// from a thread of its own (its chunks wait on host checks of the states).  With ref
 // (profile mode) the halves' sampling intervals go to iv.
 int run_halves(ccuba_ctx *ctx, const std::vector<VegasSpec> &h0,
                const std::vector<VegasSpec> &h1, std::vector<VState> &st0,
@@ -1042,6 +1042,8 @@ int run_halves(ccuba_ctx *ctx, const std::vector<VegasSpec> &h0,
   e1.set_time_reference(ref);
   int r0 = CCUBA_OK, r1 = CCUBA_OK;
   if (e0.fixed() && e1.fixed()) {
+    // both halves' graphs are captured before either is launched
+    if ((rc = e0.prepare_run(ctx->stream)) || (rc = e1.prepare_run(ctx->stream2))) return rc;
     r0 = e0.launch_run(ctx->stream);
     if (!r0) r1 = e1.launch_run(ctx->stream2);
     // (what was queued is waited for, also after a failed launch)

@@ -13,6 +13,7 @@
 // precision and streams is 2 when the batch runs as two halves.
 #include "tune.h"
 
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -173,18 +174,26 @@ namespace {
 
 // Full iterations (sampling, fold, refine) of specs as the batch call runs
 // them: as one engine on the context's stream, or with split as two halves
-// side by side on its two streams, both launched from this thread (each
-// half with the single-integral tile plan if it holds one integral).  Three
-// iterations after one of warm-up, twice; the better time in ms.
+// side by side on its two streams (each half with the single-integral tile
+// plan if it holds one integral), replayed from graphs captured before
+// either half is launched.  Each job runs its first iterations (up to 6 of
+// its budget, without early stopping); the best of three such runs, from
+// fresh engines, in ms.
 double time_batch(ccuba_ctx *ctx, const std::vector<VegasSpec> &specs, bool split) {
-  double best = 1e30;
-  const size_t cut = split ? batch_cut(specs) : specs.size();
-  const std::vector<VegasSpec> h0(specs.begin(), specs.begin() + cut),
-      h1(specs.begin() + cut, specs.end());
-  VegasEngine e0(ctx), e1(ctx);
-  if (e0.setup(h0, h0.size() == 1, ctx->stream) != 0) return best;
-  if (!h1.empty() && e1.setup(h1, h1.size() == 1, ctx->stream2) != 0) return best;
+  constexpr int kIters = 6;
+  std::vector<VegasSpec> cut_specs = specs;
+  for (VegasSpec &sp : cut_specs) {
+    long long budget = 0;
+    for (int t = 0; t < kIters; ++t) budget += sp.nstart + (long long)t * sp.nincrease;
+    sp.maxeval = std::min(sp.maxeval, budget);
+    sp.mineval = 0;
+    sp.epsrel = sp.epsabs = 0.0;
+  }
+  const size_t cut = split ? batch_cut(cut_specs) : cut_specs.size();
+  const std::vector<VegasSpec> h0(cut_specs.begin(), cut_specs.begin() + cut),
+      h1(cut_specs.begin() + cut, cut_specs.end());
   hipEvent_t a, b, j;
+  double best = 1e30;
   if (hipEventCreate(&a) != hipSuccess) return best;
   if (hipEventCreate(&b) != hipSuccess) {
     (void)hipEventDestroy(a);
@@ -195,24 +204,28 @@ double time_batch(ccuba_ctx *ctx, const std::vector<VegasSpec> &specs, bool spli
     (void)hipEventDestroy(b);
     return best;
   }
-  for (int r = 0; r < 3; ++r) {  // pass 0 warms up
-    const int iters = r == 0 ? 1 : 3;
-    bool ok = hipEventRecord(a, ctx->stream) == hipSuccess;
+  for (int r = 0; r < 3; ++r) {
+    VegasEngine e0(ctx), e1(ctx);
+    bool ok = e0.setup(h0, h0.size() == 1, ctx->stream) == CCUBA_OK &&
+              (h1.empty() || e1.setup(h1, h1.size() == 1, ctx->stream2) == CCUBA_OK) &&
+              e0.prepare_run(ctx->stream) == CCUBA_OK &&
+              (h1.empty() || e1.prepare_run(ctx->stream2) == CCUBA_OK);
+    ok = ok && hipEventRecord(a, ctx->stream) == hipSuccess;
     if (!h1.empty()) ok = ok && hipStreamWaitEvent(ctx->stream2, a, 0) == hipSuccess;
-    for (int q = 0; q < iters && ok; ++q) {
-      ok = e0.step(ctx->stream) == CCUBA_OK;
-      if (!h1.empty()) ok = ok && e1.step(ctx->stream2) == CCUBA_OK;
-    }
+    ok = ok && e0.launch_run(ctx->stream) == CCUBA_OK;
     if (!h1.empty())
-      ok = ok && hipEventRecord(j, ctx->stream2) == hipSuccess &&
+      ok = ok && e1.launch_run(ctx->stream2) == CCUBA_OK &&
+           hipEventRecord(j, ctx->stream2) == hipSuccess &&
            hipStreamWaitEvent(ctx->stream, j, 0) == hipSuccess;
     ok = ok && hipEventRecord(b, ctx->stream) == hipSuccess;
-    if (!ok || hipEventSynchronize(b) != hipSuccess) break;
+    const bool done = ok && hipEventSynchronize(b) == hipSuccess;
+    (void)e0.finish_run(ctx->stream);
+    if (!h1.empty()) (void)e1.finish_run(ctx->stream2);
+    if (!done) break;
     float ms = 0;
     (void)hipEventElapsedTime(&ms, a, b);
-    if (r > 0 && ms < best) best = ms;
+    if (ms < best) best = ms;
   }
-  (void)hipStreamSynchronize(ctx->stream2);
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   (void)hipEventDestroy(j);
@@ -239,6 +252,8 @@ void autotune_batch(ccuba_ctx *ctx, const std::vector<VegasSpec> &specs) {
     const VegasTune saved = ctx->tune[prec];
     VegasTune best = saved;
     double best_ms = 1e30;
+    const int profile = ctx->profile;  // (the tuning runs are not profiled)
+    ctx->profile = 0;
     const int bpcs[] = {2, 3, 4, 6};
     const long long tiles[] = {4096, 16384, 65536};
     // one engine, or two halves (2+ integrals); a tile plan that holds one
@@ -267,6 +282,7 @@ void autotune_batch(ccuba_ctx *ctx, const std::vector<VegasSpec> &specs) {
               }
             }
     }
+    ctx->profile = profile;
     ctx->tune[prec] = best;
     if (path && *path) store_cache(path, key, prec, best, true);
   }

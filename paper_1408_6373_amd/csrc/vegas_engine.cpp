@@ -509,6 +509,19 @@ int VegasEngine::run(hipStream_t s) {
   return rc ? rc : finish_run(s);
 }
 
+int VegasEngine::prepare_run(hipStream_t s) {
+  if (!fixed() || ctx_->use_graph == 0 || ctx_->profile) return CCUBA_OK;
+  // the chunks launch_run takes when no job can stop early
+  for (int remaining = max_iters_; remaining > 0;) {
+    const int k = std::min(remaining, kMaxGraphIters);
+    hipGraphExec_t exec = nullptr;
+    const int rc = graph_for(k, s, &exec);
+    if (rc) return rc;
+    remaining -= k;
+  }
+  return CCUBA_OK;
+}
+
 int VegasEngine::launch_run(hipStream_t s) {
   const bool fixed = this->fixed();
   int remaining = max_iters_;

@@ -73,6 +73,10 @@ class VegasEngine {
   // Iterate until every job is done; replays a captured graph if enabled.
   // run = launch_run then finish_run.
   int run(hipStream_t s);
+  // Capture ahead the graphs that launch_run replays when every job runs
+  // its whole budget (nothing to do otherwise), so that launch_run then only
+  // queues them.
+  int prepare_run(hipStream_t s);
   // Launch the iterations: all without waiting when every job runs its
   // whole budget (fixed()), else in chunks with host checks of the states.
   int launch_run(hipStream_t s);

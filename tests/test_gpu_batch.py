@@ -135,3 +135,40 @@ def test_autotuned_batch_equals_default(cc):
         assert _rel(r["integral"], b["integral"]) < 1e-12
         assert _rel(r["error"], b["error"]) < 1e-12
 
+
+
+@pytest.mark.parametrize("eps", [False, True])
+def test_two_halves_equal_one_stream(cc, eps):
+    """The batch run as two halves on two streams (both launched from one
+    thread when every job runs its budget, from two threads when jobs can
+    stop early) gives each integral what the one-stream run gives, and in
+    profile mode the sampling busy time (the union of the halves' launch
+    intervals, which overlap) is positive and at most their summed time.
+    The early-stopping jobs run up to 40 iterations; the values that fall
+    outside the fixed-point window go to LDS FP64 adds, whose order varies
+    from run to run, so their grids differ from a rerun's in the last bits
+    and their (small) errors by up to ~1e-11 (1e-10 below), whatever the
+    streams; the integral holds 1e-12."""
+    specs = _specs(24, 11, eps=eps)
+    out = {}
+    for streams in (1, 2):
+        c = cc.Context()
+        c.config("batch_streams", streams)
+        out[streams] = cc.vegas_batch(c, specs)
+        c.close()
+    for s, a, b in zip(specs, out[2], out[1]):
+        assert a["status"] == 0 and a["neval"] == b["neval"] and a["fail"] == b["fail"]
+        assert _rel(a["integral"], b["integral"]) < 1e-12
+        # (FP32 evaluation: binary32 v^2 products summed in another order)
+        tol = 1e-12 if s["flags"] == 0 and not eps else 1e-10
+        assert _rel(a["error"], b["error"]) < tol, (s["flags"], a["error"], b["error"])
+    import bench
+    c = cc.Context()
+    c.config("batch_streams", 2)
+    c.config("profile", 1)
+    bench._stats(cc, c)
+    cc.vegas_batch(c, specs)
+    st = bench._stats(cc, c)
+    c.close()
+    assert st.dosample_launches > 0 and st.dosample_ms > 0
+    assert 0 < st.dosample_busy_ms <= st.dosample_ms * (1 + 1e-9)
