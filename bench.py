@@ -502,7 +502,8 @@ def _batch_leg(cc):
     t0 = time.perf_counter()
     res = cc.vegas_batch(ctx, prepared)
     dt = time.perf_counter() - t0
-    tuned = {k: ctx.config_get(k) for k in ("blocks_per_cu", "ilp", "min_tile", "hist64")}
+    tuned = {k: ctx.config_get(k) for k in ("blocks_per_cu", "ilp", "min_tile", "hist64",
+                                            "batch_streams")}
     ctx.close()
     ev = sum(r["neval"] for r in res)
     return {"workload": "4096 Vegas integrals, d 2..12, 1e4..1e6 points x 10 iterations, FP32",
