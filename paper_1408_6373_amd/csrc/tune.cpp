@@ -178,8 +178,10 @@ namespace {
 // plan if it holds one integral), replayed from graphs captured before
 // either half is launched.  Each job runs its first iterations (up to 6 of
 // its budget, without early stopping); the best of three such runs, from
-// fresh engines, in ms.
-double time_batch(ccuba_ctx *ctx, const std::vector<VegasSpec> &specs, bool split) {
+// fresh engines, in ms, or of fewer once one takes longer than `cutoff' ms
+// (the candidate is then out of the race anyway).
+double time_batch(ccuba_ctx *ctx, const std::vector<VegasSpec> &specs, bool split,
+                  double cutoff) {
   constexpr int kIters = 6;
   std::vector<VegasSpec> cut_specs = specs;
   for (VegasSpec &sp : cut_specs) {
@@ -225,6 +227,7 @@ double time_batch(ccuba_ctx *ctx, const std::vector<VegasSpec> &specs, bool spli
     float ms = 0;
     (void)hipEventElapsedTime(&ms, a, b);
     if (ms < best) best = ms;
+    if (ms > cutoff) break;
   }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
@@ -275,7 +278,8 @@ void autotune_batch(ccuba_ctx *ctx, const std::vector<VegasSpec> &specs) {
               c.hist64 = h;
               c.streams = streams;
               ctx->tune[prec] = c;
-              const double ms = time_batch(ctx, mine, split);
+              // (a candidate 25% slower than the best so far stops after one run)
+              const double ms = time_batch(ctx, mine, split, 1.25 * best_ms);
               if (ms < best_ms) {
                 best_ms = ms;
                 best = c;
