@@ -176,13 +176,17 @@ namespace {
 // them: as one engine on the context's stream, or with split as two halves
 // side by side on its two streams (each half with the single-integral tile
 // plan if it holds one integral), replayed from graphs captured before
-// either half is launched.  Each job runs its first iterations (up to 6 of
-// its budget, without early stopping); the best of three such runs, from
-// fresh engines, in ms, or of fewer once one takes longer than `cutoff' ms
-// (the candidate is then out of the race anyway).
+// either half is launched.  Each job runs its first iterations (6 of its
+// budget, fewer down to 2 for batches of more than 3.3e7 points an
+// iteration, so that a run samples at most ~2e8 points; no early stopping);
+// the best of three such runs, from fresh engines, in ms, or of fewer once
+// one takes longer than `cutoff' ms (the candidate is then out of the race
+// anyway).
 double time_batch(ccuba_ctx *ctx, const std::vector<VegasSpec> &specs, bool split,
                   double cutoff) {
-  constexpr int kIters = 6;
+  double per_iter = 0.0;
+  for (const VegasSpec &sp : specs) per_iter += (double)sp.nstart;
+  const int kIters = (int)std::max(2.0, std::min(6.0, 2e8 / std::max(per_iter, 1.0)));
   std::vector<VegasSpec> cut_specs = specs;
   for (VegasSpec &sp : cut_specs) {
     long long budget = 0;
