@@ -8,7 +8,7 @@ has to come first in the process) and ``ORACLE_SANITIZE=1``, which makes the
 oracle binding load the sanitized library.  Leak detection is off: the
 interpreter's own allocations at exit are not the oracle's.  Any sanitizer
 report aborts the run (``-fno-sanitize-recover=all``, ``halt_on_error``), so
-the exit status is the verdict.
+the exit status is the outcome.
 
     python oracle/sanitize.py [extra pytest arguments]
 """
