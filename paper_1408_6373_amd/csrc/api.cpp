@@ -1028,8 +1028,8 @@ int run_batch_engine(ccuba_ctx *ctx, const std::vector<VegasSpec> &specs,
 // When every job runs its whole budget both are launched from this thread,
 // their graphs captured first and then queued one right after the other, so
 // that their first sampling launches start together; otherwise each runs
-// from a thread of its own (its chunks wait on host checks of the states).  With ref
-// (profile mode) the halves' sampling intervals go to iv.
+// from a thread of its own (its chunks wait on host checks of the states).
+// With ref (profile mode) the halves' sampling intervals go to iv.
 int run_halves(ccuba_ctx *ctx, const std::vector<VegasSpec> &h0,
                const std::vector<VegasSpec> &h1, std::vector<VState> &st0,
                std::vector<VState> &st1, hipEvent_t ref,
