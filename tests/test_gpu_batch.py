@@ -172,3 +172,25 @@ def test_two_halves_equal_one_stream(cc, eps):
     c.close()
     assert st.dosample_launches > 0 and st.dosample_ms > 0
     assert 0 < st.dosample_busy_ms <= st.dosample_ms * (1 + 1e-9)
+
+
+def test_batch_streams_setting(cc):
+    """batch_streams is a per-precision launch setting (2 by default), set for
+    both precisions by ccuba_config and refused outside {1, 2}; a one-job
+    batch never splits and gives the single call's result."""
+    c = cc.Context()
+    assert c.config_get("batch_streams", cc.FP32_EVAL) == 2
+    assert c.config_get("batch_streams", cc.FP64) == 2
+    c.config("batch_streams", 1)
+    assert c.config_get("batch_streams", cc.FP32_EVAL) == 1
+    assert c.config_get("batch_streams", cc.FP64) == 1
+    for bad in (0, 3, -1):
+        with pytest.raises(cc.CcubaError):
+            c.config("batch_streams", bad)
+    c.config("batch_streams", 2)
+    s = _specs(1, 3, prec_mix=False)[0]
+    r = cc.vegas_batch(c, [s])[0]
+    a = _alone(cc, c, s)
+    assert r["status"] == 0 and r["neval"] == a["neval"]
+    assert _rel(r["integral"], a["integral"]) < 1e-12
+    c.close()
