@@ -1023,6 +1023,13 @@ def main():
     out["roofline"] = _roofline(cc, hctx, params, cc.FP32_EVAL)
     if not args.no_fp64:
         out["fp64"]["roofline"] = _roofline(cc, hctx, params, cc.FP64)
+    # the same counter slots over the whole timed step (sampling, folds,
+    # refines and every gap): what the step as a whole makes of the VALU peak
+    for ro, ev, t in ((out["roofline"], ev32, t32),) + (
+            ((out["fp64"]["roofline"], ev64, t64),) if not args.no_fp64 else ()):
+        if ro.get("slots_per_unit"):
+            ro["step_achieved"] = ro["slots_per_unit"] * ev / t / 1e12
+            ro["step_frac"] = ro["slots_per_unit"] * ev / t / PEAK_VALU
     hctx.close()
     if not args.no_extra:
         out["batch"] = _batch_leg(cc)
