@@ -61,3 +61,30 @@ def test_concentrates_where_the_histogram_is():
     # bins 9..11 carry mass after smoothing; most new edges fall inside them
     inside = np.sum((En > U[9]) & (En < U[12]))
     assert inside > N // 2
+
+
+def test_mirror_symmetry():
+    # The refinement has no preferred direction: reflecting the grid and the
+    # histogram (x -> 1 - x) reflects the refined grid.  A one-sided
+    # smoothing or an edge placed from the wrong end breaks this.
+    rng = np.random.default_rng(2)
+    for N in (3, 7, 64, 129):
+        E = np.concatenate([[0.0], np.sort(rng.random(N - 1)), [1.0]])
+        H = rng.random(N) ** 3
+        En = O.refine_dim(H, E)
+        Er = O.refine_dim(H[::-1].copy(), (1.0 - E[::-1]).copy())
+        assert np.allclose(Er, 1.0 - En[::-1], atol=1e-13)
+
+
+def test_scale_invariance():
+    # Only the histogram's shape steers the grid: scaling it by any positive
+    # factor leaves the refined grid unchanged (the damping acts on the
+    # normalized weights).  Powers of two scale exactly.
+    rng = np.random.default_rng(3)
+    N = 100
+    E = np.concatenate([[0.0], np.sort(rng.random(N - 1)), [1.0]])
+    H = rng.random(N) ** 2
+    En = O.refine_dim(H, E)
+    for c in (2.0 ** -40, 0.5, 8.0, 2.0 ** 60):
+        assert np.array_equal(O.refine_dim(H * c, E), En)
+    assert np.allclose(O.refine_dim(H * 3.7, E), En, atol=1e-14)
